@@ -1,0 +1,179 @@
+/*
+ * fewha.h -- C ABI of the MI355X augmented wavelet reconstructor (augmented FEWHA).
+ *
+ * The library solves, frame after frame, the wavelet-domain MAP system of atmospheric
+ * tomography (Sec. 3, equation for M and the right-hand side b)
+ *
+ *     M c = b,   M = W^-T A^T C_eta^-1 A W^-1 + alpha D,   b = W^-T A^T C_eta^-1 s,
+ *
+ * with augmented preconditioned conjugate gradients (Sec. 4.1, Alg. 2) inside the frame
+ * update of the augmented wavelet reconstructor (Sec. 5, Alg. 3: right-hand side,
+ * residual update, augmented PCG).  A is the tomography operator (Sec. 2): bilinear
+ * propagation from every layer to every guide-star direction (natural: shift; laser:
+ * cone-scaled shift) followed by the Shack-Hartmann operator.  W is the periodic
+ * Daubechies-3 wavelet transform of every layer scaled by its constant delta_l (Sec. 3).
+ *
+ * Conventions shared by every entry point
+ *  - Element type: device vectors (coefficients, slopes) are double in FEWHA_FP64 and
+ *    float in FEWHA_FP32_OP_FP64_RED.  Inner products, the recycle Gram matrix, its
+ *    factorisation and all scalars are double in both modes.
+ *  - Layouts: a coefficient vector is the concatenation over layers of an n_l x n_l
+ *    row-major 2-D Mallat pyramid (approximation block top-left; at each level the block
+ *    right of it holds the x-detail, below it the y-detail, diagonal the xy-detail).  A
+ *    nodal layer vector uses the same offsets with row-major node values (row = y).
+ *    A slope vector is the concatenation over sensors of [s^x (n_sub^2 row-major);
+ *    s^y (n_sub^2)].
+ *  - Ownership: all device buffers are allocated by the caller.  The workspace passed to
+ *    fewha_setup belongs to the context until fewha_destroy; the library allocates no
+ *    device memory of its own.  Host arrays inside fewha_config are read during
+ *    fewha_setup only.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Compute calls are
+ *    stream-ordered and asynchronous; argument errors are returned synchronously.  A
+ *    context must be used from one stream at a time and is not thread-safe.
+ *  - Errors: every call returns a fewha_status; fewha_last_error() gives a message.
+ */
+#ifndef FEWHA_H
+#define FEWHA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEWHA_ABI_VERSION 1
+#define FEWHA_MAX_LAYERS 32
+#define FEWHA_MAX_WFS 32
+#define FEWHA_MAX_RECYCLE 32
+
+typedef struct fewha_ctx fewha_ctx;
+
+typedef enum {
+    FEWHA_OK = 0,
+    FEWHA_E_INVAL = 1,      /* bad argument or geometry (e.g. a footprint leaves a layer grid) */
+    FEWHA_E_NOMEM = 2,      /* workspace too small */
+    FEWHA_E_HIP = 3,        /* a HIP runtime call failed */
+    FEWHA_E_NOT_SPD = 4,    /* a diagonal entry of M is not positive */
+    FEWHA_E_BREAKDOWN = 5,  /* (p, q) <= 0 or a non-finite scalar was met in a solve */
+    FEWHA_E_STATE = 6       /* state buffer does not belong to this configuration */
+} fewha_status;
+
+typedef enum { FEWHA_FP64 = 0, FEWHA_FP32_OP_FP64_RED = 1 } fewha_precision;
+
+/* Recycling variants of Alg. 2 (Sec. 4.1).  PAPER: sequential single-vector Galerkin and
+ * initial-direction projections against the previous frame's directions, as printed.
+ * GALERKIN: the same projections solved jointly with the k x k Gram matrix U^T Q (FP64
+ * Cholesky, near-dependent columns dropped) over a ring of the k most recent directions. */
+typedef enum { FEWHA_RECYCLE_PAPER = 0, FEWHA_RECYCLE_GALERKIN = 1 } fewha_recycle_mode;
+
+/* One turbulence layer (Sec. 2 layered atmosphere; Sec. 3 layer grid of 2^(2 J_l) nodes). */
+typedef struct {
+    double height;      /* h_l [m] */
+    double weight;      /* gamma_l, fraction of turbulence strength (enters the prior) */
+    double spacing;     /* d_l [m], node spacing; also the wavelet scaling delta_l */
+    double origin_x;    /* grid centre [m]; node (a,b) is at origin + ((b-(n-1)/2) d, (a-(n-1)/2) d) */
+    double origin_y;
+    int32_t n;          /* nodes per side, a power of two, 8 <= n <= 1024 */
+    int32_t levels;     /* wavelet levels, 1 <= levels <= log2(n) */
+} fewha_layer;
+
+/* One Shack-Hartmann sensor and its guide star (Sec. 2). */
+typedef struct {
+    int32_t n_sub;               /* subapertures per side; nodes (n_sub+1)^2 at ((j-n_sub/2) d_s, (i-n_sub/2) d_s) */
+    int32_t pad_;
+    double subap;                /* d_s [m] */
+    double theta_x, theta_y;     /* guide-star direction [rad] */
+    double lgs_height;           /* H [m] of a laser guide star; 0 for a natural guide star */
+    const double* slope_weight;  /* host, 2 n_sub^2: diagonal of C_eta^-1 (0 = inactive subaperture) */
+} fewha_wfs;
+
+typedef struct {
+    int32_t abi_version;         /* FEWHA_ABI_VERSION */
+    int32_t n_layers;            /* 1..FEWHA_MAX_LAYERS */
+    const fewha_layer* layers;   /* host */
+    int32_t n_wfs;               /* 1..FEWHA_MAX_WFS */
+    int32_t pad_;
+    const fewha_wfs* wfs;        /* host */
+    double alpha;                /* regularisation weight (Sec. 3) */
+    double r0, L0;               /* Fried parameter and outer scale [m] for the default prior */
+    const double* prior_diag;    /* host, N entries of D, or NULL for the default von Karman prior */
+    const double* precond_inv;   /* host, N entries of J^-1, or NULL for 1/diag(M) computed exactly */
+    int32_t max_iter;            /* PCG iterations per frame (operator applications), 1..256 */
+    int32_t recycle_k;           /* recycled directions, 0..FEWHA_MAX_RECYCLE (0 = plain PCG) */
+    int32_t recycle_mode;        /* fewha_recycle_mode */
+    int32_t project_all;         /* GALERKIN only: project every new direction against all of U */
+    double rel_tol;              /* reserved, must be 0 (fixed iteration count) */
+    int32_t precision;           /* fewha_precision */
+    int32_t pad2_;
+} fewha_config;
+
+/* Written by the device at the end of every fewha_solve_aug. */
+typedef struct {
+    int32_t iters;          /* operator applications in the frame */
+    int32_t recycle_used;   /* recycled directions used for the projections */
+    int32_t dropped;        /* Gram columns dropped as numerically dependent */
+    int32_t flags;          /* bit 0: breakdown ((p,q) <= 0 or non-finite scalar) */
+    double rel_res;         /* ||r|| / ||b|| at the end of the frame (FP64) */
+} fewha_solve_info;
+
+/* Device bytes the workspace of `cfg` needs. */
+fewha_status fewha_workspace_size(const fewha_config* cfg, size_t* bytes);
+
+/* Validate `cfg`, build the geometry tables, the prior D and the Jacobi preconditioner
+ * J^-1 = 1/diag(M) (Sec. 4, computed exactly on the host from the separable structure
+ * of the wavelet basis), copy them into `d_workspace` (device, >= fewha_workspace_size
+ * bytes, 256-byte aligned) and return a context.  The recycle store is empty and the
+ * carried state (c, r, b_prev) is zero.  Synchronises `stream` before returning. */
+fewha_status fewha_setup(const fewha_config* cfg, void* d_workspace, size_t bytes, void* stream,
+                         fewha_ctx** out);
+
+/* Number of coefficients N = sum_l n_l^2 and of slopes S = sum_g 2 n_sub,g^2. */
+fewha_status fewha_sizes(const fewha_ctx* ctx, int64_t* n_coeff, int64_t* n_slopes);
+
+/* y = M x (equation for M, Sec. 3).  d_x, d_y: device, N elements; d_y must not alias d_x. */
+fewha_status fewha_apply_A(fewha_ctx* ctx, const void* d_x, void* d_y, void* stream);
+
+/* b = W^-T A^T C_eta^-1 s (right-hand side, Sec. 3).  d_s: device, S; d_b: device, N. */
+fewha_status fewha_rhs(fewha_ctx* ctx, const void* d_s, void* d_b, void* stream);
+
+/* One frame of Alg. 3 (right-hand side, residual update, augmented PCG of Alg. 2) for the
+ * slopes d_s (device, S): the carried coefficients c^(i), residual r^(i), previous
+ * right-hand side b^(i) and recycled directions are updated in the context and the new
+ * coefficients are written to d_c (device, N).  The first frame after setup or
+ * fewha_reset runs Alg. 1 from r = b - M c.  d_info (device, may be NULL) receives a
+ * fewha_solve_info. */
+fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d_info, void* stream);
+
+/* Drop the recycle store: the next solve runs Alg. 1 from r = b - M c with the carried c. */
+fewha_status fewha_reset(fewha_ctx* ctx);
+
+/* Operator pieces, for testing (in/out device, element type of the context):
+ *   FEWHA_PIECE_WINV  : coefficients (N) -> nodal layers (N), W^-1 = DWT^T / delta_l
+ *   FEWHA_PIECE_WINVT : nodal layers (N) -> coefficients (N), W^-T = DWT / delta_l
+ *   FEWHA_PIECE_A     : nodal layers (N) -> slopes (S), Gamma_g P_g summed over layers,
+ *                       zero on inactive subapertures
+ *   FEWHA_PIECE_AT    : slopes (S) -> nodal layers (N), sum_g P_g^T Gamma_g^T (inactive ignored) */
+typedef enum { FEWHA_PIECE_WINV = 0, FEWHA_PIECE_WINVT = 1, FEWHA_PIECE_A = 2, FEWHA_PIECE_AT = 3 } fewha_piece;
+fewha_status fewha_apply_piece(fewha_ctx* ctx, int32_t piece, const void* d_in, void* d_out, void* stream);
+
+/* Copy the scaled prior alpha D (N) or the preconditioner J^-1 (N) in use to d_out (device,
+ * element type of the context).  which: 0 = alpha D, 1 = J^-1. */
+fewha_status fewha_get_vector(fewha_ctx* ctx, int32_t which, void* d_out, void* stream);
+
+/* Checkpoint of the carried state (c, r, b_prev, recycle store and its bookkeeping).
+ * fewha_state_size gives the bytes; get/set copy to/from a device buffer of that size. */
+fewha_status fewha_state_size(const fewha_ctx* ctx, size_t* bytes);
+fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream);
+fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream);
+
+/* Release the context (the workspace stays the caller's). */
+fewha_status fewha_destroy(fewha_ctx* ctx);
+
+/* Message of the last error on `ctx` (or of the last failed setup when ctx is NULL). */
+const char* fewha_last_error(const fewha_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEWHA_H */

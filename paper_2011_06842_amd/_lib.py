@@ -1,0 +1,269 @@
+"""ctypes binding of the C ABI in include/fewha.h (argument marshalling only).
+
+Device memory and streams come from PyTorch; every computation runs in the HIP kernels of
+libfewha.so.  There is no fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfewha.so")
+
+FEWHA_ABI_VERSION = 1
+FEWHA_FP64, FEWHA_FP32_OP_FP64_RED = 0, 1
+FEWHA_RECYCLE_PAPER, FEWHA_RECYCLE_GALERKIN = 0, 1
+PIECE_WINV, PIECE_WINVT, PIECE_A, PIECE_AT = 0, 1, 2, 3
+STATUS = {0: "FEWHA_OK", 1: "FEWHA_E_INVAL", 2: "FEWHA_E_NOMEM", 3: "FEWHA_E_HIP", 4: "FEWHA_E_NOT_SPD",
+          5: "FEWHA_E_BREAKDOWN", 6: "FEWHA_E_STATE"}
+
+EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
+           "fewha_solve_aug", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
+           "fewha_get_state", "fewha_set_state", "fewha_destroy", "fewha_last_error"]
+
+
+class fewha_layer(C.Structure):
+    _fields_ = [("height", C.c_double), ("weight", C.c_double), ("spacing", C.c_double),
+                ("origin_x", C.c_double), ("origin_y", C.c_double), ("n", C.c_int32), ("levels", C.c_int32)]
+
+
+class fewha_wfs(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("pad_", C.c_int32), ("subap", C.c_double), ("theta_x", C.c_double),
+                ("theta_y", C.c_double), ("lgs_height", C.c_double), ("slope_weight", C.POINTER(C.c_double))]
+
+
+class fewha_config(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("n_layers", C.c_int32), ("layers", C.POINTER(fewha_layer)),
+                ("n_wfs", C.c_int32), ("pad_", C.c_int32), ("wfs", C.POINTER(fewha_wfs)),
+                ("alpha", C.c_double), ("r0", C.c_double), ("L0", C.c_double),
+                ("prior_diag", C.POINTER(C.c_double)), ("precond_inv", C.POINTER(C.c_double)),
+                ("max_iter", C.c_int32), ("recycle_k", C.c_int32), ("recycle_mode", C.c_int32),
+                ("project_all", C.c_int32), ("rel_tol", C.c_double), ("precision", C.c_int32),
+                ("pad2_", C.c_int32)]
+
+
+class fewha_solve_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("recycle_used", C.c_int32), ("dropped", C.c_int32),
+                ("flags", C.c_int32), ("rel_res", C.c_double)]
+
+
+class FewhaError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfewha.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FewhaError(f"{path} is missing: build it with paper_2011_06842_amd.build.build()")
+    lib = C.CDLL(path)
+    vp, st = C.c_void_p, C.c_int
+    sig = {
+        "fewha_workspace_size": ([C.POINTER(fewha_config), C.POINTER(C.c_size_t)], st),
+        "fewha_setup": ([C.POINTER(fewha_config), vp, C.c_size_t, vp, C.POINTER(vp)], st),
+        "fewha_sizes": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], st),
+        "fewha_apply_A": ([vp, vp, vp, vp], st),
+        "fewha_rhs": ([vp, vp, vp, vp], st),
+        "fewha_solve_aug": ([vp, vp, vp, vp, vp], st),
+        "fewha_reset": ([vp], st),
+        "fewha_apply_piece": ([vp, C.c_int32, vp, vp, vp], st),
+        "fewha_get_vector": ([vp, C.c_int32, vp, vp], st),
+        "fewha_state_size": ([vp, C.POINTER(C.c_size_t)], st),
+        "fewha_get_state": ([vp, vp, vp], st),
+        "fewha_set_state": ([vp, vp, vp], st),
+        "fewha_destroy": ([vp], st),
+        "fewha_last_error": ([vp], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        msg = _lib.fewha_last_error(ctx).decode() if _lib is not None else ""
+        raise FewhaError(f"{STATUS.get(status, status)}: {msg}")
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
+    """fewha_config from any object with the attributes of a system description (layers with
+    height/weight/spacing/origin_x/origin_y/n/levels; wfs with n_sub/subap/theta_x/theta_y/
+    lgs_height/weight; alpha, r0, L0, max_iter, recycle_k, recycle_mode, project_all,
+    precision).  `keep` collects the host arrays that must outlive the setup call."""
+    keep = [] if keep is None else keep
+    L, G = len(spec.layers), len(spec.wfs)
+    layers = (fewha_layer * L)()
+    for i, l in enumerate(spec.layers):
+        layers[i] = fewha_layer(l.height, l.weight, l.spacing, l.origin_x, l.origin_y, l.n, l.levels)
+    wfs = (fewha_wfs * G)()
+    for i, w in enumerate(spec.wfs):
+        if w.weight is None:
+            raise FewhaError(f"sensor {i}: slope weights are not set")
+        wt = np.ascontiguousarray(w.weight, dtype=np.float64)
+        keep.append(wt)
+        wfs[i] = fewha_wfs(w.n_sub, 0, w.subap, w.theta_x, w.theta_y, w.lgs_height,
+                           wt.ctypes.data_as(C.POINTER(C.c_double)))
+    keep += [layers, wfs]
+
+    def dptr(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+
+    cfg = fewha_config()
+    cfg.abi_version = FEWHA_ABI_VERSION
+    cfg.n_layers, cfg.layers = L, layers
+    cfg.n_wfs, cfg.wfs = G, wfs
+    cfg.alpha, cfg.r0, cfg.L0 = spec.alpha, spec.r0, spec.L0
+    cfg.prior_diag = dptr(prior_diag)
+    cfg.precond_inv = dptr(precond_inv)
+    cfg.max_iter = spec.max_iter
+    cfg.recycle_k = spec.recycle_k
+    cfg.recycle_mode = FEWHA_RECYCLE_PAPER if spec.recycle_mode == "paper" else FEWHA_RECYCLE_GALERKIN
+    cfg.project_all = int(bool(spec.project_all))
+    cfg.rel_tol = 0.0
+    cfg.precision = FEWHA_FP64 if spec.precision == "fp64" else FEWHA_FP32_OP_FP64_RED
+    return cfg
+
+
+def fewha_workspace_size(spec, **kw) -> int:
+    lib = load_library()
+    keep = []
+    cfg = make_config(spec, keep=keep, **kw)
+    n = C.c_size_t()
+    _check(lib.fewha_workspace_size(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+class FewhaContext:
+    """One solver context: owns its workspace tensor; calls mirror the C ABI names."""
+
+    def __init__(self, spec, device="cuda", prior_diag=None, precond_inv=None, stream=None):
+        import torch
+        self.lib = load_library()
+        keep = []
+        cfg = make_config(spec, prior_diag=prior_diag, precond_inv=precond_inv, keep=keep)
+        n = C.c_size_t()
+        _check(self.lib.fewha_workspace_size(C.byref(cfg), C.byref(n)))
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        base = _ptr(self.workspace)
+        off = (-base) % 256
+        self._ws_ptr = base + off
+        ctx = C.c_void_p()
+        _check(self.lib.fewha_setup(C.byref(cfg), C.c_void_p(self._ws_ptr), n.value, C.c_void_p(_stream(stream)),
+                                    C.byref(ctx)))
+        self.ctx = ctx
+        self.dtype = torch.float64 if spec.precision == "fp64" else torch.float32
+        self.device = device
+        Nc, Sc = C.c_int64(), C.c_int64()
+        _check(self.lib.fewha_sizes(self.ctx, C.byref(Nc), C.byref(Sc)), self.ctx)
+        self.N, self.S = Nc.value, Sc.value
+
+    # -- helpers
+    def _vec(self, n):
+        import torch
+        return torch.empty(n, dtype=self.dtype, device=self.device)
+
+    def _in(self, t, n):
+        if t.dtype != self.dtype or t.numel() != n or not t.is_contiguous() or not t.is_cuda:
+            raise FewhaError(f"expected a contiguous {self.dtype} device tensor of {n} elements")
+        return t
+
+    # -- C ABI calls
+    def fewha_apply_A(self, x, y=None, stream=None):
+        x = self._in(x, self.N)
+        y = self._vec(self.N) if y is None else self._in(y, self.N)
+        _check(self.lib.fewha_apply_A(self.ctx, _ptr(x), _ptr(y), _stream(stream)), self.ctx)
+        return y
+
+    def fewha_rhs(self, s, b=None, stream=None):
+        s = self._in(s, self.S)
+        b = self._vec(self.N) if b is None else self._in(b, self.N)
+        _check(self.lib.fewha_rhs(self.ctx, _ptr(s), _ptr(b), _stream(stream)), self.ctx)
+        return b
+
+    def fewha_solve_aug(self, s, c=None, info=None, stream=None):
+        """One frame; returns c (device tensor).  `info`, if given, is a 24-byte uint8 device
+        tensor that receives a fewha_solve_info (decode with :func:`decode_info`)."""
+        s = self._in(s, self.S)
+        c = self._vec(self.N) if c is None else self._in(c, self.N)
+        ip = _ptr(info) if info is not None else None
+        _check(self.lib.fewha_solve_aug(self.ctx, _ptr(s), _ptr(c), ip, _stream(stream)), self.ctx)
+        return c
+
+    def fewha_reset(self):
+        _check(self.lib.fewha_reset(self.ctx), self.ctx)
+
+    def fewha_apply_piece(self, piece, x, stream=None):
+        n_in = self.S if piece == PIECE_AT else self.N
+        n_out = self.S if piece == PIECE_A else self.N
+        x = self._in(x, n_in)
+        y = self._vec(n_out)
+        _check(self.lib.fewha_apply_piece(self.ctx, piece, _ptr(x), _ptr(y), _stream(stream)), self.ctx)
+        return y
+
+    def fewha_get_vector(self, which, stream=None):
+        y = self._vec(self.N)
+        _check(self.lib.fewha_get_vector(self.ctx, which, _ptr(y), _stream(stream)), self.ctx)
+        return y
+
+    def fewha_state_size(self):
+        n = C.c_size_t()
+        _check(self.lib.fewha_state_size(self.ctx, C.byref(n)), self.ctx)
+        return n.value
+
+    def fewha_get_state(self, stream=None):
+        import torch
+        buf = torch.empty(self.fewha_state_size(), dtype=torch.uint8, device=self.device)
+        _check(self.lib.fewha_get_state(self.ctx, _ptr(buf), _stream(stream)), self.ctx)
+        return buf
+
+    def fewha_set_state(self, buf, stream=None):
+        _check(self.lib.fewha_set_state(self.ctx, _ptr(buf), _stream(stream)), self.ctx)
+
+    def fewha_destroy(self):
+        if getattr(self, "ctx", None):
+            self.lib.fewha_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.fewha_destroy()
+        except Exception:
+            pass
+
+    def new_info(self):
+        import torch
+        return torch.zeros(C.sizeof(fewha_solve_info), dtype=torch.uint8, device=self.device)
+
+
+def decode_info(info_tensor) -> dict:
+    raw = bytes(info_tensor.cpu().numpy().tobytes())
+    s = fewha_solve_info.from_buffer_copy(raw)
+    return {"iters": s.iters, "recycle_used": s.recycle_used, "dropped": s.dropped, "flags": s.flags,
+            "rel_res": s.rel_res}

@@ -1,0 +1,283 @@
+// C ABI entry points of the augmented-FEWHA library (declared in include/fewha.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fewha_internal.h"
+
+struct fewha_ctx {
+    fewha::Ctx c;
+    uint64_t state_header[32];   // host copy of the checkpoint header (kept alive for async H2D)
+};
+
+namespace {
+
+thread_local std::string g_setup_err;
+constexpr uint64_t kStateMagic = 0x46455748415354ULL;   // "FEWHAST"
+
+fewha_status fail(fewha_ctx* ctx, fewha_status st, const std::string& msg) {
+    if (ctx) ctx->c.err = msg;
+    return st;
+}
+
+fewha_status check_launch(fewha_ctx* ctx) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return FEWHA_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+fewha_status fewha_workspace_size(const fewha_config* cfg, size_t* bytes) {
+    std::string err;
+    const fewha_status st = fewha::validate_config(cfg, err);
+    if (st != FEWHA_OK) {
+        g_setup_err = err;
+        return st;
+    }
+    if (!bytes) return FEWHA_E_INVAL;
+    *bytes = fewha::compute_layout(cfg).total;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_setup(const fewha_config* cfg, void* d_workspace, size_t bytes, void* stream, fewha_ctx** out) {
+    if (!out) return FEWHA_E_INVAL;
+    *out = nullptr;
+    std::string err;
+    fewha_status st = fewha::validate_config(cfg, err);
+    if (st != FEWHA_OK) {
+        g_setup_err = err;
+        return st;
+    }
+    const fewha::Layout lo = fewha::compute_layout(cfg);
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) {
+        g_setup_err = "workspace must be a 256-byte aligned device pointer";
+        return FEWHA_E_INVAL;
+    }
+    if (bytes < lo.total) {
+        g_setup_err = "workspace too small: need " + std::to_string(lo.total) + " bytes";
+        return FEWHA_E_NOMEM;
+    }
+    fewha_ctx* ctx = new (std::nothrow) fewha_ctx();
+    if (!ctx) return FEWHA_E_NOMEM;
+    fewha::Ctx& c = ctx->c;
+    c.L = cfg->n_layers;
+    c.G = cfg->n_wfs;
+    c.layers.assign(cfg->layers, cfg->layers + c.L);
+    c.wfs.assign(cfg->wfs, cfg->wfs + c.G);
+    for (auto& w : c.wfs) w.slope_weight = nullptr;   // host array only valid during setup
+    for (const auto& l : c.layers) {
+        c.N += int64_t(l.n) * l.n;
+        c.max_levels = std::max(c.max_levels, int(l.levels));
+        c.max_n = std::max(c.max_n, int(l.n));
+    }
+    for (const auto& w : c.wfs) {
+        c.S += 2 * int64_t(w.n_sub) * w.n_sub;
+        c.V += int64_t(w.n_sub + 1) * (w.n_sub + 1);
+    }
+    c.prec = cfg->precision;
+    c.esz = cfg->precision == FEWHA_FP64 ? 8 : 4;
+    c.alpha = cfg->alpha;
+    c.max_iter = cfg->max_iter;
+    c.k = cfg->recycle_k;
+    c.mode = cfg->recycle_mode;
+    c.project_all = cfg->project_all;
+    c.slots = cfg->recycle_k + cfg->max_iter;
+    c.ws = static_cast<char*>(d_workspace);
+    c.ws_bytes = bytes;
+    c.lay = lo;
+    hipStream_t s = as_stream(stream);
+    // zero the carried state and the scratch vectors
+    if (hipMemsetAsync(c.ws + lo.nodal, 0, lo.total - lo.nodal, s) != hipSuccess) {
+        g_setup_err = "hipMemsetAsync failed";
+        delete ctx;
+        return FEWHA_E_HIP;
+    }
+    st = fewha::build_tables(c, cfg, s);
+    if (st != FEWHA_OK) {
+        g_setup_err = c.err;
+        delete ctx;
+        return st;
+    }
+    *out = ctx;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_sizes(const fewha_ctx* ctx, int64_t* n_coeff, int64_t* n_slopes) {
+    if (!ctx) return FEWHA_E_INVAL;
+    if (n_coeff) *n_coeff = ctx->c.N;
+    if (n_slopes) *n_slopes = ctx->c.S;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_apply_A(fewha_ctx* ctx, const void* d_x, void* d_y, void* stream) {
+    if (!ctx || !d_x || !d_y) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    if (d_x == d_y) return fail(ctx, FEWHA_E_INVAL, "d_y must not alias d_x");
+    const fewha::Ctx& c = ctx->c;
+    if (c.prec == FEWHA_FP64)
+        fewha::launch_apply_M<double>(c, static_cast<const double*>(d_x), static_cast<double*>(d_y), as_stream(stream));
+    else
+        fewha::launch_apply_M<float>(c, static_cast<const float*>(d_x), static_cast<float*>(d_y), as_stream(stream));
+    return check_launch(ctx);
+}
+
+fewha_status fewha_rhs(fewha_ctx* ctx, const void* d_s, void* d_b, void* stream) {
+    if (!ctx || !d_s || !d_b) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    const fewha::Ctx& c = ctx->c;
+    if (c.prec == FEWHA_FP64)
+        fewha::launch_rhs<double>(c, static_cast<const double*>(d_s), static_cast<double*>(d_b), as_stream(stream));
+    else
+        fewha::launch_rhs<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_b), as_stream(stream));
+    return check_launch(ctx);
+}
+
+fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d_info, void* stream) {
+    if (!ctx || !d_s) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    fewha::Ctx& c = ctx->c;
+    auto* info = static_cast<fewha_solve_info*>(d_info);
+    if (c.prec == FEWHA_FP64)
+        fewha::launch_solve_frame<double>(c, static_cast<const double*>(d_s), static_cast<double*>(d_c), info,
+                                          as_stream(stream));
+    else
+        fewha::launch_solve_frame<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
+                                         as_stream(stream));
+    return check_launch(ctx);
+}
+
+fewha_status fewha_reset(fewha_ctx* ctx) {
+    if (!ctx) return FEWHA_E_INVAL;
+    ctx->c.first = true;
+    ctx->c.count = 0;
+    ctx->c.last_iters = 0;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_apply_piece(fewha_ctx* ctx, int32_t piece, const void* d_in, void* d_out, void* stream) {
+    if (!ctx || !d_in || !d_out) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    if (d_in == d_out) return fail(ctx, FEWHA_E_INVAL, "d_out must not alias d_in");
+    const fewha::Ctx& c = ctx->c;
+    hipStream_t s = as_stream(stream);
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        const T* in = static_cast<const T*>(d_in);
+        T* out = static_cast<T*>(d_out);
+        T* psi_n = c.at<T>(c.lay.psi_nodes);
+        switch (piece) {
+            case FEWHA_PIECE_WINV: fewha::launch_winv<T>(c, in, out, s); break;
+            case FEWHA_PIECE_WINVT: fewha::launch_winvt<T>(c, in, out, static_cast<const T*>(nullptr), s); break;
+            case FEWHA_PIECE_A: fewha::launch_fwd_slopes<T>(c, in, out, s); break;
+            case FEWHA_PIECE_AT:
+                fewha::launch_slopes_adj<T>(c, in, psi_n, 0, s);
+                fewha::launch_adj_gather<T>(c, psi_n, out, s);
+                break;
+        }
+    };
+    if (piece < FEWHA_PIECE_WINV || piece > FEWHA_PIECE_AT) return fail(ctx, FEWHA_E_INVAL, "unknown piece");
+    if (c.prec == FEWHA_FP64)
+        run(double{});
+    else
+        run(float{});
+    return check_launch(ctx);
+}
+
+fewha_status fewha_get_vector(fewha_ctx* ctx, int32_t which, void* d_out, void* stream) {
+    if (!ctx || !d_out) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    const fewha::Ctx& c = ctx->c;
+    size_t off;
+    if (which == 0)
+        off = c.lay.prior_a;
+    else if (which == 1)
+        off = c.lay.jinv;
+    else
+        return fail(ctx, FEWHA_E_INVAL, "which must be 0 (alpha D) or 1 (J^-1)");
+    if (hipMemcpyAsync(d_out, c.ws + off, c.esz * c.N, hipMemcpyDeviceToDevice, as_stream(stream)) != hipSuccess)
+        return fail(ctx, FEWHA_E_HIP, "hipMemcpyAsync failed");
+    return FEWHA_OK;
+}
+
+fewha_status fewha_state_size(const fewha_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return FEWHA_E_INVAL;
+    *bytes = ctx->c.lay.state_bytes;
+    return FEWHA_OK;
+}
+
+// State buffer: [256-byte header][slots x double (p_j, q_j)][c][r][b_prev][U slots][Q slots]
+fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream) {
+    if (!ctx || !d_dst) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    const fewha::Ctx& c = ctx->c;
+    hipStream_t s = as_stream(stream);
+    uint64_t* h = ctx->state_header;
+    std::memset(h, 0, sizeof(ctx->state_header));
+    h[0] = kStateMagic;
+    h[1] = uint64_t(c.N);
+    h[2] = uint64_t(c.slots);
+    h[3] = uint64_t(c.esz);
+    h[4] = uint64_t(c.head);
+    h[5] = uint64_t(c.count);
+    h[6] = uint64_t(c.last_iters);
+    h[7] = uint64_t(c.first ? 1 : 0);
+    char* dst = static_cast<char*>(d_dst);
+    const size_t vb = c.esz * c.N;
+    bool ok = hipMemcpyAsync(dst, h, 256, hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(dst + 256, c.ws + c.lay.scalars + offsetof(fewha::Scalars, gam), sizeof(double) * c.slots,
+                              hipMemcpyDeviceToDevice, s) == hipSuccess;
+    size_t o = 256 + sizeof(double) * c.slots;
+    for (size_t src : {c.lay.c, c.lay.r, c.lay.b_prev}) {
+        ok = ok && hipMemcpyAsync(dst + o, c.ws + src, vb, hipMemcpyDeviceToDevice, s) == hipSuccess;
+        o += vb;
+    }
+    ok = ok && hipMemcpyAsync(dst + o, c.ws + c.lay.ring_u, vb * c.slots, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    o += vb * c.slots;
+    ok = ok && hipMemcpyAsync(dst + o, c.ws + c.lay.ring_q, vb * c.slots, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    if (ok) ok = hipStreamSynchronize(s) == hipSuccess;   // the header is host memory
+    return ok ? FEWHA_OK : fail(ctx, FEWHA_E_HIP, "state copy failed");
+}
+
+fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream) {
+    if (!ctx || !d_src) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    fewha::Ctx& c = ctx->c;
+    hipStream_t s = as_stream(stream);
+    uint64_t h[32];
+    if (hipMemcpyAsync(h, d_src, 256, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail(ctx, FEWHA_E_HIP, "state header copy failed");
+    if (h[0] != kStateMagic || h[1] != uint64_t(c.N) || h[2] != uint64_t(c.slots) || h[3] != uint64_t(c.esz) ||
+        h[4] >= uint64_t(c.slots) || h[5] > uint64_t(c.slots))
+        return fail(ctx, FEWHA_E_STATE, "state buffer does not match this configuration");
+    const char* src = static_cast<const char*>(d_src);
+    const size_t vb = c.esz * c.N;
+    bool ok = hipMemcpyAsync(c.ws + c.lay.scalars + offsetof(fewha::Scalars, gam), src + 256, sizeof(double) * c.slots,
+                             hipMemcpyDeviceToDevice, s) == hipSuccess;
+    size_t o = 256 + sizeof(double) * c.slots;
+    for (size_t dst : {c.lay.c, c.lay.r, c.lay.b_prev}) {
+        ok = ok && hipMemcpyAsync(c.ws + dst, src + o, vb, hipMemcpyDeviceToDevice, s) == hipSuccess;
+        o += vb;
+    }
+    ok = ok && hipMemcpyAsync(c.ws + c.lay.ring_u, src + o, vb * c.slots, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    o += vb * c.slots;
+    ok = ok && hipMemcpyAsync(c.ws + c.lay.ring_q, src + o, vb * c.slots, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    if (!ok) return fail(ctx, FEWHA_E_HIP, "state copy failed");
+    c.head = int(h[4]);
+    c.count = int(h[5]);
+    c.last_iters = int(h[6]);
+    c.first = h[7] != 0;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_destroy(fewha_ctx* ctx) {
+    delete ctx;
+    return FEWHA_OK;
+}
+
+const char* fewha_last_error(const fewha_ctx* ctx) {
+    return ctx ? ctx->c.err.c_str() : g_setup_err.c_str();
+}
+
+}  // extern "C"

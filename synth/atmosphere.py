@@ -39,7 +39,7 @@ class FrozenFlowAtmosphere:
         self.dx = min(l.spacing for l in spec.layers) / 2.0
         extent = max(l.spacing * (l.n - 1) for l in spec.layers)
         n = 64
-        while n * self.dx < 2.0 * extent:
+        while n * self.dx < 1.25 * extent:
             n *= 2
         self.n = n
         self.heights = np.array([l.height for l in spec.layers])

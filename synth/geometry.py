@@ -194,6 +194,27 @@ def config_tiny(seed: int = 3, n: int = 16, levels: int = 3, n_sub: int = 8) -> 
     return spec
 
 
+def config_mixed(seed: int = 4) -> SystemSpec:
+    """Edge-case mix: layers of different grid sizes and level counts (one transformed down
+    to a 1x1 approximation), low-order 1x1 and 2x2 natural guide stars, a ragged 19x19
+    laser-guide-star sensor."""
+    rng = np.random.default_rng(seed)
+    D = 6.0
+    wfs = []
+    for ns, th, H in ((19, (15.0, 10.0), 90000.0), (1, (-20.0, 5.0), 0.0), (2, (5.0, -25.0), 0.0),
+                      (19, (0.0, 0.0), 0.0)):
+        mask = subaperture_mask(ns, D, 0.1 if ns > 2 else 0.0)
+        wfs.append(WfsSpec(ns, D / ns, th[0] * ARCSEC, th[1] * ARCSEC, H, mask))
+    layers = [LayerSpec(0.0, 0.5, 32, 5), LayerSpec(3000.0, 0.3, 16, 4), LayerSpec(9000.0, 0.2, 32, 2)]
+    spec = SystemSpec("mixed", D, 0.1, layers, wfs, alpha=1.5, r0=0.14, L0=30.0, max_iter=5,
+                      recycle_k=7, precision="fp64")
+    spec = fit_layer_grids(spec)
+    for w in spec.wfs:
+        m = np.concatenate([w.mask.ravel(), w.mask.ravel()])
+        w.weight = np.where(m, rng.uniform(0.5, 2.0, size=m.size), 0.0)
+    return spec
+
+
 def config_random_instance(rng: np.random.Generator, precision: str = "fp32") -> SystemSpec:
     """One instance of a ragged batch: telescope 8-39 m, 20-84 subapertures, 3-9 layers,
     1-6 guide stars mixing NGS and LGS, grids the next power of two of E / d_s (<= 256)."""

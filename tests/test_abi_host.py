@@ -1,0 +1,94 @@
+"""C-ABI library checks that need no GPU: the library loads, exports every declared symbol,
+and validates configurations on the host."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+import paper_2011_06842_amd as fw
+from paper_2011_06842_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fewha.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fewha_[a-z_A-Z]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fw.load_library()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(fw.EXPORTS)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the header structs have the C compiler's sizes and offsets."""
+    import subprocess
+    src = tmp_path / "probe.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "fewha.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(fewha_layer), sizeof(fewha_wfs), sizeof(fewha_config), sizeof(fewha_solve_info));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(fewha_wfs, slope_weight), offsetof(fewha_config, alpha),
+         offsetof(fewha_config, max_iter), offsetof(fewha_config, rel_tol), offsetof(fewha_config, precision));
+  return 0;
+}
+""")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    C = ctypes
+    want = [C.sizeof(_lib.fewha_layer), C.sizeof(_lib.fewha_wfs), C.sizeof(_lib.fewha_config),
+            C.sizeof(_lib.fewha_solve_info), _lib.fewha_wfs.slope_weight.offset, _lib.fewha_config.alpha.offset,
+            _lib.fewha_config.max_iter.offset, _lib.fewha_config.rel_tol.offset, _lib.fewha_config.precision.offset]
+    assert [int(v) for v in out] == want
+
+
+def _spec():
+    spec = synth.config_tiny()
+    return spec
+
+
+def test_workspace_size_is_host_only_and_grows_with_recycling():
+    spec = _spec()
+    n1 = fw.fewha_workspace_size(spec)
+    spec.recycle_k += 4
+    n2 = fw.fewha_workspace_size(spec)
+    N = sum(l.n ** 2 for l in spec.layers)
+    assert n2 - n1 >= 2 * 4 * N * 8          # four more (p, q) pairs of FP64 vectors
+    spec.precision = "fp32"
+    assert fw.fewha_workspace_size(spec) < n2
+
+
+@pytest.mark.parametrize("mutate, needle", [
+    (lambda s: setattr(s.layers[0], "n", 24), "power of two"),
+    (lambda s: setattr(s.layers[0], "levels", 9), "levels"),
+    (lambda s: setattr(s.layers[1], "spacing", s.layers[1].spacing * 0.5), "footprint"),
+    (lambda s: setattr(s, "max_iter", 0), "max_iter"),
+    (lambda s: setattr(s, "recycle_k", 99), "recycle_k"),
+    (lambda s: setattr(s.wfs[1], "lgs_height", 5000.0), "laser guide star"),
+    (lambda s: s.wfs[0].weight.__setitem__(3, -1.0), "weights"),
+    (lambda s: setattr(s, "project_all", True) or setattr(s, "recycle_mode", "paper"), "project_all"),
+])
+def test_invalid_configurations_are_rejected(mutate, needle):
+    spec = _spec()
+    mutate(spec)
+    with pytest.raises(fw.FewhaError) as e:
+        fw.fewha_workspace_size(spec)
+    assert "FEWHA_E_INVAL" in str(e.value) and needle in str(e.value)
+
+
+def test_missing_weights_rejected_by_binding():
+    spec = synth.config_small()        # weights are set by the simulator's noise calibration
+    with pytest.raises(fw.FewhaError):
+        fw.fewha_workspace_size(spec)

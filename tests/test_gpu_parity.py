@@ -1,0 +1,188 @@
+"""GPU (HIP, through the C ABI) versus the FP64 oracle, element by element on the same
+seeded inputs.  Bars: relative error <= 1e-12 (operators) / 1e-10 (frames) in FP64 and
+<= 5e-5 with the FP32 operator; bitwise for determinism and checkpoint/resume."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import AugmentedReconstructor, OracleSystem
+import paper_2011_06842_amd as fw
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _calibrated(spec, frames, seed):
+    seq = synth.make_sequence(spec, frames, seed=seed)
+    return spec, seq
+
+
+_CACHE = {}
+
+
+def system(name, precision="fp64"):
+    key = (name, precision)
+    if key not in _CACHE:
+        if name == "tiny":
+            spec, seq = synth.config_tiny(), None
+        elif name == "tiny_full_levels":
+            spec, seq = synth.config_tiny(n=8, levels=3, n_sub=12), None
+        elif name == "mixed":
+            spec, seq = synth.config_mixed(), None
+        elif name == "small":
+            spec, seq = _calibrated(synth.config_small(), 12, seed=5)
+        elif name == "elt":
+            spec, seq = _calibrated(synth.config_elt_mcao(precision=precision), 8, seed=6)
+        spec.precision = precision
+        if seq is None:
+            rng = np.random.default_rng(17)
+            base = rng.standard_normal(synth.n_slopes(spec))
+            seq = np.stack([base + 0.1 * t * rng.standard_normal(base.size) for t in range(8)])
+            m = np.concatenate([np.concatenate([w.mask.ravel(), w.mask.ravel()]) for w in spec.wfs])
+            seq = seq * m
+        _CACHE[key] = (spec, seq, OracleSystem(spec))
+    return _CACHE[key]
+
+
+OPS_CASES = ["tiny", "tiny_full_levels", "mixed", "small", "elt"]
+
+
+@pytest.mark.parametrize("name", OPS_CASES)
+def test_operator_pieces_fp64(name):
+    spec, seq, sysm = system(name)
+    ctx = fw.FewhaContext(spec, device=DEV)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(sysm.N)
+    s = rng.standard_normal(sysm.S)
+    phis = sysm.W_inv(x)
+    np.testing.assert_array_less(rel(host(ctx.fewha_apply_piece(fw.PIECE_WINV, dev(x, np.float64))),
+                                     np.concatenate([p.ravel() for p in phis])), 1e-13)
+    img = rng.standard_normal(sysm.N)
+    np.testing.assert_array_less(rel(host(ctx.fewha_apply_piece(fw.PIECE_WINVT, dev(img, np.float64))),
+                                     sysm.W_invT(sysm.split_layers(img))), 1e-13)
+    np.testing.assert_array_less(rel(host(ctx.fewha_apply_piece(fw.PIECE_A, dev(img, np.float64))),
+                                     sysm.A(sysm.split_layers(img))), 1e-13)
+    np.testing.assert_array_less(rel(host(ctx.fewha_apply_piece(fw.PIECE_AT, dev(s, np.float64))),
+                                     np.concatenate([p.ravel() for p in sysm.A_T(s)])), 1e-13)
+
+
+@pytest.mark.parametrize("name", OPS_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_prior_preconditioner_apply_and_rhs(name, precision):
+    spec, seq, sysm = system(name, precision)
+    ctx = fw.FewhaContext(spec, device=DEV)
+    dt = np.float64 if precision == "fp64" else np.float32
+    tol_vec = 1e-13 if precision == "fp64" else 2e-7
+    tol_op = 1e-12 if precision == "fp64" else 2e-5
+    D = sysm.prior()
+    np.testing.assert_allclose(host(ctx.fewha_get_vector(0)), sysm.alpha * D, rtol=tol_vec)
+    np.testing.assert_allclose(host(ctx.fewha_get_vector(1)), 1.0 / sysm.diag_M(D), rtol=tol_vec * 10)
+    x = np.random.default_rng(2).standard_normal(sysm.N)
+    y = host(ctx.fewha_apply_A(dev(x, dt)))
+    assert rel(y, sysm.apply_M(x.astype(dt).astype(np.float64), D)) <= tol_op
+    b = host(ctx.fewha_rhs(dev(seq[0], dt)))
+    assert rel(b, sysm.rhs(seq[0].astype(dt).astype(np.float64))) <= tol_op
+
+
+def _run_sequence(spec, seq, sysm, frames, ctx=None, **kw):
+    dt = np.float64 if spec.precision == "fp64" else np.float32
+    ctx = ctx or fw.FewhaContext(spec, device=DEV)
+    ref = AugmentedReconstructor(sysm, **kw)
+    info = ctx.new_info()
+    errs, infos = [], []
+    for t in range(frames):
+        c_ref, i_ref = ref.solve(seq[t].astype(dt).astype(np.float64))
+        c = host(ctx.fewha_solve_aug(dev(seq[t], dt), info=info))
+        errs.append(rel(c, c_ref))
+        gi = fw.decode_info(info)
+        infos.append((gi, i_ref))
+    return errs, infos
+
+
+@pytest.mark.parametrize("name", ["tiny", "mixed", "small"])
+@pytest.mark.parametrize("mode, project_all", [("galerkin", False), ("paper", False), ("galerkin", True)])
+def test_frame_sequence_fp64(name, mode, project_all):
+    spec, seq, sysm = system(name)
+    spec = spec.copy(recycle_mode=mode, project_all=project_all)
+    sysm = OracleSystem(spec)
+    errs, infos = _run_sequence(spec, seq, sysm, len(seq))
+    assert max(errs) <= 1e-10, errs
+    for gi, ri in infos:
+        assert gi["iters"] == ri["iters"] and gi["recycle_used"] == ri["recycle_used"]
+        assert gi["dropped"] == ri["dropped"] and gi["flags"] == 0
+        assert abs(gi["rel_res"] - ri["rel_res"]) <= 1e-9 * ri["rel_res"]
+
+
+def test_plain_pcg_k0_fp64():
+    spec, seq, sysm = system("small")
+    spec = spec.copy(recycle_k=0)
+    errs, _ = _run_sequence(spec, seq, OracleSystem(spec), 6)
+    assert max(errs) <= 1e-10, errs
+
+
+def test_frame_sequence_elt_fp32():
+    spec, seq, sysm = system("elt", "fp32")
+    errs, infos = _run_sequence(spec, seq, sysm, len(seq))
+    assert max(errs) <= 5e-5, errs
+    for gi, ri in infos:
+        assert gi["recycle_used"] == ri["recycle_used"]
+
+
+def test_frame_sequence_elt_fp64():
+    spec, seq, sysm = system("elt", "fp64")
+    errs, _ = _run_sequence(spec, seq, sysm, 4)
+    assert max(errs) <= 1e-10, errs
+
+
+def test_reset_restarts_from_true_residual():
+    spec, seq, sysm = system("small")
+    ctx = fw.FewhaContext(spec, device=DEV)
+    ref = AugmentedReconstructor(sysm)
+    for t in range(6):
+        if t == 3:
+            ctx.fewha_reset()
+            ref.reset()
+        c_ref, _ = ref.solve(seq[t])
+        c = host(ctx.fewha_solve_aug(dev(seq[t], np.float64)))
+        assert rel(c, c_ref) <= 1e-10
+
+
+def test_checkpoint_resume_and_determinism_bitwise():
+    spec, seq, sysm = system("small")
+    a = fw.FewhaContext(spec, device=DEV)
+    outs = [host(a.fewha_solve_aug(dev(seq[t], np.float64))) for t in range(8)]
+    b = fw.FewhaContext(spec, device=DEV)
+    for t in range(4):
+        b.fewha_solve_aug(dev(seq[t], np.float64))
+    state = b.fewha_get_state()
+    c = fw.FewhaContext(spec, device=DEV)
+    c.fewha_set_state(state)
+    for t in range(4, 8):
+        out = host(c.fewha_solve_aug(dev(seq[t], np.float64)))
+        assert np.array_equal(out, outs[t]), t
+    d = fw.FewhaContext(spec, device=DEV)
+    again = [host(d.fewha_solve_aug(dev(seq[t], np.float64))) for t in range(8)]
+    assert all(np.array_equal(x, y) for x, y in zip(outs, again))
+
+
+def test_state_from_other_configuration_rejected():
+    spec, seq, sysm = system("small")
+    a = fw.FewhaContext(spec, device=DEV)
+    b = fw.FewhaContext(system("tiny")[0], device=DEV)
+    with pytest.raises(fw.FewhaError, match="FEWHA_E_STATE"):
+        b.fewha_set_state(a.fewha_get_state())
