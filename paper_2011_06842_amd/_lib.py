@@ -23,7 +23,8 @@ STATUS = {0: "FEWHA_OK", 1: "FEWHA_E_INVAL", 2: "FEWHA_E_NOMEM", 3: "FEWHA_E_HIP
 
 EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
            "fewha_solve_aug", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
-           "fewha_get_state", "fewha_set_state", "fewha_destroy", "fewha_last_error"]
+           "fewha_get_state", "fewha_set_state", "fewha_profile", "fewha_profile_read", "fewha_kernel_name",
+           "fewha_destroy", "fewha_last_error"]
 
 
 class fewha_layer(C.Structure):
@@ -80,6 +81,9 @@ def load_library(path: str = LIB_PATH):
         "fewha_state_size": ([vp, C.POINTER(C.c_size_t)], st),
         "fewha_get_state": ([vp, vp, vp], st),
         "fewha_set_state": ([vp, vp, vp], st),
+        "fewha_profile": ([vp, C.c_int32], st),
+        "fewha_profile_read": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)], st),
+        "fewha_kernel_name": ([C.c_int32], C.c_char_p),
         "fewha_destroy": ([vp], st),
         "fewha_last_error": ([vp], C.c_char_p),
     }
@@ -245,6 +249,18 @@ class FewhaContext:
 
     def fewha_set_state(self, buf, stream=None):
         _check(self.lib.fewha_set_state(self.ctx, _ptr(buf), _stream(stream)), self.ctx)
+
+    def fewha_profile(self, enable=True):
+        _check(self.lib.fewha_profile(self.ctx, int(bool(enable))), self.ctx)
+
+    def fewha_profile_read(self) -> dict:
+        """{kernel family: (total ms, launches)} accumulated since fewha_profile(True)."""
+        n = 32
+        ms = (C.c_double * n)()
+        ln = (C.c_int64 * n)()
+        cnt = C.c_int32()
+        _check(self.lib.fewha_profile_read(self.ctx, ms, ln, n, C.byref(cnt)), self.ctx)
+        return {self.lib.fewha_kernel_name(i).decode(): (ms[i], ln[i]) for i in range(cnt.value)}
 
     def fewha_destroy(self):
         if getattr(self, "ctx", None):

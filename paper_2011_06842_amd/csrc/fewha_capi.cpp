@@ -24,9 +24,13 @@ fewha_status fail(fewha_ctx* ctx, fewha_status st, const std::string& msg) {
     return st;
 }
 
-fewha_status check_launch(fewha_ctx* ctx) {
+fewha_status check_launch(fewha_ctx* ctx, hipStream_t s) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    if (ctx->c.prof.on) {
+        const hipError_t p = fewha::profiler_collect(ctx->c, s);
+        if (p != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("profiler: ") + hipGetErrorString(p));
+    }
     return FEWHA_OK;
 }
 
@@ -123,10 +127,12 @@ fewha_status fewha_apply_A(fewha_ctx* ctx, const void* d_x, void* d_y, void* str
     if (d_x == d_y) return fail(ctx, FEWHA_E_INVAL, "d_y must not alias d_x");
     const fewha::Ctx& c = ctx->c;
     if (c.prec == FEWHA_FP64)
-        fewha::launch_apply_M<double>(c, static_cast<const double*>(d_x), static_cast<double*>(d_y), as_stream(stream));
+        fewha::launch_apply_M<double>(c, static_cast<const double*>(d_x), static_cast<double*>(d_y), nullptr,
+                                      as_stream(stream));
     else
-        fewha::launch_apply_M<float>(c, static_cast<const float*>(d_x), static_cast<float*>(d_y), as_stream(stream));
-    return check_launch(ctx);
+        fewha::launch_apply_M<float>(c, static_cast<const float*>(d_x), static_cast<float*>(d_y), nullptr,
+                                     as_stream(stream));
+    return check_launch(ctx, as_stream(stream));
 }
 
 fewha_status fewha_rhs(fewha_ctx* ctx, const void* d_s, void* d_b, void* stream) {
@@ -136,7 +142,7 @@ fewha_status fewha_rhs(fewha_ctx* ctx, const void* d_s, void* d_b, void* stream)
         fewha::launch_rhs<double>(c, static_cast<const double*>(d_s), static_cast<double*>(d_b), as_stream(stream));
     else
         fewha::launch_rhs<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_b), as_stream(stream));
-    return check_launch(ctx);
+    return check_launch(ctx, as_stream(stream));
 }
 
 fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d_info, void* stream) {
@@ -149,7 +155,7 @@ fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d
     else
         fewha::launch_solve_frame<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
                                          as_stream(stream));
-    return check_launch(ctx);
+    return check_launch(ctx, as_stream(stream));
 }
 
 fewha_status fewha_reset(fewha_ctx* ctx) {
@@ -172,7 +178,9 @@ fewha_status fewha_apply_piece(fewha_ctx* ctx, int32_t piece, const void* d_in, 
         T* psi_n = c.at<T>(c.lay.psi_nodes);
         switch (piece) {
             case FEWHA_PIECE_WINV: fewha::launch_winv<T>(c, in, out, s); break;
-            case FEWHA_PIECE_WINVT: fewha::launch_winvt<T>(c, in, out, static_cast<const T*>(nullptr), s); break;
+            case FEWHA_PIECE_WINVT:
+                fewha::launch_winvt<T>(c, in, out, static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), nullptr, s);
+                break;
             case FEWHA_PIECE_A: fewha::launch_fwd_slopes<T>(c, in, out, s); break;
             case FEWHA_PIECE_AT:
                 fewha::launch_slopes_adj<T>(c, in, psi_n, 0, s);
@@ -185,7 +193,7 @@ fewha_status fewha_apply_piece(fewha_ctx* ctx, int32_t piece, const void* d_in, 
         run(double{});
     else
         run(float{});
-    return check_launch(ctx);
+    return check_launch(ctx, as_stream(stream));
 }
 
 fewha_status fewha_get_vector(fewha_ctx* ctx, int32_t which, void* d_out, void* stream) {
@@ -271,7 +279,36 @@ fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream) {
     return FEWHA_OK;
 }
 
+fewha_status fewha_profile(fewha_ctx* ctx, int32_t enable) {
+    if (!ctx) return FEWHA_E_INVAL;
+    fewha::Profiler& p = ctx->c.prof;
+    p.on = enable != 0;
+    p.pending.clear();
+    for (int i = 0; i < fewha::KID_COUNT; ++i) {
+        p.ms[i] = 0;
+        p.launches[i] = 0;
+    }
+    return FEWHA_OK;
+}
+
+fewha_status fewha_profile_read(const fewha_ctx* ctx, double* ms, int64_t* launches, int32_t n, int32_t* n_out) {
+    if (!ctx) return FEWHA_E_INVAL;
+    const fewha::Profiler& p = ctx->c.prof;
+    for (int i = 0; i < n && i < fewha::KID_COUNT; ++i) {
+        if (ms) ms[i] = p.ms[i];
+        if (launches) launches[i] = p.launches[i];
+    }
+    if (n_out) *n_out = fewha::KID_COUNT;
+    return FEWHA_OK;
+}
+
+const char* fewha_kernel_name(int32_t i) {
+    return (i >= 0 && i < fewha::KID_COUNT) ? fewha::kKernelNames[i] : nullptr;
+}
+
 fewha_status fewha_destroy(fewha_ctx* ctx) {
+    if (ctx)
+        for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
     delete ctx;
     return FEWHA_OK;
 }

@@ -1,0 +1,847 @@
+// HIP kernels (gfx950 / CDNA4) of the system operator M = W^-T A^T C^-1 A W^-1 + alpha D
+// (Sec. 3) and of the right-hand side b = W^-T A^T C^-1 s.
+//
+//   W^-1 (synthesis, Sec. 3):  k_idwt_coarse  one workgroup per layer; every level whose block
+//                                             fits the coarse block, separable passes in LDS
+//                              k_idwt_step    one launch per larger block size; 32x32 output tiles,
+//                                             separable passes in LDS from a 36x36 coefficient halo
+//   A^T C^-1 A (Sec. 2):       k_data_term    per (sensor, 16x16 node tile): bilinear propagation
+//                                             from every layer (NGS shift, LGS cone), Shack-Hartmann
+//                                             slopes, noise weights, Shack-Hartmann adjoint; the
+//                                             slopes never leave LDS
+//                              k_adj_gather   per 16x16 layer tile: exact transpose of the bilinear
+//                                             propagation as a gather from LDS-staged sensor
+//                                             rectangles (no atomics, deterministic)
+//   W^-T + alpha D:            k_dwt_step / k_dwt_coarse, the mirror images of the synthesis,
+//                                             with the prior and an optional (x, Mx) partial fused
+//                                             into the final coefficients
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fewha_device.h"
+#include "fewha_internal.h"
+
+namespace fewha {
+
+namespace {
+
+__device__ __forceinline__ int ilog2i(int v) { return 31 - __clz(v); }
+
+// Filter taps split by parity, so that every index is a compile-time constant (a tap index
+// that varies across lanes would otherwise be fetched from memory inside the loops).
+template <typename T>
+struct Taps {
+    T he[3], ho[3], ge[3], go[3], h[6], g[6];
+    __device__ __forceinline__ explicit Taps(const Filt<T>& f) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            he[k] = f.h[2 * k];
+            ho[k] = f.h[2 * k + 1];
+            ge[k] = f.g[2 * k];
+            go[k] = f.g[2 * k + 1];
+        }
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            h[t] = f.h[t];
+            g[t] = f.g[t];
+        }
+    }
+};
+
+// ------------------------------------------------------------------ wavelet synthesis
+
+// Levels levels..coarse_lev of one layer in LDS.  Every coefficient of those levels lies in
+// the top-left (n >> (coarse_lev-1))^2 block of the Mallat pyramid, so the block is loaded
+// once; each level then synthesises its top-left block in place (its details are never
+// overwritten by coarser levels).  1-D periodic synthesis of a 2m block:
+// x_i = sum_{t = i mod 2} h_t a_{((i-t)/2) mod m} + g_t d_{((i-t)/2) mod m}, columns then rows.
+template <typename T>
+__global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
+                                                                 const T* __restrict__ coef, T* __restrict__ ll_out,
+                                                                 T* __restrict__ phi) {
+    constexpr int CB = CoarseBlock<T>::value;
+    __shared__ T A[CB * CB];
+    __shared__ T B[CB * CB];
+    const LayerDev d = lays[blockIdx.x];
+    const int n = d.n, lc = d.coarse_lev, levels = d.levels;
+    if (levels < lc) return;
+    const T* C = coef + d.off;
+    const Taps<T> tp(f);
+    const int nb0 = n >> (lc - 1), lg0 = ilog2i(nb0);
+    stage_to_lds<kCoarseThreads, CB * CB / kCoarseThreads, T>(
+        nb0 * nb0, [&](int e) { return C[(e >> lg0) * n + (e & (nb0 - 1))]; },
+        [&](int e, T v) { A[(e >> lg0) * CB + (e & (nb0 - 1))] = v; });
+    __syncthreads();
+    for (int lev = levels; lev >= lc; --lev) {
+        const int nb = n >> (lev - 1), m = nb >> 1, lg = ilog2i(nb);
+        for (int e = threadIdx.x; e < nb * nb; e += kCoarseThreads) {
+            const int y = e >> lg, x = e & (nb - 1), par = y & 1;
+            T acc = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int ky = (((y - par) >> 1) - k) & (m - 1);
+                acc += (par ? tp.ho[k] : tp.he[k]) * A[ky * CB + x] + (par ? tp.go[k] : tp.ge[k]) * A[(m + ky) * CB + x];
+            }
+            B[y * CB + x] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * nb; e += kCoarseThreads) {
+            const int y = e >> lg, x = e & (nb - 1), par = x & 1;
+            T acc = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int kx = (((x - par) >> 1) - k) & (m - 1);
+                acc += (par ? tp.ho[k] : tp.he[k]) * B[y * CB + kx] + (par ? tp.go[k] : tp.ge[k]) * B[y * CB + m + kx];
+            }
+            A[y * CB + x] = acc;
+        }
+        __syncthreads();
+    }
+    T* out = (lc == 1 ? phi : ll_out) + d.off;
+    const T s = lc == 1 ? T(d.inv_delta) : T(1);
+    for (int e = threadIdx.x; e < nb0 * nb0; e += kCoarseThreads) {
+        const int r = e >> lg0, c = e & (nb0 - 1);
+        out[r * n + c] = A[r * CB + c] * s;
+    }
+}
+
+// One synthesis level of block size nbs (> the coarse block) on the listed layers; 32x32
+// output tile per workgroup.  The LL band comes from the previous step (or from the
+// coefficients when this is the layer's coarsest level); the final level writes phi / delta.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restrict__ lays, StepLayers sl, int nbs,
+                                                         Filt<T> f, const T* __restrict__ coef,
+                                                         const T* __restrict__ ll_in, T* __restrict__ ll_out,
+                                                         T* __restrict__ phi) {
+    constexpr int H = kST / 2 + 2;   // coefficient rows (per band) feeding one tile
+    __shared__ T R[2 * H][2 * H + 1];
+    __shared__ T I[kST][2 * H + 1];
+    const int tx = nbs / kST, tiles = tx * tx;
+    const int li = blockIdx.x / tiles, tile = blockIdx.x - li * tiles;
+    const LayerDev d = lays[sl.l[li]];
+    const int n = d.n;
+    const int lev = ilog2i(n / nbs) + 1;
+    const int M = nbs >> 1;
+    const int y0 = (tile / tx) * kST, x0 = (tile % tx) * kST;
+    const T* C = coef + d.off;
+    const T* LL = (lev == d.levels ? coef : ll_in) + d.off;
+    const int ky0 = (y0 >> 1) - 2, kx0 = (x0 >> 1) - 2;
+    const Taps<T> tp(f);
+    stage_to_lds<kThreads, (4 * H * H + kThreads - 1) / kThreads, T>(
+        4 * H * H,
+        [&](int e) {
+            const int rr = e / (2 * H), cc = e - rr * (2 * H);
+            const int hr = rr >= H, hc = cc >= H;
+            const int kr = (ky0 + rr - H * hr) & (M - 1), kc = (kx0 + cc - H * hc) & (M - 1);
+            return (!hr && !hc) ? LL[kr * n + kc] : C[(kr + M * hr) * n + kc + M * hc];
+        },
+        [&](int e, T v) { R[e / (2 * H)][e % (2 * H)] = v; });
+    __syncthreads();
+    for (int e = threadIdx.x; e < kST * 2 * H; e += kThreads) {
+        const int yy = e / (2 * H), cc = e - yy * (2 * H), par = yy & 1;
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int kr = ((yy - par) >> 1) - k + 2;
+            acc += (par ? tp.ho[k] : tp.he[k]) * R[kr][cc] + (par ? tp.go[k] : tp.ge[k]) * R[H + kr][cc];
+        }
+        I[yy][cc] = acc;
+    }
+    __syncthreads();
+    const T s = T(d.inv_delta);
+    for (int e = threadIdx.x; e < kST * kST; e += kThreads) {
+        const int yy = e / kST, xx = e - yy * kST, par = xx & 1;
+        T acc = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int kc = ((xx - par) >> 1) - k + 2;
+            acc += (par ? tp.ho[k] : tp.he[k]) * I[yy][kc] + (par ? tp.go[k] : tp.ge[k]) * I[yy][H + kc];
+        }
+        const size_t o = size_t(d.off) + size_t(y0 + yy) * n + x0 + xx;
+        if (lev == 1)
+            phi[o] = acc * s;
+        else
+            ll_out[o] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ wavelet analysis
+
+// One analysis level of block size nbs on the listed layers: 16x16 coefficients of every band
+// per tile, rows then columns from a 36x36 halo, a_k = sum_t h_t x_{(2k+t) mod nbs}.  Final
+// coefficients are scaled by 1/delta and get + (alpha D)_i xprior_i; the partial of
+// (out, xdot) over them goes to dotpart[block].  The prior and x operands are requested
+// before the halo so that their latency overlaps it.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restrict__ lays, StepLayers sl, int nbs,
+                                                        Filt<T> f, const T* __restrict__ img,
+                                                        const T* __restrict__ ll_in, T* __restrict__ ll_out,
+                                                        T* __restrict__ out, const T* __restrict__ prior_a,
+                                                        const T* __restrict__ xprior, const T* __restrict__ xdot,
+                                                        double* __restrict__ dotpart) {
+    constexpr int W = 2 * kAT + 4;
+    __shared__ T R[W][W + 1];
+    __shared__ T I[W][2 * kAT + 1];
+    const int M = nbs >> 1, tx = M / kAT, tiles = tx * tx;
+    const int li = blockIdx.x / tiles, tile = blockIdx.x - li * tiles;
+    const LayerDev d = lays[sl.l[li]];
+    const int n = d.n;
+    const int lev = ilog2i(n / nbs) + 1;
+    const int ky0 = (tile / tx) * kAT, kx0 = (tile % tx) * kAT;
+    const int ky = threadIdx.x / kAT, kx = threadIdx.x % kAT;   // 256 threads = 16 x 16
+    const int gy = ky0 + ky, gx = kx0 + kx;
+    const bool fin_ll = lev == d.levels;
+    const size_t base = size_t(d.off);
+    const size_t o[4] = {base + size_t(gy) * n + M + gx, base + size_t(M + gy) * n + gx,
+                         base + size_t(M + gy) * n + M + gx, base + size_t(gy) * n + gx};
+    const int nout = fin_ll ? 4 : 3;
+    T pa[4] = {0, 0, 0, 0}, xp[4] = {0, 0, 0, 0}, xd[4] = {0, 0, 0, 0};
+    for (int k = 0; k < nout; ++k) {
+        if (xprior) {
+            pa[k] = prior_a[o[k]];
+            xp[k] = xprior[o[k]];
+        }
+        if (xdot) xd[k] = xdot[o[k]];
+    }
+    const T* src = (lev == 1 ? img : ll_in) + d.off;
+    const Taps<T> tp(f);
+    stage_to_lds<kThreads, (W * W + kThreads - 1) / kThreads, T>(
+        W * W, [&](int e) { return src[((2 * ky0 + e / W) & (nbs - 1)) * n + ((2 * kx0 + e % W) & (nbs - 1))]; },
+        [&](int e, T v) { R[e / W][e % W] = v; });
+    __syncthreads();
+    for (int e = threadIdx.x; e < W * 2 * kAT; e += kThreads) {
+        const int rr = e / (2 * kAT), kk = e - rr * (2 * kAT);
+        const int k = kk & (kAT - 1);
+        const bool hi = kk >= kAT;
+        T acc = 0;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) acc += (hi ? tp.g[t] : tp.h[t]) * R[rr][2 * k + t];
+        I[rr][kk] = acc;
+    }
+    __syncthreads();
+    T ll = 0, yh = 0, xh = 0, hh = 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const T lo = I[2 * ky + t][kx], hi = I[2 * ky + t][kAT + kx];
+        ll += tp.h[t] * lo;
+        yh += tp.g[t] * lo;
+        xh += tp.h[t] * hi;
+        hh += tp.g[t] * hi;
+    }
+    const T s = T(d.inv_delta);
+    const T v[4] = {xh, yh, hh, ll};
+    double dot = 0;
+    for (int k = 0; k < nout; ++k) {
+        T val = v[k] * s;
+        if (xprior) val += pa[k] * xp[k];
+        out[o[k]] = val;
+        dot += double(val) * double(xd[k]);
+    }
+    if (!fin_ll) ll_out[o[3]] = ll;
+    if (dotpart) {
+        const double vv[1] = {dot};
+        block_partials<1>(vv, dotpart, 0, 0, blockIdx.x);
+    }
+}
+
+// Levels coarse_lev..levels of one layer in LDS (mirror of k_idwt_coarse).  After the last
+// level the block holds the whole coarse Mallat pyramid; it is written once, each thread
+// owning fixed positions whose prior and x operands it requested at kernel start.
+template <typename T>
+__global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
+                                                                const T* __restrict__ img, const T* __restrict__ ll_in,
+                                                                T* __restrict__ out, const T* __restrict__ prior_a,
+                                                                const T* __restrict__ xprior,
+                                                                const T* __restrict__ xdot,
+                                                                double* __restrict__ dotpart) {
+    constexpr int CB = CoarseBlock<T>::value;
+    constexpr int PPT = CB * CB / kCoarseThreads;   // positions per thread
+    __shared__ T A[CB * CB];
+    __shared__ T B[CB * CB];
+    const LayerDev d = lays[blockIdx.x];
+    const int n = d.n, lc = d.coarse_lev, levels = d.levels;
+    double dot = 0;
+    if (levels >= lc) {
+        const int nb0 = n >> (lc - 1);
+        T pa[PPT], xp[PPT], xd[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e = threadIdx.x + k * kCoarseThreads;
+            pa[k] = xp[k] = xd[k] = 0;
+            if (e < nb0 * nb0) {
+                const size_t o = size_t(d.off) + size_t(e / nb0) * n + (e % nb0);
+                if (xprior) {
+                    pa[k] = prior_a[o];
+                    xp[k] = xprior[o];
+                }
+                if (xdot) xd[k] = xdot[o];
+            }
+        }
+        const T* src = (lc == 1 ? img : ll_in) + d.off;
+        const Taps<T> tp(f);
+        const int lg0 = ilog2i(nb0);
+        stage_to_lds<kCoarseThreads, CB * CB / kCoarseThreads, T>(
+            nb0 * nb0, [&](int e) { return src[(e >> lg0) * n + (e & (nb0 - 1))]; },
+            [&](int e, T v) { A[(e >> lg0) * CB + (e & (nb0 - 1))] = v; });
+        __syncthreads();
+        for (int lev = lc; lev <= levels; ++lev) {
+            const int nb = n >> (lev - 1), m = nb >> 1, lgm = ilog2i(m), lg = lgm + 1;
+            for (int e = threadIdx.x; e < nb * m; e += kCoarseThreads) {   // rows: [a | d]
+                const int y = e >> lgm, k = e & (m - 1);
+                T lo = 0, hi = 0;
+#pragma unroll
+                for (int t = 0; t < 6; ++t) {
+                    const T v = A[y * CB + ((2 * k + t) & (nb - 1))];
+                    lo += tp.h[t] * v;
+                    hi += tp.g[t] * v;
+                }
+                B[y * CB + k] = lo;
+                B[y * CB + m + k] = hi;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < m * nb; e += kCoarseThreads) {   // columns
+                const int k = e >> lg, x = e & (nb - 1);
+                T lo = 0, hi = 0;
+#pragma unroll
+                for (int t = 0; t < 6; ++t) {
+                    const T v = B[((2 * k + t) & (nb - 1)) * CB + x];
+                    lo += tp.h[t] * v;
+                    hi += tp.g[t] * v;
+                }
+                A[k * CB + x] = lo;
+                A[(m + k) * CB + x] = hi;
+            }
+            __syncthreads();
+        }
+        const T s = T(d.inv_delta);
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e = threadIdx.x + k * kCoarseThreads;
+            if (e < nb0 * nb0) {
+                const int r = e >> lg0, c = e & (nb0 - 1);
+                T val = A[r * CB + c] * s;
+                if (xprior) val += pa[k] * xp[k];
+                out[size_t(d.off) + size_t(r) * n + c] = val;
+                dot += double(val) * double(xd[k]);
+            }
+        }
+    }
+    if (dotpart) {
+        __shared__ double sh[kCoarseThreads / 64];
+        const double w = wave_sum(dot);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0;
+            for (int k = 0; k < kCoarseThreads / 64; ++k) t += sh[k];
+            dotpart[blockIdx.x] = t;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ tomography (Sec. 2)
+
+__device__ __forceinline__ int find_sensor(const WfsDev* __restrict__ wfs, int G, int tile) {
+    int g = 0;
+    while (g + 1 < G && wfs[g + 1].tile_off <= tile) ++g;
+    return g;
+}
+
+// Fused Gamma^T C^-1 Gamma P per sensor tile: wavefront on the tile plus a one-node halo,
+// slopes on the (kTile+1)^2 subapertures touching it, adjoint onto the kTile^2 nodes.  The
+// bilinear cell tables of the tile's rows and columns are staged in LDS for every layer, and
+// each node's layer sum is split over kLayerGroups threads (layers l = lg mod kLayerGroups),
+// combined in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __restrict__ wfs, int G,
+                                                             const LayerDev* __restrict__ lays, int L,
+                                                             const PairDev* __restrict__ pairs,
+                                                             const int32_t* __restrict__ cidx,
+                                                             const T* __restrict__ frac, const T* __restrict__ phi,
+                                                             const T* __restrict__ w, T* __restrict__ psi) {
+    constexpr int E = kTile + 2, S1 = kTile + 1;
+    __shared__ T spart[kLayerGroups][E * E];
+    __shared__ T stx[S1 * S1], sty[S1 * S1];
+    __shared__ int32_t srow[FEWHA_MAX_LAYERS][E], scol[FEWHA_MAX_LAYERS][E];
+    __shared__ T sfy[FEWHA_MAX_LAYERS][E], sfx[FEWHA_MAX_LAYERS][E];
+    const int g = find_sensor(wfs, G, blockIdx.x);
+    const WfsDev W = wfs[g];
+    const int ns = W.ns, np = ns + 1;
+    const int tl = blockIdx.x - W.tile_off;
+    const int i0 = (tl / W.tiles_x) * kTile, j0 = (tl % W.tiles_x) * kTile;
+    for (int e = threadIdx.x; e < L * 2 * E; e += kDataThreads) {
+        const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, k = q - col * E;
+        const int node = (col ? j0 : i0) - 1 + k;
+        const int nn = node < 0 ? 0 : (node > ns ? ns : node);     // clamped: halo nodes outside are unused
+        const size_t o = size_t(pairs[g * L + l].fwd_off) + col * np + nn;
+        const int32_t ci = cidx[o];
+        const T fr = frac[o];
+        if (col) {
+            scol[l][k] = ci;
+            sfx[l][k] = fr;
+        } else {
+            srow[l][k] = ci * lays[l].n;                            // row offset in the layer
+            sfy[l][k] = fr;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kLayerGroups * E * E; e += kDataThreads) {
+        const int lg = e / (E * E), node = e - lg * E * E;
+        const int li = node / E, lj = node - li * E;
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        T v = 0;
+        if (i >= 0 && i <= ns && j >= 0 && j <= ns) {
+#pragma unroll 4
+            for (int l = lg; l < L; l += kLayerGroups) {
+                const int n = lays[l].n;
+                const T fy = sfy[l][li], fx = sfx[l][lj];
+                const T* ph = phi + lays[l].off + srow[l][li] + scol[l][lj];
+                const T p00 = ph[0], p01 = ph[1], p10 = ph[n], p11 = ph[n + 1];
+                v += (T(1) - fy) * ((T(1) - fx) * p00 + fx * p01) + fy * ((T(1) - fx) * p10 + fx * p11);
+            }
+        }
+        spart[lg][node] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < E * E; e += kDataThreads) {
+        T v = spart[0][e];
+        for (int lg = 1; lg < kLayerGroups; ++lg) v += spart[lg][e];
+        spart[0][e] = v;
+    }
+    __syncthreads();
+    const T* sphi = spart[0];
+    for (int e = threadIdx.x; e < S1 * S1; e += kDataThreads) {
+        const int ls = e / S1, lt = e - ls * S1;
+        const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
+        T tx = 0, ty = 0;
+        if (si >= 0 && si < ns && sj >= 0 && sj < ns) {
+            const T p00 = sphi[ls * E + lt], p01 = sphi[ls * E + lt + 1];
+            const T p10 = sphi[(ls + 1) * E + lt], p11 = sphi[(ls + 1) * E + lt + 1];
+            const T sx = T(0.5) * ((p01 - p00) + (p11 - p10));
+            const T sy = T(0.5) * ((p10 - p00) + (p11 - p01));
+            tx = w[W.soff + si * ns + sj] * sx;
+            ty = w[W.soff + ns * ns + si * ns + sj] * sy;
+        }
+        stx[e] = tx;
+        sty[e] = ty;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTile * kTile; e += kDataThreads) {
+        const int li = e / kTile, lj = e - li * kTile;
+        const int i = i0 + li, j = j0 + lj;
+        if (i > ns || j > ns) continue;
+        const int A = (li + 1) * S1 + lj + 1, B = (li + 1) * S1 + lj, C = li * S1 + lj + 1, D = li * S1 + lj;
+        psi[W.noff + i * np + j] = T(0.5) * ((stx[B] - stx[A]) + (stx[D] - stx[C])) +
+                                   T(0.5) * ((sty[C] - sty[A]) + (sty[D] - sty[B]));
+    }
+}
+
+// Gamma^T (w s) per node (weighted = 1) or Gamma^T (mask s) (weighted = 0, mask = w != 0).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restrict__ wfs, int G, int64_t V,
+                                                          const T* __restrict__ w, const T* __restrict__ s,
+                                                          T* __restrict__ psi, int weighted) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= V) return;
+    int g = 0;
+    while (g + 1 < G && wfs[g + 1].noff <= e) ++g;
+    const WfsDev W = wfs[g];
+    const int ns = W.ns, np = ns + 1;
+    const int loc = int(e - W.noff);
+    const int i = loc / np, j = loc % np;
+    auto t = [&](int comp, int si, int sj) -> T {
+        if (si < 0 || si >= ns || sj < 0 || sj >= ns) return T(0);
+        const int64_t o = W.soff + int64_t(comp) * ns * ns + si * ns + sj;
+        const T ww = w[o];
+        return weighted ? ww * s[o] : (ww != T(0) ? s[o] : T(0));
+    };
+    psi[e] = T(0.5) * ((t(0, i, j - 1) - t(0, i, j)) + (t(0, i - 1, j - 1) - t(0, i - 1, j))) +
+             T(0.5) * ((t(1, i - 1, j) - t(1, i, j)) + (t(1, i - 1, j - 1) - t(1, i, j - 1)));
+}
+
+// Gamma P phi per subaperture (operator piece A), zero on inactive subapertures.
+template <typename T>
+__device__ __forceinline__ T wavefront_node(int g, int i, int j, int np, int L, const LayerDev* __restrict__ lays,
+                                            const PairDev* __restrict__ pairs, const int32_t* __restrict__ cidx,
+                                            const T* __restrict__ frac, const T* __restrict__ phi) {
+    T v = 0;
+    for (int l = 0; l < L; ++l) {
+        const PairDev P = pairs[g * L + l];
+        const int n = lays[l].n;
+        const int a0 = cidx[P.fwd_off + i], b0 = cidx[P.fwd_off + np + j];
+        const T fy = frac[P.fwd_off + i], fx = frac[P.fwd_off + np + j];
+        const T* ph = phi + lays[l].off + size_t(a0) * n + b0;
+        v += (T(1) - fy) * ((T(1) - fx) * ph[0] + fx * ph[1]) + fy * ((T(1) - fx) * ph[n] + fx * ph[n + 1]);
+    }
+    return v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_fwd_slopes(const WfsDev* __restrict__ wfs, int G, int64_t S,
+                                                          const LayerDev* __restrict__ lays, int L,
+                                                          const PairDev* __restrict__ pairs,
+                                                          const int32_t* __restrict__ cidx, const T* __restrict__ frac,
+                                                          const T* __restrict__ phi, const T* __restrict__ w,
+                                                          T* __restrict__ out) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= S) return;
+    int g = 0;
+    while (g + 1 < G && wfs[g + 1].soff <= e) ++g;
+    const WfsDev W = wfs[g];
+    const int ns = W.ns, np = ns + 1;
+    const int loc = int(e - W.soff);
+    const int comp = loc / (ns * ns), q = loc % (ns * ns), i = q / ns, j = q % ns;
+    const T p00 = wavefront_node(g, i, j, np, L, lays, pairs, cidx, frac, phi);
+    const T p01 = wavefront_node(g, i, j + 1, np, L, lays, pairs, cidx, frac, phi);
+    const T p10 = wavefront_node(g, i + 1, j, np, L, lays, pairs, cidx, frac, phi);
+    const T p11 = wavefront_node(g, i + 1, j + 1, np, L, lays, pairs, cidx, frac, phi);
+    const T v = comp == 0 ? T(0.5) * ((p01 - p00) + (p11 - p10)) : T(0.5) * ((p10 - p00) + (p11 - p01));
+    out[e] = w[e] != T(0) ? v : T(0);
+}
+
+// sum_g P_g^T psi_g on a kGT x kGT layer tile, for kGatherGroup sensors at a time:
+//  1. per sensor and tile row (column), the sensor rows i (columns j) whose bilinear cell has
+//     that layer row (column) as a corner, with their weights, listed in LDS in parallel;
+//  2. the rectangle of sensor nodes those lists span is copied to LDS (when it fits);
+//  3. every layer node sums its row-weight x column-weight products over the sensors in order.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restrict__ wfs, int G,
+                                                          const LayerDev* __restrict__ lays, int L,
+                                                          const PairDev* __restrict__ pairs,
+                                                          const int32_t* __restrict__ cidx, const T* __restrict__ frac,
+                                                          const int2* __restrict__ rng, const T* __restrict__ psi,
+                                                          T* __restrict__ out) {
+    constexpr int RG = kGatherRegion / sizeof(T);                  // LDS entries for sensor rectangles
+    __shared__ int32_t sidx[kGatherGroup][2][kGT][kRMax];          // sensor row / column index
+    __shared__ T sw[kGatherGroup][2][kGT][kRMax];
+    __shared__ int32_t scnt[kGatherGroup][2][kGT];
+    __shared__ int32_t sbox[kGatherGroup][6];                      // i_lo, i_hi, j_lo, j_hi, lds offset (-1: global), width
+    __shared__ T sreg[RG];
+    const int l = blockIdx.y;
+    const LayerDev d = lays[l];
+    const int n = d.n, tx = (n + kGT - 1) / kGT;
+    if (int(blockIdx.x) >= tx * tx) return;
+    const int a0 = (blockIdx.x / tx) * kGT, b0 = (blockIdx.x % tx) * kGT;
+    const int la = threadIdx.x / kGT, lb = threadIdx.x % kGT;
+    const int a = a0 + la, b = b0 + lb;
+    T acc = 0;
+    for (int g0 = 0; g0 < G; g0 += kGatherGroup) {
+        const int ng = G - g0 < kGatherGroup ? G - g0 : kGatherGroup;
+        {   // 1. lists: thread (gl, axis, k); the 16 threads of one (gl, axis) are adjacent lanes
+            const int gl = threadIdx.x / (2 * kGT), q = threadIdx.x - gl * 2 * kGT;
+            const int col = q >= kGT, k = q - col * kGT;
+            int lo = 1 << 30, hi = -1;
+            if (gl < ng) {
+                const int g = g0 + gl;
+                const int node = (col ? b0 : a0) + k;
+                const int np = wfs[g].ns + 1;
+                const PairDev P = pairs[g * L + l];
+                int cnt = 0;
+                if (node < n) {
+                    const int2 r = rng[P.rng_off + col * n + node];
+                    cnt = r.y < kRMax ? r.y : kRMax;
+                    T fr[kRMax];
+                    int32_t ci[kRMax];
+#pragma unroll
+                    for (int t = 0; t < kRMax; ++t)
+                        if (t < cnt) {
+                            const size_t o = size_t(P.fwd_off) + col * np + r.x + t;
+                            fr[t] = frac[o];
+                            ci[t] = cidx[o];
+                        }
+#pragma unroll
+                    for (int t = 0; t < kRMax; ++t)
+                        if (t < cnt) {
+                            sw[gl][col][k][t] = ci[t] == node ? T(1) - fr[t] : fr[t];
+                            sidx[gl][col][k][t] = r.x + t;
+                        }
+                    if (cnt > 0) {
+                        lo = r.x;
+                        hi = r.x + cnt - 1;
+                    }
+                }
+                scnt[gl][col][k] = cnt;
+            }
+#pragma unroll
+            for (int o = 1; o < kGT; o <<= 1) {
+                lo = min(lo, __shfl_xor(lo, o, kGT));
+                hi = max(hi, __shfl_xor(hi, o, kGT));
+            }
+            if (gl < ng && k == 0) {
+                sbox[gl][2 * col] = lo;
+                sbox[gl][2 * col + 1] = hi;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < ng) {   // rectangle of sensor gl in its fixed share of the LDS region
+            const int gl = threadIdx.x;
+            const int h = sbox[gl][1] - sbox[gl][0] + 1, w = sbox[gl][3] - sbox[gl][2] + 1;
+            const int share = RG / kGatherGroup;
+            sbox[gl][5] = w;
+            sbox[gl][4] = (h > 0 && w > 0 && h * w <= share) ? gl * share : -1;
+        }
+        __syncthreads();
+        {   // 2. rectangles: flat index over the sensors' fixed shares
+            constexpr int share = RG / kGatherGroup;
+            stage_to_lds<kThreads, (RG + kThreads - 1) / kThreads, T>(
+                ng * share,
+                [&](int f) -> T {
+                    const int gl = f / share, e = f - gl * share;
+                    const int w = sbox[gl][5], h = sbox[gl][1] - sbox[gl][0] + 1;
+                    if (sbox[gl][4] < 0 || e >= h * w) return T(0);
+                    const int ii = e / w, jj = e - ii * w;
+                    return psi[wfs[g0 + gl].noff + (sbox[gl][0] + ii) * (wfs[g0 + gl].ns + 1) + sbox[gl][2] + jj];
+                },
+                [&](int f, T v) { sreg[f] = v; });
+        }
+        __syncthreads();
+        if (a < n && b < n) {   // 3. sums
+            for (int gl = 0; gl < ng; ++gl) {
+                const int ca = scnt[gl][0][la], cb = scnt[gl][1][lb];
+                const int off = sbox[gl][4];
+                if (off >= 0) {
+                    const int i_lo = sbox[gl][0], j_lo = sbox[gl][2], w = sbox[gl][5];
+                    for (int r = 0; r < ca; ++r) {
+                        const int rowoff = off + (sidx[gl][0][la][r] - i_lo) * w;
+                        T sum = 0;
+                        for (int q = 0; q < cb; ++q) sum += sw[gl][1][lb][q] * sreg[rowoff + sidx[gl][1][lb][q] - j_lo];
+                        acc += sw[gl][0][la][r] * sum;
+                    }
+                } else {
+                    const int np = wfs[g0 + gl].ns + 1;
+                    const T* ps = psi + wfs[g0 + gl].noff;
+                    for (int r = 0; r < ca; ++r) {
+                        const T* row = ps + sidx[gl][0][la][r] * np;
+                        T sum = 0;
+                        for (int q = 0; q < cb; ++q) sum += sw[gl][1][lb][q] * row[sidx[gl][1][lb][q]];
+                        acc += sw[gl][0][la][r] * sum;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (a < n && b < n) out[d.off + size_t(a) * n + b] = acc;
+}
+
+// The same sum for configurations whose contribution lists exceed kRMax (layer grids much
+// coarser than the sensor grids): every node walks its ranges directly.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_adj_gather_wide(const WfsDev* __restrict__ wfs, int G,
+                                                               const LayerDev* __restrict__ lays, int L,
+                                                               const PairDev* __restrict__ pairs,
+                                                               const int32_t* __restrict__ cidx,
+                                                               const T* __restrict__ frac,
+                                                               const int2* __restrict__ rng,
+                                                               const T* __restrict__ psi, T* __restrict__ out) {
+    const int l = blockIdx.y;
+    const LayerDev d = lays[l];
+    const int n = d.n;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n) return;
+    const int a = idx / n, b = idx - a * n;
+    T acc = 0;
+    for (int g = 0; g < G; ++g) {
+        const WfsDev W = wfs[g];
+        const int np = W.ns + 1;
+        const PairDev P = pairs[g * L + l];
+        const int2 ra = rng[P.rng_off + a], rb = rng[P.rng_off + n + b];
+        for (int ii = 0; ii < ra.y; ++ii) {
+            const int i = ra.x + ii;
+            const T fy = frac[P.fwd_off + i];
+            const T wy = cidx[P.fwd_off + i] == a ? T(1) - fy : fy;
+            T row = 0;
+            for (int jj = 0; jj < rb.y; ++jj) {
+                const int j = rb.x + jj;
+                const T fx = frac[P.fwd_off + np + j];
+                const T wx = cidx[P.fwd_off + np + j] == b ? T(1) - fx : fx;
+                row += wx * psi[W.noff + i * np + j];
+            }
+            acc += wy * row;
+        }
+    }
+    out[d.off + idx] = acc;
+}
+
+template <typename T>
+Filt<T> make_filt() {
+    // Daubechies' closed form of the orthonormal 6-tap scaling filter; g_m = (-1)^m h_{5-m}
+    const double s10 = std::sqrt(10.0), r = std::sqrt(5.0 + 2.0 * s10), k = std::sqrt(2.0) / 32.0;
+    const double v[6] = {1 + s10 + r, 5 + s10 + 3 * r, 10 - 2 * s10 + 2 * r,
+                         10 - 2 * s10 - 2 * r, 5 + s10 - 3 * r, 1 + s10 - r};
+    Filt<T> f;
+    for (int m = 0; m < 6; ++m) f.h[m] = T(k * v[m]);
+    for (int m = 0; m < 6; ++m) f.g[m] = T(((m & 1) ? -1.0 : 1.0) * k * v[5 - m]);
+    return f;
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ profiler
+
+const char* const kKernelNames[KID_COUNT] = {
+    "idwt", "dwt", "data_term", "adj_gather", "slopes_adj", "residual", "gram",
+    "galerkin_apply", "init_dir", "dot", "update1", "update2", "scalars"};
+
+ProfScope::ProfScope(const Ctx& ctx, int kid, hipStream_t stream) : c(ctx), s(stream) {
+    Profiler& p = c.prof;
+    if (!p.on) return;
+    const size_t j = p.pending.size();
+    while (p.pool.size() < 2 * (j + 1)) {
+        hipEvent_t e;
+        (void)hipEventCreate(&e);
+        p.pool.push_back(e);
+    }
+    p.pending.push_back(kid);
+    (void)hipEventRecord(p.pool[2 * j], s);
+}
+
+ProfScope::~ProfScope() {
+    Profiler& p = c.prof;
+    if (!p.on) return;
+    (void)hipEventRecord(p.pool[2 * (p.pending.size() - 1) + 1], s);
+}
+
+hipError_t profiler_collect(const Ctx& c, hipStream_t s) {
+    Profiler& p = c.prof;
+    if (p.pending.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(s);
+    for (size_t j = 0; j < p.pending.size() && e == hipSuccess; ++j) {
+        float ms = 0;
+        e = hipEventElapsedTime(&ms, p.pool[2 * j], p.pool[2 * j + 1]);
+        p.ms[p.pending[j]] += ms;
+        p.launches[p.pending[j]] += 1;
+    }
+    p.pending.clear();
+    return e;
+}
+
+// ------------------------------------------------------------------ operator launchers
+
+inline StepLayers step_layers(const WaveStep& w) {
+    StepLayers sl{};
+    sl.count = int32_t(w.layers.size());
+    for (size_t i = 0; i < w.layers.size(); ++i) sl.l[i] = w.layers[i];
+    return sl;
+}
+
+template <typename T>
+void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
+    const Filt<T> f = make_filt<T>();
+    T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
+    const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
+    {
+        ProfScope ps_(c, KID_IDWT, s);
+        k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], phi);
+    }
+    for (size_t j = 0; j < c.steps.size(); ++j) {
+        const WaveStep& w = c.steps[j];
+        const int tiles = (w.nb / kST) * (w.nb / kST);
+        ProfScope ps_(c, KID_IDWT, s);
+        k_idwt_step<T><<<tiles * int(w.layers.size()), kThreads, 0, s>>>(lays, step_layers(w), w.nb, f, x, buf[j & 1],
+                                                                       buf[(j + 1) & 1], phi);
+    }
+}
+
+template <typename T>
+void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, const T* xdot, double* pq_part,
+                  hipStream_t s) {
+    const Filt<T> f = make_filt<T>();
+    T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
+    const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
+    const T* pa = c.at<T>(c.lay.prior_a);
+    int used = 0;
+    const int J = int(c.steps.size());
+    for (int j = 0; j < J; ++j) {                 // largest block first
+        const WaveStep& w = c.steps[J - 1 - j];
+        const int tiles = (w.nb / 2 / kAT) * (w.nb / 2 / kAT);
+        const int blocks = tiles * int(w.layers.size());
+        ProfScope ps_(c, KID_DWT, s);
+        k_dwt_step<T><<<blocks, kThreads, 0, s>>>(lays, step_layers(w), w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y,
+                                                  pa, xprior, xdot, pq_part ? pq_part + used : nullptr);
+        used += blocks;
+    }
+    ProfScope ps_(c, KID_DWT, s);
+    k_dwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, xdot,
+                                                   pq_part ? pq_part + used : nullptr);
+}
+
+template <typename T>
+void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s) {
+    ProfScope ps_(c, KID_DATA_TERM, s);
+    k_data_term<T><<<c.fwd_tiles, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.at<LayerDev>(c.lay.layers), c.L,
+                                                    c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
+                                                    c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), psi_nodes);
+}
+
+template <typename T>
+void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted, hipStream_t s) {
+    ProfScope ps_(c, KID_SLOPES_ADJ, s);
+    k_slopes_adj<T><<<cdiv(c.V, kThreads), kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.V, c.at<T>(c.lay.weight),
+                                                             slopes, psi_nodes, weighted);
+}
+
+template <typename T>
+void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s) {
+    ProfScope ps_(c, KID_ADJ_GATHER, s);
+    if (c.max_rng <= kRMax) {
+        const int tx = (c.max_n + kGT - 1) / kGT;
+        const dim3 grid(tx * tx, c.L);
+        k_adj_gather<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.at<LayerDev>(c.lay.layers), c.L,
+                                                  c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
+                                                  c.at<T>(c.lay.frac), c.at<int2>(c.lay.ranges), psi_nodes, psi_layers);
+    } else {
+        const dim3 grid(cdiv(int64_t(c.max_n) * c.max_n, kThreads), c.L);
+        k_adj_gather_wide<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.at<LayerDev>(c.lay.layers),
+                                                       c.L, c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
+                                                       c.at<T>(c.lay.frac), c.at<int2>(c.lay.ranges), psi_nodes,
+                                                       psi_layers);
+    }
+}
+
+template <typename T>
+void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s) {
+    ProfScope ps_(c, KID_DATA_TERM, s);
+    k_fwd_slopes<T><<<cdiv(c.S, kThreads), kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.S,
+                                                             c.at<LayerDev>(c.lay.layers), c.L,
+                                                             c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
+                                                             c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), slopes);
+}
+
+template <typename T>
+void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s) {
+    T* phi = c.at<T>(c.lay.nodal);
+    T* psi_n = c.at<T>(c.lay.psi_nodes);
+    T* psi_l = c.at<T>(c.lay.psi_layers);
+    launch_winv<T>(c, x, phi, s);
+    launch_data_term<T>(c, phi, psi_n, s);
+    launch_adj_gather<T>(c, psi_n, psi_l, s);
+    launch_winvt<T>(c, psi_l, y, x, pq_part ? x : static_cast<const T*>(nullptr), pq_part, s);
+}
+
+template <typename T>
+void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s) {
+    T* psi_n = c.at<T>(c.lay.psi_nodes);
+    T* psi_l = c.at<T>(c.lay.psi_layers);
+    launch_slopes_adj<T>(c, slopes, psi_n, 1, s);
+    launch_adj_gather<T>(c, psi_n, psi_l, s);
+    launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), nullptr, s);
+}
+
+#define FEWHA_INSTANTIATE_OP(T)                                                                           \
+    template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t);                                  \
+    template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, const T*, double*, hipStream_t);    \
+    template void launch_data_term<T>(const Ctx&, const T*, T*, hipStream_t);                             \
+    template void launch_slopes_adj<T>(const Ctx&, const T*, T*, int, hipStream_t);                       \
+    template void launch_adj_gather<T>(const Ctx&, const T*, T*, hipStream_t);                            \
+    template void launch_fwd_slopes<T>(const Ctx&, const T*, T*, hipStream_t);                            \
+    template void launch_apply_M<T>(const Ctx&, const T*, T*, double*, hipStream_t);                      \
+    template void launch_rhs<T>(const Ctx&, const T*, T*, hipStream_t);
+
+FEWHA_INSTANTIATE_OP(float)
+FEWHA_INSTANTIATE_OP(double)
+
+}  // namespace fewha

@@ -66,6 +66,28 @@ struct Cells {
 
 }  // namespace
 
+std::vector<WaveStep> wavelet_steps(const fewha_config* cfg) {
+    // block sizes (> the coarse block) of the tiled wavelet levels, ascending, with their layers
+    const int cb = coarse_block(cfg->precision);
+    std::vector<WaveStep> st;
+    for (int nb = 2 * cb; nb <= 1024; nb *= 2) {
+        WaveStep w;
+        w.nb = nb;
+        for (int l = 0; l < cfg->n_layers; ++l) {
+            const fewha_layer& L = cfg->layers[l];
+            if (L.n >= nb && ilog2(L.n / nb) + 1 <= L.levels) w.layers.push_back(l);
+        }
+        if (!w.layers.empty()) st.push_back(w);
+    }
+    return st;
+}
+
+int pq_partials(const fewha_config* cfg) {
+    int n = cfg->n_layers;   // coarse analysis: one workgroup per layer
+    for (const WaveStep& w : wavelet_steps(cfg)) n += (w.nb / 2 / kAT) * (w.nb / 2 / kAT) * int(w.layers.size());
+    return n;
+}
+
 fewha_status validate_config(const fewha_config* cfg, std::string& err) {
     if (!cfg) { err = "config is NULL"; return FEWHA_E_INVAL; }
     if (cfg->abi_version != FEWHA_ABI_VERSION) { err = "abi_version mismatch"; return FEWHA_E_INVAL; }
@@ -161,7 +183,9 @@ Layout compute_layout(const fewha_config* cfg) {
     lo.s_in = take(e * S);
     lo.ring_u = take(e * N * slots);
     lo.ring_q = take(e * N * slots);
-    lo.partials = take(sizeof(double) * kVecBlocks * (kKMax * kKMax + kKMax + 8));
+    lo.partials = take(sizeof(double) * kVecBlocks * (2 * kKMax + 8));
+    lo.pq_part = take(sizeof(double) * size_t(pq_partials(cfg)));
+    lo.gram_part = take(sizeof(double) * kGramBlocks * (kKMax * kKMax + kKMax));
     lo.scalars = take(sizeof(Scalars));
     lo.info = take(sizeof(fewha_solve_info));
     lo.total = o;
@@ -181,6 +205,8 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfg, hipStream_t stream)
     for (int l = 0; l < L; ++l) {
         ld[l].n = cfg->layers[l].n;
         ld[l].levels = cfg->layers[l].levels;
+        ld[l].coarse_lev = coarse_first_level(ld[l].n, coarse_block(cfg->precision));
+        ld[l].pad_ = 0;
         ld[l].off = off;
         ld[l].inv_delta = 1.0 / cfg->layers[l].spacing;
         off += int64_t(ld[l].n) * ld[l].n;
@@ -249,6 +275,10 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfg, hipStream_t stream)
         }
     }
     ctx.n_cells = int64_t(cidx.size());
+    ctx.max_rng = 0;
+    for (size_t i = 1; i < rng.size(); i += 2) ctx.max_rng = std::max(ctx.max_rng, int(rng[i]));
+    ctx.steps = wavelet_steps(cfg);
+    ctx.npq = pq_partials(cfg);
     ctx.n_ranges = int64_t(rng.size() / 2);
 
     // ---- prior D (Sec. 3): inverse von Karman spectrum at the band frequency

@@ -1,0 +1,641 @@
+// HIP kernels (gfx950 / CDNA4) of the frame update of the augmented wavelet reconstructor:
+// Alg. 3 residual update, the Galerkin projection and initial direction of Alg. 2 (Sec. 4.1),
+// and the PCG iterations of Alg. 1 / Alg. 2.
+//
+// Every inner product is reduced in FP64 in two fixed-order stages: vector kernels on a fixed
+// kVecBlocks grid write one partial per block; the consumer kernel -- every block of it,
+// redundantly -- sums those partials in the same order and derives the scalars it needs
+// (alpha, beta, mu, the k x k Gram solve).  Every block therefore holds bit-identical scalars
+// without an extra single-block launch, and results are reproducible run to run.  Block 0
+// records the scalars in device memory for the next kernels and for the frame statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "fewha_device.h"
+#include "fewha_internal.h"
+
+namespace fewha {
+
+namespace {
+
+// Rows of the per-block partial buffer (kVecBlocks columns each).
+enum : int { P_RZ = 0, P_BB = 1, P_RR = 2, P_RZ1 = 3, P_PROJ = 4 };
+
+struct SlotList { int32_t s[kKMax]; };
+
+// Sums NV rows (row0..row0+nrows-1, nrows <= NV) of the partial buffer at once.
+template <int NV>
+__device__ __forceinline__ void block_row_sums(const double* __restrict__ part, int row0, int nrows, double (&out)[NV]) {
+    __shared__ double sh[NV][kThreads / 64];
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        v[k] = 0;
+#pragma unroll
+        for (int j = 0; j < kVecBlocks / kThreads; ++j)
+            if (k < nrows) v[k] += part[size_t(row0 + k) * kVecBlocks + threadIdx.x + j * kThreads];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = wave_sum(v[k]);
+        if (lane == 0) sh[k][wv] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+    __syncthreads();
+}
+
+// Triangular solves with the factor of the Gram matrix (drop-aware), G = R^T R; t is a work
+// array of m entries (in LDS at the call sites, so that no kernel needs scratch memory).
+__device__ void chol_solve(const double* R, const int32_t* keep, int m, const double* v, double* y, double* t) {
+    for (int j = 0; j < m; ++j) {
+        t[j] = 0;
+        if (!keep[j]) continue;
+        double s = v[j];
+        for (int i = 0; i < j; ++i) s -= R[i * m + j] * t[i];
+        t[j] = s / R[j * m + j];
+    }
+    for (int j = m - 1; j >= 0; --j) {
+        y[j] = 0;
+        if (!keep[j]) continue;
+        double s = t[j];
+        for (int k = j + 1; k < m; ++k) s -= R[j * m + k] * y[k];
+        y[j] = s / R[j * m + j];
+    }
+}
+
+// ------------------------------------------------------------------ frame start
+
+// First frame: r = b - M c; later frames: r = (b - b_prev) + r (Alg. 3 residual update).
+// b_prev = b; partial (b, b).  Block 0 resets the frame's flags.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const T* __restrict__ b, T* __restrict__ b_prev,
+                                                        T* __restrict__ r, const T* __restrict__ mc,
+                                                        double* __restrict__ part, Scalars* __restrict__ sc, int m) {
+    double bb = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+        const double bi = double(b[i]);
+        if (mc)
+            r[i] = T(bi - double(mc[i]));
+        else
+            r[i] = T((bi - double(b_prev[i])) + double(r[i]));
+        b_prev[i] = b[i];
+        bb += bi * bi;
+    }
+    const double v[1] = {bb};
+    block_partials<1>(v, part, P_BB, kVecBlocks, blockIdx.x);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->flags = 0;
+        sc->used = m;
+        sc->dropped = 0;
+    }
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Gram pass: X_ab = (U_a, Q_b) (a, b < m) and X_{a,m} = (U_a, r), entry e = a (m+1) + b: a
+// dense m x N by N x (m+1) contraction, on the FP64 matrix cores.  Block (x, y) owns the 16x16
+// tile y of X over its share of the elements; each wavefront feeds v_mfma_f64_16x16x4 with
+// 16 elements per step (lane l: row/column l mod 16, elements 4 (l / 16) .. +3), the four
+// wavefronts' tiles are summed in LDS in a fixed order and written as one partial.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gram(int64_t N, int m, SlotList sl, const T* __restrict__ U,
+                                                    const T* __restrict__ Q, const T* __restrict__ r,
+                                                    double* __restrict__ gpart) {
+    __shared__ double sh[4][256];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tb_count = (m + 1 + 15) / 16;
+    const int ta = blockIdx.y / tb_count, tb = blockIdx.y - ta * tb_count;
+    const int ar = 16 * ta + (lane & 15), bc = 16 * tb + (lane & 15), kq = lane >> 4;
+    const T* pa = ar < m ? U + size_t(sl.s[ar]) * N : nullptr;
+    const T* pb = bc < m ? Q + size_t(sl.s[bc]) * N : (bc == m ? r : nullptr);
+    f64x4 c = {0.0, 0.0, 0.0, 0.0};
+    const int64_t step = int64_t(gridDim.x) * 4 * 16;
+#pragma unroll 4
+    for (int64_t base = (int64_t(blockIdx.x) * 4 + wv) * 16; base < N; base += step) {   // N % 64 == 0
+        const int64_t e0 = base + 4 * kq;
+        double av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            av[j] = pa ? double(pa[e0 + j]) : 0.0;
+            bv[j] = pb ? double(pb[e0 + j]) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], c, 0, 0, 0);
+    }
+    // lane l, register v holds tile entry (row 4 v + l / 16, column l mod 16)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sh[wv][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = c[v];
+    __syncthreads();
+    const int t = threadIdx.x, row = 16 * ta + (t >> 4), col = 16 * tb + (t & 15);
+    if (row < m && col <= m) {
+        const double v = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+        gpart[size_t(row * (m + 1) + col) * kGramBlocks + blockIdx.x] = v;
+    }
+}
+
+// Reduce the Gram partials and solve for the Galerkin coefficients y (Sec. 4.1).
+// GALERKIN: G_ab = X_ab (a <= b, mirrored), Cholesky processing columns in order and dropping
+// column j when its pivot is <= 1e-14 max diag G; y = G^-1 U^T r.
+// PAPER: sequential sigma_j with the running residual, (r, p_j) = sigma_j g_j +
+// sum_{i<j} sigma_i (q_i, p_j); X is kept for the initial-direction step.
+__global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, SlotList sl,
+                                                               Scalars* __restrict__ sc,
+                                                               const double* __restrict__ gpart) {
+    __shared__ double X[kKMax * (kKMax + 1)];
+    __shared__ double R[kKMax * kKMax], v[kKMax], y[kKMax], t[kKMax], gm[kKMax];
+    __shared__ int32_t keep[kKMax];
+    const int ne = m * (m + 1);
+    {   // 8 lanes per entry, each summing kGramBlocks / 8 partials requested all at once
+        constexpr int PER = kGramBlocks / 8;
+        const int sub = threadIdx.x & 7;
+        for (int e0 = 0; e0 < ne; e0 += kSolveThreads / 8) {
+            const int e = e0 + (threadIdx.x >> 3);
+            double v[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) v[k] = e < ne ? gpart[size_t(e) * kGramBlocks + sub * PER + k] : 0.0;
+            double s = 0;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) s += v[k];
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) s += __shfl_down(s, o, 8);
+            if (sub == 0 && e < ne) X[e] = s;
+        }
+    }
+    if (threadIdx.x < m) gm[threadIdx.x] = sc->gam[sl.s[threadIdx.x]];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const int W = m + 1;
+    for (int a = 0; a < m; ++a) v[a] = X[a * W + m];
+    if (mode == FEWHA_RECYCLE_PAPER) {
+        for (int j = 0; j < m; ++j) {
+            double s = v[j];
+            for (int i = 0; i < j; ++i) s -= y[i] * X[j * W + i];
+            y[j] = s / gm[j];
+        }
+        for (int j = 0; j < m; ++j) sc->y[j] = y[j];
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) sc->R[a * m + b] = X[a * W + b];
+        sc->dropped = 0;
+        return;
+    }
+    double dmax = 0;
+    for (int j = 0; j < m; ++j) dmax = fmax(dmax, X[j * W + j]);
+    const double thr = 1e-14 * dmax;
+    int dropped = 0;
+    for (int i = 0; i < m * m; ++i) R[i] = 0;
+    for (int j = 0; j < m; ++j) {
+        double d = X[j * W + j];
+        for (int i = 0; i < j; ++i) d -= R[i * m + j] * R[i * m + j];
+        if (!(d > thr)) {
+            keep[j] = 0;
+            ++dropped;
+            continue;
+        }
+        keep[j] = 1;
+        const double rjj = sqrt(d);
+        R[j * m + j] = rjj;
+        for (int k = j + 1; k < m; ++k) {
+            double s = X[j * W + k];
+            for (int i = 0; i < j; ++i) s -= R[i * m + j] * R[i * m + k];
+            R[j * m + k] = s / rjj;
+        }
+    }
+    chol_solve(R, keep, m, v, y, t);
+    for (int i = 0; i < m * m; ++i) sc->R[i] = R[i];
+    for (int j = 0; j < m; ++j) {
+        sc->keep[j] = keep[j];
+        sc->y[j] = y[j];
+    }
+    sc->dropped = dropped;
+}
+
+// Galerkin step c += U y, r -= Q y; then z = J^-1 r and partials of (Q_a, z).
+template <typename T, int MB>
+__global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, int m, SlotList sl, const T* __restrict__ U,
+                                                              const T* __restrict__ Q, const Scalars* __restrict__ sc,
+                                                              T* __restrict__ c, T* __restrict__ r, T* __restrict__ z,
+                                                              const T* __restrict__ jinv, double* __restrict__ part) {
+    double y[MB], acc[MB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+        y[a] = a < m ? sc->y[a] : 0.0;
+        acc[a] = 0;
+    }
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+        double ci = double(c[i]), ri = double(r[i]);
+        double qv[MB];
+#pragma unroll
+        for (int a = 0; a < MB; ++a) {
+            if (a < m) {
+                qv[a] = double(Q[size_t(sl.s[a]) * N + i]);
+                ci += y[a] * double(U[size_t(sl.s[a]) * N + i]);
+                ri -= y[a] * qv[a];
+            }
+        }
+        c[i] = T(ci);
+        const T rt = T(ri);
+        r[i] = rt;
+        const T zt = jinv[i] * rt;
+        z[i] = zt;
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+            if (a < m) acc[a] += qv[a] * double(zt);
+    }
+    __shared__ double sh[MB][kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+        const double s = wave_sum(acc[a]);
+        if (lane == 0) sh[a][wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < m) {
+        const int a = threadIdx.x;
+        part[size_t(P_PROJ + a) * kVecBlocks + blockIdx.x] = (sh[a][0] + sh[a][1]) + (sh[a][2] + sh[a][3]);
+    }
+}
+
+// Initial direction M-conjugate to U (condition 1 of the augmented CG): every block reduces
+// the (Q_a, z) partials and solves for y2 (GALERKIN: y2 = G^-1 Q^T z; PAPER: sequential tau_j
+// with the running z, (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j)); p_0 = z - U y2.
+// Without recycled directions p_0 = z = J^-1 r (Alg. 1).  Partial of (r, p_0).
+template <typename T, int MB>
+__global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mode, SlotList sl,
+                                                        const T* __restrict__ U, Scalars* __restrict__ sc,
+                                                        const T* __restrict__ z, const T* __restrict__ r,
+                                                        const T* __restrict__ jinv, T* __restrict__ p,
+                                                        double* __restrict__ part) {
+    constexpr int MB1 = MB > 0 ? MB : 1;
+    __shared__ double sy[MB1];
+    if (MB > 0) {
+        double v[MB1];
+        block_row_sums<MB1>(part, P_PROJ, m, v);
+        __shared__ double y2[kKMax], vt[kKMax], t[kKMax], gm[kKMax], R[kKMax * kKMax];
+        __shared__ int32_t keep[kKMax];
+        for (int e = threadIdx.x; e < m * m; e += blockDim.x) R[e] = sc->R[e];
+        if (threadIdx.x < m) {
+            keep[threadIdx.x] = sc->keep[threadIdx.x];
+            gm[threadIdx.x] = sc->gam[sl.s[threadIdx.x]];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int j = 0; j < m; ++j) vt[j] = v[j];
+            if (mode == FEWHA_RECYCLE_PAPER) {
+                for (int j = 0; j < m; ++j) {
+                    double s = vt[j];
+                    for (int i = 0; i < j; ++i) s -= y2[i] * R[i * m + j];
+                    y2[j] = s / gm[j];
+                }
+            } else {
+                chol_solve(R, keep, m, vt, y2, t);
+            }
+            for (int j = 0; j < m; ++j) sy[j] = y2[j];
+            if (blockIdx.x == 0)
+                for (int j = 0; j < m; ++j) sc->y2[j] = y2[j];
+        }
+        __syncthreads();
+    }
+    double y2[MB1];
+#pragma unroll
+    for (int a = 0; a < MB; ++a) y2[a] = a < m ? sy[a] : 0.0;
+    double rz = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+        T pt;
+        if (MB == 0) {
+            pt = jinv[i] * r[i];
+        } else {
+            double pi = double(z[i]);
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+                if (a < m) pi -= y2[a] * double(U[size_t(sl.s[a]) * N + i]);
+            pt = T(pi);
+        }
+        p[i] = pt;
+        rz += double(r[i]) * double(pt);
+    }
+    const double vv[1] = {rz};
+    block_partials<1>(vv, part, P_RZ, kVecBlocks, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ PCG iteration
+
+// alpha = (r, z) / (p, q) from the analysis partials of (p, q) = (p, Mp) and the (r, z) of
+// this iteration; c += alpha p, r -= alpha q; unless last: z = J^-1 r with partials of (r, z)
+// and, over the in-loop projection set, (Q_a, z) and (U_a, r); always the partial (r, r).
+template <typename T, int MP>
+__global__ void __launch_bounds__(kThreads) k_update1(int64_t N, int it, int mp, SlotList pl, const T* __restrict__ U,
+                                                       const T* __restrict__ Q, Scalars* __restrict__ sc,
+                                                       const T* __restrict__ p, const T* __restrict__ q,
+                                                       T* __restrict__ c, T* __restrict__ r, T* __restrict__ z,
+                                                       const T* __restrict__ jinv, int last, int npq,
+                                                       const double* __restrict__ pq_part, double* __restrict__ part,
+                                                       int pslot) {
+    const double pq = block_sum_array(pq_part, npq);
+    double rz;
+    if (it == 0) {
+        double t[1];
+        block_row_sums<1>(part, P_RZ, 1, t);
+        rz = t[0];
+    } else {
+        rz = sc->rzb[it & 1];
+    }
+    double alpha = rz / pq;
+    const bool broken = sc->flags != 0 || !(pq > 0) || !isfinite(alpha);
+    if (broken) alpha = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->gam[pslot] = pq;
+        sc->alpha = alpha;
+        if (it == 0) sc->rzb[0] = rz;
+        if (broken) sc->flags |= 1;
+    }
+    constexpr int NV = 2 + 2 * MP;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+        c[i] = T(double(c[i]) + alpha * double(p[i]));
+        const T rt = T(double(r[i]) - alpha * double(q[i]));
+        r[i] = rt;
+        const double rd = double(rt);
+        acc[0] += rd * rd;
+        if (!last) {
+            const T zt = jinv[i] * rt;
+            z[i] = zt;
+            const double zd = double(zt);
+            acc[1] += rd * zd;
+#pragma unroll
+            for (int a = 0; a < MP; ++a)
+                if (a < mp) {
+                    acc[2 + a] += double(Q[size_t(pl.s[a]) * N + i]) * zd;
+                    acc[2 + MP + a] += double(U[size_t(pl.s[a]) * N + i]) * rd;
+                }
+        }
+    }
+    __shared__ double sh[NV][kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) sh[k][wv] = s;
+    }
+    __syncthreads();
+    // rows: P_RR, P_RZ1, P_PROJ + a (Q_a, z), P_PROJ + mp + a (U_a, r)
+    const int k = threadIdx.x;
+    const int nv = last ? 1 : 2 + 2 * mp;
+    if (k < nv) {
+        int src = k;
+        if (k >= 2 + mp) src = 2 + MP + (k - 2 - mp);
+        const int row = k == 0 ? P_RR : (k == 1 ? P_RZ1 : P_PROJ + (k - 2));
+        part[size_t(row) * kVecBlocks + blockIdx.x] = (sh[src][0] + sh[src][1]) + (sh[src][2] + sh[src][3]);
+    }
+}
+
+// Projection coefficients y3 of the new z against the in-loop set (the most recent recycled
+// direction: mu = (z, q_m) / (p_m, q_m); or all of U through the Gram factor), the projected
+// (r, z) = (r, z) - sum_a y3_a (U_a, r) and beta; p_next = z - U y3 + beta p.
+template <typename T, int MP>
+__global__ void __launch_bounds__(kThreads) k_update2(int64_t N, int it, int mp, int project_all, SlotList pl,
+                                                       const T* __restrict__ U, Scalars* __restrict__ sc,
+                                                       const T* __restrict__ z, const T* __restrict__ p,
+                                                       T* __restrict__ pn, const double* __restrict__ part) {
+    constexpr int NV = 1 + 2 * MP;
+    constexpr int MP1 = MP > 0 ? MP : 1;
+    __shared__ double sy[MP1];
+    __shared__ double sbeta;
+    double v[NV];
+    block_row_sums<NV>(part, P_RZ1, 1 + 2 * mp, v);   // (r,z), (Q_a,z) a < mp, (U_a,r) a < mp
+    __shared__ double y3[MP1], qz[MP1], t[MP1], R[MP1 * MP1];
+    __shared__ int32_t keep[MP1];
+    if (MP > 1 && project_all) {
+        for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) R[e] = sc->R[e];
+        if (threadIdx.x < mp) keep[threadIdx.x] = sc->keep[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if constexpr (MP > 0) {
+            if (project_all) {
+                if (MP == 1) {
+                    R[0] = sc->R[0];
+                    keep[0] = sc->keep[0];
+                }
+                for (int a = 0; a < mp; ++a) qz[a] = v[1 + a];
+                chol_solve(R, keep, mp, qz, y3, t);
+            } else {
+                y3[0] = v[1] / sc->gam[pl.s[0]];
+            }
+        }
+        double rzn = v[0];
+        if constexpr (MP > 0)
+            for (int a = 0; a < mp; ++a) rzn -= y3[a] * v[1 + mp + a];
+        const double rz_old = sc->rzb[it & 1];
+        double beta = rz_old != 0 ? rzn / rz_old : 0.0;
+        const bool broken = sc->flags != 0 || !isfinite(beta);
+        if (broken) {
+            beta = 0;
+            for (int a = 0; a < mp; ++a) y3[a] = 0;
+        }
+        for (int a = 0; a < mp; ++a) sy[a] = y3[a];
+        sbeta = beta;
+        if (blockIdx.x == 0) {
+            sc->rzb[(it + 1) & 1] = rzn;
+            sc->beta = beta;
+            sc->mu = mp ? y3[0] : 0.0;
+            if (broken) sc->flags |= 1;
+        }
+    }
+    __syncthreads();
+    const double beta = sbeta;
+    double yr[MP1];
+#pragma unroll
+    for (int a = 0; a < MP; ++a) yr[a] = a < mp ? sy[a] : 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+        double vv = double(z[i]) + beta * double(p[i]);
+#pragma unroll
+        for (int a = 0; a < MP; ++a)
+            if (a < mp) vv -= yr[a] * double(U[size_t(pl.s[a]) * N + i]);
+        pn[i] = T(vv);
+    }
+}
+
+// Frame statistics (relative residual in FP64) into the context's and the caller's info.
+__global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ sc, const double* __restrict__ part,
+                                                      fewha_solve_info* __restrict__ info,
+                                                      fewha_solve_info* __restrict__ info_user, int iters) {
+    double v[2];
+    block_row_sums<2>(part, P_BB, 2, v);   // rows P_BB, P_RR
+    if (threadIdx.x == 0) {
+        fewha_solve_info in;
+        in.iters = iters;
+        in.recycle_used = sc->used;
+        in.dropped = sc->dropped;
+        in.flags = sc->flags;
+        in.rel_res = v[0] > 0 ? sqrt(v[1] / v[0]) : 0.0;
+        sc->bb = v[0];
+        sc->rr = v[1];
+        *info = in;
+        if (info_user) *info_user = in;
+    }
+}
+
+int bucket(int m) {
+    if (m <= 0) return 0;
+    if (m <= 1) return 1;
+    if (m <= 4) return 4;
+    if (m <= 8) return 8;
+    if (m <= 16) return 16;
+    return 32;
+}
+
+template <typename T, int MB>
+void launch_gal(int64_t N, int m, const SlotList& sl, const T* U, const T* Q, const Scalars* sc, T* c, T* r, T* z,
+                const T* jinv, double* part, hipStream_t s) {
+    k_galerkin_apply<T, MB><<<kVecBlocks, kThreads, 0, s>>>(N, m, sl, U, Q, sc, c, r, z, jinv, part);
+}
+
+template <typename T, int MB>
+void launch_init(int64_t N, int m, int mode, const SlotList& sl, const T* U, Scalars* sc, const T* z, const T* r,
+                 const T* jinv, T* p, double* part, hipStream_t s) {
+    k_init_dir<T, MB><<<kVecBlocks, kThreads, 0, s>>>(N, m, mode, sl, U, sc, z, r, jinv, p, part);
+}
+
+template <typename T, int MP>
+void launch_upd(int64_t N, int it, int mp, const SlotList& pl, const T* U, const T* Q, Scalars* sc, const T* p,
+                const T* q, T* c, T* r, T* z, const T* jinv, int last, int npq, const double* pq_part, double* part,
+                int pslot, int project_all, T* pn, const Ctx& ctx, hipStream_t s) {
+    {
+        ProfScope ps_(ctx, KID_UPDATE1, s);
+        k_update1<T, MP><<<kVecBlocks, kThreads, 0, s>>>(N, it, mp, pl, U, Q, sc, p, q, c, r, z, jinv, last, npq,
+                                                         pq_part, part, pslot);
+    }
+    if (!last) {
+        ProfScope ps_(ctx, KID_UPDATE2, s);
+        k_update2<T, MP><<<kVecBlocks, kThreads, 0, s>>>(N, it, mp, project_all, pl, U, sc, z, p, pn, part);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info_user, hipStream_t s) {
+    const int64_t N = c.N;
+    const int K = c.slots;
+    T* b = c.at<T>(c.lay.b);
+    T* bp = c.at<T>(c.lay.b_prev);
+    T* r = c.at<T>(c.lay.r);
+    T* z = c.at<T>(c.lay.z);
+    T* cv = c.at<T>(c.lay.c);
+    T* vx = c.at<T>(c.lay.vx);
+    T* U = c.at<T>(c.lay.ring_u);
+    T* Q = c.at<T>(c.lay.ring_q);
+    const T* jinv = c.at<T>(c.lay.jinv);
+    double* part = c.at<double>(c.lay.partials);
+    double* pqp = c.at<double>(c.lay.pq_part);
+    double* gpart = c.at<double>(c.lay.gram_part);
+    Scalars* sc = c.at<Scalars>(c.lay.scalars);
+    fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
+
+    int m = 0;
+    if (!c.first && c.k > 0)
+        m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
+    SlotList act{};
+    for (int j = 0; j < m; ++j) act.s[j] = ((c.head - m + j) % K + K) % K;
+
+    // a1: right-hand side
+    launch_rhs<T>(c, slopes, b, s);
+    // a2: residual
+    if (c.first) launch_apply_M<T>(c, cv, vx, nullptr, s);
+    {
+        ProfScope ps_(c, KID_RESIDUAL, s);
+        k_residual<T><<<kVecBlocks, kThreads, 0, s>>>(N, b, bp, r, c.first ? vx : nullptr, part, sc, m);
+    }
+    // a3 + a4: Galerkin step and initial direction
+    T* p0 = U + size_t(c.head) * N;
+    const int mb = bucket(m);
+    if (m > 0) {
+        {
+            ProfScope ps_(c, KID_GRAM, s);
+            const dim3 grid(kGramBlocks, ((m + 15) / 16) * ((m + 1 + 15) / 16));
+            k_gram<T><<<grid, kThreads, 0, s>>>(N, m, act, U, Q, r, gpart);
+        }
+        {
+            ProfScope ps_(c, KID_SCALARS, s);
+            k_gram_solve<<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
+        }
+        ProfScope ps_(c, KID_GALERKIN, s);
+        switch (mb) {
+            case 1: launch_gal<T, 1>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            case 4: launch_gal<T, 4>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            case 8: launch_gal<T, 8>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            case 16: launch_gal<T, 16>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            default: launch_gal<T, 32>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+        }
+    }
+    {
+        ProfScope ps_(c, KID_INIT_DIR, s);
+        switch (mb) {
+            case 0: launch_init<T, 0>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 1: launch_init<T, 1>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 4: launch_init<T, 4>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 8: launch_init<T, 8>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 16: launch_init<T, 16>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            default: launch_init<T, 32>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+        }
+    }
+    // in-loop projection set: all of U (project_all) or the most recent recycled direction
+    SlotList pl{};
+    int mp = 0;
+    if (m > 0) {
+        if (c.project_all) {
+            pl = act;
+            mp = m;
+        } else {
+            pl.s[0] = ((c.head - 1) % K + K) % K;
+            mp = 1;
+        }
+    }
+    const int mpb = bucket(mp);
+    // a5 + a6: iterations
+    for (int it = 0; it < c.max_iter; ++it) {
+        const int ps = (c.head + it) % K;
+        T* p = U + size_t(ps) * N;
+        T* q = Q + size_t(ps) * N;
+        T* pn = U + size_t((c.head + it + 1) % K) * N;
+        launch_apply_M<T>(c, p, q, pqp, s);
+        const int last = it == c.max_iter - 1;
+        switch (mpb) {
+            case 0: launch_upd<T, 0>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+                                     c.project_all, pn, c, s); break;
+            case 1: launch_upd<T, 1>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+                                     c.project_all, pn, c, s); break;
+            case 4: launch_upd<T, 4>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+                                     c.project_all, pn, c, s); break;
+            case 8: launch_upd<T, 8>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+                                     c.project_all, pn, c, s); break;
+            case 16: launch_upd<T, 16>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+                                       c.project_all, pn, c, s); break;
+            default: launch_upd<T, 32>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+                                       c.project_all, pn, c, s); break;
+        }
+    }
+    {
+        ProfScope ps_(c, KID_SCALARS, s);
+        k_finish<<<1, kThreads, 0, s>>>(sc, part, info, info_user, c.max_iter);
+    }
+    if (c_out) (void)hipMemcpyAsync(c_out, cv, sizeof(T) * N, hipMemcpyDeviceToDevice, s);
+    // a7: ring bookkeeping (the fixed iteration count makes it host-known)
+    c.head = (c.head + c.max_iter) % K;
+    c.count = std::min(c.count + c.max_iter, K);
+    c.last_iters = c.max_iter;
+    c.first = false;
+}
+
+template void launch_solve_frame<float>(Ctx&, const float*, float*, fewha_solve_info*, hipStream_t);
+template void launch_solve_frame<double>(Ctx&, const double*, double*, fewha_solve_info*, hipStream_t);
+
+}  // namespace fewha
