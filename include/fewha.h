@@ -167,6 +167,13 @@ fewha_status fewha_state_size(const fewha_ctx* ctx, size_t* bytes);
 fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream);
 fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream);
 
+/* Frame execution mode.  Enabled (the default): the first frame of every recycle-ring phase is
+ * captured once into a HIP graph on a private stream and later frames replay it on `stream`
+ * (the slopes, coefficients and statistics pass through device-to-device copies outside the
+ * graph, so the caller's pointers may change between frames).  Disabled: every kernel is
+ * launched individually.  Both modes give bit-identical results. */
+fewha_status fewha_use_graphs(fewha_ctx* ctx, int32_t enable);
+
 /* Diagnostic kernel profiler.  While enabled, every kernel launch of the compute calls is
  * bracketed by HIP events recorded on the call's stream and the call synchronises that
  * stream before returning (so a profiled run is not a latency measurement).
@@ -176,6 +183,19 @@ fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream);
 fewha_status fewha_profile(fewha_ctx* ctx, int32_t enable);
 fewha_status fewha_profile_read(const fewha_ctx* ctx, double* ms, int64_t* launches, int32_t n, int32_t* n_out);
 const char* fewha_kernel_name(int32_t i);
+
+/* Diagnostic timer of one operator kernel (profiler index 0-5: coarse synthesis, tiled synthesis
+ * step, fused data term, propagation adjoint, tiled analysis step, coarse analysis; `step`
+ * selects the tiled level, see fewha_wavelet_steps).  The kernel is launched `reps` times with
+ * the arguments it has inside M x (input: the carried coefficients), captured into one graph and
+ * replayed between two events recorded on `stream`; *avg_ms receives the mean duration.
+ * Overwrites the context's scratch vectors (not the carried state).  Synchronises `stream`. */
+fewha_status fewha_time_kernel(fewha_ctx* ctx, int32_t kernel, int32_t step, int32_t reps, void* stream,
+                               float* avg_ms);
+
+/* Tiled wavelet levels of the context (ascending block size) and the number of layers in each. */
+fewha_status fewha_wavelet_steps(const fewha_ctx* ctx, int32_t* block_sizes, int32_t* layer_counts, int32_t n,
+                                 int32_t* n_out);
 
 /* Release the context (the workspace stays the caller's). */
 fewha_status fewha_destroy(fewha_ctx* ctx);

@@ -23,8 +23,8 @@ STATUS = {0: "FEWHA_OK", 1: "FEWHA_E_INVAL", 2: "FEWHA_E_NOMEM", 3: "FEWHA_E_HIP
 
 EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
            "fewha_solve_aug", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
-           "fewha_get_state", "fewha_set_state", "fewha_profile", "fewha_profile_read", "fewha_kernel_name",
-           "fewha_destroy", "fewha_last_error"]
+           "fewha_get_state", "fewha_set_state", "fewha_use_graphs", "fewha_profile", "fewha_profile_read",
+           "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error"]
 
 
 class fewha_layer(C.Structure):
@@ -81,9 +81,12 @@ def load_library(path: str = LIB_PATH):
         "fewha_state_size": ([vp, C.POINTER(C.c_size_t)], st),
         "fewha_get_state": ([vp, vp, vp], st),
         "fewha_set_state": ([vp, vp, vp], st),
+        "fewha_use_graphs": ([vp, C.c_int32], st),
         "fewha_profile": ([vp, C.c_int32], st),
         "fewha_profile_read": ([vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)], st),
         "fewha_kernel_name": ([C.c_int32], C.c_char_p),
+        "fewha_time_kernel": ([vp, C.c_int32, C.c_int32, C.c_int32, vp, C.POINTER(C.c_float)], st),
+        "fewha_wavelet_steps": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)], st),
         "fewha_destroy": ([vp], st),
         "fewha_last_error": ([vp], C.c_char_p),
     }
@@ -250,6 +253,9 @@ class FewhaContext:
     def fewha_set_state(self, buf, stream=None):
         _check(self.lib.fewha_set_state(self.ctx, _ptr(buf), _stream(stream)), self.ctx)
 
+    def fewha_use_graphs(self, enable=True):
+        _check(self.lib.fewha_use_graphs(self.ctx, int(bool(enable))), self.ctx)
+
     def fewha_profile(self, enable=True):
         _check(self.lib.fewha_profile(self.ctx, int(bool(enable))), self.ctx)
 
@@ -261,6 +267,20 @@ class FewhaContext:
         cnt = C.c_int32()
         _check(self.lib.fewha_profile_read(self.ctx, ms, ln, n, C.byref(cnt)), self.ctx)
         return {self.lib.fewha_kernel_name(i).decode(): (ms[i], ln[i]) for i in range(cnt.value)}
+
+    def fewha_time_kernel(self, kernel, step=0, reps=50, stream=None) -> float:
+        """Mean duration in ms of one operator kernel (see include/fewha.h)."""
+        ms = C.c_float()
+        _check(self.lib.fewha_time_kernel(self.ctx, kernel, step, reps, _stream(stream), C.byref(ms)), self.ctx)
+        return ms.value
+
+    def fewha_wavelet_steps(self):
+        """[(block size, layer count)] of the tiled wavelet levels."""
+        bs = (C.c_int32 * 16)()
+        lc = (C.c_int32 * 16)()
+        n = C.c_int32()
+        _check(self.lib.fewha_wavelet_steps(self.ctx, bs, lc, 16, C.byref(n)), self.ctx)
+        return [(bs[i], lc[i]) for i in range(n.value)]
 
     def fewha_destroy(self):
         if getattr(self, "ctx", None):

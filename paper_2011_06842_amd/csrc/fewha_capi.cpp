@@ -149,12 +149,14 @@ fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d
     if (!ctx || !d_s) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
     fewha::Ctx& c = ctx->c;
     auto* info = static_cast<fewha_solve_info*>(d_info);
+    hipError_t e;
     if (c.prec == FEWHA_FP64)
-        fewha::launch_solve_frame<double>(c, static_cast<const double*>(d_s), static_cast<double*>(d_c), info,
-                                          as_stream(stream));
+        e = fewha::launch_solve_frame<double>(c, static_cast<const double*>(d_s), static_cast<double*>(d_c), info,
+                                              as_stream(stream));
     else
-        fewha::launch_solve_frame<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
-                                         as_stream(stream));
+        e = fewha::launch_solve_frame<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
+                                             as_stream(stream));
+    if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("frame launch failed: ") + hipGetErrorString(e));
     return check_launch(ctx, as_stream(stream));
 }
 
@@ -302,13 +304,45 @@ fewha_status fewha_profile_read(const fewha_ctx* ctx, double* ms, int64_t* launc
     return FEWHA_OK;
 }
 
+fewha_status fewha_time_kernel(fewha_ctx* ctx, int32_t kernel, int32_t step, int32_t reps, void* stream,
+                               float* avg_ms) {
+    if (!ctx || !avg_ms) return FEWHA_E_INVAL;
+    fewha::Ctx& c = ctx->c;
+    hipError_t e = c.prec == FEWHA_FP64
+                       ? fewha::time_operator_kernel<double>(c, kernel, step, reps, as_stream(stream), avg_ms)
+                       : fewha::time_operator_kernel<float>(c, kernel, step, reps, as_stream(stream), avg_ms);
+    if (e == hipErrorInvalidValue) return fail(ctx, FEWHA_E_INVAL, "kernel is not an operator kernel or bad step");
+    if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("kernel timing failed: ") + hipGetErrorString(e));
+    return FEWHA_OK;
+}
+
+fewha_status fewha_wavelet_steps(const fewha_ctx* ctx, int32_t* block_sizes, int32_t* layer_counts, int32_t n,
+                                 int32_t* n_out) {
+    if (!ctx) return FEWHA_E_INVAL;
+    const auto& st = ctx->c.steps;
+    for (int i = 0; i < n && i < int(st.size()); ++i) {
+        if (block_sizes) block_sizes[i] = st[i].nb;
+        if (layer_counts) layer_counts[i] = int32_t(st[i].layers.size());
+    }
+    if (n_out) *n_out = int32_t(st.size());
+    return FEWHA_OK;
+}
+
 const char* fewha_kernel_name(int32_t i) {
     return (i >= 0 && i < fewha::KID_COUNT) ? fewha::kKernelNames[i] : nullptr;
 }
 
+fewha_status fewha_use_graphs(fewha_ctx* ctx, int32_t enable) {
+    if (!ctx) return FEWHA_E_INVAL;
+    ctx->c.use_graphs = enable != 0;
+    return FEWHA_OK;
+}
+
 fewha_status fewha_destroy(fewha_ctx* ctx) {
-    if (ctx)
+    if (ctx) {
         for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
+        fewha::release_graphs(ctx->c);
+    }
     delete ctx;
     return FEWHA_OK;
 }

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fewha.h"
@@ -94,10 +96,11 @@ struct Layout {
     size_t state_bytes;
 };
 
-// Kernel families, for the optional event profiler.
+// Kernels, for the optional event profiler and the per-kernel timer.
 enum KernelId : int {
-    KID_IDWT = 0, KID_DWT, KID_DATA_TERM, KID_ADJ_GATHER, KID_SLOPES_ADJ, KID_RESIDUAL, KID_GRAM,
-    KID_GALERKIN, KID_INIT_DIR, KID_DOT, KID_UPDATE1, KID_UPDATE2, KID_SCALARS, KID_COUNT
+    KID_IDWT_COARSE = 0, KID_IDWT_STEP, KID_DATA_TERM, KID_ADJ_GATHER, KID_DWT_STEP, KID_DWT_COARSE,
+    KID_SLOPES_ADJ, KID_RESIDUAL, KID_GRAM, KID_GRAM_SOLVE, KID_GALERKIN, KID_INIT_DIR, KID_UPDATE1,
+    KID_UPDATE2, KID_FINISH, KID_FWD_SLOPES, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 
@@ -135,6 +138,10 @@ struct Ctx {
     Layout lay{};
     std::string err;
     mutable Profiler prof;
+    // captured frame graphs, keyed by (ring head, first frame, recycled directions)
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
     template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
 
@@ -164,6 +171,9 @@ template <typename T> void launch_adj_gather(const Ctx& c, const T* psi_nodes, T
 template <typename T> void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s);
 template <typename T> void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s);
 template <typename T> void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s);
-template <typename T> void launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info, hipStream_t s);
+template <typename T> hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info,
+                                                   hipStream_t s);
+void release_graphs(Ctx& c);
+template <typename T> hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t s, float* ms);
 
 }  // namespace fewha

@@ -683,8 +683,8 @@ inline unsigned cdiv(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
 // ------------------------------------------------------------------ profiler
 
 const char* const kKernelNames[KID_COUNT] = {
-    "idwt", "dwt", "data_term", "adj_gather", "slopes_adj", "residual", "gram",
-    "galerkin_apply", "init_dir", "dot", "update1", "update2", "scalars"};
+    "idwt_coarse", "idwt_step", "data_term", "adj_gather", "dwt_step", "dwt_coarse", "slopes_adj", "residual",
+    "gram", "gram_solve", "galerkin_apply", "init_dir", "update1", "update2", "finish", "fwd_slopes"};
 
 ProfScope::ProfScope(const Ctx& ctx, int kid, hipStream_t stream) : c(ctx), s(stream) {
     Profiler& p = c.prof;
@@ -734,13 +734,13 @@ void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
     T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
     {
-        ProfScope ps_(c, KID_IDWT, s);
+        ProfScope ps_(c, KID_IDWT_COARSE, s);
         k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], phi);
     }
     for (size_t j = 0; j < c.steps.size(); ++j) {
         const WaveStep& w = c.steps[j];
         const int tiles = (w.nb / kST) * (w.nb / kST);
-        ProfScope ps_(c, KID_IDWT, s);
+        ProfScope ps_(c, KID_IDWT_STEP, s);
         k_idwt_step<T><<<tiles * int(w.layers.size()), kThreads, 0, s>>>(lays, step_layers(w), w.nb, f, x, buf[j & 1],
                                                                        buf[(j + 1) & 1], phi);
     }
@@ -759,12 +759,12 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, const T* xd
         const WaveStep& w = c.steps[J - 1 - j];
         const int tiles = (w.nb / 2 / kAT) * (w.nb / 2 / kAT);
         const int blocks = tiles * int(w.layers.size());
-        ProfScope ps_(c, KID_DWT, s);
+        ProfScope ps_(c, KID_DWT_STEP, s);
         k_dwt_step<T><<<blocks, kThreads, 0, s>>>(lays, step_layers(w), w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y,
                                                   pa, xprior, xdot, pq_part ? pq_part + used : nullptr);
         used += blocks;
     }
-    ProfScope ps_(c, KID_DWT, s);
+    ProfScope ps_(c, KID_DWT_COARSE, s);
     k_dwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, xdot,
                                                    pq_part ? pq_part + used : nullptr);
 }
@@ -804,7 +804,7 @@ void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStrea
 
 template <typename T>
 void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s) {
-    ProfScope ps_(c, KID_DATA_TERM, s);
+    ProfScope ps_(c, KID_FWD_SLOPES, s);
     k_fwd_slopes<T><<<cdiv(c.S, kThreads), kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.S,
                                                              c.at<LayerDev>(c.lay.layers), c.L,
                                                              c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
@@ -831,6 +831,91 @@ void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s) {
     launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), nullptr, s);
 }
 
+// Launches one operator kernel with the arguments it has inside M x (input: the coefficient
+// vector c; intermediates: the context buffers).  step selects the tiled wavelet level.
+template <typename T>
+static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
+    const Filt<T> f = make_filt<T>();
+    const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
+    T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
+    const T* x = c.at<T>(c.lay.c);
+    T* y = c.at<T>(c.lay.vy);
+    const int J = int(c.steps.size());
+    switch (kid) {
+        case KID_IDWT_COARSE:
+            k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], c.at<T>(c.lay.nodal));
+            break;
+        case KID_IDWT_STEP: {
+            if (step < 0 || step >= J) return hipErrorInvalidValue;
+            const WaveStep& w = c.steps[step];
+            k_idwt_step<T><<<(w.nb / kST) * (w.nb / kST) * int(w.layers.size()), kThreads, 0, s>>>(
+                lays, step_layers(w), w.nb, f, x, buf[step & 1], buf[(step + 1) & 1], c.at<T>(c.lay.nodal));
+            break;
+        }
+        case KID_DATA_TERM:
+            launch_data_term<T>(c, c.at<T>(c.lay.nodal), c.at<T>(c.lay.psi_nodes), s);
+            break;
+        case KID_ADJ_GATHER:
+            launch_adj_gather<T>(c, c.at<T>(c.lay.psi_nodes), c.at<T>(c.lay.psi_layers), s);
+            break;
+        case KID_DWT_STEP: {
+            if (step < 0 || step >= J) return hipErrorInvalidValue;
+            const WaveStep& w = c.steps[step];
+            const int j = J - 1 - step;
+            k_dwt_step<T><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * int(w.layers.size()), kThreads, 0, s>>>(
+                lays, step_layers(w), w.nb, f, c.at<T>(c.lay.psi_layers), buf[(j + 1) & 1], buf[j & 1], y,
+                c.at<T>(c.lay.prior_a), x, x, c.at<double>(c.lay.pq_part));
+            break;
+        }
+        case KID_DWT_COARSE:
+            k_dwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J - 1) & 1], y,
+                                                           c.at<T>(c.lay.prior_a), x, x, c.at<double>(c.lay.pq_part));
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Average duration of one operator kernel: `reps` launches captured into one graph, replayed
+// between two events on stream s (the graph keeps the gaps between launches small).
+template <typename T>
+hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t s, float* ms) {
+    if (reps < 1 || !ms) return hipErrorInvalidValue;
+    const bool prof_on = c.prof.on;     // no profiler events inside the captured graph
+    c.prof.on = false;
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        for (int r = 0; r < reps && le == hipSuccess; ++r) le = launch_one<T>(c, kid, step, cs);
+        e = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, s);            // warm-up replay
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = hipGraphLaunch(ge, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e == hipSuccess) *ms = t / reps;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+    c.prof.on = prof_on;
+    return e;
+}
+
 #define FEWHA_INSTANTIATE_OP(T)                                                                           \
     template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t);                                  \
     template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, const T*, double*, hipStream_t);    \
@@ -839,7 +924,8 @@ void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s) {
     template void launch_adj_gather<T>(const Ctx&, const T*, T*, hipStream_t);                            \
     template void launch_fwd_slopes<T>(const Ctx&, const T*, T*, hipStream_t);                            \
     template void launch_apply_M<T>(const Ctx&, const T*, T*, double*, hipStream_t);                      \
-    template void launch_rhs<T>(const Ctx&, const T*, T*, hipStream_t);
+    template void launch_rhs<T>(const Ctx&, const T*, T*, hipStream_t);                                   \
+    template hipError_t time_operator_kernel<T>(Ctx&, int, int, int, hipStream_t, float*);
 
 FEWHA_INSTANTIATE_OP(float)
 FEWHA_INSTANTIATE_OP(double)

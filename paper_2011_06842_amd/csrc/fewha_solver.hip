@@ -68,6 +68,100 @@ __device__ void chol_solve(const double* R, const int32_t* keep, int m, const do
     }
 }
 
+// Small dense algebra of the recycle space on one wavefront (m <= MB <= 64): lane k owns
+// column k (and row k) of the factor in registers, pivots and solution entries travel by
+// shuffles, so no step waits on a chain of dependent memory reads.
+
+// G = R^T R (R upper) of the symmetric matrix whose upper triangle is X[a * ld + b] (a <= b),
+// columns in order, column j dropped (row j of R zero, keep[j] = 0) when its pivot is
+// <= 1e-14 max diag G.  R is written to Rout[i * m + k] (LDS or global); returns the drop count.
+template <int MB>
+__device__ int wave_cholesky(const double* X, int ld, int m, double* Rout, int32_t* keep) {
+    const int k = threadIdx.x & 63;
+    double g[MB], c[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        g[i] = (i < m && k < m && i <= k) ? X[i * ld + k] : 0.0;
+        c[i] = 0.0;
+    }
+    double dmax = k < m ? X[k * ld + k] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+    const double thr = 1e-14 * dmax;
+    int dropped = 0;
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        if (j < m) {
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (i < j) s += __shfl(c[i], j, 64) * c[i];
+            const double d = __shfl(g[j] - s, j, 64);
+            const bool kj = d > thr;
+            const double rjj = kj ? sqrt(d) : 0.0;
+            c[j] = !kj ? 0.0 : (k == j ? rjj : (k > j ? (g[j] - s) / rjj : 0.0));
+            dropped += kj ? 0 : 1;
+            if (k == 0) keep[j] = kj ? 1 : 0;
+        }
+    }
+    if (k < m)
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (i < m) Rout[i * m + k] = c[i];
+    return dropped;
+}
+
+// y = G^-1 v with the factor above (dropped columns give y_j = 0); lane k passes v_k and gets y_k.
+template <int MB>
+__device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, double v) {
+    const int k = threadIdx.x & 63;
+    double col[MB], row[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        col[i] = (i < m && k < m) ? R[i * m + k] : 0.0;   // R[i][k]
+        row[i] = (i < m && k < m) ? R[k * m + i] : 0.0;   // R[k][i]
+    }
+    // R^T t = v, column by column
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        if (j < m) {
+            const double rjj = __shfl(col[j], j, 64);
+            const double tj = keep[j] ? __shfl(v, j, 64) / rjj : 0.0;
+            if (k == j) v = tj;
+            else if (k > j) v -= col[j] * tj;
+        }
+    }
+    // R y = t, from the last column back
+#pragma unroll
+    for (int j = MB - 1; j >= 0; --j) {
+        if (j < m) {
+            const double rjj = __shfl(col[j], j, 64);
+            const double yj = keep[j] ? __shfl(v, j, 64) / rjj : 0.0;
+            if (k == j) v = yj;
+            else if (k < j) v -= row[j] * yj;
+        }
+    }
+    return k < m ? v : 0.0;
+}
+
+// Sequential single-vector projections as a triangular solve: x_j = (v_j - sum_{i<j} x_i L(j, i)) / d_j,
+// with L(j, i) = M[j * ldr + i * ldc] read by lane j... column-oriented: after x_j, lanes k > j
+// subtract x_j L(k, j).  Lane k passes v_k, gets x_k.
+template <int MB>
+__device__ double wave_forward_sub(const double* Mx, int ldr, int ldc, const double* diag, int m, double v) {
+    const int k = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < MB; ++j) {
+        if (j < m) {
+            const double xj = __shfl(v, j, 64) / diag[j];
+            const double lkj = (k > j && k < m) ? Mx[k * ldr + j * ldc] : 0.0;
+            if (k == j) v = xj;
+            else if (k > j) v -= xj * lkj;
+        }
+    }
+    return k < m ? v : 0.0;
+}
+
 // ------------------------------------------------------------------ frame start
 
 // First frame: r = b - M c; later frames: r = (b - b_prev) + r (Alg. 3 residual update).
@@ -114,18 +208,24 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, int m, SlotList sl
     const T* pa = ar < m ? U + size_t(sl.s[ar]) * N : nullptr;
     const T* pb = bc < m ? Q + size_t(sl.s[bc]) * N : (bc == m ? r : nullptr);
     f64x4 c = {0.0, 0.0, 0.0, 0.0};
+    constexpr int DEPTH = 4;                       // 16-element chunks whose loads are in flight together
     const int64_t step = int64_t(gridDim.x) * 4 * 16;
-#pragma unroll 4
-    for (int64_t base = (int64_t(blockIdx.x) * 4 + wv) * 16; base < N; base += step) {   // N % 64 == 0
-        const int64_t e0 = base + 4 * kq;
-        double av[4], bv[4];
+    for (int64_t base = (int64_t(blockIdx.x) * 4 + wv) * 16; base < N; base += DEPTH * step) {   // N % 64 == 0
+        double av[DEPTH][4], bv[DEPTH][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            av[j] = pa ? double(pa[e0 + j]) : 0.0;
-            bv[j] = pb ? double(pb[e0 + j]) : 0.0;
+        for (int d = 0; d < DEPTH; ++d) {
+            const int64_t e0 = base + d * step + 4 * kq;
+            const bool in = base + d * step < N;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                av[d][j] = (in && pa) ? double(pa[e0 + j]) : 0.0;
+                bv[d][j] = (in && pb) ? double(pb[e0 + j]) : 0.0;
+            }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], c, 0, 0, 0);
+        for (int d = 0; d < DEPTH; ++d)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][j], bv[d][j], c, 0, 0, 0);
     }
     // lane l, register v holds tile entry (row 4 v + l / 16, column l mod 16)
 #pragma unroll
@@ -143,12 +243,12 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, int m, SlotList sl
 // column j when its pivot is <= 1e-14 max diag G; y = G^-1 U^T r.
 // PAPER: sequential sigma_j with the running residual, (r, p_j) = sigma_j g_j +
 // sum_{i<j} sigma_i (q_i, p_j); X is kept for the initial-direction step.
+template <int MB>
 __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, SlotList sl,
                                                                Scalars* __restrict__ sc,
                                                                const double* __restrict__ gpart) {
     __shared__ double X[kKMax * (kKMax + 1)];
-    __shared__ double R[kKMax * kKMax], v[kKMax], y[kKMax], t[kKMax], gm[kKMax];
-    __shared__ int32_t keep[kKMax];
+    __shared__ double gm[kKMax];
     const int ne = m * (m + 1);
     {   // 8 lanes per entry, each summing kGramBlocks / 8 partials requested all at once
         constexpr int PER = kGramBlocks / 8;
@@ -168,50 +268,23 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     }
     if (threadIdx.x < m) gm[threadIdx.x] = sc->gam[sl.s[threadIdx.x]];
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int W = m + 1;
-    for (int a = 0; a < m; ++a) v[a] = X[a * W + m];
+    if (threadIdx.x >= 64) return;
+    const int k = threadIdx.x, W = m + 1;
+    const double v = k < m ? X[k * W + m] : 0.0;   // (U_k, r)
+    double y;
     if (mode == FEWHA_RECYCLE_PAPER) {
-        for (int j = 0; j < m; ++j) {
-            double s = v[j];
-            for (int i = 0; i < j; ++i) s -= y[i] * X[j * W + i];
-            y[j] = s / gm[j];
-        }
-        for (int j = 0; j < m; ++j) sc->y[j] = y[j];
-        for (int a = 0; a < m; ++a)
-            for (int b = 0; b < m; ++b) sc->R[a * m + b] = X[a * W + b];
-        sc->dropped = 0;
-        return;
+        // (r, p_j) = sigma_j g_j + sum_{i<j} sigma_i (q_i, p_j),  (q_i, p_j) = X[j][i]
+        y = wave_forward_sub<MB>(X, W, 1, gm, m, v);
+        if (k < m)
+            for (int b = 0; b < m; ++b) sc->R[k * m + b] = X[k * W + b];
+        if (k == 0) sc->dropped = 0;
+    } else {
+        const int dropped = wave_cholesky<MB>(X, W, m, sc->R, sc->keep);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        y = wave_chol_solve<MB>(sc->R, sc->keep, m, v);
+        if (k == 0) sc->dropped = dropped;
     }
-    double dmax = 0;
-    for (int j = 0; j < m; ++j) dmax = fmax(dmax, X[j * W + j]);
-    const double thr = 1e-14 * dmax;
-    int dropped = 0;
-    for (int i = 0; i < m * m; ++i) R[i] = 0;
-    for (int j = 0; j < m; ++j) {
-        double d = X[j * W + j];
-        for (int i = 0; i < j; ++i) d -= R[i * m + j] * R[i * m + j];
-        if (!(d > thr)) {
-            keep[j] = 0;
-            ++dropped;
-            continue;
-        }
-        keep[j] = 1;
-        const double rjj = sqrt(d);
-        R[j * m + j] = rjj;
-        for (int k = j + 1; k < m; ++k) {
-            double s = X[j * W + k];
-            for (int i = 0; i < j; ++i) s -= R[i * m + j] * R[i * m + k];
-            R[j * m + k] = s / rjj;
-        }
-    }
-    chol_solve(R, keep, m, v, y, t);
-    for (int i = 0; i < m * m; ++i) sc->R[i] = R[i];
-    for (int j = 0; j < m; ++j) {
-        sc->keep[j] = keep[j];
-        sc->y[j] = y[j];
-    }
-    sc->dropped = dropped;
+    if (k < m) sc->y[k] = y;
 }
 
 // Galerkin step c += U y, r -= Q y; then z = J^-1 r and partials of (Q_a, z).
@@ -271,38 +344,39 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mod
                                                         const T* __restrict__ jinv, T* __restrict__ p,
                                                         double* __restrict__ part) {
     constexpr int MB1 = MB > 0 ? MB : 1;
-    __shared__ double sy[MB1];
+    __shared__ double y2[kKMax];
     if (MB > 0) {
         double v[MB1];
         block_row_sums<MB1>(part, P_PROJ, m, v);
-        __shared__ double y2[kKMax], vt[kKMax], t[kKMax], gm[kKMax], R[kKMax * kKMax];
+        __shared__ double gm[kKMax], R[kKMax * kKMax];
         __shared__ int32_t keep[kKMax];
-        for (int e = threadIdx.x; e < m * m; e += blockDim.x) R[e] = sc->R[e];
+        for (int e = threadIdx.x; e < m * m; e += kThreads) R[e] = sc->R[e];
         if (threadIdx.x < m) {
             keep[threadIdx.x] = sc->keep[threadIdx.x];
             gm[threadIdx.x] = sc->gam[sl.s[threadIdx.x]];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int j = 0; j < m; ++j) vt[j] = v[j];
-            if (mode == FEWHA_RECYCLE_PAPER) {
-                for (int j = 0; j < m; ++j) {
-                    double s = vt[j];
-                    for (int i = 0; i < j; ++i) s -= y2[i] * R[i * m + j];
-                    y2[j] = s / gm[j];
-                }
-            } else {
-                chol_solve(R, keep, m, vt, y2, t);
+        if (threadIdx.x < 64) {
+            const int k = threadIdx.x;
+            double vk = 0;
+#pragma unroll
+            for (int a = 0; a < MB1; ++a)
+                if (a == k) vk = v[a];
+            double yk;
+            if (mode == FEWHA_RECYCLE_PAPER)   // (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j),  (p_i, q_j) = R[i][j]
+                yk = wave_forward_sub<MB1>(R, 1, m, gm, m, vk);
+            else
+                yk = wave_chol_solve<MB1>(R, keep, m, vk);
+            if (k < m) {
+                y2[k] = yk;
+                if (blockIdx.x == 0) sc->y2[k] = yk;
             }
-            for (int j = 0; j < m; ++j) sy[j] = y2[j];
-            if (blockIdx.x == 0)
-                for (int j = 0; j < m; ++j) sc->y2[j] = y2[j];
         }
         __syncthreads();
     }
-    double y2[MB1];
+    double yv[MB1];
 #pragma unroll
-    for (int a = 0; a < MB; ++a) y2[a] = a < m ? sy[a] : 0.0;
+    for (int a = 0; a < MB; ++a) yv[a] = a < m ? y2[a] : 0.0;
     double rz = 0;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
         T pt;
@@ -312,7 +386,7 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mod
             double pi = double(z[i]);
 #pragma unroll
             for (int a = 0; a < MB; ++a)
-                if (a < m) pi -= y2[a] * double(U[size_t(sl.s[a]) * N + i]);
+                if (a < m) pi -= yv[a] * double(U[size_t(sl.s[a]) * N + i]);
             pt = T(pi);
         }
         p[i] = pt;
@@ -385,14 +459,11 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, int it, int mp,
         if (lane == 0) sh[k][wv] = s;
     }
     __syncthreads();
-    // rows: P_RR, P_RZ1, P_PROJ + a (Q_a, z), P_PROJ + mp + a (U_a, r)
+    // rows: P_RR, P_RZ1, P_PROJ + a (Q_a, z), P_PROJ + MP + a (U_a, r)
     const int k = threadIdx.x;
-    const int nv = last ? 1 : 2 + 2 * mp;
-    if (k < nv) {
-        int src = k;
-        if (k >= 2 + mp) src = 2 + MP + (k - 2 - mp);
+    if (k < (last ? 1 : NV)) {
         const int row = k == 0 ? P_RR : (k == 1 ? P_RZ1 : P_PROJ + (k - 2));
-        part[size_t(row) * kVecBlocks + blockIdx.x] = (sh[src][0] + sh[src][1]) + (sh[src][2] + sh[src][3]);
+        part[size_t(row) * kVecBlocks + blockIdx.x] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
     }
 }
 
@@ -409,30 +480,39 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, int it, int mp,
     __shared__ double sy[MP1];
     __shared__ double sbeta;
     double v[NV];
-    block_row_sums<NV>(part, P_RZ1, 1 + 2 * mp, v);   // (r,z), (Q_a,z) a < mp, (U_a,r) a < mp
-    __shared__ double y3[MP1], qz[MP1], t[MP1], R[MP1 * MP1];
+    block_row_sums<NV>(part, P_RZ1, NV, v);   // (r,z), (Q_a,z) a < MP, (U_a,r) a < MP (entries a >= mp unused)
+    __shared__ double y3[MP1], R[MP1 * MP1];
     __shared__ int32_t keep[MP1];
     if (MP > 1 && project_all) {
-        for (int e = threadIdx.x; e < mp * mp; e += blockDim.x) R[e] = sc->R[e];
+        for (int e = threadIdx.x; e < mp * mp; e += kThreads) R[e] = sc->R[e];
         if (threadIdx.x < mp) keep[threadIdx.x] = sc->keep[threadIdx.x];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        const int k = threadIdx.x;
         if constexpr (MP > 0) {
             if (project_all) {
-                if (MP == 1) {
+                if (MP == 1 && k == 0) {
                     R[0] = sc->R[0];
                     keep[0] = sc->keep[0];
                 }
-                for (int a = 0; a < mp; ++a) qz[a] = v[1 + a];
-                chol_solve(R, keep, mp, qz, y3, t);
-            } else {
+                double vk = 0;
+#pragma unroll
+                for (int a = 0; a < MP; ++a)
+                    if (a == k) vk = v[1 + a];
+                const double yk = wave_chol_solve<MP1>(R, keep, mp, vk);
+                if (k < mp) y3[k] = yk;
+            } else if (k == 0) {
                 y3[0] = v[1] / sc->gam[pl.s[0]];
             }
         }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         double rzn = v[0];
-        if constexpr (MP > 0)
-            for (int a = 0; a < mp; ++a) rzn -= y3[a] * v[1 + mp + a];
+#pragma unroll
+        for (int a = 0; a < MP; ++a)
+            if (a < mp) rzn -= y3[a] * v[1 + MP + a];
         const double rz_old = sc->rzb[it & 1];
         double beta = rz_old != 0 ? rzn / rz_old : 0.0;
         const bool broken = sc->flags != 0 || !isfinite(beta);
@@ -521,8 +601,9 @@ void launch_upd(int64_t N, int it, int mp, const SlotList& pl, const T* U, const
 
 }  // namespace
 
+// Enqueues one frame on stream s (no host-state change, so it can be captured).
 template <typename T>
-void launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info_user, hipStream_t s) {
+void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s) {
     const int64_t N = c.N;
     const int K = c.slots;
     T* b = c.at<T>(c.lay.b);
@@ -564,8 +645,13 @@ void launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* inf
             k_gram<T><<<grid, kThreads, 0, s>>>(N, m, act, U, Q, r, gpart);
         }
         {
-            ProfScope ps_(c, KID_SCALARS, s);
-            k_gram_solve<<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
+            ProfScope ps_(c, KID_GRAM_SOLVE, s);
+            if (m <= 8)
+                k_gram_solve<8><<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
+            else if (m <= 16)
+                k_gram_solve<16><<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
+            else
+                k_gram_solve<32><<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
         }
         ProfScope ps_(c, KID_GALERKIN, s);
         switch (mb) {
@@ -624,18 +710,64 @@ void launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* inf
         }
     }
     {
-        ProfScope ps_(c, KID_SCALARS, s);
+        ProfScope ps_(c, KID_FINISH, s);
         k_finish<<<1, kThreads, 0, s>>>(sc, part, info, info_user, c.max_iter);
     }
-    if (c_out) (void)hipMemcpyAsync(c_out, cv, sizeof(T) * N, hipMemcpyDeviceToDevice, s);
+}
+
+
+template <typename T>
+hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info_user, hipStream_t s) {
+    const int64_t N = c.N;
+    int m = 0;
+    if (!c.first && c.k > 0)
+        m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
+    hipError_t e = hipSuccess;
+    if (c.use_graphs && !c.prof.on) {
+        // the graph reads the slopes from, and writes the frame statistics to, context buffers
+        T* s_in = c.at<T>(c.lay.s_in);
+        fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
+        const auto key = std::make_tuple(c.head, c.first ? 1 : 0, m);
+        auto it = c.graphs.find(key);
+        if (it == c.graphs.end()) {
+            if (!c.cap_stream) e = hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking);
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            if (e == hipSuccess) e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                enqueue_frame<T>(c, s_in, nullptr, c.cap_stream);
+                e = hipStreamEndCapture(c.cap_stream, &g);
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+            it = c.graphs.emplace(key, ge).first;
+        }
+        e = hipMemcpyAsync(s_in, slopes, sizeof(T) * c.S, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipGraphLaunch(it->second, s);
+        if (e == hipSuccess && info_user)
+            e = hipMemcpyAsync(info_user, info, sizeof(fewha_solve_info), hipMemcpyDeviceToDevice, s);
+    } else {
+        enqueue_frame<T>(c, slopes, info_user, s);
+    }
+    if (e == hipSuccess && c_out) e = hipMemcpyAsync(c_out, c.at<T>(c.lay.c), sizeof(T) * N, hipMemcpyDeviceToDevice, s);
     // a7: ring bookkeeping (the fixed iteration count makes it host-known)
+    const int K = c.slots;
     c.head = (c.head + c.max_iter) % K;
     c.count = std::min(c.count + c.max_iter, K);
     c.last_iters = c.max_iter;
     c.first = false;
+    return e;
 }
 
-template void launch_solve_frame<float>(Ctx&, const float*, float*, fewha_solve_info*, hipStream_t);
-template void launch_solve_frame<double>(Ctx&, const double*, double*, fewha_solve_info*, hipStream_t);
+void release_graphs(Ctx& c) {
+    for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
+    c.graphs.clear();
+    if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
+    c.cap_stream = nullptr;
+}
+
+template hipError_t launch_solve_frame<float>(Ctx&, const float*, float*, fewha_solve_info*, hipStream_t);
+template hipError_t launch_solve_frame<double>(Ctx&, const double*, double*, fewha_solve_info*, hipStream_t);
 
 }  // namespace fewha
