@@ -177,9 +177,9 @@ fewha_status fewha_use_graphs(fewha_ctx* ctx, int32_t enable);
 /* Diagnostic kernel profiler.  While enabled, every kernel launch of the compute calls is
  * bracketed by HIP events recorded on the call's stream and the call synchronises that
  * stream before returning (so a profiled run is not a latency measurement).
- * fewha_profile_read fills per-family totals (milliseconds and launch counts, host
- * arrays of n entries) accumulated since enabling and returns the number of families in
- * *n_out; fewha_kernel_name(i) names family i (NULL when out of range). */
+ * fewha_profile_read fills per-kernel totals (milliseconds and launch counts, host
+ * arrays of n entries) accumulated since enabling and returns the number of kernels in
+ * *n_out; fewha_kernel_name(i) names kernel i (NULL when out of range). */
 fewha_status fewha_profile(fewha_ctx* ctx, int32_t enable);
 fewha_status fewha_profile_read(const fewha_ctx* ctx, double* ms, int64_t* launches, int32_t n, int32_t* n_out);
 const char* fewha_kernel_name(int32_t i);

@@ -199,6 +199,32 @@ def test_graph_replay_matches_direct_launches_bitwise(name):
         assert fw.decode_info(info_a) == fw.decode_info(info_b)
 
 
+@pytest.mark.parametrize("name, precision", [("small", "fp64"), ("elt", "fp32")])
+def test_kernel_timer_leaves_carried_state_and_rejects_bad_ids(name, precision):
+    """The per-kernel timer runs operator kernels on scratch buffers only: the next frame is
+    bitwise the one an untimed context computes."""
+    spec, seq, _ = system(name, precision)
+    dt = np.float64 if precision == "fp64" else np.float32
+    a = fw.FewhaContext(spec, device=DEV)
+    b = fw.FewhaContext(spec, device=DEV)
+    for t in range(3):
+        a.fewha_solve_aug(dev(seq[t], dt))
+        b.fewha_solve_aug(dev(seq[t], dt))
+    steps = a.fewha_wavelet_steps()
+    for kid in range(6):
+        for st in (range(len(steps)) if kid in (1, 4) else [0]):
+            assert a.fewha_time_kernel(kid, st, 3) > 0
+    with pytest.raises(fw.FewhaError):
+        a.fewha_time_kernel(7, 0, 3)
+    with pytest.raises(fw.FewhaError):
+        a.fewha_time_kernel(1, len(steps), 3)
+    if name == "elt":
+        assert [nb for nb, _ in steps] == [128, 256]
+    ca = host(a.fewha_solve_aug(dev(seq[3], dt)))
+    cb = host(b.fewha_solve_aug(dev(seq[3], dt)))
+    assert np.array_equal(ca, cb)
+
+
 def test_state_from_other_configuration_rejected():
     spec, seq, sysm = system("small")
     a = fw.FewhaContext(spec, device=DEV)
