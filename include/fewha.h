@@ -46,6 +46,7 @@ extern "C" {
 #define FEWHA_MAX_LAYERS 32
 #define FEWHA_MAX_WFS 32
 #define FEWHA_MAX_RECYCLE 32
+#define FEWHA_MAX_INSTANCES 4096
 
 typedef struct fewha_ctx fewha_ctx;
 
@@ -105,7 +106,8 @@ typedef struct {
     int32_t project_all;         /* GALERKIN only: project every new direction against all of U */
     double rel_tol;              /* reserved, must be 0 (fixed iteration count) */
     int32_t precision;           /* fewha_precision */
-    int32_t pad2_;
+    int32_t block_elems;         /* elements per workgroup of the vector kernels (0 = 384); fixes the
+                                    reduction order, so results are reproducible for a given value */
 } fewha_config;
 
 /* Written by the device at the end of every fewha_solve_aug. */
@@ -128,7 +130,26 @@ fewha_status fewha_workspace_size(const fewha_config* cfg, size_t* bytes);
 fewha_status fewha_setup(const fewha_config* cfg, void* d_workspace, size_t bytes, void* stream,
                          fewha_ctx** out);
 
-/* Number of coefficients N = sum_l n_l^2 and of slopes S = sum_g 2 n_sub,g^2. */
+/* Batch of independent instances solved together (throughput form of Alg. 3: every instance
+ * is its own system of Sec. 3 with its own geometry, prior, preconditioner, carried state and
+ * recycle store; each frame advances all of them).  cfgs: host array of n configurations
+ * (1 <= n <= FEWHA_MAX_INSTANCES) that agree on precision, max_iter, recycle_k, recycle_mode,
+ * project_all, rel_tol and block_elems.  The context's vectors are the concatenations over
+ * instances in order (coefficients, slopes; see fewha_instances); every other entry point
+ * works on the batch as on a single system, and d_info of fewha_solve_aug receives n
+ * records.  An instance gets bit-identical results alone or in a batch (same block_elems).
+ * fewha_setup / fewha_workspace_size are the n = 1 case. */
+fewha_status fewha_workspace_size_batch(const fewha_config* cfgs, int32_t n, size_t* bytes);
+fewha_status fewha_setup_batch(const fewha_config* cfgs, int32_t n, void* d_workspace, size_t bytes, void* stream,
+                               fewha_ctx** out);
+
+/* Instance offsets: coeff_offsets[i] / slope_offsets[i] for i <= n_inst (the last entry is the
+ * total), host arrays of n entries (filled up to n); *n_out receives the instance count. */
+fewha_status fewha_instances(const fewha_ctx* ctx, int64_t* coeff_offsets, int64_t* slope_offsets, int32_t n,
+                             int32_t* n_out);
+
+/* Number of coefficients N = sum_l n_l^2 and of slopes S = sum_g 2 n_sub,g^2 (totals over the
+ * instances of a batch). */
 fewha_status fewha_sizes(const fewha_ctx* ctx, int64_t* n_coeff, int64_t* n_slopes);
 
 /* y = M x (equation for M, Sec. 3).  d_x, d_y: device, N elements; d_y must not alias d_x. */
@@ -162,7 +183,10 @@ fewha_status fewha_apply_piece(fewha_ctx* ctx, int32_t piece, const void* d_in, 
 fewha_status fewha_get_vector(fewha_ctx* ctx, int32_t which, void* d_out, void* stream);
 
 /* Checkpoint of the carried state (c, r, b_prev, recycle store and its bookkeeping).
- * fewha_state_size gives the bytes; get/set copy to/from a device buffer of that size. */
+ * fewha_state_size gives the bytes; get/set copy to/from a device buffer of that size.
+ * Layout: 256-byte header of uint64 (magic, N, slots, element size, ring head, stored count,
+ * previous iterations, first-frame flag, instances), then per instance `slots` doubles
+ * (p_j, q_j), then c, r, b_prev (N each) and the ring U, Q (slots x N each, slot-major). */
 fewha_status fewha_state_size(const fewha_ctx* ctx, size_t* bytes);
 fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream);
 fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream);

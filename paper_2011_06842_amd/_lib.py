@@ -21,7 +21,8 @@ PIECE_WINV, PIECE_WINVT, PIECE_A, PIECE_AT = 0, 1, 2, 3
 STATUS = {0: "FEWHA_OK", 1: "FEWHA_E_INVAL", 2: "FEWHA_E_NOMEM", 3: "FEWHA_E_HIP", 4: "FEWHA_E_NOT_SPD",
           5: "FEWHA_E_BREAKDOWN", 6: "FEWHA_E_STATE"}
 
-EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
+EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", "fewha_setup_batch",
+           "fewha_instances", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
            "fewha_solve_aug", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
            "fewha_get_state", "fewha_set_state", "fewha_use_graphs", "fewha_profile", "fewha_profile_read",
            "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error"]
@@ -44,7 +45,7 @@ class fewha_config(C.Structure):
                 ("prior_diag", C.POINTER(C.c_double)), ("precond_inv", C.POINTER(C.c_double)),
                 ("max_iter", C.c_int32), ("recycle_k", C.c_int32), ("recycle_mode", C.c_int32),
                 ("project_all", C.c_int32), ("rel_tol", C.c_double), ("precision", C.c_int32),
-                ("pad2_", C.c_int32)]
+                ("block_elems", C.c_int32)]
 
 
 class fewha_solve_info(C.Structure):
@@ -71,6 +72,9 @@ def load_library(path: str = LIB_PATH):
     sig = {
         "fewha_workspace_size": ([C.POINTER(fewha_config), C.POINTER(C.c_size_t)], st),
         "fewha_setup": ([C.POINTER(fewha_config), vp, C.c_size_t, vp, C.POINTER(vp)], st),
+        "fewha_workspace_size_batch": ([C.POINTER(fewha_config), C.c_int32, C.POINTER(C.c_size_t)], st),
+        "fewha_setup_batch": ([C.POINTER(fewha_config), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)], st),
+        "fewha_instances": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)], st),
         "fewha_sizes": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], st),
         "fewha_apply_A": ([vp, vp, vp, vp], st),
         "fewha_rhs": ([vp, vp, vp, vp], st),
@@ -119,7 +123,8 @@ def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
     """fewha_config from any object with the attributes of a system description (layers with
     height/weight/spacing/origin_x/origin_y/n/levels; wfs with n_sub/subap/theta_x/theta_y/
     lgs_height/weight; alpha, r0, L0, max_iter, recycle_k, recycle_mode, project_all,
-    precision).  `keep` collects the host arrays that must outlive the setup call."""
+    precision, optionally block_elems).  `keep` collects the host arrays that must outlive the
+    setup call."""
     keep = [] if keep is None else keep
     L, G = len(spec.layers), len(spec.wfs)
     layers = (fewha_layer * L)()
@@ -155,41 +160,66 @@ def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
     cfg.project_all = int(bool(spec.project_all))
     cfg.rel_tol = 0.0
     cfg.precision = FEWHA_FP64 if spec.precision == "fp64" else FEWHA_FP32_OP_FP64_RED
+    cfg.block_elems = int(getattr(spec, "block_elems", 0) or 0)
     return cfg
 
 
-def fewha_workspace_size(spec, **kw) -> int:
+def _configs(specs, prior_diag, precond_inv, keep):
+    """Array of fewha_config for one system description or a list of them (a batch)."""
+    batch = isinstance(specs, (list, tuple))
+    specs = list(specs) if batch else [specs]
+    pd = prior_diag if batch and prior_diag is not None else [prior_diag] * len(specs)
+    pj = precond_inv if batch and precond_inv is not None else [precond_inv] * len(specs)
+    arr = (fewha_config * len(specs))()
+    for i, sp in enumerate(specs):
+        arr[i] = make_config(sp, prior_diag=pd[i], precond_inv=pj[i], keep=keep)
+    return arr, specs
+
+
+def fewha_workspace_size(spec, prior_diag=None, precond_inv=None) -> int:
+    """Workspace bytes of one system description or of a batch (a list of them)."""
     lib = load_library()
     keep = []
-    cfg = make_config(spec, keep=keep, **kw)
+    arr, specs = _configs(spec, prior_diag, precond_inv, keep)
     n = C.c_size_t()
-    _check(lib.fewha_workspace_size(C.byref(cfg), C.byref(n)))
+    _check(lib.fewha_workspace_size_batch(arr, len(specs), C.byref(n)))
     return n.value
 
 
 class FewhaContext:
-    """One solver context: owns its workspace tensor; calls mirror the C ABI names."""
+    """One solver context: owns its workspace tensor; calls mirror the C ABI names.  `spec` is
+    one system description or a list of them (a batch of independent instances, solved
+    together; vectors are then the concatenation over instances, see `coeff_offsets` and
+    `slope_offsets`)."""
 
     def __init__(self, spec, device="cuda", prior_diag=None, precond_inv=None, stream=None):
         import torch
         self.lib = load_library()
         keep = []
-        cfg = make_config(spec, prior_diag=prior_diag, precond_inv=precond_inv, keep=keep)
+        arr, specs = _configs(spec, prior_diag, precond_inv, keep)
+        nb = len(specs)
         n = C.c_size_t()
-        _check(self.lib.fewha_workspace_size(C.byref(cfg), C.byref(n)))
+        _check(self.lib.fewha_workspace_size_batch(arr, nb, C.byref(n)))
         self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
         base = _ptr(self.workspace)
         off = (-base) % 256
         self._ws_ptr = base + off
         ctx = C.c_void_p()
-        _check(self.lib.fewha_setup(C.byref(cfg), C.c_void_p(self._ws_ptr), n.value, C.c_void_p(_stream(stream)),
-                                    C.byref(ctx)))
+        _check(self.lib.fewha_setup_batch(arr, nb, C.c_void_p(self._ws_ptr), n.value, C.c_void_p(_stream(stream)),
+                                          C.byref(ctx)))
         self.ctx = ctx
-        self.dtype = torch.float64 if spec.precision == "fp64" else torch.float32
+        self.dtype = torch.float64 if specs[0].precision == "fp64" else torch.float32
         self.device = device
         Nc, Sc = C.c_int64(), C.c_int64()
         _check(self.lib.fewha_sizes(self.ctx, C.byref(Nc), C.byref(Sc)), self.ctx)
         self.N, self.S = Nc.value, Sc.value
+        co = (C.c_int64 * (nb + 1))()
+        so = (C.c_int64 * (nb + 1))()
+        cnt = C.c_int32()
+        _check(self.lib.fewha_instances(self.ctx, co, so, nb + 1, C.byref(cnt)), self.ctx)
+        self.B = cnt.value
+        self.coeff_offsets = [co[i] for i in range(nb + 1)]
+        self.slope_offsets = [so[i] for i in range(nb + 1)]
 
     # -- helpers
     def _vec(self, n):
@@ -215,8 +245,9 @@ class FewhaContext:
         return b
 
     def fewha_solve_aug(self, s, c=None, info=None, stream=None):
-        """One frame; returns c (device tensor).  `info`, if given, is a 24-byte uint8 device
-        tensor that receives a fewha_solve_info (decode with :func:`decode_info`)."""
+        """One frame; returns c (device tensor).  `info`, if given, is a uint8 device tensor
+        (:meth:`new_info`) that receives one fewha_solve_info per instance (decode with
+        :func:`decode_info`)."""
         s = self._in(s, self.S)
         c = self._vec(self.N) if c is None else self._in(c, self.N)
         ip = _ptr(info) if info is not None else None
@@ -260,7 +291,7 @@ class FewhaContext:
         _check(self.lib.fewha_profile(self.ctx, int(bool(enable))), self.ctx)
 
     def fewha_profile_read(self) -> dict:
-        """{kernel family: (total ms, launches)} accumulated since fewha_profile(True)."""
+        """{kernel: (total ms, launches)} accumulated since fewha_profile(True)."""
         n = 32
         ms = (C.c_double * n)()
         ln = (C.c_int64 * n)()
@@ -295,11 +326,16 @@ class FewhaContext:
 
     def new_info(self):
         import torch
-        return torch.zeros(C.sizeof(fewha_solve_info), dtype=torch.uint8, device=self.device)
+        return torch.zeros(C.sizeof(fewha_solve_info) * self.B, dtype=torch.uint8, device=self.device)
 
 
-def decode_info(info_tensor) -> dict:
+def decode_info(info_tensor):
+    """dict of one fewha_solve_info, or a list of them for a batch."""
     raw = bytes(info_tensor.cpu().numpy().tobytes())
-    s = fewha_solve_info.from_buffer_copy(raw)
-    return {"iters": s.iters, "recycle_used": s.recycle_used, "dropped": s.dropped, "flags": s.flags,
-            "rel_res": s.rel_res}
+    sz = C.sizeof(fewha_solve_info)
+    out = []
+    for i in range(len(raw) // sz):
+        s = fewha_solve_info.from_buffer_copy(raw[i * sz:(i + 1) * sz])
+        out.append({"iters": s.iters, "recycle_used": s.recycle_used, "dropped": s.dropped, "flags": s.flags,
+                    "rel_res": s.rel_res})
+    return out[0] if len(out) == 1 else out

@@ -40,28 +40,33 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 extern "C" {
 
-fewha_status fewha_workspace_size(const fewha_config* cfg, size_t* bytes) {
+fewha_status fewha_workspace_size_batch(const fewha_config* cfgs, int32_t n, size_t* bytes) {
     std::string err;
-    const fewha_status st = fewha::validate_config(cfg, err);
+    const fewha_status st = fewha::validate_batch(cfgs, n, err);
     if (st != FEWHA_OK) {
         g_setup_err = err;
         return st;
     }
     if (!bytes) return FEWHA_E_INVAL;
-    *bytes = fewha::compute_layout(cfg).total;
+    *bytes = fewha::compute_layout(cfgs, n).total;
     return FEWHA_OK;
 }
 
-fewha_status fewha_setup(const fewha_config* cfg, void* d_workspace, size_t bytes, void* stream, fewha_ctx** out) {
+fewha_status fewha_workspace_size(const fewha_config* cfg, size_t* bytes) {
+    return fewha_workspace_size_batch(cfg, 1, bytes);
+}
+
+fewha_status fewha_setup_batch(const fewha_config* cfgs, int32_t n, void* d_workspace, size_t bytes, void* stream,
+                               fewha_ctx** out) {
     if (!out) return FEWHA_E_INVAL;
     *out = nullptr;
     std::string err;
-    fewha_status st = fewha::validate_config(cfg, err);
+    fewha_status st = fewha::validate_batch(cfgs, n, err);
     if (st != FEWHA_OK) {
         g_setup_err = err;
         return st;
     }
-    const fewha::Layout lo = fewha::compute_layout(cfg);
+    const fewha::Layout lo = fewha::compute_layout(cfgs, n);
     if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) {
         g_setup_err = "workspace must be a 256-byte aligned device pointer";
         return FEWHA_E_INVAL;
@@ -73,28 +78,13 @@ fewha_status fewha_setup(const fewha_config* cfg, void* d_workspace, size_t byte
     fewha_ctx* ctx = new (std::nothrow) fewha_ctx();
     if (!ctx) return FEWHA_E_NOMEM;
     fewha::Ctx& c = ctx->c;
-    c.L = cfg->n_layers;
-    c.G = cfg->n_wfs;
-    c.layers.assign(cfg->layers, cfg->layers + c.L);
-    c.wfs.assign(cfg->wfs, cfg->wfs + c.G);
-    for (auto& w : c.wfs) w.slope_weight = nullptr;   // host array only valid during setup
-    for (const auto& l : c.layers) {
-        c.N += int64_t(l.n) * l.n;
-        c.max_levels = std::max(c.max_levels, int(l.levels));
-        c.max_n = std::max(c.max_n, int(l.n));
-    }
-    for (const auto& w : c.wfs) {
-        c.S += 2 * int64_t(w.n_sub) * w.n_sub;
-        c.V += int64_t(w.n_sub + 1) * (w.n_sub + 1);
-    }
+    const fewha_config* cfg = &cfgs[0];
     c.prec = cfg->precision;
     c.esz = cfg->precision == FEWHA_FP64 ? 8 : 4;
-    c.alpha = cfg->alpha;
     c.max_iter = cfg->max_iter;
     c.k = cfg->recycle_k;
     c.mode = cfg->recycle_mode;
     c.project_all = cfg->project_all;
-    c.slots = cfg->recycle_k + cfg->max_iter;
     c.ws = static_cast<char*>(d_workspace);
     c.ws_bytes = bytes;
     c.lay = lo;
@@ -105,13 +95,29 @@ fewha_status fewha_setup(const fewha_config* cfg, void* d_workspace, size_t byte
         delete ctx;
         return FEWHA_E_HIP;
     }
-    st = fewha::build_tables(c, cfg, s);
+    st = fewha::build_tables(c, cfgs, n, s);
     if (st != FEWHA_OK) {
         g_setup_err = c.err;
         delete ctx;
         return st;
     }
     *out = ctx;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_setup(const fewha_config* cfg, void* d_workspace, size_t bytes, void* stream, fewha_ctx** out) {
+    return fewha_setup_batch(cfg, 1, d_workspace, bytes, stream, out);
+}
+
+fewha_status fewha_instances(const fewha_ctx* ctx, int64_t* coeff_offsets, int64_t* slope_offsets, int32_t n,
+                             int32_t* n_out) {
+    if (!ctx) return FEWHA_E_INVAL;
+    const fewha::Ctx& c = ctx->c;
+    for (int i = 0; i <= c.B && i < n; ++i) {
+        if (coeff_offsets) coeff_offsets[i] = i < c.B ? c.insts[i].off : c.N;
+        if (slope_offsets) slope_offsets[i] = c.s_offs[i];
+    }
+    if (n_out) *n_out = c.B;
     return FEWHA_OK;
 }
 
@@ -219,7 +225,7 @@ fewha_status fewha_state_size(const fewha_ctx* ctx, size_t* bytes) {
     return FEWHA_OK;
 }
 
-// State buffer: [256-byte header][slots x double (p_j, q_j)][c][r][b_prev][U slots][Q slots]
+// State buffer: [256-byte header][instances x slots x double (p_j, q_j)][c][r][b_prev][U slots][Q slots]
 fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream) {
     if (!ctx || !d_dst) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
     const fewha::Ctx& c = ctx->c;
@@ -234,12 +240,15 @@ fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream) {
     h[5] = uint64_t(c.count);
     h[6] = uint64_t(c.last_iters);
     h[7] = uint64_t(c.first ? 1 : 0);
+    h[8] = uint64_t(c.B);
     char* dst = static_cast<char*>(d_dst);
     const size_t vb = c.esz * c.N;
     bool ok = hipMemcpyAsync(dst, h, 256, hipMemcpyHostToDevice, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(dst + 256, c.ws + c.lay.scalars + offsetof(fewha::Scalars, gam), sizeof(double) * c.slots,
-                              hipMemcpyDeviceToDevice, s) == hipSuccess;
-    size_t o = 256 + sizeof(double) * c.slots;
+    for (int i = 0; i < c.B; ++i)
+        ok = ok && hipMemcpyAsync(dst + 256 + sizeof(double) * c.slots * i,
+                                  c.ws + c.lay.scalars + sizeof(fewha::Scalars) * i + offsetof(fewha::Scalars, gam),
+                                  sizeof(double) * c.slots, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    size_t o = 256 + sizeof(double) * c.slots * c.B;
     for (size_t src : {c.lay.c, c.lay.r, c.lay.b_prev}) {
         ok = ok && hipMemcpyAsync(dst + o, c.ws + src, vb, hipMemcpyDeviceToDevice, s) == hipSuccess;
         o += vb;
@@ -259,13 +268,16 @@ fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream) {
     if (hipMemcpyAsync(h, d_src, 256, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return fail(ctx, FEWHA_E_HIP, "state header copy failed");
     if (h[0] != kStateMagic || h[1] != uint64_t(c.N) || h[2] != uint64_t(c.slots) || h[3] != uint64_t(c.esz) ||
-        h[4] >= uint64_t(c.slots) || h[5] > uint64_t(c.slots))
+        h[4] >= uint64_t(c.slots) || h[5] > uint64_t(c.slots) || h[8] != uint64_t(c.B))
         return fail(ctx, FEWHA_E_STATE, "state buffer does not match this configuration");
     const char* src = static_cast<const char*>(d_src);
     const size_t vb = c.esz * c.N;
-    bool ok = hipMemcpyAsync(c.ws + c.lay.scalars + offsetof(fewha::Scalars, gam), src + 256, sizeof(double) * c.slots,
-                             hipMemcpyDeviceToDevice, s) == hipSuccess;
-    size_t o = 256 + sizeof(double) * c.slots;
+    bool ok = true;
+    for (int i = 0; i < c.B; ++i)
+        ok = ok && hipMemcpyAsync(c.ws + c.lay.scalars + sizeof(fewha::Scalars) * i + offsetof(fewha::Scalars, gam),
+                                  src + 256 + sizeof(double) * c.slots * i, sizeof(double) * c.slots,
+                                  hipMemcpyDeviceToDevice, s) == hipSuccess;
+    size_t o = 256 + sizeof(double) * c.slots * c.B;
     for (size_t dst : {c.lay.c, c.lay.r, c.lay.b_prev}) {
         ok = ok && hipMemcpyAsync(c.ws + dst, src + o, vb, hipMemcpyDeviceToDevice, s) == hipSuccess;
         o += vb;
@@ -322,7 +334,7 @@ fewha_status fewha_wavelet_steps(const fewha_ctx* ctx, int32_t* block_sizes, int
     const auto& st = ctx->c.steps;
     for (int i = 0; i < n && i < int(st.size()); ++i) {
         if (block_sizes) block_sizes[i] = st[i].nb;
-        if (layer_counts) layer_counts[i] = int32_t(st[i].layers.size());
+        if (layer_counts) layer_counts[i] = int32_t(st[i].nl);
     }
     if (n_out) *n_out = int32_t(st.size());
     return FEWHA_OK;

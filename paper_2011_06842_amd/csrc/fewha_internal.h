@@ -14,7 +14,9 @@
 namespace fewha {
 
 constexpr int kThreads = 256;       // threads of every 1-D kernel (4 wavefronts of 64)
-constexpr int kVecBlocks = 512;     // fixed grid of the vector/reduction kernels (determinism)
+constexpr int kVecBlocksMax = 1024; // vector-kernel workgroups of one instance (grid-stride beyond)
+constexpr int kDefaultBlockElems = 384;  // default elements per vector workgroup
+constexpr int kGramElems = 768;     // elements per Gram workgroup (one instance: <= kGramBlocks)
 constexpr int kKMax = FEWHA_MAX_RECYCLE;
 constexpr int kSlotsMax = kKMax + 256;
 constexpr int kTile = 16;           // wavefront-node tile side of the fused data-term kernel
@@ -27,20 +29,27 @@ constexpr int kST = 32;             // output tile side of a tiled synthesis ste
 constexpr int kAT = 16;             // coefficient tile side (per band) of a tiled analysis step
 constexpr int kGT = 16;             // layer-node tile side of the adjoint gather
 constexpr int kRMax = 6;            // contributions per layer row/column kept in LDS by the gather
-constexpr int kGramBlocks = 256;    // grid of the Gram pass
+constexpr int kGramBlocks = 256;    // Gram workgroups of one instance at most
 constexpr int kDataThreads = 1024;  // threads of the fused data-term kernel
 constexpr int kSolveThreads = 1024; // threads of the single-block Gram reduction and solve
 constexpr int kLayerGroups = 3;     // threads sharing one wavefront node's layer sum
 constexpr int kGatherGroup = 8;     // sensors whose gather lists are built together
 constexpr int kGatherRegion = 16384; // LDS bytes for the gather's sensor-node rectangles
 
-// Device descriptors (plain data, copied into the workspace at setup).
+// Device descriptors (plain data, copied into the workspace at setup).  The layers and
+// sensors of all instances of a batch are listed one after the other; a sensor only sees the
+// layers of its own instance.
 struct LayerDev {
     int32_t n, levels;
     int32_t coarse_lev;   // finest level whose block fits the coarse block (levels >= coarse_lev run in LDS)
-    int32_t pad_;
+    int32_t inst;         // instance of the layer
     int64_t off;          // offset of the layer in coefficient / nodal vectors
     double inv_delta;     // 1 / delta_l
+    int32_t l0;           // first layer of the instance
+    int32_t g0, ng;       // sensors of the instance
+    int32_t pq0;          // first (p, q) partial of the layer: tiled analysis tiles by level, then coarse
+    int32_t pq_coarse;    // index of the coarse analysis partial (relative to pq0)
+    int32_t gt0;          // first tile of the layer in the gather grid
 };
 
 inline int coarse_first_level(int n, int cb) {
@@ -49,31 +58,47 @@ inline int coarse_first_level(int n, int cb) {
     return l;
 }
 
-// One tiled wavelet level of block size nb and the layers that have it.
-struct WaveStep {
-    int nb = 0;
-    std::vector<int> layers;
-};
-struct StepLayers { int32_t count; int32_t l[FEWHA_MAX_LAYERS]; };
-
 struct WfsDev {
     int32_t ns;           // subapertures per side
     int32_t tiles_x;      // node tiles per side (ceil((ns+1)/kTile))
     int32_t tile_off;     // first tile of this sensor in the fused kernel's grid
-    int32_t pad_;
+    int32_t inst;         // instance of the sensor
     int64_t soff;         // slope offset
     int64_t noff;         // wavefront-node offset
+    int32_t l0, nl;       // layers of the instance
+    int32_t pair0;        // pair (this sensor, layer l0 + j) is pair0 + j
+    int32_t pad_;
 };
 
-struct PairDev {          // one (sensor g, layer l) pair, index g * L + l
+struct PairDev {          // one (sensor, layer) pair of the same instance
     int64_t fwd_off;      // rows then columns: 2 (ns+1) entries of cell index / fraction
     int64_t rng_off;      // rows then columns: 2 n entries of (first node, count)
+};
+
+// One independent instance of a batch (a single system is a batch of one).
+struct InstDev {
+    int64_t off, n;       // coefficient range
+    int32_t vb0, nvb;     // vector workgroups [vb0, vb0 + nvb): partial columns of the instance
+    int32_t gb0, ngb;     // Gram workgroups
+    int32_t pq0, npq;     // (p, q) partials of its analysis tiles
+};
+
+// What a vector-kernel workgroup works on: elements local * kThreads + t, stepping by
+// nb * kThreads, of its instance's range; partial column `col` (the instance's columns are
+// col - local .. col - local + nb - 1); the instance's (p, q) partials [pq0, pq0 + npq).
+struct VecBlk {
+    int64_t off;
+    int32_t n, local, nb, inst, col, pq0, npq, pad_;
+};
+struct GramBlk {
+    int64_t off;
+    int32_t n, local, nb, inst, gbase, pad_;   // partial of entry e: gbase + e * nb + local
 };
 
 template <typename T>
 struct Filt { T h[6], g[6]; };
 
-// Scalars of a solve, in device memory (never copied to the host inside a frame).
+// Scalars of one instance's solve, in device memory (never copied to the host inside a frame).
 struct Scalars {
     double rzb[2];        // (r, z) of the current iteration, double-buffered by iteration parity
     double rz, rz_new, pq, alpha, beta, mu, rr, bb, zq_last, ru_last;
@@ -88,6 +113,7 @@ struct Scalars {
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
     size_t layers, wfs, pairs, cellidx, frac, ranges, weight, prior_a, jinv;
+    size_t insts, vecblk, gramblk, step_layers, data_tiles, gather_tiles;
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
     size_t c, r, z, b, b_prev, s_in;
     size_t ring_u, ring_q;
@@ -112,10 +138,22 @@ struct Profiler {
     int64_t launches[KID_COUNT] = {};
 };
 
+// One tiled wavelet level of block size nb: its layers (global ids) at step_off of the
+// device list of step layers.
+struct StepInfo {
+    int nb = 0, nl = 0, loff = 0;
+};
+
 struct Ctx {
     // configuration
-    int L = 0, G = 0;
+    int B = 1;                 // instances
+    int L = 0, G = 0;          // layers and sensors of all instances
     int64_t N = 0, S = 0, V = 0;
+    int VB = 0, GB = 0;        // vector and Gram workgroups of all instances
+    int block_elems = kDefaultBlockElems;
+    int gather_tiles = 0;      // total layer tiles of the gather
+    std::vector<InstDev> insts;
+    std::vector<int64_t> s_offs;   // slope offsets of the instances (B + 1)
     int prec = 0;              // fewha_precision
     size_t esz = 8;            // element size
     double alpha = 0;
@@ -124,7 +162,7 @@ struct Ctx {
     int slots = 0;             // ring capacity k + max_iter
     int fwd_tiles = 0;         // total tiles of the fused data-term kernel
     int max_rng = 0;           // largest gather contribution count of a layer row/column
-    std::vector<WaveStep> steps;  // tiled wavelet levels (ascending block size)
+    std::vector<StepInfo> steps;  // tiled wavelet levels (ascending block size)
     int npq = 0;               // (p, q) partial entries written by one analysis
     int64_t n_cells = 0, n_ranges = 0;
     std::vector<fewha_layer> layers;
@@ -154,12 +192,10 @@ struct ProfScope {
 };
 hipError_t profiler_collect(const Ctx& c, hipStream_t s);
 
-// Host setup (fewha_setup.cpp)
-fewha_status validate_config(const fewha_config* cfg, std::string& err);
-Layout compute_layout(const fewha_config* cfg);
-std::vector<WaveStep> wavelet_steps(const fewha_config* cfg);
-int pq_partials(const fewha_config* cfg);
-fewha_status build_tables(Ctx& ctx, const fewha_config* cfg, hipStream_t stream);
+// Host setup (fewha_setup.cpp): a batch is an array of n configurations
+fewha_status validate_batch(const fewha_config* cfgs, int n, std::string& err);
+Layout compute_layout(const fewha_config* cfgs, int n);
+fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int n, hipStream_t stream);
 
 // Launchers (fewha_kernels.hip)
 template <typename T> void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s);

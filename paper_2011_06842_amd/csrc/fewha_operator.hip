@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* 
 // output tile per workgroup.  The LL band comes from the previous step (or from the
 // coefficients when this is the layer's coarsest level); the final level writes phi / delta.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restrict__ lays, StepLayers sl, int nbs,
+__global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restrict__ lays,
+                                                         const int32_t* __restrict__ sl, int nbs,
                                                          Filt<T> f, const T* __restrict__ coef,
                                                          const T* __restrict__ ll_in, T* __restrict__ ll_out,
                                                          T* __restrict__ phi) {
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
     __shared__ T I[kST][2 * H + 1];
     const int tx = nbs / kST, tiles = tx * tx;
     const int li = blockIdx.x / tiles, tile = blockIdx.x - li * tiles;
-    const LayerDev d = lays[sl.l[li]];
+    const LayerDev d = lays[sl[li]];
     const int n = d.n;
     const int lev = ilog2i(n / nbs) + 1;
     const int M = nbs >> 1;
@@ -171,10 +172,12 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
 // One analysis level of block size nbs on the listed layers: 16x16 coefficients of every band
 // per tile, rows then columns from a 36x36 halo, a_k = sum_t h_t x_{(2k+t) mod nbs}.  Final
 // coefficients are scaled by 1/delta and get + (alpha D)_i xprior_i; the partial of
-// (out, xdot) over them goes to dotpart[block].  The prior and x operands are requested
-// before the halo so that their latency overlaps it.
+// (out, xdot) over them goes to the tile's slot among the layer's partials (tiles of finer
+// levels first).  The prior and x operands are requested before the halo so that their
+// latency overlaps it.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restrict__ lays, StepLayers sl, int nbs,
+__global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restrict__ lays,
+                                                        const int32_t* __restrict__ sl, int nbs,
                                                         Filt<T> f, const T* __restrict__ img,
                                                         const T* __restrict__ ll_in, T* __restrict__ ll_out,
                                                         T* __restrict__ out, const T* __restrict__ prior_a,
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
     __shared__ T I[W][2 * kAT + 1];
     const int M = nbs >> 1, tx = M / kAT, tiles = tx * tx;
     const int li = blockIdx.x / tiles, tile = blockIdx.x - li * tiles;
-    const LayerDev d = lays[sl.l[li]];
+    const LayerDev d = lays[sl[li]];
     const int n = d.n;
     const int lev = ilog2i(n / nbs) + 1;
     const int ky0 = (tile / tx) * kAT, kx0 = (tile % tx) * kAT;
@@ -240,8 +243,13 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
     }
     if (!fin_ll) ll_out[o[3]] = ll;
     if (dotpart) {
+        int slot = d.pq0 + tile;
+        for (int j = 1; j < lev; ++j) {
+            const int mt = (n >> j) / kAT;
+            slot += mt * mt;
+        }
         const double vv[1] = {dot};
-        block_partials<1>(vv, dotpart, 0, 0, blockIdx.x);
+        block_partials<1>(vv, dotpart, 0, 0, slot);
     }
 }
 
@@ -335,17 +343,23 @@ __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* _
         if (threadIdx.x == 0) {
             double t = 0;
             for (int k = 0; k < kCoarseThreads / 64; ++k) t += sh[k];
-            dotpart[blockIdx.x] = t;
+            dotpart[d.pq0 + d.pq_coarse] = t;
         }
     }
 }
 
 // ------------------------------------------------------------------ tomography (Sec. 2)
 
-__device__ __forceinline__ int find_sensor(const WfsDev* __restrict__ wfs, int G, int tile) {
-    int g = 0;
-    while (g + 1 < G && wfs[g + 1].tile_off <= tile) ++g;
-    return g;
+// Sensor owning element e of a concatenation with per-sensor offsets (binary search).
+template <typename Off>
+__device__ __forceinline__ int find_sensor(const WfsDev* __restrict__ wfs, int G, int64_t e, Off off) {
+    int lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off(wfs[mid]) <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // Fused Gamma^T C^-1 Gamma P per sensor tile: wavefront on the tile plus a one-node halo,
@@ -354,8 +368,9 @@ __device__ __forceinline__ int find_sensor(const WfsDev* __restrict__ wfs, int G
 // each node's layer sum is split over kLayerGroups threads (layers l = lg mod kLayerGroups),
 // combined in a fixed order.
 template <typename T>
-__global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __restrict__ wfs, int G,
-                                                             const LayerDev* __restrict__ lays, int L,
+__global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __restrict__ wfs,
+                                                             const int32_t* __restrict__ tile_sensor,
+                                                             const LayerDev* __restrict__ lays,
                                                              const PairDev* __restrict__ pairs,
                                                              const int32_t* __restrict__ cidx,
                                                              const T* __restrict__ frac, const T* __restrict__ phi,
@@ -365,23 +380,24 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
     __shared__ T stx[S1 * S1], sty[S1 * S1];
     __shared__ int32_t srow[FEWHA_MAX_LAYERS][E], scol[FEWHA_MAX_LAYERS][E];
     __shared__ T sfy[FEWHA_MAX_LAYERS][E], sfx[FEWHA_MAX_LAYERS][E];
-    const int g = find_sensor(wfs, G, blockIdx.x);
-    const WfsDev W = wfs[g];
+    const WfsDev W = wfs[tile_sensor[blockIdx.x]];
     const int ns = W.ns, np = ns + 1;
+    const int L = W.nl;
+    const LayerDev* __restrict__ ly = lays + W.l0;               // the layers of the sensor's instance
     const int tl = blockIdx.x - W.tile_off;
     const int i0 = (tl / W.tiles_x) * kTile, j0 = (tl % W.tiles_x) * kTile;
     for (int e = threadIdx.x; e < L * 2 * E; e += kDataThreads) {
         const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, k = q - col * E;
         const int node = (col ? j0 : i0) - 1 + k;
         const int nn = node < 0 ? 0 : (node > ns ? ns : node);     // clamped: halo nodes outside are unused
-        const size_t o = size_t(pairs[g * L + l].fwd_off) + col * np + nn;
+        const size_t o = size_t(pairs[W.pair0 + l].fwd_off) + col * np + nn;
         const int32_t ci = cidx[o];
         const T fr = frac[o];
         if (col) {
             scol[l][k] = ci;
             sfx[l][k] = fr;
         } else {
-            srow[l][k] = ci * lays[l].n;                            // row offset in the layer
+            srow[l][k] = ci * ly[l].n;                              // row offset in the layer
             sfy[l][k] = fr;
         }
     }
@@ -394,9 +410,9 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
         if (i >= 0 && i <= ns && j >= 0 && j <= ns) {
 #pragma unroll 4
             for (int l = lg; l < L; l += kLayerGroups) {
-                const int n = lays[l].n;
+                const int n = ly[l].n;
                 const T fy = sfy[l][li], fx = sfx[l][lj];
-                const T* ph = phi + lays[l].off + srow[l][li] + scol[l][lj];
+                const T* ph = phi + ly[l].off + srow[l][li] + scol[l][lj];
                 const T p00 = ph[0], p01 = ph[1], p10 = ph[n], p11 = ph[n + 1];
                 v += (T(1) - fy) * ((T(1) - fx) * p00 + fx * p01) + fy * ((T(1) - fx) * p10 + fx * p11);
             }
@@ -444,9 +460,7 @@ __global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restric
                                                           T* __restrict__ psi, int weighted) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= V) return;
-    int g = 0;
-    while (g + 1 < G && wfs[g + 1].noff <= e) ++g;
-    const WfsDev W = wfs[g];
+    const WfsDev W = wfs[find_sensor(wfs, G, e, [](const WfsDev& w) { return w.noff; })];
     const int ns = W.ns, np = ns + 1;
     const int loc = int(e - W.noff);
     const int i = loc / np, j = loc % np;
@@ -462,16 +476,18 @@ __global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restric
 
 // Gamma P phi per subaperture (operator piece A), zero on inactive subapertures.
 template <typename T>
-__device__ __forceinline__ T wavefront_node(int g, int i, int j, int np, int L, const LayerDev* __restrict__ lays,
+__device__ __forceinline__ T wavefront_node(const WfsDev& W, int i, int j, const LayerDev* __restrict__ lays,
                                             const PairDev* __restrict__ pairs, const int32_t* __restrict__ cidx,
                                             const T* __restrict__ frac, const T* __restrict__ phi) {
+    const int np = W.ns + 1;
     T v = 0;
-    for (int l = 0; l < L; ++l) {
-        const PairDev P = pairs[g * L + l];
-        const int n = lays[l].n;
+    for (int l = 0; l < W.nl; ++l) {
+        const PairDev P = pairs[W.pair0 + l];
+        const LayerDev d = lays[W.l0 + l];
+        const int n = d.n;
         const int a0 = cidx[P.fwd_off + i], b0 = cidx[P.fwd_off + np + j];
         const T fy = frac[P.fwd_off + i], fx = frac[P.fwd_off + np + j];
-        const T* ph = phi + lays[l].off + size_t(a0) * n + b0;
+        const T* ph = phi + d.off + size_t(a0) * n + b0;
         v += (T(1) - fy) * ((T(1) - fx) * ph[0] + fx * ph[1]) + fy * ((T(1) - fx) * ph[n] + fx * ph[n + 1]);
     }
     return v;
@@ -479,23 +495,21 @@ __device__ __forceinline__ T wavefront_node(int g, int i, int j, int np, int L, 
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_fwd_slopes(const WfsDev* __restrict__ wfs, int G, int64_t S,
-                                                          const LayerDev* __restrict__ lays, int L,
+                                                          const LayerDev* __restrict__ lays,
                                                           const PairDev* __restrict__ pairs,
                                                           const int32_t* __restrict__ cidx, const T* __restrict__ frac,
                                                           const T* __restrict__ phi, const T* __restrict__ w,
                                                           T* __restrict__ out) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= S) return;
-    int g = 0;
-    while (g + 1 < G && wfs[g + 1].soff <= e) ++g;
-    const WfsDev W = wfs[g];
-    const int ns = W.ns, np = ns + 1;
+    const WfsDev W = wfs[find_sensor(wfs, G, e, [](const WfsDev& w) { return w.soff; })];
+    const int ns = W.ns;
     const int loc = int(e - W.soff);
     const int comp = loc / (ns * ns), q = loc % (ns * ns), i = q / ns, j = q % ns;
-    const T p00 = wavefront_node(g, i, j, np, L, lays, pairs, cidx, frac, phi);
-    const T p01 = wavefront_node(g, i, j + 1, np, L, lays, pairs, cidx, frac, phi);
-    const T p10 = wavefront_node(g, i + 1, j, np, L, lays, pairs, cidx, frac, phi);
-    const T p11 = wavefront_node(g, i + 1, j + 1, np, L, lays, pairs, cidx, frac, phi);
+    const T p00 = wavefront_node(W, i, j, lays, pairs, cidx, frac, phi);
+    const T p01 = wavefront_node(W, i, j + 1, lays, pairs, cidx, frac, phi);
+    const T p10 = wavefront_node(W, i + 1, j, lays, pairs, cidx, frac, phi);
+    const T p11 = wavefront_node(W, i + 1, j + 1, lays, pairs, cidx, frac, phi);
     const T v = comp == 0 ? T(0.5) * ((p01 - p00) + (p11 - p10)) : T(0.5) * ((p10 - p00) + (p11 - p01));
     out[e] = w[e] != T(0) ? v : T(0);
 }
@@ -506,8 +520,9 @@ __global__ void __launch_bounds__(kThreads) k_fwd_slopes(const WfsDev* __restric
 //  2. the rectangle of sensor nodes those lists span is copied to LDS (when it fits);
 //  3. every layer node sums its row-weight x column-weight products over the sensors in order.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restrict__ wfs, int G,
-                                                          const LayerDev* __restrict__ lays, int L,
+__global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restrict__ wfs,
+                                                          const LayerDev* __restrict__ lays,
+                                                          const int32_t* __restrict__ tile_layer,
                                                           const PairDev* __restrict__ pairs,
                                                           const int32_t* __restrict__ cidx, const T* __restrict__ frac,
                                                           const int2* __restrict__ rng, const T* __restrict__ psi,
@@ -518,13 +533,15 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
     __shared__ int32_t scnt[kGatherGroup][2][kGT];
     __shared__ int32_t sbox[kGatherGroup][6];                      // i_lo, i_hi, j_lo, j_hi, lds offset (-1: global), width
     __shared__ T sreg[RG];
-    const int l = blockIdx.y;
+    const int l = tile_layer[blockIdx.x];
     const LayerDev d = lays[l];
     const int n = d.n, tx = (n + kGT - 1) / kGT;
-    if (int(blockIdx.x) >= tx * tx) return;
-    const int a0 = (blockIdx.x / tx) * kGT, b0 = (blockIdx.x % tx) * kGT;
+    const int tile = blockIdx.x - d.gt0;
+    const int a0 = (tile / tx) * kGT, b0 = (tile % tx) * kGT;
     const int la = threadIdx.x / kGT, lb = threadIdx.x % kGT;
     const int a = a0 + la, b = b0 + lb;
+    const int G = d.ng, lloc = l - d.l0;                 // sensors of the layer's instance
+    const WfsDev* __restrict__ wf = wfs + d.g0;
     T acc = 0;
     for (int g0 = 0; g0 < G; g0 += kGatherGroup) {
         const int ng = G - g0 < kGatherGroup ? G - g0 : kGatherGroup;
@@ -535,8 +552,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
             if (gl < ng) {
                 const int g = g0 + gl;
                 const int node = (col ? b0 : a0) + k;
-                const int np = wfs[g].ns + 1;
-                const PairDev P = pairs[g * L + l];
+                const int np = wf[g].ns + 1;
+                const PairDev P = pairs[wf[g].pair0 + lloc];
                 int cnt = 0;
                 if (node < n) {
                     const int2 r = rng[P.rng_off + col * n + node];
@@ -591,7 +608,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
                     const int w = sbox[gl][5], h = sbox[gl][1] - sbox[gl][0] + 1;
                     if (sbox[gl][4] < 0 || e >= h * w) return T(0);
                     const int ii = e / w, jj = e - ii * w;
-                    return psi[wfs[g0 + gl].noff + (sbox[gl][0] + ii) * (wfs[g0 + gl].ns + 1) + sbox[gl][2] + jj];
+                    return psi[wf[g0 + gl].noff + (sbox[gl][0] + ii) * (wf[g0 + gl].ns + 1) + sbox[gl][2] + jj];
                 },
                 [&](int f, T v) { sreg[f] = v; });
         }
@@ -609,8 +626,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
                         acc += sw[gl][0][la][r] * sum;
                     }
                 } else {
-                    const int np = wfs[g0 + gl].ns + 1;
-                    const T* ps = psi + wfs[g0 + gl].noff;
+                    const int np = wf[g0 + gl].ns + 1;
+                    const T* ps = psi + wf[g0 + gl].noff;
                     for (int r = 0; r < ca; ++r) {
                         const T* row = ps + sidx[gl][0][la][r] * np;
                         T sum = 0;
@@ -628,8 +645,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
 // The same sum for configurations whose contribution lists exceed kRMax (layer grids much
 // coarser than the sensor grids): every node walks its ranges directly.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_adj_gather_wide(const WfsDev* __restrict__ wfs, int G,
-                                                               const LayerDev* __restrict__ lays, int L,
+__global__ void __launch_bounds__(kThreads) k_adj_gather_wide(const WfsDev* __restrict__ wfs,
+                                                               const LayerDev* __restrict__ lays,
                                                                const PairDev* __restrict__ pairs,
                                                                const int32_t* __restrict__ cidx,
                                                                const T* __restrict__ frac,
@@ -642,10 +659,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_wide(const WfsDev* __re
     if (idx >= n * n) return;
     const int a = idx / n, b = idx - a * n;
     T acc = 0;
-    for (int g = 0; g < G; ++g) {
+    for (int g = d.g0; g < d.g0 + d.ng; ++g) {
         const WfsDev W = wfs[g];
         const int np = W.ns + 1;
-        const PairDev P = pairs[g * L + l];
+        const PairDev P = pairs[W.pair0 + (l - d.l0)];
         const int2 ra = rng[P.rng_off + a], rb = rng[P.rng_off + n + b];
         for (int ii = 0; ii < ra.y; ++ii) {
             const int i = ra.x + ii;
@@ -721,28 +738,22 @@ hipError_t profiler_collect(const Ctx& c, hipStream_t s) {
 
 // ------------------------------------------------------------------ operator launchers
 
-inline StepLayers step_layers(const WaveStep& w) {
-    StepLayers sl{};
-    sl.count = int32_t(w.layers.size());
-    for (size_t i = 0; i < w.layers.size(); ++i) sl.l[i] = w.layers[i];
-    return sl;
-}
-
 template <typename T>
 void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
     const Filt<T> f = make_filt<T>();
     T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
+    const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
     {
         ProfScope ps_(c, KID_IDWT_COARSE, s);
         k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], phi);
     }
     for (size_t j = 0; j < c.steps.size(); ++j) {
-        const WaveStep& w = c.steps[j];
+        const StepInfo& w = c.steps[j];
         const int tiles = (w.nb / kST) * (w.nb / kST);
         ProfScope ps_(c, KID_IDWT_STEP, s);
-        k_idwt_step<T><<<tiles * int(w.layers.size()), kThreads, 0, s>>>(lays, step_layers(w), w.nb, f, x, buf[j & 1],
-                                                                       buf[(j + 1) & 1], phi);
+        k_idwt_step<T><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, buf[j & 1], buf[(j + 1) & 1],
+                                                         phi);
     }
 }
 
@@ -752,29 +763,27 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, const T* xd
     const Filt<T> f = make_filt<T>();
     T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
+    const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
     const T* pa = c.at<T>(c.lay.prior_a);
-    int used = 0;
     const int J = int(c.steps.size());
     for (int j = 0; j < J; ++j) {                 // largest block first
-        const WaveStep& w = c.steps[J - 1 - j];
+        const StepInfo& w = c.steps[J - 1 - j];
         const int tiles = (w.nb / 2 / kAT) * (w.nb / 2 / kAT);
-        const int blocks = tiles * int(w.layers.size());
         ProfScope ps_(c, KID_DWT_STEP, s);
-        k_dwt_step<T><<<blocks, kThreads, 0, s>>>(lays, step_layers(w), w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y,
-                                                  pa, xprior, xdot, pq_part ? pq_part + used : nullptr);
-        used += blocks;
+        k_dwt_step<T><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y,
+                                                        pa, xprior, xdot, pq_part);
     }
     ProfScope ps_(c, KID_DWT_COARSE, s);
-    k_dwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, xdot,
-                                                   pq_part ? pq_part + used : nullptr);
+    k_dwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, xdot, pq_part);
 }
 
 template <typename T>
 void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s) {
     ProfScope ps_(c, KID_DATA_TERM, s);
-    k_data_term<T><<<c.fwd_tiles, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.at<LayerDev>(c.lay.layers), c.L,
-                                                    c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
-                                                    c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), psi_nodes);
+    k_data_term<T><<<c.fwd_tiles, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int32_t>(c.lay.data_tiles),
+                                                        c.at<LayerDev>(c.lay.layers), c.at<PairDev>(c.lay.pairs),
+                                                        c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), phi,
+                                                        c.at<T>(c.lay.weight), psi_nodes);
 }
 
 template <typename T>
@@ -788,15 +797,14 @@ template <typename T>
 void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s) {
     ProfScope ps_(c, KID_ADJ_GATHER, s);
     if (c.max_rng <= kRMax) {
-        const int tx = (c.max_n + kGT - 1) / kGT;
-        const dim3 grid(tx * tx, c.L);
-        k_adj_gather<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.at<LayerDev>(c.lay.layers), c.L,
-                                                  c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
-                                                  c.at<T>(c.lay.frac), c.at<int2>(c.lay.ranges), psi_nodes, psi_layers);
+        k_adj_gather<T><<<c.gather_tiles, kThreads, 0, s>>>(
+            c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers), c.at<int32_t>(c.lay.gather_tiles),
+            c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), c.at<int2>(c.lay.ranges),
+            psi_nodes, psi_layers);
     } else {
         const dim3 grid(cdiv(int64_t(c.max_n) * c.max_n, kThreads), c.L);
-        k_adj_gather_wide<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.at<LayerDev>(c.lay.layers),
-                                                       c.L, c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
+        k_adj_gather_wide<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
+                                                       c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
                                                        c.at<T>(c.lay.frac), c.at<int2>(c.lay.ranges), psi_nodes,
                                                        psi_layers);
     }
@@ -806,9 +814,9 @@ template <typename T>
 void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s) {
     ProfScope ps_(c, KID_FWD_SLOPES, s);
     k_fwd_slopes<T><<<cdiv(c.S, kThreads), kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.S,
-                                                             c.at<LayerDev>(c.lay.layers), c.L,
-                                                             c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
-                                                             c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), slopes);
+                                                             c.at<LayerDev>(c.lay.layers), c.at<PairDev>(c.lay.pairs),
+                                                             c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), phi,
+                                                             c.at<T>(c.lay.weight), slopes);
 }
 
 template <typename T>
@@ -837,6 +845,7 @@ template <typename T>
 static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
     const Filt<T> f = make_filt<T>();
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
+    const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
     T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
     const T* x = c.at<T>(c.lay.c);
     T* y = c.at<T>(c.lay.vy);
@@ -847,9 +856,9 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
             break;
         case KID_IDWT_STEP: {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
-            const WaveStep& w = c.steps[step];
-            k_idwt_step<T><<<(w.nb / kST) * (w.nb / kST) * int(w.layers.size()), kThreads, 0, s>>>(
-                lays, step_layers(w), w.nb, f, x, buf[step & 1], buf[(step + 1) & 1], c.at<T>(c.lay.nodal));
+            const StepInfo& w = c.steps[step];
+            k_idwt_step<T><<<(w.nb / kST) * (w.nb / kST) * w.nl, kThreads, 0, s>>>(
+                lays, sl + w.loff, w.nb, f, x, buf[step & 1], buf[(step + 1) & 1], c.at<T>(c.lay.nodal));
             break;
         }
         case KID_DATA_TERM:
@@ -860,10 +869,10 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
             break;
         case KID_DWT_STEP: {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
-            const WaveStep& w = c.steps[step];
+            const StepInfo& w = c.steps[step];
             const int j = J - 1 - step;
-            k_dwt_step<T><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * int(w.layers.size()), kThreads, 0, s>>>(
-                lays, step_layers(w), w.nb, f, c.at<T>(c.lay.psi_layers), buf[(j + 1) & 1], buf[j & 1], y,
+            k_dwt_step<T><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * w.nl, kThreads, 0, s>>>(
+                lays, sl + w.loff, w.nb, f, c.at<T>(c.lay.psi_layers), buf[(j + 1) & 1], buf[j & 1], y,
                 c.at<T>(c.lay.prior_a), x, x, c.at<double>(c.lay.pq_part));
             break;
         }

@@ -59,34 +59,9 @@ int coef_level(int row, int col, int n, int levels) {
     return levels;
 }
 
-struct Cells {
-    std::vector<int32_t> idx;   // rows then columns
-    std::vector<double> frac;
-};
-
 }  // namespace
 
-std::vector<WaveStep> wavelet_steps(const fewha_config* cfg) {
-    // block sizes (> the coarse block) of the tiled wavelet levels, ascending, with their layers
-    const int cb = coarse_block(cfg->precision);
-    std::vector<WaveStep> st;
-    for (int nb = 2 * cb; nb <= 1024; nb *= 2) {
-        WaveStep w;
-        w.nb = nb;
-        for (int l = 0; l < cfg->n_layers; ++l) {
-            const fewha_layer& L = cfg->layers[l];
-            if (L.n >= nb && ilog2(L.n / nb) + 1 <= L.levels) w.layers.push_back(l);
-        }
-        if (!w.layers.empty()) st.push_back(w);
-    }
-    return st;
-}
-
-int pq_partials(const fewha_config* cfg) {
-    int n = cfg->n_layers;   // coarse analysis: one workgroup per layer
-    for (const WaveStep& w : wavelet_steps(cfg)) n += (w.nb / 2 / kAT) * (w.nb / 2 / kAT) * int(w.layers.size());
-    return n;
-}
+namespace {
 
 fewha_status validate_config(const fewha_config* cfg, std::string& err) {
     if (!cfg) { err = "config is NULL"; return FEWHA_E_INVAL; }
@@ -120,6 +95,7 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
     if (cfg->rel_tol != 0.0) { err = "rel_tol is reserved and must be 0"; return FEWHA_E_INVAL; }
     if (cfg->precision != FEWHA_FP64 && cfg->precision != FEWHA_FP32_OP_FP64_RED) { err = "bad precision"; return FEWHA_E_INVAL; }
     if (cfg->project_all && cfg->recycle_mode != FEWHA_RECYCLE_GALERKIN) { err = "project_all needs GALERKIN mode"; return FEWHA_E_INVAL; }
+    if (cfg->block_elems != 0 && (cfg->block_elems < 64 || cfg->block_elems > (1 << 22))) { err = "block_elems must be 0 or in [64, 2^22]"; return FEWHA_E_INVAL; }
     // every projected sensor node must fall inside every layer grid (no padding, no wrap)
     for (int g = 0; g < cfg->n_wfs; ++g) {
         const fewha_wfs& W = cfg->wfs[g];
@@ -142,29 +118,127 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
     return FEWHA_OK;
 }
 
-Layout compute_layout(const fewha_config* cfg) {
-    Layout lo{};
-    const size_t e = cfg->precision == FEWHA_FP64 ? 8 : 4;
-    int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0;
-    for (int l = 0; l < cfg->n_layers; ++l) N += int64_t(cfg->layers[l].n) * cfg->layers[l].n;
-    for (int g = 0; g < cfg->n_wfs; ++g) {
-        const int ns = cfg->wfs[g].n_sub;
-        S += 2 * int64_t(ns) * ns;
-        V += int64_t(ns + 1) * (ns + 1);
-        for (int l = 0; l < cfg->n_layers; ++l) {
-            cells += 2 * (ns + 1);
-            ranges += 2 * cfg->layers[l].n;
+// Derived sizes of one instance and of the batch (identical for validation, layout and setup).
+struct Sizes {
+    int B = 0, L = 0, G = 0, slots = 0, esz = 8, KE = 1;
+    int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;
+    int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, step_list = 0;
+    std::vector<StepInfo> steps;
+};
+
+int block_elems(const fewha_config* c) { return c->block_elems ? c->block_elems : kDefaultBlockElems; }
+
+int vec_blocks(int64_t n, int be) { return int(std::min<int64_t>(kVecBlocksMax, std::max<int64_t>(1, (n + be - 1) / be))); }
+
+int gram_blocks(int64_t n) { return int(std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + kGramElems - 1) / kGramElems))); }
+
+// (p, q) partials of one layer: one per tile of every tiled analysis level, then the coarse one
+int layer_pq(int n, int levels, int cb) {
+    const int lc = coarse_first_level(n, cb);
+    int t = 0;
+    for (int lev = 1; lev <= levels && lev < lc; ++lev) {
+        const int m = (n >> (lev - 1)) / 2 / kAT;
+        t += m * m;
+    }
+    return t + 1;
+}
+
+Sizes batch_sizes(const fewha_config* cfgs, int nb) {
+    Sizes z;
+    z.B = nb;
+    z.esz = cfgs[0].precision == FEWHA_FP64 ? 8 : 4;
+    z.slots = cfgs[0].recycle_k + cfgs[0].max_iter;
+    z.KE = std::max(1, cfgs[0].recycle_k * (cfgs[0].recycle_k + 1));
+    const int cb = coarse_block(cfgs[0].precision);
+    for (int i = 0; i < nb; ++i) {
+        const fewha_config* c = &cfgs[i];
+        int64_t Ni = 0;
+        for (int l = 0; l < c->n_layers; ++l) {
+            const int n = c->layers[l].n;
+            Ni += int64_t(n) * n;
+            z.NPQ += layer_pq(n, c->layers[l].levels, cb);
+            const int tx = (n + kGT - 1) / kGT;
+            z.gather_tiles += tx * tx;
+        }
+        for (int g = 0; g < c->n_wfs; ++g) {
+            const int ns = c->wfs[g].n_sub;
+            z.S += 2 * int64_t(ns) * ns;
+            z.V += int64_t(ns + 1) * (ns + 1);
+            const int tx = (ns + 1 + kTile - 1) / kTile;
+            z.data_tiles += tx * tx;
+            for (int l = 0; l < c->n_layers; ++l) {
+                z.cells += 2 * (ns + 1);
+                z.ranges += 2 * c->layers[l].n;
+            }
+        }
+        z.pairs += int64_t(c->n_layers) * c->n_wfs;
+        z.L += c->n_layers;
+        z.G += c->n_wfs;
+        z.N += Ni;
+        z.VB += vec_blocks(Ni, block_elems(c));
+        z.GB += gram_blocks(Ni);
+    }
+    // tiled wavelet levels: block sizes above the coarse block, with every layer that has them
+    for (int nbs = 2 * cb; nbs <= 1024; nbs *= 2) {
+        StepInfo st;
+        st.nb = nbs;
+        st.loff = z.step_list;
+        for (int i = 0; i < nb; ++i)
+            for (int l = 0; l < cfgs[i].n_layers; ++l) {
+                const fewha_layer& Ly = cfgs[i].layers[l];
+                if (Ly.n >= nbs && ilog2(Ly.n / nbs) + 1 <= Ly.levels) ++st.nl;
+            }
+        if (st.nl) {
+            z.steps.push_back(st);
+            z.step_list += st.nl;
         }
     }
-    const int slots = cfg->recycle_k + cfg->max_iter;
+    return z;
+}
+
+}  // namespace
+
+fewha_status validate_batch(const fewha_config* cfgs, int n, std::string& err) {
+    if (!cfgs) { err = "config is NULL"; return FEWHA_E_INVAL; }
+    if (n < 1 || n > FEWHA_MAX_INSTANCES) { err = "instance count out of range"; return FEWHA_E_INVAL; }
+    for (int i = 0; i < n; ++i) {
+        const fewha_status st = validate_config(&cfgs[i], err);
+        if (st != FEWHA_OK) {
+            if (n > 1) err = "instance " + std::to_string(i) + ": " + err;
+            return st;
+        }
+        const fewha_config& a = cfgs[0];
+        const fewha_config& b = cfgs[i];
+        if (a.precision != b.precision || a.max_iter != b.max_iter || a.recycle_k != b.recycle_k ||
+            a.recycle_mode != b.recycle_mode || a.project_all != b.project_all || a.rel_tol != b.rel_tol ||
+            block_elems(&a) != block_elems(&b)) {
+            err = "instance " + std::to_string(i) +
+                  ": precision, iterations, recycling and block_elems must be the same for every instance";
+            return FEWHA_E_INVAL;
+        }
+    }
+    return FEWHA_OK;
+}
+
+Layout compute_layout(const fewha_config* cfgs, int nb) {
+    const Sizes z = batch_sizes(cfgs, nb);
+    Layout lo{};
+    const size_t e = size_t(z.esz);
+    const int64_t N = z.N, S = z.S, V = z.V;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + bytes); return r; };
-    lo.layers = take(sizeof(LayerDev) * cfg->n_layers);
-    lo.wfs = take(sizeof(WfsDev) * cfg->n_wfs);
-    lo.pairs = take(sizeof(PairDev) * cfg->n_layers * cfg->n_wfs);
-    lo.cellidx = take(sizeof(int32_t) * cells);
-    lo.frac = take(e * cells);
-    lo.ranges = take(2 * sizeof(int32_t) * ranges);
+    lo.layers = take(sizeof(LayerDev) * z.L);
+    lo.wfs = take(sizeof(WfsDev) * z.G);
+    lo.pairs = take(sizeof(PairDev) * z.pairs);
+    lo.cellidx = take(sizeof(int32_t) * z.cells);
+    lo.frac = take(e * z.cells);
+    lo.ranges = take(2 * sizeof(int32_t) * z.ranges);
+    lo.insts = take(sizeof(InstDev) * z.B);
+    lo.vecblk = take(sizeof(VecBlk) * z.VB);
+    lo.gramblk = take(sizeof(GramBlk) * z.GB);
+    lo.step_layers = take(sizeof(int32_t) * std::max(1, z.step_list));
+    lo.data_tiles = take(sizeof(int32_t) * z.data_tiles);
+    lo.gather_tiles = take(sizeof(int32_t) * z.gather_tiles);
     lo.weight = take(e * S);
     lo.prior_a = take(e * N);
     lo.jinv = take(e * N);
@@ -181,68 +255,178 @@ Layout compute_layout(const fewha_config* cfg) {
     lo.b = take(e * N);
     lo.b_prev = take(e * N);
     lo.s_in = take(e * S);
-    lo.ring_u = take(e * N * slots);
-    lo.ring_q = take(e * N * slots);
-    lo.partials = take(sizeof(double) * kVecBlocks * (2 * kKMax + 8));
-    lo.pq_part = take(sizeof(double) * size_t(pq_partials(cfg)));
-    lo.gram_part = take(sizeof(double) * kGramBlocks * (kKMax * kKMax + kKMax));
-    lo.scalars = take(sizeof(Scalars));
-    lo.info = take(sizeof(fewha_solve_info));
+    lo.ring_u = take(e * N * z.slots);
+    lo.ring_q = take(e * N * z.slots);
+    lo.partials = take(sizeof(double) * size_t(z.VB) * (2 * kKMax + 8));
+    lo.pq_part = take(sizeof(double) * size_t(z.NPQ));
+    lo.gram_part = take(sizeof(double) * size_t(z.GB) * z.KE);
+    lo.scalars = take(sizeof(Scalars) * z.B);
+    lo.info = take(sizeof(fewha_solve_info) * z.B);
     lo.total = o;
-    lo.state_bytes = 256 + sizeof(double) * slots + e * N * (3 + 2 * size_t(slots));
+    lo.state_bytes = 256 + sizeof(double) * size_t(z.B) * z.slots + e * N * (3 + 2 * size_t(z.slots));
     return lo;
 }
 
-fewha_status build_tables(Ctx& ctx, const fewha_config* cfg, hipStream_t stream) {
-    const int L = cfg->n_layers, G = cfg->n_wfs;
-    const bool f32 = cfg->precision == FEWHA_FP32_OP_FP64_RED;
+namespace {
+
+// Host tables of all instances, concatenated in instance order.
+struct Tables {
+    std::vector<LayerDev> ld;
+    std::vector<WfsDev> wd;
+    std::vector<PairDev> pd;
+    std::vector<int32_t> cidx, rng;
+    std::vector<double> cfrac, D, Jinv, wts;
+};
+
+// Prior D (Sec. 3): inverse von Karman spectrum at the band frequency of every coefficient.
+void prior_of(const fewha_config* cfg, const LayerDev* ld, double* D) {
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        const fewha_layer& Ly = cfg->layers[l];
+        const int n = Ly.n, J = ilog2(n);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) {
+                const int lev = coef_level(a, b, n, Ly.levels);
+                const double f = std::ldexp(1.0, J - lev) / (n * Ly.spacing);
+                D[(ld[l].off - ld[0].off) + int64_t(a) * n + b] =
+                    std::pow(f * f + 1.0 / (cfg->L0 * cfg->L0), 11.0 / 6.0) * std::pow(cfg->r0, 5.0 / 3.0) /
+                    (0.023 * Ly.weight);
+            }
+    }
+}
+
+// diag(M) - alpha D of one instance: the wavelet basis function of coefficient (a, b) at level
+// lev is the outer product of two 1-D level-lev functions; bilinear propagation and both slope
+// components keep that product form, so every diagonal block is a pair of small matrix
+// products.  `pair(g, l)` gives the instance-local pair's table entry.
+template <typename PairOf>
+void data_diag_of(const fewha_config* cfg, const LayerDev* ld, PairOf pair, const std::vector<int32_t>& cidx,
+                  const std::vector<double>& cfrac, double* diag) {
     double h[6], g6[6];
     db3(h, g6);
+    const int G = cfg->n_wfs;
+    for (int l = 0; l < cfg->n_layers; ++l) {
+        const fewha_layer& Ly = cfg->layers[l];
+        const int n = Ly.n;
+        for (int lev = 1; lev <= Ly.levels; ++lev) {
+            const int m2 = n >> (lev - 1);
+            std::vector<double> B(size_t(m2) * n);   // basis functions B[p][y], p < m2
+            std::vector<double> tmp(n);
+            for (int p = 0; p < m2; ++p) {
+                std::fill(tmp.begin(), tmp.end(), 0.0);
+                tmp[p] = 1.0;
+                synth1d(tmp, n, lev, h, g6);
+                std::copy(tmp.begin(), tmp.end(), B.begin() + size_t(p) * n);
+            }
+            std::vector<double> blk(size_t(m2) * m2, 0.0);
+            for (int g = 0; g < G; ++g) {
+                const fewha_wfs& W = cfg->wfs[g];
+                const int ns = W.n_sub;
+                const PairDev& p = pair(g, l);
+                // interpolated 1-D functions at the sensor nodes, rows (y) and columns (x)
+                std::vector<double> Yh(size_t(ns + 1) * m2), Xh(size_t(ns + 1) * m2);
+                for (int axis = 0; axis < 2; ++axis) {
+                    std::vector<double>& H = axis == 0 ? Yh : Xh;
+                    for (int i = 0; i <= ns; ++i) {
+                        const int c0 = cidx[p.fwd_off + axis * (ns + 1) + i];
+                        const double f = cfrac[p.fwd_off + axis * (ns + 1) + i];
+                        for (int q = 0; q < m2; ++q)
+                            H[size_t(i) * m2 + q] = (1 - f) * B[size_t(q) * n + c0] + f * B[size_t(q) * n + c0 + 1];
+                    }
+                }
+                // s^x_ij = avg_y(i) * diff_x(j), s^y_ij = diff_y(i) * avg_x(j)
+                std::vector<double> Sy2(size_t(ns) * m2), Dy2(size_t(ns) * m2), Sx2(size_t(ns) * m2), Dx2(size_t(ns) * m2);
+                for (int i = 0; i < ns; ++i)
+                    for (int q = 0; q < m2; ++q) {
+                        const double y0 = Yh[size_t(i) * m2 + q], y1 = Yh[size_t(i + 1) * m2 + q];
+                        const double x0 = Xh[size_t(i) * m2 + q], x1 = Xh[size_t(i + 1) * m2 + q];
+                        Sy2[size_t(i) * m2 + q] = 0.25 * (y0 + y1) * (y0 + y1);
+                        Dy2[size_t(i) * m2 + q] = (y1 - y0) * (y1 - y0);
+                        Sx2[size_t(i) * m2 + q] = 0.25 * (x0 + x1) * (x0 + x1);
+                        Dx2[size_t(i) * m2 + q] = (x1 - x0) * (x1 - x0);
+                    }
+                const double* wx = W.slope_weight;
+                const double* wy = W.slope_weight + size_t(ns) * ns;
+                std::vector<double> T1(size_t(ns) * m2), T2(size_t(ns) * m2);
+                for (int i = 0; i < ns; ++i)
+                    for (int q = 0; q < m2; ++q) {
+                        double s1 = 0, s2 = 0;
+                        for (int j = 0; j < ns; ++j) {
+                            s1 += wx[size_t(i) * ns + j] * Dx2[size_t(j) * m2 + q];
+                            s2 += wy[size_t(i) * ns + j] * Sx2[size_t(j) * m2 + q];
+                        }
+                        T1[size_t(i) * m2 + q] = s1;
+                        T2[size_t(i) * m2 + q] = s2;
+                    }
+                for (int a = 0; a < m2; ++a)
+                    for (int b = 0; b < m2; ++b) {
+                        if (coef_level(a, b, n, Ly.levels) != lev) continue;
+                        double s = 0;
+                        for (int i = 0; i < ns; ++i)
+                            s += Sy2[size_t(i) * m2 + a] * T1[size_t(i) * m2 + b] + Dy2[size_t(i) * m2 + a] * T2[size_t(i) * m2 + b];
+                        blk[size_t(a) * m2 + b] += s;
+                    }
+            }
+            const double id2 = 1.0 / (Ly.spacing * Ly.spacing);
+            for (int a = 0; a < m2; ++a)
+                for (int b = 0; b < m2; ++b)
+                    if (coef_level(a, b, n, Ly.levels) == lev)
+                        diag[(ld[l].off - ld[0].off) + int64_t(a) * n + b] = blk[size_t(a) * m2 + b] * id2;
+        }
+    }
+}
 
-    // ---- descriptors
-    std::vector<LayerDev> ld(L);
-    int64_t off = 0;
+// Appends instance `inst` (configuration cfg) to the concatenated tables.
+fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, int64_t& off, int64_t& soff,
+                          int64_t& noff, int& toff, int& gtoff, int& pqoff, std::string& err) {
+    const int L = cfg->n_layers, G = cfg->n_wfs;
+    const int l0 = int(t.ld.size()), g0 = int(t.wd.size());
+    const int64_t off0 = off;
     for (int l = 0; l < L; ++l) {
-        ld[l].n = cfg->layers[l].n;
-        ld[l].levels = cfg->layers[l].levels;
-        ld[l].coarse_lev = coarse_first_level(ld[l].n, coarse_block(cfg->precision));
-        ld[l].pad_ = 0;
-        ld[l].off = off;
-        ld[l].inv_delta = 1.0 / cfg->layers[l].spacing;
-        off += int64_t(ld[l].n) * ld[l].n;
+        LayerDev d{};
+        d.n = cfg->layers[l].n;
+        d.levels = cfg->layers[l].levels;
+        d.coarse_lev = coarse_first_level(d.n, cb);
+        d.inst = inst;
+        d.off = off;
+        d.inv_delta = 1.0 / cfg->layers[l].spacing;
+        d.l0 = l0;
+        d.g0 = g0;
+        d.ng = G;
+        d.pq0 = pqoff;
+        d.pq_coarse = layer_pq(d.n, d.levels, cb) - 1;
+        d.gt0 = gtoff;
+        const int tx = (d.n + kGT - 1) / kGT;
+        gtoff += tx * tx;
+        pqoff += d.pq_coarse + 1;
+        off += int64_t(d.n) * d.n;
+        t.ld.push_back(d);
     }
-    std::vector<WfsDev> wd(G);
-    int64_t soff = 0, noff = 0;
-    int toff = 0;
-    for (int g = 0; g < G; ++g) {
-        const int ns = cfg->wfs[g].n_sub;
-        wd[g].ns = ns;
-        wd[g].tiles_x = (ns + 1 + kTile - 1) / kTile;
-        wd[g].tile_off = toff;
-        wd[g].pad_ = 0;
-        wd[g].soff = soff;
-        wd[g].noff = noff;
-        toff += wd[g].tiles_x * wd[g].tiles_x;
-        soff += 2 * int64_t(ns) * ns;
-        noff += int64_t(ns + 1) * (ns + 1);
-    }
-    ctx.fwd_tiles = toff;
-
-    // ---- bilinear cells of every (sensor, layer) pair, Sec. 2: the layer point seen from
-    // node x is (1 - h/H) x + theta h (H = infinity for a natural guide star)
-    std::vector<PairDev> pd(size_t(G) * L);
-    std::vector<int32_t> cidx;
-    std::vector<double> cfrac;
-    std::vector<int32_t> rng;
+    // bilinear cells of every (sensor, layer) pair, Sec. 2: the layer point seen from node x
+    // is (1 - h/H) x + theta h (H = infinity for a natural guide star)
     for (int g = 0; g < G; ++g) {
         const fewha_wfs& W = cfg->wfs[g];
         const int ns = W.n_sub;
+        WfsDev w{};
+        w.ns = ns;
+        w.tiles_x = (ns + 1 + kTile - 1) / kTile;
+        w.tile_off = toff;
+        w.inst = inst;
+        w.soff = soff;
+        w.noff = noff;
+        w.l0 = l0;
+        w.nl = L;
+        w.pair0 = int(t.pd.size());
+        toff += w.tiles_x * w.tiles_x;
+        soff += 2 * int64_t(ns) * ns;
+        noff += int64_t(ns + 1) * (ns + 1);
+        t.wd.push_back(w);
+        t.wts.insert(t.wts.end(), W.slope_weight, W.slope_weight + 2 * ns * ns);
         for (int l = 0; l < L; ++l) {
             const fewha_layer& Ly = cfg->layers[l];
             const double scale = W.lgs_height > 0 ? 1.0 - Ly.height / W.lgs_height : 1.0;
-            PairDev& p = pd[size_t(g) * L + l];
-            p.fwd_off = int64_t(cidx.size());
-            p.rng_off = int64_t(rng.size() / 2);
+            PairDev p;
+            p.fwd_off = int64_t(t.cidx.size());
+            p.rng_off = int64_t(t.rng.size() / 2);
             for (int axis = 0; axis < 2; ++axis) {            // 0: rows (y), 1: columns (x)
                 const double th = axis == 0 ? W.theta_y : W.theta_x;
                 const double org = axis == 0 ? Ly.origin_y : Ly.origin_x;
@@ -251,14 +435,15 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfg, hipStream_t stream)
                     const double x = (j - 0.5 * ns) * W.subap;
                     const double u = (scale * x + th * Ly.height - org) / Ly.spacing + 0.5 * (Ly.n - 1);
                     if (!(u >= 0.0) || !(u <= Ly.n - 1)) {
-                        ctx.err = "guide-star footprint of sensor " + std::to_string(g) + " leaves the grid of layer " + std::to_string(l);
+                        err = "guide-star footprint of sensor " + std::to_string(g) + " leaves the grid of layer " +
+                              std::to_string(l);
                         return FEWHA_E_INVAL;
                     }
                     int i0 = int(std::floor(u));
                     if (i0 > Ly.n - 2) i0 = Ly.n - 2;
                     c0[j] = i0;
-                    cidx.push_back(i0);
-                    cfrac.push_back(u - i0);
+                    t.cidx.push_back(i0);
+                    t.cfrac.push_back(u - i0);
                 }
                 // gather ranges of the adjoint: nodes j with cell c0[j] in {a-1, a}
                 for (int a = 0; a < Ly.n; ++a) {
@@ -268,158 +453,148 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfg, hipStream_t stream)
                             if (first < 0) first = j;
                             last = j;
                         }
-                    rng.push_back(first < 0 ? 0 : first);
-                    rng.push_back(first < 0 ? 0 : last - first + 1);
+                    t.rng.push_back(first < 0 ? 0 : first);
+                    t.rng.push_back(first < 0 ? 0 : last - first + 1);
                 }
             }
+            t.pd.push_back(p);
         }
     }
-    ctx.n_cells = int64_t(cidx.size());
-    ctx.max_rng = 0;
-    for (size_t i = 1; i < rng.size(); i += 2) ctx.max_rng = std::max(ctx.max_rng, int(rng[i]));
-    ctx.steps = wavelet_steps(cfg);
-    ctx.npq = pq_partials(cfg);
-    ctx.n_ranges = int64_t(rng.size() / 2);
-
-    // ---- prior D (Sec. 3): inverse von Karman spectrum at the band frequency
-    const int64_t N = ctx.N;
-    std::vector<double> D(N);
-    if (cfg->prior_diag) {
-        std::memcpy(D.data(), cfg->prior_diag, sizeof(double) * N);
-    } else {
-        for (int l = 0; l < L; ++l) {
-            const fewha_layer& Ly = cfg->layers[l];
-            const int n = Ly.n, J = ilog2(n);
-            for (int a = 0; a < n; ++a)
-                for (int b = 0; b < n; ++b) {
-                    const int lev = coef_level(a, b, n, Ly.levels);
-                    const double f = std::ldexp(1.0, J - lev) / (n * Ly.spacing);
-                    D[ld[l].off + int64_t(a) * n + b] =
-                        std::pow(f * f + 1.0 / (cfg->L0 * cfg->L0), 11.0 / 6.0) *
-                        std::pow(cfg->r0, 5.0 / 3.0) / (0.023 * Ly.weight);
-                }
-        }
-    }
-
-    // ---- Jacobi preconditioner: diag(M)_i = alpha D_i + ||C^-1/2 A W^-1 e_i||^2.  The
-    // wavelet basis function of coefficient (a, b) at level lev is the outer product of two
-    // 1-D level-lev functions; bilinear propagation and both slope components keep that
-    // product form, so every diagonal block is a pair of small matrix products.
-    std::vector<double> Jinv(N);
+    // prior and exact Jacobi preconditioner J^-1 = 1 / diag(M) (Sec. 4)
+    const int64_t Ni = off - off0;
+    const size_t base = t.D.size();
+    t.D.resize(base + Ni);
+    t.Jinv.resize(base + Ni);
+    double* D = t.D.data() + base;
+    if (cfg->prior_diag)
+        std::memcpy(D, cfg->prior_diag, sizeof(double) * Ni);
+    else
+        prior_of(cfg, &t.ld[l0], D);
     if (cfg->precond_inv) {
-        std::memcpy(Jinv.data(), cfg->precond_inv, sizeof(double) * N);
+        std::memcpy(t.Jinv.data() + base, cfg->precond_inv, sizeof(double) * Ni);
     } else {
-        std::vector<double> diag(N, 0.0);
-        for (int l = 0; l < L; ++l) {
-            const fewha_layer& Ly = cfg->layers[l];
-            const int n = Ly.n;
-            for (int lev = 1; lev <= Ly.levels; ++lev) {
-                const int m2 = n >> (lev - 1);
-                // basis functions B[p][y], p < m2
-                std::vector<double> B(size_t(m2) * n);
-                std::vector<double> tmp(n);
-                for (int p = 0; p < m2; ++p) {
-                    std::fill(tmp.begin(), tmp.end(), 0.0);
-                    tmp[p] = 1.0;
-                    synth1d(tmp, n, lev, h, g6);
-                    std::copy(tmp.begin(), tmp.end(), B.begin() + size_t(p) * n);
-                }
-                std::vector<double> blk(size_t(m2) * m2, 0.0);
-                for (int g = 0; g < G; ++g) {
-                    const fewha_wfs& W = cfg->wfs[g];
-                    const int ns = W.n_sub;
-                    const PairDev& p = pd[size_t(g) * L + l];
-                    // interpolated 1-D functions at the sensor nodes, rows (y) and columns (x)
-                    std::vector<double> Yh(size_t(ns + 1) * m2), Xh(size_t(ns + 1) * m2);
-                    for (int axis = 0; axis < 2; ++axis) {
-                        std::vector<double>& H = axis == 0 ? Yh : Xh;
-                        for (int i = 0; i <= ns; ++i) {
-                            const int c0 = cidx[p.fwd_off + axis * (ns + 1) + i];
-                            const double f = cfrac[p.fwd_off + axis * (ns + 1) + i];
-                            for (int q = 0; q < m2; ++q)
-                                H[size_t(i) * m2 + q] = (1 - f) * B[size_t(q) * n + c0] + f * B[size_t(q) * n + c0 + 1];
-                        }
-                    }
-                    // s^x_ij = avg_y(i) * diff_x(j), s^y_ij = diff_y(i) * avg_x(j)
-                    std::vector<double> Sy2(size_t(ns) * m2), Dy2(size_t(ns) * m2), Sx2(size_t(ns) * m2), Dx2(size_t(ns) * m2);
-                    for (int i = 0; i < ns; ++i)
-                        for (int q = 0; q < m2; ++q) {
-                            const double y0 = Yh[size_t(i) * m2 + q], y1 = Yh[size_t(i + 1) * m2 + q];
-                            const double x0 = Xh[size_t(i) * m2 + q], x1 = Xh[size_t(i + 1) * m2 + q];
-                            Sy2[size_t(i) * m2 + q] = 0.25 * (y0 + y1) * (y0 + y1);
-                            Dy2[size_t(i) * m2 + q] = (y1 - y0) * (y1 - y0);
-                            Sx2[size_t(i) * m2 + q] = 0.25 * (x0 + x1) * (x0 + x1);
-                            Dx2[size_t(i) * m2 + q] = (x1 - x0) * (x1 - x0);
-                        }
-                    const double* wx = W.slope_weight;
-                    const double* wy = W.slope_weight + size_t(ns) * ns;
-                    std::vector<double> T1(size_t(ns) * m2), T2(size_t(ns) * m2);
-                    for (int i = 0; i < ns; ++i)
-                        for (int q = 0; q < m2; ++q) {
-                            double s1 = 0, s2 = 0;
-                            for (int j = 0; j < ns; ++j) {
-                                s1 += wx[size_t(i) * ns + j] * Dx2[size_t(j) * m2 + q];
-                                s2 += wy[size_t(i) * ns + j] * Sx2[size_t(j) * m2 + q];
-                            }
-                            T1[size_t(i) * m2 + q] = s1;
-                            T2[size_t(i) * m2 + q] = s2;
-                        }
-                    for (int a = 0; a < m2; ++a)
-                        for (int b = 0; b < m2; ++b) {
-                            if (coef_level(a, b, n, Ly.levels) != lev) continue;
-                            double s = 0;
-                            for (int i = 0; i < ns; ++i)
-                                s += Sy2[size_t(i) * m2 + a] * T1[size_t(i) * m2 + b] + Dy2[size_t(i) * m2 + a] * T2[size_t(i) * m2 + b];
-                            blk[size_t(a) * m2 + b] += s;
-                        }
-                }
-                const double id2 = 1.0 / (Ly.spacing * Ly.spacing);
-                for (int a = 0; a < m2; ++a)
-                    for (int b = 0; b < m2; ++b)
-                        if (coef_level(a, b, n, Ly.levels) == lev)
-                            diag[ld[l].off + int64_t(a) * n + b] = blk[size_t(a) * m2 + b] * id2;
-            }
-        }
-        for (int64_t i = 0; i < N; ++i) {
+        std::vector<double> diag(Ni, 0.0);
+        data_diag_of(cfg, &t.ld[l0], [&](int g, int l) -> const PairDev& { return t.pd[t.wd[g0 + g].pair0 + l]; },
+                     t.cidx, t.cfrac, diag.data());
+        for (int64_t i = 0; i < Ni; ++i) {
             const double d = diag[i] + cfg->alpha * D[i];
             if (!(d > 0) || !std::isfinite(d)) {
-                ctx.err = "diag(M) is not positive at index " + std::to_string(i);
+                err = "diag(M) is not positive at index " + std::to_string(i);
                 return FEWHA_E_NOT_SPD;
             }
-            Jinv[i] = 1.0 / d;
+            t.Jinv[base + i] = 1.0 / d;
         }
+    }
+    for (int64_t i = 0; i < Ni; ++i) t.D[base + i] *= cfg->alpha;   // the device keeps alpha D
+    return FEWHA_OK;
+}
+
+}  // namespace
+
+fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_t stream) {
+    const Sizes z = batch_sizes(cfgs, nb);
+    const int cb = coarse_block(cfgs[0].precision);
+    const bool f32 = cfgs[0].precision == FEWHA_FP32_OP_FP64_RED;
+    ctx.B = nb;
+    ctx.L = z.L;
+    ctx.G = z.G;
+    ctx.N = z.N;
+    ctx.S = z.S;
+    ctx.V = z.V;
+    ctx.VB = z.VB;
+    ctx.GB = z.GB;
+    ctx.npq = z.NPQ;
+    ctx.slots = z.slots;
+    ctx.fwd_tiles = z.data_tiles;
+    ctx.gather_tiles = z.gather_tiles;
+    ctx.steps = z.steps;
+    ctx.block_elems = block_elems(&cfgs[0]);
+
+    Tables t;
+    int64_t off = 0, soff = 0, noff = 0;
+    int toff = 0, gtoff = 0, pqoff = 0;
+    ctx.insts.assign(nb, InstDev{});
+    ctx.s_offs.assign(nb + 1, 0);
+    std::vector<VecBlk> vb;
+    std::vector<GramBlk> gb;
+    for (int i = 0; i < nb; ++i) {
+        const int64_t off0 = off;
+        const int pq0 = pqoff;
+        const fewha_status st = add_instance(t, &cfgs[i], i, cb, off, soff, noff, toff, gtoff, pqoff, ctx.err);
+        if (st != FEWHA_OK) {
+            if (nb > 1) ctx.err = "instance " + std::to_string(i) + ": " + ctx.err;
+            return st;
+        }
+        InstDev& I = ctx.insts[i];
+        I.off = off0;
+        I.n = off - off0;
+        I.nvb = vec_blocks(I.n, ctx.block_elems);
+        I.vb0 = int(vb.size());
+        I.ngb = gram_blocks(I.n);
+        I.gb0 = int(gb.size());
+        I.pq0 = pq0;
+        I.npq = pqoff - pq0;
+        for (int k = 0; k < I.nvb; ++k)
+            vb.push_back(VecBlk{I.off, int32_t(I.n), k, I.nvb, i, I.vb0 + k, I.pq0, I.npq, 0});
+        for (int k = 0; k < I.ngb; ++k)
+            gb.push_back(GramBlk{I.off, int32_t(I.n), k, I.ngb, i, I.gb0 * z.KE, 0});
+        ctx.s_offs[i + 1] = soff;
+    }
+    for (const LayerDev& d : t.ld) {
+        ctx.max_levels = std::max(ctx.max_levels, int(d.levels));
+        ctx.max_n = std::max(ctx.max_n, int(d.n));
+    }
+    ctx.n_cells = int64_t(t.cidx.size());
+    ctx.n_ranges = int64_t(t.rng.size() / 2);
+    ctx.max_rng = 0;
+    for (size_t i = 1; i < t.rng.size(); i += 2) ctx.max_rng = std::max(ctx.max_rng, int(t.rng[i]));
+    // layers of every tiled wavelet level, and the block -> sensor / layer tables
+    std::vector<int32_t> sl;
+    for (const StepInfo& st : z.steps)
+        for (int l = 0; l < z.L; ++l)
+            if (t.ld[l].n >= st.nb && ilog2(t.ld[l].n / st.nb) + 1 <= t.ld[l].levels) sl.push_back(l);
+    if (sl.empty()) sl.push_back(0);
+    std::vector<int32_t> dtiles, gtiles;
+    for (int g = 0; g < z.G; ++g)
+        for (int k = 0; k < t.wd[g].tiles_x * t.wd[g].tiles_x; ++k) dtiles.push_back(g);
+    for (int l = 0; l < z.L; ++l) {
+        const int tx = (t.ld[l].n + kGT - 1) / kGT;
+        for (int k = 0; k < tx * tx; ++k) gtiles.push_back(l);
     }
 
     // ---- upload (typed copies of the floating tables)
     const Layout& lo = ctx.lay;
     auto up = [&](size_t dst, const void* src, size_t bytes) -> bool {
-        return hipMemcpyAsync(ctx.ws + dst, src, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
+        return bytes == 0 || hipMemcpyAsync(ctx.ws + dst, src, bytes, hipMemcpyHostToDevice, stream) == hipSuccess;
     };
-    auto typed = [&](const std::vector<double>& v, double scale) {
+    auto typed = [&](const std::vector<double>& v) {
         std::vector<char> out(v.size() * ctx.esz);
         if (f32) {
             float* o = reinterpret_cast<float*>(out.data());
-            for (size_t i = 0; i < v.size(); ++i) o[i] = float(v[i] * scale);
+            for (size_t i = 0; i < v.size(); ++i) o[i] = float(v[i]);
         } else {
-            double* o = reinterpret_cast<double*>(out.data());
-            for (size_t i = 0; i < v.size(); ++i) o[i] = v[i] * scale;
+            std::memcpy(out.data(), v.data(), v.size() * sizeof(double));
         }
         return out;
     };
-    std::vector<double> wts;
-    for (int g = 0; g < G; ++g) {
-        const int ns = cfg->wfs[g].n_sub;
-        wts.insert(wts.end(), cfg->wfs[g].slope_weight, cfg->wfs[g].slope_weight + 2 * ns * ns);
-    }
-    const auto frac_t = typed(cfrac, 1.0);
-    const auto w_t = typed(wts, 1.0);
-    const auto pa_t = typed(D, cfg->alpha);
-    const auto j_t = typed(Jinv, 1.0);
-    bool ok = up(lo.layers, ld.data(), sizeof(LayerDev) * L) && up(lo.wfs, wd.data(), sizeof(WfsDev) * G) &&
-              up(lo.pairs, pd.data(), sizeof(PairDev) * pd.size()) &&
-              up(lo.cellidx, cidx.data(), sizeof(int32_t) * cidx.size()) && up(lo.frac, frac_t.data(), frac_t.size()) &&
-              up(lo.ranges, rng.data(), sizeof(int32_t) * rng.size()) && up(lo.weight, w_t.data(), w_t.size()) &&
-              up(lo.prior_a, pa_t.data(), pa_t.size()) && up(lo.jinv, j_t.data(), j_t.size());
+    const auto frac_t = typed(t.cfrac);
+    const auto w_t = typed(t.wts);
+    const auto pa_t = typed(t.D);
+    const auto j_t = typed(t.Jinv);
+    bool ok = up(lo.layers, t.ld.data(), sizeof(LayerDev) * t.ld.size()) &&
+              up(lo.wfs, t.wd.data(), sizeof(WfsDev) * t.wd.size()) &&
+              up(lo.pairs, t.pd.data(), sizeof(PairDev) * t.pd.size()) &&
+              up(lo.cellidx, t.cidx.data(), sizeof(int32_t) * t.cidx.size()) &&
+              up(lo.frac, frac_t.data(), frac_t.size()) &&
+              up(lo.ranges, t.rng.data(), sizeof(int32_t) * t.rng.size()) &&
+              up(lo.insts, ctx.insts.data(), sizeof(InstDev) * ctx.insts.size()) &&
+              up(lo.vecblk, vb.data(), sizeof(VecBlk) * vb.size()) &&
+              up(lo.gramblk, gb.data(), sizeof(GramBlk) * gb.size()) &&
+              up(lo.step_layers, sl.data(), sizeof(int32_t) * sl.size()) &&
+              up(lo.data_tiles, dtiles.data(), sizeof(int32_t) * dtiles.size()) &&
+              up(lo.gather_tiles, gtiles.data(), sizeof(int32_t) * gtiles.size()) &&
+              up(lo.weight, w_t.data(), w_t.size()) && up(lo.prior_a, pa_t.data(), pa_t.size()) &&
+              up(lo.jinv, j_t.data(), j_t.size());
     if (ok) ok = hipStreamSynchronize(stream) == hipSuccess;   // host vectors die at return
     if (!ok) { ctx.err = "hipMemcpyAsync of the setup tables failed"; return FEWHA_E_HIP; }
     return FEWHA_OK;

@@ -2,12 +2,18 @@
 // Alg. 3 residual update, the Galerkin projection and initial direction of Alg. 2 (Sec. 4.1),
 // and the PCG iterations of Alg. 1 / Alg. 2.
 //
-// Every inner product is reduced in FP64 in two fixed-order stages: vector kernels on a fixed
-// kVecBlocks grid write one partial per block; the consumer kernel -- every block of it,
-// redundantly -- sums those partials in the same order and derives the scalars it needs
-// (alpha, beta, mu, the k x k Gram solve).  Every block therefore holds bit-identical scalars
-// without an extra single-block launch, and results are reproducible run to run.  Block 0
-// records the scalars in device memory for the next kernels and for the frame statistics.
+// Every inner product is reduced in FP64 in two fixed-order stages: each vector workgroup
+// writes one partial per inner product; the consumer kernel -- every workgroup of it,
+// redundantly -- sums its instance's partials in the same order and derives the scalars it
+// needs (alpha, beta, mu, the k x k Gram solve).  Every workgroup therefore holds
+// bit-identical scalars without an extra single-block launch, and results are reproducible
+// run to run.  Workgroup 0 of an instance records its scalars in device memory for the next
+// kernels and for the frame statistics.
+//
+// A batch of independent instances runs through the same kernels: a workgroup's instance,
+// element range and partial column come from the workgroup table (absent for a single
+// instance, where the launch itself defines them).  An instance's workgroup count depends on
+// its own size only, so it gets the same bits alone or in a batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,22 +26,38 @@ namespace fewha {
 
 namespace {
 
-// Rows of the per-block partial buffer (kVecBlocks columns each).
+// Rows of the partial buffer (one column per vector workgroup of the batch).
 enum : int { P_RZ = 0, P_BB = 1, P_RR = 2, P_RZ1 = 3, P_PROJ = 4 };
 
 struct SlotList { int32_t s[kKMax]; };
 
-// Sums NV rows (row0..row0+nrows-1, nrows <= NV) of the partial buffer at once.
+// Work of one vector workgroup (see VecBlk).
+struct Seg {
+    int64_t off;
+    int n, local, nb, inst, col, pq0, npq;
+};
+
+__device__ __forceinline__ Seg seg_of(const VecBlk* __restrict__ vb, int64_t N, int npq) {
+    if (!vb) return Seg{0, int(N), int(blockIdx.x), int(gridDim.x), 0, int(blockIdx.x), 0, npq};
+    const VecBlk v = vb[blockIdx.x];
+    return Seg{v.off, v.n, v.local, v.nb, v.inst, v.col, v.pq0, v.npq};
+}
+
+// Sums NV rows (row0..row0+nrows-1, nrows <= NV) of the instance's partial columns at once.
 template <int NV>
-__device__ __forceinline__ void block_row_sums(const double* __restrict__ part, int row0, int nrows, double (&out)[NV]) {
+__device__ __forceinline__ void block_row_sums(const double* __restrict__ part, int pstride, const Seg& sg, int row0,
+                                               int nrows, double (&out)[NV]) {
     __shared__ double sh[NV][kThreads / 64];
+    const int c0 = sg.col - sg.local;
     double v[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         v[k] = 0;
 #pragma unroll
-        for (int j = 0; j < kVecBlocks / kThreads; ++j)
-            if (k < nrows) v[k] += part[size_t(row0 + k) * kVecBlocks + threadIdx.x + j * kThreads];
+        for (int j = 0; j < kVecBlocksMax / kThreads; ++j) {
+            const int b = threadIdx.x + j * kThreads;
+            if (k < nrows && b < sg.nb) v[k] += part[size_t(row0 + k) * pstride + c0 + b];
+        }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -167,11 +189,14 @@ __device__ double wave_forward_sub(const double* Mx, int ldr, int ldc, const dou
 // First frame: r = b - M c; later frames: r = (b - b_prev) + r (Alg. 3 residual update).
 // b_prev = b; partial (b, b).  Block 0 resets the frame's flags.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const T* __restrict__ b, T* __restrict__ b_prev,
+__global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* __restrict__ vb, int pstride,
+                                                        const T* __restrict__ b, T* __restrict__ b_prev,
                                                         T* __restrict__ r, const T* __restrict__ mc,
-                                                        double* __restrict__ part, Scalars* __restrict__ sc, int m) {
+                                                        double* __restrict__ part, Scalars* __restrict__ scs, int m) {
+    const Seg sg = seg_of(vb, N, 0);
     double bb = 0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
         const double bi = double(b[i]);
         if (mc)
             r[i] = T(bi - double(mc[i]));
@@ -181,8 +206,9 @@ __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const T* __res
         bb += bi * bi;
     }
     const double v[1] = {bb};
-    block_partials<1>(v, part, P_BB, kVecBlocks, blockIdx.x);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    block_partials<1>(v, part, P_BB, pstride, sg.col);
+    if (sg.local == 0 && threadIdx.x == 0) {
+        Scalars* sc = scs + sg.inst;
         sc->flags = 0;
         sc->used = m;
         sc->dropped = 0;
@@ -197,25 +223,36 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // 16 elements per step (lane l: row/column l mod 16, elements 4 (l / 16) .. +3), the four
 // wavefronts' tiles are summed in LDS in a fixed order and written as one partial.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gram(int64_t N, int m, SlotList sl, const T* __restrict__ U,
-                                                    const T* __restrict__ Q, const T* __restrict__ r,
-                                                    double* __restrict__ gpart) {
+__global__ void __launch_bounds__(kThreads) k_gram(int64_t N, const GramBlk* __restrict__ gt, int m, SlotList sl,
+                                                    const T* __restrict__ U, const T* __restrict__ Q,
+                                                    const T* __restrict__ r, double* __restrict__ gpart) {
     __shared__ double sh[4][256];
+    GramBlk g;
+    if (gt) {
+        g = gt[blockIdx.x];
+    } else {
+        g.off = 0;
+        g.n = int(N);
+        g.local = blockIdx.x;
+        g.nb = gridDim.x;
+        g.gbase = 0;
+    }
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tb_count = (m + 1 + 15) / 16;
     const int ta = blockIdx.y / tb_count, tb = blockIdx.y - ta * tb_count;
     const int ar = 16 * ta + (lane & 15), bc = 16 * tb + (lane & 15), kq = lane >> 4;
-    const T* pa = ar < m ? U + size_t(sl.s[ar]) * N : nullptr;
-    const T* pb = bc < m ? Q + size_t(sl.s[bc]) * N : (bc == m ? r : nullptr);
+    const T* pa = ar < m ? U + size_t(sl.s[ar]) * N + g.off : nullptr;
+    const T* pb = bc < m ? Q + size_t(sl.s[bc]) * N + g.off : (bc == m ? r + g.off : nullptr);
     f64x4 c = {0.0, 0.0, 0.0, 0.0};
     constexpr int DEPTH = 4;                       // 16-element chunks whose loads are in flight together
-    const int64_t step = int64_t(gridDim.x) * 4 * 16;
-    for (int64_t base = (int64_t(blockIdx.x) * 4 + wv) * 16; base < N; base += DEPTH * step) {   // N % 64 == 0
+    const int64_t step = int64_t(g.nb) * 4 * 16;
+    const int64_t n = g.n;
+    for (int64_t base = (int64_t(g.local) * 4 + wv) * 16; base < n; base += DEPTH * step) {   // n % 64 == 0
         double av[DEPTH][4], bv[DEPTH][4];
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d) {
             const int64_t e0 = base + d * step + 4 * kq;
-            const bool in = base + d * step < N;
+            const bool in = base + d * step < n;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 av[d][j] = (in && pa) ? double(pa[e0 + j]) : 0.0;
@@ -234,7 +271,7 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, int m, SlotList sl
     const int t = threadIdx.x, row = 16 * ta + (t >> 4), col = 16 * tb + (t & 15);
     if (row < m && col <= m) {
         const double v = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
-        gpart[size_t(row * (m + 1) + col) * kGramBlocks + blockIdx.x] = v;
+        gpart[size_t(g.gbase) + size_t(row * (m + 1) + col) * g.nb + g.local] = v;
     }
 }
 
@@ -245,19 +282,27 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, int m, SlotList sl
 // sum_{i<j} sigma_i (q_i, p_j); X is kept for the initial-direction step.
 template <int MB>
 __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, SlotList sl,
-                                                               Scalars* __restrict__ sc,
+                                                               Scalars* __restrict__ scs,
+                                                               const InstDev* __restrict__ insts, int ke,
                                                                const double* __restrict__ gpart) {
     __shared__ double X[kKMax * (kKMax + 1)];
     __shared__ double gm[kKMax];
+    const InstDev I = insts[blockIdx.x];               // one workgroup per instance
+    Scalars* __restrict__ sc = scs + blockIdx.x;
+    const double* __restrict__ gp = gpart + size_t(I.gb0) * ke;
+    const int ngb = I.ngb;
     const int ne = m * (m + 1);
-    {   // 8 lanes per entry, each summing kGramBlocks / 8 partials requested all at once
+    {   // 8 lanes per entry, each summing up to kGramBlocks / 8 partials requested all at once
         constexpr int PER = kGramBlocks / 8;
         const int sub = threadIdx.x & 7;
         for (int e0 = 0; e0 < ne; e0 += kSolveThreads / 8) {
             const int e = e0 + (threadIdx.x >> 3);
             double v[PER];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) v[k] = e < ne ? gpart[size_t(e) * kGramBlocks + sub * PER + k] : 0.0;
+            for (int k = 0; k < PER; ++k) {
+                const int j = sub * PER + k;
+                v[k] = (e < ne && j < ngb) ? gp[size_t(e) * ngb + j] : 0.0;
+            }
             double s = 0;
 #pragma unroll
             for (int k = 0; k < PER; ++k) s += v[k];
@@ -289,17 +334,21 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
 
 // Galerkin step c += U y, r -= Q y; then z = J^-1 r and partials of (Q_a, z).
 template <typename T, int MB>
-__global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, int m, SlotList sl, const T* __restrict__ U,
-                                                              const T* __restrict__ Q, const Scalars* __restrict__ sc,
+__global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, const VecBlk* __restrict__ vb, int pstride,
+                                                              int m, SlotList sl, const T* __restrict__ U,
+                                                              const T* __restrict__ Q, const Scalars* __restrict__ scs,
                                                               T* __restrict__ c, T* __restrict__ r, T* __restrict__ z,
                                                               const T* __restrict__ jinv, double* __restrict__ part) {
+    const Seg sg = seg_of(vb, N, 0);
+    const Scalars* __restrict__ sc = scs + sg.inst;
     double y[MB], acc[MB];
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
         y[a] = a < m ? sc->y[a] : 0.0;
         acc[a] = 0;
     }
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
         double ci = double(c[i]), ri = double(r[i]);
         double qv[MB];
 #pragma unroll
@@ -329,7 +378,7 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, int m, S
     __syncthreads();
     if (threadIdx.x < m) {
         const int a = threadIdx.x;
-        part[size_t(P_PROJ + a) * kVecBlocks + blockIdx.x] = (sh[a][0] + sh[a][1]) + (sh[a][2] + sh[a][3]);
+        part[size_t(P_PROJ + a) * pstride + sg.col] = (sh[a][0] + sh[a][1]) + (sh[a][2] + sh[a][3]);
     }
 }
 
@@ -338,16 +387,18 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, int m, S
 // with the running z, (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j)); p_0 = z - U y2.
 // Without recycled directions p_0 = z = J^-1 r (Alg. 1).  Partial of (r, p_0).
 template <typename T, int MB>
-__global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mode, SlotList sl,
-                                                        const T* __restrict__ U, Scalars* __restrict__ sc,
-                                                        const T* __restrict__ z, const T* __restrict__ r,
-                                                        const T* __restrict__ jinv, T* __restrict__ p,
-                                                        double* __restrict__ part) {
+__global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, const VecBlk* __restrict__ vb, int pstride, int m,
+                                                        int mode, SlotList sl, const T* __restrict__ U,
+                                                        Scalars* __restrict__ scs, const T* __restrict__ z,
+                                                        const T* __restrict__ r, const T* __restrict__ jinv,
+                                                        T* __restrict__ p, double* __restrict__ part) {
     constexpr int MB1 = MB > 0 ? MB : 1;
+    const Seg sg = seg_of(vb, N, 0);
+    Scalars* __restrict__ sc = scs + sg.inst;
     __shared__ double y2[kKMax];
     if (MB > 0) {
         double v[MB1];
-        block_row_sums<MB1>(part, P_PROJ, m, v);
+        block_row_sums<MB1>(part, pstride, sg, P_PROJ, m, v);
         __shared__ double gm[kKMax], R[kKMax * kKMax];
         __shared__ int32_t keep[kKMax];
         for (int e = threadIdx.x; e < m * m; e += kThreads) R[e] = sc->R[e];
@@ -369,7 +420,7 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mod
                 yk = wave_chol_solve<MB1>(R, keep, m, vk);
             if (k < m) {
                 y2[k] = yk;
-                if (blockIdx.x == 0) sc->y2[k] = yk;
+                if (sg.local == 0) sc->y2[k] = yk;
             }
         }
         __syncthreads();
@@ -378,7 +429,8 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mod
 #pragma unroll
     for (int a = 0; a < MB; ++a) yv[a] = a < m ? y2[a] : 0.0;
     double rz = 0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
         T pt;
         if (MB == 0) {
             pt = jinv[i] * r[i];
@@ -393,7 +445,7 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mod
         rz += double(r[i]) * double(pt);
     }
     const double vv[1] = {rz};
-    block_partials<1>(vv, part, P_RZ, kVecBlocks, blockIdx.x);
+    block_partials<1>(vv, part, P_RZ, pstride, sg.col);
 }
 
 // ------------------------------------------------------------------ PCG iteration
@@ -402,18 +454,21 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, int m, int mod
 // this iteration; c += alpha p, r -= alpha q; unless last: z = J^-1 r with partials of (r, z)
 // and, over the in-loop projection set, (Q_a, z) and (U_a, r); always the partial (r, r).
 template <typename T, int MP>
-__global__ void __launch_bounds__(kThreads) k_update1(int64_t N, int it, int mp, SlotList pl, const T* __restrict__ U,
-                                                       const T* __restrict__ Q, Scalars* __restrict__ sc,
+__global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* __restrict__ vb, int pstride, int it,
+                                                       int mp, SlotList pl, const T* __restrict__ U,
+                                                       const T* __restrict__ Q, Scalars* __restrict__ scs,
                                                        const T* __restrict__ p, const T* __restrict__ q,
                                                        T* __restrict__ c, T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ jinv, int last, int npq,
                                                        const double* __restrict__ pq_part, double* __restrict__ part,
                                                        int pslot) {
-    const double pq = block_sum_array(pq_part, npq);
+    const Seg sg = seg_of(vb, N, npq);
+    Scalars* __restrict__ sc = scs + sg.inst;
+    const double pq = block_sum_array(pq_part + sg.pq0, sg.npq);
     double rz;
     if (it == 0) {
         double t[1];
-        block_row_sums<1>(part, P_RZ, 1, t);
+        block_row_sums<1>(part, pstride, sg, P_RZ, 1, t);
         rz = t[0];
     } else {
         rz = sc->rzb[it & 1];
@@ -421,7 +476,7 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, int it, int mp,
     double alpha = rz / pq;
     const bool broken = sc->flags != 0 || !(pq > 0) || !isfinite(alpha);
     if (broken) alpha = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (sg.local == 0 && threadIdx.x == 0) {
         sc->pq = pq;
         sc->gam[pslot] = pq;
         sc->alpha = alpha;
@@ -432,7 +487,8 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, int it, int mp,
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
         c[i] = T(double(c[i]) + alpha * double(p[i]));
         const T rt = T(double(r[i]) - alpha * double(q[i]));
         r[i] = rt;
@@ -463,7 +519,7 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, int it, int mp,
     const int k = threadIdx.x;
     if (k < (last ? 1 : NV)) {
         const int row = k == 0 ? P_RR : (k == 1 ? P_RZ1 : P_PROJ + (k - 2));
-        part[size_t(row) * kVecBlocks + blockIdx.x] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+        part[size_t(row) * pstride + sg.col] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
     }
 }
 
@@ -471,16 +527,19 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, int it, int mp,
 // direction: mu = (z, q_m) / (p_m, q_m); or all of U through the Gram factor), the projected
 // (r, z) = (r, z) - sum_a y3_a (U_a, r) and beta; p_next = z - U y3 + beta p.
 template <typename T, int MP>
-__global__ void __launch_bounds__(kThreads) k_update2(int64_t N, int it, int mp, int project_all, SlotList pl,
-                                                       const T* __restrict__ U, Scalars* __restrict__ sc,
-                                                       const T* __restrict__ z, const T* __restrict__ p,
-                                                       T* __restrict__ pn, const double* __restrict__ part) {
+__global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* __restrict__ vb, int pstride, int it,
+                                                       int mp, int project_all, SlotList pl, const T* __restrict__ U,
+                                                       Scalars* __restrict__ scs, const T* __restrict__ z,
+                                                       const T* __restrict__ p, T* __restrict__ pn,
+                                                       const double* __restrict__ part) {
     constexpr int NV = 1 + 2 * MP;
     constexpr int MP1 = MP > 0 ? MP : 1;
+    const Seg sg = seg_of(vb, N, 0);
+    Scalars* __restrict__ sc = scs + sg.inst;
     __shared__ double sy[MP1];
     __shared__ double sbeta;
     double v[NV];
-    block_row_sums<NV>(part, P_RZ1, NV, v);   // (r,z), (Q_a,z) a < MP, (U_a,r) a < MP (entries a >= mp unused)
+    block_row_sums<NV>(part, pstride, sg, P_RZ1, NV, v);   // (r,z), (Q_a,z) a < MP, (U_a,r) a < MP (entries a >= mp unused)
     __shared__ double y3[MP1], R[MP1 * MP1];
     __shared__ int32_t keep[MP1];
     if (MP > 1 && project_all) {
@@ -522,7 +581,7 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, int it, int mp,
         }
         for (int a = 0; a < mp; ++a) sy[a] = y3[a];
         sbeta = beta;
-        if (blockIdx.x == 0) {
+        if (sg.local == 0) {
             sc->rzb[(it + 1) & 1] = rzn;
             sc->beta = beta;
             sc->mu = mp ? y3[0] : 0.0;
@@ -534,7 +593,8 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, int it, int mp,
     double yr[MP1];
 #pragma unroll
     for (int a = 0; a < MP; ++a) yr[a] = a < mp ? sy[a] : 0.0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
         double vv = double(z[i]) + beta * double(p[i]);
 #pragma unroll
         for (int a = 0; a < MP; ++a)
@@ -543,12 +603,19 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, int it, int mp,
     }
 }
 
-// Frame statistics (relative residual in FP64) into the context's and the caller's info.
-__global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ sc, const double* __restrict__ part,
-                                                      fewha_solve_info* __restrict__ info,
-                                                      fewha_solve_info* __restrict__ info_user, int iters) {
+// Frame statistics (relative residual in FP64) of every instance (one workgroup each) into
+// the context's and the caller's info.
+__global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
+                                                      int pstride, const double* __restrict__ part,
+                                                      fewha_solve_info* __restrict__ infos,
+                                                      fewha_solve_info* __restrict__ infos_user, int iters) {
+    const InstDev I = insts[blockIdx.x];
+    const Seg sg{I.off, int(I.n), 0, I.nvb, int(blockIdx.x), I.vb0, I.pq0, I.npq};
+    Scalars* __restrict__ sc = scs + blockIdx.x;
+    fewha_solve_info* info = infos + blockIdx.x;
+    fewha_solve_info* info_user = infos_user ? infos_user + blockIdx.x : nullptr;
     double v[2];
-    block_row_sums<2>(part, P_BB, 2, v);   // rows P_BB, P_RR
+    block_row_sums<2>(part, pstride, sg, P_BB, 2, v);   // rows P_BB, P_RR
     if (threadIdx.x == 0) {
         fewha_solve_info in;
         in.iters = iters;
@@ -572,30 +639,38 @@ int bucket(int m) {
     return 32;
 }
 
+// Launch geometry shared by the vector kernels of one context.
+struct VecLaunch {
+    int64_t N;
+    const VecBlk* vb;   // workgroup table (NULL for a single instance)
+    int grid, pstride;
+};
+
 template <typename T, int MB>
-void launch_gal(int64_t N, int m, const SlotList& sl, const T* U, const T* Q, const Scalars* sc, T* c, T* r, T* z,
-                const T* jinv, double* part, hipStream_t s) {
-    k_galerkin_apply<T, MB><<<kVecBlocks, kThreads, 0, s>>>(N, m, sl, U, Q, sc, c, r, z, jinv, part);
+void launch_gal(const VecLaunch& vl, int m, const SlotList& sl, const T* U, const T* Q, const Scalars* sc, T* c, T* r,
+                T* z, const T* jinv, double* part, hipStream_t s) {
+    k_galerkin_apply<T, MB><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, m, sl, U, Q, sc, c, r, z, jinv, part);
 }
 
 template <typename T, int MB>
-void launch_init(int64_t N, int m, int mode, const SlotList& sl, const T* U, Scalars* sc, const T* z, const T* r,
-                 const T* jinv, T* p, double* part, hipStream_t s) {
-    k_init_dir<T, MB><<<kVecBlocks, kThreads, 0, s>>>(N, m, mode, sl, U, sc, z, r, jinv, p, part);
+void launch_init(const VecLaunch& vl, int m, int mode, const SlotList& sl, const T* U, Scalars* sc, const T* z,
+                 const T* r, const T* jinv, T* p, double* part, hipStream_t s) {
+    k_init_dir<T, MB><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, m, mode, sl, U, sc, z, r, jinv, p, part);
 }
 
 template <typename T, int MP>
-void launch_upd(int64_t N, int it, int mp, const SlotList& pl, const T* U, const T* Q, Scalars* sc, const T* p,
-                const T* q, T* c, T* r, T* z, const T* jinv, int last, int npq, const double* pq_part, double* part,
-                int pslot, int project_all, T* pn, const Ctx& ctx, hipStream_t s) {
+void launch_upd(const VecLaunch& vl, int it, int mp, const SlotList& pl, const T* U, const T* Q, Scalars* sc,
+                const T* p, const T* q, T* c, T* r, T* z, const T* jinv, int last, int npq, const double* pq_part,
+                double* part, int pslot, int project_all, T* pn, const Ctx& ctx, hipStream_t s) {
     {
         ProfScope ps_(ctx, KID_UPDATE1, s);
-        k_update1<T, MP><<<kVecBlocks, kThreads, 0, s>>>(N, it, mp, pl, U, Q, sc, p, q, c, r, z, jinv, last, npq,
-                                                         pq_part, part, pslot);
+        k_update1<T, MP><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, it, mp, pl, U, Q, sc, p, q, c, r, z,
+                                                      jinv, last, npq, pq_part, part, pslot);
     }
     if (!last) {
         ProfScope ps_(ctx, KID_UPDATE2, s);
-        k_update2<T, MP><<<kVecBlocks, kThreads, 0, s>>>(N, it, mp, project_all, pl, U, sc, z, p, pn, part);
+        k_update2<T, MP><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, it, mp, project_all, pl, U, sc, z, p, pn,
+                                                      part);
     }
 }
 
@@ -619,7 +694,11 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
     double* pqp = c.at<double>(c.lay.pq_part);
     double* gpart = c.at<double>(c.lay.gram_part);
     Scalars* sc = c.at<Scalars>(c.lay.scalars);
+    const InstDev* insts = c.at<InstDev>(c.lay.insts);
     fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
+    const VecLaunch vl{N, c.B > 1 ? c.at<VecBlk>(c.lay.vecblk) : nullptr, c.VB, c.VB};
+    const GramBlk* gt = c.B > 1 ? c.at<GramBlk>(c.lay.gramblk) : nullptr;
+    const int ke = std::max(1, c.k * (c.k + 1));
 
     int m = 0;
     if (!c.first && c.k > 0)
@@ -633,7 +712,7 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
     if (c.first) launch_apply_M<T>(c, cv, vx, nullptr, s);
     {
         ProfScope ps_(c, KID_RESIDUAL, s);
-        k_residual<T><<<kVecBlocks, kThreads, 0, s>>>(N, b, bp, r, c.first ? vx : nullptr, part, sc, m);
+        k_residual<T><<<vl.grid, kThreads, 0, s>>>(N, vl.vb, vl.pstride, b, bp, r, c.first ? vx : nullptr, part, sc, m);
     }
     // a3 + a4: Galerkin step and initial direction
     T* p0 = U + size_t(c.head) * N;
@@ -641,36 +720,36 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
     if (m > 0) {
         {
             ProfScope ps_(c, KID_GRAM, s);
-            const dim3 grid(kGramBlocks, ((m + 15) / 16) * ((m + 1 + 15) / 16));
-            k_gram<T><<<grid, kThreads, 0, s>>>(N, m, act, U, Q, r, gpart);
+            const dim3 grid(c.GB, ((m + 15) / 16) * ((m + 1 + 15) / 16));
+            k_gram<T><<<grid, kThreads, 0, s>>>(N, gt, m, act, U, Q, r, gpart);
         }
         {
             ProfScope ps_(c, KID_GRAM_SOLVE, s);
             if (m <= 8)
-                k_gram_solve<8><<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
+                k_gram_solve<8><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, act, sc, insts, ke, gpart);
             else if (m <= 16)
-                k_gram_solve<16><<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
+                k_gram_solve<16><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, act, sc, insts, ke, gpart);
             else
-                k_gram_solve<32><<<1, kSolveThreads, 0, s>>>(m, c.mode, act, sc, gpart);
+                k_gram_solve<32><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, act, sc, insts, ke, gpart);
         }
         ProfScope ps_(c, KID_GALERKIN, s);
         switch (mb) {
-            case 1: launch_gal<T, 1>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            case 4: launch_gal<T, 4>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            case 8: launch_gal<T, 8>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            case 16: launch_gal<T, 16>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            default: launch_gal<T, 32>(N, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            case 1: launch_gal<T, 1>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            case 4: launch_gal<T, 4>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            case 8: launch_gal<T, 8>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            case 16: launch_gal<T, 16>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+            default: launch_gal<T, 32>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
         }
     }
     {
         ProfScope ps_(c, KID_INIT_DIR, s);
         switch (mb) {
-            case 0: launch_init<T, 0>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 1: launch_init<T, 1>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 4: launch_init<T, 4>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 8: launch_init<T, 8>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 16: launch_init<T, 16>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            default: launch_init<T, 32>(N, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 0: launch_init<T, 0>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 1: launch_init<T, 1>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 4: launch_init<T, 4>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 8: launch_init<T, 8>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 16: launch_init<T, 16>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            default: launch_init<T, 32>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
         }
     }
     // in-loop projection set: all of U (project_all) or the most recent recycled direction
@@ -695,23 +774,23 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
         launch_apply_M<T>(c, p, q, pqp, s);
         const int last = it == c.max_iter - 1;
         switch (mpb) {
-            case 0: launch_upd<T, 0>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+            case 0: launch_upd<T, 0>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
                                      c.project_all, pn, c, s); break;
-            case 1: launch_upd<T, 1>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+            case 1: launch_upd<T, 1>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
                                      c.project_all, pn, c, s); break;
-            case 4: launch_upd<T, 4>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+            case 4: launch_upd<T, 4>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
                                      c.project_all, pn, c, s); break;
-            case 8: launch_upd<T, 8>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+            case 8: launch_upd<T, 8>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
                                      c.project_all, pn, c, s); break;
-            case 16: launch_upd<T, 16>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+            case 16: launch_upd<T, 16>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
                                        c.project_all, pn, c, s); break;
-            default: launch_upd<T, 32>(N, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
+            default: launch_upd<T, 32>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
                                        c.project_all, pn, c, s); break;
         }
     }
     {
         ProfScope ps_(c, KID_FINISH, s);
-        k_finish<<<1, kThreads, 0, s>>>(sc, part, info, info_user, c.max_iter);
+        k_finish<<<c.B, kThreads, 0, s>>>(sc, insts, vl.pstride, part, info, info_user, c.max_iter);
     }
 }
 
@@ -746,7 +825,7 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
         e = hipMemcpyAsync(s_in, slopes, sizeof(T) * c.S, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipGraphLaunch(it->second, s);
         if (e == hipSuccess && info_user)
-            e = hipMemcpyAsync(info_user, info, sizeof(fewha_solve_info), hipMemcpyDeviceToDevice, s);
+            e = hipMemcpyAsync(info_user, info, sizeof(fewha_solve_info) * c.B, hipMemcpyDeviceToDevice, s);
     } else {
         enqueue_frame<T>(c, slopes, info_user, s);
     }

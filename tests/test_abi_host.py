@@ -92,3 +92,19 @@ def test_missing_weights_rejected_by_binding():
     spec = synth.config_small()        # weights are set by the simulator's noise calibration
     with pytest.raises(fw.FewhaError):
         fw.fewha_workspace_size(spec)
+
+
+def test_batch_workspace_is_the_sum_of_its_instances_and_settings_must_agree():
+    a, b = synth.config_tiny(), synth.config_mixed()
+    b = b.copy(max_iter=a.max_iter, recycle_k=a.recycle_k)
+    single = fw.fewha_workspace_size(a) + fw.fewha_workspace_size(b)
+    both = fw.fewha_workspace_size([a, b])
+    assert 0.8 * single < both <= single      # shared tables and alignment only
+    with pytest.raises(fw.FewhaError) as e:
+        fw.fewha_workspace_size([a, b.copy(max_iter=a.max_iter + 1)])
+    assert "instance 1" in str(e.value) and "same for every instance" in str(e.value)
+    bad = b.copy()
+    bad.layers[0].n = 24
+    with pytest.raises(fw.FewhaError) as e:
+        fw.fewha_workspace_size([a, bad])
+    assert "instance 1" in str(e.value) and "power of two" in str(e.value)

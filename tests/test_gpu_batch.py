@@ -1,0 +1,177 @@
+"""Batches of independent instances (one context, concatenated vectors) on the GPU, through
+the C ABI: every instance must give the bits it gets when solved alone, and match its own
+FP64 oracle within 1e-10 per frame."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import AugmentedReconstructor, OracleSystem
+import paper_2011_06842_amd as fw
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+COMMON = dict(max_iter=5, recycle_k=4, recycle_mode="galerkin", project_all=False, precision="fp64", rel_tol=0.0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def dev(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dtype)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _random_weights(spec, seed):
+    rng = np.random.default_rng(seed)
+    for w in spec.wfs:
+        m = np.concatenate([w.mask.ravel(), w.mask.ravel()])
+        w.weight = np.where(m, rng.uniform(0.5, 2.0, size=m.size), 0.0)
+    return spec
+
+
+_CACHE = {}
+
+
+def known_batch():
+    """Three systems of different shapes (grids 8-64, 1x1 to 40x40 sensors, 2-4 layers)
+    with the batch-wide settings in common, and 6 frames of slopes each."""
+    if "known" not in _CACHE:
+        specs = [synth.config_tiny().copy(**COMMON), synth.config_mixed().copy(**COMMON)]
+        small = synth.config_small().copy(**COMMON)
+        seqs = []
+        for k, sp in enumerate(specs):
+            rng = np.random.default_rng(30 + k)
+            S = synth.n_slopes(sp)
+            base = rng.standard_normal(S)
+            m = np.concatenate([np.concatenate([w.mask.ravel(), w.mask.ravel()]) for w in sp.wfs])
+            seqs.append(np.stack([(base + 0.1 * t * rng.standard_normal(S)) * m for t in range(6)]))
+        seqs.append(synth.make_sequence(small, 6, seed=8))
+        specs.append(small)
+        _CACHE["known"] = (specs, seqs, [OracleSystem(sp) for sp in specs])
+    return _CACHE["known"]
+
+
+def random_batch(n=5, precision="fp32"):
+    key = ("random", n, precision)
+    if key not in _CACHE:
+        rng = np.random.default_rng(2024)
+        specs, seqs = [], []
+        while len(specs) < n:
+            sp = synth.config_random_instance(rng, precision=precision).copy(max_iter=6, recycle_k=5, rel_tol=0.0)
+            if synth.n_coeffs(sp) > 200_000:      # keep the test batch small
+                continue
+            seqs.append(synth.make_sequence(sp, 5, seed=int(rng.integers(1 << 30))))
+            specs.append(sp)
+        _CACHE[key] = (specs, seqs)
+    return _CACHE[key]
+
+
+def concat(seqs, t, dtype):
+    return dev(np.concatenate([s[t] for s in seqs]), dtype)
+
+
+def test_batch_layout_and_offsets():
+    specs, _, _ = known_batch()
+    ctx = fw.FewhaContext(specs, device=DEV)
+    assert ctx.B == 3
+    assert ctx.coeff_offsets == list(np.cumsum([0] + [synth.n_coeffs(s) for s in specs]))
+    assert ctx.slope_offsets == list(np.cumsum([0] + [synth.n_slopes(s) for s in specs]))
+    assert ctx.N == ctx.coeff_offsets[-1] and ctx.S == ctx.slope_offsets[-1]
+
+
+def test_batch_operator_pieces_match_oracle():
+    specs, seqs, systems = known_batch()
+    ctx = fw.FewhaContext(specs, device=DEV)
+    co, so = ctx.coeff_offsets, ctx.slope_offsets
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(ctx.N)
+    s = rng.standard_normal(ctx.S)
+    y = host(ctx.fewha_apply_A(dev(x, np.float64)))
+    b = host(ctx.fewha_rhs(dev(s, np.float64)))
+    at = host(ctx.fewha_apply_piece(fw.PIECE_AT, dev(s, np.float64)))
+    a = host(ctx.fewha_apply_piece(fw.PIECE_A, dev(x, np.float64)))
+    for i, sysm in enumerate(systems):
+        xi, si = x[co[i]:co[i + 1]], s[so[i]:so[i + 1]]
+        D = sysm.prior()
+        assert rel(y[co[i]:co[i + 1]], sysm.apply_M(xi, D)) <= 1e-12, i
+        assert rel(b[co[i]:co[i + 1]], sysm.rhs(si)) <= 1e-12, i
+        assert rel(at[co[i]:co[i + 1]], np.concatenate([p.ravel() for p in sysm.A_T(si)])) <= 1e-13, i
+        assert rel(a[so[i]:so[i + 1]], sysm.A(sysm.split_layers(xi))) <= 1e-13, i
+
+
+@pytest.mark.parametrize("mode, project_all", [("galerkin", False), ("paper", False), ("galerkin", True)])
+def test_batch_frames_match_oracle_and_single_instances(mode, project_all):
+    specs, seqs, _ = known_batch()
+    specs = [sp.copy(recycle_mode=mode, project_all=project_all) for sp in specs]
+    systems = [OracleSystem(sp) for sp in specs]
+    batch = fw.FewhaContext(specs, device=DEV)
+    singles = [fw.FewhaContext(sp, device=DEV) for sp in specs]
+    refs = [AugmentedReconstructor(sysm) for sysm in systems]
+    co = batch.coeff_offsets
+    info = batch.new_info()
+    for t in range(len(seqs[0])):
+        c = host(batch.fewha_solve_aug(concat(seqs, t, np.float64), info=info))
+        infos = fw.decode_info(info)
+        for i in range(len(specs)):
+            ci = host(singles[i].fewha_solve_aug(dev(seqs[i][t], np.float64)))
+            assert np.array_equal(c[co[i]:co[i + 1]], ci), (t, i)
+            c_ref, i_ref = refs[i].solve(seqs[i][t])
+            assert rel(c[co[i]:co[i + 1]], c_ref) <= 1e-10, (t, i)
+            assert infos[i]["recycle_used"] == i_ref["recycle_used"] and infos[i]["flags"] == 0
+            assert abs(infos[i]["rel_res"] - i_ref["rel_res"]) <= 1e-9 * i_ref["rel_res"]
+
+
+def test_ragged_random_batch_fp32_bitwise_to_single_instances():
+    """Random instances (8-39 m, 20-84 subapertures, 3-9 layers, 1-6 NGS/LGS): batched and
+    alone, with and without graph capture, every frame's coefficients agree bitwise."""
+    specs, seqs = random_batch()
+    batch = fw.FewhaContext(specs, device=DEV)
+    direct = fw.FewhaContext(specs, device=DEV)
+    direct.fewha_use_graphs(False)
+    singles = [fw.FewhaContext(sp, device=DEV) for sp in specs]
+    co = batch.coeff_offsets
+    for t in range(len(seqs[0])):
+        s = concat(seqs, t, np.float32)
+        c = batch.fewha_solve_aug(s)
+        cd = direct.fewha_solve_aug(s)
+        assert torch.equal(c, cd), t
+        ch = host(c)
+        for i, sp in enumerate(specs):
+            ci = host(singles[i].fewha_solve_aug(dev(seqs[i][t], np.float32)))
+            assert np.array_equal(ch[co[i]:co[i + 1]], ci), (t, i)
+
+
+def test_ragged_random_batch_fp32_matches_oracle_first_frames():
+    specs, seqs = random_batch()
+    batch = fw.FewhaContext(specs, device=DEV)
+    co = batch.coeff_offsets
+    refs = [AugmentedReconstructor(OracleSystem(sp)) for sp in specs]
+    for t in range(2):
+        c = host(batch.fewha_solve_aug(concat(seqs, t, np.float32)))
+        for i in range(len(specs)):
+            c_ref, _ = refs[i].solve(seqs[i][t].astype(np.float32).astype(np.float64))
+            assert rel(c[co[i]:co[i + 1]], c_ref) <= 5e-5, (t, i)
+
+
+def test_batch_checkpoint_resume_bitwise():
+    specs, seqs, _ = known_batch()
+    a = fw.FewhaContext(specs, device=DEV)
+    outs = [host(a.fewha_solve_aug(concat(seqs, t, np.float64))) for t in range(6)]
+    b = fw.FewhaContext(specs, device=DEV)
+    for t in range(3):
+        b.fewha_solve_aug(concat(seqs, t, np.float64))
+    state = b.fewha_get_state()
+    c = fw.FewhaContext(specs, device=DEV)
+    c.fewha_set_state(state)
+    for t in range(3, 6):
+        assert np.array_equal(host(c.fewha_solve_aug(concat(seqs, t, np.float64))), outs[t]), t
+    single = fw.FewhaContext(specs[0], device=DEV)
+    with pytest.raises(fw.FewhaError):
+        single.fewha_set_state(state)
