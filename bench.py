@@ -37,6 +37,11 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "adj_gather_elt_mcao_fp32_pmc.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_06842_amd", "csrc", "fewha_operator.hip")
 
 
+def log(msg):
+    """Progress of the legs on stderr (stdout carries the one JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def coarse_sizes(spec):
     """Per layer: side of the top-left block the coarse kernels transform in LDS (0 if none)."""
     out = []
@@ -66,6 +71,26 @@ def op_kernel_bytes(name, step, spec, steps, N, S, V, e):
     if name == "adj_gather":      # sensor nodes in, layer images out
         return (V + N) * e
     raise ValueError(name)
+
+
+def frame_kernel_bytes(name, N, S, V, e, m, it, mp):
+    """Algorithmic bytes of one steady-state frame's launches of a solver kernel (m recycled
+    directions, it iterations, mp directions projected in the loop)."""
+    if name == "slopes_adj":      # slopes and weights in, sensor nodes out
+        return (2 * S + V) * e
+    if name == "residual":        # b, b_prev, r in; r, b_prev out
+        return 5 * N * e
+    if name == "gram":            # m U, m Q, r in
+        return (2 * m + 1) * N * e
+    if name == "galerkin_apply":  # c, r, J^-1, m U, m Q in; c, r, z out
+        return (6 + 2 * m) * N * e
+    if name == "init_dir":        # z, r, m U in; p out
+        return (3 + m) * N * e
+    if name == "update1":         # p, q, c, r, J^-1 (+ U, Q of the projection) in; c, r, z out; last: no z
+        return ((it - 1) * (8 + 2 * mp) + 6) * N * e
+    if name == "update2":         # z, p (+ U of the projection) in; next p out
+        return (it - 1) * (3 + mp) * N * e
+    return 0.0
 
 
 def source_sha256(path):
@@ -109,6 +134,129 @@ def copy_probe(mib):
     return 0
 
 
+def run_batch(args, dev):
+    """Throughput form: B independent instances of the ELT geometry in one context (one frame
+    advances all of them).  Instance i reads the slope stream of atmosphere i mod A at a time
+    offset, so that every instance sees its own frames; all share the noise weights, hence
+    one exact Jacobi preconditioner, passed explicitly to the later contexts of the tuner."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2011_06842_amd as fw
+
+    B = args.batch
+    A = min(4, B)
+    stride = 2
+    F = args.batch_warmup + args.batch_steps
+    need = F + stride * ((B + A - 1) // A)
+    base = synth.config_elt_mcao(precision="fp32")
+    t0 = time.perf_counter()
+    specs_a, seqs = [], []
+    for a in range(A):
+        sp = base.copy()
+        seqs.append(synth.make_sequence(sp, need, seed=SEED + 1 + a).astype(np.float32))
+        specs_a.append(sp)
+    spec = specs_a[0]
+    specs = [spec] * B
+    S1 = seqs[0].shape[1]
+    frames = torch.empty((F, B * S1), dtype=torch.float32)
+    for i in range(B):
+        o = stride * (i // A)
+        frames[:, i * S1:(i + 1) * S1] = torch.from_numpy(seqs[i % A][o:o + F])
+    frames = frames.to(dev)
+    t_gen = time.perf_counter() - t0
+    log(f"batched leg: {B} instances, slopes generated in {t_gen:.1f} s")
+    it, m = spec.max_iter, spec.recycle_k
+    mp = 1
+
+    def timed(ctx, warm, steps):
+        c = torch.empty(ctx.N, dtype=torch.float32, device=dev)
+        for t in range(warm):
+            ctx.fewha_solve_aug(frames[t], c)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        w0 = time.perf_counter()
+        ev[0].record()
+        for k in range(steps):
+            ctx.fewha_solve_aug(frames[warm + k], c)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        return wall, np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+
+    # tuner: elements per vector workgroup (fixes the reduction order of every instance)
+    t0 = time.perf_counter()
+    tune = {}
+    jinv = None
+    for be in args.block_elems:
+        sp = spec.copy()
+        sp.block_elems = be
+        ctx = fw.FewhaContext([sp] * B, device=dev, precond_inv=jinv)
+        if jinv is None:
+            j = ctx.fewha_get_vector(1).double().cpu().numpy()
+            n1 = ctx.coeff_offsets[1]
+            jinv = [j[:n1]] * B
+        wall, fm = timed(ctx, 3, max(3, args.batch_steps // 4))
+        tune[be] = float(np.median(fm))
+        log(f"batched leg: block_elems {be}: frame {tune[be]:.3f} ms")
+        del ctx
+        torch.cuda.empty_cache()
+    best = min(tune, key=tune.get)
+    t_setup = time.perf_counter() - t0
+    sp = spec.copy()
+    sp.block_elems = best
+    ctx = fw.FewhaContext([sp] * B, device=dev, precond_inv=jinv)
+    wall, fm = timed(ctx, args.batch_warmup, args.batch_steps)
+    log(f"batched leg: timed {args.batch_steps} frames, p50 {np.median(fm):.3f} ms")
+    N, S = ctx.N, ctx.S
+    V = B * sum((w.n_sub + 1) ** 2 for w in spec.wfs)
+
+    # per-kernel profile of further frames (synchronous per launch, outside the timed region)
+    ctx.fewha_profile(True)
+    P = 3
+    for t in range(P):
+        ctx.fewha_solve_aug(frames[t])
+    prof = ctx.fewha_profile_read()
+    ctx.fewha_profile(False)
+    steps = ctx.fewha_wavelet_steps()
+    e = 4
+    kern = {}
+    for name, (ms, nl) in prof.items():
+        if not nl:
+            continue
+        if name in OP_KERNELS:
+            if name.endswith("_step"):
+                b = sum(op_kernel_bytes(name, k, spec, steps, N, S, V, e) for k in range(len(steps)))
+                b *= (nl / P) / len(steps)
+            else:
+                b = op_kernel_bytes(name, None, spec, steps, N, S, V, e) * (B if "coarse" in name else 1)
+                b *= nl / P
+        else:
+            b = frame_kernel_bytes(name, N, S, V, e, m, it, mp)
+        ms_f = ms / P
+        kern[name] = {"ms_per_frame": round(ms_f, 4), "launches_per_frame": nl / P,
+                      "GB_s": round(b / (ms_f * 1e-3) / 1e9, 1) if b else None}
+    dom = max((k for k in kern if kern[k]["GB_s"]), key=lambda k: kern[k]["ms_per_frame"])
+    ach = kern[dom]["GB_s"]
+    return {
+        "workload": f"elt_mcao_fp32_x{B}_instances",
+        "instances": B,
+        "applies_per_s": round(B * it * args.batch_steps / wall, 1),
+        "frame_ms_p50": round(float(np.percentile(fm, 50)), 4),
+        "frame_ms_p99": round(float(np.percentile(fm, 99)), 4),
+        "instance_frames_per_s": round(B * args.batch_steps / wall, 1),
+        "steps": args.batch_steps, "warmup": args.batch_warmup,
+        "block_elems": best, "tuner_frame_ms": {str(k): round(v, 4) for k, v in tune.items()},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "share_of_frame": round(kern[dom]["ms_per_frame"] / float(np.median(fm)), 3)},
+        "kernels": dict(sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_frame"])),
+        "input": f"{A} seeded atmospheres, instance i reads atmosphere i mod {A} from frame {stride} (i div {A})",
+        "input_generation_s": round(t_gen, 1), "setup_and_tuning_s": round(t_setup, 1),
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +267,10 @@ def main(argv=None):
     ap.add_argument("--profile-frames", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
+    ap.add_argument("--batch", type=int, default=64, help="instances of the batched leg (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-warmup", type=int, default=5)
+    ap.add_argument("--block-elems", type=lambda v: [int(x) for x in v.split(",")], default=[384, 2048, 8192])
     args = ap.parse_args(argv)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
@@ -140,6 +292,7 @@ def main(argv=None):
     seq64 = synth.make_sequence(spec, F, seed=SEED)
     t_gen = time.perf_counter() - t_gen
     seq32 = seq64.astype(np.float32)
+    log(f"single instance: {F} frames generated in {t_gen:.1f} s")
     slopes = torch.from_numpy(seq32).to(dev)                  # resident in HBM before timing
     ctx = fw.FewhaContext(spec, device=dev)
     N, S = ctx.N, ctx.S
@@ -178,6 +331,7 @@ def main(argv=None):
     e1.record()
     torch.cuda.synchronize()
     op_ms = e0.elapsed_time(e1) / R
+    log(f"single instance: frame p50 {np.median(frame_ms):.4f} ms, apply {1000 * op_ms:.1f} us")
 
     # per-kernel durations from HIP events around every launch of a fresh run of the same
     # frames (profiling synchronises per call, so it runs outside the timed region)
@@ -254,6 +408,7 @@ def main(argv=None):
         "paper_context": "CPU aug. FEWHA MCAO 1.9 ms/frame on 12 Haswell cores (different system size)",
     }
 
+    log("single instance: kernel profile and per-kernel timing done")
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
         from oracle import AugmentedReconstructor, OracleSystem
@@ -278,6 +433,10 @@ def main(argv=None):
         # differences accumulate slowly; the per-frame bound applies from an identical state)
         out["rel_err_vs_oracle_free_running"] = {"frames": nf, "max": max(errs), "last": errs[-1]}
     out["input_generation_s"] = round(t_gen, 2)
+    if args.batch > 0:
+        del ctx, pctx
+        torch.cuda.empty_cache()
+        out["batched"] = run_batch(args, dev)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -28,13 +28,13 @@ inline int coarse_block(int /*precision*/) { return 64; }
 constexpr int kST = 32;             // output tile side of a tiled synthesis step
 constexpr int kAT = 16;             // coefficient tile side (per band) of a tiled analysis step
 constexpr int kGT = 16;             // layer-node tile side of the adjoint gather
-constexpr int kRMax = 6;            // contributions per layer row/column kept in LDS by the gather
+constexpr int kRMax = 6;            // contributions per layer row/column held by a gather record
+constexpr int kXcds = 8;            // accelerator complex dies; workgroup i runs on die i mod kXcds
 constexpr int kGramBlocks = 256;    // Gram workgroups of one instance at most
 constexpr int kDataThreads = 1024;  // threads of the fused data-term kernel
 constexpr int kSolveThreads = 1024; // threads of the single-block Gram reduction and solve
 constexpr int kLayerGroups = 3;     // threads sharing one wavefront node's layer sum
-constexpr int kGatherGroup = 8;     // sensors whose gather lists are built together
-constexpr int kGatherRegion = 16384; // LDS bytes for the gather's sensor-node rectangles
+constexpr int kGatherGroup = 8;     // sensors whose gather lists are staged together
 
 // Device descriptors (plain data, copied into the workspace at setup).  The layers and
 // sensors of all instances of a batch are listed one after the other; a sensor only sees the
@@ -49,7 +49,7 @@ struct LayerDev {
     int32_t g0, ng;       // sensors of the instance
     int32_t pq0;          // first (p, q) partial of the layer: tiled analysis tiles by level, then coarse
     int32_t pq_coarse;    // index of the coarse analysis partial (relative to pq0)
-    int32_t gt0;          // first tile of the layer in the gather grid
+    int32_t rb0;          // the gather records of (sensor d.g0 + j, this layer) start at recbase[rb0 + j]
 };
 
 inline int coarse_first_level(int n, int cb) {
@@ -68,6 +68,15 @@ struct WfsDev {
     int32_t l0, nl;       // layers of the instance
     int32_t pair0;        // pair (this sensor, layer l0 + j) is pair0 + j
     int32_t pad_;
+    int64_t fwd0;         // bilinear cells of pair (this sensor, layer l0 + j) at fwd0 + j * 2 (ns + 1)
+};
+
+// Transpose of the bilinear propagation along one axis, for one layer row (column) a of one
+// pair: sensor rows (columns) start .. start + count - 1 contribute with weights w.
+template <typename T>
+struct GatherRec {
+    int32_t start, count;
+    T w[kRMax];
 };
 
 struct PairDev {          // one (sensor, layer) pair of the same instance
@@ -113,7 +122,7 @@ struct Scalars {
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
     size_t layers, wfs, pairs, cellidx, frac, ranges, weight, prior_a, jinv;
-    size_t insts, vecblk, gramblk, step_layers, data_tiles, gather_tiles;
+    size_t insts, vecblk, gramblk, step_layers, data_tiles, gather_tiles, grecs, recbase;
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
     size_t c, r, z, b, b_prev, s_in;
     size_t ring_u, ring_q;
@@ -151,7 +160,8 @@ struct Ctx {
     int64_t N = 0, S = 0, V = 0;
     int VB = 0, GB = 0;        // vector and Gram workgroups of all instances
     int block_elems = kDefaultBlockElems;
-    int gather_tiles = 0;      // total layer tiles of the gather
+    int data_grid = 0;         // workgroups of the fused data term (tiles, padded to kXcds)
+    int gather_grid = 0;       // workgroups of the gather (layer tiles, padded to kXcds)
     std::vector<InstDev> insts;
     std::vector<int64_t> s_offs;   // slope offsets of the instances (B + 1)
     int prec = 0;              // fewha_precision
@@ -160,7 +170,6 @@ struct Ctx {
     int max_iter = 0, k = 0, mode = 1, project_all = 0;
     int max_levels = 0, max_n = 0;
     int slots = 0;             // ring capacity k + max_iter
-    int fwd_tiles = 0;         // total tiles of the fused data-term kernel
     int max_rng = 0;           // largest gather contribution count of a layer row/column
     std::vector<StepInfo> steps;  // tiled wavelet levels (ascending block size)
     int npq = 0;               // (p, q) partial entries written by one analysis

@@ -28,6 +28,13 @@ namespace {
 
 __device__ __forceinline__ int ilog2i(int v) { return 31 - __clz(v); }
 
+// Workgroup index in an order that gives die x (workgroups x, x + kXcds, ...) a contiguous
+// share of the tiles, so that the halos neighbouring tiles share are fetched into one L2.
+__device__ __forceinline__ int die_ordered_block() {
+    const int g = gridDim.x, b = blockIdx.x;
+    return (g % kXcds) ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
+}
+
 // Filter taps split by parity, so that every index is a compile-time constant (a tap index
 // that varies across lanes would otherwise be fetched from memory inside the loops).
 template <typename T>
@@ -119,7 +126,8 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
     __shared__ T R[2 * H][2 * H + 1];
     __shared__ T I[kST][2 * H + 1];
     const int tx = nbs / kST, tiles = tx * tx;
-    const int li = blockIdx.x / tiles, tile = blockIdx.x - li * tiles;
+    const int bid = die_ordered_block();
+    const int li = bid / tiles, tile = bid - li * tiles;
     const LayerDev d = lays[sl[li]];
     const int n = d.n;
     const int lev = ilog2i(n / nbs) + 1;
@@ -187,7 +195,8 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
     __shared__ T R[W][W + 1];
     __shared__ T I[W][2 * kAT + 1];
     const int M = nbs >> 1, tx = M / kAT, tiles = tx * tx;
-    const int li = blockIdx.x / tiles, tile = blockIdx.x - li * tiles;
+    const int bid = die_ordered_block();
+    const int li = bid / tiles, tile = bid - li * tiles;
     const LayerDev d = lays[sl[li]];
     const int n = d.n;
     const int lev = ilog2i(n / nbs) + 1;
@@ -369,37 +378,79 @@ __device__ __forceinline__ int find_sensor(const WfsDev* __restrict__ wfs, int G
 // combined in a fixed order.
 template <typename T>
 __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __restrict__ wfs,
-                                                             const int32_t* __restrict__ tile_sensor,
+                                                             const int2* __restrict__ tiles,
                                                              const LayerDev* __restrict__ lays,
                                                              const PairDev* __restrict__ pairs,
                                                              const int32_t* __restrict__ cidx,
                                                              const T* __restrict__ frac, const T* __restrict__ phi,
                                                              const T* __restrict__ w, T* __restrict__ psi) {
     constexpr int E = kTile + 2, S1 = kTile + 1;
+    static_assert(S1 * S1 <= kDataThreads, "one subaperture per thread");
     __shared__ T spart[kLayerGroups][E * E];
     __shared__ T stx[S1 * S1], sty[S1 * S1];
     __shared__ int32_t srow[FEWHA_MAX_LAYERS][E], scol[FEWHA_MAX_LAYERS][E];
     __shared__ T sfy[FEWHA_MAX_LAYERS][E], sfx[FEWHA_MAX_LAYERS][E];
-    const WfsDev W = wfs[tile_sensor[blockIdx.x]];
+    __shared__ int32_t sn[FEWHA_MAX_LAYERS];
+    __shared__ int64_t soffl[FEWHA_MAX_LAYERS];
+    const int2 st = tiles[blockIdx.x];
+    if (st.x < 0) return;                                        // padding of the die-ordered grid
+    const WfsDev W = wfs[st.x];
     const int ns = W.ns, np = ns + 1;
     const int L = W.nl;
-    const LayerDev* __restrict__ ly = lays + W.l0;               // the layers of the sensor's instance
-    const int tl = blockIdx.x - W.tile_off;
+    const int tl = st.y;
     const int i0 = (tl / W.tiles_x) * kTile, j0 = (tl % W.tiles_x) * kTile;
-    for (int e = threadIdx.x; e < L * 2 * E; e += kDataThreads) {
-        const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, k = q - col * E;
-        const int node = (col ? j0 : i0) - 1 + k;
-        const int nn = node < 0 ? 0 : (node > ns ? ns : node);     // clamped: halo nodes outside are unused
-        const size_t o = size_t(pairs[W.pair0 + l].fwd_off) + col * np + nn;
-        const int32_t ci = cidx[o];
-        const T fr = frac[o];
-        if (col) {
-            scol[l][k] = ci;
-            sfx[l][k] = fr;
-        } else {
-            srow[l][k] = ci * ly[l].n;                              // row offset in the layer
-            sfy[l][k] = fr;
+    // slope weights of this thread's subaperture, requested before anything waits
+    T wxs = 0, wys = 0;
+    {
+        const int e = threadIdx.x;
+        const int ls = e / S1, lt = e - ls * S1;
+        const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
+        if (e < S1 * S1 && si >= 0 && si < ns && sj >= 0 && sj < ns) {
+            wxs = w[W.soff + si * ns + sj];
+            wys = w[W.soff + ns * ns + si * ns + sj];
         }
+    }
+    // the layers of the sensor's instance and the bilinear cells of the tile's rows and
+    // columns on each: every load is issued before the first LDS store
+    constexpr int PER = (FEWHA_MAX_LAYERS * 2 * E + kDataThreads - 1) / kDataThreads;
+    int32_t ci[PER];
+    T fr[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * kDataThreads;
+        if (e < L * 2 * E) {
+            const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
+            const int node = (col ? j0 : i0) - 1 + kk;
+            const int nn = node < 0 ? 0 : (node > ns ? ns : node);   // clamped: halo nodes outside are unused
+            const size_t o = size_t(W.fwd0) + size_t(l) * 2 * np + col * np + nn;
+            ci[k] = cidx[o];
+            fr[k] = frac[o];
+        }
+    }
+    int32_t ln = 0;
+    int64_t loff = 0;
+    if (threadIdx.x < L) {
+        const LayerDev d = lays[W.l0 + threadIdx.x];
+        ln = d.n;
+        loff = d.off;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * kDataThreads;
+        if (e < L * 2 * E) {
+            const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
+            if (col) {
+                scol[l][kk] = ci[k];
+                sfx[l][kk] = fr[k];
+            } else {
+                srow[l][kk] = ci[k];
+                sfy[l][kk] = fr[k];
+            }
+        }
+    }
+    if (threadIdx.x < L) {
+        sn[threadIdx.x] = ln;
+        soffl[threadIdx.x] = loff;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kLayerGroups * E * E; e += kDataThreads) {
@@ -410,9 +461,9 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
         if (i >= 0 && i <= ns && j >= 0 && j <= ns) {
 #pragma unroll 4
             for (int l = lg; l < L; l += kLayerGroups) {
-                const int n = ly[l].n;
+                const int n = sn[l];
                 const T fy = sfy[l][li], fx = sfx[l][lj];
-                const T* ph = phi + ly[l].off + srow[l][li] + scol[l][lj];
+                const T* ph = phi + soffl[l] + size_t(srow[l][li]) * n + scol[l][lj];
                 const T p00 = ph[0], p01 = ph[1], p10 = ph[n], p11 = ph[n + 1];
                 v += (T(1) - fy) * ((T(1) - fx) * p00 + fx * p01) + fy * ((T(1) - fx) * p10 + fx * p11);
             }
@@ -436,8 +487,8 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
             const T p10 = sphi[(ls + 1) * E + lt], p11 = sphi[(ls + 1) * E + lt + 1];
             const T sx = T(0.5) * ((p01 - p00) + (p11 - p10));
             const T sy = T(0.5) * ((p10 - p00) + (p11 - p01));
-            tx = w[W.soff + si * ns + sj] * sx;
-            ty = w[W.soff + ns * ns + si * ns + sj] * sy;
+            tx = wxs * sx;                                          // e == threadIdx.x (S1^2 <= threads)
+            ty = wys * sy;
         }
         stx[e] = tx;
         sty[e] = ty;
@@ -514,136 +565,82 @@ __global__ void __launch_bounds__(kThreads) k_fwd_slopes(const WfsDev* __restric
     out[e] = w[e] != T(0) ? v : T(0);
 }
 
-// sum_g P_g^T psi_g on a kGT x kGT layer tile, for kGatherGroup sensors at a time:
-//  1. per sensor and tile row (column), the sensor rows i (columns j) whose bilinear cell has
-//     that layer row (column) as a corner, with their weights, listed in LDS in parallel;
-//  2. the rectangle of sensor nodes those lists span is copied to LDS (when it fits);
-//  3. every layer node sums its row-weight x column-weight products over the sensors in order.
-template <typename T>
+// sum_g P_g^T psi_g on a kGT x kGT layer tile.  Along each axis the transpose of the bilinear
+// propagation sends layer row (column) a the sensor rows (columns) of its precomputed record,
+// so a layer node sums w_row(i) w_col(j) psi_g(i, j) over at most RF x RF sensor nodes per
+// sensor.  Every thread reads its own row and column records (shared rows are broadcast
+// within a wavefront) and then its sensor nodes, SU sensors at a time with all loads in
+// flight together; no LDS and no barrier, sensors summed in order.
+template <typename T, int RF, int SU>
 __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restrict__ wfs,
                                                           const LayerDev* __restrict__ lays,
-                                                          const int32_t* __restrict__ tile_layer,
-                                                          const PairDev* __restrict__ pairs,
-                                                          const int32_t* __restrict__ cidx, const T* __restrict__ frac,
-                                                          const int2* __restrict__ rng, const T* __restrict__ psi,
-                                                          T* __restrict__ out) {
-    constexpr int RG = kGatherRegion / sizeof(T);                  // LDS entries for sensor rectangles
-    __shared__ int32_t sidx[kGatherGroup][2][kGT][kRMax];          // sensor row / column index
-    __shared__ T sw[kGatherGroup][2][kGT][kRMax];
-    __shared__ int32_t scnt[kGatherGroup][2][kGT];
-    __shared__ int32_t sbox[kGatherGroup][6];                      // i_lo, i_hi, j_lo, j_hi, lds offset (-1: global), width
-    __shared__ T sreg[RG];
-    const int l = tile_layer[blockIdx.x];
-    const LayerDev d = lays[l];
+                                                          const int2* __restrict__ tiles,
+                                                          const int64_t* __restrict__ recbase,
+                                                          const GatherRec<T>* __restrict__ recs,
+                                                          const T* __restrict__ psi, T* __restrict__ out) {
+    const int2 lt = tiles[blockIdx.x];
+    if (lt.x < 0) return;                                // padding of the die-ordered grid
+    const LayerDev d = lays[lt.x];
     const int n = d.n, tx = (n + kGT - 1) / kGT;
-    const int tile = blockIdx.x - d.gt0;
-    const int a0 = (tile / tx) * kGT, b0 = (tile % tx) * kGT;
-    const int la = threadIdx.x / kGT, lb = threadIdx.x % kGT;
-    const int a = a0 + la, b = b0 + lb;
-    const int G = d.ng, lloc = l - d.l0;                 // sensors of the layer's instance
+    const int a = (lt.y / tx) * kGT + threadIdx.x / kGT, b = (lt.y % tx) * kGT + threadIdx.x % kGT;
+    if (a >= n || b >= n) return;
+    const int G = d.ng;
     const WfsDev* __restrict__ wf = wfs + d.g0;
+    const int64_t* __restrict__ rb = recbase + d.rb0;
     T acc = 0;
-    for (int g0 = 0; g0 < G; g0 += kGatherGroup) {
-        const int ng = G - g0 < kGatherGroup ? G - g0 : kGatherGroup;
-        {   // 1. lists: thread (gl, axis, k); the 16 threads of one (gl, axis) are adjacent lanes
-            const int gl = threadIdx.x / (2 * kGT), q = threadIdx.x - gl * 2 * kGT;
-            const int col = q >= kGT, k = q - col * kGT;
-            int lo = 1 << 30, hi = -1;
-            if (gl < ng) {
-                const int g = g0 + gl;
-                const int node = (col ? b0 : a0) + k;
-                const int np = wf[g].ns + 1;
-                const PairDev P = pairs[wf[g].pair0 + lloc];
-                int cnt = 0;
-                if (node < n) {
-                    const int2 r = rng[P.rng_off + col * n + node];
-                    cnt = r.y < kRMax ? r.y : kRMax;
-                    T fr[kRMax];
-                    int32_t ci[kRMax];
+    for (int g0 = 0; g0 < G; g0 += SU) {
+        // unconditional loads (clamped sensor index, masked counts): no branch joins that
+        // would wait for them, so every record and then every node load is in flight at once
+        int ra[SU], ca[SU], rbs[SU], cbn[SU], np[SU];
+        T wa[SU][RF], wb[SU][RF];
+        const T* ps[SU];
 #pragma unroll
-                    for (int t = 0; t < kRMax; ++t)
-                        if (t < cnt) {
-                            const size_t o = size_t(P.fwd_off) + col * np + r.x + t;
-                            fr[t] = frac[o];
-                            ci[t] = cidx[o];
-                        }
+        for (int u = 0; u < SU; ++u) {
+            const int g = min(g0 + u, G - 1);
+            const bool valid = g0 + u < G;
+            const GatherRec<T>* r = recs + rb[g];
+            const GatherRec<T> rr = r[a];
+            const GatherRec<T> rc = r[n + b];
+            ra[u] = rr.start;
+            ca[u] = valid ? rr.count : 0;
+            rbs[u] = rc.start;
+            cbn[u] = valid ? rc.count : 0;
 #pragma unroll
-                    for (int t = 0; t < kRMax; ++t)
-                        if (t < cnt) {
-                            sw[gl][col][k][t] = ci[t] == node ? T(1) - fr[t] : fr[t];
-                            sidx[gl][col][k][t] = r.x + t;
-                        }
-                    if (cnt > 0) {
-                        lo = r.x;
-                        hi = r.x + cnt - 1;
-                    }
+            for (int t = 0; t < RF; ++t) {   // masks as factors: a select would let the load sink into a branch
+                wa[u][t] = rr.w[t] * T(t < ca[u]);
+                wb[u][t] = rc.w[t] * T(t < cbn[u]);
+            }
+            np[u] = wf[g].ns + 1;
+            ps[u] = psi + wf[g].noff;
+        }
+        T v[SU][RF][RF];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+#pragma unroll
+            for (int r = 0; r < RF; ++r)
+#pragma unroll
+                for (int q = 0; q < RF; ++q) {
+                    const bool ok = r < ca[u] && q < cbn[u];
+                    v[u][r][q] = ps[u][ok ? (ra[u] + r) * np[u] + rbs[u] + q : 0];
                 }
-                scnt[gl][col][k] = cnt;
-            }
 #pragma unroll
-            for (int o = 1; o < kGT; o <<= 1) {
-                lo = min(lo, __shfl_xor(lo, o, kGT));
-                hi = max(hi, __shfl_xor(hi, o, kGT));
+        for (int u = 0; u < SU; ++u) {
+            T sum = 0;
+#pragma unroll
+            for (int r = 0; r < RF; ++r) {
+                T row = 0;
+#pragma unroll
+                for (int q = 0; q < RF; ++q) row += wb[u][q] * v[u][r][q];
+                sum += wa[u][r] * row;
             }
-            if (gl < ng && k == 0) {
-                sbox[gl][2 * col] = lo;
-                sbox[gl][2 * col + 1] = hi;
-            }
+            acc += sum;
         }
-        __syncthreads();
-        if (threadIdx.x < ng) {   // rectangle of sensor gl in its fixed share of the LDS region
-            const int gl = threadIdx.x;
-            const int h = sbox[gl][1] - sbox[gl][0] + 1, w = sbox[gl][3] - sbox[gl][2] + 1;
-            const int share = RG / kGatherGroup;
-            sbox[gl][5] = w;
-            sbox[gl][4] = (h > 0 && w > 0 && h * w <= share) ? gl * share : -1;
-        }
-        __syncthreads();
-        {   // 2. rectangles: flat index over the sensors' fixed shares
-            constexpr int share = RG / kGatherGroup;
-            stage_to_lds<kThreads, (RG + kThreads - 1) / kThreads, T>(
-                ng * share,
-                [&](int f) -> T {
-                    const int gl = f / share, e = f - gl * share;
-                    const int w = sbox[gl][5], h = sbox[gl][1] - sbox[gl][0] + 1;
-                    if (sbox[gl][4] < 0 || e >= h * w) return T(0);
-                    const int ii = e / w, jj = e - ii * w;
-                    return psi[wf[g0 + gl].noff + (sbox[gl][0] + ii) * (wf[g0 + gl].ns + 1) + sbox[gl][2] + jj];
-                },
-                [&](int f, T v) { sreg[f] = v; });
-        }
-        __syncthreads();
-        if (a < n && b < n) {   // 3. sums
-            for (int gl = 0; gl < ng; ++gl) {
-                const int ca = scnt[gl][0][la], cb = scnt[gl][1][lb];
-                const int off = sbox[gl][4];
-                if (off >= 0) {
-                    const int i_lo = sbox[gl][0], j_lo = sbox[gl][2], w = sbox[gl][5];
-                    for (int r = 0; r < ca; ++r) {
-                        const int rowoff = off + (sidx[gl][0][la][r] - i_lo) * w;
-                        T sum = 0;
-                        for (int q = 0; q < cb; ++q) sum += sw[gl][1][lb][q] * sreg[rowoff + sidx[gl][1][lb][q] - j_lo];
-                        acc += sw[gl][0][la][r] * sum;
-                    }
-                } else {
-                    const int np = wf[g0 + gl].ns + 1;
-                    const T* ps = psi + wf[g0 + gl].noff;
-                    for (int r = 0; r < ca; ++r) {
-                        const T* row = ps + sidx[gl][0][la][r] * np;
-                        T sum = 0;
-                        for (int q = 0; q < cb; ++q) sum += sw[gl][1][lb][q] * row[sidx[gl][1][lb][q]];
-                        acc += sw[gl][0][la][r] * sum;
-                    }
-                }
-            }
-        }
-        __syncthreads();
     }
-    if (a < n && b < n) out[d.off + size_t(a) * n + b] = acc;
+    out[d.off + size_t(a) * n + b] = acc;
 }
 
 // The same sum for configurations whose contribution lists exceed kRMax (layer grids much
-// coarser than the sensor grids): every node walks its ranges directly.
+// coarser than the sensor grids): every node walks its ranges and the bilinear cells.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_adj_gather_wide(const WfsDev* __restrict__ wfs,
                                                                const LayerDev* __restrict__ lays,
@@ -780,7 +777,7 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, const T* xd
 template <typename T>
 void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s) {
     ProfScope ps_(c, KID_DATA_TERM, s);
-    k_data_term<T><<<c.fwd_tiles, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int32_t>(c.lay.data_tiles),
+    k_data_term<T><<<c.data_grid, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles),
                                                         c.at<LayerDev>(c.lay.layers), c.at<PairDev>(c.lay.pairs),
                                                         c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), phi,
                                                         c.at<T>(c.lay.weight), psi_nodes);
@@ -797,10 +794,17 @@ template <typename T>
 void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s) {
     ProfScope ps_(c, KID_ADJ_GATHER, s);
     if (c.max_rng <= kRMax) {
-        k_adj_gather<T><<<c.gather_tiles, kThreads, 0, s>>>(
-            c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers), c.at<int32_t>(c.lay.gather_tiles),
-            c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), c.at<int2>(c.lay.ranges),
-            psi_nodes, psi_layers);
+        auto go = [&](auto kern) {
+            kern<<<c.gather_grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
+                                                   c.at<int2>(c.lay.gather_tiles), c.at<int64_t>(c.lay.recbase),
+                                                   c.at<GatherRec<T>>(c.lay.grecs), psi_nodes, psi_layers);
+        };
+        if (c.max_rng <= 2)
+            go(k_adj_gather<T, 2, 4>);
+        else if (c.max_rng <= 3)
+            go(k_adj_gather<T, 3, 2>);
+        else
+            go(k_adj_gather<T, kRMax, 1>);
     } else {
         const dim3 grid(cdiv(int64_t(c.max_n) * c.max_n, kThreads), c.L);
         k_adj_gather_wide<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),

@@ -5,8 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "fewha_internal.h"
@@ -16,6 +18,20 @@ namespace fewha {
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Workgroup table that gives die x (workgroups x, x + kXcds, ...) the x-th contiguous share of
+// `items`, so that neighbouring tiles share one die's L2; padding entries are (-1, 0).
+std::vector<int2> die_order(const std::vector<int2>& items) {
+    const int T = int(items.size()), grid = round_up(std::max(T, 1), kXcds), per = grid / kXcds;
+    std::vector<int2> out(grid, make_int2(-1, 0));
+    for (int b = 0; b < grid; ++b) {
+        const int e = (b % kXcds) * per + b / kXcds;
+        if (e < T) out[b] = items[e];
+    }
+    return out;
+}
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -121,7 +137,7 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
 // Derived sizes of one instance and of the batch (identical for validation, layout and setup).
 struct Sizes {
     int B = 0, L = 0, G = 0, slots = 0, esz = 8, KE = 1;
-    int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;
+    int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;   // pairs: also the record bases
     int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, step_list = 0;
     std::vector<StepInfo> steps;
 };
@@ -237,8 +253,10 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.vecblk = take(sizeof(VecBlk) * z.VB);
     lo.gramblk = take(sizeof(GramBlk) * z.GB);
     lo.step_layers = take(sizeof(int32_t) * std::max(1, z.step_list));
-    lo.data_tiles = take(sizeof(int32_t) * z.data_tiles);
-    lo.gather_tiles = take(sizeof(int32_t) * z.gather_tiles);
+    lo.data_tiles = take(sizeof(int2) * round_up(z.data_tiles, kXcds));
+    lo.gather_tiles = take(sizeof(int2) * round_up(z.gather_tiles, kXcds));
+    lo.grecs = take((z.esz == 8 ? sizeof(GatherRec<double>) : sizeof(GatherRec<float>)) * z.ranges);
+    lo.recbase = take(sizeof(int64_t) * std::max<int64_t>(1, z.pairs));
     lo.weight = take(e * S);
     lo.prior_a = take(e * N);
     lo.jinv = take(e * N);
@@ -394,7 +412,7 @@ fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, 
         d.ng = G;
         d.pq0 = pqoff;
         d.pq_coarse = layer_pq(d.n, d.levels, cb) - 1;
-        d.gt0 = gtoff;
+        d.rb0 = 0;                                   // set once every pair exists (build_tables)
         const int tx = (d.n + kGT - 1) / kGT;
         gtoff += tx * tx;
         pqoff += d.pq_coarse + 1;
@@ -416,6 +434,7 @@ fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, 
         w.l0 = l0;
         w.nl = L;
         w.pair0 = int(t.pd.size());
+        w.fwd0 = int64_t(t.cidx.size());
         toff += w.tiles_x * w.tiles_x;
         soff += 2 * int64_t(ns) * ns;
         noff += int64_t(ns + 1) * (ns + 1);
@@ -460,7 +479,7 @@ fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, 
             t.pd.push_back(p);
         }
     }
-    // prior and exact Jacobi preconditioner J^-1 = 1 / diag(M) (Sec. 4)
+    // prior (Sec. 3); the preconditioner follows for all instances at once (jacobi_of)
     const int64_t Ni = off - off0;
     const size_t base = t.D.size();
     t.D.resize(base + Ni);
@@ -470,22 +489,30 @@ fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, 
         std::memcpy(D, cfg->prior_diag, sizeof(double) * Ni);
     else
         prior_of(cfg, &t.ld[l0], D);
-    if (cfg->precond_inv) {
-        std::memcpy(t.Jinv.data() + base, cfg->precond_inv, sizeof(double) * Ni);
-    } else {
-        std::vector<double> diag(Ni, 0.0);
-        data_diag_of(cfg, &t.ld[l0], [&](int g, int l) -> const PairDev& { return t.pd[t.wd[g0 + g].pair0 + l]; },
-                     t.cidx, t.cfrac, diag.data());
-        for (int64_t i = 0; i < Ni; ++i) {
-            const double d = diag[i] + cfg->alpha * D[i];
-            if (!(d > 0) || !std::isfinite(d)) {
-                err = "diag(M) is not positive at index " + std::to_string(i);
-                return FEWHA_E_NOT_SPD;
-            }
-            t.Jinv[base + i] = 1.0 / d;
+    if (cfg->precond_inv) std::memcpy(t.Jinv.data() + base, cfg->precond_inv, sizeof(double) * Ni);
+    return FEWHA_OK;
+}
+
+// Exact Jacobi preconditioner J^-1 = 1 / diag(M) (Sec. 4) of instance i, whose coefficients
+// start at `base` of the concatenation and whose first layer / sensor are l0 / g0.
+fewha_status jacobi_of(Tables& t, const fewha_config* cfg, size_t base, int l0, int g0, std::string& err) {
+    const int64_t Ni = [&] {
+        int64_t n = 0;
+        for (int l = 0; l < cfg->n_layers; ++l) n += int64_t(cfg->layers[l].n) * cfg->layers[l].n;
+        return n;
+    }();
+    std::vector<double> diag(Ni, 0.0);
+    data_diag_of(cfg, &t.ld[l0], [&](int g, int l) -> const PairDev& { return t.pd[t.wd[g0 + g].pair0 + l]; },
+                 t.cidx, t.cfrac, diag.data());
+    const double* D = t.D.data() + base;
+    for (int64_t i = 0; i < Ni; ++i) {
+        const double d = diag[i] + cfg->alpha * D[i];
+        if (!(d > 0) || !std::isfinite(d)) {
+            err = "diag(M) is not positive at index " + std::to_string(i);
+            return FEWHA_E_NOT_SPD;
         }
+        t.Jinv[base + i] = 1.0 / d;
     }
-    for (int64_t i = 0; i < Ni; ++i) t.D[base + i] *= cfg->alpha;   // the device keeps alpha D
     return FEWHA_OK;
 }
 
@@ -505,8 +532,8 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     ctx.GB = z.GB;
     ctx.npq = z.NPQ;
     ctx.slots = z.slots;
-    ctx.fwd_tiles = z.data_tiles;
-    ctx.gather_tiles = z.gather_tiles;
+    ctx.data_grid = round_up(std::max(z.data_tiles, 1), kXcds);
+    ctx.gather_grid = round_up(std::max(z.gather_tiles, 1), kXcds);
     ctx.steps = z.steps;
     ctx.block_elems = block_elems(&cfgs[0]);
 
@@ -517,9 +544,12 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     ctx.s_offs.assign(nb + 1, 0);
     std::vector<VecBlk> vb;
     std::vector<GramBlk> gb;
+    std::vector<int> l0s(nb), g0s(nb);
     for (int i = 0; i < nb; ++i) {
         const int64_t off0 = off;
         const int pq0 = pqoff;
+        l0s[i] = int(t.ld.size());
+        g0s[i] = int(t.wd.size());
         const fewha_status st = add_instance(t, &cfgs[i], i, cb, off, soff, noff, toff, gtoff, pqoff, ctx.err);
         if (st != FEWHA_OK) {
             if (nb > 1) ctx.err = "instance " + std::to_string(i) + ": " + ctx.err;
@@ -540,6 +570,32 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
             gb.push_back(GramBlk{I.off, int32_t(I.n), k, I.ngb, i, I.gb0 * z.KE, 0});
         ctx.s_offs[i + 1] = soff;
     }
+    {   // exact Jacobi preconditioners, instances in parallel (a bounded pool of host threads)
+        std::vector<int> todo;
+        for (int i = 0; i < nb; ++i)
+            if (!cfgs[i].precond_inv) todo.push_back(i);
+        const int nthreads = int(std::min<size_t>(todo.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency()))));
+        std::vector<fewha_status> sts(nb, FEWHA_OK);
+        std::vector<std::string> errs(nb);
+        std::atomic<size_t> next{0};
+        auto work = [&] {
+            for (size_t k = next++; k < todo.size(); k = next++) {
+                const int i = todo[k];
+                sts[i] = jacobi_of(t, &cfgs[i], size_t(ctx.insts[i].off), l0s[i], g0s[i], errs[i]);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int k = 1; k < nthreads; ++k) pool.emplace_back(work);
+        work();
+        for (auto& th : pool) th.join();
+        for (int i = 0; i < nb; ++i)
+            if (sts[i] != FEWHA_OK) {
+                ctx.err = (nb > 1 ? "instance " + std::to_string(i) + ": " : std::string()) + errs[i];
+                return sts[i];
+            }
+        for (int i = 0; i < nb; ++i)   // the device keeps alpha D
+            for (int64_t j = 0; j < ctx.insts[i].n; ++j) t.D[ctx.insts[i].off + j] *= cfgs[i].alpha;
+    }
     for (const LayerDev& d : t.ld) {
         ctx.max_levels = std::max(ctx.max_levels, int(d.levels));
         ctx.max_n = std::max(ctx.max_n, int(d.n));
@@ -554,13 +610,54 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
         for (int l = 0; l < z.L; ++l)
             if (t.ld[l].n >= st.nb && ilog2(t.ld[l].n / st.nb) + 1 <= t.ld[l].levels) sl.push_back(l);
     if (sl.empty()) sl.push_back(0);
-    std::vector<int32_t> dtiles, gtiles;
+    std::vector<int2> dt_items, gt_items;
     for (int g = 0; g < z.G; ++g)
-        for (int k = 0; k < t.wd[g].tiles_x * t.wd[g].tiles_x; ++k) dtiles.push_back(g);
+        for (int k = 0; k < t.wd[g].tiles_x * t.wd[g].tiles_x; ++k) dt_items.push_back(make_int2(g, k));
     for (int l = 0; l < z.L; ++l) {
         const int tx = (t.ld[l].n + kGT - 1) / kGT;
-        for (int k = 0; k < tx * tx; ++k) gtiles.push_back(l);
+        for (int k = 0; k < tx * tx; ++k) gt_items.push_back(make_int2(l, k));
     }
+    const std::vector<int2> dtiles = die_order(dt_items), gtiles = die_order(gt_items);
+    // record bases of every (layer, sensor of its instance) pair
+    std::vector<int64_t> recbase;
+    for (int l = 0; l < z.L; ++l) {
+        LayerDev& d = t.ld[l];
+        d.rb0 = int32_t(recbase.size());
+        for (int j = 0; j < d.ng; ++j) recbase.push_back(t.pd[t.wd[d.g0 + j].pair0 + (l - d.l0)].rng_off);
+    }
+    // gather records: per pair, layer rows then columns, parallel to the ranges
+    std::vector<char> recs;
+    auto build_recs = [&](auto tag) {
+        using R = GatherRec<decltype(tag)>;
+        std::vector<R> out(t.rng.size() / 2);
+        for (int g = 0; g < z.G; ++g) {
+            const WfsDev& w = t.wd[g];
+            const int np = w.ns + 1;
+            for (int j = 0; j < w.nl; ++j) {
+                const PairDev& p = t.pd[w.pair0 + j];
+                const int n = t.ld[w.l0 + j].n;
+                for (int axis = 0; axis < 2; ++axis)
+                    for (int a = 0; a < n; ++a) {
+                        const size_t ri = size_t(p.rng_off) + size_t(axis) * n + a;
+                        R r{};
+                        r.start = t.rng[2 * ri];
+                        r.count = t.rng[2 * ri + 1];
+                        for (int q = 0; q < std::min(r.count, kRMax); ++q) {
+                            const size_t ci = size_t(p.fwd_off) + size_t(axis) * np + r.start + q;
+                            const double f = t.cfrac[ci];
+                            r.w[q] = decltype(tag)(t.cidx[ci] == a ? 1.0 - f : f);
+                        }
+                        out[ri] = r;
+                    }
+            }
+        }
+        recs.resize(out.size() * sizeof(R));
+        std::memcpy(recs.data(), out.data(), recs.size());
+    };
+    if (f32)
+        build_recs(float{});
+    else
+        build_recs(double{});
 
     // ---- upload (typed copies of the floating tables)
     const Layout& lo = ctx.lay;
@@ -591,8 +688,10 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
               up(lo.vecblk, vb.data(), sizeof(VecBlk) * vb.size()) &&
               up(lo.gramblk, gb.data(), sizeof(GramBlk) * gb.size()) &&
               up(lo.step_layers, sl.data(), sizeof(int32_t) * sl.size()) &&
-              up(lo.data_tiles, dtiles.data(), sizeof(int32_t) * dtiles.size()) &&
-              up(lo.gather_tiles, gtiles.data(), sizeof(int32_t) * gtiles.size()) &&
+              up(lo.data_tiles, dtiles.data(), sizeof(int2) * dtiles.size()) &&
+              up(lo.gather_tiles, gtiles.data(), sizeof(int2) * gtiles.size()) &&
+              up(lo.grecs, recs.data(), recs.size()) &&
+              up(lo.recbase, recbase.data(), sizeof(int64_t) * recbase.size()) &&
               up(lo.weight, w_t.data(), w_t.size()) && up(lo.prior_a, pa_t.data(), pa_t.size()) &&
               up(lo.jinv, j_t.data(), j_t.size());
     if (ok) ok = hipStreamSynchronize(stream) == hipSuccess;   // host vectors die at return
