@@ -187,7 +187,7 @@ fewha_status fewha_apply_piece(fewha_ctx* ctx, int32_t piece, const void* d_in, 
         switch (piece) {
             case FEWHA_PIECE_WINV: fewha::launch_winv<T>(c, in, out, s); break;
             case FEWHA_PIECE_WINVT:
-                fewha::launch_winvt<T>(c, in, out, static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), nullptr, s);
+                fewha::launch_winvt<T>(c, in, out, static_cast<const T*>(nullptr), nullptr, s);
                 break;
             case FEWHA_PIECE_A: fewha::launch_fwd_slopes<T>(c, in, out, s); break;
             case FEWHA_PIECE_AT:

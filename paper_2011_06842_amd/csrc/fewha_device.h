@@ -37,12 +37,22 @@ __device__ __forceinline__ void block_partials(const double (&v)[NV], double* __
     __syncthreads();
 }
 
-// Fixed-order sum of `count` consecutive doubles by a whole block (every thread gets it).
+// Fixed-order sum of `count` (>= 1) consecutive doubles by a whole block (every thread gets
+// it).  Four unconditional loads per step (clamped index, zeroed by a factor), so that they
+// are in flight together.
 __device__ __forceinline__ double block_sum_array(const double* __restrict__ a, int count) {
     __shared__ double sh[kThreads / 64];
     double v = 0;
-#pragma unroll 4
-    for (int b = threadIdx.x; b < count; b += kThreads) v += a[b];
+    for (int b0 = 0; b0 < count; b0 += 4 * kThreads) {
+        double x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int b = b0 + k * kThreads + threadIdx.x;
+            x[k] = a[b < count ? b : count - 1] * (b < count ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += x[k];
+    }
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -51,15 +61,16 @@ __device__ __forceinline__ double block_sum_array(const double* __restrict__ a, 
     return r;
 }
 
-// Copies `count` values into LDS with NT threads: every load of a thread is issued before its
-// first LDS store, so the global latencies overlap instead of adding up (count <= NT * MAXPER).
+// Copies `count` (>= 1) values into LDS with NT threads: every load of a thread is issued,
+// unconditionally (clamped index), before its first LDS store, so the global latencies overlap
+// instead of adding up (count <= NT * MAXPER).
 template <int NT, int MAXPER, typename T, typename Src, typename Dst>
 __device__ __forceinline__ void stage_to_lds(int count, Src src, Dst dst) {
     T v[MAXPER];
 #pragma unroll
     for (int k = 0; k < MAXPER; ++k) {
         const int e = threadIdx.x + k * NT;
-        if (e < count) v[k] = src(e);
+        v[k] = src(e < count ? e : count - 1);
     }
 #pragma unroll
     for (int k = 0; k < MAXPER; ++k) {

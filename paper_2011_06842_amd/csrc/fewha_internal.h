@@ -27,7 +27,9 @@ template <typename T> struct CoarseBlock { static constexpr int value = 64; };
 inline int coarse_block(int /*precision*/) { return 64; }
 constexpr int kST = 32;             // output tile side of a tiled synthesis step
 constexpr int kAT = 16;             // coefficient tile side (per band) of a tiled analysis step
-constexpr int kGT = 16;             // layer-node tile side of the adjoint gather
+constexpr int kGT = 32;             // layer-node tile columns of the adjoint gather
+constexpr int kGRowStep = kThreads / kGT;        // tile rows per gather thread row (8)
+constexpr int64_t kGatherWide = int64_t(1) << 21;  // from this many coefficients on, 4 rows per gather thread
 constexpr int kRMax = 6;            // contributions per layer row/column held by a gather record
 constexpr int kXcds = 8;            // accelerator complex dies; workgroup i runs on die i mod kXcds
 constexpr int kGramBlocks = 256;    // Gram workgroups of one instance at most
@@ -162,6 +164,7 @@ struct Ctx {
     int block_elems = kDefaultBlockElems;
     int data_grid = 0;         // workgroups of the fused data term (tiles, padded to kXcds)
     int gather_grid = 0;       // workgroups of the gather (layer tiles, padded to kXcds)
+    int gather_rows = 1;       // layer rows per gather thread (tile of 8 gather_rows x kGT nodes)
     std::vector<InstDev> insts;
     std::vector<int64_t> s_offs;   // slope offsets of the instances (B + 1)
     int prec = 0;              // fewha_precision
@@ -208,8 +211,8 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int n, hipStream_t
 
 // Launchers (fewha_kernels.hip)
 template <typename T> void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s);
-template <typename T> void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, const T* xdot,
-                                        double* pq_part, hipStream_t s);
+template <typename T> void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part,
+                                        hipStream_t s);
 template <typename T> void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s);
 template <typename T> void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted, hipStream_t s);
 template <typename T> void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s);

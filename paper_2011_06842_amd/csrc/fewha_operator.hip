@@ -179,18 +179,17 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
 
 // One analysis level of block size nbs on the listed layers: 16x16 coefficients of every band
 // per tile, rows then columns from a 36x36 halo, a_k = sum_t h_t x_{(2k+t) mod nbs}.  Final
-// coefficients are scaled by 1/delta and get + (alpha D)_i xprior_i; the partial of
-// (out, xdot) over them goes to the tile's slot among the layer's partials (tiles of finer
+// coefficients are scaled by 1/delta and (PRIOR) get + (alpha D)_i x_i, and the partial of
+// (x, out) over them goes to the tile's slot among the layer's partials (tiles of finer
 // levels first).  The prior and x operands are requested before the halo so that their
 // latency overlaps it.
-template <typename T>
+template <typename T, bool PRIOR>
 __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restrict__ lays,
                                                         const int32_t* __restrict__ sl, int nbs,
                                                         Filt<T> f, const T* __restrict__ img,
                                                         const T* __restrict__ ll_in, T* __restrict__ ll_out,
                                                         T* __restrict__ out, const T* __restrict__ prior_a,
-                                                        const T* __restrict__ xprior, const T* __restrict__ xdot,
-                                                        double* __restrict__ dotpart) {
+                                                        const T* __restrict__ xprior, double* __restrict__ dotpart) {
     constexpr int W = 2 * kAT + 4;
     __shared__ T R[W][W + 1];
     __shared__ T I[W][2 * kAT + 1];
@@ -208,13 +207,13 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
     const size_t o[4] = {base + size_t(gy) * n + M + gx, base + size_t(M + gy) * n + gx,
                          base + size_t(M + gy) * n + M + gx, base + size_t(gy) * n + gx};
     const int nout = fin_ll ? 4 : 3;
-    T pa[4] = {0, 0, 0, 0}, xp[4] = {0, 0, 0, 0}, xd[4] = {0, 0, 0, 0};
-    for (int k = 0; k < nout; ++k) {
-        if (xprior) {
+    T pa[4] = {0, 0, 0, 0}, xp[4] = {0, 0, 0, 0};
+    if (PRIOR) {   // o[3] (the LL position) is a valid address even when it is not an output
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
             pa[k] = prior_a[o[k]];
             xp[k] = xprior[o[k]];
         }
-        if (xdot) xd[k] = xdot[o[k]];
     }
     const T* src = (lev == 1 ? img : ll_in) + d.off;
     const Taps<T> tp(f);
@@ -246,12 +245,12 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
     double dot = 0;
     for (int k = 0; k < nout; ++k) {
         T val = v[k] * s;
-        if (xprior) val += pa[k] * xp[k];
+        if (PRIOR) val += pa[k] * xp[k];
         out[o[k]] = val;
-        dot += double(val) * double(xd[k]);
+        dot += double(val) * double(xp[k]);   // (x, M x) partial: x is the prior operand
     }
     if (!fin_ll) ll_out[o[3]] = ll;
-    if (dotpart) {
+    if (PRIOR && dotpart) {
         int slot = d.pq0 + tile;
         for (int j = 1; j < lev; ++j) {
             const int mt = (n >> j) / kAT;
@@ -265,12 +264,11 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
 // Levels coarse_lev..levels of one layer in LDS (mirror of k_idwt_coarse).  After the last
 // level the block holds the whole coarse Mallat pyramid; it is written once, each thread
 // owning fixed positions whose prior and x operands it requested at kernel start.
-template <typename T>
+template <typename T, bool PRIOR>
 __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
                                                                 const T* __restrict__ img, const T* __restrict__ ll_in,
                                                                 T* __restrict__ out, const T* __restrict__ prior_a,
                                                                 const T* __restrict__ xprior,
-                                                                const T* __restrict__ xdot,
                                                                 double* __restrict__ dotpart) {
     constexpr int CB = CoarseBlock<T>::value;
     constexpr int PPT = CB * CB / kCoarseThreads;   // positions per thread
@@ -281,18 +279,16 @@ __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* _
     double dot = 0;
     if (levels >= lc) {
         const int nb0 = n >> (lc - 1);
-        T pa[PPT], xp[PPT], xd[PPT];
+        T pa[PPT], xp[PPT];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
+        for (int k = 0; k < PPT; ++k) {   // unconditional (clamped) loads
             const int e = threadIdx.x + k * kCoarseThreads;
-            pa[k] = xp[k] = xd[k] = 0;
-            if (e < nb0 * nb0) {
-                const size_t o = size_t(d.off) + size_t(e / nb0) * n + (e % nb0);
-                if (xprior) {
-                    pa[k] = prior_a[o];
-                    xp[k] = xprior[o];
-                }
-                if (xdot) xd[k] = xdot[o];
+            const int ec = e < nb0 * nb0 ? e : 0;
+            const size_t o = size_t(d.off) + size_t(ec / nb0) * n + (ec % nb0);
+            pa[k] = xp[k] = 0;
+            if (PRIOR) {
+                pa[k] = prior_a[o];
+                xp[k] = xprior[o];
             }
         }
         const T* src = (lc == 1 ? img : ll_in) + d.off;
@@ -338,13 +334,13 @@ __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* _
             if (e < nb0 * nb0) {
                 const int r = e >> lg0, c = e & (nb0 - 1);
                 T val = A[r * CB + c] * s;
-                if (xprior) val += pa[k] * xp[k];
+                if (PRIOR) val += pa[k] * xp[k];
                 out[size_t(d.off) + size_t(r) * n + c] = val;
-                dot += double(val) * double(xd[k]);
+                dot += double(val) * double(xp[k]);
             }
         }
     }
-    if (dotpart) {
+    if (PRIOR && dotpart) {
         __shared__ double sh[kCoarseThreads / 64];
         const double w = wave_sum(dot);
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
@@ -515,11 +511,11 @@ __global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restric
     const int ns = W.ns, np = ns + 1;
     const int loc = int(e - W.noff);
     const int i = loc / np, j = loc % np;
-    auto t = [&](int comp, int si, int sj) -> T {
-        if (si < 0 || si >= ns || sj < 0 || sj >= ns) return T(0);
-        const int64_t o = W.soff + int64_t(comp) * ns * ns + si * ns + sj;
-        const T ww = w[o];
-        return weighted ? ww * s[o] : (ww != T(0) ? s[o] : T(0));
+    auto t = [&](int comp, int si, int sj) -> T {   // unconditional loads (clamped), zeroed by a factor
+        const bool ok = si >= 0 && si < ns && sj >= 0 && sj < ns;
+        const int64_t o = W.soff + int64_t(comp) * ns * ns + (ok ? si * ns + sj : 0);
+        const T ww = w[o], sv = s[o];
+        return (weighted ? ww * sv : sv * T(ww != T(0))) * T(ok);
     };
     psi[e] = T(0.5) * ((t(0, i, j - 1) - t(0, i, j)) + (t(0, i - 1, j - 1) - t(0, i - 1, j))) +
              T(0.5) * ((t(1, i - 1, j) - t(1, i, j)) + (t(1, i - 1, j - 1) - t(1, i, j - 1)));
@@ -565,78 +561,108 @@ __global__ void __launch_bounds__(kThreads) k_fwd_slopes(const WfsDev* __restric
     out[e] = w[e] != T(0) ? v : T(0);
 }
 
-// sum_g P_g^T psi_g on a kGT x kGT layer tile.  Along each axis the transpose of the bilinear
-// propagation sends layer row (column) a the sensor rows (columns) of its precomputed record,
-// so a layer node sums w_row(i) w_col(j) psi_g(i, j) over at most RF x RF sensor nodes per
-// sensor.  Every thread reads its own row and column records (shared rows are broadcast
-// within a wavefront) and then its sensor nodes, SU sensors at a time with all loads in
-// flight together; no LDS and no barrier, sensors summed in order.
-template <typename T, int RF, int SU>
+// sum_g P_g^T psi_g on a layer tile of TR = 8 NRW rows x kGT columns.  Along each axis the
+// transpose of the bilinear propagation sends layer row (column) a the sensor rows (columns)
+// of its precomputed record, so a layer node sums w_row(i) w_col(j) psi_g(i, j) over at most
+// RF x RF sensor nodes per sensor.  The records of the tile's rows and columns are staged in
+// LDS (kGatherGroup sensors at a time, all loads issued before the first store); every thread
+// then owns NRW nodes of one column and reads their sensor nodes directly (L1/L2), sensors
+// summed in order.
+template <typename T, int RF, int NRW>
 __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restrict__ wfs,
                                                           const LayerDev* __restrict__ lays,
                                                           const int2* __restrict__ tiles,
                                                           const int64_t* __restrict__ recbase,
                                                           const GatherRec<T>* __restrict__ recs,
                                                           const T* __restrict__ psi, T* __restrict__ out) {
+    constexpr int TR = kGRowStep * NRW;
+    constexpr int NR = TR + kGT;                         // records per sensor: tile rows, then columns
+    constexpr int PER = (kGatherGroup * NR + kThreads - 1) / kThreads;
+    __shared__ int32_t s_start[kGatherGroup][NR], s_cnt[kGatherGroup][NR];
+    __shared__ T s_w[kGatherGroup][NR][RF];
     const int2 lt = tiles[blockIdx.x];
     if (lt.x < 0) return;                                // padding of the die-ordered grid
     const LayerDev d = lays[lt.x];
     const int n = d.n, tx = (n + kGT - 1) / kGT;
-    const int a = (lt.y / tx) * kGT + threadIdx.x / kGT, b = (lt.y % tx) * kGT + threadIdx.x % kGT;
-    if (a >= n || b >= n) return;
+    const int a0 = (lt.y / tx) * TR, b0 = (lt.y % tx) * kGT;
+    const int la = threadIdx.x / kGT, lb = threadIdx.x % kGT;
+    const int b = b0 + lb;
     const int G = d.ng;
     const WfsDev* __restrict__ wf = wfs + d.g0;
     const int64_t* __restrict__ rb = recbase + d.rb0;
-    T acc = 0;
-    for (int g0 = 0; g0 < G; g0 += SU) {
-        // unconditional loads (clamped sensor index, masked counts): no branch joins that
-        // would wait for them, so every record and then every node load is in flight at once
-        int ra[SU], ca[SU], rbs[SU], cbn[SU], np[SU];
-        T wa[SU][RF], wb[SU][RF];
-        const T* ps[SU];
+    T acc[NRW];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int g = min(g0 + u, G - 1);
-            const bool valid = g0 + u < G;
-            const GatherRec<T>* r = recs + rb[g];
-            const GatherRec<T> rr = r[a];
-            const GatherRec<T> rc = r[n + b];
-            ra[u] = rr.start;
-            ca[u] = valid ? rr.count : 0;
-            rbs[u] = rc.start;
-            cbn[u] = valid ? rc.count : 0;
+    for (int k = 0; k < NRW; ++k) acc[k] = 0;
+    for (int g0 = 0; g0 < G; g0 += kGatherGroup) {
+        const int ng = G - g0 < kGatherGroup ? G - g0 : kGatherGroup;
+        {   // records of (sensor g0 + gl, tile row / column e)
+            GatherRec<T> r[PER];
 #pragma unroll
-            for (int t = 0; t < RF; ++t) {   // masks as factors: a select would let the load sink into a branch
-                wa[u][t] = rr.w[t] * T(t < ca[u]);
-                wb[u][t] = rc.w[t] * T(t < cbn[u]);
+            for (int k = 0; k < PER; ++k) {
+                const int f = threadIdx.x + k * kThreads, gl = f / NR, e = f - gl * NR;
+                const int node = e < TR ? a0 + e : b0 + e - TR;
+                r[k].count = 0;
+                if (gl < ng && node < n) r[k] = recs[rb[g0 + gl] + (e < TR ? 0 : n) + node];
             }
-            np[u] = wf[g].ns + 1;
-            ps[u] = psi + wf[g].noff;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int f = threadIdx.x + k * kThreads, gl = f / NR, e = f - gl * NR;
+                if (gl < ng) {
+                    s_start[gl][e] = r[k].count > 0 ? r[k].start : 0;
+                    s_cnt[gl][e] = r[k].count;
+#pragma unroll
+                    for (int t = 0; t < RF; ++t) s_w[gl][e][t] = r[k].w[t] * T(t < r[k].count);
+                }
+            }
         }
-        T v[SU][RF][RF];
+        __syncthreads();
+        if (b < n) {
+            constexpr int GU = RF * RF * NRW <= 16 ? 2 : 1;      // sensors whose loads are in flight together
+#pragma unroll GU
+            for (int gl = 0; gl < ng; ++gl) {
+                const int np = wf[g0 + gl].ns + 1;
+                const T* __restrict__ ps = psi + wf[g0 + gl].noff;
+                const int jc = s_start[gl][TR + lb], cc = s_cnt[gl][TR + lb];
+                T wc[RF];
 #pragma unroll
-        for (int u = 0; u < SU; ++u)
+                for (int q = 0; q < RF; ++q) wc[q] = s_w[gl][TR + lb][q];
+                T v[NRW][RF][RF];
 #pragma unroll
-            for (int r = 0; r < RF; ++r)
+                for (int k = 0; k < NRW; ++k) {
+                    const int e = la + k * kGRowStep;
+                    const int ir = s_start[gl][e], cr = s_cnt[gl][e];
 #pragma unroll
-                for (int q = 0; q < RF; ++q) {
-                    const bool ok = r < ca[u] && q < cbn[u];
-                    v[u][r][q] = ps[u][ok ? (ra[u] + r) * np[u] + rbs[u] + q : 0];
+                    for (int r = 0; r < RF; ++r)
+#pragma unroll
+                        for (int q = 0; q < RF; ++q) {
+                            const bool ok = r < cr && q < cc;    // masked entries read node 0 (weight 0)
+                            v[k][r][q] = ps[ok ? (ir + r) * np + jc + q : 0];
+                        }
                 }
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            T sum = 0;
+                for (int k = 0; k < NRW; ++k) {
+                    const int e = la + k * kGRowStep;
+                    T sum = 0;
 #pragma unroll
-            for (int r = 0; r < RF; ++r) {
-                T row = 0;
+                    for (int r = 0; r < RF; ++r) {
+                        T row = 0;
 #pragma unroll
-                for (int q = 0; q < RF; ++q) row += wb[u][q] * v[u][r][q];
-                sum += wa[u][r] * row;
+                        for (int q = 0; q < RF; ++q) row += wc[q] * v[k][r][q];
+                        sum += s_w[gl][e][r] * row;
+                    }
+                    acc[k] += sum;
+                }
             }
-            acc += sum;
+        }
+        __syncthreads();
+    }
+    if (b < n) {
+#pragma unroll
+        for (int k = 0; k < NRW; ++k) {
+            const int a = a0 + la + k * kGRowStep;
+            if (a < n) out[d.off + size_t(a) * n + b] = acc[k];
         }
     }
-    out[d.off + size_t(a) * n + b] = acc;
 }
 
 // The same sum for configurations whose contribution lists exceed kRMax (layer grids much
@@ -755,8 +781,7 @@ void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
 }
 
 template <typename T>
-void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, const T* xdot, double* pq_part,
-                  hipStream_t s) {
+void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part, hipStream_t s) {
     const Filt<T> f = make_filt<T>();
     T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
@@ -767,11 +792,18 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, const T* xd
         const StepInfo& w = c.steps[J - 1 - j];
         const int tiles = (w.nb / 2 / kAT) * (w.nb / 2 / kAT);
         ProfScope ps_(c, KID_DWT_STEP, s);
-        k_dwt_step<T><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y,
-                                                        pa, xprior, xdot, pq_part);
+        if (xprior)
+            k_dwt_step<T, true><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1],
+                                                                  buf[j & 1], y, pa, xprior, pq_part);
+        else
+            k_dwt_step<T, false><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1],
+                                                                   buf[j & 1], y, pa, xprior, nullptr);
     }
     ProfScope ps_(c, KID_DWT_COARSE, s);
-    k_dwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, xdot, pq_part);
+    if (xprior)
+        k_dwt_coarse<T, true><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, pq_part);
+    else
+        k_dwt_coarse<T, false><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, nullptr);
 }
 
 template <typename T>
@@ -799,12 +831,13 @@ void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStrea
                                                    c.at<int2>(c.lay.gather_tiles), c.at<int64_t>(c.lay.recbase),
                                                    c.at<GatherRec<T>>(c.lay.grecs), psi_nodes, psi_layers);
         };
+        const bool wide = c.gather_rows > 1;
         if (c.max_rng <= 2)
-            go(k_adj_gather<T, 2, 4>);
+            wide ? go(k_adj_gather<T, 2, 4>) : go(k_adj_gather<T, 2, 1>);
         else if (c.max_rng <= 3)
-            go(k_adj_gather<T, 3, 2>);
+            wide ? go(k_adj_gather<T, 3, 4>) : go(k_adj_gather<T, 3, 1>);
         else
-            go(k_adj_gather<T, kRMax, 1>);
+            wide ? go(k_adj_gather<T, kRMax, 4>) : go(k_adj_gather<T, kRMax, 1>);
     } else {
         const dim3 grid(cdiv(int64_t(c.max_n) * c.max_n, kThreads), c.L);
         k_adj_gather_wide<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
@@ -831,7 +864,7 @@ void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t
     launch_winv<T>(c, x, phi, s);
     launch_data_term<T>(c, phi, psi_n, s);
     launch_adj_gather<T>(c, psi_n, psi_l, s);
-    launch_winvt<T>(c, psi_l, y, x, pq_part ? x : static_cast<const T*>(nullptr), pq_part, s);
+    launch_winvt<T>(c, psi_l, y, x, pq_part, s);
 }
 
 template <typename T>
@@ -840,7 +873,7 @@ void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s) {
     T* psi_l = c.at<T>(c.lay.psi_layers);
     launch_slopes_adj<T>(c, slopes, psi_n, 1, s);
     launch_adj_gather<T>(c, psi_n, psi_l, s);
-    launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), static_cast<const T*>(nullptr), nullptr, s);
+    launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), nullptr, s);
 }
 
 // Launches one operator kernel with the arguments it has inside M x (input: the coefficient
@@ -875,14 +908,15 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
             const StepInfo& w = c.steps[step];
             const int j = J - 1 - step;
-            k_dwt_step<T><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * w.nl, kThreads, 0, s>>>(
+            k_dwt_step<T, true><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * w.nl, kThreads, 0, s>>>(
                 lays, sl + w.loff, w.nb, f, c.at<T>(c.lay.psi_layers), buf[(j + 1) & 1], buf[j & 1], y,
-                c.at<T>(c.lay.prior_a), x, x, c.at<double>(c.lay.pq_part));
+                c.at<T>(c.lay.prior_a), x, c.at<double>(c.lay.pq_part));
             break;
         }
         case KID_DWT_COARSE:
-            k_dwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J - 1) & 1], y,
-                                                           c.at<T>(c.lay.prior_a), x, x, c.at<double>(c.lay.pq_part));
+            k_dwt_coarse<T, true><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J - 1) & 1],
+                                                                 y, c.at<T>(c.lay.prior_a), x,
+                                                                 c.at<double>(c.lay.pq_part));
             break;
         default:
             return hipErrorInvalidValue;
@@ -931,7 +965,7 @@ hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t
 
 #define FEWHA_INSTANTIATE_OP(T)                                                                           \
     template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t);                                  \
-    template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, const T*, double*, hipStream_t);    \
+    template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, double*, hipStream_t);    \
     template void launch_data_term<T>(const Ctx&, const T*, T*, hipStream_t);                             \
     template void launch_slopes_adj<T>(const Ctx&, const T*, T*, int, hipStream_t);                       \
     template void launch_adj_gather<T>(const Ctx&, const T*, T*, hipStream_t);                            \

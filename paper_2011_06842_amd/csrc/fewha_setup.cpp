@@ -138,9 +138,14 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
 struct Sizes {
     int B = 0, L = 0, G = 0, slots = 0, esz = 8, KE = 1;
     int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;   // pairs: also the record bases
-    int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, step_list = 0;
+    int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, step_list = 0, gather_rows = 1;
     std::vector<StepInfo> steps;
 };
+
+int gather_tiles_of(int n, int rows) {
+    const int tr = kGRowStep * rows;
+    return ((n + tr - 1) / tr) * ((n + kGT - 1) / kGT);
+}
 
 int block_elems(const fewha_config* c) { return c->block_elems ? c->block_elems : kDefaultBlockElems; }
 
@@ -173,8 +178,6 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
             const int n = c->layers[l].n;
             Ni += int64_t(n) * n;
             z.NPQ += layer_pq(n, c->layers[l].levels, cb);
-            const int tx = (n + kGT - 1) / kGT;
-            z.gather_tiles += tx * tx;
         }
         for (int g = 0; g < c->n_wfs; ++g) {
             const int ns = c->wfs[g].n_sub;
@@ -194,6 +197,10 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
         z.VB += vec_blocks(Ni, block_elems(c));
         z.GB += gram_blocks(Ni);
     }
+    // adjoint-gather tiles: 8 x kGT nodes for small systems (more workgroups), 32 x kGT beyond
+    z.gather_rows = z.N >= kGatherWide ? 4 : 1;
+    for (int i = 0; i < nb; ++i)
+        for (int l = 0; l < cfgs[i].n_layers; ++l) z.gather_tiles += gather_tiles_of(cfgs[i].layers[l].n, z.gather_rows);
     // tiled wavelet levels: block sizes above the coarse block, with every layer that has them
     for (int nbs = 2 * cb; nbs <= 1024; nbs *= 2) {
         StepInfo st;
@@ -395,7 +402,7 @@ void data_diag_of(const fewha_config* cfg, const LayerDev* ld, PairOf pair, cons
 
 // Appends instance `inst` (configuration cfg) to the concatenated tables.
 fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, int64_t& off, int64_t& soff,
-                          int64_t& noff, int& toff, int& gtoff, int& pqoff, std::string& err) {
+                          int64_t& noff, int& toff, int& pqoff, std::string& err) {
     const int L = cfg->n_layers, G = cfg->n_wfs;
     const int l0 = int(t.ld.size()), g0 = int(t.wd.size());
     const int64_t off0 = off;
@@ -413,8 +420,6 @@ fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, 
         d.pq0 = pqoff;
         d.pq_coarse = layer_pq(d.n, d.levels, cb) - 1;
         d.rb0 = 0;                                   // set once every pair exists (build_tables)
-        const int tx = (d.n + kGT - 1) / kGT;
-        gtoff += tx * tx;
         pqoff += d.pq_coarse + 1;
         off += int64_t(d.n) * d.n;
         t.ld.push_back(d);
@@ -534,12 +539,13 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     ctx.slots = z.slots;
     ctx.data_grid = round_up(std::max(z.data_tiles, 1), kXcds);
     ctx.gather_grid = round_up(std::max(z.gather_tiles, 1), kXcds);
+    ctx.gather_rows = z.gather_rows;
     ctx.steps = z.steps;
     ctx.block_elems = block_elems(&cfgs[0]);
 
     Tables t;
     int64_t off = 0, soff = 0, noff = 0;
-    int toff = 0, gtoff = 0, pqoff = 0;
+    int toff = 0, pqoff = 0;
     ctx.insts.assign(nb, InstDev{});
     ctx.s_offs.assign(nb + 1, 0);
     std::vector<VecBlk> vb;
@@ -550,7 +556,7 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
         const int pq0 = pqoff;
         l0s[i] = int(t.ld.size());
         g0s[i] = int(t.wd.size());
-        const fewha_status st = add_instance(t, &cfgs[i], i, cb, off, soff, noff, toff, gtoff, pqoff, ctx.err);
+        const fewha_status st = add_instance(t, &cfgs[i], i, cb, off, soff, noff, toff, pqoff, ctx.err);
         if (st != FEWHA_OK) {
             if (nb > 1) ctx.err = "instance " + std::to_string(i) + ": " + ctx.err;
             return st;
@@ -613,10 +619,8 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     std::vector<int2> dt_items, gt_items;
     for (int g = 0; g < z.G; ++g)
         for (int k = 0; k < t.wd[g].tiles_x * t.wd[g].tiles_x; ++k) dt_items.push_back(make_int2(g, k));
-    for (int l = 0; l < z.L; ++l) {
-        const int tx = (t.ld[l].n + kGT - 1) / kGT;
-        for (int k = 0; k < tx * tx; ++k) gt_items.push_back(make_int2(l, k));
-    }
+    for (int l = 0; l < z.L; ++l)
+        for (int k = 0; k < gather_tiles_of(t.ld[l].n, z.gather_rows); ++k) gt_items.push_back(make_int2(l, k));
     const std::vector<int2> dtiles = die_order(dt_items), gtiles = die_order(gt_items);
     // record bases of every (layer, sensor of its instance) pair
     std::vector<int64_t> recbase;

@@ -50,13 +50,18 @@ __device__ __forceinline__ void block_row_sums(const double* __restrict__ part, 
     __shared__ double sh[NV][kThreads / 64];
     const int c0 = sg.col - sg.local;
     double v[NV];
+    // every load is unconditional (a clamped index, zeroed by a factor): loads behind
+    // conditions would each be waited for before the next one is issued
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         v[k] = 0;
+        const int kr = k < nrows ? k : 0;
+        const double fk = k < nrows ? 1.0 : 0.0;
 #pragma unroll
         for (int j = 0; j < kVecBlocksMax / kThreads; ++j) {
             const int b = threadIdx.x + j * kThreads;
-            if (k < nrows && b < sg.nb) v[k] += part[size_t(row0 + k) * pstride + c0 + b];
+            const int bc = b < sg.nb ? b : sg.nb - 1;
+            v[k] += part[size_t(row0 + kr) * pstride + c0 + bc] * (b < sg.nb ? fk : 0.0);
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -217,6 +222,22 @@ __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* 
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// Four consecutive elements (16-byte aligned) as doubles times a factor, as vector loads.
+__device__ __forceinline__ void load4(const float* p, double (&v)[4], double f) {
+    const float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = double(x.x) * f;
+    v[1] = double(x.y) * f;
+    v[2] = double(x.z) * f;
+    v[3] = double(x.w) * f;
+}
+__device__ __forceinline__ void load4(const double* p, double (&v)[4], double f) {
+    const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
+    v[0] = x.x * f;
+    v[1] = x.y * f;
+    v[2] = y.x * f;
+    v[3] = y.y * f;
+}
+
 // Gram pass: X_ab = (U_a, Q_b) (a, b < m) and X_{a,m} = (U_a, r), entry e = a (m+1) + b: a
 // dense m x N by N x (m+1) contraction, on the FP64 matrix cores.  Block (x, y) owns the 16x16
 // tile y of X over its share of the elements; each wavefront feeds v_mfma_f64_16x16x4 with
@@ -241,8 +262,11 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, const GramBlk* __r
     const int tb_count = (m + 1 + 15) / 16;
     const int ta = blockIdx.y / tb_count, tb = blockIdx.y - ta * tb_count;
     const int ar = 16 * ta + (lane & 15), bc = 16 * tb + (lane & 15), kq = lane >> 4;
-    const T* pa = ar < m ? U + size_t(sl.s[ar]) * N + g.off : nullptr;
-    const T* pb = bc < m ? Q + size_t(sl.s[bc]) * N + g.off : (bc == m ? r + g.off : nullptr);
+    // rows / columns outside the tile read a valid vector and are zeroed by a factor (loads
+    // behind a condition would each be waited for before the next)
+    const T* pa = U + size_t(sl.s[ar < m ? ar : 0]) * N + g.off;
+    const T* pb = (bc < m ? Q + size_t(sl.s[bc]) * N : r) + g.off;
+    const double ma = ar < m ? 1.0 : 0.0, mb = bc <= m ? 1.0 : 0.0;
     f64x4 c = {0.0, 0.0, 0.0, 0.0};
     constexpr int DEPTH = 4;                       // 16-element chunks whose loads are in flight together
     const int64_t step = int64_t(g.nb) * 4 * 16;
@@ -251,13 +275,11 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, const GramBlk* __r
         double av[DEPTH][4], bv[DEPTH][4];
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d) {
-            const int64_t e0 = base + d * step + 4 * kq;
-            const bool in = base + d * step < n;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                av[d][j] = (in && pa) ? double(pa[e0 + j]) : 0.0;
-                bv[d][j] = (in && pb) ? double(pb[e0 + j]) : 0.0;
-            }
+            const bool in = base + d * step < n;   // uniform over the wavefront
+            const int64_t e0 = (in ? base + d * step : 0) + 4 * kq;
+            const double f = in ? 1.0 : 0.0;
+            load4(pa + e0, av[d], ma * f);
+            load4(pb + e0, bv[d], mb * f);
         }
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d)
@@ -299,9 +321,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
             const int e = e0 + (threadIdx.x >> 3);
             double v[PER];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
+            for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped, zeroed by a factor)
                 const int j = sub * PER + k;
-                v[k] = (e < ne && j < ngb) ? gp[size_t(e) * ngb + j] : 0.0;
+                const bool ok = e < ne && j < ngb;
+                v[k] = gp[ok ? size_t(e) * ngb + j : 0] * (ok ? 1.0 : 0.0);
             }
             double s = 0;
 #pragma unroll
@@ -341,10 +364,11 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, const Ve
                                                               const T* __restrict__ jinv, double* __restrict__ part) {
     const Seg sg = seg_of(vb, N, 0);
     const Scalars* __restrict__ sc = scs + sg.inst;
+    // slots a >= m of the list repeat slot 0 with coefficient 0 (unconditional loads)
     double y[MB], acc[MB];
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
-        y[a] = a < m ? sc->y[a] : 0.0;
+        y[a] = sc->y[a] * (a < m ? 1.0 : 0.0);
         acc[a] = 0;
     }
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
@@ -353,11 +377,9 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, const Ve
         double qv[MB];
 #pragma unroll
         for (int a = 0; a < MB; ++a) {
-            if (a < m) {
-                qv[a] = double(Q[size_t(sl.s[a]) * N + i]);
-                ci += y[a] * double(U[size_t(sl.s[a]) * N + i]);
-                ri -= y[a] * qv[a];
-            }
+            qv[a] = double(Q[size_t(sl.s[a]) * N + i]);
+            ci += y[a] * double(U[size_t(sl.s[a]) * N + i]);
+            ri -= y[a] * qv[a];
         }
         c[i] = T(ci);
         const T rt = T(ri);
@@ -365,8 +387,7 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, const Ve
         const T zt = jinv[i] * rt;
         z[i] = zt;
 #pragma unroll
-        for (int a = 0; a < MB; ++a)
-            if (a < m) acc[a] += qv[a] * double(zt);
+        for (int a = 0; a < MB; ++a) acc[a] += qv[a] * double(zt);
     }
     __shared__ double sh[MB][kThreads / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -427,7 +448,7 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, const VecBlk* 
     }
     double yv[MB1];
 #pragma unroll
-    for (int a = 0; a < MB; ++a) yv[a] = a < m ? y2[a] : 0.0;
+    for (int a = 0; a < MB; ++a) yv[a] = a < m ? y2[a] : 0.0;   // slots a >= m repeat slot 0
     double rz = 0;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
@@ -437,8 +458,7 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, const VecBlk* 
         } else {
             double pi = double(z[i]);
 #pragma unroll
-            for (int a = 0; a < MB; ++a)
-                if (a < m) pi -= yv[a] * double(U[size_t(sl.s[a]) * N + i]);
+            for (int a = 0; a < MB; ++a) pi -= yv[a] * double(U[size_t(sl.s[a]) * N + i]);
             pt = T(pi);
         }
         p[i] = pt;
@@ -500,11 +520,10 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
             const double zd = double(zt);
             acc[1] += rd * zd;
 #pragma unroll
-            for (int a = 0; a < MP; ++a)
-                if (a < mp) {
-                    acc[2 + a] += double(Q[size_t(pl.s[a]) * N + i]) * zd;
-                    acc[2 + MP + a] += double(U[size_t(pl.s[a]) * N + i]) * rd;
-                }
+            for (int a = 0; a < MP; ++a) {   // slots a >= mp repeat slot 0; their sums are unused
+                acc[2 + a] += double(Q[size_t(pl.s[a]) * N + i]) * zd;
+                acc[2 + MP + a] += double(U[size_t(pl.s[a]) * N + i]) * rd;
+            }
         }
     }
     __shared__ double sh[NV][kThreads / 64];
@@ -597,8 +616,7 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
         const int64_t i = sg.off + j;
         double vv = double(z[i]) + beta * double(p[i]);
 #pragma unroll
-        for (int a = 0; a < MP; ++a)
-            if (a < mp) vv -= yr[a] * double(U[size_t(pl.s[a]) * N + i]);
+        for (int a = 0; a < MP; ++a) vv -= yr[a] * double(U[size_t(pl.s[a]) * N + i]);   // yr = 0 beyond mp
         pn[i] = T(vv);
     }
 }
@@ -630,14 +648,22 @@ __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, 
     }
 }
 
+// Compile-time sizes of the recycle-space loops: exact up to 16, then in steps of 4.
 int bucket(int m) {
-    if (m <= 0) return 0;
-    if (m <= 1) return 1;
-    if (m <= 4) return 4;
-    if (m <= 8) return 8;
-    if (m <= 16) return 16;
-    return 32;
+    if (m <= 16) return m < 0 ? 0 : m;
+    return (m + 3) / 4 * 4;
 }
+
+// Slot list padded to `mb` entries by repeating the first (the kernels give the padding
+// coefficient 0, so every ring load is unconditional).
+SlotList padded(const SlotList& sl, int m, int mb) {
+    SlotList p = sl;
+    for (int a = m; a < mb; ++a) p.s[a] = m > 0 ? sl.s[0] : 0;
+    return p;
+}
+
+#define FEWHA_MB_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(20) X(24) X(28) X(32)
 
 // Launch geometry shared by the vector kernels of one context.
 struct VecLaunch {
@@ -717,6 +743,7 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
     // a3 + a4: Galerkin step and initial direction
     T* p0 = U + size_t(c.head) * N;
     const int mb = bucket(m);
+    const SlotList actp = padded(act, m, mb);
     if (m > 0) {
         {
             ProfScope ps_(c, KID_GRAM, s);
@@ -734,22 +761,18 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
         }
         ProfScope ps_(c, KID_GALERKIN, s);
         switch (mb) {
-            case 1: launch_gal<T, 1>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            case 4: launch_gal<T, 4>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            case 8: launch_gal<T, 8>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            case 16: launch_gal<T, 16>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
-            default: launch_gal<T, 32>(vl, m, act, U, Q, sc, cv, r, z, jinv, part, s); break;
+#define X(v) case v: launch_gal<T, v>(vl, m, actp, U, Q, sc, cv, r, z, jinv, part, s); break;
+            FEWHA_MB_CASES(X)
+#undef X
         }
     }
     {
         ProfScope ps_(c, KID_INIT_DIR, s);
         switch (mb) {
-            case 0: launch_init<T, 0>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 1: launch_init<T, 1>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 4: launch_init<T, 4>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 8: launch_init<T, 8>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            case 16: launch_init<T, 16>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
-            default: launch_init<T, 32>(vl, m, c.mode, act, U, sc, z, r, jinv, p0, part, s); break;
+            case 0: launch_init<T, 0>(vl, m, c.mode, actp, U, sc, z, r, jinv, p0, part, s); break;
+#define X(v) case v: launch_init<T, v>(vl, m, c.mode, actp, U, sc, z, r, jinv, p0, part, s); break;
+            FEWHA_MB_CASES(X)
+#undef X
         }
     }
     // in-loop projection set: all of U (project_all) or the most recent recycled direction
@@ -765,6 +788,7 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
         }
     }
     const int mpb = bucket(mp);
+    pl = padded(pl, mp, mpb);
     // a5 + a6: iterations
     for (int it = 0; it < c.max_iter; ++it) {
         const int ps = (c.head + it) % K;
@@ -776,16 +800,10 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
         switch (mpb) {
             case 0: launch_upd<T, 0>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
                                      c.project_all, pn, c, s); break;
-            case 1: launch_upd<T, 1>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
-                                     c.project_all, pn, c, s); break;
-            case 4: launch_upd<T, 4>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
-                                     c.project_all, pn, c, s); break;
-            case 8: launch_upd<T, 8>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
-                                     c.project_all, pn, c, s); break;
-            case 16: launch_upd<T, 16>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
-                                       c.project_all, pn, c, s); break;
-            default: launch_upd<T, 32>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
-                                       c.project_all, pn, c, s); break;
+#define X(v) case v: launch_upd<T, v>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps, \
+                                      c.project_all, pn, c, s); break;
+            FEWHA_MB_CASES(X)
+#undef X
         }
     }
     {
