@@ -104,7 +104,12 @@ typedef struct {
     int32_t recycle_k;           /* recycled directions, 0..FEWHA_MAX_RECYCLE (0 = plain PCG) */
     int32_t recycle_mode;        /* fewha_recycle_mode */
     int32_t project_all;         /* GALERKIN only: project every new direction against all of U */
-    double rel_tol;              /* reserved, must be 0 (fixed iteration count) */
+    double rel_tol;              /* 0: exactly max_iter iterations per frame.  > 0 (< 1): iterate until
+                                    ||r|| <= rel_tol ||b|| (FP64) or max_iter; the instances of a batch
+                                    iterate in lock step until every one has met it, each recording the
+                                    iteration at which it first did (checked every iteration, the stop
+                                    decided every 4 iterations on the host, so a frame synchronises its
+                                    stream and is never captured into a graph) */
     int32_t precision;           /* fewha_precision */
     int32_t block_elems;         /* elements per workgroup of the vector kernels (0 = 384); fixes the
                                     reduction order, so results are reproducible for a given value */
@@ -112,10 +117,12 @@ typedef struct {
 
 /* Written by the device at the end of every fewha_solve_aug. */
 typedef struct {
-    int32_t iters;          /* operator applications in the frame */
+    int32_t iters;          /* operator applications in the frame; with rel_tol > 0, the first
+                               iteration whose residual met the tolerance */
     int32_t recycle_used;   /* recycled directions used for the projections */
     int32_t dropped;        /* Gram columns dropped as numerically dependent */
-    int32_t flags;          /* bit 0: breakdown ((p,q) <= 0 or non-finite scalar) */
+    int32_t flags;          /* bit 0: breakdown ((p,q) <= 0 or non-finite scalar);
+                               bit 1: rel_tol not met within the frame */
     double rel_res;         /* ||r|| / ||b|| at the end of the frame (FP64) */
 } fewha_solve_info;
 
@@ -165,6 +172,9 @@ fewha_status fewha_rhs(fewha_ctx* ctx, const void* d_s, void* d_b, void* stream)
  * fewha_reset runs Alg. 1 from r = b - M c.  d_info (device, may be NULL) receives a
  * fewha_solve_info. */
 fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d_info, void* stream);
+
+/* Iterations (operator applications per instance) of the last fewha_solve_aug. */
+fewha_status fewha_frame_iterations(const fewha_ctx* ctx, int32_t* iters);
 
 /* Drop the recycle store: the next solve runs Alg. 1 from r = b - M c with the carried c. */
 fewha_status fewha_reset(fewha_ctx* ctx);

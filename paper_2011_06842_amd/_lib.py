@@ -22,7 +22,7 @@ STATUS = {0: "FEWHA_OK", 1: "FEWHA_E_INVAL", 2: "FEWHA_E_NOMEM", 3: "FEWHA_E_HIP
           5: "FEWHA_E_BREAKDOWN", 6: "FEWHA_E_STATE"}
 
 EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", "fewha_setup_batch",
-           "fewha_instances", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
+           "fewha_instances", "fewha_frame_iterations", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
            "fewha_solve_aug", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
            "fewha_get_state", "fewha_set_state", "fewha_use_graphs", "fewha_profile", "fewha_profile_read",
            "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error"]
@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH):
         "fewha_workspace_size_batch": ([C.POINTER(fewha_config), C.c_int32, C.POINTER(C.c_size_t)], st),
         "fewha_setup_batch": ([C.POINTER(fewha_config), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)], st),
         "fewha_instances": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)], st),
+        "fewha_frame_iterations": ([vp, C.POINTER(C.c_int32)], st),
         "fewha_sizes": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], st),
         "fewha_apply_A": ([vp, vp, vp, vp], st),
         "fewha_rhs": ([vp, vp, vp, vp], st),
@@ -158,7 +159,7 @@ def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
     cfg.recycle_k = spec.recycle_k
     cfg.recycle_mode = FEWHA_RECYCLE_PAPER if spec.recycle_mode == "paper" else FEWHA_RECYCLE_GALERKIN
     cfg.project_all = int(bool(spec.project_all))
-    cfg.rel_tol = 0.0
+    cfg.rel_tol = float(getattr(spec, "rel_tol", 0.0) or 0.0)
     cfg.precision = FEWHA_FP64 if spec.precision == "fp64" else FEWHA_FP32_OP_FP64_RED
     cfg.block_elems = int(getattr(spec, "block_elems", 0) or 0)
     return cfg
@@ -253,6 +254,11 @@ class FewhaContext:
         ip = _ptr(info) if info is not None else None
         _check(self.lib.fewha_solve_aug(self.ctx, _ptr(s), _ptr(c), ip, _stream(stream)), self.ctx)
         return c
+
+    def fewha_frame_iterations(self) -> int:
+        n = C.c_int32()
+        _check(self.lib.fewha_frame_iterations(self.ctx, C.byref(n)), self.ctx)
+        return n.value
 
     def fewha_reset(self):
         _check(self.lib.fewha_reset(self.ctx), self.ctx)

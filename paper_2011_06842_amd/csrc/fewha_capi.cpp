@@ -85,6 +85,7 @@ fewha_status fewha_setup_batch(const fewha_config* cfgs, int32_t n, void* d_work
     c.k = cfg->recycle_k;
     c.mode = cfg->recycle_mode;
     c.project_all = cfg->project_all;
+    c.rel_tol = cfg->rel_tol;
     c.ws = static_cast<char*>(d_workspace);
     c.ws_bytes = bytes;
     c.lay = lo;
@@ -164,6 +165,12 @@ fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d
                                              as_stream(stream));
     if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("frame launch failed: ") + hipGetErrorString(e));
     return check_launch(ctx, as_stream(stream));
+}
+
+fewha_status fewha_frame_iterations(const fewha_ctx* ctx, int32_t* iters) {
+    if (!ctx || !iters) return FEWHA_E_INVAL;
+    *iters = ctx->c.frame_iters;
+    return FEWHA_OK;
 }
 
 fewha_status fewha_reset(fewha_ctx* ctx) {

@@ -119,6 +119,7 @@ struct Scalars {
     double R[kKMax * kKMax];
     int32_t keep[kKMax];
     int32_t flags, dropped, used, iters;
+    int32_t conv_iter;    // tolerance mode: first iteration whose residual met the tolerance (0: not yet)
 };
 
 // Byte layout of the workspace (offsets from its base).
@@ -128,7 +129,7 @@ struct Layout {
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
     size_t c, r, z, b, b_prev, s_in;
     size_t ring_u, ring_q;
-    size_t partials, pq_part, gram_part, scalars, info;
+    size_t partials, pq_part, gram_part, scalars, info, done;
     size_t total;
     size_t state_bytes;
 };
@@ -171,6 +172,9 @@ struct Ctx {
     size_t esz = 8;            // element size
     double alpha = 0;
     int max_iter = 0, k = 0, mode = 1, project_all = 0;
+    double rel_tol = 0;        // > 0: iterate until every instance meets it (or max_iter)
+    int check_every = 4;       // tolerance mode: iterations between host checks of the done flags
+    int frame_iters = 0;       // iterations of the last frame
     int max_levels = 0, max_n = 0;
     int slots = 0;             // ring capacity k + max_iter
     int max_rng = 0;           // largest gather contribution count of a layer row/column

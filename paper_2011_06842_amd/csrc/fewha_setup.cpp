@@ -108,7 +108,7 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
     if (cfg->max_iter < 1 || cfg->max_iter > 256) { err = "max_iter out of range [1, 256]"; return FEWHA_E_INVAL; }
     if (cfg->recycle_k < 0 || cfg->recycle_k > FEWHA_MAX_RECYCLE) { err = "recycle_k out of range"; return FEWHA_E_INVAL; }
     if (cfg->recycle_mode != FEWHA_RECYCLE_PAPER && cfg->recycle_mode != FEWHA_RECYCLE_GALERKIN) { err = "bad recycle_mode"; return FEWHA_E_INVAL; }
-    if (cfg->rel_tol != 0.0) { err = "rel_tol is reserved and must be 0"; return FEWHA_E_INVAL; }
+    if (!(cfg->rel_tol >= 0.0) || !(cfg->rel_tol < 1.0)) { err = "rel_tol must be in [0, 1)"; return FEWHA_E_INVAL; }
     if (cfg->precision != FEWHA_FP64 && cfg->precision != FEWHA_FP32_OP_FP64_RED) { err = "bad precision"; return FEWHA_E_INVAL; }
     if (cfg->project_all && cfg->recycle_mode != FEWHA_RECYCLE_GALERKIN) { err = "project_all needs GALERKIN mode"; return FEWHA_E_INVAL; }
     if (cfg->block_elems != 0 && (cfg->block_elems < 64 || cfg->block_elems > (1 << 22))) { err = "block_elems must be 0 or in [64, 2^22]"; return FEWHA_E_INVAL; }
@@ -287,6 +287,7 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.gram_part = take(sizeof(double) * size_t(z.GB) * z.KE);
     lo.scalars = take(sizeof(Scalars) * z.B);
     lo.info = take(sizeof(fewha_solve_info) * z.B);
+    lo.done = take(sizeof(int32_t) * z.B);
     lo.total = o;
     lo.state_bytes = 256 + sizeof(double) * size_t(z.B) * z.slots + e * N * (3 + 2 * size_t(z.slots));
     return lo;

@@ -217,6 +217,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* 
         sc->flags = 0;
         sc->used = m;
         sc->dropped = 0;
+        sc->conv_iter = 0;
     }
 }
 
@@ -622,11 +623,13 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
 }
 
 // Frame statistics (relative residual in FP64) of every instance (one workgroup each) into
-// the context's and the caller's info.
+// the context's and the caller's info.  Tolerance mode: iters is the instance's first
+// iteration that met the tolerance (flag bit 1: not met within the frame).
 __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
                                                       int pstride, const double* __restrict__ part,
                                                       fewha_solve_info* __restrict__ infos,
-                                                      fewha_solve_info* __restrict__ infos_user, int iters) {
+                                                      fewha_solve_info* __restrict__ infos_user, int iters,
+                                                      int tol_mode) {
     const InstDev I = insts[blockIdx.x];
     const Seg sg{I.off, int(I.n), 0, I.nvb, int(blockIdx.x), I.vb0, I.pq0, I.npq};
     Scalars* __restrict__ sc = scs + blockIdx.x;
@@ -636,10 +639,10 @@ __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, 
     block_row_sums<2>(part, pstride, sg, P_BB, 2, v);   // rows P_BB, P_RR
     if (threadIdx.x == 0) {
         fewha_solve_info in;
-        in.iters = iters;
+        in.iters = tol_mode && sc->conv_iter ? sc->conv_iter : iters;
         in.recycle_used = sc->used;
         in.dropped = sc->dropped;
-        in.flags = sc->flags;
+        in.flags = sc->flags | (tol_mode && !sc->conv_iter ? 2 : 0);
         in.rel_res = v[0] > 0 ? sqrt(v[1] / v[0]) : 0.0;
         sc->bb = v[0];
         sc->rr = v[1];
@@ -649,6 +652,24 @@ __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, 
 }
 
 // Compile-time sizes of the recycle-space loops: exact up to 16, then in steps of 4.
+// Tolerance check after iteration `it1` (1-based): every instance (one workgroup each) with
+// ||r|| <= tol ||b|| (FP64, from the partials of (r, r) and (b, b)) records it1 the first time
+// and raises its done flag.
+__global__ void __launch_bounds__(kThreads) k_check(Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
+                                                     int pstride, const double* __restrict__ part, int it1,
+                                                     double tol, int32_t* __restrict__ done) {
+    const InstDev I = insts[blockIdx.x];
+    const Seg sg{I.off, int(I.n), 0, I.nvb, int(blockIdx.x), I.vb0, I.pq0, I.npq};
+    double v[2];
+    block_row_sums<2>(part, pstride, sg, P_BB, 2, v);   // rows P_BB, P_RR
+    if (threadIdx.x == 0) {
+        Scalars* sc = scs + blockIdx.x;
+        const bool met = sqrt(v[1]) <= tol * sqrt(v[0]);
+        if (met && sc->conv_iter == 0) sc->conv_iter = it1;
+        done[blockIdx.x] = sc->conv_iter != 0;
+    }
+}
+
 int bucket(int m) {
     if (m <= 16) return m < 0 ? 0 : m;
     return (m + 3) / 4 * 4;
@@ -702,116 +723,173 @@ void launch_upd(const VecLaunch& vl, int it, int mp, const SlotList& pl, const T
 
 }  // namespace
 
-// Enqueues one frame on stream s (no host-state change, so it can be captured).
+// Pointers and recycle sets of one frame (derived from the host-side ring bookkeeping).
 template <typename T>
-void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s) {
-    const int64_t N = c.N;
-    const int K = c.slots;
-    T* b = c.at<T>(c.lay.b);
-    T* bp = c.at<T>(c.lay.b_prev);
-    T* r = c.at<T>(c.lay.r);
-    T* z = c.at<T>(c.lay.z);
-    T* cv = c.at<T>(c.lay.c);
-    T* vx = c.at<T>(c.lay.vx);
-    T* U = c.at<T>(c.lay.ring_u);
-    T* Q = c.at<T>(c.lay.ring_q);
-    const T* jinv = c.at<T>(c.lay.jinv);
-    double* part = c.at<double>(c.lay.partials);
-    double* pqp = c.at<double>(c.lay.pq_part);
-    double* gpart = c.at<double>(c.lay.gram_part);
-    Scalars* sc = c.at<Scalars>(c.lay.scalars);
-    const InstDev* insts = c.at<InstDev>(c.lay.insts);
-    fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
-    const VecLaunch vl{N, c.B > 1 ? c.at<VecBlk>(c.lay.vecblk) : nullptr, c.VB, c.VB};
-    const GramBlk* gt = c.B > 1 ? c.at<GramBlk>(c.lay.gramblk) : nullptr;
-    const int ke = std::max(1, c.k * (c.k + 1));
+struct Frame {
+    int64_t N;
+    int K, m, mb, mp, mpb;
+    SlotList act, actp, pl;
+    T *b, *bp, *r, *z, *cv, *vx, *U, *Q;
+    const T* jinv;
+    double *part, *pqp, *gpart;
+    Scalars* sc;
+    const InstDev* insts;
+    fewha_solve_info* info;
+    VecLaunch vl;
+    const GramBlk* gt;
+    int ke;
 
-    int m = 0;
-    if (!c.first && c.k > 0)
-        m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
-    SlotList act{};
-    for (int j = 0; j < m; ++j) act.s[j] = ((c.head - m + j) % K + K) % K;
+    explicit Frame(const Ctx& c) {
+        N = c.N;
+        K = c.slots;
+        b = c.at<T>(c.lay.b);
+        bp = c.at<T>(c.lay.b_prev);
+        r = c.at<T>(c.lay.r);
+        z = c.at<T>(c.lay.z);
+        cv = c.at<T>(c.lay.c);
+        vx = c.at<T>(c.lay.vx);
+        U = c.at<T>(c.lay.ring_u);
+        Q = c.at<T>(c.lay.ring_q);
+        jinv = c.at<T>(c.lay.jinv);
+        part = c.at<double>(c.lay.partials);
+        pqp = c.at<double>(c.lay.pq_part);
+        gpart = c.at<double>(c.lay.gram_part);
+        sc = c.at<Scalars>(c.lay.scalars);
+        insts = c.at<InstDev>(c.lay.insts);
+        info = c.at<fewha_solve_info>(c.lay.info);
+        vl = VecLaunch{N, c.B > 1 ? c.at<VecBlk>(c.lay.vecblk) : nullptr, c.VB, c.VB};
+        gt = c.B > 1 ? c.at<GramBlk>(c.lay.gramblk) : nullptr;
+        ke = std::max(1, c.k * (c.k + 1));
+        m = 0;
+        if (!c.first && c.k > 0)
+            m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
+        act = SlotList{};
+        for (int j = 0; j < m; ++j) act.s[j] = ((c.head - m + j) % K + K) % K;
+        mb = bucket(m);
+        actp = padded(act, m, mb);
+        // in-loop projection set: all of U (project_all) or the most recent recycled direction
+        pl = SlotList{};
+        mp = 0;
+        if (m > 0) {
+            if (c.project_all) {
+                pl = act;
+                mp = m;
+            } else {
+                pl.s[0] = ((c.head - 1) % K + K) % K;
+                mp = 1;
+            }
+        }
+        mpb = bucket(mp);
+        pl = padded(pl, mp, mpb);
+    }
+};
 
-    // a1: right-hand side
-    launch_rhs<T>(c, slopes, b, s);
-    // a2: residual
-    if (c.first) launch_apply_M<T>(c, cv, vx, nullptr, s);
+// a1 - a4: right-hand side, residual update, Galerkin step and initial direction.
+template <typename T>
+void enqueue_prologue(const Ctx& c, const Frame<T>& f, const T* slopes, hipStream_t s) {
+    const int m = f.m;
+    launch_rhs<T>(c, slopes, f.b, s);
+    if (c.first) launch_apply_M<T>(c, f.cv, f.vx, nullptr, s);
     {
         ProfScope ps_(c, KID_RESIDUAL, s);
-        k_residual<T><<<vl.grid, kThreads, 0, s>>>(N, vl.vb, vl.pstride, b, bp, r, c.first ? vx : nullptr, part, sc, m);
+        k_residual<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.b, f.bp, f.r,
+                                                     c.first ? f.vx : nullptr, f.part, f.sc, m);
     }
-    // a3 + a4: Galerkin step and initial direction
-    T* p0 = U + size_t(c.head) * N;
-    const int mb = bucket(m);
-    const SlotList actp = padded(act, m, mb);
+    T* p0 = f.U + size_t(c.head) * f.N;
     if (m > 0) {
         {
             ProfScope ps_(c, KID_GRAM, s);
             const dim3 grid(c.GB, ((m + 15) / 16) * ((m + 1 + 15) / 16));
-            k_gram<T><<<grid, kThreads, 0, s>>>(N, gt, m, act, U, Q, r, gpart);
+            k_gram<T><<<grid, kThreads, 0, s>>>(f.N, f.gt, m, f.act, f.U, f.Q, f.r, f.gpart);
         }
         {
             ProfScope ps_(c, KID_GRAM_SOLVE, s);
             if (m <= 8)
-                k_gram_solve<8><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, act, sc, insts, ke, gpart);
+                k_gram_solve<8><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart);
             else if (m <= 16)
-                k_gram_solve<16><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, act, sc, insts, ke, gpart);
+                k_gram_solve<16><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart);
             else
-                k_gram_solve<32><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, act, sc, insts, ke, gpart);
+                k_gram_solve<32><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart);
         }
         ProfScope ps_(c, KID_GALERKIN, s);
-        switch (mb) {
-#define X(v) case v: launch_gal<T, v>(vl, m, actp, U, Q, sc, cv, r, z, jinv, part, s); break;
+        switch (f.mb) {
+#define X(v) case v: launch_gal<T, v>(f.vl, m, f.actp, f.U, f.Q, f.sc, f.cv, f.r, f.z, f.jinv, f.part, s); break;
             FEWHA_MB_CASES(X)
 #undef X
         }
     }
-    {
-        ProfScope ps_(c, KID_INIT_DIR, s);
-        switch (mb) {
-            case 0: launch_init<T, 0>(vl, m, c.mode, actp, U, sc, z, r, jinv, p0, part, s); break;
-#define X(v) case v: launch_init<T, v>(vl, m, c.mode, actp, U, sc, z, r, jinv, p0, part, s); break;
-            FEWHA_MB_CASES(X)
+    ProfScope ps_(c, KID_INIT_DIR, s);
+    switch (f.mb) {
+        case 0: launch_init<T, 0>(f.vl, m, c.mode, f.actp, f.U, f.sc, f.z, f.r, f.jinv, p0, f.part, s); break;
+#define X(v) case v: launch_init<T, v>(f.vl, m, c.mode, f.actp, f.U, f.sc, f.z, f.r, f.jinv, p0, f.part, s); break;
+        FEWHA_MB_CASES(X)
 #undef X
-        }
-    }
-    // in-loop projection set: all of U (project_all) or the most recent recycled direction
-    SlotList pl{};
-    int mp = 0;
-    if (m > 0) {
-        if (c.project_all) {
-            pl = act;
-            mp = m;
-        } else {
-            pl.s[0] = ((c.head - 1) % K + K) % K;
-            mp = 1;
-        }
-    }
-    const int mpb = bucket(mp);
-    pl = padded(pl, mp, mpb);
-    // a5 + a6: iterations
-    for (int it = 0; it < c.max_iter; ++it) {
-        const int ps = (c.head + it) % K;
-        T* p = U + size_t(ps) * N;
-        T* q = Q + size_t(ps) * N;
-        T* pn = U + size_t((c.head + it + 1) % K) * N;
-        launch_apply_M<T>(c, p, q, pqp, s);
-        const int last = it == c.max_iter - 1;
-        switch (mpb) {
-            case 0: launch_upd<T, 0>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps,
-                                     c.project_all, pn, c, s); break;
-#define X(v) case v: launch_upd<T, v>(vl, it, mp, pl, U, Q, sc, p, q, cv, r, z, jinv, last, c.npq, pqp, part, ps, \
-                                      c.project_all, pn, c, s); break;
-            FEWHA_MB_CASES(X)
-#undef X
-        }
-    }
-    {
-        ProfScope ps_(c, KID_FINISH, s);
-        k_finish<<<c.B, kThreads, 0, s>>>(sc, insts, vl.pstride, part, info, info_user, c.max_iter);
     }
 }
 
+// a5 + a6: iteration `it` (the last one skips the next direction).
+template <typename T>
+void enqueue_iteration(const Ctx& c, const Frame<T>& f, int it, int last, hipStream_t s) {
+    const int ps = (c.head + it) % f.K;
+    T* p = f.U + size_t(ps) * f.N;
+    T* q = f.Q + size_t(ps) * f.N;
+    T* pn = f.U + size_t((c.head + it + 1) % f.K) * f.N;
+    launch_apply_M<T>(c, p, q, f.pqp, s);
+    switch (f.mpb) {
+        case 0: launch_upd<T, 0>(f.vl, it, f.mp, f.pl, f.U, f.Q, f.sc, p, q, f.cv, f.r, f.z, f.jinv, last, c.npq,
+                                 f.pqp, f.part, ps, c.project_all, pn, c, s); break;
+#define X(v) case v: launch_upd<T, v>(f.vl, it, f.mp, f.pl, f.U, f.Q, f.sc, p, q, f.cv, f.r, f.z, f.jinv, last, \
+                                      c.npq, f.pqp, f.part, ps, c.project_all, pn, c, s); break;
+        FEWHA_MB_CASES(X)
+#undef X
+    }
+}
+
+template <typename T>
+void enqueue_finish(const Ctx& c, const Frame<T>& f, int iters, fewha_solve_info* info_user, hipStream_t s) {
+    ProfScope ps_(c, KID_FINISH, s);
+    k_finish<<<c.B, kThreads, 0, s>>>(f.sc, f.insts, f.vl.pstride, f.part, f.info, info_user, iters,
+                                      c.rel_tol > 0 ? 1 : 0);
+}
+
+// Enqueues one fixed-count frame on stream s (no host-state change, so it can be captured).
+template <typename T>
+void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s) {
+    const Frame<T> f(c);
+    enqueue_prologue<T>(c, f, slopes, s);
+    for (int it = 0; it < c.max_iter; ++it) enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
+    enqueue_finish<T>(c, f, c.max_iter, info_user, s);
+}
+
+// Tolerance mode: the instances iterate in lock step (the recycle ring stays shared); after
+// every iteration each instance records when it first met the tolerance, and every
+// check_every iterations the host reads the done flags and stops once all are set.
+template <typename T>
+hipError_t run_tolerance_frame(Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s, int* iters) {
+    const Frame<T> f(c);
+    int32_t* done = c.at<int32_t>(c.lay.done);
+    std::vector<int32_t> hdone(c.B);
+    enqueue_prologue<T>(c, f, slopes, s);
+    int it = 0;
+    hipError_t e = hipSuccess;
+    for (; it < c.max_iter; ++it) {
+        enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
+        k_check<<<c.B, kThreads, 0, s>>>(f.sc, f.insts, f.vl.pstride, f.part, it + 1, c.rel_tol, done);
+        if ((it + 1) % c.check_every == 0 && it + 1 < c.max_iter) {
+            e = hipMemcpyAsync(hdone.data(), done, sizeof(int32_t) * c.B, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) break;
+            if (std::all_of(hdone.begin(), hdone.end(), [](int32_t v) { return v != 0; })) {
+                ++it;
+                break;
+            }
+        }
+    }
+    if (it > c.max_iter) it = c.max_iter;
+    enqueue_finish<T>(c, f, it, info_user, s);
+    *iters = it;
+    return e;
+}
 
 template <typename T>
 hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info_user, hipStream_t s) {
@@ -820,7 +898,10 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
     if (!c.first && c.k > 0)
         m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
     hipError_t e = hipSuccess;
-    if (c.use_graphs && !c.prof.on) {
+    int iters = c.max_iter;
+    if (c.rel_tol > 0) {
+        e = run_tolerance_frame<T>(c, slopes, info_user, s, &iters);
+    } else if (c.use_graphs && !c.prof.on) {
         // the graph reads the slopes from, and writes the frame statistics to, context buffers
         T* s_in = c.at<T>(c.lay.s_in);
         fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
@@ -848,11 +929,12 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
         enqueue_frame<T>(c, slopes, info_user, s);
     }
     if (e == hipSuccess && c_out) e = hipMemcpyAsync(c_out, c.at<T>(c.lay.c), sizeof(T) * N, hipMemcpyDeviceToDevice, s);
-    // a7: ring bookkeeping (the fixed iteration count makes it host-known)
+    // a7: ring bookkeeping (the host knows every frame's iteration count)
     const int K = c.slots;
-    c.head = (c.head + c.max_iter) % K;
-    c.count = std::min(c.count + c.max_iter, K);
-    c.last_iters = c.max_iter;
+    c.head = (c.head + iters) % K;
+    c.count = std::min(c.count + iters, K);
+    c.last_iters = iters;
+    c.frame_iters = iters;
     c.first = false;
     return e;
 }
