@@ -257,6 +257,81 @@ def run_batch(args, dev):
     }
 
 
+def _ragged_instance(args):
+    """One seeded random instance and its slope sequence (runs in a worker process)."""
+    seed, frames = args
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    sp = synth.config_random_instance(rng, precision="fp32")
+    seq = synth.make_sequence(sp, frames, seed=seed + 1).astype(np.float32)
+    return sp, seq
+
+
+def run_ragged(args, dev):
+    """Ragged batch: independent random instances (telescope 8-39 m, 20-84 subapertures, 3-9
+    layers, 1-6 NGS/LGS, grids up to 256^2), FP32 operator, every frame iterated until each
+    instance has ||r|| <= 1e-4 ||b|| (cap 200), the instances in lock step."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+
+    import paper_2011_06842_amd as fw
+
+    B = args.ragged
+    F = args.ragged_warmup + args.ragged_steps
+    t0 = time.perf_counter()
+    workers = max(1, min(16, os.cpu_count() or 1, B))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        pairs = list(ex.map(_ragged_instance, [(SEED + 1000 + 7 * i, F) for i in range(B)]))
+    specs = [p[0] for p in pairs]
+    t_gen = time.perf_counter() - t0
+    log(f"ragged leg: {B} instances, slopes generated in {t_gen:.1f} s ({workers} processes)")
+    frames = torch.from_numpy(np.concatenate([p[1] for p in pairs], axis=1)).to(dev)
+    t0 = time.perf_counter()
+    ctx = fw.FewhaContext(specs, device=dev)
+    t_setup = time.perf_counter() - t0
+    c = torch.empty(ctx.N, dtype=torch.float32, device=dev)
+    info = ctx.new_info()
+    for t in range(args.ragged_warmup):
+        ctx.fewha_solve_aug(frames[t], c, info)
+    torch.cuda.synchronize()
+    ms, iters, firsts, unmet = [], [], [], 0
+    w0 = time.perf_counter()
+    for k in range(args.ragged_steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.fewha_solve_aug(frames[args.ragged_warmup + k], c, info)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        iters.append(ctx.fewha_frame_iterations())
+        inf = fw.decode_info(info)
+        firsts += [x["iters"] for x in inf]
+        unmet += sum(1 for x in inf if x["flags"] & 2)
+    wall = time.perf_counter() - w0
+    log(f"ragged leg: {args.ragged_steps} frames, p50 {np.median(ms):.2f} ms, {np.mean(iters):.1f} iterations")
+    sizes = [synth_n(sp) for sp in specs]
+    return {
+        "workload": f"ragged_random_fp32_x{B}_tol1e-4",
+        "instances": B, "coefficients": int(ctx.N), "coefficients_min_max": [min(sizes), max(sizes)],
+        "applies_per_s": round(B * sum(iters) / wall, 1),
+        "frame_ms_p50": round(float(np.percentile(ms, 50)), 3),
+        "frame_ms_p99": round(float(np.percentile(ms, 99)), 3),
+        "frame_iterations_mean": round(float(np.mean(iters)), 2),
+        "instance_iterations_to_tol_mean": round(float(np.mean(firsts)), 2),
+        "instance_iterations_to_tol_max": int(max(firsts)),
+        "tolerance_unmet_instance_frames": unmet,
+        "steps": args.ragged_steps, "warmup": args.ragged_warmup,
+        "input_generation_s": round(t_gen, 1), "setup_s": round(t_setup, 1),
+        "note": "instances iterate in lock step until all meet the tolerance; applies/s counts the work done",
+    }
+
+
+def synth_n(spec):
+    return int(sum(l.n * l.n for l in spec.layers))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +346,9 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-warmup", type=int, default=5)
     ap.add_argument("--block-elems", type=lambda v: [int(x) for x in v.split(",")], default=[384, 2048, 8192])
+    ap.add_argument("--ragged", type=int, default=64, help="instances of the ragged tolerance leg (0: skip)")
+    ap.add_argument("--ragged-steps", type=int, default=8)
+    ap.add_argument("--ragged-warmup", type=int, default=2)
     args = ap.parse_args(argv)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
@@ -437,6 +515,9 @@ def main(argv=None):
         del ctx, pctx
         torch.cuda.empty_cache()
         out["batched"] = run_batch(args, dev)
+        torch.cuda.empty_cache()
+    if args.ragged > 0:
+        out["ragged"] = run_ragged(args, dev)
     print(json.dumps(out), flush=True)
     return 0
 
