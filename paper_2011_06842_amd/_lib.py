@@ -25,7 +25,11 @@ EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", 
            "fewha_instances", "fewha_frame_iterations", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
            "fewha_solve_aug", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
            "fewha_get_state", "fewha_set_state", "fewha_use_graphs", "fewha_profile", "fewha_profile_read",
-           "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error"]
+           "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error",
+           "fewha_unet_workspace_size", "fewha_unet_setup", "fewha_unet_num_params", "fewha_unet_num_nodes",
+           "fewha_unet_set_params", "fewha_unet_get_params", "fewha_unet_forward", "fewha_unet_backward",
+           "fewha_unet_adam_step", "fewha_unet_get_grads", "fewha_unet_destroy", "fewha_unet_last_error"]
+UNET_MAX_GROUPS = 8
 
 
 class fewha_layer(C.Structure):
@@ -51,6 +55,12 @@ class fewha_config(C.Structure):
 class fewha_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("recycle_used", C.c_int32), ("dropped", C.c_int32),
                 ("flags", C.c_int32), ("rel_res", C.c_double)]
+
+
+class fewha_unet_config(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("n_groups", C.c_int32), ("images", C.c_int32 * 8),
+                ("size", C.c_int32 * 8), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
 
 
 class FewhaError(RuntimeError):
@@ -94,6 +104,18 @@ def load_library(path: str = LIB_PATH):
         "fewha_wavelet_steps": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)], st),
         "fewha_destroy": ([vp], st),
         "fewha_last_error": ([vp], C.c_char_p),
+        "fewha_unet_workspace_size": ([C.POINTER(fewha_unet_config), C.POINTER(C.c_size_t)], st),
+        "fewha_unet_setup": ([C.POINTER(fewha_unet_config), vp, C.c_size_t, vp, C.POINTER(vp)], st),
+        "fewha_unet_num_params": ([vp, C.POINTER(C.c_int64)], st),
+        "fewha_unet_num_nodes": ([vp, C.POINTER(C.c_int64)], st),
+        "fewha_unet_set_params": ([vp, vp, vp], st),
+        "fewha_unet_get_params": ([vp, vp, vp], st),
+        "fewha_unet_forward": ([vp, vp, vp, vp], st),
+        "fewha_unet_backward": ([vp, vp, vp, vp, vp], st),
+        "fewha_unet_adam_step": ([vp, vp], st),
+        "fewha_unet_get_grads": ([vp, vp, vp], st),
+        "fewha_unet_destroy": ([vp], st),
+        "fewha_unet_last_error": ([vp], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -345,3 +367,92 @@ def decode_info(info_tensor):
         out.append({"iters": s.iters, "recycle_used": s.recycle_used, "dropped": s.dropped, "flags": s.flags,
                     "rel_res": s.rel_res})
     return out[0] if len(out) == 1 else out
+
+
+def _ucheck(status: int, net=None):
+    if status != 0:
+        msg = _lib.fewha_unet_last_error(net).decode() if _lib is not None else ""
+        raise FewhaError(f"{STATUS.get(status, status)}: {msg}")
+
+
+class UNetContext:
+    """The warm-start U-Net (include/fewha_unet.h): `groups` is a list of (images, size) of
+    square images; inputs are (nodes, 4) FP32, outputs (nodes,) FP32, groups in order."""
+
+    def __init__(self, groups, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, device="cuda", stream=None):
+        import torch
+        self.lib = load_library()
+        cfg = fewha_unet_config()
+        cfg.abi_version = FEWHA_ABI_VERSION
+        cfg.n_groups = len(groups)
+        for g, (n, sz) in enumerate(groups):
+            cfg.images[g] = n
+            cfg.size[g] = sz
+        cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = lr, beta1, beta2, eps
+        nbytes = C.c_size_t()
+        _ucheck(self.lib.fewha_unet_workspace_size(C.byref(cfg), C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        base = _ptr(self.workspace)
+        net = C.c_void_p()
+        _ucheck(self.lib.fewha_unet_setup(C.byref(cfg), C.c_void_p(base + (-base) % 256), nbytes.value,
+                                          C.c_void_p(_stream(stream)), C.byref(net)))
+        self.net = net
+        self.device = device
+        self.groups = list(groups)
+        n = C.c_int64()
+        _ucheck(self.lib.fewha_unet_num_params(self.net, C.byref(n)), self.net)
+        self.n_params = n.value
+        _ucheck(self.lib.fewha_unet_num_nodes(self.net, C.byref(n)), self.net)
+        self.nodes = n.value
+
+    def _f32(self, t, n):
+        import torch
+        if t.dtype != torch.float32 or t.numel() != n or not t.is_contiguous() or not t.is_cuda:
+            raise FewhaError(f"expected a contiguous float32 device tensor of {n} elements")
+        return t
+
+    def set_params(self, params, stream=None):
+        _ucheck(self.lib.fewha_unet_set_params(self.net, _ptr(self._f32(params, self.n_params)), _stream(stream)),
+                self.net)
+
+    def get_params(self, stream=None):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _ucheck(self.lib.fewha_unet_get_params(self.net, _ptr(out), _stream(stream)), self.net)
+        return out
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+        x = self._f32(x, 4 * self.nodes)
+        out = torch.empty(self.nodes, dtype=torch.float32, device=self.device) if out is None else out
+        _ucheck(self.lib.fewha_unet_forward(self.net, _ptr(x), _ptr(self._f32(out, self.nodes)), _stream(stream)),
+                self.net)
+        return out
+
+    def backward(self, x, target, loss=None, stream=None):
+        import torch
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device) if loss is None else loss
+        _ucheck(self.lib.fewha_unet_backward(self.net, _ptr(self._f32(x, 4 * self.nodes)),
+                                             _ptr(self._f32(target, self.nodes)), _ptr(loss), _stream(stream)),
+                self.net)
+        return loss
+
+    def adam_step(self, stream=None):
+        _ucheck(self.lib.fewha_unet_adam_step(self.net, _stream(stream)), self.net)
+
+    def get_grads(self, stream=None):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _ucheck(self.lib.fewha_unet_get_grads(self.net, _ptr(out), _stream(stream)), self.net)
+        return out
+
+    def destroy(self):
+        if getattr(self, "net", None):
+            self.lib.fewha_unet_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,905 @@
+// Learned warm start (declared in include/fewha_unet.h): U-Net forward, backward and Adam on
+// the bfloat16 matrix cores of gfx950 (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+//   k_conv3x3      implicit GEMM of a same-size 3x3 convolution over NHWC bf16 activations:
+//                  out[p][co] = sum_{tap, ci} in[p + tap][ci] w[tap][co][ci]; 128 pixels x 32
+//                  output channels per workgroup, 32 x 32 per wavefront (2 x 2 MFMA tiles);
+//                  zero padding by masking; the decoder's 2x nearest upsampling and skip
+//                  concatenation are folded into the operand loads; the input gradient is
+//                  the same kernel on the ReLU-masked output gradient with flipped,
+//                  transposed weights.
+//   k_conv_wgrad   weight gradient sum_p x[p + tap][ci] dy[p][co]: tiles of 32 pixels are
+//                  transposed through LDS so that every MFMA operand is one 16-byte read;
+//                  per-chunk FP32 partials, summed in a fixed order by k_reduce_chunks.
+//   small kernels  input packing, pooling and its adjoint, the upsample/concat adjoint, the
+//                  1x1 head with the MSE loss, ReLU', bias gradients, Adam, layouts.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fewha_unet.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t bf16_t;   // bfloat16 storage
+
+constexpr int kT = 256;            // threads of every kernel
+constexpr int kConvPix = 128;      // pixels per convolution workgroup
+constexpr int kWChunk = 2048;      // pixels per weight-gradient workgroup
+constexpr int kBChunk = 2048;      // pixels per bias-gradient workgroup
+constexpr int kLevels = 4;
+constexpr int kCh[kLevels] = {32, 64, 128, 256};
+constexpr int kInCh = 32;          // padded input channels
+constexpr int kInputs = 4;         // used input channels
+constexpr int kConvs = 14;
+
+__host__ __device__ inline float bf2f(bf16_t h) {
+    const uint32_t u = uint32_t(h) << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// Round to nearest even (finite inputs).
+__host__ __device__ inline bf16_t f2bf(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return bf16_t(u >> 16);
+}
+
+__device__ inline bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ inline uint4 and_mask(uint4 v, uint32_t m) { return make_uint4(v.x & m, v.y & m, v.z & m, v.w & m); }
+
+// ------------------------------------------------------------------ convolution (implicit GEMM)
+
+enum { CONV_DIRECT = 0, CONV_CONCAT_UP = 1 };
+
+// MODE CONV_DIRECT: in0 [N][H][W][Cin].  MODE CONV_CONCAT_UP: channels [0, C1) come from the
+// 2x nearest upsampling of in0 [N][H/2][W/2][C1], channels [C1, Cin) from in1 [N][H][W][Cin-C1].
+// OUT_BF16: out = bf16(relu?(acc + bias)) [P][Cout]; else out = acc (FP32) [P][Cout].
+// Cin, C1, Cout multiples of 32.
+template <int MODE, bool OUT_BF16>
+__global__ void __launch_bounds__(kT) k_conv3x3(const bf16_t* __restrict__ in0, const bf16_t* __restrict__ in1,
+                                                 int C1, int Cin, int N, int H, int W,
+                                                 const bf16_t* __restrict__ wt, const float* __restrict__ bias,
+                                                 int relu, void* __restrict__ out, int Cout) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int P = N * H * W;
+    const int co0 = blockIdx.y * 32;
+    const int pb = blockIdx.x * kConvPix + wv * 32;
+    int pn[2], py[2], px[2];
+    bool pin[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        const int p = pb + 16 * mt + r16;
+        pin[mt] = p < P;
+        const int pc = pin[mt] ? p : 0;
+        pn[mt] = pc / (H * W);
+        const int rem = pc - pn[mt] * H * W;
+        py[mt] = rem / W;
+        px[mt] = rem - py[mt] * W;
+    }
+    const int C2 = Cin - C1, Hh = H >> 1, Wh = W >> 1;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        size_t off0[2], off1[2];
+        uint32_t vm[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int ys = py[mt] + dy, xs = px[mt] + dx;
+            const bool ok = pin[mt] && ys >= 0 && ys < H && xs >= 0 && xs < W;
+            const int yc = ok ? ys : 0, xc = ok ? xs : 0;     // clamped: a valid address, zeroed below
+            if (MODE == CONV_DIRECT) {
+                off0[mt] = (size_t(pn[mt] * H + yc) * W + xc) * Cin;
+                off1[mt] = 0;
+            } else {
+                off0[mt] = (size_t(pn[mt] * Hh + (yc >> 1)) * Wh + (xc >> 1)) * C1;
+                off1[mt] = (size_t(pn[mt] * H + yc) * W + xc) * C2;
+            }
+            vm[mt] = ok ? 0xFFFFFFFFu : 0u;
+        }
+        const bf16_t* __restrict__ wtap = wt + size_t(tap) * Cout * Cin;
+        for (int cb = 0; cb < Cin; cb += 32) {
+            const int ci = cb + 8 * kg;
+            uint4 a[2], b[2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const bf16_t* src = (MODE == CONV_DIRECT || cb < C1) ? in0 + off0[mt] + ci : in1 + off1[mt] + (ci - C1);
+                a[mt] = and_mask(*reinterpret_cast<const uint4*>(src), vm[mt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+                b[nt] = *reinterpret_cast<const uint4*>(wtap + size_t(co0 + 16 * nt + r16) * Cin + ci);
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[mt]), as_bf16x8(b[nt]),
+                                                                          acc[mt][nt], 0, 0, 0);
+        }
+    }
+    // lane l, register v: pixel row 4 (l / 16) + v, output channel l mod 16 of the tile
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int p = pb + 16 * mt + 4 * kg + v, co = co0 + 16 * nt + r16;
+                if (p >= P) continue;
+                float val = acc[mt][nt][v];
+                if (OUT_BF16) {
+                    if (bias) val += bias[co];
+                    if (relu) val = fmaxf(val, 0.f);
+                    static_cast<bf16_t*>(out)[size_t(p) * Cout + co] = f2bf(val);
+                } else {
+                    static_cast<float*>(out)[size_t(p) * Cout + co] = val;
+                }
+            }
+}
+
+// ------------------------------------------------------------------ weight gradient
+
+// dW[tap][co][ci] partial over the pixels of chunk blockIdx.x (kWChunk pixels): block
+// (tap, co tile of 32, ci tile of 32) from blockIdx.y.  Per step of 32 pixels the block
+// stages dy[32 px][32 co] and x[32 px (shifted by tap)][32 ci] into LDS transposed, and
+// wavefront w computes the 16 x 16 sub-tile (w / 2, w % 2) with one MFMA (K = 32 pixels).
+template <int MODE>
+__global__ void __launch_bounds__(kT) k_conv_wgrad(const bf16_t* __restrict__ dy, const bf16_t* __restrict__ in0,
+                                                    const bf16_t* __restrict__ in1, int C1, int Cin, int N, int H,
+                                                    int W, int Cout, float* __restrict__ part, int chunk0) {
+    constexpr int LD = 32 + 8;                 // padded row (bf16) of the transposed tiles
+    __shared__ __align__(16) bf16_t sdy[32][LD];   // [co][pixel]
+    __shared__ __align__(16) bf16_t sx[32][LD];    // [ci][pixel]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int nci = Cin / 32, nco = Cout / 32;
+    const int tap = blockIdx.y / (nco * nci);
+    const int rem = blockIdx.y - tap * nco * nci;
+    const int co0 = (rem / nci) * 32, ci0 = (rem % nci) * 32;
+    const int dyy = tap / 3 - 1, dxx = tap % 3 - 1;
+    const int P = N * H * W, C2 = Cin - C1, Hh = H >> 1, Wh = W >> 1;
+    const int p_begin = blockIdx.x * kWChunk;
+    const int p_end = min(P, p_begin + kWChunk);
+    // staging role of the thread: pixel sp (0..31), channel group sc (0..3) of 8 channels
+    const int sp = threadIdx.x >> 3, sc = threadIdx.x & 7;   // 32 pixels x 8 groups: dy uses sc < 4, x uses sc >= 4
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int mt = wv >> 1, nt = wv & 1;
+    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
+        const int p = p0 + sp;
+        const bool pin = p < p_end;
+        const int pc = pin ? p : p_begin;
+        uint4 v;
+        if (sc < 4) {   // dy[p][co0 + 8 sc .. +7]
+            v = and_mask(*reinterpret_cast<const uint4*>(dy + size_t(pc) * Cout + co0 + 8 * sc), pin ? 0xFFFFFFFFu : 0u);
+        } else {        // x[p + tap][ci0 + 8 (sc - 4) .. +7]
+            const int n = pc / (H * W), r = pc - n * H * W, y = r / W, x = r - (r / W) * W;
+            const int ys = y + dyy, xs = x + dxx;
+            const bool ok = pin && ys >= 0 && ys < H && xs >= 0 && xs < W;
+            const int yc = ok ? ys : 0, xc = ok ? xs : 0;
+            const int ci = ci0 + 8 * (sc - 4);
+            const bf16_t* src;
+            if (MODE == CONV_DIRECT)
+                src = in0 + (size_t(n * H + yc) * W + xc) * Cin + ci;
+            else if (ci < C1)
+                src = in0 + (size_t(n * Hh + (yc >> 1)) * Wh + (xc >> 1)) * C1 + ci;
+            else
+                src = in1 + (size_t(n * H + yc) * W + xc) * C2 + (ci - C1);
+            v = and_mask(*reinterpret_cast<const uint4*>(src), ok ? 0xFFFFFFFFu : 0u);
+        }
+        const bf16_t* e = reinterpret_cast<const bf16_t*>(&v);
+        bf16_t (*dst)[LD] = sc < 4 ? sdy : sx;
+        const int c8 = 8 * (sc & 3);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[c8 + i][sp] = e[i];
+        __syncthreads();
+        const uint4 a = *reinterpret_cast<const uint4*>(&sdy[16 * mt + r16][8 * kg]);
+        const uint4 b = *reinterpret_cast<const uint4*>(&sx[16 * nt + r16][8 * kg]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
+        __syncthreads();
+    }
+    // lane l, register v: co row 4 (l / 16) + v, ci column l mod 16 of the sub-tile
+    float* dst = part + (size_t(chunk0 + blockIdx.x) * 9 + tap) * Cout * Cin;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int co = co0 + 16 * mt + 4 * kg + v, ci = ci0 + 16 * nt + r16;
+        dst[size_t(co) * Cin + ci] = acc[v];
+    }
+}
+
+// out[i] = sum_{c < chunks} part[c * n + i] (fixed order), optionally scaled.
+__global__ void __launch_bounds__(kT) k_reduce_chunks(const float* __restrict__ part, int chunks, int64_t n,
+                                                       float* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[size_t(c) * n + i];
+    out[i] = s;
+}
+
+// ------------------------------------------------------------------ small kernels
+
+// in [P][4] FP32 -> x [P][32] bf16 (channels 4..31 zero)
+__global__ void __launch_bounds__(kT) k_pack_input(const float* __restrict__ in, int64_t P, bf16_t* __restrict__ x) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e >= P * kInCh) return;
+    const int64_t p = e / kInCh;
+    const int c = int(e - p * kInCh);
+    x[e] = c < kInputs ? f2bf(in[p * kInputs + c]) : bf16_t(0);
+}
+
+// 2x2 average pooling, bf16 -> bf16 (sum in FP32)
+__global__ void __launch_bounds__(kT) k_pool2(const bf16_t* __restrict__ x, int N, int H, int W, int C,
+                                               bf16_t* __restrict__ y) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2;
+    if (e >= int64_t(N) * Ho * Wo * C) return;
+    const int c = int(e % C);
+    const int64_t q = e / C;
+    const int xo = int(q % Wo), yo = int((q / Wo) % Ho), n = int(q / (int64_t(Wo) * Ho));
+    const size_t b = (size_t(n * H + 2 * yo) * W + 2 * xo) * C + c;
+    const float s = (bf2f(x[b]) + bf2f(x[b + C])) + (bf2f(x[b + size_t(W) * C]) + bf2f(x[b + size_t(W) * C + C]));
+    y[e] = f2bf(0.25f * s);
+}
+
+// g_full[n][y][x][c] += 0.25 g_low[n][y/2][x/2][c]   (adjoint of the pooling)
+__global__ void __launch_bounds__(kT) k_pool2_grad_add(const float* __restrict__ gl, int N, int H, int W, int C,
+                                                        float* __restrict__ gf) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e >= int64_t(N) * H * W * C) return;
+    const int c = int(e % C);
+    const int64_t q = e / C;
+    const int x = int(q % W), y = int((q / W) % H), n = int(q / (int64_t(W) * H));
+    gf[e] += 0.25f * gl[(size_t(n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+}
+
+// Adjoint of [upsample(low), skip]: g_low[q][c] = sum of the 2x2 window of gcat[..][c < C1];
+// g_skip[p][c] = gcat[p][C1 + c] (written, the first gradient of the skip tensor).
+__global__ void __launch_bounds__(kT) k_split_concat_grad(const float* __restrict__ gcat, int N, int H, int W, int C1,
+                                                           int C2, float* __restrict__ glow,
+                                                           float* __restrict__ gskip) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    const int64_t nl = int64_t(N) * (H / 2) * (W / 2) * C1, ns = int64_t(N) * H * W * C2;
+    const int Cc = C1 + C2;
+    if (e < nl) {
+        const int c = int(e % C1);
+        const int64_t q = e / C1;
+        const int xo = int(q % (W / 2)), yo = int((q / (W / 2)) % (H / 2)), n = int(q / (int64_t(W / 2) * (H / 2)));
+        const size_t b = (size_t(n * H + 2 * yo) * W + 2 * xo) * Cc + c;
+        glow[e] = (gcat[b] + gcat[b + Cc]) + (gcat[b + size_t(W) * Cc] + gcat[b + size_t(W) * Cc + Cc]);
+    } else if (e < nl + ns) {
+        const int64_t f = e - nl;
+        const int c = int(f % C2);
+        const int64_t p = f / C2;
+        gskip[f] = gcat[p * Cc + C1 + c];
+    }
+}
+
+// dpre = bf16(g * (act > 0))
+__global__ void __launch_bounds__(kT) k_relu_grad(const float* __restrict__ g, const bf16_t* __restrict__ act,
+                                                   int64_t n, bf16_t* __restrict__ dpre) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e >= n) return;
+    dpre[e] = f2bf(bf2f(act[e]) > 0.f ? g[e] : 0.f);
+}
+
+// bias-gradient partial of chunk blockIdx.x: part[chunk][co] = sum_p dpre[p][co]
+__global__ void __launch_bounds__(kT) k_bias_grad(const bf16_t* __restrict__ dpre, int P, int C,
+                                                   float* __restrict__ part, int chunk0) {
+    const int p0 = blockIdx.x * kBChunk, p1 = min(P, p0 + kBChunk);
+    for (int co = threadIdx.x; co < C; co += kT) {
+        float s = 0.f;
+        for (int p = p0; p < p1; ++p) s += bf2f(dpre[size_t(p) * C + co]);
+        part[size_t(chunk0 + blockIdx.x) * C + co] = s;
+    }
+}
+
+// out[p] = sum_c x[p][c] w[c] + b
+__global__ void __launch_bounds__(kT) k_head(const bf16_t* __restrict__ x, const float* __restrict__ w,
+                                              const float* __restrict__ b, int64_t P, float* __restrict__ out) {
+    const int64_t p = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (p >= P) return;
+    float s = 0.f;
+#pragma unroll 8
+    for (int c = 0; c < kCh[0]; ++c) s += bf2f(x[p * kCh[0] + c]) * bf2f(f2bf(w[c]));
+    out[p] = s + b[0];
+}
+
+// MSE: dout = 2 (out - t) / total; gx[p][c] = dout w_bf16[c]; per-block partials of the loss
+// sum, of the head weight gradient and of the head bias gradient
+// (part row: [loss, gw[0..31], gb]).
+__global__ void __launch_bounds__(kT) k_head_back(const float* __restrict__ out, const float* __restrict__ t,
+                                                   const bf16_t* __restrict__ x, const float* __restrict__ w,
+                                                   int64_t P, double total, float* __restrict__ gx,
+                                                   float* __restrict__ part, int block0) {
+    constexpr int C = kCh[0];
+    __shared__ float sh[kT / 64][C + 2];
+    const int64_t p = int64_t(blockIdx.x) * kT + threadIdx.x;
+    float l = 0.f, gb = 0.f, gw[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) gw[c] = 0.f;
+    if (p < P) {
+        const float d = out[p] - t[p];
+        const float dout = float(2.0 * double(d) / total);
+        l = d * d;
+        gb = dout;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            gw[c] = bf2f(x[p * C + c]) * dout;
+            gx[p * C + c] = dout * bf2f(f2bf(w[c]));
+        }
+    }
+    auto wsum = [](float v) {
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        return v;
+    };
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    l = wsum(l);
+    gb = wsum(gb);
+#pragma unroll
+    for (int c = 0; c < C; ++c) gw[c] = wsum(gw[c]);
+    if (lane == 0) {
+        sh[wv][0] = l;
+#pragma unroll
+        for (int c = 0; c < C; ++c) sh[wv][1 + c] = gw[c];
+        sh[wv][C + 1] = gb;
+    }
+    __syncthreads();
+    if (threadIdx.x < C + 2) {
+        const int k = threadIdx.x;
+        part[size_t(block0 + blockIdx.x) * (C + 2) + k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+    }
+}
+
+// Adam over n master entries; conv weights (internal layout [9][Cout][Cin]) also refresh their
+// bf16 forward copy and the flipped, transposed copy wd[8 - tap][ci][co] of the input gradient.
+__global__ void __launch_bounds__(kT) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2, bf16_t* __restrict__ wt,
+                                              bf16_t* __restrict__ wd, int Cout, int Cin) {
+    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wt) {
+        const bf16_t h = f2bf(wi);
+        wt[i] = h;
+        const int64_t per = int64_t(Cout) * Cin;
+        const int tap = int(i / per);
+        const int64_t r = i - tap * per;
+        const int co = int(r / Cin), ci = int(r - int64_t(co) * Cin);
+        wd[(size_t(8 - tap) * Cin + ci) * Cout + co] = h;
+    }
+}
+
+// Network-order parameters <-> internal layout.  dir 0: ext -> master (+ bf16 copies);
+// dir 1: master -> ext.  Conv weights: ext [3][3][Cin][Cout], internal [9][Cout][Cin].
+__global__ void __launch_bounds__(kT) k_conv_layout(float* __restrict__ ext, float* __restrict__ w, int Cin, int Cout,
+                                                     int dir, bf16_t* __restrict__ wt, bf16_t* __restrict__ wd) {
+    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+    const int64_t n = int64_t(9) * Cin * Cout;
+    if (i >= n) return;
+    const int tap = int(i / (int64_t(Cin) * Cout));
+    const int64_t r = i - tap * int64_t(Cin) * Cout;
+    const int ci = int(r / Cout), co = int(r - int64_t(ci) * Cout);
+    const size_t j = (size_t(tap) * Cout + co) * Cin + ci;
+    if (dir == 0) {
+        const float x = ext[i];
+        w[j] = x;
+        const bf16_t h = f2bf(x);
+        wt[j] = h;
+        wd[(size_t(8 - tap) * Cin + ci) * Cout + co] = h;
+    } else {
+        ext[i] = w[j];
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_copy(float* __restrict__ dst, const float* __restrict__ src, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(kT) k_zero(float* __restrict__ x, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (i < n) x[i] = 0.f;
+}
+
+// reduced head row -> loss (mean) and the head gradients
+__global__ void k_head_finish(const float* __restrict__ hred, double total, float* __restrict__ loss,
+                              float* __restrict__ gw, float* __restrict__ gb) {
+    const int k = threadIdx.x;
+    if (k == 0 && loss) loss[0] = float(double(hred[0]) / total);
+    if (k < kCh[0]) gw[k] = hred[1 + k];
+    if (k == 0) gb[0] = hred[kCh[0] + 1];
+}
+
+inline unsigned blocks(int64_t n, int per = kT) { return unsigned((n + per - 1) / per); }
+
+// ------------------------------------------------------------------ host network
+
+struct ConvSpec {
+    const char* name;
+    int cin, cout;
+    int level;       // resolution level of its output
+    bool concat;     // decoder first convolution: [upsample(coarser), skip]
+};
+
+const ConvSpec kSpecs[kConvs] = {
+    {"e0a", kInCh, 32, 0, false},   {"e0b", 32, 32, 0, false},    {"e1a", 32, 64, 1, false},
+    {"e1b", 64, 64, 1, false},      {"e2a", 64, 128, 2, false},   {"e2b", 128, 128, 2, false},
+    {"e3a", 128, 256, 3, false},    {"e3b", 256, 256, 3, false},  {"d2a", 384, 128, 2, true},
+    {"d2b", 128, 128, 2, false},    {"d1a", 192, 64, 1, true},    {"d1b", 64, 64, 1, false},
+    {"d0a", 96, 32, 0, true},       {"d0b", 32, 32, 0, false}};
+
+enum { E0A, E0B, E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B, D0A, D0B };
+
+}  // namespace
+
+struct fewha_unet {
+    // configuration
+    int G = 0;
+    int images[FEWHA_UNET_MAX_GROUPS] = {}, size[FEWHA_UNET_MAX_GROUPS] = {};
+    float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    int64_t nodes = 0, n_params = 0;
+    int step = 0;
+    std::string err;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t used = 0;
+    // parameters (internal layout), FP32 master/m/v/grad share offsets
+    int64_t w_off[kConvs] = {}, b_off[kConvs] = {}, hw_off = 0, hb_off = 0, n_master = 0;
+    int64_t ext_w[kConvs] = {}, ext_b[kConvs] = {}, ext_hw = 0, ext_hb = 0;
+    float *master = nullptr, *mom1 = nullptr, *mom2 = nullptr, *grad = nullptr;
+    bf16_t* wt[kConvs] = {};
+    bf16_t* wd[kConvs] = {};
+    // activations per group: x, conv outputs, pooled inputs
+    bf16_t* x[FEWHA_UNET_MAX_GROUPS] = {};
+    bf16_t* act[FEWHA_UNET_MAX_GROUPS][kConvs] = {};
+    bf16_t* pool[FEWHA_UNET_MAX_GROUPS][3] = {};
+    float* out[FEWHA_UNET_MAX_GROUPS] = {};
+    // gradient buffers (largest sizes over groups; groups are processed one after the other)
+    float* gact[kConvs] = {};       // gradient of each conv output
+    float* gcat[3] = {};            // gradient of the concatenated decoder inputs (levels 2, 1, 0)
+    float* gpool[3] = {};           // gradient of the pooled inputs of levels 1, 2, 3
+    bf16_t* dpre = nullptr;         // bf16 ReLU-masked gradient of the current conv
+    float* wpart[kConvs] = {};      // weight-gradient partials [chunks][9][Cout][Cin]
+    float* bpart[kConvs] = {};      // bias-gradient partials [chunks][Cout]
+    int wchunks[kConvs] = {}, bchunks[kConvs] = {};
+    float* hpart = nullptr;         // head partials [blocks][34]
+    int hblocks = 0;
+    float* hred = nullptr;          // reduced head row [loss sum, gw[32], gb]
+
+    int64_t P(int g, int level) const {
+        const int s = size[g] >> level;
+        return int64_t(images[g]) * s * s;
+    }
+
+    // bump allocation on the workspace (or size counting when ws is null)
+    template <typename Tp>
+    Tp* take(int64_t count) {
+        const size_t off = used;
+        used = (used + size_t(count) * sizeof(Tp) + 255) & ~size_t(255);
+        return ws ? reinterpret_cast<Tp*>(ws + off) : nullptr;
+    }
+
+    void layout() {
+        used = 0;
+        // parameters
+        int64_t o = 0, e = 0;
+        for (int k = 0; k < kConvs; ++k) {
+            const int64_t nw = int64_t(9) * kSpecs[k].cin * kSpecs[k].cout;
+            w_off[k] = o;
+            o += nw;
+            b_off[k] = o;
+            o += kSpecs[k].cout;
+            ext_w[k] = e;
+            e += nw;
+            ext_b[k] = e;
+            e += kSpecs[k].cout;
+        }
+        hw_off = o;
+        o += kCh[0];
+        hb_off = o;
+        o += 1;
+        ext_hw = e;
+        e += kCh[0];
+        ext_hb = e;
+        e += 1;
+        n_master = o;
+        n_params = e;
+        master = take<float>(o);
+        mom1 = take<float>(o);
+        mom2 = take<float>(o);
+        grad = take<float>(o);
+        for (int k = 0; k < kConvs; ++k) {
+            wt[k] = take<bf16_t>(int64_t(9) * kSpecs[k].cin * kSpecs[k].cout);
+            wd[k] = take<bf16_t>(int64_t(9) * kSpecs[k].cin * kSpecs[k].cout);
+        }
+        // activations
+        nodes = 0;
+        for (int g = 0; g < G; ++g) {
+            nodes += P(g, 0);
+            x[g] = take<bf16_t>(P(g, 0) * kInCh);
+            for (int k = 0; k < kConvs; ++k) act[g][k] = take<bf16_t>(P(g, kSpecs[k].level) * kSpecs[k].cout);
+            for (int l = 0; l < 3; ++l) pool[g][l] = take<bf16_t>(P(g, l + 1) * kCh[l]);
+            out[g] = take<float>(P(g, 0));
+        }
+        // gradients: sized for the largest group
+        auto maxP = [&](int level) {
+            int64_t m = 0;
+            for (int g = 0; g < G; ++g) m = std::max(m, P(g, level));
+            return m;
+        };
+        int64_t maxpc = 0;
+        for (int k = 0; k < kConvs; ++k) {
+            gact[k] = take<float>(maxP(kSpecs[k].level) * kSpecs[k].cout);
+            maxpc = std::max(maxpc, maxP(kSpecs[k].level) * std::max(kSpecs[k].cout, kSpecs[k].cin));
+        }
+        for (int l = 0; l < 3; ++l) {
+            gcat[l] = take<float>(maxP(2 - l) * kSpecs[D2A + 2 * l].cin);
+            gpool[l] = take<float>(maxP(l + 1) * kCh[l]);
+        }
+        dpre = take<bf16_t>(maxpc);
+        for (int k = 0; k < kConvs; ++k) {
+            wchunks[k] = bchunks[k] = 0;
+            for (int g = 0; g < G; ++g) {
+                wchunks[k] += int((P(g, kSpecs[k].level) + kWChunk - 1) / kWChunk);
+                bchunks[k] += int((P(g, kSpecs[k].level) + kBChunk - 1) / kBChunk);
+            }
+            wpart[k] = take<float>(int64_t(wchunks[k]) * 9 * kSpecs[k].cin * kSpecs[k].cout);
+            bpart[k] = take<float>(int64_t(bchunks[k]) * kSpecs[k].cout);
+        }
+        hblocks = 0;
+        for (int g = 0; g < G; ++g) hblocks += int(blocks(P(g, 0)));
+        hpart = take<float>(int64_t(hblocks) * (kCh[0] + 2));
+        hred = take<float>(kCh[0] + 2);
+    }
+
+    // ---- launches
+    // upsampled channels of a decoder concatenation: the coarser level's channel count
+    static int concat_c1(int k) { return kSpecs[k].cin - kSpecs[k].cout; }
+
+    const bf16_t* conv_in0(int k, int g) const {
+        switch (k) {
+            case E0A: return x[g];
+            case E1A: return pool[g][0];
+            case E2A: return pool[g][1];
+            case E3A: return pool[g][2];
+            case D2A: return act[g][E3B];
+            case D1A: return act[g][D2B];
+            case D0A: return act[g][D1B];
+            default: return act[g][k - 1];
+        }
+    }
+    const bf16_t* conv_in1(int k, int g) const {
+        switch (k) {
+            case D2A: return act[g][E2B];
+            case D1A: return act[g][E1B];
+            case D0A: return act[g][E0B];
+            default: return nullptr;
+        }
+    }
+
+    void forward_group(int g, const float* in, hipStream_t s) {
+        const int64_t P0 = P(g, 0);
+        k_pack_input<<<blocks(P0 * kInCh), kT, 0, s>>>(in, P0, x[g]);
+        for (int k = 0; k < kConvs; ++k) {
+            const ConvSpec& c = kSpecs[k];
+            if (k == E1A || k == E2A || k == E3A) {   // pool the previous level's output
+                const int l = c.level - 1, Hs = size[g] >> l;
+                k_pool2<<<blocks(P(g, l + 1) * kCh[l]), kT, 0, s>>>(act[g][k - 1], images[g], Hs, Hs, kCh[l], pool[g][l]);
+            }
+            const int H = size[g] >> c.level;
+            const dim3 grid(blocks(P(g, c.level), kConvPix), c.cout / 32);
+            const float* bias = master + b_off[k];
+            if (c.concat)
+                k_conv3x3<CONV_CONCAT_UP, true><<<grid, kT, 0, s>>>(conv_in0(k, g), conv_in1(k, g), concat_c1(k), c.cin,
+                                                                  images[g], H, H, wt[k], bias, 1, act[g][k], c.cout);
+            else
+                k_conv3x3<CONV_DIRECT, true><<<grid, kT, 0, s>>>(conv_in0(k, g), nullptr, 0, c.cin, images[g], H, H,
+                                                                wt[k], bias, 1, act[g][k], c.cout);
+        }
+        k_head<<<blocks(P0), kT, 0, s>>>(act[g][D0B], master + hw_off, master + hb_off, P0, out[g]);
+    }
+
+    // gradient of conv k's output is in gact[k]: weight/bias partials, and (unless k == E0A)
+    // the gradient of its input into gin (FP32)
+    void conv_back(int k, int g, int wc0, int bc0, float* gin, hipStream_t s) {
+        const ConvSpec& c = kSpecs[k];
+        const int H = size[g] >> c.level;
+        const int64_t Pn = P(g, c.level);
+        k_relu_grad<<<blocks(Pn * c.cout), kT, 0, s>>>(gact[k], act[g][k], Pn * c.cout, dpre);
+        const dim3 wg(blocks(Pn, kWChunk), 9 * (c.cout / 32) * (c.cin / 32));
+        if (c.concat)
+            k_conv_wgrad<CONV_CONCAT_UP><<<wg, kT, 0, s>>>(dpre, conv_in0(k, g), conv_in1(k, g), concat_c1(k), c.cin,
+                                                         images[g], H, H, c.cout, wpart[k], wc0);
+        else
+            k_conv_wgrad<CONV_DIRECT><<<wg, kT, 0, s>>>(dpre, conv_in0(k, g), nullptr, 0, c.cin, images[g], H, H,
+                                                       c.cout, wpart[k], wc0);
+        k_bias_grad<<<blocks(Pn, kBChunk), kT, 0, s>>>(dpre, int(Pn), c.cout, bpart[k], bc0);
+        if (gin) {
+            const dim3 grid(blocks(Pn, kConvPix), c.cin / 32);
+            k_conv3x3<CONV_DIRECT, false><<<grid, kT, 0, s>>>(dpre, nullptr, 0, c.cout, images[g], H, H, wd[k], nullptr,
+                                                             0, gin, c.cin);
+        }
+    }
+
+    void backward_group(int g, const float* target, double total, int* wc, int* bc, int hb0, hipStream_t s) {
+        const int64_t P0 = P(g, 0);
+        k_head_back<<<blocks(P0), kT, 0, s>>>(out[g], target, act[g][D0B], master + hw_off, P0, total, gact[D0B],
+                                              hpart, hb0);
+        auto chunks = [&](int k, int per) { return int((P(g, kSpecs[k].level) + per - 1) / per); };
+        auto back = [&](int k, float* gin) {
+            conv_back(k, g, wc[k], bc[k], gin, s);
+            wc[k] += chunks(k, kWChunk);
+            bc[k] += chunks(k, kBChunk);
+        };
+        auto split = [&](int lvl_out, float* gc, float* glow, float* gskip, int c1, int c2) {
+            const int H = size[g] >> lvl_out;
+            const int64_t n = P(g, lvl_out + 1) * c1 + P(g, lvl_out) * c2;
+            k_split_concat_grad<<<blocks(n), kT, 0, s>>>(gc, images[g], H, H, c1, c2, glow, gskip);
+        };
+        auto pool_add = [&](int lvl, const float* gl, float* gf, int C) {
+            const int H = size[g] >> lvl;
+            k_pool2_grad_add<<<blocks(P(g, lvl) * C), kT, 0, s>>>(gl, images[g], H, H, C, gf);
+        };
+        // decoder
+        back(D0B, gact[D0A]);
+        back(D0A, gcat[2]);
+        split(0, gcat[2], gact[D1B], gact[E0B], kCh[1], kCh[0]);
+        back(D1B, gact[D1A]);
+        back(D1A, gcat[1]);
+        split(1, gcat[1], gact[D2B], gact[E1B], kCh[2], kCh[1]);
+        back(D2B, gact[D2A]);
+        back(D2A, gcat[0]);
+        split(2, gcat[0], gact[E3B], gact[E2B], kCh[3], kCh[2]);
+        // encoder
+        back(E3B, gact[E3A]);
+        back(E3A, gpool[2]);
+        pool_add(2, gpool[2], gact[E2B], kCh[2]);
+        back(E2B, gact[E2A]);
+        back(E2A, gpool[1]);
+        pool_add(1, gpool[1], gact[E1B], kCh[1]);
+        back(E1B, gact[E1A]);
+        back(E1A, gpool[0]);
+        pool_add(0, gpool[0], gact[E0B], kCh[0]);
+        back(E0B, gact[E0A]);
+        back(E0A, nullptr);
+    }
+};
+
+namespace {
+
+thread_local std::string g_unet_err;
+
+fewha_status ufail(fewha_unet* n, fewha_status st, const std::string& m) {
+    if (n) n->err = m;
+    else g_unet_err = m;
+    return st;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+fewha_status validate(const fewha_unet_config* c, std::string& err) {
+    if (!c) { err = "config is NULL"; return FEWHA_E_INVAL; }
+    if (c->abi_version != FEWHA_ABI_VERSION) { err = "abi_version mismatch"; return FEWHA_E_INVAL; }
+    if (c->n_groups < 1 || c->n_groups > FEWHA_UNET_MAX_GROUPS) { err = "n_groups out of range"; return FEWHA_E_INVAL; }
+    for (int g = 0; g < c->n_groups; ++g) {
+        const int s = c->size[g];
+        if (s < 16 || s > 4096 || (s & (s - 1))) { err = "image size must be a power of two in [16, 4096]"; return FEWHA_E_INVAL; }
+        if (c->images[g] < 1) { err = "images per group must be >= 1"; return FEWHA_E_INVAL; }
+        if (int64_t(c->images[g]) * s * s > (int64_t(1) << 30)) { err = "group too large"; return FEWHA_E_INVAL; }
+    }
+    if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) || !(c->eps > 0)) {
+        err = "bad Adam settings";
+        return FEWHA_E_INVAL;
+    }
+    return FEWHA_OK;
+}
+
+void configure(fewha_unet& n, const fewha_unet_config* c) {
+    n.G = c->n_groups;
+    for (int g = 0; g < n.G; ++g) {
+        n.images[g] = c->images[g];
+        n.size[g] = c->size[g];
+    }
+    n.lr = c->lr;
+    n.b1 = c->beta1;
+    n.b2 = c->beta2;
+    n.eps = c->eps;
+}
+
+fewha_status check(fewha_unet* n) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ufail(n, FEWHA_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    return FEWHA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fewha_status fewha_unet_workspace_size(const fewha_unet_config* cfg, size_t* bytes) {
+    std::string err;
+    const fewha_status st = validate(cfg, err);
+    if (st != FEWHA_OK) return ufail(nullptr, st, err);
+    if (!bytes) return FEWHA_E_INVAL;
+    fewha_unet n;
+    configure(n, cfg);
+    n.layout();
+    *bytes = n.used;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_unet_setup(const fewha_unet_config* cfg, void* d_workspace, size_t bytes, void* stream,
+                              fewha_unet** out) {
+    if (!out) return FEWHA_E_INVAL;
+    *out = nullptr;
+    std::string err;
+    fewha_status st = validate(cfg, err);
+    if (st != FEWHA_OK) return ufail(nullptr, st, err);
+    if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) & 255))
+        return ufail(nullptr, FEWHA_E_INVAL, "workspace must be a 256-byte aligned device pointer");
+    fewha_unet* n = new (std::nothrow) fewha_unet();
+    if (!n) return FEWHA_E_NOMEM;
+    configure(*n, cfg);
+    n->layout();
+    if (bytes < n->used) {
+        const size_t need = n->used;
+        delete n;
+        return ufail(nullptr, FEWHA_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+    }
+    n->ws = static_cast<char*>(d_workspace);
+    n->ws_bytes = bytes;
+    n->layout();
+    hipStream_t s = as_stream(stream);
+    if (hipMemsetAsync(n->ws, 0, n->used, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        delete n;
+        return ufail(nullptr, FEWHA_E_HIP, "workspace initialisation failed");
+    }
+    *out = n;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_unet_num_params(const fewha_unet* net, int64_t* n) {
+    if (!net || !n) return FEWHA_E_INVAL;
+    *n = net->n_params;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_unet_num_nodes(const fewha_unet* net, int64_t* n) {
+    if (!net || !n) return FEWHA_E_INVAL;
+    *n = net->nodes;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_unet_set_params(fewha_unet* net, const float* d_params, void* stream) {
+    if (!net || !d_params) return ufail(net, FEWHA_E_INVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    float* ext = const_cast<float*>(d_params);   // read only (direction 0)
+    for (int k = 0; k < kConvs; ++k) {
+        const int64_t nw = int64_t(9) * kSpecs[k].cin * kSpecs[k].cout;
+        k_conv_layout<<<blocks(nw), kT, 0, s>>>(ext + net->ext_w[k], net->master + net->w_off[k], kSpecs[k].cin,
+                                                kSpecs[k].cout, 0, net->wt[k], net->wd[k]);
+        k_copy<<<blocks(kSpecs[k].cout), kT, 0, s>>>(net->master + net->b_off[k], d_params + net->ext_b[k],
+                                                     kSpecs[k].cout);
+    }
+    k_copy<<<1, kT, 0, s>>>(net->master + net->hw_off, d_params + net->ext_hw, kCh[0]);
+    k_copy<<<1, kT, 0, s>>>(net->master + net->hb_off, d_params + net->ext_hb, 1);
+    k_zero<<<blocks(net->n_master), kT, 0, s>>>(net->mom1, net->n_master);
+    k_zero<<<blocks(net->n_master), kT, 0, s>>>(net->mom2, net->n_master);
+    net->step = 0;
+    return check(net);
+}
+
+static fewha_status export_vec(fewha_unet* net, const float* src, float* d_out, hipStream_t s) {
+    for (int k = 0; k < kConvs; ++k) {
+        const int64_t nw = int64_t(9) * kSpecs[k].cin * kSpecs[k].cout;
+        k_conv_layout<<<blocks(nw), kT, 0, s>>>(d_out + net->ext_w[k], const_cast<float*>(src) + net->w_off[k],
+                                                kSpecs[k].cin, kSpecs[k].cout, 1, nullptr, nullptr);
+        k_copy<<<blocks(kSpecs[k].cout), kT, 0, s>>>(d_out + net->ext_b[k], src + net->b_off[k], kSpecs[k].cout);
+    }
+    k_copy<<<1, kT, 0, s>>>(d_out + net->ext_hw, src + net->hw_off, kCh[0]);
+    k_copy<<<1, kT, 0, s>>>(d_out + net->ext_hb, src + net->hb_off, 1);
+    return check(net);
+}
+
+fewha_status fewha_unet_get_params(fewha_unet* net, float* d_params, void* stream) {
+    if (!net || !d_params) return ufail(net, FEWHA_E_INVAL, "NULL argument");
+    return export_vec(net, net->master, d_params, as_stream(stream));
+}
+
+fewha_status fewha_unet_get_grads(fewha_unet* net, float* d_grads, void* stream) {
+    if (!net || !d_grads) return ufail(net, FEWHA_E_INVAL, "NULL argument");
+    return export_vec(net, net->grad, d_grads, as_stream(stream));
+}
+
+fewha_status fewha_unet_forward(fewha_unet* net, const float* d_in, float* d_out, void* stream) {
+    if (!net || !d_in || !d_out) return ufail(net, FEWHA_E_INVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    int64_t o = 0;
+    for (int g = 0; g < net->G; ++g) {
+        net->forward_group(g, d_in + o * kInputs, s);
+        const int64_t P0 = net->P(g, 0);
+        k_copy<<<blocks(P0), kT, 0, s>>>(d_out + o, net->out[g], P0);
+        o += P0;
+    }
+    return check(net);
+}
+
+fewha_status fewha_unet_backward(fewha_unet* net, const float* d_in, const float* d_target, float* d_loss,
+                                 void* stream) {
+    if (!net || !d_in || !d_target) return ufail(net, FEWHA_E_INVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    int wc[kConvs] = {}, bc[kConvs] = {};
+    int hb = 0;
+    int64_t o = 0;
+    const double total = double(net->nodes);
+    for (int g = 0; g < net->G; ++g) {
+        net->forward_group(g, d_in + o * kInputs, s);
+        net->backward_group(g, d_target + o, total, wc, bc, hb, s);
+        hb += int(blocks(net->P(g, 0)));
+        o += net->P(g, 0);
+    }
+    // fixed-order reduction of every partial into the gradient vector
+    for (int k = 0; k < kConvs; ++k) {
+        const int64_t nw = int64_t(9) * kSpecs[k].cin * kSpecs[k].cout;
+        k_reduce_chunks<<<blocks(nw), kT, 0, s>>>(net->wpart[k], net->wchunks[k], nw, net->grad + net->w_off[k]);
+        k_reduce_chunks<<<blocks(kSpecs[k].cout), kT, 0, s>>>(net->bpart[k], net->bchunks[k], kSpecs[k].cout,
+                                                              net->grad + net->b_off[k]);
+    }
+    // head: part rows [loss sum, gw[32], gb]
+    constexpr int HC = kCh[0] + 2;
+    k_reduce_chunks<<<1, kT, 0, s>>>(net->hpart, net->hblocks, HC, net->hred);
+    k_head_finish<<<1, 64, 0, s>>>(net->hred, total, d_loss, net->grad + net->hw_off, net->grad + net->hb_off);
+    return check(net);
+}
+
+fewha_status fewha_unet_adam_step(fewha_unet* net, void* stream) {
+    if (!net) return FEWHA_E_INVAL;
+    hipStream_t s = as_stream(stream);
+    net->step += 1;
+    const float c1 = float(1.0 - std::pow(double(net->b1), net->step));
+    const float c2 = float(1.0 - std::pow(double(net->b2), net->step));
+    auto adam = [&](int64_t off, int64_t n, bf16_t* wt, bf16_t* wd, int cout, int cin) {
+        k_adam<<<blocks(n), kT, 0, s>>>(net->master + off, net->mom1 + off, net->mom2 + off, net->grad + off, n,
+                                       net->lr, net->b1, net->b2, net->eps, c1, c2, wt, wd, cout, cin);
+    };
+    for (int k = 0; k < kConvs; ++k) {
+        adam(net->w_off[k], int64_t(9) * kSpecs[k].cin * kSpecs[k].cout, net->wt[k], net->wd[k], kSpecs[k].cout,
+             kSpecs[k].cin);
+        adam(net->b_off[k], kSpecs[k].cout, nullptr, nullptr, 0, 0);
+    }
+    adam(net->hw_off, kCh[0] + 1, nullptr, nullptr, 0, 0);   // head weights and bias (contiguous)
+    return check(net);
+}
+
+fewha_status fewha_unet_destroy(fewha_unet* net) {
+    delete net;
+    return FEWHA_OK;
+}
+
+const char* fewha_unet_last_error(const fewha_unet* net) { return net ? net->err.c_str() : g_unet_err.c_str(); }
+
+}  // extern "C"

@@ -11,19 +11,23 @@ import synth
 import paper_2011_06842_amd as fw
 from paper_2011_06842_amd import _lib
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fewha.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+HEADER = os.path.join(INCLUDE, "fewha.h")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fewha_[a-z_A-Z]+)\s*\(", text)))
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if f.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, f)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(fewha_[a-z_A-Z]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     lib = fw.load_library()
     names = declared_functions()
-    assert len(names) >= 14
+    assert len(names) >= 30
     for name in names:
         assert hasattr(lib, name), name
     assert sorted(names) == sorted(fw.EXPORTS)
@@ -108,3 +112,29 @@ def test_batch_workspace_is_the_sum_of_its_instances_and_settings_must_agree():
     with pytest.raises(fw.FewhaError) as e:
         fw.fewha_workspace_size([a, bad])
     assert "instance 1" in str(e.value) and "power of two" in str(e.value)
+
+
+
+def test_unet_config_layout_and_validation(tmp_path):
+    import subprocess
+    src = tmp_path / "probe.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "fewha_unet.h"
+int main(void) { printf("%zu %zu\\n", sizeof(fewha_unet_config), offsetof(fewha_unet_config, lr)); return 0; }
+""")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    assert [int(v) for v in out] == [ctypes.sizeof(_lib.fewha_unet_config), _lib.fewha_unet_config.lr.offset]
+    lib = fw.load_library()
+    cfg = _lib.fewha_unet_config()
+    cfg.abi_version, cfg.n_groups = 1, 1
+    cfg.images[0], cfg.size[0] = 2, 24           # not a power of two
+    cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = 1e-3, 0.9, 0.999, 1e-8
+    n = ctypes.c_size_t()
+    assert lib.fewha_unet_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == 1
+    assert b"power of two" in lib.fewha_unet_last_error(None)
+    cfg.size[0] = 32
+    assert lib.fewha_unet_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == 0 and n.value > 0
