@@ -80,6 +80,26 @@ fewha_status fewha_unet_adam_step(fewha_unet* net, void* stream);
 /* Copy the gradients of the last fewha_unet_backward (device, FP32, network order). */
 fewha_status fewha_unet_get_grads(fewha_unet* net, float* d_grads, void* stream);
 
+/* Image groups of the context: images[g], size[g] for g < *n_groups (host arrays of
+ * FEWHA_UNET_MAX_GROUPS entries). */
+fewha_status fewha_unet_groups(const fewha_unet* net, int32_t* images, int32_t* size, int32_t* n_groups);
+
+/* Normalisation of the warm start: network inputs W^-1 c / scale_c and W^-1 J^-1 r / scale_r
+ * (then h_l / 20 km and gamma_l), output times scale_out is the nodal correction. */
+typedef struct {
+    float scale_c, scale_r, scale_out;
+} fewha_warmstart;
+
+/* One frame of Alg. 3 (see fewha_solve_aug) with a learned warm start between the residual
+ * update and the Galerkin step: the network's nodal correction d gives the candidate
+ * c + W d (W = delta^2 W^-T per layer) and its true residual b - M (c + W d), one extra
+ * operator application; the candidate replaces (c, r) only when that residual is smaller
+ * than the updated one (info flag bit 2: rejected).  ctx must hold a single instance whose
+ * layers, in order, are the network's images (consecutive equal-size layers form a group).
+ * Launches directly (no graph). */
+fewha_status fewha_solve_aug_ws(fewha_ctx* ctx, fewha_unet* net, const fewha_warmstart* ws, const void* d_s,
+                                void* d_c, void* d_info, void* stream);
+
 fewha_status fewha_unet_destroy(fewha_unet* net);
 const char* fewha_unet_last_error(const fewha_unet* net);
 

@@ -28,7 +28,8 @@ EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", 
            "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error",
            "fewha_unet_workspace_size", "fewha_unet_setup", "fewha_unet_num_params", "fewha_unet_num_nodes",
            "fewha_unet_set_params", "fewha_unet_get_params", "fewha_unet_forward", "fewha_unet_backward",
-           "fewha_unet_adam_step", "fewha_unet_get_grads", "fewha_unet_destroy", "fewha_unet_last_error"]
+           "fewha_unet_adam_step", "fewha_unet_get_grads", "fewha_unet_destroy", "fewha_unet_last_error",
+           "fewha_unet_groups", "fewha_solve_aug_ws"]
 UNET_MAX_GROUPS = 8
 
 
@@ -61,6 +62,10 @@ class fewha_unet_config(C.Structure):
     _fields_ = [("abi_version", C.c_int32), ("n_groups", C.c_int32), ("images", C.c_int32 * 8),
                 ("size", C.c_int32 * 8), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
                 ("eps", C.c_float)]
+
+
+class fewha_warmstart(C.Structure):
+    _fields_ = [("scale_c", C.c_float), ("scale_r", C.c_float), ("scale_out", C.c_float)]
 
 
 class FewhaError(RuntimeError):
@@ -116,6 +121,8 @@ def load_library(path: str = LIB_PATH):
         "fewha_unet_get_grads": ([vp, vp, vp], st),
         "fewha_unet_destroy": ([vp], st),
         "fewha_unet_last_error": ([vp], C.c_char_p),
+        "fewha_unet_groups": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
+        "fewha_solve_aug_ws": ([vp, vp, C.POINTER(fewha_warmstart), vp, vp, vp, vp], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -275,6 +282,17 @@ class FewhaContext:
         c = self._vec(self.N) if c is None else self._in(c, self.N)
         ip = _ptr(info) if info is not None else None
         _check(self.lib.fewha_solve_aug(self.ctx, _ptr(s), _ptr(c), ip, _stream(stream)), self.ctx)
+        return c
+
+    def fewha_solve_aug_ws(self, net, scales, s, c=None, info=None, stream=None):
+        """One frame warm-started by the U-Net `net` (UNetContext); scales = (scale_c,
+        scale_r, scale_out).  Returns c (device tensor)."""
+        s = self._in(s, self.S)
+        c = self._vec(self.N) if c is None else self._in(c, self.N)
+        ws = fewha_warmstart(*[float(v) for v in scales])
+        ip = _ptr(info) if info is not None else None
+        _check(self.lib.fewha_solve_aug_ws(self.ctx, net.net, C.byref(ws), _ptr(s), _ptr(c), ip, _stream(stream)),
+               self.ctx)
         return c
 
     def fewha_frame_iterations(self) -> int:

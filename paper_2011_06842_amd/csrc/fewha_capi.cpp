@@ -2,12 +2,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
 
 #include "fewha_internal.h"
+#include "../../include/fewha_unet.h"
 
 struct fewha_ctx {
     fewha::Ctx c;
@@ -163,6 +165,34 @@ fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d
     else
         e = fewha::launch_solve_frame<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
                                              as_stream(stream));
+    if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("frame launch failed: ") + hipGetErrorString(e));
+    return check_launch(ctx, as_stream(stream));
+}
+
+fewha_status fewha_solve_aug_ws(fewha_ctx* ctx, fewha_unet* net, const fewha_warmstart* ws, const void* d_s,
+                                void* d_c, void* d_info, void* stream) {
+    if (!ctx || !net || !ws || !d_s) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    fewha::Ctx& c = ctx->c;
+    if (c.B != 1) return fail(ctx, FEWHA_E_INVAL, "the warm start needs a single-instance context");
+    if (!(ws->scale_c > 0) || !(ws->scale_r > 0) || !std::isfinite(ws->scale_out))
+        return fail(ctx, FEWHA_E_INVAL, "bad warm-start scales");
+    int32_t images[FEWHA_UNET_MAX_GROUPS], size[FEWHA_UNET_MAX_GROUPS], G = 0;
+    fewha_unet_groups(net, images, size, &G);
+    int l = 0;
+    for (int g = 0; g < G; ++g)
+        for (int k = 0; k < images[g]; ++k, ++l)
+            if (l >= c.L || c.layers_n[l] != size[g])
+                return fail(ctx, FEWHA_E_INVAL, "the network's images do not match the layers");
+    if (l != c.L) return fail(ctx, FEWHA_E_INVAL, "the network's images do not match the layers");
+    const fewha::WarmStart w{net, ws->scale_c, ws->scale_r, ws->scale_out};
+    auto* info = static_cast<fewha_solve_info*>(d_info);
+    hipError_t e;
+    if (c.prec == FEWHA_FP64)
+        e = fewha::launch_solve_frame_ws<double>(c, w, static_cast<const double*>(d_s), static_cast<double*>(d_c), info,
+                                                 as_stream(stream));
+    else
+        e = fewha::launch_solve_frame_ws<float>(c, w, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
+                                                as_stream(stream));
     if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("frame launch failed: ") + hipGetErrorString(e));
     return check_launch(ctx, as_stream(stream));
 }

@@ -120,6 +120,7 @@ struct Scalars {
     int32_t keep[kKMax];
     int32_t flags, dropped, used, iters;
     int32_t conv_iter;    // tolerance mode: first iteration whose residual met the tolerance (0: not yet)
+    int32_t ws_state;     // warm start of this frame: 0 none, 1 accepted, 2 rejected
 };
 
 // Byte layout of the workspace (offsets from its base).
@@ -130,6 +131,7 @@ struct Layout {
     size_t c, r, z, b, b_prev, s_in;
     size_t ring_u, ring_q;
     size_t partials, pq_part, gram_part, scalars, info, done;
+    size_t ws_in, ws_out, lconst;   // warm start: network input (N x 4 FP32), output (N FP32), layer constants
     size_t total;
     size_t state_bytes;
 };
@@ -167,6 +169,7 @@ struct Ctx {
     int gather_grid = 0;       // workgroups of the gather (layer tiles, padded to kXcds)
     int gather_rows = 1;       // layer rows per gather thread (tile of 8 gather_rows x kGT nodes)
     std::vector<InstDev> insts;
+    std::vector<int> layers_n;     // grid size of every layer (host)
     std::vector<int64_t> s_offs;   // slope offsets of the instances (B + 1)
     int prec = 0;              // fewha_precision
     size_t esz = 8;            // element size
@@ -225,6 +228,13 @@ template <typename T> void launch_apply_M(const Ctx& c, const T* x, T* y, double
 template <typename T> void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s);
 template <typename T> hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info,
                                                    hipStream_t s);
+// Warm start of a frame by the U-Net (include/fewha_unet.h): input/output scales.
+struct WarmStart {
+    void* net;                 // fewha_unet*
+    float scale_c, scale_r, scale_out;
+};
+template <typename T> hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& w, const T* slopes, T* c_out,
+                                                      fewha_solve_info* info, hipStream_t s);
 void release_graphs(Ctx& c);
 template <typename T> hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t s, float* ms);
 

@@ -288,6 +288,9 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.scalars = take(sizeof(Scalars) * z.B);
     lo.info = take(sizeof(fewha_solve_info) * z.B);
     lo.done = take(sizeof(int32_t) * z.B);
+    lo.ws_in = take(sizeof(float) * 4 * N);
+    lo.ws_out = take(sizeof(float) * N);
+    lo.lconst = take(sizeof(float) * 2 * z.L);
     lo.total = o;
     lo.state_bytes = 256 + sizeof(double) * size_t(z.B) * z.slots + e * N * (3 + 2 * size_t(z.slots));
     return lo;
@@ -603,7 +606,9 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
         for (int i = 0; i < nb; ++i)   // the device keeps alpha D
             for (int64_t j = 0; j < ctx.insts[i].n; ++j) t.D[ctx.insts[i].off + j] *= cfgs[i].alpha;
     }
+    ctx.layers_n.clear();
     for (const LayerDev& d : t.ld) {
+        ctx.layers_n.push_back(d.n);
         ctx.max_levels = std::max(ctx.max_levels, int(d.levels));
         ctx.max_n = std::max(ctx.max_n, int(d.n));
     }
@@ -664,6 +669,14 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     else
         build_recs(double{});
 
+    // warm-start layer constants: height / 20 km and turbulence weight of every layer
+    std::vector<float> lconst;
+    for (int i = 0; i < nb; ++i)
+        for (int l = 0; l < cfgs[i].n_layers; ++l) {
+            lconst.push_back(float(cfgs[i].layers[l].height / 20000.0));
+            lconst.push_back(float(cfgs[i].layers[l].weight));
+        }
+
     // ---- upload (typed copies of the floating tables)
     const Layout& lo = ctx.lay;
     auto up = [&](size_t dst, const void* src, size_t bytes) -> bool {
@@ -697,6 +710,7 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
               up(lo.gather_tiles, gtiles.data(), sizeof(int2) * gtiles.size()) &&
               up(lo.grecs, recs.data(), recs.size()) &&
               up(lo.recbase, recbase.data(), sizeof(int64_t) * recbase.size()) &&
+              up(lo.lconst, lconst.data(), sizeof(float) * lconst.size()) &&
               up(lo.weight, w_t.data(), w_t.size()) && up(lo.prior_a, pa_t.data(), pa_t.size()) &&
               up(lo.jinv, j_t.data(), j_t.size());
     if (ok) ok = hipStreamSynchronize(stream) == hipSuccess;   // host vectors die at return

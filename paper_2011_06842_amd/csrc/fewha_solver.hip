@@ -21,6 +21,7 @@
 
 #include "fewha_device.h"
 #include "fewha_internal.h"
+#include "../../include/fewha_unet.h"
 
 namespace fewha {
 
@@ -218,6 +219,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* 
         sc->used = m;
         sc->dropped = 0;
         sc->conv_iter = 0;
+        sc->ws_state = 0;
     }
 }
 
@@ -642,12 +644,99 @@ __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, 
         in.iters = tol_mode && sc->conv_iter ? sc->conv_iter : iters;
         in.recycle_used = sc->used;
         in.dropped = sc->dropped;
-        in.flags = sc->flags | (tol_mode && !sc->conv_iter ? 2 : 0);
+        in.flags = sc->flags | (tol_mode && !sc->conv_iter ? 2 : 0) | (sc->ws_state == 2 ? 4 : 0);
         in.rel_res = v[0] > 0 ? sqrt(v[1] / v[0]) : 0.0;
         sc->bb = v[0];
         sc->rr = v[1];
         *info = in;
         if (info_user) *info_user = in;
+    }
+}
+
+// ------------------------------------------------------------------ warm start
+
+// z = J^-1 r
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_scale(int64_t N, const T* __restrict__ jinv, const T* __restrict__ r,
+                                                     T* __restrict__ z) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < N) z[i] = jinv[i] * r[i];
+}
+
+__device__ __forceinline__ int layer_of(const LayerDev* __restrict__ lays, int L, int64_t i) {
+    int lo = 0, hi = L - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lays[mid].off <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// network input of node i: [W^-1 c / s_c, W^-1 J^-1 r / s_r, h / 20 km, gamma] (FP32)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ws_pack(int64_t N, const LayerDev* __restrict__ lays, int L,
+                                                       const float2* __restrict__ lconst, const T* __restrict__ pc,
+                                                       const T* __restrict__ pr, float isc, float isr,
+                                                       float* __restrict__ in) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= N) return;
+    const float2 k = lconst[layer_of(lays, L, i)];
+    reinterpret_cast<float4*>(in)[i] = make_float4(float(pc[i]) * isc, float(pr[i]) * isr, k.x, k.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ws_unpack(int64_t N, const float* __restrict__ out, float so,
+                                                         T* __restrict__ d) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < N) d[i] = T(out[i] * so);
+}
+
+// candidate c + W d with W = delta^2 W^-T (W^-1 = DWT^T / delta, DWT orthonormal)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ws_candidate(int64_t N, const LayerDev* __restrict__ lays, int L,
+                                                            const T* __restrict__ c, const T* __restrict__ wtd,
+                                                            T* __restrict__ cw) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= N) return;
+    const double id = lays[layer_of(lays, L, i)].inv_delta;
+    cw[i] = T(double(c[i]) + double(wtd[i]) / (id * id));
+}
+
+// rw = b - M cw (in place over M cw); partials of (rw, rw) and (r, r) in rows P_PROJ, P_PROJ + 1
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ws_residual(int64_t N, const VecBlk* __restrict__ vb, int pstride,
+                                                           const T* __restrict__ b, T* __restrict__ rw,
+                                                           const T* __restrict__ r, double* __restrict__ part) {
+    const Seg sg = seg_of(vb, N, 0);
+    double a = 0, o = 0;
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
+        const T v = T(double(b[i]) - double(rw[i]));
+        rw[i] = v;
+        a += double(v) * double(v);
+        o += double(r[i]) * double(r[i]);
+    }
+    const double vv[2] = {a, o};
+    block_partials<2>(vv, part, P_PROJ, pstride, sg.col);
+}
+
+// keep the candidate when its residual is smaller than the updated one
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ws_select(int64_t N, const VecBlk* __restrict__ vb, int pstride,
+                                                         const double* __restrict__ part, T* __restrict__ c,
+                                                         T* __restrict__ r, const T* __restrict__ cw,
+                                                         const T* __restrict__ rw, Scalars* __restrict__ scs) {
+    const Seg sg = seg_of(vb, N, 0);
+    double v[2];
+    block_row_sums<2>(part, pstride, sg, P_PROJ, 2, v);
+    const bool take = v[0] < v[1];
+    if (sg.local == 0 && threadIdx.x == 0) scs[sg.inst].ws_state = take ? 1 : 2;
+    if (!take) return;
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
+        c[i] = cw[i];
+        r[i] = rw[i];
     }
 }
 
@@ -729,7 +818,7 @@ struct Frame {
     int64_t N;
     int K, m, mb, mp, mpb;
     SlotList act, actp, pl;
-    T *b, *bp, *r, *z, *cv, *vx, *U, *Q;
+    T *b, *bp, *r, *z, *cv, *vx, *vy, *U, *Q;
     const T* jinv;
     double *part, *pqp, *gpart;
     Scalars* sc;
@@ -748,6 +837,7 @@ struct Frame {
         z = c.at<T>(c.lay.z);
         cv = c.at<T>(c.lay.c);
         vx = c.at<T>(c.lay.vx);
+        vy = c.at<T>(c.lay.vy);
         U = c.at<T>(c.lay.ring_u);
         Q = c.at<T>(c.lay.ring_q);
         jinv = c.at<T>(c.lay.jinv);
@@ -784,17 +874,20 @@ struct Frame {
     }
 };
 
-// a1 - a4: right-hand side, residual update, Galerkin step and initial direction.
+// a1 + a2: right-hand side and residual update.
 template <typename T>
-void enqueue_prologue(const Ctx& c, const Frame<T>& f, const T* slopes, hipStream_t s) {
-    const int m = f.m;
+void enqueue_rhs_residual(const Ctx& c, const Frame<T>& f, const T* slopes, hipStream_t s) {
     launch_rhs<T>(c, slopes, f.b, s);
     if (c.first) launch_apply_M<T>(c, f.cv, f.vx, nullptr, s);
-    {
-        ProfScope ps_(c, KID_RESIDUAL, s);
-        k_residual<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.b, f.bp, f.r,
-                                                     c.first ? f.vx : nullptr, f.part, f.sc, m);
-    }
+    ProfScope ps_(c, KID_RESIDUAL, s);
+    k_residual<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.b, f.bp, f.r,
+                                                 c.first ? f.vx : nullptr, f.part, f.sc, f.m);
+}
+
+// a3 + a4: Galerkin step and initial direction.
+template <typename T>
+void enqueue_galerkin_init(const Ctx& c, const Frame<T>& f, hipStream_t s) {
+    const int m = f.m;
     T* p0 = f.U + size_t(c.head) * f.N;
     if (m > 0) {
         {
@@ -856,24 +949,29 @@ void enqueue_finish(const Ctx& c, const Frame<T>& f, int iters, fewha_solve_info
 template <typename T>
 void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s) {
     const Frame<T> f(c);
-    enqueue_prologue<T>(c, f, slopes, s);
+    enqueue_rhs_residual<T>(c, f, slopes, s);
+    enqueue_galerkin_init<T>(c, f, s);
     for (int it = 0; it < c.max_iter; ++it) enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
     enqueue_finish<T>(c, f, c.max_iter, info_user, s);
 }
 
-// Tolerance mode: the instances iterate in lock step (the recycle ring stays shared); after
-// every iteration each instance records when it first met the tolerance, and every
-// check_every iterations the host reads the done flags and stops once all are set.
-template <typename T>
-hipError_t run_tolerance_frame(Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s, int* iters) {
+// Frame with direct launches: fixed count, or tolerance mode (the instances iterate in lock
+// step, the recycle ring stays shared; after every iteration each instance records when it
+// first met the tolerance, and every check_every iterations the host reads the done flags
+// and stops once all are set).  `between` runs after the residual update (a warm start).
+template <typename T, typename Hook>
+hipError_t run_frame(Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s, int* iters, Hook between) {
     const Frame<T> f(c);
     int32_t* done = c.at<int32_t>(c.lay.done);
     std::vector<int32_t> hdone(c.B);
-    enqueue_prologue<T>(c, f, slopes, s);
+    enqueue_rhs_residual<T>(c, f, slopes, s);
+    hipError_t e = between(f);
+    if (e != hipSuccess) return e;
+    enqueue_galerkin_init<T>(c, f, s);
     int it = 0;
-    hipError_t e = hipSuccess;
     for (; it < c.max_iter; ++it) {
         enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
+        if (c.rel_tol <= 0) continue;
         k_check<<<c.B, kThreads, 0, s>>>(f.sc, f.insts, f.vl.pstride, f.part, it + 1, c.rel_tol, done);
         if ((it + 1) % c.check_every == 0 && it + 1 < c.max_iter) {
             e = hipMemcpyAsync(hdone.data(), done, sizeof(int32_t) * c.B, hipMemcpyDeviceToHost, s);
@@ -891,16 +989,29 @@ hipError_t run_tolerance_frame(Ctx& c, const T* slopes, fewha_solve_info* info_u
     return e;
 }
 
+// Host ring bookkeeping after a frame of `iters` iterations, and the coefficient copy.
+template <typename T>
+hipError_t end_frame(Ctx& c, T* c_out, int iters, hipError_t e, hipStream_t s) {
+    if (e == hipSuccess && c_out)
+        e = hipMemcpyAsync(c_out, c.at<T>(c.lay.c), sizeof(T) * c.N, hipMemcpyDeviceToDevice, s);
+    const int K = c.slots;
+    c.head = (c.head + iters) % K;
+    c.count = std::min(c.count + iters, K);
+    c.last_iters = iters;
+    c.frame_iters = iters;
+    c.first = false;
+    return e;
+}
+
 template <typename T>
 hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info_user, hipStream_t s) {
-    const int64_t N = c.N;
     int m = 0;
     if (!c.first && c.k > 0)
         m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
     hipError_t e = hipSuccess;
     int iters = c.max_iter;
     if (c.rel_tol > 0) {
-        e = run_tolerance_frame<T>(c, slopes, info_user, s, &iters);
+        e = run_frame<T>(c, slopes, info_user, s, &iters, [](const Frame<T>&) { return hipSuccess; });
     } else if (c.use_graphs && !c.prof.on) {
         // the graph reads the slopes from, and writes the frame statistics to, context buffers
         T* s_in = c.at<T>(c.lay.s_in);
@@ -928,15 +1039,43 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
     } else {
         enqueue_frame<T>(c, slopes, info_user, s);
     }
-    if (e == hipSuccess && c_out) e = hipMemcpyAsync(c_out, c.at<T>(c.lay.c), sizeof(T) * N, hipMemcpyDeviceToDevice, s);
-    // a7: ring bookkeeping (the host knows every frame's iteration count)
-    const int K = c.slots;
-    c.head = (c.head + iters) % K;
-    c.count = std::min(c.count + iters, K);
-    c.last_iters = iters;
-    c.frame_iters = iters;
-    c.first = false;
-    return e;
+    return end_frame<T>(c, c_out, iters, e, s);
+}
+
+// Warm-started frame: after the residual update, the network maps [W^-1 c, W^-1 J^-1 r,
+// h / 20 km, gamma] of every layer to a nodal correction d; the candidate c + W d
+// (W = delta^2 W^-T) and its true residual b - M (c + W d) replace (c, r) when that residual
+// is smaller than the updated one (plain augmented PCG judges the correction); then the
+// Galerkin step, the initial direction and the iterations as in any frame.
+template <typename T>
+hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& w, const T* slopes, T* c_out, fewha_solve_info* info_user,
+                                 hipStream_t s) {
+    int iters = c.max_iter;
+    const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
+    float* in = c.at<float>(c.lay.ws_in);
+    float* out = c.at<float>(c.lay.ws_out);
+    T* nod = c.at<T>(c.lay.nodal);
+    T* nod_r = c.at<T>(c.lay.psi_layers);
+    auto hook = [&](const Frame<T>& f) -> hipError_t {
+        const unsigned gN = unsigned((f.N + kThreads - 1) / kThreads);
+        k_scale<T><<<gN, kThreads, 0, s>>>(f.N, f.jinv, f.r, f.z);            // z = J^-1 r
+        launch_winv<T>(c, f.cv, nod, s);                                      // W^-1 c
+        launch_winv<T>(c, f.z, nod_r, s);                                     // W^-1 J^-1 r
+        k_ws_pack<T><<<gN, kThreads, 0, s>>>(f.N, lays, c.L, c.at<float2>(c.lay.lconst), nod, nod_r, 1.f / w.scale_c,
+                                            1.f / w.scale_r, in);
+        const fewha_status st = fewha_unet_forward(static_cast<fewha_unet*>(w.net), in, out, s);
+        if (st != FEWHA_OK) return hipErrorLaunchFailure;
+        k_ws_unpack<T><<<gN, kThreads, 0, s>>>(f.N, out, w.scale_out, nod);   // d (nodal)
+        launch_winvt<T>(c, nod, f.z, static_cast<const T*>(nullptr), nullptr, s);   // W^-T d
+        k_ws_candidate<T><<<gN, kThreads, 0, s>>>(f.N, lays, c.L, f.cv, f.z, f.vy);  // c + delta^2 W^-T d
+        launch_apply_M<T>(c, f.vy, f.vx, nullptr, s);
+        k_ws_residual<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.b, f.vx, f.r, f.part);
+        k_ws_select<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.part, f.cv, f.r, f.vy, f.vx,
+                                                      f.sc);
+        return hipGetLastError();
+    };
+    const hipError_t e = run_frame<T>(c, slopes, info_user, s, &iters, hook);
+    return end_frame<T>(c, c_out, iters, e, s);
 }
 
 void release_graphs(Ctx& c) {
@@ -948,5 +1087,9 @@ void release_graphs(Ctx& c) {
 
 template hipError_t launch_solve_frame<float>(Ctx&, const float*, float*, fewha_solve_info*, hipStream_t);
 template hipError_t launch_solve_frame<double>(Ctx&, const double*, double*, fewha_solve_info*, hipStream_t);
+template hipError_t launch_solve_frame_ws<float>(Ctx&, const WarmStart&, const float*, float*, fewha_solve_info*,
+                                                 hipStream_t);
+template hipError_t launch_solve_frame_ws<double>(Ctx&, const WarmStart&, const double*, double*, fewha_solve_info*,
+                                                  hipStream_t);
 
 }  // namespace fewha

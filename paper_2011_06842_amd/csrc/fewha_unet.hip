@@ -895,6 +895,16 @@ fewha_status fewha_unet_adam_step(fewha_unet* net, void* stream) {
     return check(net);
 }
 
+fewha_status fewha_unet_groups(const fewha_unet* net, int32_t* images, int32_t* size, int32_t* n_groups) {
+    if (!net) return FEWHA_E_INVAL;
+    for (int g = 0; g < net->G; ++g) {
+        if (images) images[g] = net->images[g];
+        if (size) size[g] = net->size[g];
+    }
+    if (n_groups) *n_groups = net->G;
+    return FEWHA_OK;
+}
+
 fewha_status fewha_unet_destroy(fewha_unet* net) {
     delete net;
     return FEWHA_OK;
