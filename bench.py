@@ -328,6 +328,151 @@ def run_ragged(args, dev):
     }
 
 
+UNET_CONVS = [(32, 32, 0), (32, 32, 0), (32, 64, 1), (64, 64, 1), (64, 128, 2), (128, 128, 2), (128, 256, 3),
+              (256, 256, 3), (384, 128, 2), (128, 128, 2), (192, 64, 1), (64, 64, 1), (96, 32, 0), (32, 32, 0)]
+BF16_PEAK_TFS = 2500.0
+
+
+def unet_forward_flops(groups):
+    """Matrix-core flops the forward pass executes (padded input channels included)."""
+    f = 0
+    for n, size in groups:
+        for cin, cout, lev in UNET_CONVS:
+            f += 2 * n * (size >> lev) ** 2 * 9 * cin * cout
+    return f
+
+
+def run_unet(args, dev):
+    """U-Net on one ELT frame (a 256^2 ground layer and eight 128^2 layers): forward and one
+    training step (forward, backward, Adam), timed with HIP events on the context's stream."""
+    import numpy as np
+    import torch
+
+    import paper_2011_06842_amd as fw
+    from paper_2011_06842_amd import warmstart as W
+
+    groups = [(1, 256), (8, 128)]
+    net = fw.UNetContext(groups, device=dev)
+    rng = np.random.default_rng(SEED)
+    net.set_params(W.init_params(net.n_params, None, SEED, dev) + 0.01)
+    x = torch.from_numpy(rng.standard_normal(4 * net.nodes).astype(np.float32)).to(dev)
+    t = torch.from_numpy(rng.standard_normal(net.nodes).astype(np.float32)).to(dev)
+    out = torch.empty(net.nodes, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        net.forward(x, out)
+    torch.cuda.synchronize()
+    R = args.unet_reps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(R):
+        net.forward(x, out)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / R
+    net.backward(x, t)
+    net.adam_step()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(R):
+        net.backward(x, t)
+        net.adam_step()
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / R
+    ff = unet_forward_flops(groups)
+    ach = ff / (fwd_ms * 1e-3) / 1e12
+    log(f"U-Net: forward {fwd_ms:.3f} ms ({ach:.1f} TFLOP/s), training step {train_ms:.3f} ms")
+    return {
+        "workload": "unet_4level_32-256ch_elt_frame (1x256^2 + 8x128^2 images)",
+        "params": net.n_params, "forward_ms": round(fwd_ms, 4), "train_step_ms": round(train_ms, 4),
+        "forward_gflop": round(ff / 1e9, 2), "train_step_gflop": round(3 * ff / 1e9, 2),
+        "roofline": {"bound": "mfma", "kernel": "forward (all layers)", "achieved": round(ach, 2),
+                     "peak": BF16_PEAK_TFS, "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFS, 4),
+                     "traffic": None},
+        "train_tflops": round(3 * ff / (train_ms * 1e-3) / 1e12, 2),
+    }
+
+
+def run_warmstart(args, dev):
+    """Plain versus learned-warm-start augmented PCG at equal final residual (tolerance 1e-3,
+    the 8 m NGS system): the network is trained here on converged solves of two seeded
+    sequences and evaluated on a third; plus the per-frame cost of the warm start on the ELT
+    frame (fixed 6 iterations, untrained network: correction, transforms and the extra apply)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2011_06842_amd as fw
+    from paper_2011_06842_amd import warmstart as W
+
+    tol, cap = 1e-3, 120
+    t0 = time.perf_counter()
+    cal = [synth.config_small() for _ in range(3)]
+    seqs = [synth.make_sequence(sp, args.ws_frames, seed=s) for sp, s in zip(cal, (21, 22, 23))]
+    spec = cal[0].copy(rel_tol=tol, max_iter=cap)
+    truth = cal[0].copy(rel_tol=1e-6, max_iter=256)
+    xs, ys = [], []
+    for sq in seqs[:2]:
+        x, y = W.collect(spec, fw.FewhaContext(spec, device=dev), fw.FewhaContext(truth, device=dev), sq, dev)
+        xs.append(x)
+        ys.append(y)
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    scales = W.scales_of(x, y)
+    xn, yn = W.normalise(x, y, scales)
+    params, losses = W.train(spec, xn, yn, batch=4, epochs=args.ws_epochs, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    net = W.inference_net(spec, params, dev)
+    res = {}
+    for name in ("plain", "warm"):
+        ctx = fw.FewhaContext(spec, device=dev)
+        info = ctx.new_info()
+        ms, its = [], []
+        for t in range(seqs[2].shape[0]):
+            s = torch.from_numpy(seqs[2][t]).to(dev)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            if name == "plain":
+                ctx.fewha_solve_aug(s, info=info)
+            else:
+                ctx.fewha_solve_aug_ws(net, scales, s, info=info)
+            torch.cuda.synchronize()
+            if t > 0:
+                ms.append(1000 * (time.perf_counter() - w0))
+                its.append(fw.decode_info(info)["iters"])
+        res[name] = {"iterations_to_tol_mean": round(float(np.mean(its)), 2),
+                     "frame_ms_p50": round(float(np.percentile(ms, 50)), 3),
+                     "frame_ms_p99": round(float(np.percentile(ms, 99)), 3)}
+    # cost of the warm start on the ELT frame (fixed iterations, zero-correction network)
+    elt = synth.config_elt_mcao(precision="fp32")
+    sq = synth.make_sequence(elt, 12, seed=SEED + 5).astype(np.float32)
+    enet = W.inference_net(elt, W.init_params(fw.UNetContext(W.layer_groups(elt), device=dev).n_params, elt, 0,
+                                              dev), dev)
+    cost = {}
+    for name in ("plain_direct", "warm"):
+        ctx = fw.FewhaContext(elt, device=dev)
+        ctx.fewha_use_graphs(False)
+        ev = []
+        for t in range(12):
+            s = torch.from_numpy(sq[t]).to(dev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            if name == "warm":
+                ctx.fewha_solve_aug_ws(enet, (1.0, 1.0, 1.0), s)
+            else:
+                ctx.fewha_solve_aug(s)
+            e1.record()
+            torch.cuda.synchronize()
+            if t >= 2:
+                ev.append(e0.elapsed_time(e1))
+        cost[name + "_frame_ms_p50"] = round(float(np.median(ev)), 4)
+    log(f"warm start: iterations {res['plain']['iterations_to_tol_mean']} -> {res['warm']['iterations_to_tol_mean']}, "
+        f"ELT frame {cost['plain_direct_frame_ms_p50']} -> {cost['warm_frame_ms_p50']} ms")
+    return {"workload": "small_ngs_fp64 tolerance 1e-3 (train 2 x %d frames, evaluate 1 x %d)" % (args.ws_frames,
+                                                                                              args.ws_frames),
+            "training_loss_first_last": [round(losses[0], 4), round(losses[-1], 4)],
+            "train_and_collect_s": round(t_train, 1), **res, "elt_frame_cost": cost}
+
+
 def synth_n(spec):
     return int(sum(l.n * l.n for l in spec.layers))
 
@@ -349,6 +494,11 @@ def main(argv=None):
     ap.add_argument("--ragged", type=int, default=64, help="instances of the ragged tolerance leg (0: skip)")
     ap.add_argument("--ragged-steps", type=int, default=8)
     ap.add_argument("--ragged-warmup", type=int, default=2)
+    ap.add_argument("--unet", type=int, default=1, help="U-Net timing leg (0: skip)")
+    ap.add_argument("--unet-reps", type=int, default=10)
+    ap.add_argument("--warmstart", type=int, default=1, help="warm-start comparison leg (0: skip)")
+    ap.add_argument("--ws-frames", type=int, default=24)
+    ap.add_argument("--ws-epochs", type=int, default=25)
     args = ap.parse_args(argv)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
@@ -518,6 +668,12 @@ def main(argv=None):
         torch.cuda.empty_cache()
     if args.ragged > 0:
         out["ragged"] = run_ragged(args, dev)
+        torch.cuda.empty_cache()
+    if args.unet:
+        out["unet"] = run_unet(args, dev)
+        torch.cuda.empty_cache()
+    if args.warmstart:
+        out["warmstart"] = run_warmstart(args, dev)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -134,7 +134,8 @@ def init_params(n_params, spec, seed, device="cuda"):
         parts += [w.ravel(), np.zeros(cout)]
     parts += [np.zeros(32), np.zeros(1)]
     v = np.concatenate(parts).astype(np.float32)
-    assert v.size == n_params
+    if v.size != n_params:
+        raise ValueError(f"parameter count {v.size} != network's {n_params}")
     return torch.from_numpy(v).to(device)
 
 
