@@ -10,7 +10,7 @@
  *
  * Conventions
  *  - Images are grouped by size: group g holds images[g] images of size[g] x size[g] nodes
- *    (size a power of two >= 16).  Inputs are FP32 NHWC with 4 channels per node, groups one
+ *    (size a power of two in [16, 4096], at most 2^25 nodes per group).  Inputs are FP32 NHWC with 4 channels per node, groups one
  *    after the other; outputs are FP32, one value per node, in the same order.
  *  - Parameters are one FP32 vector in the order of the network: for each 3x3 convolution
  *    e0a e0b e1a e1b e2a e2b e3a e3b d2a d2b d1a d1b d0a d0b its weights [3][3][Cin][Cout]

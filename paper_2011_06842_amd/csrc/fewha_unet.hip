@@ -8,9 +8,10 @@
 //                  concatenation are folded into the operand loads; the input gradient is
 //                  the same kernel on the ReLU-masked output gradient with flipped,
 //                  transposed weights.
-//   k_conv_wgrad   weight gradient sum_p x[p + tap][ci] dy[p][co]: tiles of 32 pixels are
-//                  transposed through LDS so that every MFMA operand is one 16-byte read;
-//                  per-chunk FP32 partials, summed in a fixed order by k_reduce_chunks.
+//   k_conv_wgrad   weight gradient sum_p x[p + tap][ci] dy[p][co] of all nine taps and the
+//                  bias gradient sum_p dy[p][co]: tiles of 64 pixels are transposed through LDS
+//                  so that every MFMA operand is one 16-byte read; per-chunk FP32 partials,
+//                  summed in a fixed order by k_reduce_table (one launch for the network).
 //   small kernels  input packing, pooling and its adjoint, the upsample/concat adjoint, the
 //                  1x1 head with the MSE loss, ReLU', bias gradients, Adam, layouts.
 #include <hip/hip_runtime.h>
@@ -31,9 +32,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t bf16_t;   // bfloat16 storage
 
 constexpr int kT = 256;            // threads of every kernel
-constexpr int kConvPix = 128;      // pixels per convolution workgroup
-constexpr int kWChunk = 2048;      // pixels per weight-gradient workgroup
-constexpr int kBChunk = 2048;      // pixels per bias-gradient workgroup
+constexpr int kConvPix = 256;      // pixels per convolution workgroup (without a reduction split)
+constexpr int kWBlocks = 768;      // weight-gradient workgroups aimed at per convolution (3 per CU)
 constexpr int kLevels = 4;
 constexpr int kCh[kLevels] = {32, 64, 128, 256};
 constexpr int kInCh = 32;          // padded input channels
@@ -65,171 +65,387 @@ enum { CONV_DIRECT = 0, CONV_CONCAT_UP = 1 };
 
 // MODE CONV_DIRECT: in0 [N][H][W][Cin].  MODE CONV_CONCAT_UP: channels [0, C1) come from the
 // 2x nearest upsampling of in0 [N][H/2][W/2][C1], channels [C1, Cin) from in1 [N][H][W][Cin-C1].
+// Every input tensor carries one extra pixel of zeros after its last pixel (the zero row):
+// operands outside the image read it, so the zero padding costs no masking.
 // OUT_BF16: out = bf16(relu?(acc + bias)) [P][Cout]; else out = acc (FP32) [P][Cout].
-// Cin, C1, Cout multiples of 32.
-template <int MODE, bool OUT_BF16>
+// Cin, C1, Cout multiples of 32.  A wavefront computes 64 pixels x 32 output channels (4 x 2
+// MFMA tiles of 16 x 16, K = 32 channels of one tap per reduction position).  KS (1, 2 or 4)
+// splits the reduction over the wavefronts of a workgroup: the workgroup covers 256 / KS
+// pixels, wavefront w the 64 pixels w mod (4 / KS) and every KS-th reduction position from
+// w / (4 / KS); the KS partial tiles are summed in a fixed order through LDS.  Requires
+// 9 Cin / 32 to be a multiple of 3 KS.  Byte offsets into the inputs must fit in 32 bits
+// (with at most 2^25 pixels per level and 64 bytes per full-resolution pixel they do).
+template <int MODE, bool OUT_BF16, int KS>
 __global__ void __launch_bounds__(kT) k_conv3x3(const bf16_t* __restrict__ in0, const bf16_t* __restrict__ in1,
                                                  int C1, int Cin, int N, int H, int W,
                                                  const bf16_t* __restrict__ wt, const float* __restrict__ bias,
                                                  int relu, void* __restrict__ out, int Cout) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int PG = 4 / KS;            // 64-pixel groups per workgroup
+    constexpr int MT = 4;                 // 16-pixel MFMA tiles per wavefront
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar position counters
     const int r16 = lane & 15, kg = lane >> 4;
+    const int pg = wv % PG, ks = wv / PG;
     const int P = N * H * W;
     const int co0 = blockIdx.y * 32;
-    const int pb = blockIdx.x * kConvPix + wv * 32;
-    int pn[2], py[2], px[2];
-    bool pin[2];
+    const int pb = blockIdx.x * (64 * PG) + pg * 64;
+    const int C2 = Cin - C1, Hh = H >> 1, Wh = W >> 1, Ph = N * Hh * Wh;
+    const int lh = __builtin_ctz(H), lw = __builtin_ctz(W);   // H, W powers of two
+    // per MFMA row tile: the in-image bits of the lane's nine taps, the element offset of its
+    // pixel in the full-resolution input (in0, or in1 when concatenating), and for the
+    // upsampled input its half-resolution pixel and the parities of its coordinates
+    const int Cf = MODE == CONV_DIRECT ? Cin : C2;
+    uint32_t okbits[MT], oc[MT], hc[MT], par[MT];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
+    for (int mt = 0; mt < MT; ++mt) {
         const int p = pb + 16 * mt + r16;
-        pin[mt] = p < P;
-        const int pc = pin[mt] ? p : 0;
-        pn[mt] = pc / (H * W);
-        const int rem = pc - pn[mt] * H * W;
-        py[mt] = rem / W;
-        px[mt] = rem - py[mt] * W;
-    }
-    const int C2 = Cin - C1, Hh = H >> 1, Wh = W >> 1;
-    f32x4 acc[2][2];
+        const bool pin = p < P;
+        const int pc = pin ? p : 0;
+        const int pn = pc >> (lh + lw), py = (pc >> lw) & (H - 1), px = pc & (W - 1);
+        uint32_t bits = 0;
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+        for (int t = 0; t < 9; ++t) {
+            const int ys = py + t / 3 - 1, xs = px + t % 3 - 1;
+            bits |= uint32_t(pin & (unsigned(ys) < unsigned(H)) & (unsigned(xs) < unsigned(W))) << t;
+        }
+        okbits[mt] = bits;
+        oc[mt] = (uint32_t(pc) * Cf + 8 * kg) * 2u;                // byte offsets from here on
+        hc[mt] = uint32_t((pn * Hh + (py >> 1)) * Wh + (px >> 1));
+        par[mt] = uint32_t((py & 1) | ((px & 1) << 1));
+    }
+    const uint32_t oz = (uint32_t(P) * Cf + 8 * kg) * 2u;          // the zero row
+    const uint32_t ozh = (uint32_t(Ph) * C1 + 8 * kg) * 2u;
+    // weight offsets (elements) of the lane's two output-channel rows, relative to a tap's
+    // [Cout][Cin] block
+    uint32_t ob[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) ob[nt] = (uint32_t(co0 + 16 * nt + r16) * Cin + 8 * kg) * 2u;
+
+    f32x4 acc[MT][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        size_t off0[2], off1[2];
-        uint32_t vm[2];
+    // The reduction runs over (tap, 32-channel block) positions.  Operands are fetched two
+    // positions ahead into a ring of three register sets, so that every MFMA waits only for
+    // loads issued two positions earlier; fetches past the wavefront's last position repeat
+    // the last tap (valid addresses, unused values).
+    int ftap = 0, fcb = 32 * ks;          // Cin / 32 >= KS, so the first position is in tap 0
+    auto fetch = [&](uint4 (&a)[MT], uint4 (&b)[2]) {
+        const int dy = ftap / 3 - 1, dx = ftap - 3 * (ftap / 3) - 1;
+        const uint32_t shift = uint32_t((dy * W + dx) * Cf) * 2u;   // uniform
+        const bool upsampled = MODE == CONV_CONCAT_UP && fcb < C1;
+        const char* base = reinterpret_cast<const char*>(MODE == CONV_DIRECT ? in0 + fcb
+                                                         : upsampled         ? in0 + fcb
+                                                                             : in1 + (fcb - C1));
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            const int ys = py[mt] + dy, xs = px[mt] + dx;
-            const bool ok = pin[mt] && ys >= 0 && ys < H && xs >= 0 && xs < W;
-            const int yc = ok ? ys : 0, xc = ok ? xs : 0;     // clamped: a valid address, zeroed below
-            if (MODE == CONV_DIRECT) {
-                off0[mt] = (size_t(pn[mt] * H + yc) * W + xc) * Cin;
-                off1[mt] = 0;
+        for (int mt = 0; mt < MT; ++mt) {
+            const bool ok = (okbits[mt] >> ftap) & 1u;
+            uint32_t off;
+            if (upsampled) {
+                // half-resolution pixel of the shifted full-resolution pixel: floor((2y' + e + d) / 2)
+                const int sy = (int(par[mt] & 1u) + dy) >> 1, sx = (int(par[mt] >> 1) + dx) >> 1;
+                off = ok ? ((hc[mt] + uint32_t(sy * Wh + sx)) * uint32_t(C1) + 8 * kg) * 2u : ozh;
             } else {
-                off0[mt] = (size_t(pn[mt] * Hh + (yc >> 1)) * Wh + (xc >> 1)) * C1;
-                off1[mt] = (size_t(pn[mt] * H + yc) * W + xc) * C2;
+                off = ok ? oc[mt] + shift : oz;
             }
-            vm[mt] = ok ? 0xFFFFFFFFu : 0u;
+            a[mt] = *reinterpret_cast<const uint4*>(base + off);
         }
-        const bf16_t* __restrict__ wtap = wt + size_t(tap) * Cout * Cin;
-        for (int cb = 0; cb < Cin; cb += 32) {
-            const int ci = cb + 8 * kg;
-            uint4 a[2], b[2];
+        const char* wtap = reinterpret_cast<const char*>(wt + (size_t(ftap) * Cout * Cin + fcb));
 #pragma unroll
-            for (int mt = 0; mt < 2; ++mt) {
-                const bf16_t* src = (MODE == CONV_DIRECT || cb < C1) ? in0 + off0[mt] + ci : in1 + off1[mt] + (ci - C1);
-                a[mt] = and_mask(*reinterpret_cast<const uint4*>(src), vm[mt]);
-            }
+        for (int nt = 0; nt < 2; ++nt) b[nt] = *reinterpret_cast<const uint4*>(wtap + ob[nt]);
+        // next position of this wavefront (32 KS <= Cin: at most one tap carry)
+        fcb += 32 * KS;
+        if (fcb >= Cin) {
+            fcb -= Cin;
+            ftap = ftap < 8 ? ftap + 1 : 8;
+        }
+    };
+    // weights as the A operand and pixels as B: the tile is C[co][pixel], so that a lane's
+    // four results are four consecutive output channels of one pixel (one vector store)
+    auto mma = [&](const uint4 (&a)[MT], const uint4 (&b)[2]) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt)
-                b[nt] = *reinterpret_cast<const uint4*>(wtap + size_t(co0 + 16 * nt + r16) * Cin + ci);
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[mt]), as_bf16x8(b[nt]),
-                                                                          acc[mt][nt], 0, 0, 0);
-        }
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(b[nt]), as_bf16x8(a[mt]), acc[mt][nt],
+                                                                      0, 0, 0);
+    };
+    uint4 a0[MT], b0[2], a1[MT], b1[2], a2[MT], b2[2];
+    fetch(a0, b0);
+    fetch(a1, b1);
+    const int iters = 9 * (Cin >> 5) / KS;
+    for (int it = 0; it < iters; it += 3) {
+        fetch(a2, b2);
+        mma(a0, b0);
+        fetch(a0, b0);
+        mma(a1, b1);
+        fetch(a1, b1);
+        mma(a2, b2);
     }
-    // lane l, register v: pixel row 4 (l / 16) + v, output channel l mod 16 of the tile
+    if constexpr (KS > 1) {   // fixed-order sum of the KS partial tiles into wavefronts with ks == 0
+        __shared__ f32x4 red[KS - 1][PG][MT * 2][64];
+        if (ks > 0) {
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) red[ks - 1][pg][2 * mt + nt][lane] = acc[mt][nt];
+        }
+        __syncthreads();
+        if (ks > 0) return;
+#pragma unroll
+        for (int j = 0; j < KS - 1; ++j)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) acc[mt][nt] += red[j][pg][2 * mt + nt][lane];
+    }
+    // lane l, register v: output channel 4 (l / 16) + v, pixel l mod 16 of the tile
+    float bv[2][4] = {};
+    if (OUT_BF16 && bias) {
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int p = pb + 16 * mt + 4 * kg + v, co = co0 + 16 * nt + r16;
-                if (p >= P) continue;
-                float val = acc[mt][nt][v];
-                if (OUT_BF16) {
-                    if (bias) val += bias[co];
+            for (int v = 0; v < 4; ++v) bv[nt][v] = bias[co0 + 16 * nt + 4 * kg + v];
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int p = pb + 16 * mt + r16;
+        if (p >= P) continue;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const size_t o = size_t(p) * Cout + co0 + 16 * nt + 4 * kg;
+            if (OUT_BF16) {
+                uint32_t h[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    float val = acc[mt][nt][v] + bv[nt][v];
                     if (relu) val = fmaxf(val, 0.f);
-                    static_cast<bf16_t*>(out)[size_t(p) * Cout + co] = f2bf(val);
-                } else {
-                    static_cast<float*>(out)[size_t(p) * Cout + co] = val;
+                    h[v] = f2bf(val);
                 }
+                *reinterpret_cast<uint2*>(static_cast<bf16_t*>(out) + o) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+            } else {
+                *reinterpret_cast<float4*>(static_cast<float*>(out) + o) =
+                    make_float4(acc[mt][nt][0], acc[mt][nt][1], acc[mt][nt][2], acc[mt][nt][3]);
             }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ weight gradient
 
-// dW[tap][co][ci] partial over the pixels of chunk blockIdx.x (kWChunk pixels): block
-// (tap, co tile of 32, ci tile of 32) from blockIdx.y.  Per step of 32 pixels the block
-// stages dy[32 px][32 co] and x[32 px (shifted by tap)][32 ci] into LDS transposed, and
-// wavefront w computes the 16 x 16 sub-tile (w / 2, w % 2) with one MFMA (K = 32 pixels).
+// Weight and bias gradient partials of the pixels of chunk blockIdx.x (chunk_px pixels, a
+// multiple of 64) for
+// the (co tile of 32, ci tile of 32) pair blockIdx.y, all nine taps at once:
+//   part[chunk][tap][co][ci] = sum_p dy[p][co] x[p + tap][ci],
+//   part[chunk][9 Cout Cin + co] = sum_p dy[p][co]   (written by the ci-tile-0 blocks).
+// Per step of 64 pixels the block stages dy[64][32 co] and the nine shifted inputs
+// x[64 (+ tap)][32 ci] into LDS transposed (channel rows, pixel columns), so that every
+// MFMA operand (8 consecutive pixels of one channel) is one 16-byte LDS read; wavefront w
+// accumulates the 16 x 16 sub-tile (w / 2, w % 2) of every tap (2 MFMAs of K = 32 per tap
+// and step).  Staging: thread t moves pixels 2 (t mod 32) and 2 (t mod 32) + 1 of the 8
+// channels 8 ((t / 32) mod 4) .. +7 of five of the ten sources (dy and the nine taps), as
+// packed pixel pairs (one 4-byte LDS write per channel).
 template <int MODE>
 __global__ void __launch_bounds__(kT) k_conv_wgrad(const bf16_t* __restrict__ dy, const bf16_t* __restrict__ in0,
                                                     const bf16_t* __restrict__ in1, int C1, int Cin, int N, int H,
-                                                    int W, int Cout, float* __restrict__ part, int chunk0) {
-    constexpr int LD = 32 + 8;                 // padded row (bf16) of the transposed tiles
-    __shared__ __align__(16) bf16_t sdy[32][LD];   // [co][pixel]
-    __shared__ __align__(16) bf16_t sx[32][LD];    // [ci][pixel]
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+                                                    int W, int Cout, int chunk_px, float* __restrict__ part,
+                                                    int chunk0) {
+    constexpr int SP = 64;                     // pixels per step
+    constexpr int LD = SP + 8;                 // padded row (bf16): 36 dwords, 16-byte aligned rows
+    __shared__ __align__(16) bf16_t st[10][32][LD];   // source 0: dy [co][px]; 1 + tap: x [ci][px]
+    __shared__ float bsh[2][32];                      // bias partials of waves 0 and 1
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform
     const int r16 = lane & 15, kg = lane >> 4;
-    const int nci = Cin / 32, nco = Cout / 32;
-    const int tap = blockIdx.y / (nco * nci);
-    const int rem = blockIdx.y - tap * nco * nci;
-    const int co0 = (rem / nci) * 32, ci0 = (rem % nci) * 32;
-    const int dyy = tap / 3 - 1, dxx = tap % 3 - 1;
+    const int nci = Cin / 32;
+    const int co0 = (blockIdx.y / nci) * 32, ci0 = (blockIdx.y % nci) * 32;
+    const bool with_bias = ci0 == 0;
     const int P = N * H * W, C2 = Cin - C1, Hh = H >> 1, Wh = W >> 1;
-    const int p_begin = blockIdx.x * kWChunk;
-    const int p_end = min(P, p_begin + kWChunk);
-    // staging role of the thread: pixel sp (0..31), channel group sc (0..3) of 8 channels
-    const int sp = threadIdx.x >> 3, sc = threadIdx.x & 7;   // 32 pixels x 8 groups: dy uses sc < 4, x uses sc >= 4
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int mt = wv >> 1, nt = wv & 1;
-    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
-        const int p = p0 + sp;
-        const bool pin = p < p_end;
-        const int pc = pin ? p : p_begin;
-        uint4 v;
-        if (sc < 4) {   // dy[p][co0 + 8 sc .. +7]
-            v = and_mask(*reinterpret_cast<const uint4*>(dy + size_t(pc) * Cout + co0 + 8 * sc), pin ? 0xFFFFFFFFu : 0u);
-        } else {        // x[p + tap][ci0 + 8 (sc - 4) .. +7]
-            const int n = pc / (H * W), r = pc - n * H * W, y = r / W, x = r - (r / W) * W;
-            const int ys = y + dyy, xs = x + dxx;
-            const bool ok = pin && ys >= 0 && ys < H && xs >= 0 && xs < W;
-            const int yc = ok ? ys : 0, xc = ok ? xs : 0;
-            const int ci = ci0 + 8 * (sc - 4);
-            const bf16_t* src;
-            if (MODE == CONV_DIRECT)
-                src = in0 + (size_t(n * H + yc) * W + xc) * Cin + ci;
-            else if (ci < C1)
-                src = in0 + (size_t(n * Hh + (yc >> 1)) * Wh + (xc >> 1)) * C1 + ci;
-            else
-                src = in1 + (size_t(n * H + yc) * W + xc) * C2 + (ci - C1);
-            v = and_mask(*reinterpret_cast<const uint4*>(src), ok ? 0xFFFFFFFFu : 0u);
-        }
-        const bf16_t* e = reinterpret_cast<const bf16_t*>(&v);
-        bf16_t (*dst)[LD] = sc < 4 ? sdy : sx;
-        const int c8 = 8 * (sc & 3);
+    const int lh = __builtin_ctz(H), lw = __builtin_ctz(W);   // H, W powers of two
+    const int p_begin = blockIdx.x * chunk_px;
+    const int p_end = min(P, p_begin + chunk_px);
+    // staging role: pixel pair (2 pair, 2 pair + 1) of the step and channel group grp, so that
+    // the lanes of one load cover whole 64-byte pixel rows; sources 2 j + half
+    const int pair = (threadIdx.x & 127) >> 2, grp = threadIdx.x & 3, half = wv >> 1;
+    // LDS rows hold 32 dwords of pixel pairs; the dword column of a row of channel group g
+    // is rotated by 8 g (mod 32), which spreads the four groups of a store over the banks
+    auto col = [](int dw, int g) { return ((dw + 8 * g) & 31); };
+    f32x4 acc[9];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) dst[c8 + i][sp] = e[i];
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) bsum[i] = 0.f;
+    const int mt = wv >> 1, nt = wv & 1;
+    // the thread's ten 16-byte loads of the step starting at pixel p0 (issued together; the
+    // bias sums take the dy values as they are staged)
+    // Inputs outside the image and pixels past the chunk read the zero row of their tensor
+    // (one pixel of zeros after the last), so no masking is needed; byte offsets fit in 32 bits.
+    const int Cf = MODE == CONV_DIRECT ? Cin : C2;           // channels of the full-resolution input
+    const bool up = MODE == CONV_CONCAT_UP && ci0 < C1;     // this ci tile comes from the upsampling
+    const char* xbase = reinterpret_cast<const char*>(up ? in0 + ci0 : MODE == CONV_DIRECT ? in0 + ci0 : in1 + (ci0 - C1));
+    const char* dbase = reinterpret_cast<const char*>(dy + co0);
+    const uint32_t xC = up ? C1 : Cf;                          // channels per pixel of that input
+    const uint32_t Ph = uint32_t(N) * Hh * Wh;
+    const uint32_t xzero = ((up ? Ph : uint32_t(P)) * xC + 8 * grp) * 2u;
+    const uint32_t dzero = (uint32_t(P) * Cout + 8 * grp) * 2u;
+    uint4 v[5][2];
+    auto load_step = [&](int p0) {
+        uint32_t okb[2], xo[2], dofs[2], hc[2], par[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int p = p0 + 2 * pair + e;
+            const bool pin = p < p_end;
+            const int pc = pin ? p : p_begin;
+            const int pn = pc >> (lh + lw), py = (pc >> lw) & (H - 1), px = pc & (W - 1);
+            uint32_t bits = 0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int ys = py + t / 3 - 1, xs = px + t % 3 - 1;
+                bits |= uint32_t(pin & (unsigned(ys) < unsigned(H)) & (unsigned(xs) < unsigned(W))) << t;
+            }
+            okb[e] = bits;
+            xo[e] = (uint32_t(pc) * xC + 8 * grp) * 2u;
+            dofs[e] = pin ? (uint32_t(pc) * Cout + 8 * grp) * 2u : dzero;
+            hc[e] = uint32_t((pn * Hh + (py >> 1)) * Wh + (px >> 1));
+            par[e] = uint32_t((py & 1) | ((px & 1) << 1));
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int src_id = 2 * j + half;        // 0: dy, 1 + tap: shifted input (uniform)
+            const int tap = src_id > 0 ? src_id - 1 : 4;
+            const int dyy = tap / 3 - 1, dxx = tap - 3 * (tap / 3) - 1;
+            const uint32_t shift = uint32_t((dyy * W + dxx) * int(xC)) * 2u;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const char* src;
+                if (src_id == 0) {
+                    src = dbase + dofs[e];
+                } else {
+                    const bool ok = (okb[e] >> tap) & 1u;
+                    uint32_t off;
+                    if (up) {
+                        const int sy = (int(par[e] & 1u) + dyy) >> 1, sx = (int(par[e] >> 1) + dxx) >> 1;
+                        off = ok ? ((hc[e] + uint32_t(sy * Wh + sx)) * xC + 8 * grp) * 2u : xzero;
+                    } else {
+                        off = ok ? xo[e] + shift : xzero;
+                    }
+                    src = xbase + off;
+                }
+                v[j][e] = *reinterpret_cast<const uint4*>(src);
+            }
+        }
+    };
+    load_step(p_begin);
+    for (int p0 = p_begin; p0 < p_end; p0 += SP) {
+        if (with_bias && half == 0) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const bf16_t* h = reinterpret_cast<const bf16_t*>(&v[0][e]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bsum[i] += bf2f(h[i]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int src_id = 2 * j + half;
+            const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&v[j][0]);
+            const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&v[j][1]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {      // channels 2i, 2i + 1 of the group: (pixel 0, pixel 1) pairs
+                const uint32_t lo = (w0[i] & 0xFFFFu) | (w1[i] << 16);
+                const uint32_t hi = (w0[i] >> 16) | (w1[i] & 0xFFFF0000u);
+                *reinterpret_cast<uint32_t*>(&st[src_id][8 * grp + 2 * i][2 * col(pair, grp)]) = lo;
+                *reinterpret_cast<uint32_t*>(&st[src_id][8 * grp + 2 * i + 1][2 * col(pair, grp)]) = hi;
+            }
+        }
         __syncthreads();
-        const uint4 a = *reinterpret_cast<const uint4*>(&sdy[16 * mt + r16][8 * kg]);
-        const uint4 b = *reinterpret_cast<const uint4*>(&sx[16 * nt + r16][8 * kg]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(b), acc, 0, 0, 0);
+        // the next step's loads fly while this step's MFMAs run (the last step reloads itself)
+        load_step(p0 + SP < p_end ? p0 + SP : p0);
+#pragma unroll
+        for (int kk = 0; kk < SP / 32; ++kk) {
+            // all operands of the K step first, then the nine MFMAs
+            // rows 16 mt + r16 (dy) and 16 nt + r16 (x) belong to channel groups 2 mt + r16 / 8
+            // and 2 nt + r16 / 8; the lane's 4 dwords start at logical dword 16 kk + 4 kg
+            const int ra = 16 * mt + r16, rb = 16 * nt + r16;
+            const uint4 a = *reinterpret_cast<const uint4*>(&st[0][ra][2 * col(16 * kk + 4 * kg, ra >> 3)]);
+            uint4 b[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                b[t] = *reinterpret_cast<const uint4*>(&st[1 + t][rb][2 * col(16 * kk + 4 * kg, rb >> 3)]);
+            // x as the A operand and dy as B: the tile is C[ci][co], a lane's four results are
+            // four consecutive input channels (one vector store)
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(b[t]), as_bf16x8(a), acc[t], 0, 0, 0);
+        }
         __syncthreads();
     }
-    // lane l, register v: co row 4 (l / 16) + v, ci column l mod 16 of the sub-tile
-    float* dst = part + (size_t(chunk0 + blockIdx.x) * 9 + tap) * Cout * Cin;
+    const size_t row = size_t(9) * Cout * Cin + Cout;
+    float* dst = part + size_t(chunk0 + blockIdx.x) * row;
+    // lane l, register v: ci row 4 (l / 16) + v, co column l mod 16 of the sub-tile
+    {
+        const int co = co0 + 16 * mt + r16, ci = ci0 + 16 * nt + 4 * kg;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int co = co0 + 16 * mt + 4 * kg + v, ci = ci0 + 16 * nt + r16;
-        dst[size_t(co) * Cin + ci] = acc[v];
+        for (int t = 0; t < 9; ++t)
+            *reinterpret_cast<float4*>(dst + (size_t(t) * Cout + co) * Cin + ci) =
+                make_float4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+    }
+    if (with_bias) {
+        // waves 0 and 1 hold the dy values: sum over the 16 lanes of each channel group (lane
+        // mod 4), then wave 0 adds wave 1's sums
+        if (half == 0) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                float v = bsum[i];
+#pragma unroll
+                for (int o = 4; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+                bsum[i] = v;
+            }
+            if (wv == 1 && lane < 4) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bsh[1][8 * grp + i] = bsum[i];
+            }
+        }
+        __syncthreads();
+        if (wv == 0 && lane < 4) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dst[size_t(9) * Cout * Cin + co0 + 8 * grp + i] = bsum[i] + bsh[1][8 * grp + i];
+        }
     }
 }
 
-// out[i] = sum_{c < chunks} part[c * n + i] (fixed order), optionally scaled.
-__global__ void __launch_bounds__(kT) k_reduce_chunks(const float* __restrict__ part, int chunks, int64_t n,
-                                                       float* __restrict__ out) {
-    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+// Fixed-order sums of chunk partials for several tensors in one launch: tensor k owns
+// blocks [block0[k], block0[k + 1]), one element per thread; the chunks are summed in order
+// in eight interleaved partial sums (eight loads in flight), combined in a fixed order.
+struct ReduceTable {
+    const float* part[16];
+    float* out[16];
+    int64_t n[16];
+    int chunks[16];
+    int block0[17];
+    int count;
+};
+
+__global__ void __launch_bounds__(kT) k_reduce_table(ReduceTable tb) {
+    int k = 0;
+    while (k + 1 < tb.count && int(blockIdx.x) >= tb.block0[k + 1]) ++k;
+    const int64_t i = int64_t(blockIdx.x - tb.block0[k]) * kT + threadIdx.x;
+    const int64_t n = tb.n[k];
     if (i >= n) return;
-    float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[size_t(c) * n + i];
-    out[i] = s;
+    const float* __restrict__ p = tb.part[k] + i;
+    const int C = tb.chunks[k];
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    for (; c + 8 <= C; c += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += p[size_t(c + u) * n];
+    }
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+        if (c + u < C) s[u] += p[size_t(c + u) * n];
+    tb.out[k][i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -290,23 +506,13 @@ __global__ void __launch_bounds__(kT) k_split_concat_grad(const float* __restric
     }
 }
 
-// dpre = bf16(g * (act > 0))
+// dpre = bf16(g * (act > 0)) for the n = P C entries, then the zero row (C zeros) that the
+// input-gradient convolution reads for its zero padding
 __global__ void __launch_bounds__(kT) k_relu_grad(const float* __restrict__ g, const bf16_t* __restrict__ act,
-                                                   int64_t n, bf16_t* __restrict__ dpre) {
+                                                   int64_t n, int C, bf16_t* __restrict__ dpre) {
     const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
-    if (e >= n) return;
-    dpre[e] = f2bf(bf2f(act[e]) > 0.f ? g[e] : 0.f);
-}
-
-// bias-gradient partial of chunk blockIdx.x: part[chunk][co] = sum_p dpre[p][co]
-__global__ void __launch_bounds__(kT) k_bias_grad(const bf16_t* __restrict__ dpre, int P, int C,
-                                                   float* __restrict__ part, int chunk0) {
-    const int p0 = blockIdx.x * kBChunk, p1 = min(P, p0 + kBChunk);
-    for (int co = threadIdx.x; co < C; co += kT) {
-        float s = 0.f;
-        for (int p = p0; p < p1; ++p) s += bf2f(dpre[size_t(p) * C + co]);
-        part[size_t(chunk0 + blockIdx.x) * C + co] = s;
-    }
+    if (e >= n + C) return;
+    dpre[e] = e < n ? f2bf(bf2f(act[e]) > 0.f ? g[e] : 0.f) : bf16_t(0);
 }
 
 // out[p] = sum_c x[p][c] w[c] + b
@@ -366,12 +572,19 @@ __global__ void __launch_bounds__(kT) k_head_back(const float* __restrict__ out,
     }
 }
 
-// Adam over n master entries; conv weights (internal layout [9][Cout][Cin]) also refresh their
-// bf16 forward copy and the flipped, transposed copy wd[8 - tap][ci][co] of the input gradient.
+// Adam over all n master entries in one launch; the entries of conv k's weights
+// [w_off[k], w_off[k] + nw[k]) (internal layout [9][Cout][Cin]) also refresh their bf16
+// forward copy and the flipped, transposed copy wd[8 - tap][ci][co] of the input gradient.
+struct AdamTable {
+    int64_t w_off[kConvs], nw[kConvs];
+    bf16_t* wt[kConvs];
+    bf16_t* wd[kConvs];
+    int cout[kConvs], cin[kConvs];
+};
+
 __global__ void __launch_bounds__(kT) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                                               const float* __restrict__ g, int64_t n, float lr, float b1, float b2,
-                                              float eps, float c1, float c2, bf16_t* __restrict__ wt,
-                                              bf16_t* __restrict__ wd, int Cout, int Cin) {
+                                              float eps, float c1, float c2, AdamTable tb) {
     const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
@@ -381,14 +594,18 @@ __global__ void __launch_bounds__(kT) k_adam(float* __restrict__ w, float* __res
     v[i] = vi;
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     w[i] = wi;
-    if (wt) {
+    int k = 0;
+    while (k + 1 < kConvs && i >= tb.w_off[k + 1]) ++k;
+    const int64_t j = i - tb.w_off[k];
+    if (j < tb.nw[k]) {
         const bf16_t h = f2bf(wi);
-        wt[i] = h;
+        tb.wt[k][j] = h;
+        const int Cout = tb.cout[k], Cin = tb.cin[k];
         const int64_t per = int64_t(Cout) * Cin;
-        const int tap = int(i / per);
-        const int64_t r = i - tap * per;
+        const int tap = int(j / per);
+        const int64_t r = j - tap * per;
         const int co = int(r / Cin), ci = int(r - int64_t(co) * Cin);
-        wd[(size_t(8 - tap) * Cin + ci) * Cout + co] = h;
+        tb.wd[k][(size_t(8 - tap) * Cin + ci) * Cout + co] = h;
     }
 }
 
@@ -483,9 +700,9 @@ struct fewha_unet {
     float* gcat[3] = {};            // gradient of the concatenated decoder inputs (levels 2, 1, 0)
     float* gpool[3] = {};           // gradient of the pooled inputs of levels 1, 2, 3
     bf16_t* dpre = nullptr;         // bf16 ReLU-masked gradient of the current conv
-    float* wpart[kConvs] = {};      // weight-gradient partials [chunks][9][Cout][Cin]
-    float* bpart[kConvs] = {};      // bias-gradient partials [chunks][Cout]
-    int wchunks[kConvs] = {}, bchunks[kConvs] = {};
+    float* wpart[kConvs] = {};      // gradient partials [chunks][9 Cout Cin + Cout] (weights, bias)
+    int wchunks[kConvs] = {};
+    int chunk_px[kConvs] = {};      // pixels per weight-gradient chunk
     float* hpart = nullptr;         // head partials [blocks][34]
     int hblocks = 0;
     float* hred = nullptr;          // reduced head row [loss sum, gw[32], gb]
@@ -540,9 +757,10 @@ struct fewha_unet {
         nodes = 0;
         for (int g = 0; g < G; ++g) {
             nodes += P(g, 0);
-            x[g] = take<bf16_t>(P(g, 0) * kInCh);
-            for (int k = 0; k < kConvs; ++k) act[g][k] = take<bf16_t>(P(g, kSpecs[k].level) * kSpecs[k].cout);
-            for (int l = 0; l < 3; ++l) pool[g][l] = take<bf16_t>(P(g, l + 1) * kCh[l]);
+            // every convolution input carries a zero row (one pixel of zeros after the last)
+            x[g] = take<bf16_t>((P(g, 0) + 1) * kInCh);
+            for (int k = 0; k < kConvs; ++k) act[g][k] = take<bf16_t>((P(g, kSpecs[k].level) + 1) * kSpecs[k].cout);
+            for (int l = 0; l < 3; ++l) pool[g][l] = take<bf16_t>((P(g, l + 1) + 1) * kCh[l]);
             out[g] = take<float>(P(g, 0));
         }
         // gradients: sized for the largest group
@@ -560,21 +778,26 @@ struct fewha_unet {
             gcat[l] = take<float>(maxP(2 - l) * kSpecs[D2A + 2 * l].cin);
             gpool[l] = take<float>(maxP(l + 1) * kCh[l]);
         }
-        dpre = take<bf16_t>(maxpc);
+        dpre = take<bf16_t>(maxpc + 256);   // + a zero row of up to 256 channels
         for (int k = 0; k < kConvs; ++k) {
-            wchunks[k] = bchunks[k] = 0;
-            for (int g = 0; g < G; ++g) {
-                wchunks[k] += int((P(g, kSpecs[k].level) + kWChunk - 1) / kWChunk);
-                bchunks[k] += int((P(g, kSpecs[k].level) + kBChunk - 1) / kBChunk);
-            }
-            wpart[k] = take<float>(int64_t(wchunks[k]) * 9 * kSpecs[k].cin * kSpecs[k].cout);
-            bpart[k] = take<float>(int64_t(bchunks[k]) * kSpecs[k].cout);
+            // chunks sized so that a convolution's launches add up to about kWBlocks workgroups
+            const int64_t tiles = int64_t(kSpecs[k].cout / 32) * (kSpecs[k].cin / 32);
+            int64_t pk = 0;
+            for (int g = 0; g < G; ++g) pk += P(g, kSpecs[k].level);
+            const int64_t want = (pk * tiles + kWBlocks - 1) / kWBlocks;
+            chunk_px[k] = int(std::min<int64_t>(4096, std::max<int64_t>(64, (want + 63) / 64 * 64)));
+            wchunks[k] = 0;
+            for (int g = 0; g < G; ++g) wchunks[k] += int((P(g, kSpecs[k].level) + chunk_px[k] - 1) / chunk_px[k]);
+            wpart[k] = take<float>(int64_t(wchunks[k]) * grad_row(k));
         }
         hblocks = 0;
         for (int g = 0; g < G; ++g) hblocks += int(blocks(P(g, 0)));
         hpart = take<float>(int64_t(hblocks) * (kCh[0] + 2));
         hred = take<float>(kCh[0] + 2);
     }
+
+    // gradient entries of conv k: weights [9][Cout][Cin], then bias [Cout]
+    static int64_t grad_row(int k) { return int64_t(9) * kSpecs[k].cin * kSpecs[k].cout + kSpecs[k].cout; }
 
     // ---- launches
     // upsampled channels of a decoder concatenation: the coarser level's channel count
@@ -601,6 +824,23 @@ struct fewha_unet {
         }
     }
 
+    // 3x3 convolution launch: the reduction is split over the wavefronts of a workgroup
+    // (KS = 2 or 4) when the output alone gives fewer than 768 workgroups of 128 pixels
+    template <int MODE, bool OUT>
+    static void conv(const bf16_t* in0, const bf16_t* in1, int C1, int Cin, int N, int H, const bf16_t* w,
+                     const float* bias, int relu, void* out, int Cout, hipStream_t s) {
+        const int64_t Pn = int64_t(N) * H * H;
+        const int64_t b1 = int64_t(blocks(Pn, kConvPix)) * (Cout / 32);
+        const int ks = b1 >= 768 ? 1 : Cin % 128 == 0 ? 4 : Cin % 64 == 0 ? 2 : 1;
+        const dim3 grid(blocks(Pn, kConvPix / ks), Cout / 32);
+        if (ks == 4)
+            k_conv3x3<MODE, OUT, 4><<<grid, kT, 0, s>>>(in0, in1, C1, Cin, N, H, H, w, bias, relu, out, Cout);
+        else if (ks == 2)
+            k_conv3x3<MODE, OUT, 2><<<grid, kT, 0, s>>>(in0, in1, C1, Cin, N, H, H, w, bias, relu, out, Cout);
+        else
+            k_conv3x3<MODE, OUT, 1><<<grid, kT, 0, s>>>(in0, in1, C1, Cin, N, H, H, w, bias, relu, out, Cout);
+    }
+
     void forward_group(int g, const float* in, hipStream_t s) {
         const int64_t P0 = P(g, 0);
         k_pack_input<<<blocks(P0 * kInCh), kT, 0, s>>>(in, P0, x[g]);
@@ -611,49 +851,42 @@ struct fewha_unet {
                 k_pool2<<<blocks(P(g, l + 1) * kCh[l]), kT, 0, s>>>(act[g][k - 1], images[g], Hs, Hs, kCh[l], pool[g][l]);
             }
             const int H = size[g] >> c.level;
-            const dim3 grid(blocks(P(g, c.level), kConvPix), c.cout / 32);
             const float* bias = master + b_off[k];
             if (c.concat)
-                k_conv3x3<CONV_CONCAT_UP, true><<<grid, kT, 0, s>>>(conv_in0(k, g), conv_in1(k, g), concat_c1(k), c.cin,
-                                                                  images[g], H, H, wt[k], bias, 1, act[g][k], c.cout);
+                conv<CONV_CONCAT_UP, true>(conv_in0(k, g), conv_in1(k, g), concat_c1(k), c.cin, images[g], H, wt[k],
+                                           bias, 1, act[g][k], c.cout, s);
             else
-                k_conv3x3<CONV_DIRECT, true><<<grid, kT, 0, s>>>(conv_in0(k, g), nullptr, 0, c.cin, images[g], H, H,
-                                                                wt[k], bias, 1, act[g][k], c.cout);
+                conv<CONV_DIRECT, true>(conv_in0(k, g), nullptr, 0, c.cin, images[g], H, wt[k], bias, 1, act[g][k],
+                                        c.cout, s);
         }
         k_head<<<blocks(P0), kT, 0, s>>>(act[g][D0B], master + hw_off, master + hb_off, P0, out[g]);
     }
 
     // gradient of conv k's output is in gact[k]: weight/bias partials, and (unless k == E0A)
     // the gradient of its input into gin (FP32)
-    void conv_back(int k, int g, int wc0, int bc0, float* gin, hipStream_t s) {
+    void conv_back(int k, int g, int wc0, float* gin, hipStream_t s) {
         const ConvSpec& c = kSpecs[k];
         const int H = size[g] >> c.level;
         const int64_t Pn = P(g, c.level);
-        k_relu_grad<<<blocks(Pn * c.cout), kT, 0, s>>>(gact[k], act[g][k], Pn * c.cout, dpre);
-        const dim3 wg(blocks(Pn, kWChunk), 9 * (c.cout / 32) * (c.cin / 32));
+        k_relu_grad<<<blocks((Pn + 1) * c.cout), kT, 0, s>>>(gact[k], act[g][k], Pn * c.cout, c.cout, dpre);
+        const dim3 wg(blocks(Pn, chunk_px[k]), (c.cout / 32) * (c.cin / 32));
         if (c.concat)
             k_conv_wgrad<CONV_CONCAT_UP><<<wg, kT, 0, s>>>(dpre, conv_in0(k, g), conv_in1(k, g), concat_c1(k), c.cin,
-                                                         images[g], H, H, c.cout, wpart[k], wc0);
+                                                         images[g], H, H, c.cout, chunk_px[k], wpart[k], wc0);
         else
             k_conv_wgrad<CONV_DIRECT><<<wg, kT, 0, s>>>(dpre, conv_in0(k, g), nullptr, 0, c.cin, images[g], H, H,
-                                                       c.cout, wpart[k], wc0);
-        k_bias_grad<<<blocks(Pn, kBChunk), kT, 0, s>>>(dpre, int(Pn), c.cout, bpart[k], bc0);
-        if (gin) {
-            const dim3 grid(blocks(Pn, kConvPix), c.cin / 32);
-            k_conv3x3<CONV_DIRECT, false><<<grid, kT, 0, s>>>(dpre, nullptr, 0, c.cout, images[g], H, H, wd[k], nullptr,
-                                                             0, gin, c.cin);
-        }
+                                                       c.cout, chunk_px[k], wpart[k], wc0);
+        if (gin) conv<CONV_DIRECT, false>(dpre, nullptr, 0, c.cout, images[g], H, wd[k], nullptr, 0, gin, c.cin, s);
     }
 
-    void backward_group(int g, const float* target, double total, int* wc, int* bc, int hb0, hipStream_t s) {
+    void backward_group(int g, const float* target, double total, int* wc, int hb0, hipStream_t s) {
         const int64_t P0 = P(g, 0);
         k_head_back<<<blocks(P0), kT, 0, s>>>(out[g], target, act[g][D0B], master + hw_off, P0, total, gact[D0B],
                                               hpart, hb0);
         auto chunks = [&](int k, int per) { return int((P(g, kSpecs[k].level) + per - 1) / per); };
         auto back = [&](int k, float* gin) {
-            conv_back(k, g, wc[k], bc[k], gin, s);
-            wc[k] += chunks(k, kWChunk);
-            bc[k] += chunks(k, kBChunk);
+            conv_back(k, g, wc[k], gin, s);
+            wc[k] += chunks(k, chunk_px[k]);
         };
         auto split = [&](int lvl_out, float* gc, float* glow, float* gskip, int c1, int c2) {
             const int H = size[g] >> lvl_out;
@@ -709,7 +942,7 @@ fewha_status validate(const fewha_unet_config* c, std::string& err) {
         const int s = c->size[g];
         if (s < 16 || s > 4096 || (s & (s - 1))) { err = "image size must be a power of two in [16, 4096]"; return FEWHA_E_INVAL; }
         if (c->images[g] < 1) { err = "images per group must be >= 1"; return FEWHA_E_INVAL; }
-        if (int64_t(c->images[g]) * s * s > (int64_t(1) << 30)) { err = "group too large"; return FEWHA_E_INVAL; }
+        if (int64_t(c->images[g]) * s * s > (int64_t(1) << 25)) { err = "group too large (at most 2^25 nodes)"; return FEWHA_E_INVAL; }
     }
     if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) || !(c->eps > 0)) {
         err = "bad Adam settings";
@@ -852,26 +1085,32 @@ fewha_status fewha_unet_backward(fewha_unet* net, const float* d_in, const float
                                  void* stream) {
     if (!net || !d_in || !d_target) return ufail(net, FEWHA_E_INVAL, "NULL argument");
     hipStream_t s = as_stream(stream);
-    int wc[kConvs] = {}, bc[kConvs] = {};
+    int wc[kConvs] = {};
     int hb = 0;
     int64_t o = 0;
     const double total = double(net->nodes);
     for (int g = 0; g < net->G; ++g) {
         net->forward_group(g, d_in + o * kInputs, s);
-        net->backward_group(g, d_target + o, total, wc, bc, hb, s);
+        net->backward_group(g, d_target + o, total, wc, hb, s);
         hb += int(blocks(net->P(g, 0)));
         o += net->P(g, 0);
     }
-    // fixed-order reduction of every partial into the gradient vector
-    for (int k = 0; k < kConvs; ++k) {
-        const int64_t nw = int64_t(9) * kSpecs[k].cin * kSpecs[k].cout;
-        k_reduce_chunks<<<blocks(nw), kT, 0, s>>>(net->wpart[k], net->wchunks[k], nw, net->grad + net->w_off[k]);
-        k_reduce_chunks<<<blocks(kSpecs[k].cout), kT, 0, s>>>(net->bpart[k], net->bchunks[k], kSpecs[k].cout,
-                                                              net->grad + net->b_off[k]);
+    // fixed-order reduction of every partial into the gradient vector (conv weights and bias
+    // rows, then the head row [loss sum, gw[32], gb]), one launch
+    ReduceTable tb{};
+    int nb = 0;
+    for (int k = 0; k <= kConvs; ++k) {
+        const bool head = k == kConvs;
+        tb.part[k] = head ? net->hpart : net->wpart[k];
+        tb.out[k] = head ? net->hred : net->grad + net->w_off[k];
+        tb.n[k] = head ? kCh[0] + 2 : fewha_unet::grad_row(k);
+        tb.chunks[k] = head ? net->hblocks : net->wchunks[k];
+        tb.block0[k] = nb;
+        nb += int(blocks(tb.n[k]));
     }
-    // head: part rows [loss sum, gw[32], gb]
-    constexpr int HC = kCh[0] + 2;
-    k_reduce_chunks<<<1, kT, 0, s>>>(net->hpart, net->hblocks, HC, net->hred);
+    tb.count = kConvs + 1;
+    tb.block0[kConvs + 1] = nb;
+    k_reduce_table<<<nb, kT, 0, s>>>(tb);
     k_head_finish<<<1, 64, 0, s>>>(net->hred, total, d_loss, net->grad + net->hw_off, net->grad + net->hb_off);
     return check(net);
 }
@@ -882,16 +1121,17 @@ fewha_status fewha_unet_adam_step(fewha_unet* net, void* stream) {
     net->step += 1;
     const float c1 = float(1.0 - std::pow(double(net->b1), net->step));
     const float c2 = float(1.0 - std::pow(double(net->b2), net->step));
-    auto adam = [&](int64_t off, int64_t n, bf16_t* wt, bf16_t* wd, int cout, int cin) {
-        k_adam<<<blocks(n), kT, 0, s>>>(net->master + off, net->mom1 + off, net->mom2 + off, net->grad + off, n,
-                                       net->lr, net->b1, net->b2, net->eps, c1, c2, wt, wd, cout, cin);
-    };
+    AdamTable tb{};
     for (int k = 0; k < kConvs; ++k) {
-        adam(net->w_off[k], int64_t(9) * kSpecs[k].cin * kSpecs[k].cout, net->wt[k], net->wd[k], kSpecs[k].cout,
-             kSpecs[k].cin);
-        adam(net->b_off[k], kSpecs[k].cout, nullptr, nullptr, 0, 0);
+        tb.w_off[k] = net->w_off[k];
+        tb.nw[k] = int64_t(9) * kSpecs[k].cin * kSpecs[k].cout;
+        tb.wt[k] = net->wt[k];
+        tb.wd[k] = net->wd[k];
+        tb.cout[k] = kSpecs[k].cout;
+        tb.cin[k] = kSpecs[k].cin;
     }
-    adam(net->hw_off, kCh[0] + 1, nullptr, nullptr, 0, 0);   // head weights and bias (contiguous)
+    k_adam<<<blocks(net->n_master), kT, 0, s>>>(net->master, net->mom1, net->mom2, net->grad, net->n_master, net->lr,
+                                                net->b1, net->b2, net->eps, c1, c2, tb);
     return check(net);
 }
 
