@@ -16,6 +16,7 @@ solve (6 per frame), with the slopes already resident in device memory.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,8 +34,8 @@ SEED = 20201112
 COARSE_BLOCK = 64      # largest wavelet block a single workgroup transforms in LDS
 # operator kernels in the library's profiler numbering (see include/fewha.h)
 OP_KERNELS = ["idwt_coarse", "idwt_step", "data_term", "adj_gather", "dwt_step", "dwt_coarse"]
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "adj_gather_elt_mcao_fp32_pmc.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_06842_amd", "csrc", "fewha_operator.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2011_06842_amd", "csrc")
 
 
 def log(msg):
@@ -93,31 +94,42 @@ def frame_kernel_bytes(name, N, S, V, e, m, it, mp):
     return 0.0
 
 
-def source_sha256(path):
-    import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+def source_sha256():
+    """Hash of the library's sources: counter figures stay valid only while it matches."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".cpp", ".h")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
 
 
-def pmc_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
-    summary is missing, covers another kernel, or the kernel source changed since."""
-    try:
-        with open(PMC_SUMMARY) as f:
-            txt = f.read()
-    except OSError:
-        return None
-    vals = {}
-    for line in txt.splitlines():
-        if line.startswith("- ") and ":" in line:
-            k, v = line[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel") != kernel or vals.get("source_sha256") != source_sha256(KERNEL_SOURCE):
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+def pmc_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` in `workload` ("single" or "batched") from the
+    committed counter summaries (profiles/*_pmc.md, blocks of "- key: value" lines starting at
+    "- kernel:"), or None when none matches or the sources changed since."""
+    import glob
+    sha = source_sha256()
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*_pmc.md"))):
+        with open(path) as f:
+            lines = f.read().splitlines()
+        blocks, cur = [], None
+        for line in lines:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                k, v = k.strip(), v.strip().strip("`")
+                if k == "kernel":
+                    cur = {}
+                    blocks.append(cur)
+                if cur is not None:
+                    cur[k] = v
+        for blk in blocks:
+            if blk.get("kernel") == kernel and blk.get("workload") == workload and blk.get("source_sha256") == sha:
+                try:
+                    return float(blk["traffic_bytes_per_launch"])
+                except (KeyError, ValueError):
+                    return None
+    return None
 
 
 def copy_probe(mib):
@@ -148,7 +160,8 @@ def run_batch(args, dev):
     B = args.batch
     A = min(4, B)
     stride = 2
-    F = args.batch_warmup + args.batch_steps
+    tune_warm, tune_steps = 3, max(3, args.batch_steps // 4)
+    F = max(args.batch_warmup + args.batch_steps, tune_warm + tune_steps)
     need = F + stride * ((B + A - 1) // A)
     base = synth.config_elt_mcao(precision="fp32")
     t0 = time.perf_counter()
@@ -197,7 +210,7 @@ def run_batch(args, dev):
             j = ctx.fewha_get_vector(1).double().cpu().numpy()
             n1 = ctx.coeff_offsets[1]
             jinv = [j[:n1]] * B
-        wall, fm = timed(ctx, 3, max(3, args.batch_steps // 4))
+        wall, fm = timed(ctx, tune_warm, tune_steps)
         tune[be] = float(np.median(fm))
         log(f"batched leg: block_elems {be}: frame {tune[be]:.3f} ms")
         del ctx
@@ -249,7 +262,7 @@ def run_batch(args, dev):
         "steps": args.batch_steps, "warmup": args.batch_warmup,
         "block_elems": best, "tuner_frame_ms": {str(k): round(v, 4) for k, v in tune.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom, "batched"),
                      "share_of_frame": round(kern[dom]["ms_per_frame"] / float(np.median(fm)), 3)},
         "kernels": dict(sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_frame"])),
         "input": f"{A} seeded atmospheres, instance i reads atmosphere i mod {A} from frame {stride} (i div {A})",
@@ -649,7 +662,7 @@ def main(argv=None):
     d = opk[dk]
     achieved = d["bytes"] / (d["avg_us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "kernel": dk, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": pmc_traffic(dom),
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": pmc_traffic(dk, "single"),
                 "bytes_per_launch": d["bytes"], "avg_launch_us": d["avg_us"],
                 "share_of_frame": round(per_kernel[dom] * 1e-3 / float(np.median(frame_ms)), 3)}
 
