@@ -52,6 +52,7 @@ struct LayerDev {
     int32_t pq0;          // first (p, q) partial of the layer: tiled analysis tiles by level, then coarse
     int32_t pq_coarse;    // index of the coarse analysis partial (relative to pq0)
     int32_t rb0;          // the gather records of (sensor d.g0 + j, this layer) start at recbase[rb0 + j]
+    int32_t wb0;          // gather windows of (tile k of this layer, sensor d.g0 + j) at gwin[wb0 + k ng + j]
 };
 
 inline int coarse_first_level(int n, int cb) {
@@ -126,7 +127,7 @@ struct Scalars {
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
     size_t layers, wfs, pairs, cellidx, frac, ranges, weight, prior_a, jinv;
-    size_t insts, vecblk, gramblk, step_layers, data_tiles, gather_tiles, grecs, recbase;
+    size_t insts, vecblk, gramblk, step_layers, data_tiles, gather_tiles, grecs, recbase, gwin;
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
     size_t c, r, z, b, b_prev, s_in;
     size_t ring_u, ring_q;
@@ -181,6 +182,7 @@ struct Ctx {
     int max_levels = 0, max_n = 0;
     int slots = 0;             // ring capacity k + max_iter
     int max_rng = 0;           // largest gather contribution count of a layer row/column
+    int max_gwin = 0;          // largest sensor-node window (rows x columns) of a gather tile
     std::vector<StepInfo> steps;  // tiled wavelet levels (ascending block size)
     int npq = 0;               // (p, q) partial entries written by one analysis
     int64_t n_cells = 0, n_ranges = 0;

@@ -665,6 +665,112 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
     }
 }
 
+// The same sum with the sensor nodes staged in LDS: per (tile, sensor) the setup stores the
+// rectangle of sensor nodes the tile's records reach (gwin); the workgroup loads it with
+// coalesced reads (PERW per thread, at most PERW x 256 nodes), then every layer node reads
+// its RF x RF window from LDS.  The next sensor's rectangle and records are fetched into
+// registers while the current one is summed.  Used for large systems, where the direct
+// per-node reads of k_adj_gather are bound by load latency and instruction count.
+template <typename T, int RF, int NRW, int PERW>
+__global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __restrict__ wfs,
+                                                              const LayerDev* __restrict__ lays,
+                                                              const int2* __restrict__ tiles,
+                                                              const int64_t* __restrict__ recbase,
+                                                              const GatherRec<T>* __restrict__ recs,
+                                                              const int4* __restrict__ gwin,
+                                                              const T* __restrict__ psi, T* __restrict__ out) {
+    constexpr int TR = kGRowStep * NRW;
+    constexpr int NR = TR + kGT;                         // records per sensor: tile rows, then columns
+    static_assert(NR <= kThreads, "one record per thread");
+    __shared__ int32_t s_start[NR], s_cnt[NR];
+    __shared__ T s_w[NR][RF];
+    __shared__ T win[PERW * kThreads];
+    const int2 lt = tiles[blockIdx.x];
+    if (lt.x < 0) return;                                // padding of the die-ordered grid
+    const LayerDev d = lays[lt.x];
+    const int n = d.n, tx = (n + kGT - 1) / kGT;
+    const int a0 = (lt.y / tx) * TR, b0 = (lt.y % tx) * kGT;
+    const int la = threadIdx.x / kGT, lb = threadIdx.x % kGT;
+    const int b = b0 + lb;
+    const int G = d.ng;
+    const WfsDev* __restrict__ wf = wfs + d.g0;
+    const int64_t* __restrict__ rb = recbase + d.rb0;
+    const int4* __restrict__ wt = gwin + d.wb0 + int64_t(lt.y) * G;
+    // the thread's record (clamped to a valid one; only threads < NR stage theirs)
+    const int re = threadIdx.x < NR ? threadIdx.x : NR - 1;
+    const int rnode = re < TR ? a0 + re : b0 + re - TR;
+    const bool rvalid = rnode < n;
+    const int64_t roff = (re < TR ? 0 : n) + (rvalid ? rnode : 0);
+    GatherRec<T> rr;
+    T wv[PERW];
+    int4 wn;
+    auto fetch = [&](int gl) {
+        wn = wt[gl];
+        const int np = wf[gl].ns + 1;
+        const T* __restrict__ ps = psi + wf[gl].noff;
+        const int size = wn.y * wn.w;
+        const float inv = 1.0f / float(wn.w);
+#pragma unroll
+        for (int k = 0; k < PERW; ++k) {
+            const int e = min(int(threadIdx.x) + k * kThreads, size - 1);
+            int r = int((float(e) + 0.5f) * inv);          // exact for these small sizes
+            r = r * wn.w > e ? r - 1 : r;
+            const int c = e - r * wn.w;
+            wv[k] = ps[(wn.x + r) * np + wn.z + c];
+        }
+        rr = recs[rb[gl] + roff];
+    };
+    T acc[NRW];
+#pragma unroll
+    for (int k = 0; k < NRW; ++k) acc[k] = 0;
+    fetch(0);
+    for (int gl = 0; gl < G; ++gl) {
+        const int4 w = wn;
+#pragma unroll
+        for (int k = 0; k < PERW; ++k) win[threadIdx.x + k * kThreads] = wv[k];
+        if (threadIdx.x < NR) {
+            const int cnt = rvalid ? rr.count : 0;
+            s_start[threadIdx.x] = cnt > 0 ? rr.start : 0;
+            s_cnt[threadIdx.x] = cnt;
+#pragma unroll
+            for (int q = 0; q < RF; ++q) s_w[threadIdx.x][q] = rr.w[q] * T(q < cnt);
+        }
+        __syncthreads();
+        fetch(gl + 1 < G ? gl + 1 : gl);                  // in flight during the sums below
+        if (b < n) {
+            const int jc = s_start[TR + lb] - w.z, cc = s_cnt[TR + lb];
+            T wc[RF];
+#pragma unroll
+            for (int q = 0; q < RF; ++q) wc[q] = s_w[TR + lb][q];
+#pragma unroll
+            for (int k = 0; k < NRW; ++k) {
+                const int e = la + k * kGRowStep;
+                const int ir = s_start[e] - w.x, cr = s_cnt[e];
+                T sum = 0;
+#pragma unroll
+                for (int r = 0; r < RF; ++r) {
+                    T row = 0;
+#pragma unroll
+                    for (int q = 0; q < RF; ++q) {
+                        const bool ok = r < cr && q < cc;     // masked entries read element 0 (weight 0)
+                        row += wc[q] * win[ok ? (ir + r) * w.w + jc + q : 0];
+                    }
+                    sum += s_w[e][r] * row;
+                }
+                acc[k] += sum;
+            }
+        }
+        __syncthreads();
+    }
+    if (b < n) {
+#pragma unroll
+        for (int k = 0; k < NRW; ++k) {
+            const int a = a0 + la + k * kGRowStep;
+            if (a < n) out[d.off + size_t(a) * n + b] = acc[k];
+        }
+    }
+}
+
 // The same sum for configurations whose contribution lists exceed kRMax (layer grids much
 // coarser than the sensor grids): every node walks its ranges and the bilinear cells.
 template <typename T>
@@ -832,7 +938,21 @@ void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStrea
                                                    c.at<GatherRec<T>>(c.lay.grecs), psi_nodes, psi_layers);
         };
         const bool wide = c.gather_rows > 1;
-        if (c.max_rng <= 2)
+        auto gow = [&](auto kern) {
+            kern<<<c.gather_grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
+                                                   c.at<int2>(c.lay.gather_tiles), c.at<int64_t>(c.lay.recbase),
+                                                   c.at<GatherRec<T>>(c.lay.grecs), c.at<int4>(c.lay.gwin),
+                                                   psi_nodes, psi_layers);
+        };
+        // large systems with windows that fit: LDS-staged sensor nodes
+        if (wide && c.max_rng <= 2 && c.max_gwin <= 4 * kThreads) {
+            if (c.max_gwin <= 2 * kThreads)
+                gow(k_adj_gather_win<T, 2, 4, 2>);
+            else
+                gow(k_adj_gather_win<T, 2, 4, 4>);
+        } else if (wide && c.max_rng <= 3 && c.max_gwin <= 4 * kThreads) {
+            gow(k_adj_gather_win<T, 3, 4, 4>);
+        } else if (c.max_rng <= 2)
             wide ? go(k_adj_gather<T, 2, 4>) : go(k_adj_gather<T, 2, 1>);
         else if (c.max_rng <= 3)
             wide ? go(k_adj_gather<T, 3, 4>) : go(k_adj_gather<T, 3, 1>);

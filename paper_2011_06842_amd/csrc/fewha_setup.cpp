@@ -139,6 +139,7 @@ struct Sizes {
     int B = 0, L = 0, G = 0, slots = 0, esz = 8, KE = 1;
     int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;   // pairs: also the record bases
     int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, step_list = 0, gather_rows = 1;
+    int64_t gwin = 0;   // gather windows: (layer tile, sensor of its instance) pairs
     std::vector<StepInfo> steps;
 };
 
@@ -200,7 +201,11 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
     // adjoint-gather tiles: 8 x kGT nodes for small systems (more workgroups), 32 x kGT beyond
     z.gather_rows = z.N >= kGatherWide ? 4 : 1;
     for (int i = 0; i < nb; ++i)
-        for (int l = 0; l < cfgs[i].n_layers; ++l) z.gather_tiles += gather_tiles_of(cfgs[i].layers[l].n, z.gather_rows);
+        for (int l = 0; l < cfgs[i].n_layers; ++l) {
+            const int gt = gather_tiles_of(cfgs[i].layers[l].n, z.gather_rows);
+            z.gather_tiles += gt;
+            z.gwin += int64_t(gt) * cfgs[i].n_wfs;
+        }
     // tiled wavelet levels: block sizes above the coarse block, with every layer that has them
     for (int nbs = 2 * cb; nbs <= 1024; nbs *= 2) {
         StepInfo st;
@@ -264,6 +269,7 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.gather_tiles = take(sizeof(int2) * round_up(z.gather_tiles, kXcds));
     lo.grecs = take((z.esz == 8 ? sizeof(GatherRec<double>) : sizeof(GatherRec<float>)) * z.ranges);
     lo.recbase = take(sizeof(int64_t) * std::max<int64_t>(1, z.pairs));
+    lo.gwin = take(sizeof(int4) * std::max<int64_t>(1, z.gwin));
     lo.weight = take(e * S);
     lo.prior_a = take(e * N);
     lo.jinv = take(e * N);
@@ -635,6 +641,41 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
         d.rb0 = int32_t(recbase.size());
         for (int j = 0; j < d.ng; ++j) recbase.push_back(t.pd[t.wd[d.g0 + j].pair0 + (l - d.l0)].rng_off);
     }
+    // gather windows: per (layer tile, sensor of the layer's instance) the rectangle of sensor
+    // nodes that the tile's records reach, {first row, rows, first column, columns}; a tile
+    // the sensor does not see gets the 1 x 1 window {0, 1, 0, 1} (all its weights are zero)
+    std::vector<int4> gwin;
+    ctx.max_gwin = 1;
+    {
+        const int tr = kGRowStep * z.gather_rows;
+        for (int l = 0; l < z.L; ++l) {
+            LayerDev& d = t.ld[l];
+            d.wb0 = int32_t(gwin.size());
+            const int n = d.n, tx = (n + kGT - 1) / kGT, nt = gather_tiles_of(n, z.gather_rows);
+            for (int k = 0; k < nt; ++k) {
+                const int a0 = (k / tx) * tr, b0 = (k % tx) * kGT;
+                for (int j = 0; j < d.ng; ++j) {
+                    const PairDev& p = t.pd[t.wd[d.g0 + j].pair0 + (l - d.l0)];
+                    int lo[2] = {INT32_MAX, INT32_MAX}, hi[2] = {INT32_MIN, INT32_MIN};
+                    for (int axis = 0; axis < 2; ++axis) {
+                        const int first = axis == 0 ? a0 : b0, cnt = axis == 0 ? tr : kGT;
+                        for (int a = first; a < std::min(n, first + cnt); ++a) {
+                            const size_t ri = size_t(p.rng_off) + size_t(axis) * n + a;
+                            const int st = t.rng[2 * ri], c = t.rng[2 * ri + 1];
+                            if (c > 0) {
+                                lo[axis] = std::min(lo[axis], st);
+                                hi[axis] = std::max(hi[axis], st + c);
+                            }
+                        }
+                    }
+                    int4 w = make_int4(0, 1, 0, 1);
+                    if (lo[0] < hi[0] && lo[1] < hi[1]) w = make_int4(lo[0], hi[0] - lo[0], lo[1], hi[1] - lo[1]);
+                    ctx.max_gwin = std::max(ctx.max_gwin, w.y * w.w);
+                    gwin.push_back(w);
+                }
+            }
+        }
+    }
     // gather records: per pair, layer rows then columns, parallel to the ranges
     std::vector<char> recs;
     auto build_recs = [&](auto tag) {
@@ -710,6 +751,7 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
               up(lo.gather_tiles, gtiles.data(), sizeof(int2) * gtiles.size()) &&
               up(lo.grecs, recs.data(), recs.size()) &&
               up(lo.recbase, recbase.data(), sizeof(int64_t) * recbase.size()) &&
+              up(lo.gwin, gwin.data(), sizeof(int4) * gwin.size()) &&
               up(lo.lconst, lconst.data(), sizeof(float) * lconst.size()) &&
               up(lo.weight, w_t.data(), w_t.size()) && up(lo.prior_a, pa_t.data(), pa_t.size()) &&
               up(lo.jinv, j_t.data(), j_t.size());
