@@ -182,7 +182,7 @@ struct Ctx {
     int max_levels = 0, max_n = 0;
     int slots = 0;             // ring capacity k + max_iter
     int max_rng = 0;           // largest gather contribution count of a layer row/column
-    int max_gwin = 0;          // largest sensor-node window (rows x columns) of a gather tile
+    int max_gwin_side = 0;     // largest side of the sensor-node rectangle of a gather tile
     std::vector<StepInfo> steps;  // tiled wavelet levels (ascending block size)
     int npq = 0;               // (p, q) partial entries written by one analysis
     int64_t n_cells = 0, n_ranges = 0;

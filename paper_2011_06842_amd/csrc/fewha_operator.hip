@@ -371,9 +371,11 @@ __device__ __forceinline__ int find_sensor(const WfsDev* __restrict__ wfs, int G
 // slopes on the (kTile+1)^2 subapertures touching it, adjoint onto the kTile^2 nodes.  The
 // bilinear cell tables of the tile's rows and columns are staged in LDS for every layer, and
 // each node's layer sum is split over kLayerGroups threads (layers l = lg mod kLayerGroups),
-// combined in a fixed order.
-template <typename T>
-__global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __restrict__ wfs,
+// combined in a fixed order.  NT threads per workgroup: 1024 for small systems (few tiles),
+// 256 for large ones (more workgroups per CU to overlap their memory latencies); the
+// arithmetic of every node is the same for both.
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs,
                                                              const int2* __restrict__ tiles,
                                                              const LayerDev* __restrict__ lays,
                                                              const PairDev* __restrict__ pairs,
@@ -381,7 +383,7 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
                                                              const T* __restrict__ frac, const T* __restrict__ phi,
                                                              const T* __restrict__ w, T* __restrict__ psi) {
     constexpr int E = kTile + 2, S1 = kTile + 1;
-    static_assert(S1 * S1 <= kDataThreads, "one subaperture per thread");
+    constexpr int PS = (S1 * S1 + NT - 1) / NT;              // subapertures per thread
     __shared__ T spart[kLayerGroups][E * E];
     __shared__ T stx[S1 * S1], sty[S1 * S1];
     __shared__ int32_t srow[FEWHA_MAX_LAYERS][E], scol[FEWHA_MAX_LAYERS][E];
@@ -395,25 +397,27 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
     const int L = W.nl;
     const int tl = st.y;
     const int i0 = (tl / W.tiles_x) * kTile, j0 = (tl % W.tiles_x) * kTile;
-    // slope weights of this thread's subaperture, requested before anything waits
-    T wxs = 0, wys = 0;
-    {
-        const int e = threadIdx.x;
+    // slope weights of this thread's subapertures, requested before anything waits
+    T wxs[PS], wys[PS];
+#pragma unroll
+    for (int k = 0; k < PS; ++k) {
+        const int e = threadIdx.x + k * NT;
         const int ls = e / S1, lt = e - ls * S1;
         const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
+        wxs[k] = wys[k] = 0;
         if (e < S1 * S1 && si >= 0 && si < ns && sj >= 0 && sj < ns) {
-            wxs = w[W.soff + si * ns + sj];
-            wys = w[W.soff + ns * ns + si * ns + sj];
+            wxs[k] = w[W.soff + si * ns + sj];
+            wys[k] = w[W.soff + ns * ns + si * ns + sj];
         }
     }
     // the layers of the sensor's instance and the bilinear cells of the tile's rows and
     // columns on each: every load is issued before the first LDS store
-    constexpr int PER = (FEWHA_MAX_LAYERS * 2 * E + kDataThreads - 1) / kDataThreads;
+    constexpr int PER = (FEWHA_MAX_LAYERS * 2 * E + NT - 1) / NT;
     int32_t ci[PER];
     T fr[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * kDataThreads;
+        const int e = threadIdx.x + k * NT;
         if (e < L * 2 * E) {
             const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
             const int node = (col ? j0 : i0) - 1 + kk;
@@ -432,7 +436,7 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * kDataThreads;
+        const int e = threadIdx.x + k * NT;
         if (e < L * 2 * E) {
             const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
             if (col) {
@@ -449,7 +453,7 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
         soffl[threadIdx.x] = loff;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kLayerGroups * E * E; e += kDataThreads) {
+    for (int e = threadIdx.x; e < kLayerGroups * E * E; e += NT) {
         const int lg = e / (E * E), node = e - lg * E * E;
         const int li = node / E, lj = node - li * E;
         const int i = i0 - 1 + li, j = j0 - 1 + lj;
@@ -467,14 +471,17 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
         spart[lg][node] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < E * E; e += kDataThreads) {
+    for (int e = threadIdx.x; e < E * E; e += NT) {
         T v = spart[0][e];
         for (int lg = 1; lg < kLayerGroups; ++lg) v += spart[lg][e];
         spart[0][e] = v;
     }
     __syncthreads();
     const T* sphi = spart[0];
-    for (int e = threadIdx.x; e < S1 * S1; e += kDataThreads) {
+#pragma unroll
+    for (int k = 0; k < PS; ++k) {
+        const int e = threadIdx.x + k * NT;
+        if (e >= S1 * S1) break;
         const int ls = e / S1, lt = e - ls * S1;
         const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
         T tx = 0, ty = 0;
@@ -483,14 +490,14 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
             const T p10 = sphi[(ls + 1) * E + lt], p11 = sphi[(ls + 1) * E + lt + 1];
             const T sx = T(0.5) * ((p01 - p00) + (p11 - p10));
             const T sy = T(0.5) * ((p10 - p00) + (p11 - p01));
-            tx = wxs * sx;                                          // e == threadIdx.x (S1^2 <= threads)
-            ty = wys * sy;
+            tx = wxs[k] * sx;
+            ty = wys[k] * sy;
         }
         stx[e] = tx;
         sty[e] = ty;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTile * kTile; e += kDataThreads) {
+    for (int e = threadIdx.x; e < kTile * kTile; e += NT) {
         const int li = e / kTile, lj = e - li * kTile;
         const int i = i0 + li, j = j0 + lj;
         if (i > ns || j > ns) continue;
@@ -666,12 +673,16 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
 }
 
 // The same sum with the sensor nodes staged in LDS: per (tile, sensor) the setup stores the
-// rectangle of sensor nodes the tile's records reach (gwin); the workgroup loads it with
-// coalesced reads (PERW per thread, at most PERW x 256 nodes), then every layer node reads
-// its RF x RF window from LDS.  The next sensor's rectangle and records are fetched into
-// registers while the current one is summed.  Used for large systems, where the direct
-// per-node reads of k_adj_gather are bound by load latency and instruction count.
-template <typename T, int RF, int NRW, int PERW>
+// rectangle of sensor nodes the tile's records reach (gwin, extended by RF - 1 rows and
+// columns so that every RF x RF window of a record lies inside it; at most 32 x 32).  The
+// workgroup loads it with coalesced reads (thread t: column t mod 32, rows t / 32 + 8 k,
+// clamped to the sensor grid) into a 32 x 32 LDS image, then every layer node reads its
+// RF x RF window at fixed offsets from one base (the weights of entries past a record's
+// count are zero; a record the sensor does not see points at the rectangle's origin).  The
+// next sensor's rectangle and records are fetched into registers while the current one is
+// summed.  Used for large systems, where the per-node reads of k_adj_gather are bound by
+// instruction issue.
+template <typename T, int RF, int NRW>
 __global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __restrict__ wfs,
                                                               const LayerDev* __restrict__ lays,
                                                               const int2* __restrict__ tiles,
@@ -681,10 +692,12 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __res
                                                               const T* __restrict__ psi, T* __restrict__ out) {
     constexpr int TR = kGRowStep * NRW;
     constexpr int NR = TR + kGT;                         // records per sensor: tile rows, then columns
+    constexpr int WP = 32;                               // LDS image pitch (and largest side)
+    constexpr int PERW = WP * WP / kThreads;             // image rows per thread (4)
     static_assert(NR <= kThreads, "one record per thread");
-    __shared__ int32_t s_start[NR], s_cnt[NR];
+    __shared__ int32_t s_base[NR];                       // rows: (start - r0) WP; columns: start - c0
     __shared__ T s_w[NR][RF];
-    __shared__ T win[PERW * kThreads];
+    __shared__ T win[WP * WP];
     const int2 lt = tiles[blockIdx.x];
     if (lt.x < 0) return;                                // padding of the die-ordered grid
     const LayerDev d = lays[lt.x];
@@ -701,6 +714,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __res
     const int rnode = re < TR ? a0 + re : b0 + re - TR;
     const bool rvalid = rnode < n;
     const int64_t roff = (re < TR ? 0 : n) + (rvalid ? rnode : 0);
+    const int icol = threadIdx.x % WP, irow = threadIdx.x / WP;
     GatherRec<T> rr;
     T wv[PERW];
     int4 wn;
@@ -708,16 +722,9 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __res
         wn = wt[gl];
         const int np = wf[gl].ns + 1;
         const T* __restrict__ ps = psi + wf[gl].noff;
-        const int size = wn.y * wn.w;
-        const float inv = 1.0f / float(wn.w);
+        const int cc = min(wn.z + icol, np - 1);
 #pragma unroll
-        for (int k = 0; k < PERW; ++k) {
-            const int e = min(int(threadIdx.x) + k * kThreads, size - 1);
-            int r = int((float(e) + 0.5f) * inv);          // exact for these small sizes
-            r = r * wn.w > e ? r - 1 : r;
-            const int c = e - r * wn.w;
-            wv[k] = ps[(wn.x + r) * np + wn.z + c];
-        }
+        for (int k = 0; k < PERW; ++k) wv[k] = ps[uint32_t(min(wn.x + irow + k * (kThreads / WP), np - 1) * np + cc)];
         rr = recs[rb[gl] + roff];
     };
     T acc[NRW];
@@ -725,36 +732,32 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __res
     for (int k = 0; k < NRW; ++k) acc[k] = 0;
     fetch(0);
     for (int gl = 0; gl < G; ++gl) {
-        const int4 w = wn;
 #pragma unroll
         for (int k = 0; k < PERW; ++k) win[threadIdx.x + k * kThreads] = wv[k];
         if (threadIdx.x < NR) {
             const int cnt = rvalid ? rr.count : 0;
-            s_start[threadIdx.x] = cnt > 0 ? rr.start : 0;
-            s_cnt[threadIdx.x] = cnt;
+            const int st = cnt > 0 ? rr.start : (re < TR ? wn.x : wn.z);
+            s_base[threadIdx.x] = re < TR ? (st - wn.x) * WP : st - wn.z;
 #pragma unroll
             for (int q = 0; q < RF; ++q) s_w[threadIdx.x][q] = rr.w[q] * T(q < cnt);
         }
         __syncthreads();
         fetch(gl + 1 < G ? gl + 1 : gl);                  // in flight during the sums below
         if (b < n) {
-            const int jc = s_start[TR + lb] - w.z, cc = s_cnt[TR + lb];
+            const int cb = s_base[TR + lb];
             T wc[RF];
 #pragma unroll
             for (int q = 0; q < RF; ++q) wc[q] = s_w[TR + lb][q];
 #pragma unroll
             for (int k = 0; k < NRW; ++k) {
                 const int e = la + k * kGRowStep;
-                const int ir = s_start[e] - w.x, cr = s_cnt[e];
+                const T* __restrict__ wp = win + s_base[e] + cb;
                 T sum = 0;
 #pragma unroll
                 for (int r = 0; r < RF; ++r) {
                     T row = 0;
 #pragma unroll
-                    for (int q = 0; q < RF; ++q) {
-                        const bool ok = r < cr && q < cc;     // masked entries read element 0 (weight 0)
-                        row += wc[q] * win[ok ? (ir + r) * w.w + jc + q : 0];
-                    }
+                    for (int q = 0; q < RF; ++q) row += wc[q] * wp[r * WP + q];
                     sum += s_w[e][r] * row;
                 }
                 acc[k] += sum;
@@ -915,10 +918,16 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
 template <typename T>
 void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s) {
     ProfScope ps_(c, KID_DATA_TERM, s);
-    k_data_term<T><<<c.data_grid, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles),
-                                                        c.at<LayerDev>(c.lay.layers), c.at<PairDev>(c.lay.pairs),
-                                                        c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), phi,
-                                                        c.at<T>(c.lay.weight), psi_nodes);
+    auto go = [&](auto kern, int nt) {
+        kern<<<c.data_grid, nt, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles),
+                                        c.at<LayerDev>(c.lay.layers), c.at<PairDev>(c.lay.pairs),
+                                        c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), phi,
+                                        c.at<T>(c.lay.weight), psi_nodes);
+    };
+    if (c.gather_rows > 1)   // large system (the wide adjoint-gather tiles): smaller workgroups
+        go(k_data_term<T, 256>, 256);
+    else
+        go(k_data_term<T, kDataThreads>, kDataThreads);
 }
 
 template <typename T>
@@ -945,13 +954,11 @@ void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStrea
                                                    psi_nodes, psi_layers);
         };
         // large systems with windows that fit: LDS-staged sensor nodes
-        if (wide && c.max_rng <= 2 && c.max_gwin <= 4 * kThreads) {
-            if (c.max_gwin <= 2 * kThreads)
-                gow(k_adj_gather_win<T, 2, 4, 2>);
-            else
-                gow(k_adj_gather_win<T, 2, 4, 4>);
-        } else if (wide && c.max_rng <= 3 && c.max_gwin <= 4 * kThreads) {
-            gow(k_adj_gather_win<T, 3, 4, 4>);
+        // (rectangles, extended by RF - 1, of at most 32 x 32 sensor nodes)
+        if (wide && c.max_rng <= 2 && c.max_gwin_side + 1 <= 32) {
+            gow(k_adj_gather_win<T, 2, 4>);
+        } else if (wide && c.max_rng <= 3 && c.max_gwin_side + 2 <= 32) {
+            gow(k_adj_gather_win<T, 3, 4>);
         } else if (c.max_rng <= 2)
             wide ? go(k_adj_gather<T, 2, 4>) : go(k_adj_gather<T, 2, 1>);
         else if (c.max_rng <= 3)

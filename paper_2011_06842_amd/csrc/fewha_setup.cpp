@@ -645,7 +645,7 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     // nodes that the tile's records reach, {first row, rows, first column, columns}; a tile
     // the sensor does not see gets the 1 x 1 window {0, 1, 0, 1} (all its weights are zero)
     std::vector<int4> gwin;
-    ctx.max_gwin = 1;
+    ctx.max_gwin_side = 1;
     {
         const int tr = kGRowStep * z.gather_rows;
         for (int l = 0; l < z.L; ++l) {
@@ -670,7 +670,7 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
                     }
                     int4 w = make_int4(0, 1, 0, 1);
                     if (lo[0] < hi[0] && lo[1] < hi[1]) w = make_int4(lo[0], hi[0] - lo[0], lo[1], hi[1] - lo[1]);
-                    ctx.max_gwin = std::max(ctx.max_gwin, w.y * w.w);
+                    ctx.max_gwin_side = std::max(ctx.max_gwin_side, std::max(w.y, w.w));
                     gwin.push_back(w);
                 }
             }

@@ -350,9 +350,15 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
             for (int b = 0; b < m; ++b) sc->R[k * m + b] = X[k * W + b];
         if (k == 0) sc->dropped = 0;
     } else {
-        const int dropped = wave_cholesky<MB>(X, W, m, sc->R, sc->keep);
+        // the factor goes to LDS first (the solve reads it back at LDS latency, in order
+        // within the wavefront), then to the scalars for the kernels after this one
+        __shared__ double sR[kKMax * kKMax];
+        __shared__ int32_t skeep[kKMax];
+        const int dropped = wave_cholesky<MB>(X, W, m, sR, skeep);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        y = wave_chol_solve<MB>(sc->R, sc->keep, m, v);
+        y = wave_chol_solve<MB>(sR, skeep, m, v);
+        for (int e = k; e < m * m; e += 64) sc->R[e] = sR[e];
+        if (k < m) sc->keep[k] = skeep[k];
         if (k == 0) sc->dropped = dropped;
     }
     if (k < m) sc->y[k] = y;
