@@ -318,6 +318,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     const int ngb = I.ngb;
     const int ne = m * (m + 1);
     {   // 8 lanes per entry, each summing up to kGramBlocks / 8 partials requested all at once
+        // (lane sub takes partials sub, sub + 8, ...: the 8 lanes of an entry read 64
+        // contiguous bytes per load)
         constexpr int PER = kGramBlocks / 8;
         const int sub = threadIdx.x & 7;
         for (int e0 = 0; e0 < ne; e0 += kSolveThreads / 8) {
@@ -325,7 +327,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
             double v[PER];
 #pragma unroll
             for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped, zeroed by a factor)
-                const int j = sub * PER + k;
+                const int j = k * 8 + sub;
                 const bool ok = e < ne && j < ngb;
                 v[k] = gp[ok ? size_t(e) * ngb + j : 0] * (ok ? 1.0 : 0.0);
             }
