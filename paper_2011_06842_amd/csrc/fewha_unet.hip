@@ -68,6 +68,7 @@ enum { CONV_DIRECT = 0, CONV_CONCAT_UP = 1 };
 // Every input tensor carries one extra pixel of zeros after its last pixel (the zero row):
 // operands outside the image read it, so the zero padding costs no masking.
 // OUT_BF16: out = bf16(relu?(acc + bias)) [P][Cout]; else out = acc (FP32) [P][Cout].
+// One launch covers several image groups (square images, per-group tensors).
 // Cin, C1, Cout multiples of 32.  A wavefront computes 64 pixels x 32 output channels (4 x 2
 // MFMA tiles of 16 x 16, K = 32 channels of one tap per reduction position).  KS (1, 2 or 4)
 // splits the reduction over the wavefronts of a workgroup: the workgroup covers 256 / KS
@@ -75,20 +76,36 @@ enum { CONV_DIRECT = 0, CONV_CONCAT_UP = 1 };
 // w / (4 / KS); the KS partial tiles are summed in a fixed order through LDS.  Requires
 // 9 Cin / 32 to be a multiple of 3 KS.  Byte offsets into the inputs must fit in 32 bits
 // (with at most 2^25 pixels per level and 64 bytes per full-resolution pixel they do).
+// The image groups of one launch: group g covers workgroups [block0[g], block0[g + 1]).
+struct ConvGroup {
+    const bf16_t* in0;
+    const bf16_t* in1;
+    void* out;
+    int N, H, block0;
+};
+struct ConvGroups {
+    ConvGroup g[FEWHA_UNET_MAX_GROUPS + 1];   // entry `count` holds the end block
+    int count;
+};
+
 template <int MODE, bool OUT_BF16, int KS>
-__global__ void __launch_bounds__(kT) k_conv3x3(const bf16_t* __restrict__ in0, const bf16_t* __restrict__ in1,
-                                                 int C1, int Cin, int N, int H, int W,
-                                                 const bf16_t* __restrict__ wt, const float* __restrict__ bias,
-                                                 int relu, void* __restrict__ out, int Cout) {
+__global__ void __launch_bounds__(kT) k_conv3x3(ConvGroups cg, int C1, int Cin, const bf16_t* __restrict__ wt,
+                                                 const float* __restrict__ bias, int relu, int Cout) {
     constexpr int PG = 4 / KS;            // 64-pixel groups per workgroup
     constexpr int MT = 4;                 // 16-pixel MFMA tiles per wavefront
+    int gi = 0;
+    while (gi + 1 < cg.count && int(blockIdx.x) >= cg.g[gi + 1].block0) ++gi;
+    const bf16_t* __restrict__ in0 = cg.g[gi].in0;
+    const bf16_t* __restrict__ in1 = cg.g[gi].in1;
+    void* __restrict__ out = cg.g[gi].out;
+    const int N = cg.g[gi].N, H = cg.g[gi].H, W = H;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar position counters
     const int r16 = lane & 15, kg = lane >> 4;
     const int pg = wv % PG, ks = wv / PG;
     const int P = N * H * W;
     const int co0 = blockIdx.y * 32;
-    const int pb = blockIdx.x * (64 * PG) + pg * 64;
+    const int pb = (int(blockIdx.x) - cg.g[gi].block0) * (64 * PG) + pg * 64;
     const int C2 = Cin - C1, Hh = H >> 1, Wh = W >> 1, Ph = N * Hh * Wh;
     const int lh = __builtin_ctz(H), lw = __builtin_ctz(W);   // H, W powers of two
     // per MFMA row tile: the in-image bits of the lane's nine taps, the element offset of its
@@ -824,42 +841,68 @@ struct fewha_unet {
         }
     }
 
-    // 3x3 convolution launch: the reduction is split over the wavefronts of a workgroup
-    // (KS = 2 or 4) when the output alone gives fewer than 768 workgroups of 128 pixels
+    // 3x3 convolution launch over the groups of `cg` (their N and H set): the reduction is
+    // split over the wavefronts of a workgroup (KS = 2 or 4) when the output alone gives fewer
+    // than 768 workgroups of 256 pixels
     template <int MODE, bool OUT>
-    static void conv(const bf16_t* in0, const bf16_t* in1, int C1, int Cin, int N, int H, const bf16_t* w,
-                     const float* bias, int relu, void* out, int Cout, hipStream_t s) {
-        const int64_t Pn = int64_t(N) * H * H;
-        const int64_t b1 = int64_t(blocks(Pn, kConvPix)) * (Cout / 32);
+    static void conv(ConvGroups cg, int C1, int Cin, const bf16_t* w, const float* bias, int relu, int Cout,
+                     hipStream_t s) {
+        int64_t b1 = 0;
+        for (int g = 0; g < cg.count; ++g) b1 += int64_t(blocks(int64_t(cg.g[g].N) * cg.g[g].H * cg.g[g].H, kConvPix));
+        b1 *= Cout / 32;
         const int ks = b1 >= 768 ? 1 : Cin % 128 == 0 ? 4 : Cin % 64 == 0 ? 2 : 1;
-        const dim3 grid(blocks(Pn, kConvPix / ks), Cout / 32);
+        int nb = 0;
+        for (int g = 0; g < cg.count; ++g) {
+            cg.g[g].block0 = nb;
+            nb += int(blocks(int64_t(cg.g[g].N) * cg.g[g].H * cg.g[g].H, kConvPix / ks));
+        }
+        cg.g[cg.count].block0 = nb;
+        const dim3 grid(nb, Cout / 32);
         if (ks == 4)
-            k_conv3x3<MODE, OUT, 4><<<grid, kT, 0, s>>>(in0, in1, C1, Cin, N, H, H, w, bias, relu, out, Cout);
+            k_conv3x3<MODE, OUT, 4><<<grid, kT, 0, s>>>(cg, C1, Cin, w, bias, relu, Cout);
         else if (ks == 2)
-            k_conv3x3<MODE, OUT, 2><<<grid, kT, 0, s>>>(in0, in1, C1, Cin, N, H, H, w, bias, relu, out, Cout);
+            k_conv3x3<MODE, OUT, 2><<<grid, kT, 0, s>>>(cg, C1, Cin, w, bias, relu, Cout);
         else
-            k_conv3x3<MODE, OUT, 1><<<grid, kT, 0, s>>>(in0, in1, C1, Cin, N, H, H, w, bias, relu, out, Cout);
+            k_conv3x3<MODE, OUT, 1><<<grid, kT, 0, s>>>(cg, C1, Cin, w, bias, relu, Cout);
     }
 
-    void forward_group(int g, const float* in, hipStream_t s) {
-        const int64_t P0 = P(g, 0);
-        k_pack_input<<<blocks(P0 * kInCh), kT, 0, s>>>(in, P0, x[g]);
+    static ConvGroups one_group(const bf16_t* in0, const bf16_t* in1, void* out, int N, int H) {
+        ConvGroups cg{};
+        cg.g[0] = ConvGroup{in0, in1, out, N, H, 0};
+        cg.count = 1;
+        return cg;
+    }
+
+    // forward pass of every group, each convolution one launch over all groups
+    void forward_all(const float* in, hipStream_t s) {
+        int64_t o = 0;
+        for (int g = 0; g < G; ++g) {
+            const int64_t P0 = P(g, 0);
+            k_pack_input<<<blocks(P0 * kInCh), kT, 0, s>>>(in + o * kInputs, P0, x[g]);
+            o += P0;
+        }
         for (int k = 0; k < kConvs; ++k) {
             const ConvSpec& c = kSpecs[k];
-            if (k == E1A || k == E2A || k == E3A) {   // pool the previous level's output
-                const int l = c.level - 1, Hs = size[g] >> l;
-                k_pool2<<<blocks(P(g, l + 1) * kCh[l]), kT, 0, s>>>(act[g][k - 1], images[g], Hs, Hs, kCh[l], pool[g][l]);
+            ConvGroups cg{};
+            cg.count = G;
+            for (int g = 0; g < G; ++g) {
+                if (k == E1A || k == E2A || k == E3A) {   // pool the previous level's output
+                    const int l = c.level - 1, Hs = size[g] >> l;
+                    k_pool2<<<blocks(P(g, l + 1) * kCh[l]), kT, 0, s>>>(act[g][k - 1], images[g], Hs, Hs, kCh[l],
+                                                                        pool[g][l]);
+                }
+                cg.g[g] = ConvGroup{conv_in0(k, g), conv_in1(k, g), act[g][k], images[g], size[g] >> c.level, 0};
             }
-            const int H = size[g] >> c.level;
             const float* bias = master + b_off[k];
             if (c.concat)
-                conv<CONV_CONCAT_UP, true>(conv_in0(k, g), conv_in1(k, g), concat_c1(k), c.cin, images[g], H, wt[k],
-                                           bias, 1, act[g][k], c.cout, s);
+                conv<CONV_CONCAT_UP, true>(cg, concat_c1(k), c.cin, wt[k], bias, 1, c.cout, s);
             else
-                conv<CONV_DIRECT, true>(conv_in0(k, g), nullptr, 0, c.cin, images[g], H, wt[k], bias, 1, act[g][k],
-                                        c.cout, s);
+                conv<CONV_DIRECT, true>(cg, 0, c.cin, wt[k], bias, 1, c.cout, s);
         }
-        k_head<<<blocks(P0), kT, 0, s>>>(act[g][D0B], master + hw_off, master + hb_off, P0, out[g]);
+        for (int g = 0; g < G; ++g) {
+            const int64_t P0 = P(g, 0);
+            k_head<<<blocks(P0), kT, 0, s>>>(act[g][D0B], master + hw_off, master + hb_off, P0, out[g]);
+        }
     }
 
     // gradient of conv k's output is in gact[k]: weight/bias partials, and (unless k == E0A)
@@ -876,7 +919,7 @@ struct fewha_unet {
         else
             k_conv_wgrad<CONV_DIRECT><<<wg, kT, 0, s>>>(dpre, conv_in0(k, g), nullptr, 0, c.cin, images[g], H, H,
                                                        c.cout, chunk_px[k], wpart[k], wc0);
-        if (gin) conv<CONV_DIRECT, false>(dpre, nullptr, 0, c.cout, images[g], H, wd[k], nullptr, 0, gin, c.cin, s);
+        if (gin) conv<CONV_DIRECT, false>(one_group(dpre, nullptr, gin, images[g], H), 0, c.cout, wd[k], nullptr, 0, c.cin, s);
     }
 
     void backward_group(int g, const float* target, double total, int* wc, int hb0, hipStream_t s) {
@@ -1071,9 +1114,9 @@ fewha_status fewha_unet_get_grads(fewha_unet* net, float* d_grads, void* stream)
 fewha_status fewha_unet_forward(fewha_unet* net, const float* d_in, float* d_out, void* stream) {
     if (!net || !d_in || !d_out) return ufail(net, FEWHA_E_INVAL, "NULL argument");
     hipStream_t s = as_stream(stream);
+    net->forward_all(d_in, s);
     int64_t o = 0;
     for (int g = 0; g < net->G; ++g) {
-        net->forward_group(g, d_in + o * kInputs, s);
         const int64_t P0 = net->P(g, 0);
         k_copy<<<blocks(P0), kT, 0, s>>>(d_out + o, net->out[g], P0);
         o += P0;
@@ -1089,8 +1132,8 @@ fewha_status fewha_unet_backward(fewha_unet* net, const float* d_in, const float
     int hb = 0;
     int64_t o = 0;
     const double total = double(net->nodes);
+    net->forward_all(d_in, s);
     for (int g = 0; g < net->G; ++g) {
-        net->forward_group(g, d_in + o * kInputs, s);
         net->backward_group(g, d_target + o, total, wc, hb, s);
         hb += int(blocks(net->P(g, 0)));
         o += net->P(g, 0);
