@@ -91,10 +91,11 @@ typedef struct {
 } fewha_warmstart;
 
 /* One frame of Alg. 3 (see fewha_solve_aug) with a learned warm start between the residual
- * update and the Galerkin step: the network's nodal correction d gives the candidate
- * c + W d (W = delta^2 W^-T per layer) and its true residual b - M (c + W d), one extra
- * operator application; the candidate replaces (c, r) only when that residual is smaller
- * than the updated one (info flag bit 2: rejected).  ctx must hold a single instance whose
+ * update and the Galerkin step: the network's nodal correction d gives the coefficient
+ * correction e = W d (W = delta^2 W^-T per layer); one extra operator application gives M e,
+ * and the frame takes the step tau = max(0, (e, r) / (e, M e)) that minimises the energy
+ * 1/2 c^T M c - b^T c along e: c += tau e, r -= tau M e (info flag bit 2: tau = 0, the
+ * correction was not taken).  ctx must hold a single instance whose
  * layers, in order, are the network's images (consecutive equal-size layers form a group).
  * Launches directly (no graph). */
 fewha_status fewha_solve_aug_ws(fewha_ctx* ctx, fewha_unet* net, const fewha_warmstart* ws, const void* d_s,

@@ -700,51 +700,52 @@ __global__ void __launch_bounds__(kThreads) k_ws_unpack(int64_t N, const float* 
     if (i < N) d[i] = T(out[i] * so);
 }
 
-// candidate c + W d with W = delta^2 W^-T (W^-1 = DWT^T / delta, DWT orthonormal)
+// correction in coefficients: e = W d with W = delta^2 W^-T (W^-1 = DWT^T / delta, DWT
+// orthonormal), from wtd = W^-T d
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_ws_candidate(int64_t N, const LayerDev* __restrict__ lays, int L,
-                                                            const T* __restrict__ c, const T* __restrict__ wtd,
-                                                            T* __restrict__ cw) {
+__global__ void __launch_bounds__(kThreads) k_ws_delta(int64_t N, const LayerDev* __restrict__ lays, int L,
+                                                        const T* __restrict__ wtd, T* __restrict__ e) {
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= N) return;
     const double id = lays[layer_of(lays, L, i)].inv_delta;
-    cw[i] = T(double(c[i]) + double(wtd[i]) / (id * id));
+    e[i] = T(double(wtd[i]) / (id * id));
 }
 
-// rw = b - M cw (in place over M cw); partials of (rw, rw) and (r, r) in rows P_PROJ, P_PROJ + 1
+// partials of (e, r) and (e, M e) in rows P_PROJ, P_PROJ + 1
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_ws_residual(int64_t N, const VecBlk* __restrict__ vb, int pstride,
-                                                           const T* __restrict__ b, T* __restrict__ rw,
-                                                           const T* __restrict__ r, double* __restrict__ part) {
+__global__ void __launch_bounds__(kThreads) k_ws_dots(int64_t N, const VecBlk* __restrict__ vb, int pstride,
+                                                       const T* __restrict__ e, const T* __restrict__ me,
+                                                       const T* __restrict__ r, double* __restrict__ part) {
     const Seg sg = seg_of(vb, N, 0);
-    double a = 0, o = 0;
+    double er = 0, em = 0;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
-        const T v = T(double(b[i]) - double(rw[i]));
-        rw[i] = v;
-        a += double(v) * double(v);
-        o += double(r[i]) * double(r[i]);
+        const double ei = double(e[i]);
+        er += ei * double(r[i]);
+        em += ei * double(me[i]);
     }
-    const double vv[2] = {a, o};
+    const double vv[2] = {er, em};
     block_partials<2>(vv, part, P_PROJ, pstride, sg.col);
 }
 
-// keep the candidate when its residual is smaller than the updated one
+// Exact line search of the energy 1/2 c^T M c - b^T c along the correction e, restricted to
+// its own direction: tau = max(0, (e, r) / (e, M e)); c += tau e, r -= tau M e.  tau = 0
+// (the correction points uphill, or is zero) leaves the frame as it was.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_ws_select(int64_t N, const VecBlk* __restrict__ vb, int pstride,
-                                                         const double* __restrict__ part, T* __restrict__ c,
-                                                         T* __restrict__ r, const T* __restrict__ cw,
-                                                         const T* __restrict__ rw, Scalars* __restrict__ scs) {
+__global__ void __launch_bounds__(kThreads) k_ws_step(int64_t N, const VecBlk* __restrict__ vb, int pstride,
+                                                       const double* __restrict__ part, T* __restrict__ c,
+                                                       T* __restrict__ r, const T* __restrict__ e,
+                                                       const T* __restrict__ me, Scalars* __restrict__ scs) {
     const Seg sg = seg_of(vb, N, 0);
     double v[2];
     block_row_sums<2>(part, pstride, sg, P_PROJ, 2, v);
-    const bool take = v[0] < v[1];
-    if (sg.local == 0 && threadIdx.x == 0) scs[sg.inst].ws_state = take ? 1 : 2;
-    if (!take) return;
+    const double tau = v[1] > 0 && v[0] > 0 ? v[0] / v[1] : 0.0;
+    if (sg.local == 0 && threadIdx.x == 0) scs[sg.inst].ws_state = tau > 0 ? 1 : 2;
+    if (!(tau > 0)) return;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
-        c[i] = cw[i];
-        r[i] = rw[i];
+        c[i] = T(double(c[i]) + tau * double(e[i]));
+        r[i] = T(double(r[i]) - tau * double(me[i]));
     }
 }
 
@@ -1051,10 +1052,11 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
 }
 
 // Warm-started frame: after the residual update, the network maps [W^-1 c, W^-1 J^-1 r,
-// h / 20 km, gamma] of every layer to a nodal correction d; the candidate c + W d
-// (W = delta^2 W^-T) and its true residual b - M (c + W d) replace (c, r) when that residual
-// is smaller than the updated one (plain augmented PCG judges the correction); then the
-// Galerkin step, the initial direction and the iterations as in any frame.
+// h / 20 km, gamma] of every layer to a nodal correction d; the coefficient correction
+// e = W d (W = delta^2 W^-T) enters with the step that minimises the energy the PCG minimises,
+// tau = max(0, (e, r) / (e, M e)) (one extra operator apply; the solver judges the correction
+// and takes none of it when it points uphill); then the Galerkin step, the initial direction
+// and the iterations as in any frame.
 template <typename T>
 hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& w, const T* slopes, T* c_out, fewha_solve_info* info_user,
                                  hipStream_t s) {
@@ -1075,11 +1077,10 @@ hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& w, const T* slopes, T*
         if (st != FEWHA_OK) return hipErrorLaunchFailure;
         k_ws_unpack<T><<<gN, kThreads, 0, s>>>(f.N, out, w.scale_out, nod);   // d (nodal)
         launch_winvt<T>(c, nod, f.z, static_cast<const T*>(nullptr), nullptr, s);   // W^-T d
-        k_ws_candidate<T><<<gN, kThreads, 0, s>>>(f.N, lays, c.L, f.cv, f.z, f.vy);  // c + delta^2 W^-T d
-        launch_apply_M<T>(c, f.vy, f.vx, nullptr, s);
-        k_ws_residual<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.b, f.vx, f.r, f.part);
-        k_ws_select<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.part, f.cv, f.r, f.vy, f.vx,
-                                                      f.sc);
+        k_ws_delta<T><<<gN, kThreads, 0, s>>>(f.N, lays, c.L, f.z, f.vy);      // e = delta^2 W^-T d
+        launch_apply_M<T>(c, f.vy, f.vx, nullptr, s);                         // M e
+        k_ws_dots<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.vy, f.vx, f.r, f.part);
+        k_ws_step<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.part, f.cv, f.r, f.vy, f.vx, f.sc);
         return hipGetLastError();
     };
     const hipError_t e = run_frame<T>(c, slopes, info_user, s, &iters, hook);
