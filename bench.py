@@ -565,7 +565,7 @@ def main(argv=None):
     if args.copy_probe:
         return copy_probe(args.copy_probe)
     if args.gpus != 1:
-        print("bench.py measures one MI355X: the frame solve runs on a single GPU and this build has no "
+        print("bench.py measures one MI355X: the frame solve runs on a single GPU and the library has no "
               "multi-GPU path (--gpus must be 1)", file=sys.stderr)
         return 2
 

@@ -6,7 +6,7 @@
  * accumulation.  The paper has no learned component; this is the learned extension of its
  * frame update: from the previous coefficients (as a nodal field) and the preconditioned new
  * residual it predicts a nodal correction of the initial guess of augmented PCG (Alg. 2),
- * which stays the solver and the judge of the correction.
+ * which stays the solver and decides how much of the correction to take.
  *
  * Conventions
  *  - Images are grouped by size: group g holds images[g] images of size[g] x size[g] nodes

@@ -1054,7 +1054,7 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
 // Warm-started frame: after the residual update, the network maps [W^-1 c, W^-1 J^-1 r,
 // h / 20 km, gamma] of every layer to a nodal correction d; the coefficient correction
 // e = W d (W = delta^2 W^-T) enters with the step that minimises the energy the PCG minimises,
-// tau = max(0, (e, r) / (e, M e)) (one extra operator apply; the solver judges the correction
+// tau = max(0, (e, r) / (e, M e)) (one extra operator apply; the solver sizes the correction
 // and takes none of it when it points uphill); then the Galerkin step, the initial direction
 // and the iterations as in any frame.
 template <typename T>
