@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(kT) k_conv3x3(ConvGroups cg, int C1, int Cin, 
 // ------------------------------------------------------------------ weight gradient
 
 // Weight and bias gradient partials of the pixels of chunk blockIdx.x (chunk_px pixels, a
-// multiple of 64) for
+// multiple of 64; one launch covers every image group) for
 // the (co tile of 32, ci tile of 32) pair blockIdx.y, all nine taps at once:
 //   part[chunk][tap][co][ci] = sum_p dy[p][co] x[p + tap][ci],
 //   part[chunk][9 Cout Cin + co] = sum_p dy[p][co]   (written by the ci-tile-0 blocks).
@@ -263,11 +263,28 @@ __global__ void __launch_bounds__(kT) k_conv3x3(ConvGroups cg, int C1, int Cin, 
 // and step).  Staging: thread t moves pixels 2 (t mod 32) and 2 (t mod 32) + 1 of the 8
 // channels 8 ((t / 32) mod 4) .. +7 of five of the ten sources (dy and the nine taps), as
 // packed pixel pairs (one 4-byte LDS write per channel).
+// The image groups of one launch: group g's chunks are workgroups [block0[g], block0[g + 1])
+// along x, and partial rows of the same indices.
+struct WgradGroup {
+    const bf16_t* dy;
+    const bf16_t* in0;
+    const bf16_t* in1;
+    int N, H, block0;
+};
+struct WgradGroups {
+    WgradGroup g[FEWHA_UNET_MAX_GROUPS + 1];   // entry `count` holds the end block
+    int count;
+};
+
 template <int MODE>
-__global__ void __launch_bounds__(kT) k_conv_wgrad(const bf16_t* __restrict__ dy, const bf16_t* __restrict__ in0,
-                                                    const bf16_t* __restrict__ in1, int C1, int Cin, int N, int H,
-                                                    int W, int Cout, int chunk_px, float* __restrict__ part,
-                                                    int chunk0) {
+__global__ void __launch_bounds__(kT) k_conv_wgrad(WgradGroups wg, int C1, int Cin, int Cout, int chunk_px,
+                                                    float* __restrict__ part) {
+    int gi = 0;
+    while (gi + 1 < wg.count && int(blockIdx.x) >= wg.g[gi + 1].block0) ++gi;
+    const bf16_t* __restrict__ dy = wg.g[gi].dy;
+    const bf16_t* __restrict__ in0 = wg.g[gi].in0;
+    const bf16_t* __restrict__ in1 = wg.g[gi].in1;
+    const int N = wg.g[gi].N, H = wg.g[gi].H, W = H;
     constexpr int SP = 64;                     // pixels per step
     constexpr int LD = SP + 8;                 // padded row (bf16): 36 dwords, 16-byte aligned rows
     __shared__ __align__(16) bf16_t st[10][32][LD];   // source 0: dy [co][px]; 1 + tap: x [ci][px]
@@ -280,7 +297,7 @@ __global__ void __launch_bounds__(kT) k_conv_wgrad(const bf16_t* __restrict__ dy
     const bool with_bias = ci0 == 0;
     const int P = N * H * W, C2 = Cin - C1, Hh = H >> 1, Wh = W >> 1;
     const int lh = __builtin_ctz(H), lw = __builtin_ctz(W);   // H, W powers of two
-    const int p_begin = blockIdx.x * chunk_px;
+    const int p_begin = (int(blockIdx.x) - wg.g[gi].block0) * chunk_px;
     const int p_end = min(P, p_begin + chunk_px);
     // staging role: pixel pair (2 pair, 2 pair + 1) of the step and channel group grp, so that
     // the lanes of one load cover whole 64-byte pixel rows; sources 2 j + half
@@ -400,7 +417,7 @@ __global__ void __launch_bounds__(kT) k_conv_wgrad(const bf16_t* __restrict__ dy
         __syncthreads();
     }
     const size_t row = size_t(9) * Cout * Cin + Cout;
-    float* dst = part + size_t(chunk0 + blockIdx.x) * row;
+    float* dst = part + size_t(blockIdx.x) * row;
     // lane l, register v: ci row 4 (l / 16) + v, co column l mod 16 of the sub-tile
     {
         const int co = co0 + 16 * mt + r16, ci = ci0 + 16 * nt + 4 * kg;
@@ -713,10 +730,11 @@ struct fewha_unet {
     bf16_t* pool[FEWHA_UNET_MAX_GROUPS][3] = {};
     float* out[FEWHA_UNET_MAX_GROUPS] = {};
     // gradient buffers (largest sizes over groups; groups are processed one after the other)
-    float* gact[kConvs] = {};       // gradient of each conv output
-    float* gcat[3] = {};            // gradient of the concatenated decoder inputs (levels 2, 1, 0)
-    float* gpool[3] = {};           // gradient of the pooled inputs of levels 1, 2, 3
-    bf16_t* dpre = nullptr;         // bf16 ReLU-masked gradient of the current conv
+    // gradient buffers per group (every group's backward runs in the same launches)
+    float* gact[FEWHA_UNET_MAX_GROUPS][kConvs] = {};   // gradient of each conv output
+    float* gcat[FEWHA_UNET_MAX_GROUPS][3] = {};        // of the concatenated decoder inputs (levels 2, 1, 0)
+    float* gpool[FEWHA_UNET_MAX_GROUPS][3] = {};       // of the pooled inputs of levels 1, 2, 3
+    bf16_t* dpre[FEWHA_UNET_MAX_GROUPS] = {};          // bf16 ReLU-masked gradient of the current conv
     float* wpart[kConvs] = {};      // gradient partials [chunks][9 Cout Cin + Cout] (weights, bias)
     int wchunks[kConvs] = {};
     int chunk_px[kConvs] = {};      // pixels per weight-gradient chunk
@@ -780,22 +798,19 @@ struct fewha_unet {
             for (int l = 0; l < 3; ++l) pool[g][l] = take<bf16_t>((P(g, l + 1) + 1) * kCh[l]);
             out[g] = take<float>(P(g, 0));
         }
-        // gradients: sized for the largest group
-        auto maxP = [&](int level) {
-            int64_t m = 0;
-            for (int g = 0; g < G; ++g) m = std::max(m, P(g, level));
-            return m;
-        };
-        int64_t maxpc = 0;
-        for (int k = 0; k < kConvs; ++k) {
-            gact[k] = take<float>(maxP(kSpecs[k].level) * kSpecs[k].cout);
-            maxpc = std::max(maxpc, maxP(kSpecs[k].level) * std::max(kSpecs[k].cout, kSpecs[k].cin));
+        // gradients, per group
+        for (int g = 0; g < G; ++g) {
+            int64_t maxpc = 0;
+            for (int k = 0; k < kConvs; ++k) {
+                gact[g][k] = take<float>(P(g, kSpecs[k].level) * kSpecs[k].cout);
+                maxpc = std::max(maxpc, P(g, kSpecs[k].level) * kSpecs[k].cout);
+            }
+            for (int l = 0; l < 3; ++l) {
+                gcat[g][l] = take<float>(P(g, 2 - l) * kSpecs[D2A + 2 * l].cin);
+                gpool[g][l] = take<float>(P(g, l + 1) * kCh[l]);
+            }
+            dpre[g] = take<bf16_t>(maxpc + 256);   // + a zero row of up to 256 channels
         }
-        for (int l = 0; l < 3; ++l) {
-            gcat[l] = take<float>(maxP(2 - l) * kSpecs[D2A + 2 * l].cin);
-            gpool[l] = take<float>(maxP(l + 1) * kCh[l]);
-        }
-        dpre = take<bf16_t>(maxpc + 256);   // + a zero row of up to 256 channels
         for (int k = 0; k < kConvs; ++k) {
             // chunks sized so that a convolution's launches add up to about kWBlocks workgroups
             const int64_t tiles = int64_t(kSpecs[k].cout / 32) * (kSpecs[k].cin / 32);
@@ -905,63 +920,86 @@ struct fewha_unet {
         }
     }
 
-    // gradient of conv k's output is in gact[k]: weight/bias partials, and (unless k == E0A)
-    // the gradient of its input into gin (FP32)
-    void conv_back(int k, int g, int wc0, float* gin, hipStream_t s) {
+    // gradient of conv k's output is in gact[g][k] for every group: ReLU' per group, then the
+    // weight/bias partials and (unless k == E0A) the input gradient into gin[g] (FP32), each
+    // one launch over all groups
+    void conv_back(int k, float* const* gin, hipStream_t s) {
         const ConvSpec& c = kSpecs[k];
-        const int H = size[g] >> c.level;
-        const int64_t Pn = P(g, c.level);
-        k_relu_grad<<<blocks((Pn + 1) * c.cout), kT, 0, s>>>(gact[k], act[g][k], Pn * c.cout, c.cout, dpre);
-        const dim3 wg(blocks(Pn, chunk_px[k]), (c.cout / 32) * (c.cin / 32));
+        WgradGroups wg{};
+        ConvGroups cg{};
+        wg.count = cg.count = G;
+        int nb = 0;
+        for (int g = 0; g < G; ++g) {
+            const int H = size[g] >> c.level;
+            const int64_t Pn = P(g, c.level);
+            k_relu_grad<<<blocks((Pn + 1) * c.cout), kT, 0, s>>>(gact[g][k], act[g][k], Pn * c.cout, c.cout, dpre[g]);
+            wg.g[g] = WgradGroup{dpre[g], conv_in0(k, g), conv_in1(k, g), images[g], H, nb};
+            nb += int(blocks(Pn, chunk_px[k]));
+            if (gin) cg.g[g] = ConvGroup{dpre[g], nullptr, gin[g], images[g], H, 0};
+        }
+        wg.g[G].block0 = nb;
+        const dim3 grid(nb, (c.cout / 32) * (c.cin / 32));
         if (c.concat)
-            k_conv_wgrad<CONV_CONCAT_UP><<<wg, kT, 0, s>>>(dpre, conv_in0(k, g), conv_in1(k, g), concat_c1(k), c.cin,
-                                                         images[g], H, H, c.cout, chunk_px[k], wpart[k], wc0);
+            k_conv_wgrad<CONV_CONCAT_UP><<<grid, kT, 0, s>>>(wg, concat_c1(k), c.cin, c.cout, chunk_px[k], wpart[k]);
         else
-            k_conv_wgrad<CONV_DIRECT><<<wg, kT, 0, s>>>(dpre, conv_in0(k, g), nullptr, 0, c.cin, images[g], H, H,
-                                                       c.cout, chunk_px[k], wpart[k], wc0);
-        if (gin) conv<CONV_DIRECT, false>(one_group(dpre, nullptr, gin, images[g], H), 0, c.cout, wd[k], nullptr, 0, c.cin, s);
+            k_conv_wgrad<CONV_DIRECT><<<grid, kT, 0, s>>>(wg, 0, c.cin, c.cout, chunk_px[k], wpart[k]);
+        if (gin) conv<CONV_DIRECT, false>(cg, 0, c.cout, wd[k], nullptr, 0, c.cin, s);
     }
 
-    void backward_group(int g, const float* target, double total, int* wc, int hb0, hipStream_t s) {
-        const int64_t P0 = P(g, 0);
-        k_head_back<<<blocks(P0), kT, 0, s>>>(out[g], target, act[g][D0B], master + hw_off, P0, total, gact[D0B],
-                                              hpart, hb0);
-        auto chunks = [&](int k, int per) { return int((P(g, kSpecs[k].level) + per - 1) / per); };
-        auto back = [&](int k, float* gin) {
-            conv_back(k, g, wc[k], gin, s);
-            wc[k] += chunks(k, chunk_px[k]);
+    void backward_all(const float* target, double total, hipStream_t s) {
+        int64_t o = 0;
+        int hb = 0;
+        for (int g = 0; g < G; ++g) {
+            const int64_t P0 = P(g, 0);
+            k_head_back<<<blocks(P0), kT, 0, s>>>(out[g], target + o, act[g][D0B], master + hw_off, P0, total,
+                                                  gact[g][D0B], hpart, hb);
+            o += P0;
+            hb += int(blocks(P0));
+        }
+        float* gin[FEWHA_UNET_MAX_GROUPS];
+        auto back = [&](int k, auto target_of) {
+            for (int g = 0; g < G; ++g) gin[g] = target_of(g);
+            conv_back(k, target_of(0) ? gin : nullptr, s);
         };
-        auto split = [&](int lvl_out, float* gc, float* glow, float* gskip, int c1, int c2) {
-            const int H = size[g] >> lvl_out;
-            const int64_t n = P(g, lvl_out + 1) * c1 + P(g, lvl_out) * c2;
-            k_split_concat_grad<<<blocks(n), kT, 0, s>>>(gc, images[g], H, H, c1, c2, glow, gskip);
+        auto split = [&](int lvl_out, int l, int klow, int kskip, int c1, int c2) {
+            for (int g = 0; g < G; ++g) {
+                const int H = size[g] >> lvl_out;
+                const int64_t n = P(g, lvl_out + 1) * c1 + P(g, lvl_out) * c2;
+                k_split_concat_grad<<<blocks(n), kT, 0, s>>>(gcat[g][l], images[g], H, H, c1, c2, gact[g][klow],
+                                                             gact[g][kskip]);
+            }
         };
-        auto pool_add = [&](int lvl, const float* gl, float* gf, int C) {
-            const int H = size[g] >> lvl;
-            k_pool2_grad_add<<<blocks(P(g, lvl) * C), kT, 0, s>>>(gl, images[g], H, H, C, gf);
+        auto pool_add = [&](int lvl, int kf, int C) {
+            for (int g = 0; g < G; ++g) {
+                const int H = size[g] >> lvl;
+                k_pool2_grad_add<<<blocks(P(g, lvl) * C), kT, 0, s>>>(gpool[g][lvl], images[g], H, H, C, gact[g][kf]);
+            }
         };
+        auto ga = [&](int k) { return [this, k](int g) { return gact[g][k]; }; };
+        auto gc = [&](int l) { return [this, l](int g) { return gcat[g][l]; }; };
+        auto gp = [&](int l) { return [this, l](int g) { return gpool[g][l]; }; };
         // decoder
-        back(D0B, gact[D0A]);
-        back(D0A, gcat[2]);
-        split(0, gcat[2], gact[D1B], gact[E0B], kCh[1], kCh[0]);
-        back(D1B, gact[D1A]);
-        back(D1A, gcat[1]);
-        split(1, gcat[1], gact[D2B], gact[E1B], kCh[2], kCh[1]);
-        back(D2B, gact[D2A]);
-        back(D2A, gcat[0]);
-        split(2, gcat[0], gact[E3B], gact[E2B], kCh[3], kCh[2]);
+        back(D0B, ga(D0A));
+        back(D0A, gc(2));
+        split(0, 2, D1B, E0B, kCh[1], kCh[0]);
+        back(D1B, ga(D1A));
+        back(D1A, gc(1));
+        split(1, 1, D2B, E1B, kCh[2], kCh[1]);
+        back(D2B, ga(D2A));
+        back(D2A, gc(0));
+        split(2, 0, E3B, E2B, kCh[3], kCh[2]);
         // encoder
-        back(E3B, gact[E3A]);
-        back(E3A, gpool[2]);
-        pool_add(2, gpool[2], gact[E2B], kCh[2]);
-        back(E2B, gact[E2A]);
-        back(E2A, gpool[1]);
-        pool_add(1, gpool[1], gact[E1B], kCh[1]);
-        back(E1B, gact[E1A]);
-        back(E1A, gpool[0]);
-        pool_add(0, gpool[0], gact[E0B], kCh[0]);
-        back(E0B, gact[E0A]);
-        back(E0A, nullptr);
+        back(E3B, ga(E3A));
+        back(E3A, gp(2));
+        pool_add(2, E2B, kCh[2]);
+        back(E2B, ga(E2A));
+        back(E2A, gp(1));
+        pool_add(1, E1B, kCh[1]);
+        back(E1B, ga(E1A));
+        back(E1A, gp(0));
+        pool_add(0, E0B, kCh[0]);
+        back(E0B, ga(E0A));
+        back(E0A, [](int) { return static_cast<float*>(nullptr); });
     }
 };
 
@@ -1128,16 +1166,9 @@ fewha_status fewha_unet_backward(fewha_unet* net, const float* d_in, const float
                                  void* stream) {
     if (!net || !d_in || !d_target) return ufail(net, FEWHA_E_INVAL, "NULL argument");
     hipStream_t s = as_stream(stream);
-    int wc[kConvs] = {};
-    int hb = 0;
-    int64_t o = 0;
     const double total = double(net->nodes);
     net->forward_all(d_in, s);
-    for (int g = 0; g < net->G; ++g) {
-        net->backward_group(g, d_target + o, total, wc, hb, s);
-        hb += int(blocks(net->P(g, 0)));
-        o += net->P(g, 0);
-    }
+    net->backward_all(d_target, total, s);
     // fixed-order reduction of every partial into the gradient vector (conv weights and bias
     // rows, then the head row [loss sum, gw[32], gb]), one launch
     ReduceTable tb{};
