@@ -327,6 +327,14 @@ class OracleSystem:
 # ----------------------------------------------------------------------------------------
 
 
+def _ratio(num, den):
+    """num / den for the step lengths and projection coefficients of Alg. 1 and 2.  With M
+    symmetric positive definite a denominator (p, M p) or (r, J^-1 r) vanishes only for a zero
+    vector, after the residual has become exactly zero (an all-zero right-hand side): the
+    step along, or the coefficient of, a zero direction is then taken as zero."""
+    return num / den if den > 0 else 0.0
+
+
 def pcg(apply_M, b, c0, Jinv, max_iter, r0=None, callback=None):
     """Alg. 1 (PCG, split Jacobi preconditioner J^-1), exactly ``max_iter`` applies of M.
     Returns c, r and the list of (p_k, q_k, (p_k, q_k))."""
@@ -339,7 +347,7 @@ def pcg(apply_M, b, c0, Jinv, max_iter, r0=None, callback=None):
     for k in range(max_iter):
         q = apply_M(p)
         pq = p @ q
-        alpha = rz / pq
+        alpha = _ratio(rz, pq)
         c = c + alpha * p
         r = r - alpha * q
         dirs.append((p, q, pq))
@@ -347,7 +355,7 @@ def pcg(apply_M, b, c0, Jinv, max_iter, r0=None, callback=None):
             callback(c, r)
         z = Jinv * r
         rz_new = r @ z
-        beta = rz_new / rz
+        beta = _ratio(rz_new, rz)
         p = z + beta * p
         rz = rz_new
     return c, r, dirs
@@ -396,7 +404,7 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
     if m:
         if mode == "paper":
             for j in range(m):
-                sigma = (r @ U[j]) / gam[j]
+                sigma = _ratio(r @ U[j], gam[j])
                 c = c + sigma * U[j]
                 r = r - sigma * Q[j]
         else:
@@ -415,7 +423,7 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
     if m:
         if mode == "paper":
             for j in range(m):
-                z = z - (z @ Q[j]) / gam[j] * U[j]
+                z = z - _ratio(z @ Q[j], gam[j]) * U[j]
         else:
             y = _chol_solve(R, keep, np.array([qq @ z for qq in Q]))
             for j in range(m):
@@ -427,7 +435,7 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
     for k in range(max_iter):
         q = apply_M(p)
         pq = p @ q
-        alpha = rz / pq
+        alpha = _ratio(rz, pq)
         c = c + alpha * p
         r = r - alpha * q
         new.append((p, q, pq))
@@ -443,14 +451,14 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
                 for j in range(m):
                     z = z - y[j] * U[j]
             else:
-                mu = (z @ Q[-1]) / gam[-1]
+                mu = _ratio(z @ Q[-1], gam[-1])
                 z = z - mu * U[-1]
         rz_new = r @ z
-        beta = rz_new / rz
+        beta = _ratio(rz_new, rz)
         p = z + beta * p
         rz = rz_new
     info = {"iters": it, "recycle_used": m, "dropped": dropped,
-            "rel_res": float(np.sqrt(r @ r) / b_norm) if b_norm else float("nan")}
+            "rel_res": float("nan") if b_norm is None else float(np.sqrt(r @ r) / b_norm) if b_norm > 0 else 0.0}
     return c, r, new, info
 
 

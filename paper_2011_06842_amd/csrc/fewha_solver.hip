@@ -181,7 +181,10 @@ __device__ double wave_forward_sub(const double* Mx, int ldr, int ldc, const dou
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         if (j < m) {
-            const double xj = __shfl(v, j, 64) / diag[j];
+            // a recycled direction with (p, q) = 0 is the zero vector (stored by a frame whose
+            // residual was exactly zero): its coefficient is zero
+            const double vj = __shfl(v, j, 64);
+            const double xj = diag[j] > 0 ? vj / diag[j] : 0.0;
             const double lkj = (k > j && k < m) ? Mx[k * ldr + j * ldc] : 0.0;
             if (k == j) v = xj;
             else if (k > j) v -= xj * lkj;
@@ -592,7 +595,8 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
                 const double yk = wave_chol_solve<MP1>(R, keep, mp, vk);
                 if (k < mp) y3[k] = yk;
             } else if (k == 0) {
-                y3[0] = v[1] / sc->gam[pl.s[0]];
+                const double g = sc->gam[pl.s[0]];
+                y3[0] = g > 0 ? v[1] / g : 0.0;
             }
         }
     }
@@ -603,7 +607,7 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
         for (int a = 0; a < MP; ++a)
             if (a < mp) rzn -= y3[a] * v[1 + MP + a];
         const double rz_old = sc->rzb[it & 1];
-        double beta = rz_old != 0 ? rzn / rz_old : 0.0;
+        double beta = rz_old > 0 ? rzn / rz_old : 0.0;
         const bool broken = sc->flags != 0 || !isfinite(beta);
         if (broken) {
             beta = 0;

@@ -128,6 +128,32 @@ def test_frame_sequence_fp64(name, mode, project_all):
         assert abs(gi["rel_res"] - ri["rel_res"]) <= 1e-9 * ri["rel_res"]
 
 
+@pytest.mark.parametrize("mode, project_all", [("galerkin", False), ("paper", False), ("galerkin", True)])
+def test_zero_frame_then_frames_fp64(mode, project_all):
+    """An all-zero slope frame (b = 0, exact residual 0) returns c = 0 and reports the zero
+    curvature as a breakdown; the zero directions it stores get zero coefficients, so the
+    following frames are finite and match the oracle."""
+    spec, seq, _ = system("small")
+    spec = spec.copy(recycle_mode=mode, project_all=project_all)
+    sysm = OracleSystem(spec)
+    frames = np.concatenate([np.zeros_like(seq[:1]), seq[:4]])
+    errs, infos = [], []
+    ctx = fw.FewhaContext(spec, device=DEV)
+    ref = AugmentedReconstructor(sysm)
+    info = ctx.new_info()
+    for t in range(frames.shape[0]):
+        c_ref, i_ref = ref.solve(frames[t])
+        c = host(ctx.fewha_solve_aug(dev(frames[t], np.float64), info=info))
+        gi = fw.decode_info(info)
+        if t == 0:
+            np.testing.assert_array_equal(c, 0.0)
+            assert gi["flags"] == 1 and gi["rel_res"] == 0.0 and i_ref["rel_res"] == 0.0
+        else:
+            assert np.all(np.isfinite(c)) and gi["flags"] == 0, (t, gi)
+            errs.append(rel(c, c_ref))
+    assert max(errs) <= 1e-10, errs
+
+
 def test_plain_pcg_k0_fp64():
     spec, seq, sysm = system("small")
     spec = spec.copy(recycle_k=0)

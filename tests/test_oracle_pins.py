@@ -407,3 +407,28 @@ def test_recycling_reduces_error_on_slowly_varying_sequence():
         ca, ia = aug.solve(seq[t])
         cp, ip = plain.solve(seq[t])
     assert ia["rel_res"] < ip["rel_res"]
+
+
+@pytest.mark.parametrize("mode", ["galerkin", "paper"])
+def test_zero_frame_then_frames_match_plain_pcg(mode):
+    """An all-zero slope frame has b = 0: its solution is exactly c = 0 with residual 0, and
+    the directions it stores are zero vectors ((p, M p) = 0).  A zero direction contributes
+    nothing, so the next frame (r = b - 0 + 0 = b) equals Alg. 1 from c = 0: the iterates of
+    SciPy's preconditioned CG."""
+    spec = synth.config_tiny()
+    spec.max_iter, spec.recycle_k = 4, 3
+    sysm = OracleSystem(spec)
+    Md = sysm.dense_M()
+    rec = AugmentedReconstructor(sysm, Jinv=1.0 / np.diag(Md), mode=mode)
+    c0, i0 = rec.solve(np.zeros(sysm.S))
+    np.testing.assert_array_equal(c0, 0.0)
+    assert i0["rel_res"] == 0.0 and all(g == 0.0 for _, _, g in rec.store)
+    s = np.random.default_rng(31).standard_normal(sysm.S)
+    c1, i1 = rec.solve(s)
+    b = sysm.rhs(s)
+    ref = []
+    spla.cg(Md, b, x0=np.zeros_like(b), maxiter=4, rtol=1e-300, atol=0.0,
+            M=spla.LinearOperator(Md.shape, matvec=lambda v: v / np.diag(Md)),
+            callback=lambda xk: ref.append(xk.copy()))
+    assert np.all(np.isfinite(c1)) and i1["recycle_used"] == 3
+    np.testing.assert_allclose(c1, ref[-1], rtol=0, atol=1e-10 * np.abs(ref[-1]).max())
