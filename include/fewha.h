@@ -179,7 +179,7 @@ fewha_status fewha_frame_iterations(const fewha_ctx* ctx, int32_t* iters);
 /* Drop the recycle store: the next solve runs Alg. 1 from r = b - M c with the carried c. */
 fewha_status fewha_reset(fewha_ctx* ctx);
 
-/* Operator pieces, for testing (in/out device, element type of the context):
+/* Operator pieces, for testing (in/out device, 16-byte aligned, element type of the context):
  *   FEWHA_PIECE_WINV  : coefficients (N) -> nodal layers (N), W^-1 = DWT^T / delta_l
  *   FEWHA_PIECE_WINVT : nodal layers (N) -> coefficients (N), W^-T = DWT / delta_l
  *   FEWHA_PIECE_A     : nodal layers (N) -> slopes (S), Gamma_g P_g summed over layers,

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -214,6 +215,8 @@ fewha_status fewha_reset(fewha_ctx* ctx) {
 fewha_status fewha_apply_piece(fewha_ctx* ctx, int32_t piece, const void* d_in, void* d_out, void* stream) {
     if (!ctx || !d_in || !d_out) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
     if (d_in == d_out) return fail(ctx, FEWHA_E_INVAL, "d_out must not alias d_in");
+    if ((reinterpret_cast<uintptr_t>(d_in) | reinterpret_cast<uintptr_t>(d_out)) & 15)
+        return fail(ctx, FEWHA_E_INVAL, "d_in and d_out must be 16-byte aligned");
     const fewha::Ctx& c = ctx->c;
     hipStream_t s = as_stream(stream);
     auto run = [&](auto tag) {

@@ -28,6 +28,17 @@ namespace {
 
 __device__ __forceinline__ int ilog2i(int v) { return 31 - __clz(v); }
 
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
 // Workgroup index in an order that gives die x (workgroups x, x + kXcds, ...) a contiguous
 // share of the tiles, so that the halos neighbouring tiles share are fetched into one L2.
 __device__ __forceinline__ int die_ordered_block() {
@@ -147,31 +158,37 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
         },
         [&](int e, T v) { R[e / (2 * H)][e % (2 * H)] = v; });
     __syncthreads();
-    for (int e = threadIdx.x; e < kST * 2 * H; e += kThreads) {
-        const int yy = e / (2 * H), cc = e - yy * (2 * H), par = yy & 1;
-        T acc = 0;
+    // row pass: output rows 2m and 2m + 1 read the same three coefficient rows of each band
+    for (int e = threadIdx.x; e < (kST / 2) * 2 * H; e += kThreads) {
+        const int m = e / (2 * H), cc = e - m * (2 * H);
+        T ev = 0, od = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const int kr = ((yy - par) >> 1) - k + 2;
-            acc += (par ? tp.ho[k] : tp.he[k]) * R[kr][cc] + (par ? tp.go[k] : tp.ge[k]) * R[H + kr][cc];
+            const T a = R[m - k + 2][cc], b = R[H + m - k + 2][cc];
+            ev += tp.he[k] * a + tp.ge[k] * b;
+            od += tp.ho[k] * a + tp.go[k] * b;
         }
-        I[yy][cc] = acc;
+        I[2 * m][cc] = ev;
+        I[2 * m + 1][cc] = od;
     }
     __syncthreads();
+    // column pass: the pair of outputs (2m, 2m + 1) of a row, stored together
     const T s = T(d.inv_delta);
-    for (int e = threadIdx.x; e < kST * kST; e += kThreads) {
-        const int yy = e / kST, xx = e - yy * kST, par = xx & 1;
-        T acc = 0;
+    for (int e = threadIdx.x; e < kST * (kST / 2); e += kThreads) {
+        const int yy = e / (kST / 2), m = e - yy * (kST / 2);
+        T ev = 0, od = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const int kc = ((xx - par) >> 1) - k + 2;
-            acc += (par ? tp.ho[k] : tp.he[k]) * I[yy][kc] + (par ? tp.go[k] : tp.ge[k]) * I[yy][H + kc];
+            const T a = I[yy][m - k + 2], b = I[yy][H + m - k + 2];
+            ev += tp.he[k] * a + tp.ge[k] * b;
+            od += tp.ho[k] * a + tp.go[k] * b;
         }
-        const size_t o = size_t(d.off) + size_t(y0 + yy) * n + x0 + xx;
+        const size_t o = size_t(d.off) + size_t(y0 + yy) * n + x0 + 2 * m;   // even: 2-element aligned
+        using V2 = typename Vec2<T>::type;
         if (lev == 1)
-            phi[o] = acc * s;
+            *reinterpret_cast<V2*>(phi + o) = V2{ev * s, od * s};
         else
-            ll_out[o] = acc;
+            *reinterpret_cast<V2*>(ll_out + o) = V2{ev, od};
     }
 }
 
@@ -221,14 +238,18 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
         W * W, [&](int e) { return src[((2 * ky0 + e / W) & (nbs - 1)) * n + ((2 * kx0 + e % W) & (nbs - 1))]; },
         [&](int e, T v) { R[e / W][e % W] = v; });
     __syncthreads();
-    for (int e = threadIdx.x; e < W * 2 * kAT; e += kThreads) {
-        const int rr = e / (2 * kAT), kk = e - rr * (2 * kAT);
-        const int k = kk & (kAT - 1);
-        const bool hi = kk >= kAT;
-        T acc = 0;
+    // row pass: the low- and high-pass outputs of one (row, k) from the same six inputs
+    for (int e = threadIdx.x; e < W * kAT; e += kThreads) {
+        const int rr = e / kAT, k = e & (kAT - 1);
+        T lo = 0, hi = 0;
 #pragma unroll
-        for (int t = 0; t < 6; ++t) acc += (hi ? tp.g[t] : tp.h[t]) * R[rr][2 * k + t];
-        I[rr][kk] = acc;
+        for (int t = 0; t < 6; ++t) {
+            const T x = R[rr][2 * k + t];
+            lo += tp.h[t] * x;
+            hi += tp.g[t] * x;
+        }
+        I[rr][k] = lo;
+        I[rr][kAT + k] = hi;
     }
     __syncthreads();
     T ll = 0, yh = 0, xh = 0, hh = 0;
