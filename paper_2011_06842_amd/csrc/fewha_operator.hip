@@ -91,28 +91,36 @@ __global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* 
         nb0 * nb0, [&](int e) { return C[(e >> lg0) * n + (e & (nb0 - 1))]; },
         [&](int e, T v) { A[(e >> lg0) * CB + (e & (nb0 - 1))] = v; });
     __syncthreads();
+    // outputs 2i and 2i + 1 of a line read the same three coefficients of each band, so
+    // every pass computes the pair from one read
     for (int lev = levels; lev >= lc; --lev) {
-        const int nb = n >> (lev - 1), m = nb >> 1, lg = ilog2i(nb);
-        for (int e = threadIdx.x; e < nb * nb; e += kCoarseThreads) {
-            const int y = e >> lg, x = e & (nb - 1), par = y & 1;
-            T acc = 0;
+        const int nb = n >> (lev - 1), m = nb >> 1, lg = ilog2i(nb), lgm = lg - 1;
+        for (int e = threadIdx.x; e < m * nb; e += kCoarseThreads) {   // rows 2i, 2i + 1
+            const int i = e >> lg, x = e & (nb - 1);
+            T ev = 0, od = 0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const int ky = (((y - par) >> 1) - k) & (m - 1);
-                acc += (par ? tp.ho[k] : tp.he[k]) * A[ky * CB + x] + (par ? tp.go[k] : tp.ge[k]) * A[(m + ky) * CB + x];
+                const int ky = (i - k) & (m - 1);
+                const T a = A[ky * CB + x], b = A[(m + ky) * CB + x];
+                ev += tp.he[k] * a + tp.ge[k] * b;
+                od += tp.ho[k] * a + tp.go[k] * b;
             }
-            B[y * CB + x] = acc;
+            B[(2 * i) * CB + x] = ev;
+            B[(2 * i + 1) * CB + x] = od;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < nb * nb; e += kCoarseThreads) {
-            const int y = e >> lg, x = e & (nb - 1), par = x & 1;
-            T acc = 0;
+        for (int e = threadIdx.x; e < nb * m; e += kCoarseThreads) {   // columns 2i, 2i + 1
+            const int y = e >> lgm, i = e & (m - 1);
+            T ev = 0, od = 0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const int kx = (((x - par) >> 1) - k) & (m - 1);
-                acc += (par ? tp.ho[k] : tp.he[k]) * B[y * CB + kx] + (par ? tp.go[k] : tp.ge[k]) * B[y * CB + m + kx];
+                const int kx = (i - k) & (m - 1);
+                const T a = B[y * CB + kx], b = B[y * CB + m + kx];
+                ev += tp.he[k] * a + tp.ge[k] * b;
+                od += tp.ho[k] * a + tp.go[k] * b;
             }
-            A[y * CB + x] = acc;
+            A[y * CB + 2 * i] = ev;
+            A[y * CB + 2 * i + 1] = od;
         }
         __syncthreads();
     }

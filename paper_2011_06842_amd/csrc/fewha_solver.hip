@@ -96,9 +96,18 @@ __device__ void chol_solve(const double* R, const int32_t* keep, int m, const do
     }
 }
 
-// Small dense algebra of the recycle space on one wavefront (m <= MB <= 64): lane k owns
-// column k (and row k) of the factor in registers, pivots and solution entries travel by
-// shuffles, so no step waits on a chain of dependent memory reads.
+// Small dense algebra of the recycle space on one wavefront (m <= MB <= 64, all 64 lanes
+// active): lane k owns column k (and row k) of the factor in registers; pivots and solution
+// entries are broadcast by reading one lane's register into scalar registers, so no step
+// waits on a chain of memory or LDS round trips.
+
+// The value v holds in lane `lane` (wave-uniform), in every lane.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffull), lane));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
 
 // G = R^T R (R upper) of the symmetric matrix whose upper triangle is X[a * ld + b] (a <= b),
 // columns in order, column j dropped (row j of R zero, keep[j] = 0) when its pivot is
@@ -123,8 +132,8 @@ __device__ int wave_cholesky(const double* X, int ld, int m, double* Rout, int32
             double s = 0;
 #pragma unroll
             for (int i = 0; i < MB; ++i)
-                if (i < j) s += __shfl(c[i], j, 64) * c[i];
-            const double d = __shfl(g[j] - s, j, 64);
+                if (i < j) s += lane_value(c[i], j) * c[i];
+            const double d = lane_value(g[j] - s, j);
             const bool kj = d > thr;
             const double rjj = kj ? sqrt(d) : 0.0;
             c[j] = !kj ? 0.0 : (k == j ? rjj : (k > j ? (g[j] - s) / rjj : 0.0));
@@ -153,8 +162,8 @@ __device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, d
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         if (j < m) {
-            const double rjj = __shfl(col[j], j, 64);
-            const double tj = keep[j] ? __shfl(v, j, 64) / rjj : 0.0;
+            const double rjj = lane_value(col[j], j);
+            const double tj = keep[j] ? lane_value(v, j) / rjj : 0.0;
             if (k == j) v = tj;
             else if (k > j) v -= col[j] * tj;
         }
@@ -163,8 +172,8 @@ __device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, d
 #pragma unroll
     for (int j = MB - 1; j >= 0; --j) {
         if (j < m) {
-            const double rjj = __shfl(col[j], j, 64);
-            const double yj = keep[j] ? __shfl(v, j, 64) / rjj : 0.0;
+            const double rjj = lane_value(col[j], j);
+            const double yj = keep[j] ? lane_value(v, j) / rjj : 0.0;
             if (k == j) v = yj;
             else if (k < j) v -= row[j] * yj;
         }
@@ -183,7 +192,7 @@ __device__ double wave_forward_sub(const double* Mx, int ldr, int ldc, const dou
         if (j < m) {
             // a recycled direction with (p, q) = 0 is the zero vector (stored by a frame whose
             // residual was exactly zero): its coefficient is zero
-            const double vj = __shfl(v, j, 64);
+            const double vj = lane_value(v, j);
             const double xj = diag[j] > 0 ? vj / diag[j] : 0.0;
             const double lkj = (k > j && k < m) ? Mx[k * ldr + j * ldc] : 0.0;
             if (k == j) v = xj;
