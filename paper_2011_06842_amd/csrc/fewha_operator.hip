@@ -418,12 +418,15 @@ __global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs
     __shared__ int32_t srow[FEWHA_MAX_LAYERS][E], scol[FEWHA_MAX_LAYERS][E];
     __shared__ T sfy[FEWHA_MAX_LAYERS][E], sfx[FEWHA_MAX_LAYERS][E];
     __shared__ int32_t sn[FEWHA_MAX_LAYERS];
-    __shared__ int64_t soffl[FEWHA_MAX_LAYERS];
+    __shared__ uint32_t soffl[FEWHA_MAX_LAYERS];
     const int2 st = tiles[blockIdx.x];
     if (st.x < 0) return;                                        // padding of the die-ordered grid
     const WfsDev W = wfs[st.x];
     const int ns = W.ns, np = ns + 1;
     const int L = W.nl;
+    // the instance's layers follow its first one, at most FEWHA_MAX_LAYERS x 1024^2 values:
+    // byte offsets from it fit in 32 bits
+    const char* __restrict__ phib = reinterpret_cast<const char*>(phi + lays[W.l0].off);
     const int tl = st.y;
     const int i0 = (tl / W.tiles_x) * kTile, j0 = (tl % W.tiles_x) * kTile;
     // slope weights of this thread's subapertures, requested before anything waits
@@ -442,12 +445,14 @@ __global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs
     // the layers of the sensor's instance and the bilinear cells of the tile's rows and
     // columns on each: every load is issued before the first LDS store
     constexpr int PER = (FEWHA_MAX_LAYERS * 2 * E + NT - 1) / NT;
+    const int nent = L * 2 * E;                                  // table entries of the tile
     int32_t ci[PER];
     T fr[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
+        if (k * NT >= nent) break;                               // uniform: only the L layers
         const int e = threadIdx.x + k * NT;
-        if (e < L * 2 * E) {
+        if (e < nent) {
             const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
             const int node = (col ? j0 : i0) - 1 + kk;
             const int nn = node < 0 ? 0 : (node > ns ? ns : node);   // clamped: halo nodes outside are unused
@@ -457,16 +462,17 @@ __global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs
         }
     }
     int32_t ln = 0;
-    int64_t loff = 0;
+    uint32_t loff = 0;
     if (threadIdx.x < L) {
         const LayerDev d = lays[W.l0 + threadIdx.x];
         ln = d.n;
-        loff = d.off;
+        loff = uint32_t(d.off - lays[W.l0].off) * uint32_t(sizeof(T));
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
+        if (k * NT >= nent) break;
         const int e = threadIdx.x + k * NT;
-        if (e < L * 2 * E) {
+        if (e < nent) {
             const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
             if (col) {
                 scol[l][kk] = ci[k];
@@ -490,11 +496,18 @@ __global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs
         if (i >= 0 && i <= ns && j >= 0 && j <= ns) {
 #pragma unroll 4
             for (int l = lg; l < L; l += kLayerGroups) {
-                const int n = sn[l];
+                const uint32_t n = uint32_t(sn[l]);
                 const T fy = sfy[l][li], fx = sfx[l][lj];
-                const T* ph = phi + soffl[l] + size_t(srow[l][li]) * n + scol[l][lj];
-                const T p00 = ph[0], p01 = ph[1], p10 = ph[n], p11 = ph[n + 1];
-                v += (T(1) - fy) * ((T(1) - fx) * p00 + fx * p01) + fy * ((T(1) - fx) * p10 + fx * p11);
+                const uint32_t o0 = soffl[l] + (uint32_t(srow[l][li]) * n + uint32_t(scol[l][lj])) * uint32_t(sizeof(T));
+                const uint32_t o1 = o0 + n * uint32_t(sizeof(T));
+                const T p00 = *reinterpret_cast<const T*>(phib + o0);
+                const T p01 = *reinterpret_cast<const T*>(phib + o0 + sizeof(T));
+                const T p10 = *reinterpret_cast<const T*>(phib + o1);
+                const T p11 = *reinterpret_cast<const T*>(phib + o1 + sizeof(T));
+                // explicit fused multiply-adds: the same roundings in every launch shape
+                const T r0 = fma(fx, p01, (T(1) - fx) * p00);
+                const T r1 = fma(fx, p11, (T(1) - fx) * p10);
+                v = fma(fy, r1, fma(T(1) - fy, r0, v));
             }
         }
         spart[lg][node] = v;
