@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 
 METRIC = "augmented-PCG frame latency p50/p99 (ms) + operator applies/s, % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# vector-instruction issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes wide); in wave-instructions per second
+VALU_PEAK_INST_S = 256 * 4 * 2.4e9 / 4
 SEED = 20201112
 
 
@@ -106,8 +109,14 @@ def source_sha256():
 
 def pmc_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` in `workload` ("single" or "batched") from the
-    committed counter summaries (profiles/*_pmc.md, blocks of "- key: value" lines starting at
-    "- kernel:"), or None when none matches or the sources changed since."""
+    committed counter summaries, or None."""
+    return pmc_value(kernel, workload, "traffic_bytes_per_launch")
+
+
+def pmc_value(kernel, workload, key):
+    """Value `key` of `kernel` in `workload` ("single" or "batched") from the committed counter
+    summaries (profiles/*_pmc.md, blocks of "- key: value" lines starting at "- kernel:"), or
+    None when none matches or the sources changed since."""
     import glob
     sha = source_sha256()
     for path in sorted(glob.glob(os.path.join(PROFILES, "*_pmc.md"))):
@@ -124,10 +133,11 @@ def pmc_traffic(kernel, workload):
                 if cur is not None:
                     cur[k] = v
         for blk in blocks:
-            if blk.get("kernel") == kernel and blk.get("workload") == workload and blk.get("source_sha256") == sha:
+            if (blk.get("kernel") == kernel and blk.get("workload") == workload and blk.get("source_sha256") == sha
+                    and key in blk):
                 try:
-                    return float(blk["traffic_bytes_per_launch"])
-                except (KeyError, ValueError):
+                    return float(blk[key])
+                except ValueError:
                     return None
     return None
 
@@ -250,8 +260,26 @@ def run_batch(args, dev):
         ms_f = ms / P
         kern[name] = {"ms_per_frame": round(ms_f, 4), "launches_per_frame": nl / P,
                       "GB_s": round(b / (ms_f * 1e-3) / 1e9, 1) if b else None}
+        # vector-instruction issue rate: counted instructions per launch (committed counter
+        # summary) over the duration measured here
+        vi = pmc_value(name, "batched", "valu_insts_per_launch")
+        if vi:
+            rate = vi * (nl / P) / (ms_f * 1e-3)
+            kern[name]["valu_Ginst_s"] = round(rate / 1e9, 1)
+            kern[name]["valu_frac"] = round(rate / VALU_PEAK_INST_S, 4)
     dom = max((k for k in kern if kern[k]["GB_s"]), key=lambda k: kern[k]["ms_per_frame"])
     ach = kern[dom]["GB_s"]
+    # the dominant operator kernel against the roofline that bounds it (HBM or vector issue)
+    opk = max((k for k in kern if k in OP_KERNELS), key=lambda k: kern[k]["ms_per_frame"])
+    ko = kern[opk]
+    hbm_frac = ko["GB_s"] / HBM_PEAK_GBS if ko["GB_s"] else 0.0
+    if ko.get("valu_frac") is not None and ko["valu_frac"] > hbm_frac:
+        op_roof = {"bound": "valu", "kernel": opk, "achieved": ko["valu_Ginst_s"],
+                   "peak": round(VALU_PEAK_INST_S / 1e9, 1), "unit": "G wave-instructions/s",
+                   "frac": ko["valu_frac"], "hbm_frac": round(hbm_frac, 4)}
+    else:
+        op_roof = {"bound": "hbm", "kernel": opk, "achieved": ko["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(hbm_frac, 4), "valu_frac": ko.get("valu_frac")}
     return {
         "workload": f"elt_mcao_fp32_x{B}_instances",
         "instances": B,
@@ -264,6 +292,7 @@ def run_batch(args, dev):
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom, "batched"),
                      "share_of_frame": round(kern[dom]["ms_per_frame"] / float(np.median(fm)), 3)},
+        "operator_roofline": op_roof,
         "kernels": dict(sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_frame"])),
         "input": f"{A} seeded atmospheres, instance i reads atmosphere i mod {A} from frame {stride} (i div {A})",
         "input_generation_s": round(t_gen, 1), "setup_and_tuning_s": round(t_setup, 1),
