@@ -12,9 +12,34 @@ __device__ __forceinline__ int pmod(int a, int m) {
     return r < 0 ? r + m : r;
 }
 
+// The value v holds in lane `lane` (wave-uniform), in every lane: a read of that lane's
+// register into scalar registers.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffull), lane));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// v of the lane CTRL's row shift names (DPP row_shr), 0 where the shift leaves the row of 16.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_shr(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), CTRL, 0xf, 0xf, true));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, true));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Sum over the 64 lanes of a full wavefront, in every lane, in a fixed order: inclusive sums
+// within each row of 16 lanes by data-parallel row shifts of 1, 2, 4 and 8 (lane 15 of a row
+// then holds the row's sum), then (row0 + row1) + (row2 + row3).  No LDS traffic.
 __device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
+    v += dpp_row_shr<0x111>(v);
+    v += dpp_row_shr<0x112>(v);
+    v += dpp_row_shr<0x114>(v);
+    v += dpp_row_shr<0x118>(v);
+    return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
 }
 
 // Block (kThreads) reduction of NV register values; thread k < NV writes

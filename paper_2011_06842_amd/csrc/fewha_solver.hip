@@ -101,14 +101,6 @@ __device__ void chol_solve(const double* R, const int32_t* keep, int m, const do
 // entries are broadcast by reading one lane's register into scalar registers, so no step
 // waits on a chain of memory or LDS round trips.
 
-// The value v holds in lane `lane` (wave-uniform), in every lane.
-__device__ __forceinline__ double lane_value(double v, int lane) {
-    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
-    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffull), lane));
-    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane));
-    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
-
 // G = R^T R (R upper) of the symmetric matrix whose upper triangle is X[a * ld + b] (a <= b),
 // columns in order, column j dropped (row j of R zero, keep[j] = 0) when its pivot is
 // <= 1e-14 max diag G.  R is written to Rout[i * m + k] (LDS or global); returns the drop count.
