@@ -773,6 +773,20 @@ __global__ void __launch_bounds__(kThreads) k_check(Scalars* __restrict__ scs, c
     }
 }
 
+// The frame's outputs to the caller in one launch after the graph: the coefficients
+// (c -> c_out, may be null) and, by the first workgroup, the per-instance statistics
+// (info -> info_user, may be null).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_frame_out(int64_t N, const T* __restrict__ c, T* __restrict__ c_out,
+                                                         int B, const fewha_solve_info* __restrict__ info,
+                                                         fewha_solve_info* __restrict__ info_user) {
+    if (c_out)
+        for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
+            c_out[i] = c[i];
+    if (blockIdx.x == 0 && info_user)
+        for (int b = threadIdx.x; b < B; b += kThreads) info_user[b] = info[b];
+}
+
 int bucket(int m) {
     if (m <= 16) return m < 0 ? 0 : m;
     return (m + 3) / 4 * 4;
@@ -1048,8 +1062,12 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
         }
         e = hipMemcpyAsync(s_in, slopes, sizeof(T) * c.S, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipGraphLaunch(it->second, s);
-        if (e == hipSuccess && info_user)
-            e = hipMemcpyAsync(info_user, info, sizeof(fewha_solve_info) * c.B, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && (c_out || info_user)) {
+            const int64_t nb = std::min<int64_t>((c.N + 4 * kThreads - 1) / (4 * kThreads), 4096);
+            k_frame_out<T><<<unsigned(nb), kThreads, 0, s>>>(c.N, c.at<T>(c.lay.c), c_out, c.B, info, info_user);
+            e = hipGetLastError();
+        }
+        return end_frame<T>(c, static_cast<T*>(nullptr), iters, e, s);
     } else {
         enqueue_frame<T>(c, slopes, info_user, s);
     }
