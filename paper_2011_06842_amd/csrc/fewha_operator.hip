@@ -39,6 +39,30 @@ struct Vec2<double> {
     using type = double2;
 };
 
+// 16-byte vector of T and its element-wise store.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+    __device__ static void put(float* d, const float4& v) {
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+    }
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+    __device__ static void put(double* d, const double2& v) {
+        d[0] = v.x;
+        d[1] = v.y;
+    }
+};
+
 // Workgroup index in an order that gives die x (workgroups x, x + kXcds, ...) a contiguous
 // share of the tiles, so that the halos neighbouring tiles share are fetched into one L2.
 __device__ __forceinline__ int die_ordered_block() {
@@ -156,15 +180,31 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
     const T* LL = (lev == d.levels ? coef : ll_in) + d.off;
     const int ky0 = (y0 >> 1) - 2, kx0 = (x0 >> 1) - 2;
     const Taps<T> tp(f);
-    stage_to_lds<kThreads, (4 * H * H + kThreads - 1) / kThreads, T>(
-        4 * H * H,
-        [&](int e) {
-            const int rr = e / (2 * H), cc = e - rr * (2 * H);
+    // staged in pairs: kx0 is even and M a multiple of 2, so the two coefficients of a pair
+    // are adjacent (also across the periodic wrap) and the pair is 2-element aligned
+    {
+        using V2 = typename Vec2<T>::type;
+        constexpr int NP = 2 * H * H, PER = (NP + kThreads - 1) / kThreads;   // pairs (H per row)
+        V2 v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped index)
+            const int e0 = threadIdx.x + k * kThreads, e = e0 < NP ? e0 : NP - 1;
+            const int rr = e / H, cc = 2 * (e - rr * H);
             const int hr = rr >= H, hc = cc >= H;
             const int kr = (ky0 + rr - H * hr) & (M - 1), kc = (kx0 + cc - H * hc) & (M - 1);
-            return (!hr && !hc) ? LL[kr * n + kc] : C[(kr + M * hr) * n + kc + M * hc];
-        },
-        [&](int e, T v) { R[e / (2 * H)][e % (2 * H)] = v; });
+            const T* src = (!hr && !hc) ? LL + kr * n + kc : C + (kr + M * hr) * n + kc + M * hc;
+            v[k] = *reinterpret_cast<const V2*>(src);
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + k * kThreads;
+            if (e < NP) {
+                const int rr = e / H, cc = 2 * (e - rr * H);
+                R[rr][cc] = v[k].x;
+                R[rr][cc + 1] = v[k].y;
+            }
+        }
+    }
     __syncthreads();
     // row pass: output rows 2m and 2m + 1 read the same three coefficient rows of each band
     for (int e = threadIdx.x; e < (kST / 2) * 2 * H; e += kThreads) {
@@ -242,9 +282,28 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
     }
     const T* src = (lev == 1 ? img : ll_in) + d.off;
     const Taps<T> tp(f);
-    stage_to_lds<kThreads, (W * W + kThreads - 1) / kThreads, T>(
-        W * W, [&](int e) { return src[((2 * ky0 + e / W) & (nbs - 1)) * n + ((2 * kx0 + e % W) & (nbs - 1))]; },
-        [&](int e, T v) { R[e / W][e % W] = v; });
+    // staged in 16-byte chunks: 2 kx0 and nbs are multiples of the chunk, so a chunk is
+    // contiguous (also across the periodic wrap) and aligned
+    {
+        using VC = Vec16<T>;
+        constexpr int CPR = W / VC::n, NCH = W * CPR, PER = (NCH + kThreads - 1) / kThreads;
+        typename VC::type v[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped index)
+            const int e0 = threadIdx.x + k * kThreads, e = e0 < NCH ? e0 : NCH - 1;
+            const int r = e / CPR, q = e - r * CPR;
+            v[k] = *reinterpret_cast<const typename VC::type*>(
+                src + ((2 * ky0 + r) & (nbs - 1)) * n + ((2 * kx0 + q * VC::n) & (nbs - 1)));
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + k * kThreads;
+            if (e < NCH) {
+                const int r = e / CPR, q = e - r * CPR;
+                VC::put(&R[r][q * VC::n], v[k]);
+            }
+        }
+    }
     __syncthreads();
     // row pass: the low- and high-pass outputs of one (row, k) from the same six inputs
     for (int e = threadIdx.x; e < W * kAT; e += kThreads) {
