@@ -52,6 +52,7 @@ struct Vec16<float> {
         d[2] = v.z;
         d[3] = v.w;
     }
+    __device__ static void store(float* d, const float* v) { *reinterpret_cast<float4*>(d) = float4{v[0], v[1], v[2], v[3]}; }
 };
 template <>
 struct Vec16<double> {
@@ -61,6 +62,7 @@ struct Vec16<double> {
         d[0] = v.x;
         d[1] = v.y;
     }
+    __device__ static void store(double* d, const double* v) { *reinterpret_cast<double2*>(d) = double2{v[0], v[1]}; }
 };
 
 // Workgroup index in an order that gives die x (workgroups x, x + kXcds, ...) a contiguous
@@ -111,9 +113,28 @@ __global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* 
     const T* C = coef + d.off;
     const Taps<T> tp(f);
     const int nb0 = n >> (lc - 1), lg0 = ilog2i(nb0);
-    stage_to_lds<kCoarseThreads, CB * CB / kCoarseThreads, T>(
-        nb0 * nb0, [&](int e) { return C[(e >> lg0) * n + (e & (nb0 - 1))]; },
-        [&](int e, T v) { A[(e >> lg0) * CB + (e & (nb0 - 1))] = v; });
+    // 16-byte chunks of consecutive positions of a row (nb0 >= 8 is a multiple of the chunk)
+    using VC = Vec16<T>;
+    using V = typename VC::type;
+    constexpr int PERC = CB * CB / (VC::n * kCoarseThreads);
+    const int nch = nb0 * nb0 / VC::n;
+    {
+        V v[PERC];
+#pragma unroll
+        for (int k = 0; k < PERC; ++k) {   // unconditional (clamped) loads
+            const int ch0 = threadIdx.x + k * kCoarseThreads, ch = ch0 < nch ? ch0 : 0;
+            const int e = ch * VC::n;
+            v[k] = *reinterpret_cast<const V*>(C + (e >> lg0) * n + (e & (nb0 - 1)));
+        }
+#pragma unroll
+        for (int k = 0; k < PERC; ++k) {
+            const int ch = threadIdx.x + k * kCoarseThreads;
+            if (ch < nch) {
+                const int e = ch * VC::n;
+                VC::put(&A[(e >> lg0) * CB + (e & (nb0 - 1))], v[k]);
+            }
+        }
+    }
     __syncthreads();
     // outputs 2i and 2i + 1 of a line read the same three coefficients of each band, so
     // every pass computes the pair from one read
@@ -150,9 +171,12 @@ __global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* 
     }
     T* out = (lc == 1 ? phi : ll_out) + d.off;
     const T s = lc == 1 ? T(d.inv_delta) : T(1);
-    for (int e = threadIdx.x; e < nb0 * nb0; e += kCoarseThreads) {
-        const int r = e >> lg0, c = e & (nb0 - 1);
-        out[r * n + c] = A[r * CB + c] * s;
+    for (int ch = threadIdx.x; ch < nch; ch += kCoarseThreads) {
+        const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
+        T val[VC::n];
+#pragma unroll
+        for (int j = 0; j < VC::n; ++j) val[j] = A[r * CB + c + j] * s;
+        VC::store(out + r * n + c, val);
     }
 }
 
@@ -359,32 +383,40 @@ __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* _
                                                                 const T* __restrict__ xprior,
                                                                 double* __restrict__ dotpart) {
     constexpr int CB = CoarseBlock<T>::value;
-    constexpr int PPT = CB * CB / kCoarseThreads;   // positions per thread
     __shared__ T A[CB * CB];
     __shared__ T B[CB * CB];
     const LayerDev d = lays[blockIdx.x];
     const int n = d.n, lc = d.coarse_lev, levels = d.levels;
     double dot = 0;
     if (levels >= lc) {
-        const int nb0 = n >> (lc - 1);
-        T pa[PPT], xp[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {   // unconditional (clamped) loads
-            const int e = threadIdx.x + k * kCoarseThreads;
-            const int ec = e < nb0 * nb0 ? e : 0;
-            const size_t o = size_t(d.off) + size_t(ec / nb0) * n + (ec % nb0);
-            pa[k] = xp[k] = 0;
-            if (PRIOR) {
-                pa[k] = prior_a[o];
-                xp[k] = xprior[o];
-            }
-        }
+        // 16-byte chunks of consecutive positions of a row (nb0 >= 8 is a multiple of the
+        // chunk; layer offsets and rows keep chunks aligned)
+        using VC = Vec16<T>;
+        using V = typename VC::type;
+        constexpr int PERC = CB * CB / (VC::n * kCoarseThreads);
+        const int nb0 = n >> (lc - 1), lg0 = ilog2i(nb0), nch = nb0 * nb0 / VC::n;
         const T* src = (lc == 1 ? img : ll_in) + d.off;
         const Taps<T> tp(f);
-        const int lg0 = ilog2i(nb0);
-        stage_to_lds<kCoarseThreads, CB * CB / kCoarseThreads, T>(
-            nb0 * nb0, [&](int e) { return src[(e >> lg0) * n + (e & (nb0 - 1))]; },
-            [&](int e, T v) { A[(e >> lg0) * CB + (e & (nb0 - 1))] = v; });
+        V pa[PERC], xp[PERC], v[PERC];
+#pragma unroll
+        for (int k = 0; k < PERC; ++k) {   // unconditional (clamped) loads
+            const int ch0 = threadIdx.x + k * kCoarseThreads, ch = ch0 < nch ? ch0 : 0;
+            const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
+            v[k] = *reinterpret_cast<const V*>(src + r * n + c);
+            pa[k] = xp[k] = V{};
+            if (PRIOR) {
+                pa[k] = *reinterpret_cast<const V*>(prior_a + size_t(d.off) + r * n + c);
+                xp[k] = *reinterpret_cast<const V*>(xprior + size_t(d.off) + r * n + c);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PERC; ++k) {
+            const int ch = threadIdx.x + k * kCoarseThreads;
+            if (ch < nch) {
+                const int e = ch * VC::n;
+                VC::put(&A[(e >> lg0) * CB + (e & (nb0 - 1))], v[k]);
+            }
+        }
         __syncthreads();
         for (int lev = lc; lev <= levels; ++lev) {
             const int nb = n >> (lev - 1), m = nb >> 1, lgm = ilog2i(m), lg = lgm + 1;
@@ -417,14 +449,20 @@ __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* _
         }
         const T s = T(d.inv_delta);
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int e = threadIdx.x + k * kCoarseThreads;
-            if (e < nb0 * nb0) {
-                const int r = e >> lg0, c = e & (nb0 - 1);
-                T val = A[r * CB + c] * s;
-                if (PRIOR) val += pa[k] * xp[k];
-                out[size_t(d.off) + size_t(r) * n + c] = val;
-                dot += double(val) * double(xp[k]);
+        for (int k = 0; k < PERC; ++k) {
+            const int ch = threadIdx.x + k * kCoarseThreads;
+            if (ch < nch) {
+                const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
+                T val[VC::n], a[VC::n], x[VC::n];
+                VC::put(a, pa[k]);
+                VC::put(x, xp[k]);
+#pragma unroll
+                for (int j = 0; j < VC::n; ++j) {
+                    val[j] = A[r * CB + c + j] * s;
+                    if (PRIOR) val[j] += a[j] * x[j];
+                    dot += double(val[j]) * double(x[j]);
+                }
+                VC::store(out + size_t(d.off) + size_t(r) * n + c, val);
             }
         }
     }
