@@ -152,6 +152,8 @@ int block_elems(const fewha_config* c) { return c->block_elems ? c->block_elems 
 
 int vec_blocks(int64_t n, int be) { return int(std::min<int64_t>(kVecBlocksMax, std::max<int64_t>(1, (n + be - 1) / be))); }
 
+// Gram workgroups of an instance: a function of its size alone, so that an instance of a batch
+// sums its Gram partials exactly as the same instance alone does.
 int gram_blocks(int64_t n) { return int(std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + kGramElems - 1) / kGramElems))); }
 
 // (p, q) partials of one layer: one per tile of every tiled analysis level, then the coarse one
@@ -170,7 +172,7 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
     z.B = nb;
     z.esz = cfgs[0].precision == FEWHA_FP64 ? 8 : 4;
     z.slots = cfgs[0].recycle_k + cfgs[0].max_iter;
-    z.KE = std::max(1, cfgs[0].recycle_k * (cfgs[0].recycle_k + 1));
+    z.KE = std::max(1, 2 * cfgs[0].recycle_k * (cfgs[0].recycle_k + 1));   // X and Y of the Gram pass
     const int cb = coarse_block(cfgs[0].precision);
     for (int i = 0; i < nb; ++i) {
         const fewha_config* c = &cfgs[i];

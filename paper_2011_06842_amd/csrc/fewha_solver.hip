@@ -245,16 +245,22 @@ __device__ __forceinline__ void load4(const double* p, double (&v)[4], double f)
     v[3] = y.y * f;
 }
 
-// Gram pass: X_ab = (U_a, Q_b) (a, b < m) and X_{a,m} = (U_a, r), entry e = a (m+1) + b: a
-// dense m x N by N x (m+1) contraction, on the FP64 matrix cores.  Block (x, y) owns the 16x16
-// tile y of X over its share of the elements; each wavefront feeds v_mfma_f64_16x16x4 with
-// 16 elements per step (lane l: row/column l mod 16, elements 4 (l / 16) .. +3), the four
-// wavefronts' tiles are summed in LDS in a fixed order and written as one partial.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gram(int64_t N, const GramBlk* __restrict__ gt, int m, SlotList sl,
-                                                    const T* __restrict__ U, const T* __restrict__ Q,
-                                                    const T* __restrict__ r, double* __restrict__ gpart) {
-    __shared__ double sh[4][256];
+// Gram pass: X_ab = (U_a, Q_b) (a, b < m) and X_{a,m} = (U_a, r), entry e = a (m+1) + b, and
+// the same products of J^-1 Q_a: Y_ab = (J^-1 Q_a, Q_b), Y_{a,m} = (J^-1 Q_a, r), entry
+// m (m+1) + a (m+1) + b (with them the Galerkin step knows (Q_a, J^-1 r_new) before it runs,
+// so it also forms the initial direction).  Dense m x N by N x (m+1) contractions on the FP64
+// matrix cores.  Block (x, y) owns the 16x16 tiles y of X and Y over its share of the
+// elements; each wavefront feeds v_mfma_f64_16x16x4 with 16 elements per step (lane l:
+// row/column l mod 16, elements 4 (l / 16) .. +3; on a diagonal tile the row vector Q_a of Y
+// is the lane's own column operand), the four wavefronts' tiles are summed in LDS in a fixed
+// order and written as one partial each.
+template <typename T, bool ONE_TILE>
+__global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk* __restrict__ gt, int m, SlotList sl,
+                                                        const T* __restrict__ U, const T* __restrict__ Q,
+                                                        const T* __restrict__ r, const T* __restrict__ jinv,
+                                                        double* __restrict__ gpart) {
+    constexpr int NW = kGramThreads / 64;          // wavefronts per workgroup
+    __shared__ double sh[NW][256];
     GramBlk g;
     if (gt) {
         g = gt[blockIdx.x];
@@ -273,13 +279,15 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, const GramBlk* __r
     // behind a condition would each be waited for before the next)
     const T* pa = U + size_t(sl.s[ar < m ? ar : 0]) * N + g.off;
     const T* pb = (bc < m ? Q + size_t(sl.s[bc]) * N : r) + g.off;
+    const T* pq = Q + size_t(sl.s[ar < m ? ar : 0]) * N + g.off;   // rows of Y off the diagonal
+    const T* pj = jinv + g.off;
     const double ma = ar < m ? 1.0 : 0.0, mb = bc <= m ? 1.0 : 0.0;
-    f64x4 c = {0.0, 0.0, 0.0, 0.0};
-    constexpr int DEPTH = 4;                       // 16-element chunks whose loads are in flight together
-    const int64_t step = int64_t(g.nb) * 4 * 16;
+    f64x4 c = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
+    constexpr int DEPTH = 4;                       // 16-element chunks per step
+    const int64_t step = int64_t(g.nb) * NW * 16;
     const int64_t n = g.n;
-    for (int64_t base = (int64_t(g.local) * 4 + wv) * 16; base < n; base += DEPTH * step) {   // n % 64 == 0
-        double av[DEPTH][4], bv[DEPTH][4];
+    for (int64_t base = (int64_t(g.local) * NW + wv) * 16; base < n; base += DEPTH * step) {   // n % 16 == 0
+        double av[DEPTH][4], bv[DEPTH][4], jq[DEPTH][4];   // jq: J^-1 Q_a, the row operand of Y
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d) {
             const bool in = base + d * step < n;   // uniform over the wavefront
@@ -287,21 +295,48 @@ __global__ void __launch_bounds__(kThreads) k_gram(int64_t N, const GramBlk* __r
             const double f = in ? 1.0 : 0.0;
             load4(pa + e0, av[d], ma * f);
             load4(pb + e0, bv[d], mb * f);
+            load4(pj + e0, jq[d], 1.0);
+            if (ONE_TILE) {   // m < 16: the only tile is diagonal, Q_a is the lane's column operand
+#pragma unroll
+                for (int j = 0; j < 4; ++j) jq[d][j] *= bv[d][j];
+            } else {
+                double qa[4];
+                load4(pq + e0, qa, ma * f);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) jq[d][j] *= qa[j];
+            }
         }
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][j], bv[d][j], c, 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][j], bv[d][j], c, 0, 0, 0);
+                c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(jq[d][j], bv[d][j], c2, 0, 0, 0);
+            }
     }
-    // lane l, register v holds tile entry (row 4 v + l / 16, column l mod 16)
+    // lane l, register v holds tile entry (row 4 v + l / 16, column l mod 16); the NW tiles are
+    // summed by the first 256 threads, one entry each, in a fixed pairwise order
+    const int t = threadIdx.x, row = 16 * ta + (t >> 4), col = 16 * tb + (t & 15);
+    const bool wr = t < 256 && row < m && col <= m;
+    auto tile_sum = [&]() {
+        double v[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v[w] = sh[w][t & 255];
+#pragma unroll
+        for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+            for (int w = 0; w < h; ++w) v[w] = v[w] + v[w + h];
+        return v[0];
+    };
 #pragma unroll
     for (int v = 0; v < 4; ++v) sh[wv][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = c[v];
     __syncthreads();
-    const int t = threadIdx.x, row = 16 * ta + (t >> 4), col = 16 * tb + (t & 15);
-    if (row < m && col <= m) {
-        const double v = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
-        gpart[size_t(g.gbase) + size_t(row * (m + 1) + col) * g.nb + g.local] = v;
-    }
+    if (wr) gpart[size_t(g.gbase) + size_t(row * (m + 1) + col) * g.nb + g.local] = tile_sum();
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sh[wv][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = c2[v];
+    __syncthreads();
+    if (wr) gpart[size_t(g.gbase) + size_t(m * (m + 1) + row * (m + 1) + col) * g.nb + g.local] = tile_sum();
 }
 
 // Reduce the Gram partials and solve for the Galerkin coefficients y (Sec. 4.1).
@@ -314,32 +349,34 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
                                                                Scalars* __restrict__ scs,
                                                                const InstDev* __restrict__ insts, int ke,
                                                                const double* __restrict__ gpart) {
-    __shared__ double X[kKMax * (kKMax + 1)];
+    __shared__ double X[2 * kKMax * (kKMax + 1)];     // X, then Y (see k_gram)
     __shared__ double gm[kKMax];
     const InstDev I = insts[blockIdx.x];               // one workgroup per instance
     Scalars* __restrict__ sc = scs + blockIdx.x;
     const double* __restrict__ gp = gpart + size_t(I.gb0) * ke;
     const int ngb = I.ngb;
-    const int ne = m * (m + 1);
-    {   // 8 lanes per entry, each summing up to kGramBlocks / 8 partials requested all at once
-        // (lane sub takes partials sub, sub + 8, ...: the 8 lanes of an entry read 64
-        // contiguous bytes per load)
-        constexpr int PER = kGramBlocks / 8;
-        const int sub = threadIdx.x & 7;
-        for (int e0 = 0; e0 < ne; e0 += kSolveThreads / 8) {
-            const int e = e0 + (threadIdx.x >> 3);
-            double v[PER];
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped, zeroed by a factor)
-                const int j = k * 8 + sub;
-                const bool ok = e < ne && j < ngb;
-                v[k] = gp[ok ? size_t(e) * ngb + j : 0] * (ok ? 1.0 : 0.0);
-            }
+    const int ne = 2 * m * (m + 1);
+    {   // 4 lanes per entry, 256 entries per pass; each lane sums its partials (sub, sub + 4, ...:
+        // the 4 lanes of an entry read 32 contiguous bytes per load) in chunks of 16 requested
+        // all at once
+        constexpr int LPE = 4, PER = 16;
+        const int sub = threadIdx.x & (LPE - 1);
+        for (int e0 = 0; e0 < ne; e0 += kSolveThreads / LPE) {
+            const int e = e0 + threadIdx.x / LPE;
             double s = 0;
+            for (int j0 = 0; j0 < ngb; j0 += LPE * PER) {
+                double v[PER];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) s += v[k];
+                for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped, zeroed by a factor)
+                    const int j = j0 + k * LPE + sub;
+                    const bool ok = e < ne && j < ngb;
+                    v[k] = gp[ok ? size_t(e) * ngb + j : 0] * (ok ? 1.0 : 0.0);
+                }
 #pragma unroll
-            for (int o = 4; o > 0; o >>= 1) s += __shfl_down(s, o, 8);
+                for (int k = 0; k < PER; ++k) s += v[k];
+            }
+#pragma unroll
+            for (int o = LPE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPE);
             if (sub == 0 && e < ne) X[e] = s;
         }
     }
@@ -348,6 +385,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     if (threadIdx.x >= 64) return;
     const int k = threadIdx.x, W = m + 1;
     const double v = k < m ? X[k * W + m] : 0.0;   // (U_k, r)
+    // the Cholesky factor lives in LDS for both solves below (read back at LDS latency, in
+    // order within the wavefront), then goes to the scalars for the kernels after this one
+    __shared__ double sR[kKMax * kKMax];
+    __shared__ int32_t skeep[kKMax];
     double y;
     if (mode == FEWHA_RECYCLE_PAPER) {
         // (r, p_j) = sigma_j g_j + sum_{i<j} sigma_i (q_i, p_j),  (q_i, p_j) = X[j][i]
@@ -356,10 +397,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
             for (int b = 0; b < m; ++b) sc->R[k * m + b] = X[k * W + b];
         if (k == 0) sc->dropped = 0;
     } else {
-        // the factor goes to LDS first (the solve reads it back at LDS latency, in order
-        // within the wavefront), then to the scalars for the kernels after this one
-        __shared__ double sR[kKMax * kKMax];
-        __shared__ int32_t skeep[kKMax];
         const int dropped = wave_cholesky<MB>(X, W, m, sR, skeep);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         y = wave_chol_solve<MB>(sR, skeep, m, v);
@@ -368,114 +405,77 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
         if (k == 0) sc->dropped = dropped;
     }
     if (k < m) sc->y[k] = y;
+    // Initial direction (condition 1 of Alg. 2): its coefficients solve the same system with
+    // the right-hand side (Q_k, z), z = J^-1 r_new, r_new = r - Q y, that is
+    // w_k = (J^-1 Q_k, r) - sum_b (J^-1 Q_k, Q_b) y_b
+    const double* Y = X + m * W;
+    double w = k < m ? Y[k * W + m] : 0.0;
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+        if (b < m) w -= (k < m ? Y[k * W + b] : 0.0) * lane_value(y, b);
+    double y2;
+    if (mode == FEWHA_RECYCLE_PAPER) {
+        // (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j),  (p_i, q_j) = X[i][j]
+        y2 = wave_forward_sub<MB>(X, 1, W, gm, m, w);
+    } else {
+        y2 = wave_chol_solve<MB>(sR, skeep, m, w);
+    }
+    if (k < m) sc->y2[k] = y2;
 }
 
-// Galerkin step c += U y, r -= Q y; then z = J^-1 r and partials of (Q_a, z).
+// Galerkin step and initial direction in one pass (Sec. 4.1, Alg. 2): c += U y, r -= Q y,
+// z = J^-1 r, p_0 = z - U y_2 with y and y_2 from the Gram solve; partial (r, p_0).
 template <typename T, int MB>
 __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, const VecBlk* __restrict__ vb, int pstride,
                                                               int m, SlotList sl, const T* __restrict__ U,
                                                               const T* __restrict__ Q, const Scalars* __restrict__ scs,
-                                                              T* __restrict__ c, T* __restrict__ r, T* __restrict__ z,
+                                                              T* __restrict__ c, T* __restrict__ r, T* __restrict__ p,
                                                               const T* __restrict__ jinv, double* __restrict__ part) {
     const Seg sg = seg_of(vb, N, 0);
     const Scalars* __restrict__ sc = scs + sg.inst;
     // slots a >= m of the list repeat slot 0 with coefficient 0 (unconditional loads)
-    double y[MB], acc[MB];
+    double y[MB], y2[MB];
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
         y[a] = sc->y[a] * (a < m ? 1.0 : 0.0);
-        acc[a] = 0;
+        y2[a] = sc->y2[a] * (a < m ? 1.0 : 0.0);
     }
+    double rz = 0;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
         double ci = double(c[i]), ri = double(r[i]);
-        double qv[MB];
+        double uv[MB];
 #pragma unroll
         for (int a = 0; a < MB; ++a) {
-            qv[a] = double(Q[size_t(sl.s[a]) * N + i]);
-            ci += y[a] * double(U[size_t(sl.s[a]) * N + i]);
-            ri -= y[a] * qv[a];
+            uv[a] = double(U[size_t(sl.s[a]) * N + i]);
+            ci += y[a] * uv[a];
+            ri -= y[a] * double(Q[size_t(sl.s[a]) * N + i]);
         }
         c[i] = T(ci);
         const T rt = T(ri);
         r[i] = rt;
-        const T zt = jinv[i] * rt;
-        z[i] = zt;
+        double pi = double(jinv[i] * rt);
 #pragma unroll
-        for (int a = 0; a < MB; ++a) acc[a] += qv[a] * double(zt);
+        for (int a = 0; a < MB; ++a) pi -= y2[a] * uv[a];
+        const T pt = T(pi);
+        p[i] = pt;
+        rz += double(rt) * double(pt);
     }
-    __shared__ double sh[MB][kThreads / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int a = 0; a < MB; ++a) {
-        const double s = wave_sum(acc[a]);
-        if (lane == 0) sh[a][wv] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < m) {
-        const int a = threadIdx.x;
-        part[size_t(P_PROJ + a) * pstride + sg.col] = (sh[a][0] + sh[a][1]) + (sh[a][2] + sh[a][3]);
-    }
+    const double vv[1] = {rz};
+    block_partials<1>(vv, part, P_RZ, pstride, sg.col);
 }
 
-// Initial direction M-conjugate to U (condition 1 of the augmented CG): every block reduces
-// the (Q_a, z) partials and solves for y2 (GALERKIN: y2 = G^-1 Q^T z; PAPER: sequential tau_j
-// with the running z, (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j)); p_0 = z - U y2.
-// Without recycled directions p_0 = z = J^-1 r (Alg. 1).  Partial of (r, p_0).
-template <typename T, int MB>
-__global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, const VecBlk* __restrict__ vb, int pstride, int m,
-                                                        int mode, SlotList sl, const T* __restrict__ U,
-                                                        Scalars* __restrict__ scs, const T* __restrict__ z,
+// Without recycled directions p_0 = z = J^-1 r (Alg. 1).  Partial of (r, p_0).  (With them the
+// Galerkin kernel above forms p_0.)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, const VecBlk* __restrict__ vb, int pstride,
                                                         const T* __restrict__ r, const T* __restrict__ jinv,
                                                         T* __restrict__ p, double* __restrict__ part) {
-    constexpr int MB1 = MB > 0 ? MB : 1;
     const Seg sg = seg_of(vb, N, 0);
-    Scalars* __restrict__ sc = scs + sg.inst;
-    __shared__ double y2[kKMax];
-    if (MB > 0) {
-        double v[MB1];
-        block_row_sums<MB1>(part, pstride, sg, P_PROJ, m, v);
-        __shared__ double gm[kKMax], R[kKMax * kKMax];
-        __shared__ int32_t keep[kKMax];
-        for (int e = threadIdx.x; e < m * m; e += kThreads) R[e] = sc->R[e];
-        if (threadIdx.x < m) {
-            keep[threadIdx.x] = sc->keep[threadIdx.x];
-            gm[threadIdx.x] = sc->gam[sl.s[threadIdx.x]];
-        }
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            const int k = threadIdx.x;
-            double vk = 0;
-#pragma unroll
-            for (int a = 0; a < MB1; ++a)
-                if (a == k) vk = v[a];
-            double yk;
-            if (mode == FEWHA_RECYCLE_PAPER)   // (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j),  (p_i, q_j) = R[i][j]
-                yk = wave_forward_sub<MB1>(R, 1, m, gm, m, vk);
-            else
-                yk = wave_chol_solve<MB1>(R, keep, m, vk);
-            if (k < m) {
-                y2[k] = yk;
-                if (sg.local == 0) sc->y2[k] = yk;
-            }
-        }
-        __syncthreads();
-    }
-    double yv[MB1];
-#pragma unroll
-    for (int a = 0; a < MB; ++a) yv[a] = a < m ? y2[a] : 0.0;   // slots a >= m repeat slot 0
     double rz = 0;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
-        T pt;
-        if (MB == 0) {
-            pt = jinv[i] * r[i];
-        } else {
-            double pi = double(z[i]);
-#pragma unroll
-            for (int a = 0; a < MB; ++a) pi -= yv[a] * double(U[size_t(sl.s[a]) * N + i]);
-            pt = T(pi);
-        }
+        const T pt = jinv[i] * r[i];
         p[i] = pt;
         rz += double(r[i]) * double(pt);
     }
@@ -812,14 +812,8 @@ struct VecLaunch {
 
 template <typename T, int MB>
 void launch_gal(const VecLaunch& vl, int m, const SlotList& sl, const T* U, const T* Q, const Scalars* sc, T* c, T* r,
-                T* z, const T* jinv, double* part, hipStream_t s) {
-    k_galerkin_apply<T, MB><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, m, sl, U, Q, sc, c, r, z, jinv, part);
-}
-
-template <typename T, int MB>
-void launch_init(const VecLaunch& vl, int m, int mode, const SlotList& sl, const T* U, Scalars* sc, const T* z,
-                 const T* r, const T* jinv, T* p, double* part, hipStream_t s) {
-    k_init_dir<T, MB><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, m, mode, sl, U, sc, z, r, jinv, p, part);
+                T* p, const T* jinv, double* part, hipStream_t s) {
+    k_galerkin_apply<T, MB><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, m, sl, U, Q, sc, c, r, p, jinv, part);
 }
 
 template <typename T, int MP>
@@ -877,7 +871,7 @@ struct Frame {
         info = c.at<fewha_solve_info>(c.lay.info);
         vl = VecLaunch{N, c.B > 1 ? c.at<VecBlk>(c.lay.vecblk) : nullptr, c.VB, c.VB};
         gt = c.B > 1 ? c.at<GramBlk>(c.lay.gramblk) : nullptr;
-        ke = std::max(1, c.k * (c.k + 1));
+        ke = std::max(1, 2 * c.k * (c.k + 1));
         m = 0;
         if (!c.first && c.k > 0)
             m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
@@ -921,7 +915,10 @@ void enqueue_galerkin_init(const Ctx& c, const Frame<T>& f, hipStream_t s) {
         {
             ProfScope ps_(c, KID_GRAM, s);
             const dim3 grid(c.GB, ((m + 15) / 16) * ((m + 1 + 15) / 16));
-            k_gram<T><<<grid, kThreads, 0, s>>>(f.N, f.gt, m, f.act, f.U, f.Q, f.r, f.gpart);
+            if (m < 16)
+                k_gram<T, true><<<grid, kGramThreads, 0, s>>>(f.N, f.gt, m, f.act, f.U, f.Q, f.r, f.jinv, f.gpart);
+            else
+                k_gram<T, false><<<grid, kGramThreads, 0, s>>>(f.N, f.gt, m, f.act, f.U, f.Q, f.r, f.jinv, f.gpart);
         }
         {
             ProfScope ps_(c, KID_GRAM_SOLVE, s);
@@ -934,17 +931,13 @@ void enqueue_galerkin_init(const Ctx& c, const Frame<T>& f, hipStream_t s) {
         }
         ProfScope ps_(c, KID_GALERKIN, s);
         switch (f.mb) {
-#define X(v) case v: launch_gal<T, v>(f.vl, m, f.actp, f.U, f.Q, f.sc, f.cv, f.r, f.z, f.jinv, f.part, s); break;
+#define X(v) case v: launch_gal<T, v>(f.vl, m, f.actp, f.U, f.Q, f.sc, f.cv, f.r, p0, f.jinv, f.part, s); break;
             FEWHA_MB_CASES(X)
 #undef X
         }
-    }
-    ProfScope ps_(c, KID_INIT_DIR, s);
-    switch (f.mb) {
-        case 0: launch_init<T, 0>(f.vl, m, c.mode, f.actp, f.U, f.sc, f.z, f.r, f.jinv, p0, f.part, s); break;
-#define X(v) case v: launch_init<T, v>(f.vl, m, c.mode, f.actp, f.U, f.sc, f.z, f.r, f.jinv, p0, f.part, s); break;
-        FEWHA_MB_CASES(X)
-#undef X
+    } else {
+        ProfScope ps_(c, KID_INIT_DIR, s);
+        k_init_dir<T><<<f.vl.grid, kThreads, 0, s>>>(f.vl.N, f.vl.vb, f.vl.pstride, f.r, f.jinv, p0, f.part);
     }
 }
 
