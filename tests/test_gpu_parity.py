@@ -154,6 +154,30 @@ def test_zero_frame_then_frames_fp64(mode, project_all):
     assert max(errs) <= 1e-10, errs
 
 
+@pytest.mark.parametrize("mode", ["galerkin", "paper"])
+def test_large_recycle_space_fp64(mode):
+    """k = 20 recycled directions (20 iterations per frame, so that the PAPER mode, which
+    recycles the previous frame's directions, also reaches 20): the Gram pass spans 2 x 2
+    tiles of 16 (off-diagonal tiles load their own J^-1 Q rows).  Frames this long amplify
+    rounding-order differences (the non-conjugate sequential projections of the PAPER mode
+    most), so each frame's bar is 10 times the oracle's own deviation when the slopes are
+    perturbed at 1e-15, and at least 1e-10."""
+    spec, seq, _ = system("small")
+    spec = spec.copy(recycle_k=20, max_iter=20, recycle_mode=mode)
+    sysm = OracleSystem(spec)
+    frames = 4
+    errs, infos = _run_sequence(spec, seq, sysm, frames)
+    a, b = AugmentedReconstructor(sysm), AugmentedReconstructor(sysm)
+    rng = np.random.default_rng(0)
+    for t in range(frames):
+        ca, _ = a.solve(seq[t])
+        cb, _ = b.solve(seq[t] * (1 + 1e-15 * rng.standard_normal(seq[t].shape)))
+        assert errs[t] <= max(1e-10, 10 * rel(cb, ca)), (t, errs[t], rel(cb, ca))
+    assert max(gi["recycle_used"] for gi, _ in infos) == 20
+    for gi, ri in infos:
+        assert gi["recycle_used"] == ri["recycle_used"] and gi["dropped"] == ri["dropped"]
+
+
 def test_plain_pcg_k0_fp64():
     spec, seq, sysm = system("small")
     spec = spec.copy(recycle_k=0)
