@@ -84,12 +84,12 @@ def frame_kernel_bytes(name, N, S, V, e, m, it, mp):
         return (2 * S + V) * e
     if name == "residual":        # b, b_prev, r in; r, b_prev out
         return 5 * N * e
-    if name == "gram":            # m U, m Q, r in
-        return (2 * m + 1) * N * e
-    if name == "galerkin_apply":  # c, r, J^-1, m U, m Q in; c, r, z out
+    if name == "gram":            # m U, m Q, r, J^-1 in
+        return (2 * m + 2) * N * e
+    if name == "galerkin_apply":  # c, r, J^-1, m U, m Q in; c, r, p_0 out
         return (6 + 2 * m) * N * e
-    if name == "init_dir":        # z, r, m U in; p out
-        return (3 + m) * N * e
+    if name == "init_dir":        # r, J^-1 in; p_0 out (no recycled directions)
+        return 3 * N * e
     if name == "update1":         # p, q, c, r, J^-1 (+ U, Q of the projection) in; c, r, z out; last: no z
         return ((it - 1) * (8 + 2 * mp) + 6) * N * e
     if name == "update2":         # z, p (+ U of the projection) in; next p out
