@@ -7,11 +7,6 @@
 
 namespace fewha {
 
-__device__ __forceinline__ int pmod(int a, int m) {
-    const int r = a % m;
-    return r < 0 ? r + m : r;
-}
-
 // The value v holds in lane `lane` (wave-uniform), in every lane: a read of that lane's
 // register into scalar registers.
 __device__ __forceinline__ double lane_value(double v, int lane) {
@@ -84,24 +79,6 @@ __device__ __forceinline__ double block_sum_array(const double* __restrict__ a, 
     const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
     __syncthreads();
     return r;
-}
-
-// Copies `count` (>= 1) values into LDS with NT threads: every load of a thread is issued,
-// unconditionally (clamped index), before its first LDS store, so the global latencies overlap
-// instead of adding up (count <= NT * MAXPER).
-template <int NT, int MAXPER, typename T, typename Src, typename Dst>
-__device__ __forceinline__ void stage_to_lds(int count, Src src, Dst dst) {
-    T v[MAXPER];
-#pragma unroll
-    for (int k = 0; k < MAXPER; ++k) {
-        const int e = threadIdx.x + k * NT;
-        v[k] = src(e < count ? e : count - 1);
-    }
-#pragma unroll
-    for (int k = 0; k < MAXPER; ++k) {
-        const int e = threadIdx.x + k * NT;
-        if (e < count) dst(e, v[k]);
-    }
 }
 
 }  // namespace fewha

@@ -19,7 +19,7 @@ constexpr int kDefaultBlockElems = 384;  // default elements per vector workgrou
 constexpr int kGramElems = 3072;    // elements per Gram workgroup (one instance: <= kGramBlocks)
 constexpr int kKMax = FEWHA_MAX_RECYCLE;
 constexpr int kSlotsMax = kKMax + 256;
-constexpr int kTile = 16;           // wavefront-node tile side of the fused data-term kernel
+constexpr int kTile = 14;           // wavefront-node tile side of the fused data-term kernel (16 with the halo)
 constexpr int kCoarseThreads = 1024;  // threads of the one-workgroup-per-layer coarse wavelet kernels
 // Wavelet blocks up to CB x CB are transformed inside one workgroup's LDS; larger levels are
 // tiled over many workgroups (one CU's LDS bandwidth is the limit of the in-LDS passes).
@@ -34,9 +34,8 @@ constexpr int kRMax = 6;            // contributions per layer row/column held b
 constexpr int kXcds = 8;            // accelerator complex dies; workgroup i runs on die i mod kXcds
 constexpr int kGramBlocks = 64;     // Gram workgroups of one instance at most (partials per entry)
 constexpr int kGramThreads = 1024;  // threads of a Gram workgroup (16 wavefronts)
-constexpr int kDataThreads = 1024;  // threads of the fused data-term kernel
+constexpr int kDataThreads = 256;   // threads of the fused data-term kernel (one halo-tile node each)
 constexpr int kSolveThreads = 1024; // threads of the single-block Gram reduction and solve
-constexpr int kLayerGroups = 3;     // threads sharing one wavefront node's layer sum
 constexpr int kGatherGroup = 8;     // sensors whose gather lists are staged together
 
 // Device descriptors (plain data, copied into the workspace at setup).  The layers and

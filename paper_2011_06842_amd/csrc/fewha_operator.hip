@@ -495,22 +495,21 @@ __device__ __forceinline__ int find_sensor(const WfsDev* __restrict__ wfs, int G
 
 // Fused Gamma^T C^-1 Gamma P per sensor tile: wavefront on the tile plus a one-node halo,
 // slopes on the (kTile+1)^2 subapertures touching it, adjoint onto the kTile^2 nodes.  The
-// bilinear cell tables of the tile's rows and columns are staged in LDS for every layer, and
-// each node's layer sum is split over kLayerGroups threads (layers l = lg mod kLayerGroups),
-// combined in a fixed order.  NT threads per workgroup: 1024 for small systems (few tiles),
-// 256 for large ones (more workgroups per CU to overlap their memory latencies); the
-// arithmetic of every node is the same for both.
-template <typename T, int NT>
-__global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs,
-                                                             const int2* __restrict__ tiles,
-                                                             const LayerDev* __restrict__ lays,
-                                                             const PairDev* __restrict__ pairs,
-                                                             const int32_t* __restrict__ cidx,
-                                                             const T* __restrict__ frac, const T* __restrict__ phi,
-                                                             const T* __restrict__ w, T* __restrict__ psi) {
+// halo tile has exactly one node per thread; each thread sums every layer of the sensor's
+// instance in order (propagation, Sec. 2) from the bilinear cell tables of the tile's rows and
+// columns, staged in LDS; the per-layer scalars are the same for the whole workgroup.
+template <typename T>
+__global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __restrict__ wfs,
+                                                            const int2* __restrict__ tiles,
+                                                            const LayerDev* __restrict__ lays,
+                                                            const int32_t* __restrict__ cidx,
+                                                            const T* __restrict__ frac, const T* __restrict__ phi,
+                                                            const T* __restrict__ w, T* __restrict__ psi) {
     constexpr int E = kTile + 2, S1 = kTile + 1;
-    constexpr int PS = (S1 * S1 + NT - 1) / NT;              // subapertures per thread
-    __shared__ T spart[kLayerGroups][E * E];
+    static_assert(E * E == kDataThreads, "one halo-tile node per thread");
+    static_assert(S1 * S1 <= kDataThreads, "one subaperture per thread");
+    static_assert(2 * E == 32, "table entries indexed by shifts");
+    __shared__ T sphi[E * E];
     __shared__ T stx[S1 * S1], sty[S1 * S1];
     __shared__ int32_t srow[FEWHA_MAX_LAYERS][E], scol[FEWHA_MAX_LAYERS][E];
     __shared__ T sfy[FEWHA_MAX_LAYERS][E], sfx[FEWHA_MAX_LAYERS][E];
@@ -526,31 +525,27 @@ __global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs
     const char* __restrict__ phib = reinterpret_cast<const char*>(phi + lays[W.l0].off);
     const int tl = st.y;
     const int i0 = (tl / W.tiles_x) * kTile, j0 = (tl % W.tiles_x) * kTile;
-    // slope weights of this thread's subapertures, requested before anything waits
-    T wxs[PS], wys[PS];
-#pragma unroll
-    for (int k = 0; k < PS; ++k) {
-        const int e = threadIdx.x + k * NT;
-        const int ls = e / S1, lt = e - ls * S1;
-        const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
-        wxs[k] = wys[k] = 0;
-        if (e < S1 * S1 && si >= 0 && si < ns && sj >= 0 && sj < ns) {
-            wxs[k] = w[W.soff + si * ns + sj];
-            wys[k] = w[W.soff + ns * ns + si * ns + sj];
-        }
+    // slope weights of this thread's subaperture, requested before anything waits
+    const int ls = threadIdx.x / S1, lt = threadIdx.x - ls * S1;
+    const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
+    const bool sub = threadIdx.x < S1 * S1 && si >= 0 && si < ns && sj >= 0 && sj < ns;
+    T wx = 0, wy = 0;
+    if (sub) {
+        wx = w[W.soff + si * ns + sj];
+        wy = w[W.soff + ns * ns + si * ns + sj];
     }
-    // the layers of the sensor's instance and the bilinear cells of the tile's rows and
-    // columns on each: every load is issued before the first LDS store
-    constexpr int PER = (FEWHA_MAX_LAYERS * 2 * E + NT - 1) / NT;
-    const int nent = L * 2 * E;                                  // table entries of the tile
+    // the bilinear cells of the tile's rows and columns on each layer: every load is issued
+    // before the first LDS store
+    constexpr int PER = (FEWHA_MAX_LAYERS * 2 * E + kDataThreads - 1) / kDataThreads;
+    const int nent = L * 2 * E;
     int32_t ci[PER];
     T fr[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        if (k * NT >= nent) break;                               // uniform: only the L layers
-        const int e = threadIdx.x + k * NT;
+        if (k * kDataThreads >= nent) break;                     // uniform: only the L layers
+        const int e = threadIdx.x + k * kDataThreads;
         if (e < nent) {
-            const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
+            const int l = e >> 5, q = e & 31, col = q >= E, kk = q - col * E;
             const int node = (col ? j0 : i0) - 1 + kk;
             const int nn = node < 0 ? 0 : (node > ns ? ns : node);   // clamped: halo nodes outside are unused
             const size_t o = size_t(W.fwd0) + size_t(l) * 2 * np + col * np + nn;
@@ -567,10 +562,10 @@ __global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs
     }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        if (k * NT >= nent) break;
-        const int e = threadIdx.x + k * NT;
+        if (k * kDataThreads >= nent) break;
+        const int e = threadIdx.x + k * kDataThreads;
         if (e < nent) {
-            const int l = e / (2 * E), q = e - l * 2 * E, col = q >= E, kk = q - col * E;
+            const int l = e >> 5, q = e & 31, col = q >= E, kk = q - col * E;
             if (col) {
                 scol[l][kk] = ci[k];
                 sfx[l][kk] = fr[k];
@@ -585,64 +580,62 @@ __global__ void __launch_bounds__(NT) k_data_term(const WfsDev* __restrict__ wfs
         soffl[threadIdx.x] = loff;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kLayerGroups * E * E; e += NT) {
-        const int lg = e / (E * E), node = e - lg * E * E;
-        const int li = node / E, lj = node - li * E;
+    {   // this thread's node: the sum over the layers, in layer order
+        const int li = threadIdx.x / E, lj = threadIdx.x - li * E;
         const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        // layers in chunks of LC whose loads are all issued before the first is used (layers
+        // past L read the last one and are not added)
+        constexpr int LC = 9;
         T v = 0;
-        if (i >= 0 && i <= ns && j >= 0 && j <= ns) {
-#pragma unroll 4
-            for (int l = lg; l < L; l += kLayerGroups) {
+        for (int lb = 0; lb < L; lb += LC) {
+            T p[LC][4];
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                const int l = lb + k < L ? lb + k : L - 1;
                 const uint32_t n = uint32_t(sn[l]);
-                const T fy = sfy[l][li], fx = sfx[l][lj];
                 const uint32_t o0 = soffl[l] + (uint32_t(srow[l][li]) * n + uint32_t(scol[l][lj])) * uint32_t(sizeof(T));
                 const uint32_t o1 = o0 + n * uint32_t(sizeof(T));
-                const T p00 = *reinterpret_cast<const T*>(phib + o0);
-                const T p01 = *reinterpret_cast<const T*>(phib + o0 + sizeof(T));
-                const T p10 = *reinterpret_cast<const T*>(phib + o1);
-                const T p11 = *reinterpret_cast<const T*>(phib + o1 + sizeof(T));
-                // explicit fused multiply-adds: the same roundings in every launch shape
-                const T r0 = fma(fx, p01, (T(1) - fx) * p00);
-                const T r1 = fma(fx, p11, (T(1) - fx) * p10);
-                v = fma(fy, r1, fma(T(1) - fy, r0, v));
+                p[k][0] = *reinterpret_cast<const T*>(phib + o0);
+                p[k][1] = *reinterpret_cast<const T*>(phib + o0 + sizeof(T));
+                p[k][2] = *reinterpret_cast<const T*>(phib + o1);
+                p[k][3] = *reinterpret_cast<const T*>(phib + o1 + sizeof(T));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                const int l = lb + k < L ? lb + k : L - 1;
+                const T fy = sfy[l][li], fx = sfx[l][lj];
+                const T r0 = fma(fx, p[k][1], (T(1) - fx) * p[k][0]);
+                const T r1 = fma(fx, p[k][3], (T(1) - fx) * p[k][2]);
+                const T vn = fma(fy, r1, fma(T(1) - fy, r0, v));
+                v = lb + k < L ? vn : v;
             }
         }
-        spart[lg][node] = v;
+        sphi[threadIdx.x] = (i >= 0 && i <= ns && j >= 0 && j <= ns) ? v : T(0);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < E * E; e += NT) {
-        T v = spart[0][e];
-        for (int lg = 1; lg < kLayerGroups; ++lg) v += spart[lg][e];
-        spart[0][e] = v;
-    }
-    __syncthreads();
-    const T* sphi = spart[0];
-#pragma unroll
-    for (int k = 0; k < PS; ++k) {
-        const int e = threadIdx.x + k * NT;
-        if (e >= S1 * S1) break;
-        const int ls = e / S1, lt = e - ls * S1;
-        const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
+    if (threadIdx.x < S1 * S1) {   // Shack-Hartmann slopes and noise weights of the subaperture
         T tx = 0, ty = 0;
-        if (si >= 0 && si < ns && sj >= 0 && sj < ns) {
+        if (sub) {
             const T p00 = sphi[ls * E + lt], p01 = sphi[ls * E + lt + 1];
             const T p10 = sphi[(ls + 1) * E + lt], p11 = sphi[(ls + 1) * E + lt + 1];
             const T sx = T(0.5) * ((p01 - p00) + (p11 - p10));
             const T sy = T(0.5) * ((p10 - p00) + (p11 - p01));
-            tx = wxs[k] * sx;
-            ty = wys[k] * sy;
+            tx = wx * sx;
+            ty = wy * sy;
         }
-        stx[e] = tx;
-        sty[e] = ty;
+        stx[threadIdx.x] = tx;
+        sty[threadIdx.x] = ty;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTile * kTile; e += NT) {
-        const int li = e / kTile, lj = e - li * kTile;
+    if (threadIdx.x < kTile * kTile) {   // Shack-Hartmann adjoint onto the tile's nodes
+        const int li = threadIdx.x / kTile, lj = threadIdx.x - li * kTile;
         const int i = i0 + li, j = j0 + lj;
-        if (i > ns || j > ns) continue;
-        const int A = (li + 1) * S1 + lj + 1, B = (li + 1) * S1 + lj, C = li * S1 + lj + 1, D = li * S1 + lj;
-        psi[W.noff + i * np + j] = T(0.5) * ((stx[B] - stx[A]) + (stx[D] - stx[C])) +
-                                   T(0.5) * ((sty[C] - sty[A]) + (sty[D] - sty[B]));
+        if (i <= ns && j <= ns) {
+            const int A = (li + 1) * S1 + lj + 1, B = (li + 1) * S1 + lj, C = li * S1 + lj + 1, D = li * S1 + lj;
+            psi[W.noff + i * np + j] = T(0.5) * ((stx[B] - stx[A]) + (stx[D] - stx[C])) +
+                                       T(0.5) * ((sty[C] - sty[A]) + (sty[D] - sty[B]));
+        }
     }
 }
 
@@ -1057,16 +1050,9 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
 template <typename T>
 void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s) {
     ProfScope ps_(c, KID_DATA_TERM, s);
-    auto go = [&](auto kern, int nt) {
-        kern<<<c.data_grid, nt, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles),
-                                        c.at<LayerDev>(c.lay.layers), c.at<PairDev>(c.lay.pairs),
-                                        c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), phi,
-                                        c.at<T>(c.lay.weight), psi_nodes);
-    };
-    if (c.gather_rows > 1)   // large system (the wide adjoint-gather tiles): smaller workgroups
-        go(k_data_term<T, 256>, 256);
-    else
-        go(k_data_term<T, kDataThreads>, kDataThreads);
+    k_data_term<T><<<c.data_grid, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles),
+                                                        c.at<LayerDev>(c.lay.layers), c.at<int32_t>(c.lay.cellidx),
+                                                        c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), psi_nodes);
 }
 
 template <typename T>

@@ -77,25 +77,6 @@ __device__ __forceinline__ void block_row_sums(const double* __restrict__ part, 
     __syncthreads();
 }
 
-// Triangular solves with the factor of the Gram matrix (drop-aware), G = R^T R; t is a work
-// array of m entries (in LDS at the call sites, so that no kernel needs scratch memory).
-__device__ void chol_solve(const double* R, const int32_t* keep, int m, const double* v, double* y, double* t) {
-    for (int j = 0; j < m; ++j) {
-        t[j] = 0;
-        if (!keep[j]) continue;
-        double s = v[j];
-        for (int i = 0; i < j; ++i) s -= R[i * m + j] * t[i];
-        t[j] = s / R[j * m + j];
-    }
-    for (int j = m - 1; j >= 0; --j) {
-        y[j] = 0;
-        if (!keep[j]) continue;
-        double s = t[j];
-        for (int k = j + 1; k < m; ++k) s -= R[j * m + k] * y[k];
-        y[j] = s / R[j * m + j];
-    }
-}
-
 // Small dense algebra of the recycle space on one wavefront (m <= MB <= 64, all 64 lanes
 // active): lane k owns column k (and row k) of the factor in registers; pivots and solution
 // entries are broadcast by reading one lane's register into scalar registers, so no step
