@@ -5,13 +5,15 @@
 //                                             fits the coarse block, separable passes in LDS
 //                              k_idwt_step    one launch per larger block size; 32x32 output tiles,
 //                                             separable passes in LDS from a 36x36 coefficient halo
-//   A^T C^-1 A (Sec. 2):       k_data_term    per (sensor, 16x16 node tile): bilinear propagation
-//                                             from every layer (NGS shift, LGS cone), Shack-Hartmann
+//   A^T C^-1 A (Sec. 2):       k_data_term    per (sensor, 14x14 node tile), one node of the
+//                                             16x16 halo tile per thread: bilinear propagation from
+//                                             every layer (NGS shift, LGS cone), Shack-Hartmann
 //                                             slopes, noise weights, Shack-Hartmann adjoint; the
 //                                             slopes never leave LDS
-//                              k_adj_gather   per 16x16 layer tile: exact transpose of the bilinear
-//                                             propagation as a gather from LDS-staged sensor
-//                                             rectangles (no atomics, deterministic)
+//                              k_adj_gather   per 8x32 layer tile (k_adj_gather_win: 32x32 for large
+//                                             systems, sensor rectangles staged in LDS): exact
+//                                             transpose of the bilinear propagation as a gather
+//                                             (no atomics, deterministic)
 //   W^-T + alpha D:            k_dwt_step / k_dwt_coarse, the mirror images of the synthesis,
 //                                             with the prior and an optional (x, Mx) partial fused
 //                                             into the final coefficients

@@ -5,10 +5,11 @@
 // Every inner product is reduced in FP64 in two fixed-order stages: each vector workgroup
 // writes one partial per inner product; the consumer kernel -- every workgroup of it,
 // redundantly -- sums its instance's partials in the same order and derives the scalars it
-// needs (alpha, beta, mu, the k x k Gram solve).  Every workgroup therefore holds
-// bit-identical scalars without an extra single-block launch, and results are reproducible
-// run to run.  Workgroup 0 of an instance records its scalars in device memory for the next
-// kernels and for the frame statistics.
+// needs (alpha, beta, mu, the in-loop projection).  Every workgroup therefore holds
+// bit-identical scalars without an extra single-block launch between iterations, and results
+// are reproducible run to run.  Workgroup 0 of an instance records its scalars in device
+// memory for the next kernels and for the frame statistics.  The frame start's k x k solves
+// (Galerkin and initial-direction coefficients) run once per instance in k_gram_solve.
 //
 // A batch of independent instances runs through the same kernels: a workgroup's instance,
 // element range and partial column come from the workgroup table (absent for a single
