@@ -504,24 +504,67 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0;
-    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
-        const int64_t i = sg.off + j;
-        c[i] = T(double(c[i]) + alpha * double(p[i]));
-        const T rt = T(double(r[i]) - alpha * double(q[i]));
+    constexpr int MP1 = MP > 0 ? MP : 1;
+    // one element: the update and its partial-sum terms, from loaded operands
+    auto element = [&](int64_t i, T cv, T pv, T rv, T qv, T jv, const T* Qv, const T* Uv) {
+        c[i] = T(double(cv) + alpha * double(pv));
+        const T rt = T(double(rv) - alpha * double(qv));
         r[i] = rt;
         const double rd = double(rt);
         acc[0] += rd * rd;
         if (!last) {
-            const T zt = jinv[i] * rt;
+            const T zt = jv * rt;
             z[i] = zt;
             const double zd = double(zt);
             acc[1] += rd * zd;
 #pragma unroll
             for (int a = 0; a < MP; ++a) {   // slots a >= mp repeat slot 0; their sums are unused
-                acc[2 + a] += double(Q[size_t(pl.s[a]) * N + i]) * zd;
-                acc[2 + MP + a] += double(U[size_t(pl.s[a]) * N + i]) * rd;
+                acc[2 + a] += double(Qv[a]) * zd;
+                acc[2 + MP + a] += double(Uv[a]) * rd;
             }
         }
+    };
+    // four elements per step with every load issued first (the elements are visited, and
+    // summed, in the same order as one at a time), then the rest one at a time
+    const int64_t stride = int64_t(sg.nb) * kThreads;
+    int64_t j = int64_t(sg.local) * kThreads + threadIdx.x;
+    for (; j + 3 * stride < sg.n; j += 4 * stride) {
+        T cv[4], pv[4], rv[4], qv[4], jv[4] = {}, Qv[4][MP1] = {}, Uv[4][MP1] = {};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = sg.off + j + u * stride;
+            cv[u] = c[i];
+            pv[u] = p[i];
+            rv[u] = r[i];
+            qv[u] = q[i];
+        }
+        if (!last) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = sg.off + j + u * stride;
+                jv[u] = jinv[i];
+#pragma unroll
+                for (int a = 0; a < MP; ++a) {
+                    Qv[u][a] = Q[size_t(pl.s[a]) * N + i];
+                    Uv[u][a] = U[size_t(pl.s[a]) * N + i];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) element(sg.off + j + u * stride, cv[u], pv[u], rv[u], qv[u], jv[u], Qv[u], Uv[u]);
+    }
+    for (; j < sg.n; j += stride) {
+        const int64_t i = sg.off + j;
+        T jv = 0, Qv[MP1] = {}, Uv[MP1] = {};
+        if (!last) {
+            jv = jinv[i];
+#pragma unroll
+            for (int a = 0; a < MP; ++a) {
+                Qv[a] = Q[size_t(pl.s[a]) * N + i];
+                Uv[a] = U[size_t(pl.s[a]) * N + i];
+            }
+        }
+        element(i, c[i], p[i], r[i], q[i], jv, Qv, Uv);
     }
     __shared__ double sh[NV][kThreads / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -610,7 +653,28 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
     double yr[MP1];
 #pragma unroll
     for (int a = 0; a < MP; ++a) yr[a] = a < mp ? sy[a] : 0.0;
-    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+    // four elements per step with every load issued first, then the rest one at a time
+    const int64_t stride = int64_t(sg.nb) * kThreads;
+    int64_t j = int64_t(sg.local) * kThreads + threadIdx.x;
+    for (; j + 3 * stride < sg.n; j += 4 * stride) {
+        T zv[4], pv[4], uv[4][MP1] = {};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = sg.off + j + u * stride;
+            zv[u] = z[i];
+            pv[u] = p[i];
+#pragma unroll
+            for (int a = 0; a < MP; ++a) uv[u][a] = U[size_t(pl.s[a]) * N + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double vv = double(zv[u]) + beta * double(pv[u]);
+#pragma unroll
+            for (int a = 0; a < MP; ++a) vv -= yr[a] * double(uv[u][a]);   // yr = 0 beyond mp
+            pn[sg.off + j + u * stride] = T(vv);
+        }
+    }
+    for (; j < sg.n; j += stride) {
         const int64_t i = sg.off + j;
         double vv = double(z[i]) + beta * double(p[i]);
 #pragma unroll
