@@ -219,6 +219,36 @@ __device__ __forceinline__ void load4(const float* p, double (&v)[4], double f) 
     v[2] = double(x.z) * f;
     v[3] = double(x.w) * f;
 }
+// Four consecutive elements as loaded (the FP64 conversion comes later, so that the loads of
+// a step are all issued before the first one is waited for).
+template <typename T>
+struct Raw4;
+template <>
+struct Raw4<float> {
+    float4 a;
+    __device__ __forceinline__ void load(const float* p) { a = *reinterpret_cast<const float4*>(p); }
+    __device__ __forceinline__ void to(double (&v)[4], double f) const {
+        v[0] = double(a.x) * f;
+        v[1] = double(a.y) * f;
+        v[2] = double(a.z) * f;
+        v[3] = double(a.w) * f;
+    }
+};
+template <>
+struct Raw4<double> {
+    double2 a, b;
+    __device__ __forceinline__ void load(const double* p) {
+        a = reinterpret_cast<const double2*>(p)[0];
+        b = reinterpret_cast<const double2*>(p)[1];
+    }
+    __device__ __forceinline__ void to(double (&v)[4], double f) const {
+        v[0] = a.x * f;
+        v[1] = a.y * f;
+        v[2] = b.x * f;
+        v[3] = b.y * f;
+    }
+};
+
 __device__ __forceinline__ void load4(const double* p, double (&v)[4], double f) {
     const double2 x = reinterpret_cast<const double2*>(p)[0], y = reinterpret_cast<const double2*>(p)[1];
     v[0] = x.x * f;
@@ -265,36 +295,36 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
     const T* pj = jinv + g.off;
     const double ma = ar < m ? 1.0 : 0.0, mb = bc <= m ? 1.0 : 0.0;
     f64x4 c = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
-    constexpr int DEPTH = 4;                       // 16-element chunks per step
+    // one 16-element chunk per step: its three (four) loads issued together, then converted
+    // and fed to the matrix cores (more chunks in flight cost the occupancy that hides them)
     const int64_t step = int64_t(g.nb) * NW * 16;
     const int64_t n = g.n;
-    for (int64_t base = (int64_t(g.local) * NW + wv) * 16; base < n; base += DEPTH * step) {   // n % 16 == 0
-        double av[DEPTH][4], bv[DEPTH][4], jq[DEPTH][4];   // jq: J^-1 Q_a, the row operand of Y
+    for (int64_t base = (int64_t(g.local) * NW + wv) * 16; base < n; base += step) {   // n % 16 == 0
+        const int64_t e0 = base + 4 * kq;
+        Raw4<T> ra, rb, rj, rq;
+        ra.load(pa + e0);
+        rb.load(pb + e0);
+        rj.load(pj + e0);
+        if (!ONE_TILE) rq.load(pq + e0);
+        __builtin_amdgcn_sched_barrier(0);
+        double av[4], bv[4], jq[4];                // jq: J^-1 Q_a, the row operand of Y
+        ra.to(av, ma);
+        rb.to(bv, mb);
+        rj.to(jq, 1.0);
+        if (ONE_TILE) {   // m < 16: the only tile is diagonal, Q_a is the lane's column operand
 #pragma unroll
-        for (int d = 0; d < DEPTH; ++d) {
-            const bool in = base + d * step < n;   // uniform over the wavefront
-            const int64_t e0 = (in ? base + d * step : 0) + 4 * kq;
-            const double f = in ? 1.0 : 0.0;
-            load4(pa + e0, av[d], ma * f);
-            load4(pb + e0, bv[d], mb * f);
-            load4(pj + e0, jq[d], 1.0);
-            if (ONE_TILE) {   // m < 16: the only tile is diagonal, Q_a is the lane's column operand
+            for (int j = 0; j < 4; ++j) jq[j] *= bv[j];
+        } else {
+            double qa[4];
+            rq.to(qa, ma);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) jq[d][j] *= bv[d][j];
-            } else {
-                double qa[4];
-                load4(pq + e0, qa, ma * f);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) jq[d][j] *= qa[j];
-            }
+            for (int j = 0; j < 4; ++j) jq[j] *= qa[j];
         }
 #pragma unroll
-        for (int d = 0; d < DEPTH; ++d)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][j], bv[d][j], c, 0, 0, 0);
-                c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(jq[d][j], bv[d][j], c2, 0, 0, 0);
-            }
+        for (int j = 0; j < 4; ++j) {
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], c, 0, 0, 0);
+            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(jq[j], bv[j], c2, 0, 0, 0);
+        }
     }
     // lane l, register v holds tile entry (row 4 v + l / 16, column l mod 16); the NW tiles are
     // summed by the first 256 threads, one entry each, in a fixed pairwise order
