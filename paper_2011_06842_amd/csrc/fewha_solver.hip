@@ -554,14 +554,15 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
             }
         }
     };
-    // four elements per step with every load issued first (the elements are visited, and
+    // UN elements per step with every load issued first (the elements are visited, and
     // summed, in the same order as one at a time), then the rest one at a time
+    constexpr int UN = 2;
     const int64_t stride = int64_t(sg.nb) * kThreads;
     int64_t j = int64_t(sg.local) * kThreads + threadIdx.x;
-    for (; j + 3 * stride < sg.n; j += 4 * stride) {
-        T cv[4], pv[4], rv[4], qv[4], jv[4] = {}, Qv[4][MP1] = {}, Uv[4][MP1] = {};
+    for (; j + (UN - 1) * stride < sg.n; j += UN * stride) {
+        T cv[UN], pv[UN], rv[UN], qv[UN], jv[UN] = {}, Qv[UN][MP1] = {}, Uv[UN][MP1] = {};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < UN; ++u) {
             const int64_t i = sg.off + j + u * stride;
             cv[u] = c[i];
             pv[u] = p[i];
@@ -570,7 +571,7 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
         }
         if (!last) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < UN; ++u) {
                 const int64_t i = sg.off + j + u * stride;
                 jv[u] = jinv[i];
 #pragma unroll
@@ -581,7 +582,7 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) element(sg.off + j + u * stride, cv[u], pv[u], rv[u], qv[u], jv[u], Qv[u], Uv[u]);
+        for (int u = 0; u < UN; ++u) element(sg.off + j + u * stride, cv[u], pv[u], rv[u], qv[u], jv[u], Qv[u], Uv[u]);
     }
     for (; j < sg.n; j += stride) {
         const int64_t i = sg.off + j;
