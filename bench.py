@@ -396,7 +396,10 @@ def run_unet(args, dev):
     groups = [(1, 256), (8, 128)]
     net = fw.UNetContext(groups, device=dev)
     rng = np.random.default_rng(SEED)
-    net.set_params(W.init_params(net.n_params, None, SEED, dev) + 0.01)
+    # He-normal weights plus symmetric noise on every parameter (nonzero biases and head, so
+    # every layer carries gradient, with a finite loss)
+    noise = torch.from_numpy((0.02 * rng.standard_normal(net.n_params)).astype(np.float32)).to(dev)
+    net.set_params(W.init_params(net.n_params, None, SEED, dev) + noise)
     x = torch.from_numpy(rng.standard_normal(4 * net.nodes).astype(np.float32)).to(dev)
     t = torch.from_numpy(rng.standard_normal(net.nodes).astype(np.float32)).to(dev)
     out = torch.empty(net.nodes, dtype=torch.float32, device=dev)
@@ -411,7 +414,7 @@ def run_unet(args, dev):
     e1.record()
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / R
-    net.backward(x, t)
+    loss0 = float(net.backward(x, t).cpu()[0])
     net.adam_step()
     torch.cuda.synchronize()
     e0.record()
@@ -432,6 +435,7 @@ def run_unet(args, dev):
                      "peak": BF16_PEAK_TFS, "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFS, 4),
                      "traffic": None},
         "train_tflops": round(3 * ff / (train_ms * 1e-3) / 1e12, 2),
+        "first_step_loss": round(loss0, 6),
     }
 
 

@@ -16,6 +16,7 @@
 //                  1x1 head with the MSE loss, ReLU', bias gradients, Adam, layouts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -450,36 +451,74 @@ __global__ void __launch_bounds__(kT) k_conv_wgrad(WgradGroups wg, int C1, int C
     }
 }
 
-// Fixed-order sums of chunk partials for several tensors in one launch: tensor k owns
-// blocks [block0[k], block0[k + 1]), one element per thread; the chunks are summed in order
-// in eight interleaved partial sums (eight loads in flight), combined in a fixed order.
+// Fixed-order sums of chunk partials for several tensors in one launch.  Every element is the
+// sum of its chunks in eight running sums (sum j takes the chunks c with c mod 8 = j, in
+// increasing order), combined as ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)).  Tensor k
+// owns blocks [block0[k], block0[k + 1]) and splits the eight sums of an element over
+// stripes[k] threads (1, 2, 4 or 8; thread u of an element keeps the sums u, u + S, ...), so
+// that tensors with many chunks keep more loads in flight; the split leaves every bit of the
+// result unchanged.
 struct ReduceTable {
     const float* part[16];
     float* out[16];
     int64_t n[16];
     int chunks[16];
+    int stripes[16];
     int block0[17];
     int count;
 };
 
+// The running sums u + S q (q < 8 / S) of one element over C chunks of stride n, S groups of
+// eight chunks per step with every load issued before the additions.
+template <int S>
+__device__ inline void stripe_sums(const float* __restrict__ p, int64_t n, int C, int u, float* s) {
+    constexpr int J = 8 / S;
+    int c = 0;
+    for (; c + 8 * S <= C; c += 8 * S) {
+        float v[S][J];
+#pragma unroll
+        for (int g = 0; g < S; ++g)
+#pragma unroll
+            for (int q = 0; q < J; ++q) v[g][q] = p[size_t(c + 8 * g + u + S * q) * n];
+#pragma unroll
+        for (int g = 0; g < S; ++g)
+#pragma unroll
+            for (int q = 0; q < J; ++q) s[q] += v[g][q];
+    }
+    for (; c < C; c += 8) {
+#pragma unroll
+        for (int q = 0; q < J; ++q)
+            if (c + u + S * q < C) s[q] += p[size_t(c + u + S * q) * n];
+    }
+}
+
 __global__ void __launch_bounds__(kT) k_reduce_table(ReduceTable tb) {
+    __shared__ float sm[8][kT];
     int k = 0;
     while (k + 1 < tb.count && int(blockIdx.x) >= tb.block0[k + 1]) ++k;
-    const int64_t i = int64_t(blockIdx.x - tb.block0[k]) * kT + threadIdx.x;
+    const int S = tb.stripes[k];
+    const int E = kT / S;   // elements per block
+    const int u = int(threadIdx.x) / E, e = int(threadIdx.x) - u * E;
+    const int64_t i = int64_t(blockIdx.x - tb.block0[k]) * E + e;
     const int64_t n = tb.n[k];
-    if (i >= n) return;
-    const float* __restrict__ p = tb.part[k] + i;
-    const int C = tb.chunks[k];
+    const bool live = i < n;
     float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int c = 0;
-    for (; c + 8 <= C; c += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s[u] += p[size_t(c + u) * n];
+    if (live) {
+        const float* __restrict__ p = tb.part[k] + i;
+        const int C = tb.chunks[k];
+        switch (S) {
+            case 1: stripe_sums<1>(p, n, C, u, s); break;
+            case 2: stripe_sums<2>(p, n, C, u, s); break;
+            case 4: stripe_sums<4>(p, n, C, u, s); break;
+            default: stripe_sums<8>(p, n, C, u, s); break;
+        }
     }
-#pragma unroll
-    for (int u = 0; u < 7; ++u)
-        if (c + u < C) s[u] += p[size_t(c + u) * n];
-    tb.out[k][i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    for (int q = 0; q < 8 / S; ++q) sm[u + S * q][e] = s[q];
+    __syncthreads();
+    if (int(threadIdx.x) < E && live) {
+        const int t = int(threadIdx.x);
+        tb.out[k][i] = ((sm[0][t] + sm[1][t]) + (sm[2][t] + sm[3][t])) + ((sm[4][t] + sm[5][t]) + (sm[6][t] + sm[7][t]));
+    }
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -1171,16 +1210,26 @@ fewha_status fewha_unet_backward(fewha_unet* net, const float* d_in, const float
     net->backward_all(d_target, total, s);
     // fixed-order reduction of every partial into the gradient vector (conv weights and bias
     // rows, then the head row [loss sum, gw[32], gb]), one launch
+    // the tensors with the most chunks (the longest workgroups) are dispatched first
+    int order[kConvs + 1];
+    for (int k = 0; k <= kConvs; ++k) order[k] = k;
+    auto chunks_of = [&](int k) { return k == kConvs ? net->hblocks : net->wchunks[k]; };
+    std::stable_sort(order, order + kConvs + 1, [&](int a, int b) { return chunks_of(a) > chunks_of(b); });
     ReduceTable tb{};
     int nb = 0;
-    for (int k = 0; k <= kConvs; ++k) {
+    for (int t = 0; t <= kConvs; ++t) {
+        const int k = order[t];
         const bool head = k == kConvs;
-        tb.part[k] = head ? net->hpart : net->wpart[k];
-        tb.out[k] = head ? net->hred : net->grad + net->w_off[k];
-        tb.n[k] = head ? kCh[0] + 2 : fewha_unet::grad_row(k);
-        tb.chunks[k] = head ? net->hblocks : net->wchunks[k];
-        tb.block0[k] = nb;
-        nb += int(blocks(tb.n[k]));
+        tb.part[t] = head ? net->hpart : net->wpart[k];
+        tb.out[t] = head ? net->hred : net->grad + net->w_off[k];
+        tb.n[t] = head ? kCh[0] + 2 : fewha_unet::grad_row(k);
+        tb.chunks[t] = chunks_of(k);
+        // at most 32 chunks per thread, at most eight threads per element
+        int S = 1;
+        while (S < 8 && tb.chunks[t] > 32 * S) S *= 2;
+        tb.stripes[t] = S;
+        tb.block0[t] = nb;
+        nb += int((tb.n[t] + kT / S - 1) / (kT / S));
     }
     tb.count = kConvs + 1;
     tb.block0[kConvs + 1] = nb;
