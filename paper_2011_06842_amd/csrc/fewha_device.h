@@ -26,6 +26,17 @@ __device__ __forceinline__ double dpp_row_shr(double v) {
     return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
+// v of the lane CTRL names (DPP row broadcast) in the rows ROWS selects (bit r: row r of 16
+// lanes), 0 in the other rows.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), CTRL, ROWS, 0xf, false));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf, false));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // Sum over the 64 lanes of a full wavefront, in every lane, in a fixed order: inclusive sums
 // within each row of 16 lanes by data-parallel row shifts of 1, 2, 4 and 8 (lane 15 of a row
 // then holds the row's sum), then (row0 + row1) + (row2 + row3).  No LDS traffic.

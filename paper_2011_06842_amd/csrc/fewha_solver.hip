@@ -351,6 +351,54 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
     if (wr) gpart[size_t(g.gbase) + size_t(m * (m + 1) + row * (m + 1) + col) * g.nb + g.local] = tile_sum();
 }
 
+// Sums of the Gram partials of one instance: entry e (< ne) of X is the sum of its ngb
+// block partials gp[e * ngb + j].  A row of 16 lanes takes one entry (each load of a wavefront
+// reads four 128-byte runs, one per row); wavefront wv takes 4 EB consecutive entries per pass,
+// entry e0 + 4 b + row.  Lane c of a row adds the partials j = c + 16 q in increasing j, QB of
+// them per round; the row's 16 sums are then added by DPP row shifts (lane 15 of the row ends
+// with the entry's sum).  Loads outside the partials are clamped and their values dropped.
+template <int EB, int QB>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ gp, int ngb, int ne, int wv, int lane,
+                                                double* __restrict__ X) {
+    constexpr int NWS = kSolveThreads / 64;
+    const int row = lane >> 4, c = lane & 15;
+    for (int e0 = wv * 4 * EB; e0 < ne; e0 += NWS * 4 * EB) {
+        double s[EB];
+#pragma unroll
+        for (int b = 0; b < EB; ++b) s[b] = 0.0;
+        for (int j0 = 0; j0 < ngb; j0 += 16 * QB) {
+            double v[EB][QB];
+#pragma unroll
+            for (int b = 0; b < EB; ++b)
+#pragma unroll
+                for (int q = 0; q < QB; ++q) {
+                    const int e = e0 + 4 * b + row, j = j0 + 16 * q + c;
+                    const bool ok = e < ne && j < ngb;
+                    v[b][q] = gp[ok ? size_t(e) * ngb + j : 0];
+                }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int b = 0; b < EB; ++b)
+#pragma unroll
+                for (int q = 0; q < QB; ++q)
+                    s[b] += (e0 + 4 * b + row < ne && j0 + 16 * q + c < ngb) ? v[b][q] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < EB; ++b) s[b] += dpp_row_shr<0x111>(s[b]);
+#pragma unroll
+        for (int b = 0; b < EB; ++b) s[b] += dpp_row_shr<0x112>(s[b]);
+#pragma unroll
+        for (int b = 0; b < EB; ++b) s[b] += dpp_row_shr<0x114>(s[b]);
+#pragma unroll
+        for (int b = 0; b < EB; ++b) s[b] += dpp_row_shr<0x118>(s[b]);
+        if (c == 15) {
+#pragma unroll
+            for (int b = 0; b < EB; ++b)
+                if (e0 + 4 * b + row < ne) X[e0 + 4 * b + row] = s[b];
+        }
+    }
+}
+
 // Reduce the Gram partials and solve for the Galerkin coefficients y (Sec. 4.1).
 // GALERKIN: G_ab = X_ab (a <= b, mirrored), Cholesky processing columns in order and dropping
 // column j when its pivot is <= 1e-14 max diag G; y = G^-1 U^T r.
@@ -368,29 +416,11 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     const double* __restrict__ gp = gpart + size_t(I.gb0) * ke;
     const int ngb = I.ngb;
     const int ne = 2 * m * (m + 1);
-    {   // 4 lanes per entry, 256 entries per pass; each lane sums its partials (sub, sub + 4, ...:
-        // the 4 lanes of an entry read 32 contiguous bytes per load) in chunks of 16 requested
-        // all at once
-        constexpr int LPE = 4, PER = 16;
-        const int sub = threadIdx.x & (LPE - 1);
-        for (int e0 = 0; e0 < ne; e0 += kSolveThreads / LPE) {
-            const int e = e0 + threadIdx.x / LPE;
-            double s = 0;
-            for (int j0 = 0; j0 < ngb; j0 += LPE * PER) {
-                double v[PER];
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped, zeroed by a factor)
-                    const int j = j0 + k * LPE + sub;
-                    const bool ok = e < ne && j < ngb;
-                    v[k] = gp[ok ? size_t(e) * ngb + j : 0] * (ok ? 1.0 : 0.0);
-                }
-#pragma unroll
-                for (int k = 0; k < PER; ++k) s += v[k];
-            }
-#pragma unroll
-            for (int o = LPE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, LPE);
-            if (sub == 0 && e < ne) X[e] = s;
-        }
+    {   // 32 loads per lane requested at once (16 where there are at most 16 partials)
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (ngb <= 16) reduce_partials<16, 1>(gp, ngb, ne, wv, lane, X);
+        else if (ngb <= 64) reduce_partials<8, 4>(gp, ngb, ne, wv, lane, X);
+        else reduce_partials<4, 8>(gp, ngb, ne, wv, lane, X);
     }
     if (threadIdx.x < m) gm[threadIdx.x] = sc->gam[sl.s[threadIdx.x]];
     __syncthreads();
