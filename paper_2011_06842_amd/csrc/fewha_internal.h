@@ -129,7 +129,7 @@ struct Layout {
     size_t layers, wfs, pairs, cellidx, frac, ranges, weight, prior_a, jinv;
     size_t insts, vecblk, gramblk, step_layers, data_tiles, gather_tiles, grecs, recbase, gwin;
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
-    size_t c, r, z, b, b_prev, s_in;
+    size_t c, r, z, b, b_prev;
     size_t ring_u, ring_q;
     size_t partials, pq_part, gram_part, scalars, info, done;
     size_t ws_in, ws_out, lconst;   // warm start: network input (N x 4 FP32), output (N FP32), layer constants

@@ -1121,11 +1121,13 @@ void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t
     launch_winvt<T>(c, psi_l, y, x, pq_part, s);
 }
 
+// slopes NULL: the weighted slope adjoint is already in the sensor-node buffer (the graphed
+// frame launches it outside the graph, on the caller's slopes).
 template <typename T>
 void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s) {
     T* psi_n = c.at<T>(c.lay.psi_nodes);
     T* psi_l = c.at<T>(c.lay.psi_layers);
-    launch_slopes_adj<T>(c, slopes, psi_n, 1, s);
+    if (slopes) launch_slopes_adj<T>(c, slopes, psi_n, 1, s);
     launch_adj_gather<T>(c, psi_n, psi_l, s);
     launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), nullptr, s);
 }

@@ -287,7 +287,6 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.z = take(e * N);
     lo.b = take(e * N);
     lo.b_prev = take(e * N);
-    lo.s_in = take(e * S);
     lo.ring_u = take(e * N * z.slots);
     lo.ring_q = take(e * N * z.slots);
     lo.partials = take(sizeof(double) * size_t(z.VB) * (2 * kKMax + 8));

@@ -1141,8 +1141,9 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
     if (c.rel_tol > 0) {
         e = run_frame<T>(c, slopes, info_user, s, &iters, [](const Frame<T>&) { return hipSuccess; });
     } else if (c.use_graphs && !c.prof.on) {
-        // the graph reads the slopes from, and writes the frame statistics to, context buffers
-        T* s_in = c.at<T>(c.lay.s_in);
+        // the slope adjoint runs outside the graph on the caller's slopes (the graph starts from
+        // the sensor-node buffer it fills); the graph writes the frame statistics to a context
+        // buffer
         fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
         const auto key = std::make_tuple(c.head, c.first ? 1 : 0, m);
         auto it = c.graphs.find(key);
@@ -1152,7 +1153,7 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
             hipGraphExec_t ge = nullptr;
             if (e == hipSuccess) e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                enqueue_frame<T>(c, s_in, nullptr, c.cap_stream);
+                enqueue_frame<T>(c, static_cast<const T*>(nullptr), nullptr, c.cap_stream);
                 e = hipStreamEndCapture(c.cap_stream, &g);
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -1160,7 +1161,8 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
             if (e != hipSuccess) return e;
             it = c.graphs.emplace(key, ge).first;
         }
-        e = hipMemcpyAsync(s_in, slopes, sizeof(T) * c.S, hipMemcpyDeviceToDevice, s);
+        launch_slopes_adj<T>(c, slopes, c.at<T>(c.lay.psi_nodes), 1, s);
+        e = hipGetLastError();
         if (e == hipSuccess) e = hipGraphLaunch(it->second, s);
         if (e == hipSuccess && (c_out || info_user)) {
             const int64_t nb = std::min<int64_t>((c.N + 4 * kThreads - 1) / (4 * kThreads), 4096);
