@@ -747,16 +747,15 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
 // Frame statistics (relative residual in FP64) of every instance (one workgroup each) into
 // the context's and the caller's info.  Tolerance mode: iters is the instance's first
 // iteration that met the tolerance (flag bit 1: not met within the frame).
-__global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
-                                                      int pstride, const double* __restrict__ part,
-                                                      fewha_solve_info* __restrict__ infos,
-                                                      fewha_solve_info* __restrict__ infos_user, int iters,
-                                                      int tol_mode) {
-    const InstDev I = insts[blockIdx.x];
-    const Seg sg{I.off, int(I.n), 0, I.nvb, int(blockIdx.x), I.vb0, I.pq0, I.npq};
-    Scalars* __restrict__ sc = scs + blockIdx.x;
-    fewha_solve_info* info = infos + blockIdx.x;
-    fewha_solve_info* info_user = infos_user ? infos_user + blockIdx.x : nullptr;
+__device__ __forceinline__ void finish_instance(int b, Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
+                                                int pstride, const double* __restrict__ part,
+                                                fewha_solve_info* __restrict__ infos,
+                                                fewha_solve_info* __restrict__ infos_user, int iters, int tol_mode) {
+    const InstDev I = insts[b];
+    const Seg sg{I.off, int(I.n), 0, I.nvb, b, I.vb0, I.pq0, I.npq};
+    Scalars* __restrict__ sc = scs + b;
+    fewha_solve_info* info = infos + b;
+    fewha_solve_info* info_user = infos_user ? infos_user + b : nullptr;
     double v[2];
     block_row_sums<2>(part, pstride, sg, P_BB, 2, v);   // rows P_BB, P_RR
     if (threadIdx.x == 0) {
@@ -771,6 +770,14 @@ __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, 
         *info = in;
         if (info_user) *info_user = in;
     }
+}
+
+__global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
+                                                      int pstride, const double* __restrict__ part,
+                                                      fewha_solve_info* __restrict__ infos,
+                                                      fewha_solve_info* __restrict__ infos_user, int iters,
+                                                      int tol_mode) {
+    finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, tol_mode);
 }
 
 // ------------------------------------------------------------------ warm start
@@ -883,15 +890,19 @@ __global__ void __launch_bounds__(kThreads) k_check(Scalars* __restrict__ scs, c
 // The frame's outputs to the caller in one launch after the graph: the coefficients
 // (c -> c_out, may be null) and, by the first workgroup, the per-instance statistics
 // (info -> info_user, may be null).
+// End of a graphed fixed-count frame, after the graph: workgroups b < B write instance b's
+// frame statistics (as k_finish), every workgroup copies its share of c to c_out (if given).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_frame_out(int64_t N, const T* __restrict__ c, T* __restrict__ c_out,
-                                                         int B, const fewha_solve_info* __restrict__ info,
-                                                         fewha_solve_info* __restrict__ info_user) {
+                                                         int B, Scalars* __restrict__ scs,
+                                                         const InstDev* __restrict__ insts, int pstride,
+                                                         const double* __restrict__ part,
+                                                         fewha_solve_info* __restrict__ infos,
+                                                         fewha_solve_info* __restrict__ infos_user, int iters) {
+    if (int(blockIdx.x) < B) finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, 0);
     if (c_out)
         for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
             c_out[i] = c[i];
-    if (blockIdx.x == 0 && info_user)
-        for (int b = threadIdx.x; b < B; b += kThreads) info_user[b] = info[b];
 }
 
 int bucket(int m) {
@@ -1075,12 +1086,12 @@ void enqueue_finish(const Ctx& c, const Frame<T>& f, int iters, fewha_solve_info
 
 // Enqueues one fixed-count frame on stream s (no host-state change, so it can be captured).
 template <typename T>
-void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s) {
+void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s, bool finish = true) {
     const Frame<T> f(c);
     enqueue_rhs_residual<T>(c, f, slopes, s);
     enqueue_galerkin_init<T>(c, f, s);
     for (int it = 0; it < c.max_iter; ++it) enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
-    enqueue_finish<T>(c, f, c.max_iter, info_user, s);
+    if (finish) enqueue_finish<T>(c, f, c.max_iter, info_user, s);
 }
 
 // Frame with direct launches: fixed count, or tolerance mode (the instances iterate in lock
@@ -1141,9 +1152,8 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
     if (c.rel_tol > 0) {
         e = run_frame<T>(c, slopes, info_user, s, &iters, [](const Frame<T>&) { return hipSuccess; });
     } else if (c.use_graphs && !c.prof.on) {
-        // the slope adjoint runs outside the graph on the caller's slopes (the graph starts from
-        // the sensor-node buffer it fills); the graph writes the frame statistics to a context
-        // buffer
+        // the slope adjoint runs before the graph on the caller's slopes (the graph starts from
+        // the sensor-node buffer it fills); the frame statistics and the copy of c follow it
         fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
         const auto key = std::make_tuple(c.head, c.first ? 1 : 0, m);
         auto it = c.graphs.find(key);
@@ -1153,7 +1163,7 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
             hipGraphExec_t ge = nullptr;
             if (e == hipSuccess) e = hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                enqueue_frame<T>(c, static_cast<const T*>(nullptr), nullptr, c.cap_stream);
+                enqueue_frame<T>(c, static_cast<const T*>(nullptr), nullptr, c.cap_stream, false);
                 e = hipStreamEndCapture(c.cap_stream, &g);
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -1164,9 +1174,12 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
         launch_slopes_adj<T>(c, slopes, c.at<T>(c.lay.psi_nodes), 1, s);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipGraphLaunch(it->second, s);
-        if (e == hipSuccess && (c_out || info_user)) {
-            const int64_t nb = std::min<int64_t>((c.N + 4 * kThreads - 1) / (4 * kThreads), 4096);
-            k_frame_out<T><<<unsigned(nb), kThreads, 0, s>>>(c.N, c.at<T>(c.lay.c), c_out, c.B, info, info_user);
+        if (e == hipSuccess) {   // frame statistics (the graph ends with the last iteration) and c_out
+            const Frame<T> f(c);
+            const int64_t ncopy = c_out ? std::min<int64_t>((c.N + 4 * kThreads - 1) / (4 * kThreads), 4096) : 0;
+            const int64_t nb = std::max<int64_t>(c.B, ncopy);
+            k_frame_out<T><<<unsigned(nb), kThreads, 0, s>>>(c.N, c.at<T>(c.lay.c), c_out, c.B, f.sc, f.insts,
+                                                             f.vl.pstride, f.part, info, info_user, c.max_iter);
             e = hipGetLastError();
         }
         return end_frame<T>(c, static_cast<T*>(nullptr), iters, e, s);
