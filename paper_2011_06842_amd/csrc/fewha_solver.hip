@@ -123,6 +123,8 @@ __device__ int wave_cholesky(const double* X, int ld, int m, double* Rout, int32
 }
 
 // y = G^-1 v with the factor above (dropped columns give y_j = 0); lane k passes v_k and gets y_k.
+// Lane k holds 1 / R[k][k] (0 for a dropped column), so that a step of either sweep is a
+// multiply and a broadcast (no division on the dependency chain).
 template <int MB>
 __device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, double v) {
     const int k = threadIdx.x & 63;
@@ -132,12 +134,12 @@ __device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, d
         col[i] = (i < m && k < m) ? R[i * m + k] : 0.0;   // R[i][k]
         row[i] = (i < m && k < m) ? R[k * m + i] : 0.0;   // R[k][i]
     }
+    const double inv = (k < m && keep[k]) ? 1.0 / R[k * m + k] : 0.0;
     // R^T t = v, column by column
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         if (j < m) {
-            const double rjj = lane_value(col[j], j);
-            const double tj = keep[j] ? lane_value(v, j) / rjj : 0.0;
+            const double tj = lane_value(inv != 0.0 ? v * inv : 0.0, j);
             if (k == j) v = tj;
             else if (k > j) v -= col[j] * tj;
         }
@@ -146,8 +148,7 @@ __device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, d
 #pragma unroll
     for (int j = MB - 1; j >= 0; --j) {
         if (j < m) {
-            const double rjj = lane_value(col[j], j);
-            const double yj = keep[j] ? lane_value(v, j) / rjj : 0.0;
+            const double yj = lane_value(inv != 0.0 ? v * inv : 0.0, j);
             if (k == j) v = yj;
             else if (k < j) v -= row[j] * yj;
         }
@@ -161,13 +162,13 @@ __device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, d
 template <int MB>
 __device__ double wave_forward_sub(const double* Mx, int ldr, int ldc, const double* diag, int m, double v) {
     const int k = threadIdx.x & 63;
+    // a recycled direction with (p, q) = 0 is the zero vector (stored by a frame whose residual
+    // was exactly zero): its coefficient is zero.  Lane k holds 1 / d_k (0 for such a direction).
+    const double inv = (k < m && diag[k] > 0) ? 1.0 / diag[k] : 0.0;
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         if (j < m) {
-            // a recycled direction with (p, q) = 0 is the zero vector (stored by a frame whose
-            // residual was exactly zero): its coefficient is zero
-            const double vj = lane_value(v, j);
-            const double xj = diag[j] > 0 ? vj / diag[j] : 0.0;
+            const double xj = lane_value(inv != 0.0 ? v * inv : 0.0, j);
             const double lkj = (k > j && k < m) ? Mx[k * ldr + j * ldc] : 0.0;
             if (k == j) v = xj;
             else if (k > j) v -= xj * lkj;
