@@ -39,7 +39,7 @@ def unflat(v):
     return out
 
 
-def setup_case(seed=0):
+def setup_case(seed=0, groups=GROUPS):
     rng = np.random.default_rng(seed)
     p = U.init_params(rng)
     for k in p:
@@ -47,7 +47,7 @@ def setup_case(seed=0):
             p[k] = (0.05 * rng.standard_normal(p[k].shape)).astype(np.float32).astype(np.float64)
     p["head.w"] = U.bf16(0.2 * rng.standard_normal(32))
     xs, ts = [], []
-    for n, s in GROUPS:
+    for n, s in groups:
         xs.append(rng.standard_normal((n, s, s, 4)).astype(np.float32))
         ts.append(rng.standard_normal((n, s, s)).astype(np.float32))
     return p, xs, ts
@@ -59,8 +59,8 @@ def oracle_inputs(x):
     return xi
 
 
-def gpu_net(p):
-    net = fw.UNetContext(GROUPS, lr=1e-3, device=DEV)
+def gpu_net(p, groups=GROUPS):
+    net = fw.UNetContext(groups, lr=1e-3, device=DEV)
     net.set_params(torch.from_numpy(flat(p).astype(np.float32)).to(DEV))
     return net
 
@@ -130,6 +130,22 @@ def test_backward_matches_oracle_per_parameter_group():
     bad = {k: (rel(g[k], gref[k]), noise[k]) for k in gref if rel(g[k], gref[k]) > 2 * noise[k] + 1e-3}
     assert not bad, bad
     assert rel(g["head.w"], gref["head.w"]) <= 1e-3 and rel(g["d0b.w"], gref["d0b.w"]) <= 1e-2
+
+
+def test_backward_with_many_chunk_partials_matches_oracle():
+    """Two 128^2 images: the weight gradients are summed from 512 (32-channel level), 128, 64 and
+    fewer chunk partials, so the fixed-order reduction spreads an entry's eight running sums over
+    eight, four, two and one threads; same bars as the test above."""
+    groups = [(2, 128)]
+    p, xs, ts = setup_case(5, groups)
+    net = gpu_net(p, groups)
+    loss = net.backward(dev_cat(xs), dev_cat(ts)).cpu().numpy()[0]
+    g = unflat(net.get_grads().cpu().numpy().astype(np.float64))
+    ref_loss, gref = _oracle_grads(p, xs, ts)
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    noise = _oracle_self_sensitivity(p, xs, ts, gref)
+    bad = {k: (rel(g[k], gref[k]), noise[k]) for k in gref if rel(g[k], gref[k]) > 2 * noise[k] + 1e-3}
+    assert not bad, bad
 
 
 def test_adam_step_matches_oracle_on_the_same_gradients():
