@@ -26,6 +26,7 @@ constexpr int kCoarseThreads = 1024;  // threads of the one-workgroup-per-layer 
 template <typename T> struct CoarseBlock { static constexpr int value = 64; };
 inline int coarse_block(int /*precision*/) { return 64; }
 constexpr int kST = 32;             // output tile side of a tiled synthesis step
+constexpr int kSmallTileBelow = 256; // synthesis tiles of kST / 2 when a step has fewer kST tiles
 constexpr int kAT = 16;             // coefficient tile side (per band) of a tiled analysis step
 constexpr int kGT = 32;             // layer-node tile columns of the adjoint gather
 constexpr int kGRowStep = kThreads / kGT;        // tile rows per gather thread row (8)

@@ -182,26 +182,27 @@ __global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* 
     }
 }
 
-// One synthesis level of block size nbs (> the coarse block) on the listed layers; 32x32
-// output tile per workgroup.  The LL band comes from the previous step (or from the
+// One synthesis level of block size nbs (> the coarse block) on the listed layers; ST x ST
+// output tile per workgroup (the tile size changes no output bit: each output takes the same
+// row and column passes).  The LL band comes from the previous step (or from the
 // coefficients when this is the layer's coarsest level); the final level writes phi / delta.
-template <typename T>
+template <typename T, int ST>
 __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restrict__ lays,
                                                          const int32_t* __restrict__ sl, int nbs,
                                                          Filt<T> f, const T* __restrict__ coef,
                                                          const T* __restrict__ ll_in, T* __restrict__ ll_out,
                                                          T* __restrict__ phi) {
-    constexpr int H = kST / 2 + 2;   // coefficient rows (per band) feeding one tile
+    constexpr int H = ST / 2 + 2;   // coefficient rows (per band) feeding one tile
     __shared__ T R[2 * H][2 * H + 1];
-    __shared__ T I[kST][2 * H + 1];
-    const int tx = nbs / kST, tiles = tx * tx;
+    __shared__ T I[ST][2 * H + 1];
+    const int tx = nbs / ST, tiles = tx * tx;
     const int bid = die_ordered_block();
     const int li = bid / tiles, tile = bid - li * tiles;
     const LayerDev d = lays[sl[li]];
     const int n = d.n;
     const int lev = ilog2i(n / nbs) + 1;
     const int M = nbs >> 1;
-    const int y0 = (tile / tx) * kST, x0 = (tile % tx) * kST;
+    const int y0 = (tile / tx) * ST, x0 = (tile % tx) * ST;
     const T* C = coef + d.off;
     const T* LL = (lev == d.levels ? coef : ll_in) + d.off;
     const int ky0 = (y0 >> 1) - 2, kx0 = (x0 >> 1) - 2;
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
     }
     __syncthreads();
     // row pass: output rows 2m and 2m + 1 read the same three coefficient rows of each band
-    for (int e = threadIdx.x; e < (kST / 2) * 2 * H; e += kThreads) {
+    for (int e = threadIdx.x; e < (ST / 2) * 2 * H; e += kThreads) {
         const int m = e / (2 * H), cc = e - m * (2 * H);
         T ev = 0, od = 0;
 #pragma unroll
@@ -248,8 +249,8 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
     __syncthreads();
     // column pass: the pair of outputs (2m, 2m + 1) of a row, stored together
     const T s = T(d.inv_delta);
-    for (int e = threadIdx.x; e < kST * (kST / 2); e += kThreads) {
-        const int yy = e / (kST / 2), m = e - yy * (kST / 2);
+    for (int e = threadIdx.x; e < ST * (ST / 2); e += kThreads) {
+        const int yy = e / (ST / 2), m = e - yy * (ST / 2);
         T ev = 0, od = 0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -1004,6 +1005,20 @@ hipError_t profiler_collect(const Ctx& c, hipStream_t s) {
 
 // ------------------------------------------------------------------ operator launchers
 
+// A synthesis step with kST x kST tiles, or with tiles of half that side when the large tiles
+// would give fewer workgroups than the GPU has compute units (a single small instance): the
+// step is then bound by the latency of each workgroup, and four times as many smaller tiles
+// finish sooner.
+template <typename T>
+void launch_idwt_step(const StepInfo& w, const LayerDev* lays, const int32_t* sl, const Filt<T>& f, const T* x,
+                      const T* ll_in, T* ll_out, T* phi, hipStream_t s) {
+    const int tiles = (w.nb / kST) * (w.nb / kST) * w.nl;
+    if (tiles < kSmallTileBelow)
+        k_idwt_step<T, kST / 2><<<4 * tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi);
+    else
+        k_idwt_step<T, kST><<<tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi);
+}
+
 template <typename T>
 void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
     const Filt<T> f = make_filt<T>();
@@ -1015,11 +1030,8 @@ void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
         k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], phi);
     }
     for (size_t j = 0; j < c.steps.size(); ++j) {
-        const StepInfo& w = c.steps[j];
-        const int tiles = (w.nb / kST) * (w.nb / kST);
         ProfScope ps_(c, KID_IDWT_STEP, s);
-        k_idwt_step<T><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, buf[j & 1], buf[(j + 1) & 1],
-                                                         phi);
+        launch_idwt_step<T>(c.steps[j], lays, sl, f, x, buf[j & 1], buf[(j + 1) & 1], phi, s);
     }
 }
 
@@ -1149,9 +1161,8 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
             break;
         case KID_IDWT_STEP: {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
-            const StepInfo& w = c.steps[step];
-            k_idwt_step<T><<<(w.nb / kST) * (w.nb / kST) * w.nl, kThreads, 0, s>>>(
-                lays, sl + w.loff, w.nb, f, x, buf[step & 1], buf[(step + 1) & 1], c.at<T>(c.lay.nodal));
+            launch_idwt_step<T>(c.steps[step], lays, sl, f, x, buf[step & 1], buf[(step + 1) & 1],
+                                c.at<T>(c.lay.nodal), s);
             break;
         }
         case KID_DATA_TERM:
