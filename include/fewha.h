@@ -31,6 +31,18 @@
  *    stream-ordered and asynchronous; argument errors are returned synchronously.  A
  *    context must be used from one stream at a time and is not thread-safe.
  *  - Errors: every call returns a fewha_status; fewha_last_error() gives a message.
+ *  - Breakdown (the paper runs a fixed iteration count and is silent on it): a projection
+ *    coefficient, step length or beta that is not finite, or a curvature (p, M p) <= 0 while
+ *    (r, J^-1 r) != 0, stops the frame's progress.  The carried coefficients and residual keep
+ *    their last finite values (they stay each other's residual pair), the directions the frame
+ *    stores from then on are zero vectors (given no weight by later projections), and info
+ *    flag bit 0 is set; the next frame continues from that state, with no reset needed.  A
+ *    frame whose right-hand side has a non-finite squared norm (non-finite or overflowing
+ *    slopes) is not solved at all (flag bits 0 and 3, relative residual NaN).  A later
+ *    fewha_solve_aug / fewha_solve_aug_ws call that finds such a frame finished returns
+ *    FEWHA_E_BREAKDOWN once for it (after enqueueing its own frame as usual).
+ *  - Validation: alpha >= 0; slope weights >= 0; a given prior_diag or precond_inv must be
+ *    finite and > 0 everywhere (FEWHA_E_INVAL otherwise).
  */
 #ifndef FEWHA_H
 #define FEWHA_H
@@ -56,7 +68,7 @@ typedef enum {
     FEWHA_E_NOMEM = 2,      /* workspace too small */
     FEWHA_E_HIP = 3,        /* a HIP runtime call failed */
     FEWHA_E_NOT_SPD = 4,    /* a diagonal entry of M is not positive */
-    FEWHA_E_BREAKDOWN = 5,  /* (p, q) <= 0 or a non-finite scalar was met in a solve */
+    FEWHA_E_BREAKDOWN = 5,  /* an earlier frame broke down (see fewha_solve_aug); this call's work was done */
     FEWHA_E_STATE = 6       /* state buffer does not belong to this configuration */
 } fewha_status;
 
@@ -121,9 +133,11 @@ typedef struct {
                                iteration whose residual met the tolerance */
     int32_t recycle_used;   /* recycled directions used for the projections */
     int32_t dropped;        /* Gram columns dropped as numerically dependent */
-    int32_t flags;          /* bit 0: breakdown ((p,q) <= 0 or non-finite scalar);
-                               bit 1: rel_tol not met within the frame */
-    double rel_res;         /* ||r|| / ||b|| at the end of the frame (FP64) */
+    int32_t flags;          /* bit 0: breakdown (non-finite value, or (p,q) <= 0 with (r, J^-1 r) != 0);
+                               bit 1: rel_tol not met within the frame;
+                               bit 2: warm start not taken (fewha_solve_aug_ws);
+                               bit 3: right-hand side not finite, the frame was not solved */
+    double rel_res;         /* ||r|| / ||b|| at the end of the frame (FP64); NaN with flag bit 3 */
 } fewha_solve_info;
 
 /* Device bytes the workspace of `cfg` needs. */
@@ -202,10 +216,12 @@ fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream);
 fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream);
 
 /* Frame execution mode.  Enabled (the default): the first frame of every recycle-ring phase is
- * captured once into a HIP graph on a private stream and later frames replay it on `stream`
- * (the slopes, coefficients and statistics pass through device-to-device copies outside the
- * graph, so the caller's pointers may change between frames).  Disabled: every kernel is
- * launched individually.  Both modes give bit-identical results. */
+ * captured once into a HIP graph on a private stream and later frames replay it on `stream`.
+ * The graph reads and writes only context memory: the weighted slope adjoint (the first
+ * kernel of a frame) is launched before the graph on the caller's slopes, and one kernel after
+ * it writes the frame statistics and copies c to the caller, so the caller's pointers may
+ * change between frames.  Tolerance-stopped frames (rel_tol > 0) always launch directly.
+ * Disabled: every kernel is launched individually.  Both modes give bit-identical results. */
 fewha_status fewha_use_graphs(fewha_ctx* ctx, int32_t enable);
 
 /* Diagnostic kernel profiler.  While enabled, every kernel launch of the compute calls is

@@ -101,6 +101,15 @@ typedef struct {
 fewha_status fewha_solve_aug_ws(fewha_ctx* ctx, fewha_unet* net, const fewha_warmstart* ws, const void* d_s,
                                 void* d_c, void* d_info, void* stream);
 
+/* The warm start's network input for the frame with slopes d_s (device, S) that follows the
+ * coefficients d_c (device, N): with r = b - M c (b the right-hand side of d_s), every layer
+ * node gets [W^-1 c / scale_c, W^-1 J^-1 r / scale_r, h_l / 20 km, gamma_l] (d_in: device,
+ * N x 4 FP32, 16-byte aligned; scale_out unused).  This is the input fewha_solve_aug_ws forms
+ * from its own residual; for collecting training samples.  ctx must hold a single instance.
+ * Uses the context's scratch vectors; the carried state is not touched. */
+fewha_status fewha_warmstart_input(fewha_ctx* ctx, const fewha_warmstart* ws, const void* d_c, const void* d_s,
+                                   float* d_in, void* stream);
+
 fewha_status fewha_unet_destroy(fewha_unet* net);
 const char* fewha_unet_last_error(const fewha_unet* net);
 

@@ -5,7 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 no code with it, and has no CPU fallback that routes through it.
 """
 from .fewha_oracle import (db3_filters, dwt1, idwt1, dwt2, idwt2, OracleSystem,
-                           AugmentedReconstructor, pcg, exact_solution)
+                           AugmentedReconstructor, pcg, aug_pcg, exact_solution, warm_start_inputs,
+                           warm_start_correction, warm_start_step)
 
 __all__ = ["db3_filters", "dwt1", "idwt1", "dwt2", "idwt2", "OracleSystem",
-           "AugmentedReconstructor", "pcg", "exact_solution"]
+           "AugmentedReconstructor", "pcg", "aug_pcg", "exact_solution", "warm_start_inputs",
+           "warm_start_correction", "warm_start_step"]

@@ -335,6 +335,17 @@ def _ratio(num, den):
     return num / den if den > 0 else 0.0
 
 
+def _step_ok(rz, pq):
+    """Whether the step length rz / pq of Alg. 1 / Alg. 2 can be taken.  A breakdown is a
+    non-finite value, or a non-positive curvature (p, M p) <= 0 while the preconditioned
+    residual (r, J^-1 r) is not zero; (p, M p) = 0 with a zero residual is exact convergence."""
+    if not (np.isfinite(rz) and np.isfinite(pq)):
+        return False
+    if pq > 0:
+        return bool(np.isfinite(rz / pq))
+    return pq == 0 and rz == 0
+
+
 def pcg(apply_M, b, c0, Jinv, max_iter, r0=None, callback=None):
     """Alg. 1 (PCG, split Jacobi preconditioner J^-1), exactly ``max_iter`` applies of M.
     Returns c, r and the list of (p_k, q_k, (p_k, q_k))."""
@@ -394,19 +405,29 @@ def _chol_solve(R, keep, v):
 def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_all=False,
             rel_tol=0.0, b_norm=None):
     """Alg. 2 (augmented PCG).  ``U``, ``Q``, ``gam``: the recycled directions p_j, q_j = M p_j
-    and (p_j, q_j), oldest first.  Returns c, r, the new directions and an info dict."""
+    and (p_j, q_j), oldest first.  Returns c, r, the new directions and an info dict.
+
+    Breakdown (the paper runs a fixed iteration count and says nothing of it): when a
+    projection coefficient, a step length or beta is not finite, or the curvature is not
+    positive (see :func:`_step_ok`), c and r keep their last finite values (they stay each
+    other's residual pair), the frame sets info flag bit 0, and every direction it stores from
+    then on is the zero direction (p, q, (p, q)) = (0, 0, 0), which later projections give no
+    weight."""
     c = np.array(c, dtype=np.float64, copy=True)
     r = np.array(r, dtype=np.float64, copy=True)
     m = len(U)
     dropped = 0
+    broken = False
     R = keep = None
     # Galerkin initial guess: c_0 += P_m D_m^-1 P_m^T r_0 so that U^T r_0 = 0 (Sec. 4.1)
     if m:
         if mode == "paper":
+            cg, rg = c, r
             for j in range(m):
-                sigma = _ratio(r @ U[j], gam[j])
-                c = c + sigma * U[j]
-                r = r - sigma * Q[j]
+                sigma = _ratio(rg @ U[j], gam[j])
+                cg = cg + sigma * U[j]
+                rg = rg - sigma * Q[j]
+                broken |= not np.isfinite(sigma)
         else:
             G = np.zeros((m, m))
             for i in range(m):
@@ -415,26 +436,43 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
             R, keep = _chol_drop(G)
             dropped = int(m - keep.sum())
             y = _chol_solve(R, keep, np.array([u @ r for u in U]))
+            broken |= not np.all(np.isfinite(y))
+            cg, rg = c, r
             for j in range(m):
-                c = c + y[j] * U[j]
-                r = r - y[j] * Q[j]
+                cg = cg + y[j] * U[j]
+                rg = rg - y[j] * Q[j]
+        if not broken:
+            c, r = cg, rg
     # initial direction, M-conjugate to the recycled directions (condition 1)
     z = Jinv * r
-    if m:
+    if m and not broken:
         if mode == "paper":
             for j in range(m):
-                z = z - _ratio(z @ Q[j], gam[j]) * U[j]
+                tau = _ratio(z @ Q[j], gam[j])
+                broken |= not np.isfinite(tau)
+                z = z - tau * U[j]
         else:
             y = _chol_solve(R, keep, np.array([qq @ z for qq in Q]))
+            broken |= not np.all(np.isfinite(y))
             for j in range(m):
                 z = z - y[j] * U[j]
     p = z
     rz = r @ z
     new = []
     it = 0
+    zero = np.zeros_like(r)
     for k in range(max_iter):
+        if broken:
+            new.append((zero, zero, 0.0))
+            it = k + 1
+            continue
         q = apply_M(p)
         pq = p @ q
+        if not _step_ok(rz, pq):
+            broken = True
+            new.append((zero, zero, 0.0))
+            it = k + 1
+            continue
         alpha = _ratio(rz, pq)
         c = c + alpha * p
         r = r - alpha * q
@@ -450,21 +488,74 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
                 y = _chol_solve(R, keep, np.array([qq @ z for qq in Q]))
                 for j in range(m):
                     z = z - y[j] * U[j]
+                rz_new = r @ z
             else:
                 mu = _ratio(z @ Q[-1], gam[-1])
                 z = z - mu * U[-1]
-        rz_new = r @ z
+                rz_new = r @ z
+        else:
+            rz_new = r @ z
         beta = _ratio(rz_new, rz)
+        if not np.isfinite(beta):
+            broken = True
+            continue
         p = z + beta * p
         rz = rz_new
-    info = {"iters": it, "recycle_used": m, "dropped": dropped,
+    info = {"iters": it, "recycle_used": m, "dropped": dropped, "flags": 1 if broken else 0,
             "rel_res": float("nan") if b_norm is None else float(np.sqrt(r @ r) / b_norm) if b_norm > 0 else 0.0}
     return c, r, new, info
 
 
+# ----------------------------------------------------------------------------------------
+# Learned warm start (an extension: the paper has no learned part).  Between the residual
+# update of Alg. 3 and the Galerkin step of Alg. 2 a network proposes a nodal correction d of
+# every layer; the frame moves along its coefficient form e = W d by the step that minimises
+# the energy 1/2 c^T M c - b^T c along e (what the PCG iterations minimise), and never uphill.
+# ----------------------------------------------------------------------------------------
+
+
+def warm_start_inputs(system, c, r, Jinv, scale_c, scale_r):
+    """Network inputs of every layer node, (N, 4): the previous coefficients and the
+    preconditioned new residual as nodal fields, W^-1 c / scale_c and W^-1 (J^-1 r) / scale_r,
+    then the layer's height / 20 km and its turbulence weight gamma_l."""
+    out = np.empty((system.N, 4))
+    out[:, 0] = np.concatenate([p.ravel() for p in system.W_inv(c)]) / scale_c
+    out[:, 1] = np.concatenate([p.ravel() for p in system.W_inv(Jinv * r)]) / scale_r
+    for l, lay in enumerate(system.layers):
+        sl = slice(system.coff[l], system.coff[l + 1])
+        out[sl, 2] = lay.height / 20000.0
+        out[sl, 3] = lay.weight
+    return out
+
+
+def warm_start_correction(system, d):
+    """Coefficient vector e = W d of a nodal correction d (N, layers concatenated).  W is the
+    inverse of W^-1 = DWT^T / delta_l; DWT being orthonormal, W = delta_l DWT = delta_l^2 W^-T."""
+    return np.concatenate([(dwt2(dl, lay.levels) * lay.spacing).ravel()
+                           for dl, lay in zip(system.split_layers(np.asarray(d, dtype=np.float64)),
+                                              system.layers)])
+
+
+def warm_start_step(apply_M, c, r, e):
+    """Exact line search of the energy along e from c, never uphill:
+    tau = (e, r) / (e, M e) when both are positive, else 0; returns c + tau e, r - tau M e, tau."""
+    Me = apply_M(e)
+    er, eMe = float(e @ r), float(e @ Me)
+    tau = er / eMe if (eMe > 0 and er > 0) else 0.0
+    if tau > 0:
+        return c + tau * e, r - tau * Me, tau
+    return np.array(c, copy=True), np.array(r, copy=True), 0.0
+
+
 class AugmentedReconstructor:
     """Alg. 3 steps RHS -> residual update -> augmented PCG for consecutive frames.  The
-    first frame (and the first after :meth:`reset`) runs Alg. 1 from ``r = b - M c``."""
+    first frame (and the first after :meth:`reset`) runs Alg. 1 from ``r = b - M c``.
+
+    A frame whose right-hand side has a non-finite squared norm (non-finite or overflowing
+    slopes; the paper is silent) is not solved: c, r and the previous right-hand side keep
+    their values (after a first frame r becomes b_prev - M c, so that the next frame's residual
+    update gives b - M c), the frame stores ``max_iter`` zero directions, and info reports
+    flags bits 0 and 3, ``max_iter`` iterations and a NaN relative residual."""
 
     def __init__(self, system: OracleSystem, Jinv=None, max_iter=None, k=None, mode=None,
                  project_all=None, rel_tol=None):
@@ -490,26 +581,51 @@ class AugmentedReconstructor:
         self.store = []
         self.first = True
 
-    def solve(self, s):
+    def _keep(self, new):
+        if self.mode == "paper":
+            self.store = new[-self.k:] if self.k > 0 else []
+        else:
+            self.store = (self.store + new)[-self.k:] if self.k > 0 else []
+
+    def solve(self, s, correction=None, scales=(1.0, 1.0, 1.0)):
+        """One frame for slopes s.  ``correction`` (warm start, optional): a callable mapping
+        the network inputs (see :func:`warm_start_inputs`, with ``scales`` = (scale_c, scale_r,
+        scale_out)) to a normalised nodal correction; the frame takes the line-search step
+        along W (scale_out d) after the residual update (info key "tau")."""
         b = self.sys.rhs(s)
-        b_norm = float(np.sqrt(b @ b))
+        bb = float(b @ b)
+        if not np.isfinite(bb):
+            zero = np.zeros(self.sys.N)
+            if self.first:
+                self.r = self.b_prev - self.apply_M(self.c)
+            used = 0 if self.first else min(self.k, len(self.store))
+            self._keep([(zero, zero, 0.0)] * self.max_iter)
+            self.first = False
+            return self.c.copy(), {"iters": self.max_iter, "recycle_used": used, "dropped": 0, "flags": 9,
+                                   "rel_res": float("nan")}
+        b_norm = float(np.sqrt(bb))
         if self.first:
             r = b - self.apply_M(self.c)
             used = []
         else:
             r = (b - self.b_prev) + self.r          # Alg. 3 residual update
             used = self.store[-self.k:] if self.k > 0 else []
+        c0 = self.c
+        tau = None
+        if correction is not None:
+            sc, sr, so = scales
+            d = so * np.asarray(correction(warm_start_inputs(self.sys, c0, r, self.Jinv, sc, sr)), dtype=np.float64)
+            c0, r, tau = warm_start_step(self.apply_M, c0, r, warm_start_correction(self.sys, d))
         U = [u for u, _, _ in used]
         Q = [q for _, q, _ in used]
         gam = [g for _, _, g in used]
-        c, r, new, info = aug_pcg(self.apply_M, self.c, r, self.Jinv, U, Q, gam, self.max_iter,
+        c, r, new, info = aug_pcg(self.apply_M, c0, r, self.Jinv, U, Q, gam, self.max_iter,
                                   self.mode, self.project_all, self.rel_tol, b_norm)
-        if self.mode == "paper":
-            self.store = new[-self.k:] if self.k > 0 else []
-        else:
-            self.store = (self.store + new)[-self.k:] if self.k > 0 else []
+        self._keep(new)
         self.c, self.r, self.b_prev = c, r, b
         self.first = False
+        if tau is not None:
+            info["tau"] = tau
         return c, info
 
 

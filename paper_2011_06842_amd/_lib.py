@@ -15,6 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfewha.so")
 
 FEWHA_ABI_VERSION = 1
+FEWHA_E_BREAKDOWN = 5
+FLAG_BREAKDOWN, FLAG_TOL_UNMET, FLAG_WS_REJECTED, FLAG_BAD_RHS = 1, 2, 4, 8
 FEWHA_FP64, FEWHA_FP32_OP_FP64_RED = 0, 1
 FEWHA_RECYCLE_PAPER, FEWHA_RECYCLE_GALERKIN = 0, 1
 PIECE_WINV, PIECE_WINVT, PIECE_A, PIECE_AT = 0, 1, 2, 3
@@ -29,7 +31,7 @@ EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", 
            "fewha_unet_workspace_size", "fewha_unet_setup", "fewha_unet_num_params", "fewha_unet_num_nodes",
            "fewha_unet_set_params", "fewha_unet_get_params", "fewha_unet_forward", "fewha_unet_backward",
            "fewha_unet_adam_step", "fewha_unet_get_grads", "fewha_unet_destroy", "fewha_unet_last_error",
-           "fewha_unet_groups", "fewha_solve_aug_ws"]
+           "fewha_unet_groups", "fewha_solve_aug_ws", "fewha_warmstart_input"]
 UNET_MAX_GROUPS = 8
 
 
@@ -123,6 +125,7 @@ def load_library(path: str = LIB_PATH):
         "fewha_unet_last_error": ([vp], C.c_char_p),
         "fewha_unet_groups": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
         "fewha_solve_aug_ws": ([vp, vp, C.POINTER(fewha_warmstart), vp, vp, vp, vp], st),
+        "fewha_warmstart_input": ([vp, C.POINTER(fewha_warmstart), vp, vp, vp, vp], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +253,7 @@ class FewhaContext:
         self.B = cnt.value
         self.coeff_offsets = [co[i] for i in range(nb + 1)]
         self.slope_offsets = [so[i] for i in range(nb + 1)]
+        self.breakdown_reports = []   # messages of FEWHA_E_BREAKDOWN returned by frame calls
 
     # -- helpers
     def _vec(self, n):
@@ -281,8 +285,16 @@ class FewhaContext:
         s = self._in(s, self.S)
         c = self._vec(self.N) if c is None else self._in(c, self.N)
         ip = _ptr(info) if info is not None else None
-        _check(self.lib.fewha_solve_aug(self.ctx, _ptr(s), _ptr(c), ip, _stream(stream)), self.ctx)
+        self._frame_status(self.lib.fewha_solve_aug(self.ctx, _ptr(s), _ptr(c), ip, _stream(stream)))
         return c
+
+    def _frame_status(self, st):
+        """FEWHA_E_BREAKDOWN from a frame call reports an earlier frame's breakdown (this call's
+        frame was enqueued): it is recorded in `breakdown_reports`, not raised."""
+        if st == FEWHA_E_BREAKDOWN:
+            self.breakdown_reports.append(self.lib.fewha_last_error(self.ctx).decode())
+        else:
+            _check(st, self.ctx)
 
     def fewha_solve_aug_ws(self, net, scales, s, c=None, info=None, stream=None):
         """One frame warm-started by the U-Net `net` (UNetContext); scales = (scale_c,
@@ -291,9 +303,22 @@ class FewhaContext:
         c = self._vec(self.N) if c is None else self._in(c, self.N)
         ws = fewha_warmstart(*[float(v) for v in scales])
         ip = _ptr(info) if info is not None else None
-        _check(self.lib.fewha_solve_aug_ws(self.ctx, net.net, C.byref(ws), _ptr(s), _ptr(c), ip, _stream(stream)),
-               self.ctx)
+        self._frame_status(self.lib.fewha_solve_aug_ws(self.ctx, net.net, C.byref(ws), _ptr(s), _ptr(c), ip,
+                                                        _stream(stream)))
         return c
+
+    def fewha_warmstart_input(self, scales, c, s, out=None, stream=None):
+        """Network input (N, 4) FP32 device tensor of the warm start for slopes `s` after
+        coefficients `c` (see include/fewha_unet.h); scales = (scale_c, scale_r[, scale_out])."""
+        import torch
+        c = self._in(c, self.N)
+        s = self._in(s, self.S)
+        out = torch.empty((self.N, 4), dtype=torch.float32, device=self.device) if out is None else out
+        sc = list(scales) + [1.0] * (3 - len(scales))
+        ws = fewha_warmstart(*[float(v) for v in sc])
+        _check(self.lib.fewha_warmstart_input(self.ctx, C.byref(ws), _ptr(c), _ptr(s), _ptr(out), _stream(stream)),
+               self.ctx)
+        return out
 
     def fewha_frame_iterations(self) -> int:
         n = C.c_int32()

@@ -12,11 +12,6 @@
 #include "fewha_internal.h"
 #include "../../include/fewha_unet.h"
 
-struct fewha_ctx {
-    fewha::Ctx c;
-    uint64_t state_header[32];   // host copy of the checkpoint header (kept alive for async H2D)
-};
-
 namespace {
 
 thread_local std::string g_setup_err;
@@ -26,6 +21,7 @@ fewha_status fail(fewha_ctx* ctx, fewha_status st, const std::string& msg) {
     if (ctx) ctx->c.err = msg;
     return st;
 }
+
 
 fewha_status check_launch(fewha_ctx* ctx, hipStream_t s) {
     const hipError_t e = hipGetLastError();
@@ -38,6 +34,21 @@ fewha_status check_launch(fewha_ctx* ctx, hipStream_t s) {
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Status of a frame call whose frame was enqueued: FEWHA_E_BREAKDOWN once for every frame of
+// the context found broken down (the end of such a frame writes its number into the pinned
+// report word; a frame still running is reported by a later call), else FEWHA_OK.
+fewha_status solve_status(fewha_ctx* ctx) {
+    fewha::Ctx& c = ctx->c;
+    const int64_t seen = *reinterpret_cast<volatile int64_t*>(c.brk_host);
+    if (seen > c.brk_reported) {
+        c.brk_reported = seen;
+        return fail(ctx, FEWHA_E_BREAKDOWN,
+                    "frame " + std::to_string(seen) + " of this context broke down (its info flags tell how); "
+                    "the carried state kept its last finite values and this call's frame was enqueued");
+    }
+    return FEWHA_OK;
+}
 
 }  // namespace
 
@@ -105,6 +116,18 @@ fewha_status fewha_setup_batch(const fewha_config* cfgs, int32_t n, void* d_work
         delete ctx;
         return st;
     }
+    // the breakdown report word (pinned host memory the device writes; see solve_status)
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, 256, hipHostMallocMapped) != hipSuccess || hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        if (h) (void)hipHostFree(h);
+        g_setup_err = "hipHostMalloc of the breakdown report word failed";
+        delete ctx;
+        return FEWHA_E_HIP;
+    }
+    std::memset(h, 0, 256);
+    c.brk_host = static_cast<int64_t*>(h);
+    c.brk_dev = static_cast<int64_t*>(d);
     *out = ctx;
     return FEWHA_OK;
 }
@@ -167,7 +190,8 @@ fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d
         e = fewha::launch_solve_frame<float>(c, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
                                              as_stream(stream));
     if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("frame launch failed: ") + hipGetErrorString(e));
-    return check_launch(ctx, as_stream(stream));
+    const fewha_status st = check_launch(ctx, as_stream(stream));
+    return st != FEWHA_OK ? st : solve_status(ctx);
 }
 
 fewha_status fewha_solve_aug_ws(fewha_ctx* ctx, fewha_unet* net, const fewha_warmstart* ws, const void* d_s,
@@ -195,6 +219,27 @@ fewha_status fewha_solve_aug_ws(fewha_ctx* ctx, fewha_unet* net, const fewha_war
         e = fewha::launch_solve_frame_ws<float>(c, w, static_cast<const float*>(d_s), static_cast<float*>(d_c), info,
                                                 as_stream(stream));
     if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("frame launch failed: ") + hipGetErrorString(e));
+    const fewha_status st = check_launch(ctx, as_stream(stream));
+    return st != FEWHA_OK ? st : solve_status(ctx);
+}
+
+fewha_status fewha_warmstart_input(fewha_ctx* ctx, const fewha_warmstart* ws, const void* d_c, const void* d_s,
+                                   float* d_in, void* stream) {
+    if (!ctx || !ws || !d_c || !d_s || !d_in) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
+    const fewha::Ctx& c = ctx->c;
+    if (c.B != 1) return fail(ctx, FEWHA_E_INVAL, "the warm start needs a single-instance context");
+    if (!(ws->scale_c > 0) || !(ws->scale_r > 0) || !std::isfinite(ws->scale_c) || !std::isfinite(ws->scale_r))
+        return fail(ctx, FEWHA_E_INVAL, "bad warm-start scales");
+    if (reinterpret_cast<uintptr_t>(d_in) & 15) return fail(ctx, FEWHA_E_INVAL, "d_in must be 16-byte aligned");
+    const fewha::WarmStart w{nullptr, ws->scale_c, ws->scale_r, ws->scale_out};
+    hipError_t e;
+    if (c.prec == FEWHA_FP64)
+        e = fewha::launch_ws_input<double>(c, w, static_cast<const double*>(d_c), static_cast<const double*>(d_s), d_in,
+                                           as_stream(stream));
+    else
+        e = fewha::launch_ws_input<float>(c, w, static_cast<const float*>(d_c), static_cast<const float*>(d_s), d_in,
+                                          as_stream(stream));
+    if (e != hipSuccess) return fail(ctx, FEWHA_E_HIP, std::string("launch failed: ") + hipGetErrorString(e));
     return check_launch(ctx, as_stream(stream));
 }
 
@@ -394,6 +439,7 @@ fewha_status fewha_destroy(fewha_ctx* ctx) {
     if (ctx) {
         for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
         fewha::release_graphs(ctx->c);
+        if (ctx->c.brk_host) (void)hipHostFree(ctx->c.brk_host);
     }
     delete ctx;
     return FEWHA_OK;

@@ -111,6 +111,12 @@ struct GramBlk {
 template <typename T>
 struct Filt { T h[6], g[6]; };
 
+// Bits of fewha_solve_info.flags (and of Scalars::flags during a frame).
+constexpr int32_t kFlagBreakdown = 1;   // a non-finite value or non-positive curvature; c, r kept
+constexpr int32_t kFlagTolUnmet = 2;    // tolerance mode: not met within the frame
+constexpr int32_t kFlagWsRejected = 4;  // warm start: the correction was not taken
+constexpr int32_t kFlagBadRhs = 8;      // (b, b) not finite: the frame was not solved
+
 // Scalars of one instance's solve, in device memory (never copied to the host inside a frame).
 struct Scalars {
     double rzb[2];        // (r, z) of the current iteration, double-buffered by iteration parity
@@ -123,6 +129,7 @@ struct Scalars {
     int32_t flags, dropped, used, iters;
     int32_t conv_iter;    // tolerance mode: first iteration whose residual met the tolerance (0: not yet)
     int32_t ws_state;     // warm start of this frame: 0 none, 1 accepted, 2 rejected
+    int64_t frame_no;     // frames finished since setup (the breakdown report names a frame by it)
 };
 
 // Byte layout of the workspace (offsets from its base).
@@ -192,6 +199,11 @@ struct Ctx {
     // host-side ring bookkeeping (fixed iteration count: the device never decides)
     int head = 0, count = 0, last_iters = 0;
     bool first = true;
+    // breakdown report: pinned, device-mapped host word into which the end of a frame writes
+    // its frame number when an instance broke down; the host reports each new value once
+    int64_t* brk_host = nullptr;
+    int64_t* brk_dev = nullptr;
+    int64_t brk_reported = 0;
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -204,6 +216,17 @@ struct Ctx {
     std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
     template <typename P> P* at(size_t off) const { return reinterpret_cast<P*>(ws + off); }
 };
+
+// Intermediates of one operator application: the nodal image, the two wavelet ping-pong
+// buffers (N elements each), the sensor-node field (V) and the layer adjoint field (N).  The
+// context's own live in its workspace; fewha_apply_A_noalloc brings its own.
+struct OpBufs {
+    char *nodal, *tmp0, *tmp1, *psi_nodes, *psi_layers;
+};
+inline OpBufs ctx_bufs(const Ctx& c) {
+    return OpBufs{c.ws + c.lay.nodal, c.ws + c.lay.tmp0, c.ws + c.lay.tmp1, c.ws + c.lay.psi_nodes,
+                  c.ws + c.lay.psi_layers};
+}
 
 // Records HIP events around one kernel launch on `s` when profiling is enabled.
 struct ProfScope {
@@ -220,15 +243,18 @@ Layout compute_layout(const fewha_config* cfgs, int n);
 fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int n, hipStream_t stream);
 
 // Launchers (fewha_kernels.hip)
-template <typename T> void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s);
+template <typename T> void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* ob = nullptr);
 template <typename T> void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part,
-                                        hipStream_t s);
+                                        hipStream_t s, const OpBufs* ob = nullptr);
 template <typename T> void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s);
 template <typename T> void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted, hipStream_t s);
 template <typename T> void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s);
 template <typename T> void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s);
-template <typename T> void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s);
-template <typename T> void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s);
+template <typename T> void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s,
+                                          const OpBufs* ob = nullptr);
+
+template <typename T> void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s,
+                                      double* bb_part = nullptr);
 template <typename T> hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_info* info,
                                                    hipStream_t s);
 // Warm start of a frame by the U-Net (include/fewha_unet.h): input/output scales.
@@ -238,7 +264,15 @@ struct WarmStart {
 };
 template <typename T> hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& w, const T* slopes, T* c_out,
                                                       fewha_solve_info* info, hipStream_t s);
+template <typename T> hipError_t launch_ws_input(const Ctx& c, const WarmStart& w, const T* c_in, const T* slopes,
+                                                 float* in, hipStream_t s);
 void release_graphs(Ctx& c);
 template <typename T> hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t s, float* ms);
 
 }  // namespace fewha
+
+// The opaque context of the C ABI.
+struct fewha_ctx {
+    fewha::Ctx c;
+    uint64_t state_header[32];   // host copy of the checkpoint header (kept alive for async H2D)
+};

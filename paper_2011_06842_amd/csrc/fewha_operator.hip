@@ -271,17 +271,19 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
 
 // One analysis level of block size nbs on the listed layers: 16x16 coefficients of every band
 // per tile, rows then columns from a 36x36 halo, a_k = sum_t h_t x_{(2k+t) mod nbs}.  Final
-// coefficients are scaled by 1/delta and (PRIOR) get + (alpha D)_i x_i, and the partial of
-// (x, out) over them goes to the tile's slot among the layer's partials (tiles of finer
-// levels first).  The prior and x operands are requested before the halo so that their
-// latency overlaps it.
-template <typename T, bool PRIOR>
+// coefficients are scaled by 1/delta.  MODE 1 (inside M x): they get + (alpha D)_i x_i, and the
+// partial of (x, out) over them goes to the tile's slot among the layer's partials (tiles of
+// finer levels first).  MODE 2 (the right-hand side of a frame): the partial of (out, out)
+// goes there instead (its sum tells the frame whether b is finite).  The prior and x operands
+// are requested before the halo so that their latency overlaps it.
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restrict__ lays,
                                                         const int32_t* __restrict__ sl, int nbs,
                                                         Filt<T> f, const T* __restrict__ img,
                                                         const T* __restrict__ ll_in, T* __restrict__ ll_out,
                                                         T* __restrict__ out, const T* __restrict__ prior_a,
                                                         const T* __restrict__ xprior, double* __restrict__ dotpart) {
+    constexpr bool PRIOR = MODE == 1;
     constexpr int W = 2 * kAT + 4;
     __shared__ T R[W][W + 1];
     __shared__ T I[W][2 * kAT + 1];
@@ -362,10 +364,10 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
         T val = v[k] * s;
         if (PRIOR) val += pa[k] * xp[k];
         out[o[k]] = val;
-        dot += double(val) * double(xp[k]);   // (x, M x) partial: x is the prior operand
+        dot += double(val) * (MODE == 2 ? double(val) : double(xp[k]));   // (x, M x) or (b, b)
     }
     if (!fin_ll) ll_out[o[3]] = ll;
-    if (PRIOR && dotpart) {
+    if (MODE != 0 && dotpart) {
         int slot = d.pq0 + tile;
         for (int j = 1; j < lev; ++j) {
             const int mt = (n >> j) / kAT;
@@ -379,12 +381,13 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
 // Levels coarse_lev..levels of one layer in LDS (mirror of k_idwt_coarse).  After the last
 // level the block holds the whole coarse Mallat pyramid; it is written once, each thread
 // owning fixed positions whose prior and x operands it requested at kernel start.
-template <typename T, bool PRIOR>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
                                                                 const T* __restrict__ img, const T* __restrict__ ll_in,
                                                                 T* __restrict__ out, const T* __restrict__ prior_a,
                                                                 const T* __restrict__ xprior,
                                                                 double* __restrict__ dotpart) {
+    constexpr bool PRIOR = MODE == 1;
     constexpr int CB = CoarseBlock<T>::value;
     __shared__ T A[CB * CB];
     __shared__ T B[CB * CB];
@@ -463,13 +466,13 @@ __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* _
                 for (int j = 0; j < VC::n; ++j) {
                     val[j] = A[r * CB + c + j] * s;
                     if (PRIOR) val[j] += a[j] * x[j];
-                    dot += double(val[j]) * double(x[j]);
+                    dot += double(val[j]) * (MODE == 2 ? double(val[j]) : double(x[j]));
                 }
                 VC::store(out + size_t(d.off) + size_t(r) * n + c, val);
             }
         }
     }
-    if (PRIOR && dotpart) {
+    if (MODE != 0 && dotpart) {
         __shared__ double sh[kCoarseThreads / 64];
         const double w = wave_sum(dot);
         if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
@@ -653,11 +656,14 @@ __global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restric
     const int ns = W.ns, np = ns + 1;
     const int loc = int(e - W.noff);
     const int i = loc / np, j = loc % np;
-    auto t = [&](int comp, int si, int sj) -> T {   // unconditional loads (clamped), zeroed by a factor
+    // unconditional loads (clamped index); slopes outside the sensor or of an inactive
+    // subaperture (weight 0) are dropped by a select, so that even a non-finite value there is
+    // ignored, as the operator ignores inactive subapertures
+    auto t = [&](int comp, int si, int sj) -> T {
         const bool ok = si >= 0 && si < ns && sj >= 0 && sj < ns;
         const int64_t o = W.soff + int64_t(comp) * ns * ns + (ok ? si * ns + sj : 0);
         const T ww = w[o], sv = s[o];
-        return (weighted ? ww * sv : sv * T(ww != T(0))) * T(ok);
+        return ok && ww != T(0) ? (weighted ? ww * sv : sv) : T(0);
     };
     psi[e] = T(0.5) * ((t(0, i, j - 1) - t(0, i, j)) + (t(0, i - 1, j - 1) - t(0, i - 1, j))) +
              T(0.5) * ((t(1, i - 1, j) - t(1, i, j)) + (t(1, i - 1, j - 1) - t(1, i, j - 1)));
@@ -1020,9 +1026,10 @@ void launch_idwt_step(const StepInfo& w, const LayerDev* lays, const int32_t* sl
 }
 
 template <typename T>
-void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
+void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* ob) {
     const Filt<T> f = make_filt<T>();
-    T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
+    const OpBufs bb = ob ? *ob : ctx_bufs(c);
+    T* buf[2] = {reinterpret_cast<T*>(bb.tmp0), reinterpret_cast<T*>(bb.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
     const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
     {
@@ -1036,29 +1043,36 @@ void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s) {
 }
 
 template <typename T>
-void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part, hipStream_t s) {
+void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part, hipStream_t s,
+                  const OpBufs* ob) {
     const Filt<T> f = make_filt<T>();
-    T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
+    const OpBufs bb = ob ? *ob : ctx_bufs(c);
+    T* buf[2] = {reinterpret_cast<T*>(bb.tmp0), reinterpret_cast<T*>(bb.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
     const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
     const T* pa = c.at<T>(c.lay.prior_a);
     const int J = int(c.steps.size());
+    // with xprior: + alpha D x and the (x, y) partials; without it but with pq_part: (y, y)
+    const int mode = xprior ? 1 : (pq_part ? 2 : 0);
     for (int j = 0; j < J; ++j) {                 // largest block first
         const StepInfo& w = c.steps[J - 1 - j];
         const int tiles = (w.nb / 2 / kAT) * (w.nb / 2 / kAT);
         ProfScope ps_(c, KID_DWT_STEP, s);
-        if (xprior)
-            k_dwt_step<T, true><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1],
-                                                                  buf[j & 1], y, pa, xprior, pq_part);
-        else
-            k_dwt_step<T, false><<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1],
-                                                                   buf[j & 1], y, pa, xprior, nullptr);
+        auto go = [&](auto kern) {
+            kern<<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y, pa,
+                                                   xprior, pq_part);
+        };
+        if (mode == 1) go(k_dwt_step<T, 1>);
+        else if (mode == 2) go(k_dwt_step<T, 2>);
+        else go(k_dwt_step<T, 0>);
     }
     ProfScope ps_(c, KID_DWT_COARSE, s);
-    if (xprior)
-        k_dwt_coarse<T, true><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, pq_part);
-    else
-        k_dwt_coarse<T, false><<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, nullptr);
+    auto go = [&](auto kern) {
+        kern<<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, pq_part);
+    };
+    if (mode == 1) go(k_dwt_coarse<T, 1>);
+    else if (mode == 2) go(k_dwt_coarse<T, 2>);
+    else go(k_dwt_coarse<T, 0>);
 }
 
 template <typename T>
@@ -1123,25 +1137,27 @@ void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s) {
 }
 
 template <typename T>
-void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s) {
-    T* phi = c.at<T>(c.lay.nodal);
-    T* psi_n = c.at<T>(c.lay.psi_nodes);
-    T* psi_l = c.at<T>(c.lay.psi_layers);
-    launch_winv<T>(c, x, phi, s);
+void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s, const OpBufs* ob) {
+    const OpBufs bb = ob ? *ob : ctx_bufs(c);
+    T* phi = reinterpret_cast<T*>(bb.nodal);
+    T* psi_n = reinterpret_cast<T*>(bb.psi_nodes);
+    T* psi_l = reinterpret_cast<T*>(bb.psi_layers);
+    launch_winv<T>(c, x, phi, s, &bb);
     launch_data_term<T>(c, phi, psi_n, s);
     launch_adj_gather<T>(c, psi_n, psi_l, s);
-    launch_winvt<T>(c, psi_l, y, x, pq_part, s);
+    launch_winvt<T>(c, psi_l, y, x, pq_part, s, &bb);
 }
 
 // slopes NULL: the weighted slope adjoint is already in the sensor-node buffer (the graphed
-// frame launches it outside the graph, on the caller's slopes).
+// frame launches it outside the graph, on the caller's slopes).  bb_part (may be NULL): the
+// analysis tiles' partials of (b, b), in the slots of the (p, q) partials.
 template <typename T>
-void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s) {
+void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s, double* bb_part) {
     T* psi_n = c.at<T>(c.lay.psi_nodes);
     T* psi_l = c.at<T>(c.lay.psi_layers);
     if (slopes) launch_slopes_adj<T>(c, slopes, psi_n, 1, s);
     launch_adj_gather<T>(c, psi_n, psi_l, s);
-    launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), nullptr, s);
+    launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), bb_part, s);
 }
 
 // Launches one operator kernel with the arguments it has inside M x (input: the coefficient
@@ -1175,13 +1191,13 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
             const StepInfo& w = c.steps[step];
             const int j = J - 1 - step;
-            k_dwt_step<T, true><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * w.nl, kThreads, 0, s>>>(
+            k_dwt_step<T, 1><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * w.nl, kThreads, 0, s>>>(
                 lays, sl + w.loff, w.nb, f, c.at<T>(c.lay.psi_layers), buf[(j + 1) & 1], buf[j & 1], y,
                 c.at<T>(c.lay.prior_a), x, c.at<double>(c.lay.pq_part));
             break;
         }
         case KID_DWT_COARSE:
-            k_dwt_coarse<T, true><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J - 1) & 1],
+            k_dwt_coarse<T, 1><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J - 1) & 1],
                                                                  y, c.at<T>(c.lay.prior_a), x,
                                                                  c.at<double>(c.lay.pq_part));
             break;
@@ -1231,14 +1247,14 @@ hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t
 }
 
 #define FEWHA_INSTANTIATE_OP(T)                                                                           \
-    template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t);                                  \
-    template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, double*, hipStream_t);    \
+    template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t, const OpBufs*);                   \
+    template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, double*, hipStream_t, const OpBufs*); \
     template void launch_data_term<T>(const Ctx&, const T*, T*, hipStream_t);                             \
     template void launch_slopes_adj<T>(const Ctx&, const T*, T*, int, hipStream_t);                       \
     template void launch_adj_gather<T>(const Ctx&, const T*, T*, hipStream_t);                            \
     template void launch_fwd_slopes<T>(const Ctx&, const T*, T*, hipStream_t);                            \
-    template void launch_apply_M<T>(const Ctx&, const T*, T*, double*, hipStream_t);                      \
-    template void launch_rhs<T>(const Ctx&, const T*, T*, hipStream_t);                                   \
+    template void launch_apply_M<T>(const Ctx&, const T*, T*, double*, hipStream_t, const OpBufs*);       \
+    template void launch_rhs<T>(const Ctx&, const T*, T*, hipStream_t, double*);                                   \
     template hipError_t time_operator_kernel<T>(Ctx&, int, int, int, hipStream_t, float*);
 
 FEWHA_INSTANTIATE_OP(float)

@@ -112,6 +112,21 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
     if (cfg->precision != FEWHA_FP64 && cfg->precision != FEWHA_FP32_OP_FP64_RED) { err = "bad precision"; return FEWHA_E_INVAL; }
     if (cfg->project_all && cfg->recycle_mode != FEWHA_RECYCLE_GALERKIN) { err = "project_all needs GALERKIN mode"; return FEWHA_E_INVAL; }
     if (cfg->block_elems != 0 && (cfg->block_elems < 64 || cfg->block_elems > (1 << 22))) { err = "block_elems must be 0 or in [64, 2^22]"; return FEWHA_E_INVAL; }
+    // a caller-given prior or preconditioner must keep M (and J) symmetric positive definite
+    {
+        int64_t n_coef = 0;
+        for (int l = 0; l < cfg->n_layers; ++l) n_coef += int64_t(cfg->layers[l].n) * cfg->layers[l].n;
+        for (int64_t i = 0; cfg->prior_diag && i < n_coef; ++i)
+            if (!(cfg->prior_diag[i] > 0) || !std::isfinite(cfg->prior_diag[i])) {
+                err = "prior_diag must be finite and > 0 (entry " + std::to_string(i) + ")";
+                return FEWHA_E_INVAL;
+            }
+        for (int64_t i = 0; cfg->precond_inv && i < n_coef; ++i)
+            if (!(cfg->precond_inv[i] > 0) || !std::isfinite(cfg->precond_inv[i])) {
+                err = "precond_inv must be finite and > 0 (entry " + std::to_string(i) + ")";
+                return FEWHA_E_INVAL;
+            }
+    }
     // every projected sensor node must fall inside every layer grid (no padding, no wrap)
     for (int g = 0; g < cfg->n_wfs; ++g) {
         const fewha_wfs& W = cfg->wfs[g];

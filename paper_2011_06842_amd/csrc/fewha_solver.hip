@@ -180,16 +180,27 @@ __device__ double wave_forward_sub(const double* Mx, int ldr, int ldc, const dou
 // ------------------------------------------------------------------ frame start
 
 // First frame: r = b - M c; later frames: r = (b - b_prev) + r (Alg. 3 residual update).
-// b_prev = b; partial (b, b).  Block 0 resets the frame's flags.
+// b_prev = b; partial (b, b).  Block 0 resets the frame's flags.  Every workgroup first sums
+// the analysis tiles' partials of (b, b): when that is not finite (non-finite or overflowing
+// slopes) the frame is not solved -- r and b_prev keep their values (a first frame sets
+// r = b_prev - M c, so that the next residual update gives b - M c) and the frame is flagged
+// (bits 0 and 3), so that every later kernel of the frame leaves c and r alone.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* __restrict__ vb, int pstride,
                                                         const T* __restrict__ b, T* __restrict__ b_prev,
                                                         T* __restrict__ r, const T* __restrict__ mc,
-                                                        double* __restrict__ part, Scalars* __restrict__ scs, int m) {
-    const Seg sg = seg_of(vb, N, 0);
+                                                        double* __restrict__ part, Scalars* __restrict__ scs, int m,
+                                                        int npq, const double* __restrict__ bb_part) {
+    const Seg sg = seg_of(vb, N, npq);
+    const double bb_all = block_sum_array(bb_part + sg.pq0, sg.npq);
+    const bool bad = !isfinite(bb_all);
     double bb = 0;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
+        if (bad) {
+            if (mc) r[i] = T(double(b_prev[i]) - double(mc[i]));
+            continue;
+        }
         const double bi = double(b[i]);
         if (mc)
             r[i] = T(bi - double(mc[i]));
@@ -202,7 +213,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* 
     block_partials<1>(v, part, P_BB, pstride, sg.col);
     if (sg.local == 0 && threadIdx.x == 0) {
         Scalars* sc = scs + sg.inst;
-        sc->flags = 0;
+        sc->flags = bad ? (kFlagBreakdown | kFlagBadRhs) : 0;
         sc->used = m;
         sc->dropped = 0;
         sc->conv_iter = 0;
@@ -464,6 +475,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
         y2 = wave_chol_solve<MB>(sR, skeep, m, w);
     }
     if (k < m) sc->y2[k] = y2;
+    // a non-finite projection coefficient is a breakdown: the Galerkin pass then leaves the frame
+    if (__any(k < m && !(isfinite(y) && isfinite(y2))) && k == 0) sc->flags |= kFlagBreakdown;
 }
 
 // Galerkin step and initial direction in one pass (Sec. 4.1, Alg. 2): c += U y, r -= Q y,
@@ -476,6 +489,13 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, const Ve
                                                               const T* __restrict__ jinv, double* __restrict__ part) {
     const Seg sg = seg_of(vb, N, 0);
     const Scalars* __restrict__ sc = scs + sg.inst;
+    if (sc->flags != 0) {   // broken frame: c and r stay, the direction is the zero vector
+        for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads)
+            p[sg.off + j] = T(0);
+        const double vz[1] = {0.0};
+        block_partials<1>(vz, part, P_RZ, pstride, sg.col);
+        return;
+    }
     // slots a >= m of the list repeat slot 0 with coefficient 0 (unconditional loads)
     double y[MB], y2[MB];
 #pragma unroll
@@ -513,12 +533,14 @@ __global__ void __launch_bounds__(kThreads) k_galerkin_apply(int64_t N, const Ve
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, const VecBlk* __restrict__ vb, int pstride,
                                                         const T* __restrict__ r, const T* __restrict__ jinv,
-                                                        T* __restrict__ p, double* __restrict__ part) {
+                                                        T* __restrict__ p, double* __restrict__ part,
+                                                        const Scalars* __restrict__ scs) {
     const Seg sg = seg_of(vb, N, 0);
+    const T on = scs[sg.inst].flags != 0 ? T(0) : T(1);   // broken frame: the zero direction
     double rz = 0;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
-        const T pt = jinv[i] * r[i];
+        const T pt = on * jinv[i] * r[i];
         p[i] = pt;
         rz += double(r[i]) * double(pt);
     }
@@ -531,11 +553,14 @@ __global__ void __launch_bounds__(kThreads) k_init_dir(int64_t N, const VecBlk* 
 // alpha = (r, z) / (p, q) from the analysis partials of (p, q) = (p, Mp) and the (r, z) of
 // this iteration; c += alpha p, r -= alpha q; unless last: z = J^-1 r with partials of (r, z)
 // and, over the in-loop projection set, (Q_a, z) and (U_a, r); always the partial (r, r).
+// Breakdown (a non-finite value, or (p, q) <= 0 with (r, z) != 0; or a flag from earlier in
+// the frame): c and r keep their values, and this iteration's ring slot (p, q) and z become
+// zero vectors with (p, q) = 0, so that later projections give them no weight.
 template <typename T, int MP>
 __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* __restrict__ vb, int pstride, int it,
                                                        int mp, SlotList pl, const T* __restrict__ U,
                                                        const T* __restrict__ Q, Scalars* __restrict__ scs,
-                                                       const T* __restrict__ p, const T* __restrict__ q,
+                                                       T* __restrict__ p, T* __restrict__ q,
                                                        T* __restrict__ c, T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ jinv, int last, int npq,
                                                        const double* __restrict__ pq_part, double* __restrict__ part,
@@ -551,15 +576,16 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
     } else {
         rz = sc->rzb[it & 1];
     }
-    double alpha = rz / pq;
-    const bool broken = sc->flags != 0 || !(pq > 0) || !isfinite(alpha);
-    if (broken) alpha = 0;
+    // (p, q) = 0 with (r, z) = 0 is exact convergence (a zero residual), not a breakdown
+    const bool ok = isfinite(pq) && isfinite(rz) && (pq > 0 ? isfinite(rz / pq) : (pq == 0 && rz == 0));
+    const bool broken = sc->flags != 0 || !ok;
+    const double alpha = !broken && pq > 0 ? rz / pq : 0.0;
     if (sg.local == 0 && threadIdx.x == 0) {
         sc->pq = pq;
-        sc->gam[pslot] = pq;
+        sc->gam[pslot] = broken ? 0.0 : pq;
         sc->alpha = alpha;
         if (it == 0) sc->rzb[0] = rz;
-        if (broken) sc->flags |= 1;
+        if (broken) sc->flags |= kFlagBreakdown;
     }
     constexpr int NV = 2 + 2 * MP;
     double acc[NV];
@@ -568,6 +594,14 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
     constexpr int MP1 = MP > 0 ? MP : 1;
     // one element: the update and its partial-sum terms, from loaded operands
     auto element = [&](int64_t i, T cv, T pv, T rv, T qv, T jv, const T* Qv, const T* Uv) {
+        if (broken) {   // keep c and r; the slot and z become zero vectors
+            const double rd = double(rv);
+            acc[0] += rd * rd;
+            p[i] = T(0);
+            q[i] = T(0);
+            if (!last) z[i] = T(0);
+            return;
+        }
         c[i] = T(double(cv) + alpha * double(pv));
         const T rt = T(double(rv) - alpha * double(qv));
         r[i] = rt;
@@ -659,6 +693,7 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
     Scalars* __restrict__ sc = scs + sg.inst;
     __shared__ double sy[MP1];
     __shared__ double sbeta;
+    __shared__ bool sbroken;
     double v[NV];
     block_row_sums<NV>(part, pstride, sg, P_RZ1, NV, v);   // (r,z), (Q_a,z) a < MP, (U_a,r) a < MP (entries a >= mp unused)
     __shared__ double y3[MP1], R[MP1 * MP1];
@@ -696,22 +731,29 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
             if (a < mp) rzn -= y3[a] * v[1 + MP + a];
         const double rz_old = sc->rzb[it & 1];
         double beta = rz_old > 0 ? rzn / rz_old : 0.0;
-        const bool broken = sc->flags != 0 || !isfinite(beta);
+        bool broken = sc->flags != 0 || !isfinite(beta);
+        for (int a = 0; a < mp; ++a) broken = broken || !isfinite(y3[a]);
         if (broken) {
             beta = 0;
             for (int a = 0; a < mp; ++a) y3[a] = 0;
         }
         for (int a = 0; a < mp; ++a) sy[a] = y3[a];
         sbeta = beta;
+        sbroken = broken;
         if (sg.local == 0) {
             sc->rzb[(it + 1) & 1] = rzn;
             sc->beta = beta;
             sc->mu = mp ? y3[0] : 0.0;
-            if (broken) sc->flags |= 1;
+            if (broken) sc->flags |= kFlagBreakdown;
         }
     }
     __syncthreads();
     const double beta = sbeta;
+    if (sbroken) {   // broken frame: the next direction is the zero vector
+        for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads)
+            pn[sg.off + j] = T(0);
+        return;
+    }
     double yr[MP1];
 #pragma unroll
     for (int a = 0; a < MP; ++a) yr[a] = a < mp ? sy[a] : 0.0;
@@ -747,11 +789,14 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
 
 // Frame statistics (relative residual in FP64) of every instance (one workgroup each) into
 // the context's and the caller's info.  Tolerance mode: iters is the instance's first
-// iteration that met the tolerance (flag bit 1: not met within the frame).
+// iteration that met the tolerance (flag bit 1: not met within the frame).  A frame whose
+// right-hand side was not finite reports a NaN relative residual.  A broken-down instance
+// writes the frame's number into the host-visible breakdown word.
 __device__ __forceinline__ void finish_instance(int b, Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
                                                 int pstride, const double* __restrict__ part,
                                                 fewha_solve_info* __restrict__ infos,
-                                                fewha_solve_info* __restrict__ infos_user, int iters, int tol_mode) {
+                                                fewha_solve_info* __restrict__ infos_user, int iters, int tol_mode,
+                                                int64_t* __restrict__ brk) {
     const InstDev I = insts[b];
     const Seg sg{I.off, int(I.n), 0, I.nvb, b, I.vb0, I.pq0, I.npq};
     Scalars* __restrict__ sc = scs + b;
@@ -761,15 +806,19 @@ __device__ __forceinline__ void finish_instance(int b, Scalars* __restrict__ scs
     block_row_sums<2>(part, pstride, sg, P_BB, 2, v);   // rows P_BB, P_RR
     if (threadIdx.x == 0) {
         fewha_solve_info in;
+        const int32_t fl = sc->flags;
         in.iters = tol_mode && sc->conv_iter ? sc->conv_iter : iters;
         in.recycle_used = sc->used;
         in.dropped = sc->dropped;
-        in.flags = sc->flags | (tol_mode && !sc->conv_iter ? 2 : 0) | (sc->ws_state == 2 ? 4 : 0);
-        in.rel_res = v[0] > 0 ? sqrt(v[1] / v[0]) : 0.0;
+        in.flags = fl | (tol_mode && !sc->conv_iter ? kFlagTolUnmet : 0) | (sc->ws_state == 2 ? kFlagWsRejected : 0);
+        in.rel_res = (fl & kFlagBadRhs) ? __builtin_nan("") : (v[0] > 0 ? sqrt(v[1] / v[0]) : 0.0);
         sc->bb = v[0];
         sc->rr = v[1];
+        const int64_t fno = sc->frame_no + 1;
+        sc->frame_no = fno;
         *info = in;
         if (info_user) *info_user = in;
+        if (brk && (fl & kFlagBreakdown)) *reinterpret_cast<volatile int64_t*>(brk) = fno;
     }
 }
 
@@ -777,8 +826,8 @@ __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, 
                                                       int pstride, const double* __restrict__ part,
                                                       fewha_solve_info* __restrict__ infos,
                                                       fewha_solve_info* __restrict__ infos_user, int iters,
-                                                      int tol_mode) {
-    finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, tol_mode);
+                                                      int tol_mode, int64_t* __restrict__ brk) {
+    finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, tol_mode, brk);
 }
 
 // ------------------------------------------------------------------ warm start
@@ -820,6 +869,14 @@ __global__ void __launch_bounds__(kThreads) k_ws_unpack(int64_t N, const float* 
     if (i < N) d[i] = T(out[i] * so);
 }
 
+// z = J^-1 r with r = b - M c (rounded to the element type first, as the residual update does)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ws_resid(int64_t N, const T* __restrict__ jinv, const T* __restrict__ b,
+                                                        const T* __restrict__ mc, T* __restrict__ z) {
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < N) z[i] = jinv[i] * T(double(b[i]) - double(mc[i]));
+}
+
 // correction in coefficients: e = W d with W = delta^2 W^-T (W^-1 = DWT^T / delta, DWT
 // orthonormal), from wtd = W^-T d
 template <typename T>
@@ -859,8 +916,9 @@ __global__ void __launch_bounds__(kThreads) k_ws_step(int64_t N, const VecBlk* _
     const Seg sg = seg_of(vb, N, 0);
     double v[2];
     block_row_sums<2>(part, pstride, sg, P_PROJ, 2, v);
-    const double tau = v[1] > 0 && v[0] > 0 ? v[0] / v[1] : 0.0;
-    if (sg.local == 0 && threadIdx.x == 0) scs[sg.inst].ws_state = tau > 0 ? 1 : 2;
+    const bool skip = scs[sg.inst].flags != 0;   // broken frame: no correction
+    const double tau = !skip && v[1] > 0 && v[0] > 0 && isfinite(v[0] / v[1]) ? v[0] / v[1] : 0.0;
+    if (sg.local == 0 && threadIdx.x == 0) scs[sg.inst].ws_state = skip ? 0 : (tau > 0 ? 1 : 2);
     if (!(tau > 0)) return;
     for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
         const int64_t i = sg.off + j;
@@ -884,7 +942,7 @@ __global__ void __launch_bounds__(kThreads) k_check(Scalars* __restrict__ scs, c
         Scalars* sc = scs + blockIdx.x;
         const bool met = sqrt(v[1]) <= tol * sqrt(v[0]);
         if (met && sc->conv_iter == 0) sc->conv_iter = it1;
-        done[blockIdx.x] = sc->conv_iter != 0;
+        done[blockIdx.x] = sc->conv_iter != 0 || (sc->flags & kFlagBreakdown) != 0;   // a broken one cannot improve
     }
 }
 
@@ -899,8 +957,9 @@ __global__ void __launch_bounds__(kThreads) k_frame_out(int64_t N, const T* __re
                                                          const InstDev* __restrict__ insts, int pstride,
                                                          const double* __restrict__ part,
                                                          fewha_solve_info* __restrict__ infos,
-                                                         fewha_solve_info* __restrict__ infos_user, int iters) {
-    if (int(blockIdx.x) < B) finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, 0);
+                                                         fewha_solve_info* __restrict__ infos_user, int iters,
+                                                         int64_t* __restrict__ brk) {
+    if (int(blockIdx.x) < B) finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, 0, brk);
     if (c_out)
         for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
             c_out[i] = c[i];
@@ -937,7 +996,7 @@ void launch_gal(const VecLaunch& vl, int m, const SlotList& sl, const T* U, cons
 
 template <typename T, int MP>
 void launch_upd(const VecLaunch& vl, int it, int mp, const SlotList& pl, const T* U, const T* Q, Scalars* sc,
-                const T* p, const T* q, T* c, T* r, T* z, const T* jinv, int last, int npq, const double* pq_part,
+                T* p, T* q, T* c, T* r, T* z, const T* jinv, int last, int npq, const double* pq_part,
                 double* part, int pslot, int project_all, T* pn, const Ctx& ctx, hipStream_t s) {
     {
         ProfScope ps_(ctx, KID_UPDATE1, s);
@@ -1018,11 +1077,11 @@ struct Frame {
 // a1 + a2: right-hand side and residual update.
 template <typename T>
 void enqueue_rhs_residual(const Ctx& c, const Frame<T>& f, const T* slopes, hipStream_t s) {
-    launch_rhs<T>(c, slopes, f.b, s);
+    launch_rhs<T>(c, slopes, f.b, s, f.pqp);   // with the partials of (b, b)
     if (c.first) launch_apply_M<T>(c, f.cv, f.vx, nullptr, s);
     ProfScope ps_(c, KID_RESIDUAL, s);
     k_residual<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.b, f.bp, f.r,
-                                                 c.first ? f.vx : nullptr, f.part, f.sc, f.m);
+                                                 c.first ? f.vx : nullptr, f.part, f.sc, f.m, c.npq, f.pqp);
 }
 
 // a3 + a4: Galerkin step and initial direction.
@@ -1056,7 +1115,7 @@ void enqueue_galerkin_init(const Ctx& c, const Frame<T>& f, hipStream_t s) {
         }
     } else {
         ProfScope ps_(c, KID_INIT_DIR, s);
-        k_init_dir<T><<<f.vl.grid, kThreads, 0, s>>>(f.vl.N, f.vl.vb, f.vl.pstride, f.r, f.jinv, p0, f.part);
+        k_init_dir<T><<<f.vl.grid, kThreads, 0, s>>>(f.vl.N, f.vl.vb, f.vl.pstride, f.r, f.jinv, p0, f.part, f.sc);
     }
 }
 
@@ -1082,7 +1141,7 @@ template <typename T>
 void enqueue_finish(const Ctx& c, const Frame<T>& f, int iters, fewha_solve_info* info_user, hipStream_t s) {
     ProfScope ps_(c, KID_FINISH, s);
     k_finish<<<c.B, kThreads, 0, s>>>(f.sc, f.insts, f.vl.pstride, f.part, f.info, info_user, iters,
-                                      c.rel_tol > 0 ? 1 : 0);
+                                      c.rel_tol > 0 ? 1 : 0, c.brk_dev);
 }
 
 // Enqueues one fixed-count frame on stream s (no host-state change, so it can be captured).
@@ -1180,7 +1239,8 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
             const int64_t ncopy = c_out ? std::min<int64_t>((c.N + 4 * kThreads - 1) / (4 * kThreads), 4096) : 0;
             const int64_t nb = std::max<int64_t>(c.B, ncopy);
             k_frame_out<T><<<unsigned(nb), kThreads, 0, s>>>(c.N, c.at<T>(c.lay.c), c_out, c.B, f.sc, f.insts,
-                                                             f.vl.pstride, f.part, info, info_user, c.max_iter);
+                                                             f.vl.pstride, f.part, info, info_user, c.max_iter,
+                                                             c.brk_dev);
             e = hipGetLastError();
         }
         return end_frame<T>(c, static_cast<T*>(nullptr), iters, e, s);
@@ -1226,6 +1286,29 @@ hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& w, const T* slopes, T*
     return end_frame<T>(c, c_out, iters, e, s);
 }
 
+// Network input of the warm start of the frame with slopes `slopes` that follows the
+// coefficients c_in: r = b - M c_in, then [W^-1 c_in / s_c, W^-1 J^-1 r / s_r, h / 20 km, gamma]
+// per node into `in` (FP32, N x 4).  Uses the context's scratch vectors only (the carried state
+// is not touched).
+template <typename T>
+hipError_t launch_ws_input(const Ctx& c, const WarmStart& w, const T* c_in, const T* slopes, float* in,
+                           hipStream_t s) {
+    const unsigned gN = unsigned((c.N + kThreads - 1) / kThreads);
+    T* b = c.at<T>(c.lay.vy);
+    T* mc = c.at<T>(c.lay.vx);
+    T* z = c.at<T>(c.lay.z);
+    T* nod = c.at<T>(c.lay.nodal);
+    T* nod_r = c.at<T>(c.lay.psi_layers);
+    launch_rhs<T>(c, slopes, b, s);
+    launch_apply_M<T>(c, c_in, mc, nullptr, s);
+    k_ws_resid<T><<<gN, kThreads, 0, s>>>(c.N, c.at<T>(c.lay.jinv), b, mc, z);
+    launch_winv<T>(c, c_in, nod, s);
+    launch_winv<T>(c, z, nod_r, s);
+    k_ws_pack<T><<<gN, kThreads, 0, s>>>(c.N, c.at<LayerDev>(c.lay.layers), c.L, c.at<float2>(c.lay.lconst), nod,
+                                         nod_r, 1.f / w.scale_c, 1.f / w.scale_r, in);
+    return hipGetLastError();
+}
+
 void release_graphs(Ctx& c) {
     for (auto& kv : c.graphs) (void)hipGraphExecDestroy(kv.second);
     c.graphs.clear();
@@ -1239,5 +1322,9 @@ template hipError_t launch_solve_frame_ws<float>(Ctx&, const WarmStart&, const f
                                                  hipStream_t);
 template hipError_t launch_solve_frame_ws<double>(Ctx&, const WarmStart&, const double*, double*, fewha_solve_info*,
                                                   hipStream_t);
+template hipError_t launch_ws_input<float>(const Ctx&, const WarmStart&, const float*, const float*, float*,
+                                           hipStream_t);
+template hipError_t launch_ws_input<double>(const Ctx&, const WarmStart&, const double*, const double*, float*,
+                                            hipStream_t);
 
 }  // namespace fewha

@@ -2,12 +2,14 @@
 // the bfloat16 matrix cores of gfx950 (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
 //
 //   k_conv3x3      implicit GEMM of a same-size 3x3 convolution over NHWC bf16 activations:
-//                  out[p][co] = sum_{tap, ci} in[p + tap][ci] w[tap][co][ci]; 128 pixels x 32
-//                  output channels per workgroup, 32 x 32 per wavefront (2 x 2 MFMA tiles);
-//                  zero padding by masking; the decoder's 2x nearest upsampling and skip
-//                  concatenation are folded into the operand loads; the input gradient is
-//                  the same kernel on the ReLU-masked output gradient with flipped,
-//                  transposed weights.
+//                  out[p][co] = sum_{tap, ci} in[p + tap][ci] w[tap][co][ci]; 64 pixels x 32
+//                  output channels per wavefront (4 x 2 MFMA tiles of 16 x 16), the weights as
+//                  the A operand; the reduction over taps and channel blocks optionally split
+//                  over the wavefronts of a workgroup (KS = 2 or 4); zero padding reads a zero
+//                  row stored after every image, not masks; the decoder's 2x nearest upsampling
+//                  and skip concatenation are folded into the operand addresses; the input
+//                  gradient is the same kernel on the ReLU-masked output gradient with
+//                  flipped, transposed weights.
 //   k_conv_wgrad   weight gradient sum_p x[p + tap][ci] dy[p][co] of all nine taps and the
 //                  bias gradient sum_p dy[p][co]: tiles of 64 pixels are transposed through LDS
 //                  so that every MFMA operand is one 16-byte read; per-chunk FP32 partials,

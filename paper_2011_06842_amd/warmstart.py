@@ -1,6 +1,8 @@
 """Learned warm start: data collection and training through the C ABI (fewha_solve_aug,
-fewha_apply_piece, fewha_apply_A, fewha_rhs and the fewha_unet_* calls).  Every step runs in
-the library's HIP kernels; this module only orders the calls.
+fewha_warmstart_input, fewha_apply_piece and the fewha_unet_* calls).  The solves, the network
+inputs, the nodal fields and the network's forward and backward passes run in the library's
+HIP kernels; this module orders the calls, forms the training target as the difference of two
+coefficient vectors (a torch subtraction) and normalises the samples on the host (NumPy).
 
 A sample pairs, for one frame transition i -> i+1 of a slope sequence,
   input  [W^-1 c_i, W^-1 J^-1 r, h / 20 km, gamma] per layer node, with c_i the coefficients the
@@ -26,18 +28,6 @@ def layer_groups(spec):
     return groups
 
 
-def _layer_constants(spec, n_nodes):
-    """(N, 2) columns h / 20 km and gamma of every node's layer."""
-    out = np.empty((n_nodes, 2), dtype=np.float32)
-    o = 0
-    for lay in spec.layers:
-        k = lay.n * lay.n
-        out[o:o + k, 0] = lay.height / 20000.0
-        out[o:o + k, 1] = lay.weight
-        o += k
-    return out
-
-
 def collect(spec, plain, truth, slopes, device="cuda"):
     """Samples of one slope sequence.  `plain` is the deployed solver's context (its frames
     give c_i), `truth` a context converged far below the deployment tolerance (its frames
@@ -45,19 +35,13 @@ def collect(spec, plain, truth, slopes, device="cuda"):
     x (T-1, N, 4) and y (T-1, N)."""
     import torch
     dt = torch.float64 if spec.precision == "fp64" else torch.float32
-    consts = _layer_constants(spec, plain.N)
     xs, ys = [], []
     c_prev = None
     for t in range(slopes.shape[0]):
         s = torch.from_numpy(np.ascontiguousarray(slopes[t])).to(device=device, dtype=dt)
         c_star = truth.fewha_solve_aug(s)
         if c_prev is not None:
-            r = plain.fewha_rhs(s) - plain.fewha_apply_A(c_prev)
-            jr = plain.fewha_get_vector(1) * r
-            x = np.empty((plain.N, 4), dtype=np.float32)
-            x[:, 0] = plain.fewha_apply_piece(PIECE_WINV, c_prev).float().cpu().numpy()
-            x[:, 1] = plain.fewha_apply_piece(PIECE_WINV, jr).float().cpu().numpy()
-            x[:, 2:] = consts
+            x = plain.fewha_warmstart_input((1.0, 1.0), c_prev, s).cpu().numpy()
             y = plain.fewha_apply_piece(PIECE_WINV, (c_star - c_prev).contiguous()).float().cpu().numpy()
             xs.append(x)
             ys.append(y)

@@ -138,3 +138,26 @@ int main(void) { printf("%zu %zu\\n", sizeof(fewha_unet_config), offsetof(fewha_
     assert b"power of two" in lib.fewha_unet_last_error(None)
     cfg.size[0] = 32
     assert lib.fewha_unet_workspace_size(ctypes.byref(cfg), ctypes.byref(n)) == 0 and n.value > 0
+
+
+@pytest.mark.parametrize("alpha", [-1.0, float("nan"), float("inf")])
+def test_non_spd_regularisation_is_rejected(alpha):
+    """A negative (or non-finite) alpha would make M indefinite: rejected at setup."""
+    spec = _spec()
+    spec.alpha = alpha
+    with pytest.raises(fw.FewhaError) as e:
+        fw.fewha_workspace_size(spec)
+    assert "FEWHA_E_INVAL" in str(e.value) and "alpha" in str(e.value)
+
+
+@pytest.mark.parametrize("which, bad", [("prior_diag", -1.0), ("prior_diag", 0.0), ("prior_diag", float("nan")),
+                                        ("precond_inv", -2.0), ("precond_inv", 0.0), ("precond_inv", float("inf"))])
+def test_caller_prior_and_preconditioner_must_be_positive_and_finite(which, bad):
+    spec = _spec()
+    N = sum(l.n ** 2 for l in spec.layers)
+    vec = np.ones(N)
+    vec[N // 3] = bad
+    with pytest.raises(fw.FewhaError) as e:
+        fw.fewha_workspace_size(spec, **{which: vec})
+    assert "FEWHA_E_INVAL" in str(e.value) and which in str(e.value) and str(N // 3) in str(e.value)
+    assert fw.fewha_workspace_size(spec, **{which: np.ones(N)}) > 0

@@ -130,9 +130,9 @@ def test_frame_sequence_fp64(name, mode, project_all):
 
 @pytest.mark.parametrize("mode, project_all", [("galerkin", False), ("paper", False), ("galerkin", True)])
 def test_zero_frame_then_frames_fp64(mode, project_all):
-    """An all-zero slope frame (b = 0, exact residual 0) returns c = 0 and reports the zero
-    curvature as a breakdown; the zero directions it stores get zero coefficients, so the
-    following frames are finite and match the oracle."""
+    """An all-zero slope frame (b = 0, exact residual 0) returns c = 0; its zero curvature with
+    a zero residual is exact convergence, not a breakdown; the zero directions it stores get
+    zero coefficients, so the following frames are finite and match the oracle."""
     spec, seq, _ = system("small")
     spec = spec.copy(recycle_mode=mode, project_all=project_all)
     sysm = OracleSystem(spec)
@@ -147,7 +147,7 @@ def test_zero_frame_then_frames_fp64(mode, project_all):
         gi = fw.decode_info(info)
         if t == 0:
             np.testing.assert_array_equal(c, 0.0)
-            assert gi["flags"] == 1 and gi["rel_res"] == 0.0 and i_ref["rel_res"] == 0.0
+            assert gi["flags"] == 0 and gi["rel_res"] == 0.0 and i_ref["rel_res"] == 0.0 and i_ref["flags"] == 0
         else:
             assert np.all(np.isfinite(c)) and gi["flags"] == 0, (t, gi)
             errs.append(rel(c, c_ref))
@@ -326,3 +326,36 @@ def test_elt_frame_map_parity_from_identical_state(precision, frames, tol):
             assert rel(c, c_ref) <= tol, (t, rel(c, c_ref))
         else:
             ctx.fewha_solve_aug(dev(s, dt))
+
+
+def test_free_running_elt_fp32_within_the_methods_own_sensitivity():
+    """40 free-running cfg2 frames (FP32 operator, no state exchanged with the oracle).  Any
+    rounding at FP32 level makes the frame sequence of Alg. 3 drift from the FP64 one: the
+    oracle itself, with every operator output perturbed by a relative 2^-24 (seeded), drifts
+    away from the unperturbed oracle by 1e-5 after 10 frames and by 1e-4 to 1e-3 after 30 (the
+    recycled iteration amplifies it).  The bar per frame is therefore 10 times the largest such
+    oracle-vs-oracle drift so far, and at least the 5e-5 split-precision bar; the final
+    residuals of the two sequences agree within 5 %."""
+    spec = synth.config_elt_mcao(precision="fp32")
+    frames = 40
+    seq = synth.make_sequence(spec, frames, seed=6).astype(np.float32).astype(np.float64)
+    sysm = OracleSystem(spec)
+    ref = AugmentedReconstructor(sysm)
+    pert = AugmentedReconstructor(sysm, Jinv=ref.Jinv)
+    rng = np.random.default_rng(5)
+    pert.apply_M = lambda x: sysm.apply_M(x, ref.D) * (1 + 2.0 ** -24 * rng.standard_normal(sysm.N))
+    ctx = fw.FewhaContext(spec, device=DEV)
+    info = ctx.new_info()
+    sens_max, rows = 0.0, []
+    for t in range(frames):
+        c_ref, i_ref = ref.solve(seq[t])
+        c_pert, _ = pert.solve(seq[t])
+        c = host(ctx.fewha_solve_aug(dev(seq[t], np.float32), info=info))
+        gi = fw.decode_info(info)
+        sens_max = max(sens_max, rel(c_pert, c_ref))
+        err = rel(c, c_ref)
+        rows.append((t, err, sens_max))
+        assert err <= max(5e-5, 10 * sens_max), rows[-3:]
+        assert abs(gi["rel_res"] - i_ref["rel_res"]) <= 0.05 * i_ref["rel_res"], (t, gi, i_ref)
+    print("\nframe, GPU vs oracle, oracle drift under 2^-24 perturbations:",
+          [(t, f"{e:.2e}", f"{s_:.2e}") for t, e, s_ in rows[::5]])

@@ -432,3 +432,295 @@ def test_zero_frame_then_frames_match_plain_pcg(mode):
             callback=lambda xk: ref.append(xk.copy()))
     assert np.all(np.isfinite(c1)) and i1["recycle_used"] == 3
     np.testing.assert_allclose(c1, ref[-1], rtol=0, atol=1e-10 * np.abs(ref[-1]).max())
+
+
+# ---------------------------------------------------------------- wavelet scaling delta_l (Sec. 3)
+
+def test_wavelet_scaling_makes_coefficients_l2_normalised():
+    """delta_l = d_l: the coefficients are the L2-normalised representation of the layer, i.e.
+    the nodal quadrature of the squared layer function, sum_i phi_i^2 d_l^2, equals ||c_l||^2
+    on every layer (layers of different spacing and level count), and W^-T is the adjoint of
+    W^-1 under the plain Euclidean inner products (so W^-T x = DWT x / d_l as well)."""
+    sysm = OracleSystem(synth.config_mixed())
+    assert len({round(l.spacing, 12) for l in sysm.layers}) > 1
+    rng = np.random.default_rng(41)
+    c = rng.standard_normal(sysm.N)
+    for cl, phi, lay in zip(sysm.split_layers(c), sysm.W_inv(c), sysm.layers):
+        np.testing.assert_allclose((phi ** 2).sum() * lay.spacing ** 2, (cl ** 2).sum(), rtol=1e-12)
+    x = rng.standard_normal(sysm.N)
+    lhs = sum((p * xl).sum() for p, xl in zip(sysm.W_inv(c), sysm.split_layers(x)))
+    np.testing.assert_allclose(lhs, c @ sysm.W_invT(sysm.split_layers(x)), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- project_all (Alg. 2, all of U)
+
+def _non_conjugate_U(tiny, tiny_dense):
+    """Recycled directions that are not mutually M-conjugate: three PCG directions of each of
+    two different right-hand sides (as a ring spanning two frames holds)."""
+    Md, b, Jinv = tiny_dense
+    rng = np.random.default_rng(13)
+    U, Q, gam = [], [], []
+    for bb in (b, tiny.rhs(rng.standard_normal(tiny.S))):
+        _, _, dirs = pcg(lambda x: Md @ x, bb, np.zeros_like(bb), Jinv, 3)
+        U += [p for p, _, _ in dirs]
+        Q += [q for _, q, _ in dirs]
+        gam += [g for _, _, g in dirs]
+    Um = np.stack(U, 1)
+    G = Um.T @ Md @ Um
+    assert np.abs(G - np.diag(np.diag(G))).max() > 1e-3 * np.abs(np.diag(G)).max()   # really not conjugate
+    b2 = tiny.rhs(rng.standard_normal(tiny.S))
+    return Md, b2, Jinv, U, Q, gam
+
+
+def test_project_all_keeps_every_direction_conjugate_to_all_of_U(tiny, tiny_dense):
+    """With project_all every new direction is M-conjugate to every recycled direction (the
+    deflated-CG form of condition 1 of Alg. 2), also when U is not a conjugate set; projecting
+    against the most recent direction only does not give this (negative control)."""
+    Md, b2, Jinv, U, Q, gam = _non_conjugate_U(tiny, tiny_dense)
+    Um = np.stack(U, 1)
+    _, _, new, _ = aug_pcg(lambda x: Md @ x, np.zeros_like(b2), b2.copy(), Jinv, U, Q, gam, 5, "galerkin",
+                           project_all=True)
+    for p, _, _ in new:
+        scale = np.linalg.norm(Md @ p) * np.abs(Um).max() * np.sqrt(tiny.N)
+        assert np.abs(Um.T @ Md @ p).max() <= 1e-9 * scale
+    _, _, new_last, _ = aug_pcg(lambda x: Md @ x, np.zeros_like(b2), b2.copy(), Jinv, U, Q, gam, 5, "galerkin",
+                                project_all=False)
+    p = new_last[2][0]
+    scale = np.linalg.norm(Md @ p) * np.abs(Um).max() * np.sqrt(tiny.N)
+    assert np.abs(Um[:, :-1].T @ Md @ p).max() > 1e-6 * scale
+
+
+def test_project_all_iterate_is_energy_optimal_over_U_plus_krylov(tiny, tiny_dense):
+    """Deflated CG: with every direction projected against all of U, iterate k minimises the
+    M-norm error over c0 + span(U) + span(z_0, ..., z_{k-1}) for any recycled set U (here not
+    M-conjugate), by dense projection (brute force)."""
+    Md, b2, Jinv, U, Q, gam = _non_conjugate_U(tiny, tiny_dense)
+    cstar = np.linalg.solve(Md, b2)
+    c0 = np.zeros_like(b2)
+    errM = lambda v: np.sqrt((v - cstar) @ Md @ (v - cstar))
+    for k in (1, 2, 4):
+        c, _, _, _ = aug_pcg(lambda x: Md @ x, c0, b2.copy(), Jinv, U, Q, gam, k, "galerkin", project_all=True)
+        Z = []
+        for j in range(k):
+            _, rj, _, _ = aug_pcg(lambda x: Md @ x, c0, b2.copy(), Jinv, U, Q, gam, j, "galerkin", project_all=True)
+            Z.append(Jinv * rj)
+        V, _ = np.linalg.qr(np.stack(U + Z, 1))
+        best = c0 + V @ np.linalg.solve(V.T @ Md @ V, V.T @ Md @ (cstar - c0))
+        assert errM(c) <= errM(best) * (1 + 1e-7) + 1e-12 * np.sqrt(cstar @ Md @ cstar), k
+
+
+# ---------------------------------------------------------------- tolerance stop
+
+def test_rel_tol_stop_is_first_crossing_of_scipy_cg(tiny, tiny_dense):
+    """Without recycled directions the tolerance-stopped solve stops at the first iteration k
+    with ||b - M c_k|| <= tol ||b|| of SciPy's preconditioned CG, and returns that iterate; a
+    tolerance never met runs the full count."""
+    Md, b, Jinv = tiny_dense
+    xs = []
+    spla.cg(Md, b, x0=np.zeros_like(b), maxiter=40, rtol=1e-300, atol=0.0,
+            M=spla.LinearOperator(Md.shape, matvec=lambda v: Jinv * v), callback=lambda xk: xs.append(xk.copy()))
+    res = np.array([np.linalg.norm(b - Md @ x) for x in xs]) / np.linalg.norm(b)
+    checked = 0
+    for k_first in (3, 7, 12):
+        tol = np.sqrt(res[k_first - 1] * res[k_first - 2]) if res[k_first - 1] < res[k_first - 2] else None
+        if tol is None or np.any(res[:k_first - 1] <= tol):
+            continue
+        c, r, _, info = aug_pcg(lambda x: Md @ x, np.zeros_like(b), b.copy(), Jinv, [], [], [], 40,
+                                rel_tol=tol, b_norm=np.linalg.norm(b))
+        assert info["iters"] == k_first
+        np.testing.assert_allclose(c, xs[k_first - 1], atol=1e-10 * np.abs(xs[k_first - 1]).max())
+        checked += 1
+    assert checked >= 2
+    _, _, _, info = aug_pcg(lambda x: Md @ x, np.zeros_like(b), b.copy(), Jinv, [], [], [], 5,
+                            rel_tol=1e-12, b_norm=np.linalg.norm(b))
+    assert info["iters"] == 5
+
+
+@pytest.mark.parametrize("mode", ["paper", "galerkin"])
+def test_rel_tol_stop_with_recycling_is_first_crossing(tiny, tiny_dense, mode):
+    """With recycled directions: the stop is the smallest fixed count whose final residual meets
+    the tolerance, and the iterate equals that fixed-count run's."""
+    Md, b2, Jinv, U, Q, gam = _two_rhs(tiny, tiny_dense, 4)
+    bn = np.linalg.norm(b2)
+    runs = [aug_pcg(lambda x: Md @ x, np.zeros_like(b2), b2.copy(), Jinv, U, Q, gam, k, mode)
+            for k in range(1, 16)]
+    res = np.array([np.linalg.norm(r) / bn for _, r, _, _ in runs])
+    k_first = 6
+    tol = np.sqrt(res[k_first - 1] * res[k_first - 2])
+    assert res[k_first - 1] <= tol < res[k_first - 2]
+    first = 1 + int(np.argmax(res <= tol))
+    c, _, _, info = aug_pcg(lambda x: Md @ x, np.zeros_like(b2), b2.copy(), Jinv, U, Q, gam, 40, mode,
+                            rel_tol=tol, b_norm=bn)
+    assert info["iters"] == first
+    np.testing.assert_allclose(c, runs[first - 1][0], rtol=0, atol=1e-12 * np.abs(c).max())
+
+
+# ---------------------------------------------------------------- learned warm start step
+
+def test_warm_start_step_is_exact_line_search(tiny, tiny_dense):
+    """tau minimises the energy 1/2 c^T M c - b^T c along e (a dense 1-D minimisation), and a
+    correction pointing uphill is not taken."""
+    from scipy.optimize import minimize_scalar
+    from oracle import warm_start_step
+    Md, b, _ = tiny_dense
+    rng = np.random.default_rng(51)
+    c = np.linalg.solve(Md, b) + 0.1 * rng.standard_normal(tiny.N)
+    r = b - Md @ c
+    e = np.linalg.solve(Md, r) + 0.3 * rng.standard_normal(tiny.N)
+    f = lambda t: 0.5 * (c + t * e) @ Md @ (c + t * e) - b @ (c + t * e)
+    c1, r1, tau = warm_start_step(lambda x: Md @ x, c, r, e)
+    t_ref = minimize_scalar(f, bracket=(0.0, 1.0), tol=1e-12).x
+    assert tau > 0
+    np.testing.assert_allclose(tau, t_ref, rtol=1e-6)
+    np.testing.assert_allclose(r1, b - Md @ c1, atol=1e-10 * np.abs(b).max())
+    c2, r2, tau2 = warm_start_step(lambda x: Md @ x, c, r, -e)
+    assert tau2 == 0.0 and np.array_equal(c2, c) and np.array_equal(r2, r)
+    assert minimize_scalar(f, bounds=(-10.0, 0.0), method="bounded").x < 0   # the minimum lies behind
+
+
+def test_warm_start_correction_is_the_inverse_of_W_inv():
+    """e = W d is the coefficient vector whose nodal field is d: W^-1 e = d on every layer."""
+    from oracle import warm_start_correction
+    sysm = OracleSystem(synth.config_mixed())
+    d = np.random.default_rng(52).standard_normal(sysm.N)
+    e = warm_start_correction(sysm, d)
+    np.testing.assert_allclose(np.concatenate([p.ravel() for p in sysm.W_inv(e)]), d, atol=1e-12 * np.abs(d).max())
+
+
+def test_warm_start_inputs_columns():
+    """Columns: the nodal fields of c and of J^-1 r over their scales, then h / 20 km and gamma
+    of each node's layer."""
+    from oracle import warm_start_correction, warm_start_inputs
+    sysm = OracleSystem(synth.config_mixed())
+    rng = np.random.default_rng(53)
+    phi, psi = rng.standard_normal(sysm.N), rng.standard_normal(sysm.N)
+    Jinv = rng.uniform(0.5, 2.0, sysm.N)
+    c = warm_start_correction(sysm, phi)
+    r = warm_start_correction(sysm, psi) / Jinv
+    x = warm_start_inputs(sysm, c, r, Jinv, 2.0, 4.0)
+    np.testing.assert_allclose(x[:, 0], phi / 2.0, atol=1e-12)
+    np.testing.assert_allclose(x[:, 1], psi / 4.0, atol=1e-12)
+    for l, lay in enumerate(sysm.layers):
+        sl = slice(sysm.coff[l], sysm.coff[l + 1])
+        assert np.all(x[sl, 2] == lay.height / 20000.0) and np.all(x[sl, 3] == lay.weight)
+
+
+def test_warm_start_frames_zero_and_exact_correction():
+    """A zero correction leaves the frames those of plain augmented PCG; the exact correction
+    (the nodal field of c* - c) makes the frame start at the solution (tau = 1)."""
+    spec = synth.config_tiny()
+    spec.max_iter, spec.recycle_k = 3, 4
+    sysm = OracleSystem(spec)
+    rng = np.random.default_rng(54)
+    base = rng.standard_normal(sysm.S)
+    plain, warm = AugmentedReconstructor(sysm), AugmentedReconstructor(sysm)
+    for t in range(3):
+        s = base + 0.1 * t * rng.standard_normal(sysm.S)
+        cp, _ = plain.solve(s)
+        cw, iw = warm.solve(s, correction=lambda x: np.zeros(sysm.N))
+        np.testing.assert_array_equal(cw, cp)
+        assert iw["tau"] == 0.0
+    Md = sysm.dense_M()
+    exact = AugmentedReconstructor(sysm)
+    exact.solve(base)
+    s = base + 0.2 * rng.standard_normal(sysm.S)
+    cstar = np.linalg.solve(Md, sysm.rhs(s))
+    field = np.concatenate([p.ravel() for p in sysm.W_inv(cstar - exact.c)])
+    snap = AugmentedReconstructor(sysm)
+    snap.c = exact.c.copy()
+    snap.b_prev, snap.r, snap.first = exact.b_prev.copy(), exact.r.copy(), False
+    snap.max_iter = 0
+    c0, info = snap.solve(s, correction=lambda x: field / 3.0, scales=(1.0, 1.0, 3.0))
+    np.testing.assert_allclose(info["tau"], 1.0, rtol=1e-8)
+    np.testing.assert_allclose(c0, cstar, atol=1e-8 * np.abs(cstar).max())
+
+
+# ---------------------------------------------------------------- breakdown (paper silent)
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_slopes_frame_is_skipped_and_next_frame_is_plain_pcg(bad):
+    """A frame with non-finite slopes returns the previous coefficients unchanged (flags bits 0
+    and 3) and stores null directions; the carried residual stays b - M c, so the next frame is
+    Alg. 1 from the previous coefficients: SciPy's preconditioned CG from x0 = c."""
+    spec = synth.config_tiny()
+    spec.max_iter, spec.recycle_k = 4, 3
+    sysm = OracleSystem(spec)
+    Md = sysm.dense_M()
+    Jinv = 1.0 / np.diag(Md)
+    rng = np.random.default_rng(61)
+    rec = AugmentedReconstructor(sysm, Jinv=Jinv)
+    for t in range(2):
+        c_prev, _ = rec.solve(rng.standard_normal(sysm.S))
+    s_bad = rng.standard_normal(sysm.S)
+    s_bad[5] = bad
+    c_bad, info = rec.solve(s_bad)
+    np.testing.assert_array_equal(c_bad, c_prev)
+    assert info["flags"] == 9 and np.isnan(info["rel_res"])
+    s = rng.standard_normal(sysm.S)
+    c1, i1 = rec.solve(s)
+    b = sysm.rhs(s)
+    np.testing.assert_allclose(rec.r, b - Md @ c1, atol=1e-10 * np.abs(b).max())
+    ref = []
+    spla.cg(Md, b, x0=c_prev.copy(), maxiter=4, rtol=1e-300, atol=0.0,
+            M=spla.LinearOperator(Md.shape, matvec=lambda v: Jinv * v), callback=lambda xk: ref.append(xk.copy()))
+    assert i1["flags"] == 0
+    np.testing.assert_allclose(c1, ref[-1], rtol=0, atol=1e-10 * np.abs(ref[-1]).max())
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+def test_nonfinite_first_frame_keeps_residual_consistent():
+    """A non-finite first frame leaves r = b_prev - M c, so the next residual update gives the
+    true residual b - M c of the carried coefficients."""
+    spec = synth.config_tiny()
+    spec.max_iter, spec.recycle_k = 3, 3
+    sysm = OracleSystem(spec)
+    rec = AugmentedReconstructor(sysm)
+    rng = np.random.default_rng(62)
+    rec.c = rng.standard_normal(sysm.N)
+    s_bad = np.full(sysm.S, np.nan)
+    c0, info = rec.solve(s_bad)
+    assert info["flags"] == 9 and not rec.first
+    s = rng.standard_normal(sysm.S)
+    b = sysm.rhs(s)
+    np.testing.assert_allclose((b - rec.b_prev) + rec.r, b - sysm.apply_M(c0), atol=1e-12 * np.abs(b).max())
+
+
+def test_breakdown_mid_frame_keeps_last_finite_iterate(tiny, tiny_dense):
+    """A planted non-positive curvature at the third operator application (an indefinite
+    operator; the oracle is where such a fault is planted): the frame keeps the iterate of the
+    second iteration (SciPy's CG after two steps), flags the breakdown, and stores null
+    directions from there on."""
+    Md, b, Jinv = tiny_dense
+    calls = [0]
+
+    def bad_apply(x):
+        calls[0] += 1
+        return Md @ x if calls[0] < 3 else -(Md @ x)
+
+    c, r, new, info = aug_pcg(bad_apply, np.zeros_like(b), b.copy(), Jinv, [], [], [], 6)
+    ref = []
+    spla.cg(Md, b, x0=np.zeros_like(b), maxiter=2, rtol=1e-300, atol=0.0,
+            M=spla.LinearOperator(Md.shape, matvec=lambda v: Jinv * v), callback=lambda xk: ref.append(xk.copy()))
+    assert info["flags"] == 1 and len(new) == 6
+    np.testing.assert_allclose(c, ref[-1], rtol=0, atol=1e-10 * np.abs(ref[-1]).max())
+    np.testing.assert_allclose(r, b - Md @ c, atol=1e-10 * np.abs(b).max())
+    assert all(g == 0.0 and not p.any() for p, _, g in new[2:]) and new[1][2] > 0
+
+
+def test_identical_consecutive_frames_converge_monotonically(tiny, tiny_dense):
+    """Repeating one frame (singular-looking Gram: the new residual is already orthogonal to
+    the last directions) continues the same solve: the M-norm error never grows from frame to
+    frame and reaches the exact solution."""
+    Md, _, Jinv = tiny_dense
+    rec = AugmentedReconstructor(tiny, Jinv=Jinv, max_iter=3, k=6)
+    s = np.random.default_rng(63).standard_normal(tiny.S)
+    cstar = np.linalg.solve(Md, tiny.rhs(s))
+    errM = lambda v: np.sqrt((v - cstar) @ Md @ (v - cstar))
+    errs = []
+    for t in range(40):
+        c, info = rec.solve(s)
+        assert info["flags"] == 0 and np.all(np.isfinite(c))
+        errs.append(errM(c))
+    assert all(errs[i + 1] <= errs[i] * (1 + 1e-9) + 1e-14 for i in range(len(errs) - 1))
+    assert errs[-1] <= 1e-8 * np.sqrt(cstar @ Md @ cstar)
