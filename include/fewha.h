@@ -176,6 +176,18 @@ fewha_status fewha_sizes(const fewha_ctx* ctx, int64_t* n_coeff, int64_t* n_slop
 /* y = M x (equation for M, Sec. 3).  d_x, d_y: device, N elements; d_y must not alias d_x. */
 fewha_status fewha_apply_A(fewha_ctx* ctx, const void* d_x, void* d_y, void* stream);
 
+/* y = M x, as fewha_apply_A, for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation): the operator's
+ * intermediates (nodal image, two wavelet buffers, sensor nodes, layer adjoint field:
+ * 4 N + V elements, each block 256-byte aligned) live in a 16 MiB device array of the library,
+ * one per GPU, held until the process ends; its address is taken by fewha_setup on each
+ * device.  Calls nothing that allocates (also no message strings).  FEWHA_E_NOMEM (nothing
+ * launched) when the intermediates exceed 16 MiB; FEWHA_E_STATE when no context was set up on
+ * the current device.  Every call on a GPU shares that GPU's array and overwrites all of it
+ * that it uses, so calls that overlap on one GPU (other streams, other threads) race; the
+ * results equal fewha_apply_A's bit for bit. */
+fewha_status fewha_apply_A_noalloc(fewha_ctx* ctx, const void* d_x, void* d_y, void* stream);
+
 /* b = W^-T A^T C_eta^-1 s (right-hand side, Sec. 3).  d_s: device, S; d_b: device, N. */
 fewha_status fewha_rhs(fewha_ctx* ctx, const void* d_s, void* d_b, void* stream);
 

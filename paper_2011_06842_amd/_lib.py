@@ -25,7 +25,7 @@ STATUS = {0: "FEWHA_OK", 1: "FEWHA_E_INVAL", 2: "FEWHA_E_NOMEM", 3: "FEWHA_E_HIP
 
 EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", "fewha_setup_batch",
            "fewha_instances", "fewha_frame_iterations", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
-           "fewha_solve_aug", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
+           "fewha_solve_aug", "fewha_apply_A_noalloc", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
            "fewha_get_state", "fewha_set_state", "fewha_use_graphs", "fewha_profile", "fewha_profile_read",
            "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error",
            "fewha_unet_workspace_size", "fewha_unet_setup", "fewha_unet_num_params", "fewha_unet_num_nodes",
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "fewha_frame_iterations": ([vp, C.POINTER(C.c_int32)], st),
         "fewha_sizes": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)], st),
         "fewha_apply_A": ([vp, vp, vp, vp], st),
+        "fewha_apply_A_noalloc": ([vp, vp, vp, vp], st),
         "fewha_rhs": ([vp, vp, vp, vp], st),
         "fewha_solve_aug": ([vp, vp, vp, vp, vp], st),
         "fewha_reset": ([vp], st),
@@ -270,6 +271,13 @@ class FewhaContext:
         x = self._in(x, self.N)
         y = self._vec(self.N) if y is None else self._in(y, self.N)
         _check(self.lib.fewha_apply_A(self.ctx, _ptr(x), _ptr(y), _stream(stream)), self.ctx)
+        return y
+
+    def fewha_apply_A_noalloc(self, x, y, stream=None):
+        """y = M x with the library's static scratch array (see include/fewha.h); y is given."""
+        x = self._in(x, self.N)
+        y = self._in(y, self.N)
+        _check(self.lib.fewha_apply_A_noalloc(self.ctx, _ptr(x), _ptr(y), _stream(stream)), self.ctx)
         return y
 
     def fewha_rhs(self, s, b=None, stream=None):

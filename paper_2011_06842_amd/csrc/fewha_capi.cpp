@@ -18,7 +18,10 @@ thread_local std::string g_setup_err;
 constexpr uint64_t kStateMagic = 0x46455748415354ULL;   // "FEWHAST"
 
 fewha_status fail(fewha_ctx* ctx, fewha_status st, const std::string& msg) {
-    if (ctx) ctx->c.err = msg;
+    if (ctx) {
+        ctx->c.err = msg;
+        ctx->c.err_lit = nullptr;
+    }
     return st;
 }
 
@@ -128,6 +131,14 @@ fewha_status fewha_setup_batch(const fewha_config* cfgs, int32_t n, void* d_work
     std::memset(h, 0, 256);
     c.brk_host = static_cast<int64_t*>(h);
     c.brk_dev = static_cast<int64_t*>(d);
+    // the device address of fewha_apply_A_noalloc's static scratch array on this device
+    const char* serr = nullptr;
+    if (fewha::scratch_init(&serr) != FEWHA_OK) {
+        g_setup_err = serr;
+        (void)hipHostFree(h);
+        delete ctx;
+        return FEWHA_E_HIP;
+    }
     *out = ctx;
     return FEWHA_OK;
 }
@@ -446,7 +457,8 @@ fewha_status fewha_destroy(fewha_ctx* ctx) {
 }
 
 const char* fewha_last_error(const fewha_ctx* ctx) {
-    return ctx ? ctx->c.err.c_str() : g_setup_err.c_str();
+    if (!ctx) return g_setup_err.c_str();
+    return ctx->c.err_lit ? ctx->c.err_lit : ctx->c.err.c_str();
 }
 
 }  // extern "C"

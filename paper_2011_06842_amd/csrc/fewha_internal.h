@@ -209,6 +209,7 @@ struct Ctx {
     size_t ws_bytes = 0;
     Layout lay{};
     std::string err;
+    const char* err_lit = nullptr;   // static message of the last error, when set (preferred over err)
     mutable Profiler prof;
     // captured frame graphs, keyed by (ring head, first frame, recycled directions)
     bool use_graphs = true;
@@ -267,6 +268,9 @@ template <typename T> hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& 
 template <typename T> hipError_t launch_ws_input(const Ctx& c, const WarmStart& w, const T* c_in, const T* slopes,
                                                  float* in, hipStream_t s);
 void release_graphs(Ctx& c);
+// Address of fewha_apply_A_noalloc's static scratch array on the current device, taken once per
+// device (fewha_setup calls it).
+fewha_status scratch_init(const char** err);
 template <typename T> hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t s, float* ms);
 
 }  // namespace fewha
