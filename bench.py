@@ -312,8 +312,8 @@ def _ragged_instance(args):
 
 def run_ragged(args, dev):
     """Ragged batch: independent random instances (telescope 8-39 m, 20-84 subapertures, 3-9
-    layers, 1-6 NGS/LGS, grids up to 256^2), FP32 operator, every frame iterated until each
-    instance has ||r|| <= 1e-4 ||b|| (cap 200), the instances in lock step."""
+    layers, 1-6 NGS/LGS, grids up to 256^2), FP32 operator, every instance stopping at its own
+    first ||r|| <= 1e-4 ||b|| (cap 200) on the device; the frame is one graph replay."""
     import numpy as np
     import torch
     from concurrent.futures import ProcessPoolExecutor
@@ -347,26 +347,29 @@ def run_ragged(args, dev):
         e1.record()
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
-        iters.append(ctx.fewha_frame_iterations())
         inf = fw.decode_info(info)
+        iters.append(max(x["iters"] for x in inf))
         firsts += [x["iters"] for x in inf]
         unmet += sum(1 for x in inf if x["flags"] & 2)
     wall = time.perf_counter() - w0
-    log(f"ragged leg: {args.ragged_steps} frames, p50 {np.median(ms):.2f} ms, {np.mean(iters):.1f} iterations")
+    log(f"ragged leg: {args.ragged_steps} frames, p50 {np.median(ms):.2f} ms, longest instance "
+        f"{np.mean(iters):.1f} iterations, mean {np.mean(firsts):.1f}")
     sizes = [synth_n(sp) for sp in specs]
     return {
         "workload": f"ragged_random_fp32_x{B}_tol1e-4",
         "instances": B, "coefficients": int(ctx.N), "coefficients_min_max": [min(sizes), max(sizes)],
-        "applies_per_s": round(B * sum(iters) / wall, 1),
+        "applies_per_s": round(sum(firsts) / wall, 1),
         "frame_ms_p50": round(float(np.percentile(ms, 50)), 3),
         "frame_ms_p99": round(float(np.percentile(ms, 99)), 3),
-        "frame_iterations_mean": round(float(np.mean(iters)), 2),
+        "longest_instance_iterations_mean": round(float(np.mean(iters)), 2),
+        "iterations_enqueued_per_frame": int(specs[0].max_iter),
         "instance_iterations_to_tol_mean": round(float(np.mean(firsts)), 2),
         "instance_iterations_to_tol_max": int(max(firsts)),
         "tolerance_unmet_instance_frames": unmet,
         "steps": args.ragged_steps, "warmup": args.ragged_warmup,
         "input_generation_s": round(t_gen, 1), "setup_s": round(t_setup, 1),
-        "note": "instances iterate in lock step until all meet the tolerance; applies/s counts the work done",
+        "note": "each instance stops at its first crossing (its kernels return at once afterwards); "
+                "applies/s counts the applies instances performed",
     }
 
 
@@ -550,8 +553,8 @@ def run_warmstart(args, dev):
         dt = 1000 * (time.perf_counter() - w0)
         if t >= 2:
             ms.append(dt)
-            its.append(bctx.fewha_frame_iterations())
-    res["batched"] = {"instances": len(evals), "frame_iterations_mean": round(float(np.mean(its)), 2),
+            its.append(float(np.mean([x["iters"] for x in fw.decode_info(info)])))
+    res["batched"] = {"instances": len(evals), "iterations_to_tol_mean": round(float(np.mean(its)), 2),
                       "batch_frame_ms_p50": round(float(np.percentile(ms, 50)), 3),
                       "batch_frame_ms_p99": round(float(np.percentile(ms, 99)), 3),
                       "per_instance_ms_p50": round(float(np.percentile(ms, 50)) / len(evals), 3)}
@@ -563,7 +566,7 @@ def run_warmstart(args, dev):
             "truth": "256 iterations of augmented PCG (rel_tol 1e-6 cap) per training frame",
             "loss_train_validation_per_epoch": hist, "epoch_kept": best[2],
             "generate_s": round(t_gen, 1), "collect_s": round(t_collect, 1), "train_s": round(t_train, 1),
-            **res, "timing": "host wall clock per frame, including the tolerance polls"}
+            **res, "timing": "host wall clock per frame (each synchronised)"}
 
 
 def synth_n(spec):

@@ -116,12 +116,15 @@ typedef struct {
     int32_t recycle_k;           /* recycled directions, 0..FEWHA_MAX_RECYCLE (0 = plain PCG) */
     int32_t recycle_mode;        /* fewha_recycle_mode */
     int32_t project_all;         /* GALERKIN only: project every new direction against all of U */
-    double rel_tol;              /* 0: exactly max_iter iterations per frame.  > 0 (< 1): iterate until
-                                    ||r|| <= rel_tol ||b|| (FP64) or max_iter; the instances of a batch
-                                    iterate in lock step until every one has met it, each recording the
-                                    iteration at which it first did (checked every iteration, the stop
-                                    decided every 4 iterations on the host, so a frame synchronises its
-                                    stream and is never captured into a graph) */
+    double rel_tol;              /* 0: exactly max_iter iterations per frame.  > 0 (< 1): every instance
+                                    stops at its first iteration with ||r|| <= rel_tol ||b|| (FP64; decided
+                                    on the device after every iteration), or at max_iter.  A stopped
+                                    instance's kernels return at once for the rest of the frame, its c and r
+                                    stay those of its stop, and at the end of the frame its last recycle_k
+                                    directions move to the end of the shared recycle window.  The frame
+                                    never synchronises with the host: all max_iter iterations are enqueued
+                                    (and captured into a graph like fixed-count frames), those after every
+                                    instance has stopped costing only their launches */
     int32_t precision;           /* fewha_precision */
     int32_t block_elems;         /* elements per workgroup of the vector kernels (0 = 384); fixes the
                                     reduction order, so results are reproducible for a given value */
@@ -199,7 +202,8 @@ fewha_status fewha_rhs(fewha_ctx* ctx, const void* d_s, void* d_b, void* stream)
  * fewha_solve_info. */
 fewha_status fewha_solve_aug(fewha_ctx* ctx, const void* d_s, void* d_c, void* d_info, void* stream);
 
-/* Iterations (operator applications per instance) of the last fewha_solve_aug. */
+/* Iterations enqueued by the last fewha_solve_aug (max_iter; with rel_tol > 0 each instance's own
+ * count is the iters of its fewha_solve_info). */
 fewha_status fewha_frame_iterations(const fewha_ctx* ctx, int32_t* iters);
 
 /* Drop the recycle store: the next solve runs Alg. 1 from r = b - M c with the carried c. */
@@ -222,7 +226,9 @@ fewha_status fewha_get_vector(fewha_ctx* ctx, int32_t which, void* d_out, void* 
  * fewha_state_size gives the bytes; get/set copy to/from a device buffer of that size.
  * Layout: 256-byte header of uint64 (magic, N, slots, element size, ring head, stored count,
  * previous iterations, first-frame flag, instances), then per instance `slots` doubles
- * (p_j, q_j), then c, r, b_prev (N each) and the ring U, Q (slots x N each, slot-major). */
+ * (p_j, q_j) and one double (the number of real recycled directions at the end of the window,
+ * used by tolerance-stopped frames), then c, r, b_prev (N each) and the ring U, Q (slots x N
+ * each, slot-major). */
 fewha_status fewha_state_size(const fewha_ctx* ctx, size_t* bytes);
 fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream);
 fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream);

@@ -460,6 +460,7 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
     rz = r @ z
     new = []
     it = 0
+    met = False
     zero = np.zeros_like(r)
     for k in range(max_iter):
         if broken:
@@ -478,9 +479,10 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
         r = r - alpha * q
         new.append((p, q, pq))
         it = k + 1
-        if k == max_iter - 1:
-            break
         if rel_tol > 0 and np.sqrt(r @ r) <= rel_tol * b_norm:
+            met = True
+            break
+        if k == max_iter - 1:
             break
         z = Jinv * r
         if m:
@@ -501,7 +503,8 @@ def aug_pcg(apply_M, c, r, Jinv, U, Q, gam, max_iter, mode="galerkin", project_a
             continue
         p = z + beta * p
         rz = rz_new
-    info = {"iters": it, "recycle_used": m, "dropped": dropped, "flags": 1 if broken else 0,
+    flags = (1 if broken else 0) | (2 if rel_tol > 0 and not met else 0)
+    info = {"iters": it, "recycle_used": m, "dropped": dropped, "flags": flags,
             "rel_res": float("nan") if b_norm is None else float(np.sqrt(r @ r) / b_norm) if b_norm > 0 else 0.0}
     return c, r, new, info
 
@@ -601,8 +604,8 @@ class AugmentedReconstructor:
             used = 0 if self.first else min(self.k, len(self.store))
             self._keep([(zero, zero, 0.0)] * self.max_iter)
             self.first = False
-            return self.c.copy(), {"iters": self.max_iter, "recycle_used": used, "dropped": 0, "flags": 9,
-                                   "rel_res": float("nan")}
+            return self.c.copy(), {"iters": self.max_iter, "recycle_used": used, "dropped": 0,
+                                   "flags": 9 | (2 if self.rel_tol > 0 else 0), "rel_res": float("nan")}
         b_norm = float(np.sqrt(bb))
         if self.first:
             r = b - self.apply_M(self.c)

@@ -321,7 +321,8 @@ fewha_status fewha_state_size(const fewha_ctx* ctx, size_t* bytes) {
     return FEWHA_OK;
 }
 
-// State buffer: [256-byte header][instances x slots x double (p_j, q_j)][c][r][b_prev][U slots][Q slots]
+// State buffer: [256-byte header][instances x (slots doubles (p_j, q_j), 1 double: real recycled
+// directions)][c][r][b_prev][U slots][Q slots]
 fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream) {
     if (!ctx || !d_dst) return fail(ctx, FEWHA_E_INVAL, "NULL argument");
     const fewha::Ctx& c = ctx->c;
@@ -340,11 +341,15 @@ fewha_status fewha_get_state(fewha_ctx* ctx, void* d_dst, void* stream) {
     char* dst = static_cast<char*>(d_dst);
     const size_t vb = c.esz * c.N;
     bool ok = hipMemcpyAsync(dst, h, 256, hipMemcpyHostToDevice, s) == hipSuccess;
+    // per instance: (p_j, q_j) of every slot, then the count of real recycled directions
+    // (tolerance mode), as a double
+    const size_t pib = sizeof(double) * (c.slots + 1);
+    if (ok) ok = fewha::launch_state_avail(c, dst + 256, pib, true, s) == hipSuccess;
     for (int i = 0; i < c.B; ++i)
-        ok = ok && hipMemcpyAsync(dst + 256 + sizeof(double) * c.slots * i,
+        ok = ok && hipMemcpyAsync(dst + 256 + pib * i,
                                   c.ws + c.lay.scalars + sizeof(fewha::Scalars) * i + offsetof(fewha::Scalars, gam),
                                   sizeof(double) * c.slots, hipMemcpyDeviceToDevice, s) == hipSuccess;
-    size_t o = 256 + sizeof(double) * c.slots * c.B;
+    size_t o = 256 + pib * c.B;
     for (size_t src : {c.lay.c, c.lay.r, c.lay.b_prev}) {
         ok = ok && hipMemcpyAsync(dst + o, c.ws + src, vb, hipMemcpyDeviceToDevice, s) == hipSuccess;
         o += vb;
@@ -369,11 +374,13 @@ fewha_status fewha_set_state(fewha_ctx* ctx, const void* d_src, void* stream) {
     const char* src = static_cast<const char*>(d_src);
     const size_t vb = c.esz * c.N;
     bool ok = true;
+    const size_t pib = sizeof(double) * (c.slots + 1);
     for (int i = 0; i < c.B; ++i)
         ok = ok && hipMemcpyAsync(c.ws + c.lay.scalars + sizeof(fewha::Scalars) * i + offsetof(fewha::Scalars, gam),
-                                  src + 256 + sizeof(double) * c.slots * i, sizeof(double) * c.slots,
-                                  hipMemcpyDeviceToDevice, s) == hipSuccess;
-    size_t o = 256 + sizeof(double) * c.slots * c.B;
+                                  src + 256 + pib * i, sizeof(double) * c.slots, hipMemcpyDeviceToDevice,
+                                  s) == hipSuccess;
+    if (ok) ok = fewha::launch_state_avail(c, const_cast<char*>(src) + 256, pib, false, s) == hipSuccess;
+    size_t o = 256 + pib * c.B;
     for (size_t dst : {c.lay.c, c.lay.r, c.lay.b_prev}) {
         ok = ok && hipMemcpyAsync(c.ws + dst, src + o, vb, hipMemcpyDeviceToDevice, s) == hipSuccess;
         o += vb;

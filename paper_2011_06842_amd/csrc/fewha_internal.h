@@ -130,6 +130,9 @@ struct Scalars {
     int32_t conv_iter;    // tolerance mode: first iteration whose residual met the tolerance (0: not yet)
     int32_t ws_state;     // warm start of this frame: 0 none, 1 accepted, 2 rejected
     int64_t frame_no;     // frames finished since setup (the breakdown report names a frame by it)
+    int32_t avail;        // tolerance mode: real directions at the end of the recycle window (the rest of
+                          // the window is hidden from the projections)
+    int32_t pad_;
 };
 
 // Byte layout of the workspace (offsets from its base).
@@ -185,7 +188,6 @@ struct Ctx {
     double alpha = 0;
     int max_iter = 0, k = 0, mode = 1, project_all = 0;
     double rel_tol = 0;        // > 0: iterate until every instance meets it (or max_iter)
-    int check_every = 4;       // tolerance mode: iterations between host checks of the done flags
     int frame_iters = 0;       // iterations of the last frame
     int max_levels = 0, max_n = 0;
     int slots = 0;             // ring capacity k + max_iter
@@ -244,15 +246,20 @@ Layout compute_layout(const fewha_config* cfgs, int n);
 fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int n, hipStream_t stream);
 
 // Launchers (fewha_kernels.hip)
-template <typename T> void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* ob = nullptr);
+// skip (may be NULL): per-instance flags; the workgroups of an instance whose flag is set return
+// at once (tolerance mode: the instance has converged within the frame).
+template <typename T> void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* ob = nullptr,
+                                       const int32_t* skip = nullptr);
 template <typename T> void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part,
-                                        hipStream_t s, const OpBufs* ob = nullptr);
-template <typename T> void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s);
+                                        hipStream_t s, const OpBufs* ob = nullptr, const int32_t* skip = nullptr);
+template <typename T> void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s,
+                                            const int32_t* skip = nullptr);
 template <typename T> void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted, hipStream_t s);
-template <typename T> void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s);
+template <typename T> void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s,
+                                             const int32_t* skip = nullptr);
 template <typename T> void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s);
 template <typename T> void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s,
-                                          const OpBufs* ob = nullptr);
+                                          const OpBufs* ob = nullptr, const int32_t* skip = nullptr);
 
 template <typename T> void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s,
                                       double* bb_part = nullptr);
@@ -268,6 +275,9 @@ template <typename T> hipError_t launch_solve_frame_ws(Ctx& c, const WarmStart& 
 template <typename T> hipError_t launch_ws_input(const Ctx& c, const WarmStart& w, const T* c_in, const T* slopes,
                                                  float* in, hipStream_t s);
 void release_graphs(Ctx& c);
+// Copies every instance's count of real recycled directions to (to_state) or from a checkpoint:
+// the double at base + stride i + 8 slots.
+hipError_t launch_state_avail(const Ctx& c, char* base, size_t stride, bool to_state, hipStream_t s);
 // Address of fewha_apply_A_noalloc's static scratch array on the current device, taken once per
 // device (fewha_setup calls it).
 fewha_status scratch_init(const char** err);

@@ -105,11 +105,12 @@ struct Taps {
 template <typename T>
 __global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
                                                                  const T* __restrict__ coef, T* __restrict__ ll_out,
-                                                                 T* __restrict__ phi) {
+                                                                 T* __restrict__ phi, const int32_t* __restrict__ skip) {
     constexpr int CB = CoarseBlock<T>::value;
     __shared__ T A[CB * CB];
     __shared__ T B[CB * CB];
     const LayerDev d = lays[blockIdx.x];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
     const int n = d.n, lc = d.coarse_lev, levels = d.levels;
     if (levels < lc) return;
     const T* C = coef + d.off;
@@ -191,7 +192,7 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
                                                          const int32_t* __restrict__ sl, int nbs,
                                                          Filt<T> f, const T* __restrict__ coef,
                                                          const T* __restrict__ ll_in, T* __restrict__ ll_out,
-                                                         T* __restrict__ phi) {
+                                                         T* __restrict__ phi, const int32_t* __restrict__ skip) {
     constexpr int H = ST / 2 + 2;   // coefficient rows (per band) feeding one tile
     __shared__ T R[2 * H][2 * H + 1];
     __shared__ T I[ST][2 * H + 1];
@@ -199,6 +200,7 @@ __global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restri
     const int bid = die_ordered_block();
     const int li = bid / tiles, tile = bid - li * tiles;
     const LayerDev d = lays[sl[li]];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
     const int n = d.n;
     const int lev = ilog2i(n / nbs) + 1;
     const int M = nbs >> 1;
@@ -282,7 +284,8 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
                                                         Filt<T> f, const T* __restrict__ img,
                                                         const T* __restrict__ ll_in, T* __restrict__ ll_out,
                                                         T* __restrict__ out, const T* __restrict__ prior_a,
-                                                        const T* __restrict__ xprior, double* __restrict__ dotpart) {
+                                                        const T* __restrict__ xprior, double* __restrict__ dotpart,
+                                                        const int32_t* __restrict__ skip) {
     constexpr bool PRIOR = MODE == 1;
     constexpr int W = 2 * kAT + 4;
     __shared__ T R[W][W + 1];
@@ -291,6 +294,7 @@ __global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restric
     const int bid = die_ordered_block();
     const int li = bid / tiles, tile = bid - li * tiles;
     const LayerDev d = lays[sl[li]];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
     const int n = d.n;
     const int lev = ilog2i(n / nbs) + 1;
     const int ky0 = (tile / tx) * kAT, kx0 = (tile % tx) * kAT;
@@ -386,12 +390,13 @@ __global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* _
                                                                 const T* __restrict__ img, const T* __restrict__ ll_in,
                                                                 T* __restrict__ out, const T* __restrict__ prior_a,
                                                                 const T* __restrict__ xprior,
-                                                                double* __restrict__ dotpart) {
+                                                                double* __restrict__ dotpart, const int32_t* __restrict__ skip) {
     constexpr bool PRIOR = MODE == 1;
     constexpr int CB = CoarseBlock<T>::value;
     __shared__ T A[CB * CB];
     __shared__ T B[CB * CB];
     const LayerDev d = lays[blockIdx.x];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
     const int n = d.n, lc = d.coarse_lev, levels = d.levels;
     double dot = 0;
     if (levels >= lc) {
@@ -510,7 +515,8 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
                                                             const LayerDev* __restrict__ lays,
                                                             const int32_t* __restrict__ cidx,
                                                             const T* __restrict__ frac, const T* __restrict__ phi,
-                                                            const T* __restrict__ w, T* __restrict__ psi) {
+                                                            const T* __restrict__ w, T* __restrict__ psi,
+                                                            const int32_t* __restrict__ skip) {
     constexpr int E = kTile + 2, S1 = kTile + 1;
     static_assert(E * E == kDataThreads, "one halo-tile node per thread");
     static_assert(S1 * S1 <= kDataThreads, "one subaperture per thread");
@@ -524,6 +530,7 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
     const int2 st = tiles[blockIdx.x];
     if (st.x < 0) return;                                        // padding of the die-ordered grid
     const WfsDev W = wfs[st.x];
+    if (skip && skip[W.inst]) return;   // tolerance mode: the instance has converged
     const int ns = W.ns, np = ns + 1;
     const int L = W.nl;
     // the instance's layers follow its first one, at most FEWHA_MAX_LAYERS x 1024^2 values:
@@ -722,7 +729,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
                                                           const int2* __restrict__ tiles,
                                                           const int64_t* __restrict__ recbase,
                                                           const GatherRec<T>* __restrict__ recs,
-                                                          const T* __restrict__ psi, T* __restrict__ out) {
+                                                          const T* __restrict__ psi, T* __restrict__ out,
+                                                          const int32_t* __restrict__ skip) {
     constexpr int TR = kGRowStep * NRW;
     constexpr int NR = TR + kGT;                         // records per sensor: tile rows, then columns
     constexpr int PER = (kGatherGroup * NR + kThreads - 1) / kThreads;
@@ -731,6 +739,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather(const WfsDev* __restric
     const int2 lt = tiles[blockIdx.x];
     if (lt.x < 0) return;                                // padding of the die-ordered grid
     const LayerDev d = lays[lt.x];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
     const int n = d.n, tx = (n + kGT - 1) / kGT;
     const int a0 = (lt.y / tx) * TR, b0 = (lt.y % tx) * kGT;
     const int la = threadIdx.x / kGT, lb = threadIdx.x % kGT;
@@ -830,7 +839,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __res
                                                               const int64_t* __restrict__ recbase,
                                                               const GatherRec<T>* __restrict__ recs,
                                                               const int4* __restrict__ gwin,
-                                                              const T* __restrict__ psi, T* __restrict__ out) {
+                                                              const T* __restrict__ psi, T* __restrict__ out,
+                                                              const int32_t* __restrict__ skip) {
     constexpr int TR = kGRowStep * NRW;
     constexpr int NR = TR + kGT;                         // records per sensor: tile rows, then columns
     constexpr int WP = 32;                               // LDS image pitch (and largest side)
@@ -842,6 +852,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_win(const WfsDev* __res
     const int2 lt = tiles[blockIdx.x];
     if (lt.x < 0) return;                                // padding of the die-ordered grid
     const LayerDev d = lays[lt.x];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
     const int n = d.n, tx = (n + kGT - 1) / kGT;
     const int a0 = (lt.y / tx) * TR, b0 = (lt.y % tx) * kGT;
     const int la = threadIdx.x / kGT, lb = threadIdx.x % kGT;
@@ -924,9 +935,11 @@ __global__ void __launch_bounds__(kThreads) k_adj_gather_wide(const WfsDev* __re
                                                                const int32_t* __restrict__ cidx,
                                                                const T* __restrict__ frac,
                                                                const int2* __restrict__ rng,
-                                                               const T* __restrict__ psi, T* __restrict__ out) {
+                                                               const T* __restrict__ psi, T* __restrict__ out,
+                                                               const int32_t* __restrict__ skip) {
     const int l = blockIdx.y;
     const LayerDev d = lays[l];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
     const int n = d.n;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * n) return;
@@ -1017,16 +1030,16 @@ hipError_t profiler_collect(const Ctx& c, hipStream_t s) {
 // finish sooner.
 template <typename T>
 void launch_idwt_step(const StepInfo& w, const LayerDev* lays, const int32_t* sl, const Filt<T>& f, const T* x,
-                      const T* ll_in, T* ll_out, T* phi, hipStream_t s) {
+                      const T* ll_in, T* ll_out, T* phi, hipStream_t s, const int32_t* skip) {
     const int tiles = (w.nb / kST) * (w.nb / kST) * w.nl;
     if (tiles < kSmallTileBelow)
-        k_idwt_step<T, kST / 2><<<4 * tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi);
+        k_idwt_step<T, kST / 2><<<4 * tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi, skip);
     else
-        k_idwt_step<T, kST><<<tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi);
+        k_idwt_step<T, kST><<<tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi, skip);
 }
 
 template <typename T>
-void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* ob) {
+void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* ob, const int32_t* skip) {
     const Filt<T> f = make_filt<T>();
     const OpBufs bb = ob ? *ob : ctx_bufs(c);
     T* buf[2] = {reinterpret_cast<T*>(bb.tmp0), reinterpret_cast<T*>(bb.tmp1)};
@@ -1034,17 +1047,17 @@ void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* 
     const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
     {
         ProfScope ps_(c, KID_IDWT_COARSE, s);
-        k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], phi);
+        k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], phi, skip);
     }
     for (size_t j = 0; j < c.steps.size(); ++j) {
         ProfScope ps_(c, KID_IDWT_STEP, s);
-        launch_idwt_step<T>(c.steps[j], lays, sl, f, x, buf[j & 1], buf[(j + 1) & 1], phi, s);
+        launch_idwt_step<T>(c.steps[j], lays, sl, f, x, buf[j & 1], buf[(j + 1) & 1], phi, s, skip);
     }
 }
 
 template <typename T>
 void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part, hipStream_t s,
-                  const OpBufs* ob) {
+                  const OpBufs* ob, const int32_t* skip) {
     const Filt<T> f = make_filt<T>();
     const OpBufs bb = ob ? *ob : ctx_bufs(c);
     T* buf[2] = {reinterpret_cast<T*>(bb.tmp0), reinterpret_cast<T*>(bb.tmp1)};
@@ -1060,7 +1073,7 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
         ProfScope ps_(c, KID_DWT_STEP, s);
         auto go = [&](auto kern) {
             kern<<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y, pa,
-                                                   xprior, pq_part);
+                                                   xprior, pq_part, skip);
         };
         if (mode == 1) go(k_dwt_step<T, 1>);
         else if (mode == 2) go(k_dwt_step<T, 2>);
@@ -1068,7 +1081,7 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
     }
     ProfScope ps_(c, KID_DWT_COARSE, s);
     auto go = [&](auto kern) {
-        kern<<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, pq_part);
+        kern<<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, pq_part, skip);
     };
     if (mode == 1) go(k_dwt_coarse<T, 1>);
     else if (mode == 2) go(k_dwt_coarse<T, 2>);
@@ -1076,11 +1089,12 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
 }
 
 template <typename T>
-void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s) {
+void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s, const int32_t* skip) {
     ProfScope ps_(c, KID_DATA_TERM, s);
     k_data_term<T><<<c.data_grid, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles),
                                                         c.at<LayerDev>(c.lay.layers), c.at<int32_t>(c.lay.cellidx),
-                                                        c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), psi_nodes);
+                                                        c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), psi_nodes,
+                                                        skip);
 }
 
 template <typename T>
@@ -1091,20 +1105,20 @@ void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted
 }
 
 template <typename T>
-void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s) {
+void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s, const int32_t* skip) {
     ProfScope ps_(c, KID_ADJ_GATHER, s);
     if (c.max_rng <= kRMax) {
         auto go = [&](auto kern) {
             kern<<<c.gather_grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
                                                    c.at<int2>(c.lay.gather_tiles), c.at<int64_t>(c.lay.recbase),
-                                                   c.at<GatherRec<T>>(c.lay.grecs), psi_nodes, psi_layers);
+                                                   c.at<GatherRec<T>>(c.lay.grecs), psi_nodes, psi_layers, skip);
         };
         const bool wide = c.gather_rows > 1;
         auto gow = [&](auto kern) {
             kern<<<c.gather_grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
                                                    c.at<int2>(c.lay.gather_tiles), c.at<int64_t>(c.lay.recbase),
                                                    c.at<GatherRec<T>>(c.lay.grecs), c.at<int4>(c.lay.gwin),
-                                                   psi_nodes, psi_layers);
+                                                   psi_nodes, psi_layers, skip);
         };
         // large systems with windows that fit: LDS-staged sensor nodes
         // (rectangles, extended by RF - 1, of at most 32 x 32 sensor nodes)
@@ -1123,7 +1137,7 @@ void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStrea
         k_adj_gather_wide<T><<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
                                                        c.at<PairDev>(c.lay.pairs), c.at<int32_t>(c.lay.cellidx),
                                                        c.at<T>(c.lay.frac), c.at<int2>(c.lay.ranges), psi_nodes,
-                                                       psi_layers);
+                                                       psi_layers, skip);
     }
 }
 
@@ -1137,15 +1151,16 @@ void launch_fwd_slopes(const Ctx& c, const T* phi, T* slopes, hipStream_t s) {
 }
 
 template <typename T>
-void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s, const OpBufs* ob) {
+void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t s, const OpBufs* ob,
+                    const int32_t* skip) {
     const OpBufs bb = ob ? *ob : ctx_bufs(c);
     T* phi = reinterpret_cast<T*>(bb.nodal);
     T* psi_n = reinterpret_cast<T*>(bb.psi_nodes);
     T* psi_l = reinterpret_cast<T*>(bb.psi_layers);
-    launch_winv<T>(c, x, phi, s, &bb);
-    launch_data_term<T>(c, phi, psi_n, s);
-    launch_adj_gather<T>(c, psi_n, psi_l, s);
-    launch_winvt<T>(c, psi_l, y, x, pq_part, s, &bb);
+    launch_winv<T>(c, x, phi, s, &bb, skip);
+    launch_data_term<T>(c, phi, psi_n, s, skip);
+    launch_adj_gather<T>(c, psi_n, psi_l, s, skip);
+    launch_winvt<T>(c, psi_l, y, x, pq_part, s, &bb, skip);
 }
 
 // slopes NULL: the weighted slope adjoint is already in the sensor-node buffer (the graphed
@@ -1173,12 +1188,12 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
     const int J = int(c.steps.size());
     switch (kid) {
         case KID_IDWT_COARSE:
-            k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], c.at<T>(c.lay.nodal));
+            k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], c.at<T>(c.lay.nodal), nullptr);
             break;
         case KID_IDWT_STEP: {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
             launch_idwt_step<T>(c.steps[step], lays, sl, f, x, buf[step & 1], buf[(step + 1) & 1],
-                                c.at<T>(c.lay.nodal), s);
+                                c.at<T>(c.lay.nodal), s, nullptr);
             break;
         }
         case KID_DATA_TERM:
@@ -1193,13 +1208,13 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
             const int j = J - 1 - step;
             k_dwt_step<T, 1><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * w.nl, kThreads, 0, s>>>(
                 lays, sl + w.loff, w.nb, f, c.at<T>(c.lay.psi_layers), buf[(j + 1) & 1], buf[j & 1], y,
-                c.at<T>(c.lay.prior_a), x, c.at<double>(c.lay.pq_part));
+                c.at<T>(c.lay.prior_a), x, c.at<double>(c.lay.pq_part), nullptr);
             break;
         }
         case KID_DWT_COARSE:
             k_dwt_coarse<T, 1><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J - 1) & 1],
                                                                  y, c.at<T>(c.lay.prior_a), x,
-                                                                 c.at<double>(c.lay.pq_part));
+                                                                 c.at<double>(c.lay.pq_part), nullptr);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1247,13 +1262,15 @@ hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t
 }
 
 #define FEWHA_INSTANTIATE_OP(T)                                                                           \
-    template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t, const OpBufs*);                   \
-    template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, double*, hipStream_t, const OpBufs*); \
-    template void launch_data_term<T>(const Ctx&, const T*, T*, hipStream_t);                             \
+    template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t, const OpBufs*, const int32_t*);   \
+    template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, double*, hipStream_t, const OpBufs*, \
+                                  const int32_t*);                                                        \
+    template void launch_data_term<T>(const Ctx&, const T*, T*, hipStream_t, const int32_t*);             \
     template void launch_slopes_adj<T>(const Ctx&, const T*, T*, int, hipStream_t);                       \
-    template void launch_adj_gather<T>(const Ctx&, const T*, T*, hipStream_t);                            \
+    template void launch_adj_gather<T>(const Ctx&, const T*, T*, hipStream_t, const int32_t*);            \
     template void launch_fwd_slopes<T>(const Ctx&, const T*, T*, hipStream_t);                            \
-    template void launch_apply_M<T>(const Ctx&, const T*, T*, double*, hipStream_t, const OpBufs*);       \
+    template void launch_apply_M<T>(const Ctx&, const T*, T*, double*, hipStream_t, const OpBufs*,        \
+                                    const int32_t*);                                                      \
     template void launch_rhs<T>(const Ctx&, const T*, T*, hipStream_t, double*);                                   \
     template hipError_t time_operator_kernel<T>(Ctx&, int, int, int, hipStream_t, float*);
 

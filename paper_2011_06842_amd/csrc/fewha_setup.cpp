@@ -314,7 +314,7 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.ws_out = take(sizeof(float) * N);
     lo.lconst = take(sizeof(float) * 2 * z.L);
     lo.total = o;
-    lo.state_bytes = 256 + sizeof(double) * size_t(z.B) * z.slots + e * N * (3 + 2 * size_t(z.slots));
+    lo.state_bytes = 256 + sizeof(double) * size_t(z.B) * (z.slots + 1) + e * N * (3 + 2 * size_t(z.slots));
     return lo;
 }
 

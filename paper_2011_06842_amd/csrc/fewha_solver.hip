@@ -190,7 +190,8 @@ __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* 
                                                         const T* __restrict__ b, T* __restrict__ b_prev,
                                                         T* __restrict__ r, const T* __restrict__ mc,
                                                         double* __restrict__ part, Scalars* __restrict__ scs, int m,
-                                                        int npq, const double* __restrict__ bb_part) {
+                                                        int npq, const double* __restrict__ bb_part,
+                                                        int32_t* __restrict__ done) {
     const Seg sg = seg_of(vb, N, npq);
     const double bb_all = block_sum_array(bb_part + sg.pq0, sg.npq);
     const bool bad = !isfinite(bb_all);
@@ -218,6 +219,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(int64_t N, const VecBlk* 
         sc->dropped = 0;
         sc->conv_iter = 0;
         sc->ws_state = 0;
+        if (done) done[sg.inst] = 0;
     }
 }
 
@@ -420,7 +422,7 @@ template <int MB>
 __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, SlotList sl,
                                                                Scalars* __restrict__ scs,
                                                                const InstDev* __restrict__ insts, int ke,
-                                                               const double* __restrict__ gpart) {
+                                                               const double* __restrict__ gpart, int tol_mode) {
     __shared__ double X[2 * kKMax * (kKMax + 1)];     // X, then Y (see k_gram)
     __shared__ double gm[kKMax];
     const InstDev I = insts[blockIdx.x];               // one workgroup per instance
@@ -438,6 +440,18 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     __syncthreads();
     if (threadIdx.x >= 64) return;
     const int k = threadIdx.x, W = m + 1;
+    // tolerance mode: only the last `avail` slots of the window hold this instance's real
+    // directions (an instance that stopped early has fewer); the others are made zero rows and
+    // columns, which both variants skip (zero pivot / zero (p, q)), and are not reported
+    const int hide = tol_mode ? m - min(m, sc->avail) : 0;
+    if (hide > 0) {
+        for (int e = k; e < 2 * m * W; e += 64) {
+            const int row = (e % (m * W)) / W, col = e % W;
+            if (row < hide || col < hide) X[e] = 0.0;
+        }
+        if (k < hide) gm[k] = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    }
     const double v = k < m ? X[k * W + m] : 0.0;   // (U_k, r)
     // the Cholesky factor lives in LDS for both solves below (read back at LDS latency, in
     // order within the wavefront), then goes to the scalars for the kernels after this one
@@ -456,9 +470,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
         y = wave_chol_solve<MB>(sR, skeep, m, v);
         for (int e = k; e < m * m; e += 64) sc->R[e] = sR[e];
         if (k < m) sc->keep[k] = skeep[k];
-        if (k == 0) sc->dropped = dropped;
+        if (k == 0) sc->dropped = dropped - hide;
     }
     if (k < m) sc->y[k] = y;
+    if (k == 0) sc->used = m - hide;
     // Initial direction (condition 1 of Alg. 2): its coefficients solve the same system with
     // the right-hand side (Q_k, z), z = J^-1 r_new, r_new = r - Q y, that is
     // w_k = (J^-1 Q_k, r) - sum_b (J^-1 Q_k, Q_b) y_b
@@ -564,8 +579,9 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
                                                        T* __restrict__ c, T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ jinv, int last, int npq,
                                                        const double* __restrict__ pq_part, double* __restrict__ part,
-                                                       int pslot) {
+                                                       int pslot, const int32_t* __restrict__ skip) {
     const Seg sg = seg_of(vb, N, npq);
+    if (skip && skip[sg.inst]) return;   // tolerance mode: the instance has stopped
     Scalars* __restrict__ sc = scs + sg.inst;
     const double pq = block_sum_array(pq_part + sg.pq0, sg.npq);
     double rz;
@@ -686,11 +702,27 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
                                                        int mp, int project_all, SlotList pl, const T* __restrict__ U,
                                                        Scalars* __restrict__ scs, const T* __restrict__ z,
                                                        const T* __restrict__ p, T* __restrict__ pn,
-                                                       const double* __restrict__ part) {
+                                                       const double* __restrict__ part, double tol,
+                                                       int32_t* __restrict__ done) {
     constexpr int NV = 1 + 2 * MP;
     constexpr int MP1 = MP > 0 ? MP : 1;
     const Seg sg = seg_of(vb, N, 0);
+    if (done && done[sg.inst]) return;   // tolerance mode: the instance has stopped
     Scalars* __restrict__ sc = scs + sg.inst;
+    if (tol > 0) {
+        // tolerance mode: ||r|| <= tol ||b|| after this iteration's update (FP64, from the
+        // partials of (b, b) and (r, r)) stops the instance: no next direction, and every
+        // kernel of the instance returns at once for the rest of the frame
+        double w[2];
+        block_row_sums<2>(part, pstride, sg, P_BB, 2, w);   // rows P_BB, P_RR
+        if (sqrt(w[1]) <= tol * sqrt(w[0])) {
+            if (sg.local == 0 && threadIdx.x == 0) {
+                sc->conv_iter = it + 1;
+                done[sg.inst] = 1;
+            }
+            return;
+        }
+    }
     __shared__ double sy[MP1];
     __shared__ double sbeta;
     __shared__ bool sbroken;
@@ -795,8 +827,9 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
 __device__ __forceinline__ void finish_instance(int b, Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
                                                 int pstride, const double* __restrict__ part,
                                                 fewha_solve_info* __restrict__ infos,
-                                                fewha_solve_info* __restrict__ infos_user, int iters, int tol_mode,
+                                                fewha_solve_info* __restrict__ infos_user, int iters, double tol,
                                                 int64_t* __restrict__ brk) {
+    const bool tol_mode = tol > 0;
     const InstDev I = insts[b];
     const Seg sg{I.off, int(I.n), 0, I.nvb, b, I.vb0, I.pq0, I.npq};
     Scalars* __restrict__ sc = scs + b;
@@ -807,6 +840,9 @@ __device__ __forceinline__ void finish_instance(int b, Scalars* __restrict__ scs
     if (threadIdx.x == 0) {
         fewha_solve_info in;
         const int32_t fl = sc->flags;
+        // the last iteration has no next-direction kernel: its crossing is found here
+        if (tol_mode && sc->conv_iter == 0 && !(fl & kFlagBreakdown) && sqrt(v[1]) <= tol * sqrt(v[0]))
+            sc->conv_iter = iters;
         in.iters = tol_mode && sc->conv_iter ? sc->conv_iter : iters;
         in.recycle_used = sc->used;
         in.dropped = sc->dropped;
@@ -826,8 +862,62 @@ __global__ void __launch_bounds__(kThreads) k_finish(Scalars* __restrict__ scs, 
                                                       int pstride, const double* __restrict__ part,
                                                       fewha_solve_info* __restrict__ infos,
                                                       fewha_solve_info* __restrict__ infos_user, int iters,
-                                                      int tol_mode, int64_t* __restrict__ brk) {
-    finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, tol_mode, brk);
+                                                      double tol, int64_t* __restrict__ brk) {
+    finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, tol, brk);
+}
+
+// End of a tolerance-stopped frame (after the statistics): an instance that stopped after
+// `stop` < cap iterations wrote its directions to ring slots head .. head + stop - 1 only, while
+// the next frame projects against the k slots before head + cap.  Its last k directions (with
+// their (p_j, q_j)) are moved there, read before written since the two windows may overlap.
+// `avail` counts the real directions now at the end of the window: GALERKIN keeps a ring over
+// frames, PAPER only the frame's own directions.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_ring_forward(int64_t N, const VecBlk* __restrict__ vb, int K, int head,
+                                                            int cap, int k, int paper, int first,
+                                                            Scalars* __restrict__ scs, T* __restrict__ U,
+                                                            T* __restrict__ Q) {
+    const Seg sg = seg_of(vb, N, 0);
+    Scalars* __restrict__ sc = scs + sg.inst;
+    const int stop = sc->conv_iter ? sc->conv_iter : cap;
+    if (sg.local == 0 && threadIdx.x == 0) {
+        const int prev = first ? 0 : sc->avail;
+        const int got = paper ? stop : prev + stop;
+        if (stop < cap) {
+            double g[kKMax];
+            for (int a = 0; a < k; ++a) g[a] = sc->gam[(head + stop - k + a + 2 * K) % K];
+            for (int a = 0; a < k; ++a) sc->gam[(head + cap - k + a + 2 * K) % K] = g[a];
+        }
+        sc->avail = got < k ? got : k;
+    }
+    if (stop >= cap) return;
+    for (int64_t j = int64_t(sg.local) * kThreads + threadIdx.x; j < sg.n; j += int64_t(sg.nb) * kThreads) {
+        const int64_t i = sg.off + j;
+        T u[kKMax], q[kKMax];
+#pragma unroll
+        for (int a = 0; a < kKMax; ++a)
+            if (a < k) {
+                const size_t src = size_t((head + stop - k + a + 2 * K) % K) * N + i;
+                u[a] = U[src];
+                q[a] = Q[src];
+            }
+#pragma unroll
+        for (int a = 0; a < kKMax; ++a)
+            if (a < k) {
+                const size_t dst = size_t((head + cap - k + a + 2 * K) % K) * N + i;
+                U[dst] = u[a];
+                Q[dst] = q[a];
+            }
+    }
+}
+
+// avail of every instance to (to_state) or from a checkpoint: a double at base + stride i.
+__global__ void k_state_avail(Scalars* __restrict__ scs, int B, char* __restrict__ base, size_t stride, int to_state) {
+    const int i = int(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= B) return;
+    double* d = reinterpret_cast<double*>(base + stride * size_t(i));
+    if (to_state) *d = double(scs[i].avail);
+    else scs[i].avail = int(*d);
 }
 
 // ------------------------------------------------------------------ warm start
@@ -927,25 +1017,6 @@ __global__ void __launch_bounds__(kThreads) k_ws_step(int64_t N, const VecBlk* _
     }
 }
 
-// Compile-time sizes of the recycle-space loops: exact up to 16, then in steps of 4.
-// Tolerance check after iteration `it1` (1-based): every instance (one workgroup each) with
-// ||r|| <= tol ||b|| (FP64, from the partials of (r, r) and (b, b)) records it1 the first time
-// and raises its done flag.
-__global__ void __launch_bounds__(kThreads) k_check(Scalars* __restrict__ scs, const InstDev* __restrict__ insts,
-                                                     int pstride, const double* __restrict__ part, int it1,
-                                                     double tol, int32_t* __restrict__ done) {
-    const InstDev I = insts[blockIdx.x];
-    const Seg sg{I.off, int(I.n), 0, I.nvb, int(blockIdx.x), I.vb0, I.pq0, I.npq};
-    double v[2];
-    block_row_sums<2>(part, pstride, sg, P_BB, 2, v);   // rows P_BB, P_RR
-    if (threadIdx.x == 0) {
-        Scalars* sc = scs + blockIdx.x;
-        const bool met = sqrt(v[1]) <= tol * sqrt(v[0]);
-        if (met && sc->conv_iter == 0) sc->conv_iter = it1;
-        done[blockIdx.x] = sc->conv_iter != 0 || (sc->flags & kFlagBreakdown) != 0;   // a broken one cannot improve
-    }
-}
-
 // The frame's outputs to the caller in one launch after the graph: the coefficients
 // (c -> c_out, may be null) and, by the first workgroup, the per-instance statistics
 // (info -> info_user, may be null).
@@ -958,13 +1029,14 @@ __global__ void __launch_bounds__(kThreads) k_frame_out(int64_t N, const T* __re
                                                          const double* __restrict__ part,
                                                          fewha_solve_info* __restrict__ infos,
                                                          fewha_solve_info* __restrict__ infos_user, int iters,
-                                                         int64_t* __restrict__ brk) {
-    if (int(blockIdx.x) < B) finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, 0, brk);
+                                                         double tol, int64_t* __restrict__ brk) {
+    if (int(blockIdx.x) < B) finish_instance(blockIdx.x, scs, insts, pstride, part, infos, infos_user, iters, tol, brk);
     if (c_out)
         for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < N; i += int64_t(gridDim.x) * kThreads)
             c_out[i] = c[i];
 }
 
+// Compile-time sizes of the recycle-space loops: exact up to 16, then in steps of 4.
 int bucket(int m) {
     if (m <= 16) return m < 0 ? 0 : m;
     return (m + 3) / 4 * 4;
@@ -994,19 +1066,20 @@ void launch_gal(const VecLaunch& vl, int m, const SlotList& sl, const T* U, cons
     k_galerkin_apply<T, MB><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, m, sl, U, Q, sc, c, r, p, jinv, part);
 }
 
+// done (tolerance mode, else NULL): the per-instance stop flags.
 template <typename T, int MP>
 void launch_upd(const VecLaunch& vl, int it, int mp, const SlotList& pl, const T* U, const T* Q, Scalars* sc,
                 T* p, T* q, T* c, T* r, T* z, const T* jinv, int last, int npq, const double* pq_part,
-                double* part, int pslot, int project_all, T* pn, const Ctx& ctx, hipStream_t s) {
+                double* part, int pslot, int project_all, T* pn, const Ctx& ctx, hipStream_t s, int32_t* done) {
     {
         ProfScope ps_(ctx, KID_UPDATE1, s);
         k_update1<T, MP><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, it, mp, pl, U, Q, sc, p, q, c, r, z,
-                                                      jinv, last, npq, pq_part, part, pslot);
+                                                      jinv, last, npq, pq_part, part, pslot, done);
     }
     if (!last) {
         ProfScope ps_(ctx, KID_UPDATE2, s);
         k_update2<T, MP><<<vl.grid, kThreads, 0, s>>>(vl.N, vl.vb, vl.pstride, it, mp, project_all, pl, U, sc, z, p, pn,
-                                                      part);
+                                                      part, done ? ctx.rel_tol : 0.0, done);
     }
 }
 
@@ -1027,6 +1100,7 @@ struct Frame {
     VecLaunch vl;
     const GramBlk* gt;
     int ke;
+    int32_t* done;   // tolerance mode: per-instance stop flags (NULL with a fixed count)
 
     explicit Frame(const Ctx& c) {
         N = c.N;
@@ -1050,6 +1124,7 @@ struct Frame {
         vl = VecLaunch{N, c.B > 1 ? c.at<VecBlk>(c.lay.vecblk) : nullptr, c.VB, c.VB};
         gt = c.B > 1 ? c.at<GramBlk>(c.lay.gramblk) : nullptr;
         ke = std::max(1, 2 * c.k * (c.k + 1));
+        done = c.rel_tol > 0 ? c.at<int32_t>(c.lay.done) : nullptr;
         m = 0;
         if (!c.first && c.k > 0)
             m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
@@ -1081,7 +1156,7 @@ void enqueue_rhs_residual(const Ctx& c, const Frame<T>& f, const T* slopes, hipS
     if (c.first) launch_apply_M<T>(c, f.cv, f.vx, nullptr, s);
     ProfScope ps_(c, KID_RESIDUAL, s);
     k_residual<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.vl.pstride, f.b, f.bp, f.r,
-                                                 c.first ? f.vx : nullptr, f.part, f.sc, f.m, c.npq, f.pqp);
+                                                 c.first ? f.vx : nullptr, f.part, f.sc, f.m, c.npq, f.pqp, f.done);
 }
 
 // a3 + a4: Galerkin step and initial direction.
@@ -1101,11 +1176,14 @@ void enqueue_galerkin_init(const Ctx& c, const Frame<T>& f, hipStream_t s) {
         {
             ProfScope ps_(c, KID_GRAM_SOLVE, s);
             if (m <= 8)
-                k_gram_solve<8><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart);
+                k_gram_solve<8><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart,
+                                                                 f.done ? 1 : 0);
             else if (m <= 16)
-                k_gram_solve<16><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart);
+                k_gram_solve<16><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart,
+                                                                 f.done ? 1 : 0);
             else
-                k_gram_solve<32><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart);
+                k_gram_solve<32><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart,
+                                                                 f.done ? 1 : 0);
         }
         ProfScope ps_(c, KID_GALERKIN, s);
         switch (f.mb) {
@@ -1126,12 +1204,12 @@ void enqueue_iteration(const Ctx& c, const Frame<T>& f, int it, int last, hipStr
     T* p = f.U + size_t(ps) * f.N;
     T* q = f.Q + size_t(ps) * f.N;
     T* pn = f.U + size_t((c.head + it + 1) % f.K) * f.N;
-    launch_apply_M<T>(c, p, q, f.pqp, s);
+    launch_apply_M<T>(c, p, q, f.pqp, s, nullptr, f.done);
     switch (f.mpb) {
         case 0: launch_upd<T, 0>(f.vl, it, f.mp, f.pl, f.U, f.Q, f.sc, p, q, f.cv, f.r, f.z, f.jinv, last, c.npq,
-                                 f.pqp, f.part, ps, c.project_all, pn, c, s); break;
+                                 f.pqp, f.part, ps, c.project_all, pn, c, s, f.done); break;
 #define X(v) case v: launch_upd<T, v>(f.vl, it, f.mp, f.pl, f.U, f.Q, f.sc, p, q, f.cv, f.r, f.z, f.jinv, last, \
-                                      c.npq, f.pqp, f.part, ps, c.project_all, pn, c, s); break;
+                                      c.npq, f.pqp, f.part, ps, c.project_all, pn, c, s, f.done); break;
         FEWHA_MB_CASES(X)
 #undef X
     }
@@ -1140,8 +1218,18 @@ void enqueue_iteration(const Ctx& c, const Frame<T>& f, int it, int last, hipStr
 template <typename T>
 void enqueue_finish(const Ctx& c, const Frame<T>& f, int iters, fewha_solve_info* info_user, hipStream_t s) {
     ProfScope ps_(c, KID_FINISH, s);
-    k_finish<<<c.B, kThreads, 0, s>>>(f.sc, f.insts, f.vl.pstride, f.part, f.info, info_user, iters,
-                                      c.rel_tol > 0 ? 1 : 0, c.brk_dev);
+    k_finish<<<c.B, kThreads, 0, s>>>(f.sc, f.insts, f.vl.pstride, f.part, f.info, info_user, iters, c.rel_tol,
+                                      c.brk_dev);
+}
+
+// Tolerance mode, after the frame's statistics: move the last directions of instances that
+// stopped early to the end of the recycle window.
+template <typename T>
+void enqueue_ring_forward(const Ctx& c, const Frame<T>& f, hipStream_t s) {
+    if (!f.done || c.k == 0) return;
+    k_ring_forward<T><<<f.vl.grid, kThreads, 0, s>>>(f.N, f.vl.vb, f.K, c.head, c.max_iter, c.k,
+                                                     c.mode == FEWHA_RECYCLE_PAPER ? 1 : 0, c.first ? 1 : 0, f.sc,
+                                                     f.U, f.Q);
 }
 
 // Enqueues one fixed-count frame on stream s (no host-state change, so it can be captured).
@@ -1151,41 +1239,27 @@ void enqueue_frame(const Ctx& c, const T* slopes, fewha_solve_info* info_user, h
     enqueue_rhs_residual<T>(c, f, slopes, s);
     enqueue_galerkin_init<T>(c, f, s);
     for (int it = 0; it < c.max_iter; ++it) enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
-    if (finish) enqueue_finish<T>(c, f, c.max_iter, info_user, s);
+    if (finish) {
+        enqueue_finish<T>(c, f, c.max_iter, info_user, s);
+        enqueue_ring_forward<T>(c, f, s);
+    }
 }
 
-// Frame with direct launches: fixed count, or tolerance mode (the instances iterate in lock
-// step, the recycle ring stays shared; after every iteration each instance records when it
-// first met the tolerance, and every check_every iterations the host reads the done flags
-// and stops once all are set).  `between` runs after the residual update (a warm start).
+// Frame with direct launches (fixed count or tolerance mode; the device decides each
+// instance's stop, so nothing here waits for the device).  `between` runs after the residual
+// update (a warm start).
 template <typename T, typename Hook>
 hipError_t run_frame(Ctx& c, const T* slopes, fewha_solve_info* info_user, hipStream_t s, int* iters, Hook between) {
     const Frame<T> f(c);
-    int32_t* done = c.at<int32_t>(c.lay.done);
-    std::vector<int32_t> hdone(c.B);
     enqueue_rhs_residual<T>(c, f, slopes, s);
     hipError_t e = between(f);
     if (e != hipSuccess) return e;
     enqueue_galerkin_init<T>(c, f, s);
-    int it = 0;
-    for (; it < c.max_iter; ++it) {
-        enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
-        if (c.rel_tol <= 0) continue;
-        k_check<<<c.B, kThreads, 0, s>>>(f.sc, f.insts, f.vl.pstride, f.part, it + 1, c.rel_tol, done);
-        if ((it + 1) % c.check_every == 0 && it + 1 < c.max_iter) {
-            e = hipMemcpyAsync(hdone.data(), done, sizeof(int32_t) * c.B, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) break;
-            if (std::all_of(hdone.begin(), hdone.end(), [](int32_t v) { return v != 0; })) {
-                ++it;
-                break;
-            }
-        }
-    }
-    if (it > c.max_iter) it = c.max_iter;
-    enqueue_finish<T>(c, f, it, info_user, s);
-    *iters = it;
-    return e;
+    for (int it = 0; it < c.max_iter; ++it) enqueue_iteration<T>(c, f, it, it == c.max_iter - 1, s);
+    enqueue_finish<T>(c, f, c.max_iter, info_user, s);
+    enqueue_ring_forward<T>(c, f, s);
+    *iters = c.max_iter;
+    return hipGetLastError();
 }
 
 // Host ring bookkeeping after a frame of `iters` iterations, and the coefficient copy.
@@ -1209,9 +1283,7 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
         m = c.mode == FEWHA_RECYCLE_PAPER ? std::min(c.last_iters, c.k) : std::min(c.count, c.k);
     hipError_t e = hipSuccess;
     int iters = c.max_iter;
-    if (c.rel_tol > 0) {
-        e = run_frame<T>(c, slopes, info_user, s, &iters, [](const Frame<T>&) { return hipSuccess; });
-    } else if (c.use_graphs && !c.prof.on) {
+    if (c.use_graphs && !c.prof.on) {
         // the slope adjoint runs before the graph on the caller's slopes (the graph starts from
         // the sensor-node buffer it fills); the frame statistics and the copy of c follow it
         fewha_solve_info* info = c.at<fewha_solve_info>(c.lay.info);
@@ -1240,7 +1312,8 @@ hipError_t launch_solve_frame(Ctx& c, const T* slopes, T* c_out, fewha_solve_inf
             const int64_t nb = std::max<int64_t>(c.B, ncopy);
             k_frame_out<T><<<unsigned(nb), kThreads, 0, s>>>(c.N, c.at<T>(c.lay.c), c_out, c.B, f.sc, f.insts,
                                                              f.vl.pstride, f.part, info, info_user, c.max_iter,
-                                                             c.brk_dev);
+                                                             c.rel_tol, c.brk_dev);
+            enqueue_ring_forward<T>(c, f, s);
             e = hipGetLastError();
         }
         return end_frame<T>(c, static_cast<T*>(nullptr), iters, e, s);
@@ -1306,6 +1379,14 @@ hipError_t launch_ws_input(const Ctx& c, const WarmStart& w, const T* c_in, cons
     launch_winv<T>(c, z, nod_r, s);
     k_ws_pack<T><<<gN, kThreads, 0, s>>>(c.N, c.at<LayerDev>(c.lay.layers), c.L, c.at<float2>(c.lay.lconst), nod,
                                          nod_r, 1.f / w.scale_c, 1.f / w.scale_r, in);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_avail(const Ctx& c, char* base, size_t stride, bool to_state, hipStream_t s) {
+    const int B = c.B;
+    k_state_avail<<<(B + kThreads - 1) / kThreads, kThreads, 0, s>>>(c.at<Scalars>(c.lay.scalars), B,
+                                                                     base + sizeof(double) * c.slots, stride,
+                                                                     to_state ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -175,6 +175,21 @@ def config_elt_mcao(seed: int = 2, precision: str = "fp32", ground_n: int = 256,
     return fit_layer_grids(spec)
 
 
+def config_elt_full(seed: int = 2, precision: str = "fp32") -> SystemSpec:
+    """The ELT MCAO system of config_elt_mcao plus the three low-order natural guide stars of
+    the paper's MCAO asterism (Sec. 6, system table and asterism figure): one 2x2 and two 1x1
+    Shack-Hartmann sensors on an 80 arcsec radius triangle (azimuths 90, 210, 330 degrees).
+    The layer grids are refitted so that the wider natural-star footprints fit."""
+    spec = config_elt_mcao(seed=seed, precision=precision)
+    D, obs = spec.D, spec.obstruction
+    for ns, az in ((2, 90.0), (1, 210.0), (1, 330.0)):
+        a = np.deg2rad(az)
+        spec.wfs.append(WfsSpec(ns, D / ns, 80.0 * ARCSEC * np.cos(a), 80.0 * ARCSEC * np.sin(a), 0.0,
+                                subaperture_mask(ns, D, obs)))
+    spec.name = "elt_full_" + precision
+    return fit_layer_grids(spec)
+
+
 def config_tiny(seed: int = 3, n: int = 16, levels: int = 3, n_sub: int = 8) -> SystemSpec:
     """Two layers (0 and 6 km) on n x n grids and two 8x8 WFS (one NGS, one LGS at 90 km);
     small enough to assemble every operator densely."""

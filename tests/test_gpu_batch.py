@@ -177,61 +177,86 @@ def test_batch_checkpoint_resume_bitwise():
         single.fewha_set_state(state)
 
 
-def _tolerance_run(specs, seqs, tol, cap, frames):
-    """GPU frames in tolerance mode against oracles that (a) stop at the tolerance, for each
-    instance's first-crossing iteration, and (b) run the frame's lock-step iteration count, for
-    the carried state.  Long CG runs amplify rounding-order differences (a 1e-15 perturbation
-    of the slopes grows to ~1e-6 after ~70 iterations on these systems, oracle against
-    itself), so the coefficients are compared in the residual norm the tolerance bounds: both
-    meet ||r|| <= tol ||b||, hence ||M (c_gpu - c_ref)|| <= 2 tol ||b|| (+ the recursive
-    residual's drift, allowed for by the factor 2.2)."""
-    import copy
-    specs = [sp.copy(rel_tol=tol, max_iter=cap) for sp in specs]
+def _tolerance_run(specs, seqs, tol, cap, frames, precision="fp64", bar=2.2, slack_first=0, slack_rel=0.0):
+    """GPU frames in tolerance mode against one oracle per instance that stops at its own first
+    crossing (the library stops every instance there too; nothing flows from the GPU to the
+    oracles).  Long CG runs amplify rounding-order differences (a 1e-15 perturbation of the
+    slopes grows to ~1e-6 after ~70 iterations on these systems, oracle against itself), so the
+    coefficients are compared in the residual norm the tolerance bounds: both meet
+    ||r|| <= tol ||b||, hence ||M (c_gpu - c_ref)|| <= 2 tol ||b|| plus the drift of the
+    recursive residual (factor `bar`).  Returns per frame the instances' iteration counts."""
+    specs = [sp.copy(rel_tol=tol, max_iter=cap, precision=precision) for sp in specs]
+    dt = np.float64 if precision == "fp64" else np.float32
     batch = len(specs) > 1
     ctx = fw.FewhaContext(specs if batch else specs[0], device=DEV)
     systems = [OracleSystem(sp) for sp in specs]
-    refs = [AugmentedReconstructor(sysm, rel_tol=0.0) for sysm in systems]
+    refs = [AugmentedReconstructor(sysm) for sysm in systems]
     co = ctx.coeff_offsets
     info = ctx.new_info()
-    frame_iters = []
+    its, ratios = [], []
     for t in range(frames):
-        firsts = []
-        for ref, sq in zip(refs, seqs):
-            probe = copy.copy(ref)
-            probe.rel_tol = tol
-            firsts.append(probe.solve(sq[t])[1]["iters"])
-        c = host(ctx.fewha_solve_aug(concat(seqs, t, np.float64), info=info))
+        c = host(ctx.fewha_solve_aug(concat(seqs, t, dt), info=info))
         infos = fw.decode_info(info)
         infos = infos if isinstance(infos, list) else [infos]
-        n_it = ctx.fewha_frame_iterations()
-        frame_iters.append(n_it)
-        # the host stops at the first check (every 4 iterations) after every instance is done
-        assert n_it == min(cap, -(-max(x["iters"] for x in infos) // 4) * 4), (t, n_it, infos)
+        assert ctx.fewha_frame_iterations() == cap
+        row = []
         for i, ref in enumerate(refs):
-            ref.max_iter = n_it
-            c_ref, i_ref = ref.solve(seqs[i][t])
+            s_i = seqs[i][t].astype(dt).astype(np.float64)
+            c_ref, i_ref = ref.solve(s_i)
             ci = c[co[i]:co[i + 1]]
-            b = systems[i].rhs(seqs[i][t])
-            d = systems[i].apply_M(ci - c_ref, refs[i].D)
-            assert np.linalg.norm(d) <= 2.2 * tol * np.linalg.norm(b), (t, i)
-            # exact from the identical first state; afterwards the carried states differ at
-            # the amplified rounding level, so a residual crossing the tolerance between two
+            b = systems[i].rhs(s_i)
+            d = systems[i].apply_M(ci - c_ref, ref.D)
+            # an instance that does not meet the tolerance within the cap is compared at the
+            # residual level both reach
+            level = max(tol, i_ref["rel_res"], infos[i]["rel_res"])
+            ratios.append(np.linalg.norm(d) / (level * np.linalg.norm(b)))
+            assert ratios[-1] <= bar, (t, i, ratios[-1])
+            # exact from the identical first state; afterwards the carried states differ at the
+            # amplified rounding level, so a residual crossing the tolerance between two
             # iterations may land on either side
-            slack = 0 if t == 0 else 1
-            assert abs(infos[i]["iters"] - firsts[i]) <= slack and infos[i]["flags"] == 0, (t, i, infos[i], firsts[i])
-            assert infos[i]["rel_res"] <= tol and i_ref["rel_res"] <= tol
-    return frame_iters
+            slack = max(slack_first if t == 0 else slack_first + 1, slack_rel * i_ref["iters"])
+            assert abs(infos[i]["iters"] - i_ref["iters"]) <= slack, (t, i, infos[i], i_ref)
+            assert infos[i]["flags"] == i_ref["flags"] and i_ref["flags"] in (0, 2), (t, i, infos[i], i_ref)
+            assert infos[i]["recycle_used"] == i_ref["recycle_used"], (t, i, infos[i], i_ref)
+            if i_ref["flags"] == 0:
+                assert infos[i]["rel_res"] <= tol and i_ref["rel_res"] <= tol
+            row.append(infos[i]["iters"])
+        its.append(row)
+    print(f"\niterations per frame and instance: {its}; worst ||M (c - c_ref)|| / (tol ||b||): {max(ratios):.3f}")
+    return its
 
 
 def test_tolerance_mode_single_instance_matches_oracle():
     specs, seqs, _ = known_batch()
     its = _tolerance_run(specs[2:], seqs[2:], 1e-3, 80, 4)
-    assert its[0] > its[-1]          # recycling lowers the iterations to tolerance
+    assert its[0][0] > its[-1][0]          # recycling lowers the iterations to tolerance
 
 
-def test_tolerance_mode_batch_lock_step_matches_oracle():
+@pytest.mark.parametrize("mode", ["galerkin", "paper"])
+def test_tolerance_mode_batch_stops_every_instance_at_its_own_crossing(mode):
+    """Each instance of the batch stops at its own first crossing (the small systems after
+    a few iterations, the 8 m system after tens), and keeps its own recycled directions."""
     specs, seqs, _ = known_batch()
-    _tolerance_run(specs, seqs, 1e-3, 80, 4)
+    its = _tolerance_run([sp.copy(recycle_mode=mode) for sp in specs], seqs, 1e-3, 80, 4)
+    assert len({x for row in its for x in row}) > 1           # the instances stop at different points
+
+
+def test_tolerance_mode_ragged_fp32_matches_oracle():
+    """The ragged batch's own form, on its smallest instances: FP32 operator, tolerance 1e-4,
+    cap 200, random telescopes, sensors and layers; against FP64 oracles per instance in the
+    residual norm (the FP32 recursive residual drifts further from the true one over ~100
+    iterations, so the bar is 3 tol), crossings within 10 % of the oracle's (FP32 CG loses
+    conjugacy over ~100 iterations and needs a few more: 110 against 106 measured), and the
+    same instances missing the tolerance within the cap (flag bit 1) on both sides."""
+    rng = np.random.default_rng(77)
+    specs, seqs = [], []
+    while len(specs) < 3:
+        sp = synth.config_random_instance(rng, precision="fp32")
+        if synth.n_coeffs(sp) > 20_000:
+            continue
+        seqs.append(synth.make_sequence(sp, 3, seed=int(rng.integers(1 << 30))))
+        specs.append(sp)
+    _tolerance_run(specs, seqs, 1e-4, 200, 3, precision="fp32", bar=3.0, slack_first=2, slack_rel=0.1)
 
 
 def test_tolerance_not_met_is_flagged():
@@ -242,6 +267,9 @@ def test_tolerance_not_met_is_flagged():
     ctx.fewha_solve_aug(dev(seqs[2][0], np.float64), info=info)
     gi = fw.decode_info(info)
     assert ctx.fewha_frame_iterations() == 3 and gi["iters"] == 3 and gi["flags"] == 2
+    ref = AugmentedReconstructor(OracleSystem(sp))
+    _, i_ref = ref.solve(seqs[2][0])
+    assert i_ref["flags"] == 2 and i_ref["iters"] == 3
 
 
 def test_large_batch_gather_bitwise_to_single_instances():

@@ -48,6 +48,8 @@ def system(name, precision="fp64"):
             spec, seq = _calibrated(synth.config_small(), 12, seed=5)
         elif name == "elt":
             spec, seq = _calibrated(synth.config_elt_mcao(precision=precision), 8, seed=6)
+        elif name == "elt_full":
+            spec, seq = _calibrated(synth.config_elt_full(precision=precision), 6, seed=7)
         spec.precision = precision
         if seq is None:
             rng = np.random.default_rng(17)
@@ -199,6 +201,17 @@ def test_frame_sequence_elt_fp64():
     assert max(errs) <= 1e-10, errs
 
 
+@pytest.mark.parametrize("precision, tol", [("fp64", 1e-10), ("fp32", 5e-5)])
+def test_frame_sequence_elt_full_loop(precision, tol):
+    """The full ELT loop's system (6 LGS + one 2x2 and two 1x1 low-order NGS): frames from
+    setup against the oracle."""
+    spec, seq, sysm = system("elt_full", precision)
+    errs, infos = _run_sequence(spec, seq, sysm, len(seq))
+    assert max(errs) <= tol, errs
+    for gi, ri in infos:
+        assert gi["recycle_used"] == ri["recycle_used"] and gi["flags"] == 0
+
+
 def test_reset_restarts_from_true_residual():
     spec, seq, sysm = system("small")
     ctx = fw.FewhaContext(spec, device=DEV)
@@ -283,49 +296,66 @@ def test_state_from_other_configuration_rejected():
         b.fewha_set_state(a.fewha_get_state())
 
 
-def oracle_from_gpu_state(ctx, sysm, spec):
-    """An oracle reconstructor whose carried state (c, r, b_prev, recycled directions) is the
-    GPU context's checkpoint, decoded on the host from the documented state layout."""
-    raw = ctx.fewha_get_state().cpu().numpy()
-    hdr = raw[:256].view(np.uint64)
-    N, slots, esz, head, count, last_iters, first = (int(v) for v in hdr[1:8])
+STATE_MAGIC = 0x46455748415354
+
+
+def load_oracle_state(ctx, ref, spec):
+    """Round the oracle reconstructor's carried state (c, r, b_prev, recycled directions) to the
+    context's element type, in place, and write it into the GPU context through
+    fewha_set_state in the documented checkpoint layout (256-byte header of uint64: magic, N,
+    slots, element size, ring head, stored count, previous iterations, first-frame flag,
+    instances; then (p_j, q_j) per slot; c, r, b_prev; U and Q slot-major).  Both sides then
+    continue from the same state; nothing flows from the GPU to the oracle."""
+    esz = 8 if spec.precision == "fp64" else 4
     dt = np.float64 if esz == 8 else np.float32
-    o = 256
-    gam = raw[o:o + 8 * slots].view(np.float64)
-    o += 8 * slots
-    vec = lambda off, n: raw[off:off + esz * n].view(dt).astype(np.float64)
-    c, r, bp = vec(o, N), vec(o + esz * N, N), vec(o + 2 * esz * N, N)
-    o += 3 * esz * N
-    U = raw[o:o + esz * N * slots].view(dt).reshape(slots, N).astype(np.float64)
-    Q = raw[o + esz * N * slots:o + 2 * esz * N * slots].view(dt).reshape(slots, N).astype(np.float64)
-    ref = AugmentedReconstructor(sysm)
-    ref.c, ref.r, ref.b_prev, ref.first = c, r, bp, bool(first)
-    keep = min(last_iters, spec.recycle_k) if spec.recycle_mode == "paper" else min(count, spec.recycle_k)
-    order = [(head - keep + j) % slots for j in range(keep)]
-    ref.store = [(U[s], Q[s], float(gam[s])) for s in order]
-    return ref
+    rnd = lambda v: np.asarray(v, dtype=dt).astype(np.float64)
+    N = ref.sys.N
+    slots = spec.recycle_k + spec.max_iter
+    m = len(ref.store)
+    ref.c, ref.r, ref.b_prev = rnd(ref.c), rnd(ref.r), rnd(ref.b_prev)
+    ref.store = [(rnd(p), rnd(q), float(g)) for p, q, g in ref.store]
+    hdr = np.zeros(32, dtype=np.uint64)
+    hdr[:9] = [STATE_MAGIC, N, slots, esz, m % slots, m, spec.max_iter, int(ref.first), 1]
+    gam = np.zeros(slots + 1)
+    gam[slots] = m
+    U = np.zeros((slots, N), dtype=dt)
+    Q = np.zeros((slots, N), dtype=dt)
+    for j, (p, q, g) in enumerate(ref.store):
+        gam[j], U[j], Q[j] = g, p, q
+    raw = b"".join([hdr.tobytes(), gam.tobytes(), ref.c.astype(dt).tobytes(), ref.r.astype(dt).tobytes(),
+                    ref.b_prev.astype(dt).tobytes(), U.tobytes(), Q.tobytes()])
+    buf = torch.from_numpy(np.frombuffer(raw, dtype=np.uint8).copy()).to(DEV)
+    assert buf.numel() == ctx.fewha_state_size()
+    ctx.fewha_set_state(buf)
 
 
-@pytest.mark.parametrize("precision, frames, tol", [("fp32", 40, 5e-5), ("fp64", 12, 1e-10)])
-def test_elt_frame_map_parity_from_identical_state(precision, frames, tol):
-    """The carried residual is never recomputed, so two implementations with different
-    rounding drift apart slowly over a long sequence (any perturbation of r keeps moving c);
-    the frame update itself is compared from an identical carried state at several points
-    of a longer sequence."""
-    spec, _, sysm = system("elt", precision)
+@pytest.mark.parametrize("name, precision, frames, tol", [("elt", "fp32", 40, 5e-5), ("elt", "fp64", 12, 1e-10),
+                                                          ("elt_full", "fp32", 24, 5e-5),
+                                                          ("elt_full", "fp64", 8, 1e-10)])
+def test_elt_frame_map_parity_from_identical_state(name, precision, frames, tol):
+    """The frame update from an identical carried state at several points of a longer
+    sequence (free-running sequences drift apart by the method's own sensitivity, see the
+    free-running test): the oracle runs the sequence, its state is loaded into the GPU context,
+    and one frame on each side is compared.  elt_full adds the three low-order natural guide
+    stars (one 2x2, two 1x1)."""
+    spec, _, sysm = system(name, precision)
     seq = synth.make_sequence(spec.copy(), frames + 1, seed=20201112)
     dt = np.float64 if precision == "fp64" else np.float32
+    ref = AugmentedReconstructor(sysm)
     ctx = fw.FewhaContext(spec, device=DEV)
+    info = ctx.new_info()
     checks = {1, frames // 2, frames}
     for t in range(frames + 1):
-        s = seq[t].astype(dt)
+        s = seq[t].astype(dt).astype(np.float64)
         if t in checks:
-            ref = oracle_from_gpu_state(ctx, sysm, spec)
-            c_ref, i_ref = ref.solve(s.astype(np.float64))
-            c = host(ctx.fewha_solve_aug(dev(s, dt)))
+            load_oracle_state(ctx, ref, spec)
+            c = host(ctx.fewha_solve_aug(dev(s, dt), info=info))
+            c_ref, i_ref = ref.solve(s)
+            gi = fw.decode_info(info)
             assert rel(c, c_ref) <= tol, (t, rel(c, c_ref))
+            assert gi["recycle_used"] == i_ref["recycle_used"] and gi["flags"] == 0
         else:
-            ctx.fewha_solve_aug(dev(s, dt))
+            ref.solve(s)
 
 
 def test_free_running_elt_fp32_within_the_methods_own_sensitivity():
