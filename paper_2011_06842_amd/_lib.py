@@ -31,7 +31,10 @@ EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", 
            "fewha_unet_workspace_size", "fewha_unet_setup", "fewha_unet_num_params", "fewha_unet_num_nodes",
            "fewha_unet_set_params", "fewha_unet_get_params", "fewha_unet_forward", "fewha_unet_backward",
            "fewha_unet_adam_step", "fewha_unet_get_grads", "fewha_unet_destroy", "fewha_unet_last_error",
-           "fewha_unet_groups", "fewha_solve_aug_ws", "fewha_warmstart_input"]
+           "fewha_unet_groups", "fewha_solve_aug_ws", "fewha_warmstart_input",
+           "fewha_loop_workspace_size", "fewha_loop_setup", "fewha_loop_num_actuators", "fewha_loop_step",
+           "fewha_loop_piece", "fewha_loop_get_commands", "fewha_loop_set_commands", "fewha_loop_destroy", "fewha_loop_last_error"]
+LOOP_DM_SLOPES, LOOP_FIT = 0, 1
 UNET_MAX_GROUPS = 8
 
 
@@ -68,6 +71,17 @@ class fewha_unet_config(C.Structure):
 
 class fewha_warmstart(C.Structure):
     _fields_ = [("scale_c", C.c_float), ("scale_r", C.c_float), ("scale_out", C.c_float)]
+
+
+class fewha_dm(C.Structure):
+    _fields_ = [("height", C.c_double), ("spacing", C.c_double), ("origin_x", C.c_double), ("origin_y", C.c_double),
+                ("n", C.c_int32), ("pad_", C.c_int32)]
+
+
+class fewha_loop_config(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("n_dm", C.c_int32), ("dms", C.POINTER(fewha_dm)), ("gain", C.c_double),
+                ("closed", C.c_int32), ("fit_iter", C.c_int32), ("n_dirs", C.c_int32), ("n_pts", C.c_int32),
+                ("dirs", C.POINTER(C.c_double)), ("pupil_d", C.c_double), ("obstruction", C.c_double)]
 
 
 class FewhaError(RuntimeError):
@@ -127,6 +141,15 @@ def load_library(path: str = LIB_PATH):
         "fewha_unet_groups": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], st),
         "fewha_solve_aug_ws": ([vp, vp, C.POINTER(fewha_warmstart), vp, vp, vp, vp], st),
         "fewha_warmstart_input": ([vp, C.POINTER(fewha_warmstart), vp, vp, vp, vp], st),
+        "fewha_loop_workspace_size": ([vp, C.POINTER(fewha_loop_config), C.POINTER(C.c_size_t)], st),
+        "fewha_loop_setup": ([vp, C.POINTER(fewha_loop_config), vp, C.c_size_t, vp, C.POINTER(vp)], st),
+        "fewha_loop_num_actuators": ([vp, C.POINTER(C.c_int64)], st),
+        "fewha_loop_step": ([vp, vp, vp, vp, vp], st),
+        "fewha_loop_piece": ([vp, C.c_int32, vp, vp, vp], st),
+        "fewha_loop_get_commands": ([vp, C.c_int32, vp, vp], st),
+        "fewha_loop_set_commands": ([vp, vp, vp, vp, vp], st),
+        "fewha_loop_destroy": ([vp], st),
+        "fewha_loop_last_error": ([vp], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -501,6 +524,88 @@ class UNetContext:
         if getattr(self, "net", None):
             self.lib.fewha_unet_destroy(self.net)
             self.net = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class LoopContext:
+    """Closed-loop wrapper (include/fewha_loop.h) around a single-instance FewhaContext `ctx`:
+    `dms` is a list of (height, n, spacing[, origin_x, origin_y]); fit_iter 0 = direct fitting,
+    else that many CG iterations over the fitting directions `dirs` [(theta_x, theta_y)] on an
+    n_pts x n_pts pupil grid of diameter pupil_d and obstruction ratio `obstruction`."""
+
+    def __init__(self, ctx, dms, gain=0.4, closed=True, fit_iter=0, dirs=(), n_pts=0, pupil_d=0.0,
+                 obstruction=0.0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.ctx = ctx
+        arr = (fewha_dm * len(dms))()
+        for i, d in enumerate(dms):
+            d = tuple(d) + (0.0, 0.0)[len(d) - 3:] if len(d) < 5 else tuple(d)
+            arr[i] = fewha_dm(float(d[0]), float(d[2]), float(d[3]), float(d[4]), int(d[1]), 0)
+        dv = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1))
+        cfg = fewha_loop_config()
+        cfg.abi_version, cfg.n_dm, cfg.dms = FEWHA_ABI_VERSION, len(dms), arr
+        cfg.gain, cfg.closed, cfg.fit_iter = float(gain), int(bool(closed)), int(fit_iter)
+        cfg.n_dirs, cfg.n_pts = len(dv) // 2, int(n_pts)
+        cfg.dirs = dv.ctypes.data_as(C.POINTER(C.c_double)) if dv.size else None
+        cfg.pupil_d, cfg.obstruction = float(pupil_d), float(obstruction)
+        self._keep = (arr, dv)
+        n = C.c_size_t()
+        self._lcheck(self.lib.fewha_loop_workspace_size(ctx.ctx, C.byref(cfg), C.byref(n)), None)
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=ctx.device)
+        base = _ptr(self.workspace)
+        lp = C.c_void_p()
+        self._lcheck(self.lib.fewha_loop_setup(ctx.ctx, C.byref(cfg), C.c_void_p(base + (-base) % 256), n.value,
+                                               C.c_void_p(_stream(stream)), C.byref(lp)), None)
+        self.loop = lp
+        na = C.c_int64()
+        self._lcheck(self.lib.fewha_loop_num_actuators(self.loop, C.byref(na)))
+        self.n_act = na.value
+
+    def _lcheck(self, st, use_loop=True):
+        if st != 0:
+            msg = self.lib.fewha_loop_last_error(self.loop if use_loop else None).decode()
+            raise FewhaError(f"{STATUS.get(st, st)}: {msg}")
+
+    def _vec(self, n):
+        import torch
+        return torch.empty(n, dtype=self.ctx.dtype, device=self.ctx.device)
+
+    def step(self, s, a=None, info=None, stream=None):
+        """One frame of Alg. 3; returns the new commands (device tensor)."""
+        s = self.ctx._in(s, self.ctx.S)
+        a = self._vec(self.n_act) if a is None else self.ctx._in(a, self.n_act)
+        ip = _ptr(info) if info is not None else None
+        st = self.lib.fewha_loop_step(self.loop, _ptr(s), _ptr(a), ip, _stream(stream))
+        self.ctx._frame_status(st)
+        return a
+
+    def piece(self, which, x, stream=None):
+        n_in = self.n_act if which == LOOP_DM_SLOPES else self.ctx.N
+        n_out = self.ctx.S if which == LOOP_DM_SLOPES else self.n_act
+        x = self.ctx._in(x, n_in)
+        y = self._vec(n_out)
+        self._lcheck(self.lib.fewha_loop_piece(self.loop, which, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def get_commands(self, which, stream=None):
+        y = self._vec(self.n_act)
+        self._lcheck(self.lib.fewha_loop_get_commands(self.loop, which, _ptr(y), _stream(stream)))
+        return y
+
+    def set_commands(self, prev=None, cur=None, fit=None, stream=None):
+        args = [None if t is None else _ptr(self.ctx._in(t, self.n_act)) for t in (prev, cur, fit)]
+        self._lcheck(self.lib.fewha_loop_set_commands(self.loop, *args, _stream(stream)))
+
+    def destroy(self):
+        if getattr(self, "loop", None):
+            self.lib.fewha_loop_destroy(self.loop)
+            self.loop = None
 
     def __del__(self):
         try:

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfewha.so")
 SOURCES = ["fewha_setup.cpp", "fewha_operator.hip", "fewha_solver.hip", "fewha_capi.cpp", "fewha_unet.hip",
-           "fewha_noalloc.hip"]
+           "fewha_noalloc.hip", "fewha_loop.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

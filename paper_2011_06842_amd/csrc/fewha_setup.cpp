@@ -628,6 +628,18 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
         for (int i = 0; i < nb; ++i)   // the device keeps alpha D
             for (int64_t j = 0; j < ctx.insts[i].n; ++j) t.D[ctx.insts[i].off + j] *= cfgs[i].alpha;
     }
+    // host copies of the layer and sensor descriptors of all instances, in order (the slope
+    // weights are read during setup only: their pointer is not kept)
+    ctx.layers.clear();
+    ctx.wfs.clear();
+    for (int i = 0; i < nb; ++i) {
+        ctx.layers.insert(ctx.layers.end(), cfgs[i].layers, cfgs[i].layers + cfgs[i].n_layers);
+        for (int g = 0; g < cfgs[i].n_wfs; ++g) {
+            fewha_wfs w = cfgs[i].wfs[g];
+            w.slope_weight = nullptr;
+            ctx.wfs.push_back(w);
+        }
+    }
     ctx.layers_n.clear();
     for (const LayerDev& d : t.ld) {
         ctx.layers_n.push_back(d.n);
