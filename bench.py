@@ -115,11 +115,16 @@ def pmc_traffic(kernel, workload):
 
 def pmc_value(kernel, workload, key):
     """Value `key` of `kernel` in `workload` ("single" or "batched") from the committed counter
-    summaries (profiles/*_pmc.md, blocks of "- key: value" lines starting at "- kernel:"), or
-    None when none matches or the sources changed since."""
+    summaries (profiles/*_pmc.md), or None."""
+    return _profile_block_value("*_pmc.md", kernel, workload, key)
+
+
+def _profile_block_value(pattern, kernel, workload, key):
+    """Value `key` from the committed summaries matching `pattern` (blocks of "- key: value"
+    lines starting at "- kernel:"), or None when none matches or the sources changed since."""
     import glob
     sha = source_sha256()
-    for path in sorted(glob.glob(os.path.join(PROFILES, "*_pmc.md"))):
+    for path in sorted(glob.glob(os.path.join(PROFILES, pattern))):
         with open(path) as f:
             lines = f.read().splitlines()
         blocks, cur = [], None
@@ -156,31 +161,35 @@ def copy_probe(mib):
     return 0
 
 
-def run_batch(args, dev):
+BATCH_ATMOSPHERES, BATCH_STRIDE = 4, 2
+
+
+def batch_frames_needed(args):
+    """Frames of each atmosphere the batched leg reads."""
+    B = args.batch
+    A = min(BATCH_ATMOSPHERES, B)
+    F = max(args.batch_warmup + args.batch_steps, 3 + max(3, args.batch_steps // 4))
+    return F + BATCH_STRIDE * ((B + A - 1) // A)
+
+
+def run_batch(args, dev, atmos, t_gen):
     """Throughput form: B independent instances of the ELT geometry in one context (one frame
-    advances all of them).  Instance i reads the slope stream of atmosphere i mod A at a time
-    offset, so that every instance sees its own frames; all share the noise weights, hence
-    one exact Jacobi preconditioner, passed explicitly to the later contexts of the tuner."""
+    advances all of them).  Instance i reads the slope stream of atmosphere i mod A (`atmos`: A
+    (spec, sequence) pairs of seeded ELT atmospheres) at a time offset, so that every instance
+    sees its own frames; all share the noise weights, hence one exact Jacobi preconditioner,
+    passed explicitly to the later contexts of the tuner."""
     import numpy as np
     import torch
 
-    import synth
     import paper_2011_06842_amd as fw
 
     B = args.batch
-    A = min(4, B)
-    stride = 2
+    A = min(BATCH_ATMOSPHERES, B)
+    stride = BATCH_STRIDE
     tune_warm, tune_steps = 3, max(3, args.batch_steps // 4)
     F = max(args.batch_warmup + args.batch_steps, tune_warm + tune_steps)
-    need = F + stride * ((B + A - 1) // A)
-    base = synth.config_elt_mcao(precision="fp32")
-    t0 = time.perf_counter()
-    specs_a, seqs = [], []
-    for a in range(A):
-        sp = base.copy()
-        seqs.append(synth.make_sequence(sp, need, seed=SEED + 1 + a).astype(np.float32))
-        specs_a.append(sp)
-    spec = specs_a[0]
+    seqs = [a[1] for a in atmos]
+    spec = atmos[0][0]
     specs = [spec] * B
     S1 = seqs[0].shape[1]
     frames = torch.empty((F, B * S1), dtype=torch.float32)
@@ -188,8 +197,7 @@ def run_batch(args, dev):
         o = stride * (i // A)
         frames[:, i * S1:(i + 1) * S1] = torch.from_numpy(seqs[i % A][o:o + F])
     frames = frames.to(dev)
-    t_gen = time.perf_counter() - t0
-    log(f"batched leg: {B} instances, slopes generated in {t_gen:.1f} s")
+    log(f"batched leg: {B} instances")
     it, m = spec.max_iter, spec.recycle_k
     mp = 1
 
@@ -310,25 +318,24 @@ def _ragged_instance(args):
     return sp, seq
 
 
-def run_ragged(args, dev):
+def ragged_inputs(ex, args):
+    """Seeded random instances of the ragged leg and their slope sequences (process pool)."""
+    F = args.ragged_warmup + args.ragged_steps
+    return list(ex.map(_ragged_instance, [(SEED + 1000 + 7 * i, F) for i in range(args.ragged)]))
+
+
+def run_ragged(args, dev, pairs, t_gen):
     """Ragged batch: independent random instances (telescope 8-39 m, 20-84 subapertures, 3-9
     layers, 1-6 NGS/LGS, grids up to 256^2), FP32 operator, every instance stopping at its own
     first ||r|| <= 1e-4 ||b|| (cap 200) on the device; the frame is one graph replay."""
     import numpy as np
     import torch
-    from concurrent.futures import ProcessPoolExecutor
 
     import paper_2011_06842_amd as fw
 
     B = args.ragged
-    F = args.ragged_warmup + args.ragged_steps
-    t0 = time.perf_counter()
-    workers = max(1, min(16, os.cpu_count() or 1, B))
-    with ProcessPoolExecutor(max_workers=workers) as ex:
-        pairs = list(ex.map(_ragged_instance, [(SEED + 1000 + 7 * i, F) for i in range(B)]))
     specs = [p[0] for p in pairs]
-    t_gen = time.perf_counter() - t0
-    log(f"ragged leg: {B} instances, slopes generated in {t_gen:.1f} s ({workers} processes)")
+    log(f"ragged leg: {B} instances")
     frames = torch.from_numpy(np.concatenate([p[1] for p in pairs], axis=1)).to(dev)
     t0 = time.perf_counter()
     ctx = fw.FewhaContext(specs, device=dev)
@@ -451,7 +458,13 @@ def _elt_sequence(arg):
     return sp, synth.make_sequence(sp, frames, seed=seed + 7).astype(np.float32)
 
 
-def run_warmstart(args, dev):
+def warmstart_inputs(ex, args):
+    """ELT sequences of the warm-start leg: training, validation, evaluation and batch."""
+    seeds = [SEED + 300 + 11 * i for i in range(args.ws_train + 1 + args.ws_batch)]
+    return list(ex.map(_elt_sequence, [(sd, args.ws_frames) for sd in seeds]))
+
+
+def run_warmstart(args, dev, seqs, t_gen):
     """Plain, learned-warm-start and batched augmented PCG on the ELT system at equal final
     residual (every frame iterated to ||r|| <= 1e-3 ||b||, cap 200).  The network is trained
     here on converged solves (256 iterations) of seeded training sequences with their own
@@ -459,19 +472,13 @@ def run_warmstart(args, dev):
     three forms run on a held-out evaluation sequence (the batch adds further sequences)."""
     import numpy as np
     import torch
-    from concurrent.futures import ProcessPoolExecutor
 
     import paper_2011_06842_amd as fw
     from paper_2011_06842_amd import warmstart as W
 
     tol, cap, F = 1e-3, 200, args.ws_frames
     nt, B = args.ws_train, args.ws_batch
-    t0 = time.perf_counter()
-    seeds = [SEED + 300 + 11 * i for i in range(nt + 1 + B)]   # training, validation, evaluation + batch
-    with ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1, len(seeds)))) as ex:
-        seqs = list(ex.map(_elt_sequence, [(sd, F) for sd in seeds]))
-    t_gen = time.perf_counter() - t0
-    log(f"warm start: {len(seqs)} ELT sequences of {F} frames generated in {t_gen:.1f} s")
+    log(f"warm start: {len(seqs)} ELT sequences of {F} frames")
     base = seqs[0][0]
     spec = base.copy(rel_tol=tol, max_iter=cap)
     truth = base.copy(rel_tol=1e-6, max_iter=256)
@@ -573,16 +580,432 @@ def synth_n(spec):
     return int(sum(l.n * l.n for l in spec.layers))
 
 
+# ---------------------------------------------------------------- inputs and CPU baselines
+
+def host_cpu_info():
+    """Host CPU: model name, logical CPUs, and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"model": model, "nproc": os.cpu_count(), "affinity": avail}
+
+
+def pool_size():
+    """Worker processes for input generation and the all-core baseline (at most 16)."""
+    return max(1, min(16, host_cpu_info()["affinity"]))
+
+
+def make_config(name):
+    import synth
+    if name == "elt":
+        return synth.config_elt_mcao(precision="fp32")
+    if name == "full":
+        return synth.config_elt_full(precision="fp32")
+    if name == "small":
+        return synth.config_small()
+    raise ValueError(name)
+
+
+def _seq_chunk(arg):
+    """(calibrated spec, frames start..start+n-1) of one configuration (pool worker; every frame
+    depends on its index and the seed only, so chunks concatenate to the serial sequence)."""
+    import numpy as np
+    import synth
+    name, seed, start, n = arg
+    sp = make_config(name)
+    seq = synth.make_sequence(sp, n, seed=seed, start=start)
+    return sp, seq.astype(np.float32 if sp.precision == "fp32" else np.float64)
+
+
+def gen_sequence(ex, name, seed, frames, chunk=25):
+    import numpy as np
+    parts = list(ex.map(_seq_chunk, [(name, seed, s, min(chunk, frames - s)) for s in range(0, frames, chunk)]))
+    return parts[0][0], np.concatenate([p[1] for p in parts])
+
+
+_BARRIER = None
+
+
+def _set_barrier(b):
+    global _BARRIER
+    _BARRIER = b
+
+
+def _oracle_run(arg):
+    """The FP64 oracle on consecutive frames in one thread: (setup s, per-frame s, solutions).
+    `perturb` > 0 multiplies every slope by (1 + perturb * N(0, 1)) (seeded): the oracle's own
+    sensitivity to input rounding of that relative size.  `sync` waits for the other workers of
+    an all-core run after setup."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import AugmentedReconstructor, OracleSystem
+    spec, seq, keep, perturb, sync = arg
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        rec = AugmentedReconstructor(OracleSystem(spec))
+        setup = time.perf_counter() - t0
+        rng = np.random.default_rng(SEED + 5)
+        if sync:
+            _BARRIER.wait(timeout=900)
+        ts, sols = [], []
+        for t in range(len(seq)):
+            s = np.asarray(seq[t], dtype=np.float64)
+            if perturb:
+                s = s * (1.0 + perturb * rng.standard_normal(s.size))
+            w0 = time.perf_counter()
+            c, _ = rec.solve(s)
+            ts.append(time.perf_counter() - w0)
+            if keep:
+                sols.append(c)
+    return setup, ts, sols
+
+
+def _oracle_loop_run(arg):
+    """The FP64 closed-loop oracle of the full ELT loop on consecutive open-loop frames: the
+    commands after every frame (the measured slopes are the open-loop ones minus the oracle's
+    own DM slopes of a^(i-1), rounded to the slope precision)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle import AugmentedReconstructor, OracleSystem
+    from oracle.closed_loop import ClosedLoopOracle, DmSpec
+    spec, seq, n_pts, fit_iter, gain = arg
+    with threadpool_limits(limits=1):
+        ref = ClosedLoopOracle(AugmentedReconstructor(OracleSystem(spec)), [DmSpec(*d) for d in synth.elt_mcao_dms()],
+                               gain=gain, closed=True, fit_dirs=synth.mcao_fit_directions(), n_pts=n_pts,
+                               fit_iter=fit_iter)
+        out, ts = [], []
+        for t in range(len(seq)):
+            s = (np.asarray(seq[t], dtype=np.float64) - ref.dm_slopes(ref.a_prev)).astype(seq.dtype).astype(np.float64)
+            w0 = time.perf_counter()
+            a, _ = ref.step(s)
+            ts.append(time.perf_counter() - w0)
+            out.append(a.copy())
+    return out, ts
+
+
+def frame_stats(ts_s, it):
+    import numpy as np
+    ms = 1000.0 * np.asarray(ts_s)
+    return {"frame_ms_p50": round(float(np.percentile(ms, 50)), 3),
+            "frame_ms_p99": round(float(np.percentile(ms, 99)), 3),
+            "applies_per_s": round(it * len(ms) / float(ms.sum() * 1e-3), 3), "frames": int(len(ms))}
+
+
+def cpu_baselines(spec, seq, n_single, n_all, workers):
+    """Single-thread and all-core figures of the FP64 oracle on the first frames of `seq`:
+    one process (one BLAS/NumPy thread) for the single-thread figure and its solutions, one
+    more with the slopes perturbed at FP32 rounding size (2^-24), then `workers` processes each
+    solving the same frames concurrently after a common start (aggregate applies/s over the
+    span from the common start to the last finish)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    ctx = mp.get_context("fork")
+    it = spec.max_iter
+    with ProcessPoolExecutor(max_workers=2, mp_context=ctx) as ex:
+        f1 = ex.submit(_oracle_run, (spec, seq[:n_single], True, 0.0, False))
+        f2 = ex.submit(_oracle_run, (spec, seq[:n_single], True, 2.0 ** -24, False))
+        setup1, ts1, sols = f1.result()
+        _, _, sols_p = f2.result()
+    barrier = ctx.Barrier(workers)
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx, initializer=_set_barrier,
+                             initargs=(barrier,)) as ex:
+        res = list(ex.map(_oracle_run, [(spec, seq[:n_all], False, 0.0, True)] * workers))
+    # every worker starts its frames when the last one has finished setup: the span is the
+    # longest worker's loop
+    span = max(sum(r[1]) for r in res)
+    all_ts = [t for r in res for t in r[1]]
+    single = frame_stats(ts1, it)
+    allc = frame_stats(all_ts, it)
+    allc["applies_per_s"] = round(it * len(all_ts) / span, 3)
+    single["setup_s"] = round(setup1, 2)
+    return single, allc, sols, sols_p
+
+
+# ---------------------------------------------------------------- GPU legs
+
+def time_frames(ctx, slopes, t0, n, c, info):
+    """Frames t0..t0+n-1 (each a graph replay), one HIP event after each on the context's stream:
+    (wall s, per-frame ms)."""
+    import numpy as np
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev[0].record()
+    for k in range(n):
+        ctx.fewha_solve_aug(slopes[t0 + k], c, info)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return wall, np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(n)])
+
+
+def kernel_stats_value(kernel, workload, key):
+    """Value `key` of `kernel` in `workload` from the committed kernel-trace summaries
+    (profiles/*_kernel_stats.md, same block format as the counter summaries), or None."""
+    return _profile_block_value("*_kernel_stats.md", kernel, workload, key)
+
+
+def run_small(args, dev, spec, seq):
+    """The 8 m FP64 system (3 NGS, 40x40 subapertures, 3 layers on 64^2 grids, 4 levels, 10
+    PCG iterations, k = 5): frame latency over the whole sequence and applies/s."""
+    import numpy as np
+    import torch
+    import paper_2011_06842_amd as fw
+    slopes = torch.from_numpy(seq).to(dev)
+    ctx = fw.FewhaContext(spec, device=dev)
+    c = torch.empty(ctx.N, dtype=torch.float64, device=dev)
+    info = ctx.new_info()
+    W = min(args.warmup, len(seq) // 10)
+    time_frames(ctx, slopes, 0, W, c, info)
+    wall, ms = time_frames(ctx, slopes, W, len(seq) - W, c, info)
+    it = spec.max_iter
+    return {"workload": "small_8m_3ngs_fp64_single_instance", "N": ctx.N, "S": ctx.S, "pcg_iters": it,
+            "recycle_k": spec.recycle_k, "frames": len(seq) - W, "warmup": W,
+            "frame_ms_p50": round(float(np.percentile(ms, 50)), 4),
+            "frame_ms_p99": round(float(np.percentile(ms, 99)), 4),
+            "applies_per_s": round(it * (len(seq) - W) / wall, 1)}
+
+
+def run_full_loop(args, dev, spec, seq):
+    """The full ELT loop (6 LGS + 3 low-order NGS, FP32 operator with FP64 reductions): Alg. 3
+    in closed loop with the three MCAO DMs, least-squares fitting by 4 CG iterations over the
+    5 x 5 science directions, gain 0.4, over the whole sequence.  The measured slopes of frame i
+    are the open-loop ones minus the DM slopes of a^(i-1) (the telescope's part, computed
+    outside the timed region); each loop step is bracketed by HIP events on the stream."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2011_06842_amd as fw
+    ctx = fw.FewhaContext(spec, device=dev)
+    loop = fw.LoopContext(ctx, synth.elt_mcao_dms(), gain=args.loop_gain, closed=True, fit_iter=args.loop_fit_iter,
+                          dirs=synth.mcao_fit_directions(), n_pts=args.loop_pts, pupil_d=spec.D,
+                          obstruction=spec.obstruction)
+    slopes = torch.from_numpy(seq).to(dev)
+    a_next = torch.zeros(loop.n_act, dtype=torch.float32, device=dev)
+    info = ctx.new_info()
+    n = len(seq)
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    early = []
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for t in range(n):
+        s = slopes[t] - loop.piece(fw.LOOP_DM_SLOPES, loop.get_commands(0))
+        ev0[t].record()
+        loop.step(s, a_next, info)
+        ev1[t].record()
+        if t < args.loop_check_frames:
+            early.append(a_next.double().cpu().numpy())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = np.array([ev0[t].elapsed_time(ev1[t]) for t in range(n)])
+    W = min(args.warmup, n // 10)
+    m = ms[W:]
+    budget = 2.0
+    return {"workload": "elt_full_loop_fp32 (6 LGS 84x84 + NGS 2x2, 1x1, 1x1; 3 DMs; CG fitting over 5x5 "
+                        "directions)", "N": ctx.N, "S": ctx.S, "actuators": loop.n_act,
+            "frames": int(len(m)), "warmup": W, "fit_iter": args.loop_fit_iter, "fit_pupil_points": args.loop_pts,
+            "loop_step_ms_p50": round(float(np.percentile(m, 50)), 4),
+            "loop_step_ms_p99": round(float(np.percentile(m, 99)), 4),
+            "loop_step_ms_max": round(float(m.max()), 4),
+            "budget_ms": budget, "frames_over_budget": int((m > budget).sum()),
+            "wall_s": round(wall, 2), "note": "HIP events around each loop step; the DM slopes that form the "
+                                                "measured slopes run between steps"}, early
+
+
+def run_single(args, dev, spec, seq):
+    """ELT single instance: the timed frames (value), a longer latency pass, the event-timed
+    kernel profile, the per-kernel timer and the per-frame algorithmic-bytes fraction."""
+    import numpy as np
+    import torch
+    import paper_2011_06842_amd as fw
+    slopes = torch.from_numpy(seq).to(dev)                  # resident in HBM before timing
+    ctx = fw.FewhaContext(spec, device=dev)
+    N, S = ctx.N, ctx.S
+    V = sum((w.n_sub + 1) ** 2 for w in spec.wfs)
+    c = torch.empty(N, dtype=torch.float32, device=dev)
+    info = ctx.new_info()
+    time_frames(ctx, slopes, 0, args.warmup, c, info)
+    wall, frame_ms = time_frames(ctx, slopes, args.warmup, args.steps, c, info)
+    last_info = fw.decode_info(info)
+    it = spec.max_iter
+    # latency pass: the rest of the sequence
+    L0 = args.warmup + args.steps
+    lat_wall, lat_ms = time_frames(ctx, slopes, L0, len(seq) - L0, c, info) if len(seq) > L0 else (wall, frame_ms)
+    if len(seq) <= L0:
+        lat_ms = frame_ms
+    lat_all = np.concatenate([frame_ms, lat_ms]) if len(seq) > L0 else frame_ms
+
+    # operator alone (pure M applications, same stream)
+    x = torch.randn(N, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(10):
+        ctx.fewha_apply_A(x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    R = 200
+    e0.record()
+    for _ in range(R):
+        ctx.fewha_apply_A(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    op_ms = e0.elapsed_time(e1) / R
+    log(f"single instance: frame p50 {np.median(lat_all):.4f} ms over {len(lat_all)} frames, apply {1000 * op_ms:.1f} us")
+
+    # per-kernel durations from HIP events around every launch of a fresh run of the same
+    # frames (profiling synchronises per call, so it runs outside the timed region)
+    pctx = fw.FewhaContext(spec, device=dev)
+    pc = torch.empty_like(c)
+    for t in range(args.warmup):
+        pctx.fewha_solve_aug(slopes[t], pc)
+    pctx.fewha_profile(True)
+    P = min(args.profile_frames, args.steps)
+    for t in range(P):
+        pctx.fewha_solve_aug(slopes[args.warmup + t], pc)
+    prof = pctx.fewha_profile_read()
+    pctx.fewha_profile(False)
+    del pctx
+    kernels = {name: {"ms_per_frame": ms / P, "launches_per_frame": nl / P, "avg_launch_us": 1000 * ms / nl}
+               for name, (ms, nl) in prof.items() if nl}
+
+    # operator kernels one at a time: R launches with the frame's own arguments, captured in
+    # one graph and replayed between two HIP events on the context's stream
+    steps = ctx.fewha_wavelet_steps()
+    e = 4
+    m, mp = spec.recycle_k, 1
+    opk = {}
+    for kid, name in enumerate(OP_KERNELS):
+        for st in (range(len(steps)) if name.endswith("_step") else [None]):
+            us = 1000 * ctx.fewha_time_kernel(kid, st or 0, args.kernel_reps)
+            b = op_kernel_bytes(name, st, spec, steps, N, S, V, e)
+            key = name if st is None else f"{name}[{steps[st][0]}x{steps[st][0]} x{steps[st][1]}]"
+            opk[key] = {"kernel": name, "avg_us": round(us, 3), "bytes": b, "GB_s": round(b / us * 1e-3, 1)}
+    # per kernel function: launches per frame (event profile), the timer's duration of each
+    # launch shape, and the algorithmic bytes of the frame's launches (a tiled kernel's launches
+    # spread evenly over its levels)
+    per_kernel = {}
+    for v in opk.values():
+        k = v["kernel"]
+        nst = len(steps) if k.endswith("_step") else 1
+        nl = kernels.get(k, {}).get("launches_per_frame", 0) / nst
+        pk = per_kernel.setdefault(k, {"us_per_frame": 0.0, "bytes_per_frame": 0.0, "launches_per_frame": 0.0})
+        pk["us_per_frame"] += v["avg_us"] * nl
+        pk["bytes_per_frame"] += v["bytes"] * nl
+        pk["launches_per_frame"] += nl
+        v["us_per_frame"] = round(v["avg_us"] * nl, 2)
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["us_per_frame"])
+    d = per_kernel[dom]
+    bpl = d["bytes_per_frame"] / d["launches_per_frame"]
+    avg_us = d["us_per_frame"] / d["launches_per_frame"]
+    achieved = bpl / (avg_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": pmc_traffic(dom, "single"),
+                "bytes_per_launch": round(bpl, 1), "avg_launch_us": round(avg_us, 3),
+                "launches_per_frame": d["launches_per_frame"],
+                "duration_source": "HIP events around graph replays of the kernel's launches with the frame's "
+                                   "arguments, weighted by their launches per frame",
+                "share_of_frame": round(d["us_per_frame"] * 1e-3 / float(np.median(frame_ms)), 3)}
+    rp = kernel_stats_value(dom, "single", "avg_launch_us")
+    if rp:
+        roofline["rocprof_avg_launch_us"] = rp
+        roofline["frac_rocprof"] = round(bpl / (rp * 1e-6) / 1e9 / HBM_PEAK_GBS, 5)
+    # the whole frame: algorithmic bytes of every launch over the frame time
+    fb = sum(pk["bytes_per_frame"] for pk in per_kernel.values())
+    for name, kv in kernels.items():
+        if name not in OP_KERNELS:
+            fb += frame_kernel_bytes(name, N, S, V, e, m, it, mp)
+    p50 = float(np.median(lat_all))
+    frame_frac = {"bytes_per_frame": round(fb), "frame_ms_p50": round(p50, 4),
+                  "achieved_GB_s": round(fb / (p50 * 1e-3) / 1e9, 1),
+                  "frac": round(fb / (p50 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(it * args.steps / wall, 1),
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000 * wall / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "elt_mcao_fp32_single_instance", "telescope_m": spec.D,
+                   "lgs": len(spec.wfs), "n_sub": spec.wfs[0].n_sub,
+                   "layers": [l.n for l in spec.layers], "wavelet_levels": spec.layers[0].levels,
+                   "pcg_iters": it, "recycle_k": spec.recycle_k, "recycle_mode": spec.recycle_mode,
+                   "N": N, "S": S, "reductions": "f64", "frames_generated": len(seq),
+                   "input": "seeded frozen-flow von Karman screens, SNR-10 slope noise"},
+        "frame_ms_p50": round(float(np.percentile(lat_all, 50)), 4),
+        "frame_ms_p99": round(float(np.percentile(lat_all, 99)), 4),
+        "latency_frames": int(len(lat_all)),
+        "timed_frames_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
+        "frames_per_s": round(args.steps / wall, 1),
+        "operator_apply_ms": round(op_ms, 4),
+        "operator_applies_per_s_alone": round(1000.0 / op_ms, 1),
+        "last_frame_rel_res": last_info["rel_res"],
+        "roofline": roofline,
+        "frame_roofline": frame_frac,
+        "kernel_launches_per_frame": round(sum(k["launches_per_frame"] for k in kernels.values()), 2),
+        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
+                    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_frame"])},
+        "operator_kernels": opk,
+        "paper_context": "CPU aug. FEWHA MCAO 1.9 ms/frame on 12 Haswell cores (different system size)",
+    }
+    return out, ctx
+
+
+def free_running_errors(spec, slopes_dev, sols, sols_p, dev):
+    """A fresh GPU context over the frames the oracle solved: relative error of every frame's
+    coefficients against the FP64 oracle, next to the oracle's own drift under input
+    perturbations of FP32 rounding size (the method's sensitivity over the same frames)."""
+    import numpy as np
+    import paper_2011_06842_amd as fw
+    vctx = fw.FewhaContext(spec, device=dev)
+    errs, sens = [], []
+    for t, ref in enumerate(sols):
+        g = vctx.fewha_solve_aug(slopes_dev[t]).double().cpu().numpy()
+        errs.append(float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
+        sens.append(float(np.linalg.norm(sols_p[t] - ref) / np.linalg.norm(ref)))
+    return {"frames": len(sols), "max": max(errs), "last": errs[-1], "per_frame": [float(f"{x:.3e}") for x in errs],
+            "oracle_sensitivity_2^-24": [float(f"{x:.3e}") for x in sens]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-frames", type=int, default=20)
+    ap.add_argument("--latency-frames", type=int, default=2000,
+                    help="frames of the single-instance sequence (timed frames first, the rest a latency pass)")
+    ap.add_argument("--cpu-frames", type=int, default=20, help="frames of the single-thread oracle baseline")
+    ap.add_argument("--cpu-frames-all", type=int, default=5, help="frames per process of the all-core baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-frames", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
+    ap.add_argument("--small", type=int, default=1, help="8 m FP64 leg (0: skip)")
+    ap.add_argument("--small-frames", type=int, default=2000)
+    ap.add_argument("--loop", type=int, default=1, help="full ELT closed-loop leg (0: skip)")
+    ap.add_argument("--loop-frames", type=int, default=2000)
+    ap.add_argument("--loop-check-frames", type=int, default=5, help="loop frames compared with the oracle")
+    ap.add_argument("--loop-fit-iter", type=int, default=4)
+    ap.add_argument("--loop-pts", type=int, default=40)
+    ap.add_argument("--loop-gain", type=float, default=0.4)
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--batch-warmup", type=int, default=5)
@@ -605,173 +1028,96 @@ def main(argv=None):
               "multi-GPU path (--gpus must be 1)", file=sys.stderr)
         return 2
 
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
     import numpy as np
-    import torch
 
-    import synth
-    import paper_2011_06842_amd as fw
-
-    dev = "cuda:0"
-    spec = synth.config_elt_mcao(precision="fp32")
-    F = args.warmup + args.steps
-    t_gen = time.perf_counter()
-    seq64 = synth.make_sequence(spec, F, seed=SEED)
-    t_gen = time.perf_counter() - t_gen
-    seq32 = seq64.astype(np.float32)
-    log(f"single instance: {F} frames generated in {t_gen:.1f} s")
-    slopes = torch.from_numpy(seq32).to(dev)                  # resident in HBM before timing
-    ctx = fw.FewhaContext(spec, device=dev)
-    N, S = ctx.N, ctx.S
-    V = sum((w.n_sub + 1) ** 2 for w in spec.wfs)
-    c = torch.empty(N, dtype=torch.float32, device=dev)
-    info = ctx.new_info()
-
-    for t in range(args.warmup):
-        ctx.fewha_solve_aug(slopes[t], c, info)
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
+    # inputs and CPU baselines first, in forked processes, before anything touches the GPU
+    workers = pool_size()
+    F = max(args.warmup + args.steps, args.latency_frames)
     t0 = time.perf_counter()
-    ev[0].record()
-    for k in range(args.steps):
-        ctx.fewha_solve_aug(slopes[args.warmup + k], c, info)
-        ev[k + 1].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    frame_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
-    last_info = fw.decode_info(info)
-    it = spec.max_iter
-    applies_per_s = it * args.steps / wall
-
-    # operator alone (pure M applications, same stream)
-    x = torch.randn(N, dtype=torch.float32, device=dev)
-    y = torch.empty_like(x)
-    for _ in range(10):
-        ctx.fewha_apply_A(x, y)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    R = 200
-    e0.record()
-    for _ in range(R):
-        ctx.fewha_apply_A(x, y)
-    e1.record()
-    torch.cuda.synchronize()
-    op_ms = e0.elapsed_time(e1) / R
-    log(f"single instance: frame p50 {np.median(frame_ms):.4f} ms, apply {1000 * op_ms:.1f} us")
-
-    # per-kernel durations from HIP events around every launch of a fresh run of the same
-    # frames (profiling synchronises per call, so it runs outside the timed region)
-    pctx = fw.FewhaContext(spec, device=dev)
-    pc = torch.empty_like(c)
-    for t in range(args.warmup):
-        pctx.fewha_solve_aug(slopes[t], pc)
-    pctx.fewha_profile(True)
-    P = min(args.profile_frames, args.steps)
-    for t in range(P):
-        pctx.fewha_solve_aug(slopes[args.warmup + t], pc)
-    prof = pctx.fewha_profile_read()
-    pctx.fewha_profile(False)
-    kernels = {name: {"ms_per_frame": ms / P, "launches_per_frame": nl / P, "avg_launch_us": 1000 * ms / nl}
-               for name, (ms, nl) in prof.items() if nl}
-
-    # operator kernels one at a time: R launches with the frame's own arguments, captured in
-    # one graph and replayed between two HIP events on the context's stream
-    steps = ctx.fewha_wavelet_steps()
-    e = 4
-    opk = {}
-    for kid, name in enumerate(OP_KERNELS):
-        for st in (range(len(steps)) if name.endswith("_step") else [None]):
-            us = 1000 * ctx.fewha_time_kernel(kid, st or 0, args.kernel_reps)
-            b = op_kernel_bytes(name, st, spec, steps, N, S, V, e)
-            key = name if st is None else f"{name}[{steps[st][0]}x{steps[st][0]} x{steps[st][1]}]"
-            opk[key] = {"kernel": name, "avg_us": round(us, 3), "bytes": b, "GB_s": round(b / us * 1e-3, 1)}
-    # dominant operator kernel: largest time per frame (timed duration x launches per frame,
-    # a tiled kernel's launches spread evenly over its levels)
-    for v in opk.values():
-        nst = len(steps) if v["kernel"].endswith("_step") else 1
-        v["us_per_frame"] = round(v["avg_us"] * kernels.get(v["kernel"], {}).get("launches_per_frame", 0) / nst, 2)
-    per_kernel = {}
-    for v in opk.values():
-        per_kernel[v["kernel"]] = per_kernel.get(v["kernel"], 0.0) + v["us_per_frame"]
-    dom = max(per_kernel, key=per_kernel.get)
-    dk = max((k for k, v in opk.items() if v["kernel"] == dom), key=lambda k: opk[k]["avg_us"])
-    d = opk[dk]
-    achieved = d["bytes"] / (d["avg_us"] * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": dk, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": pmc_traffic(dk, "single"),
-                "bytes_per_launch": d["bytes"], "avg_launch_us": d["avg_us"],
-                "share_of_frame": round(per_kernel[dom] * 1e-3 / float(np.median(frame_ms)), 3)}
-
-    out = {
-        "metric": METRIC,
-        "value": round(applies_per_s, 1),
-        "unit": "applies/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1000 * wall / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "elt_mcao_fp32_single_instance", "telescope_m": spec.D,
-                   "lgs": len(spec.wfs), "n_sub": spec.wfs[0].n_sub,
-                   "layers": [l.n for l in spec.layers], "wavelet_levels": spec.layers[0].levels,
-                   "pcg_iters": it, "recycle_k": spec.recycle_k, "recycle_mode": spec.recycle_mode,
-                   "N": N, "S": S, "reductions": "f64", "frames_generated": F,
-                   "input": "seeded frozen-flow von Karman screens, SNR-10 slope noise"},
-        "frame_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
-        "frame_ms_p99": round(float(np.percentile(frame_ms, 99)), 4),
-        "frames_per_s": round(args.steps / wall, 1),
-        "operator_apply_ms": round(op_ms, 4),
-        "operator_applies_per_s_alone": round(1000.0 / op_ms, 1),
-        "last_frame_rel_res": last_info["rel_res"],
-        "roofline": roofline,
-        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()}
-                    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_frame"])},
-        "operator_kernels": opk,
-        "paper_context": "CPU aug. FEWHA MCAO 1.9 ms/frame on 12 Haswell cores (different system size)",
-    }
-
-    log("single instance: kernel profile and per-kernel timing done")
+    gen_s = {}
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        spec, seq = gen_sequence(ex, "elt", SEED, F)
+        small = gen_sequence(ex, "small", SEED + 2, args.small_frames) if args.small else None
+        full = gen_sequence(ex, "full", SEED + 3, args.loop_frames) if args.loop else None
+        t1 = time.perf_counter()
+        atmos = [gen_sequence(ex, "elt", SEED + 1 + a, batch_frames_needed(args))
+                 for a in range(min(BATCH_ATMOSPHERES, args.batch))] if args.batch > 0 else None
+        gen_s["batched"] = round(time.perf_counter() - t1, 1)
+        t1 = time.perf_counter()
+        ragged = ragged_inputs(ex, args) if args.ragged > 0 else None
+        gen_s["ragged"] = round(time.perf_counter() - t1, 1)
+        t1 = time.perf_counter()
+        ws = warmstart_inputs(ex, args) if args.warmstart else None
+        gen_s["warmstart"] = round(time.perf_counter() - t1, 1)
+    t_gen = time.perf_counter() - t0
+    log(f"inputs: {F} ELT frames{', small and full-loop sequences' if args.small or args.loop else ''} "
+        f"generated in {t_gen:.1f} s ({workers} processes)")
+    cpu = None
     if not args.no_cpu_baseline:
-        from threadpoolctl import threadpool_limits
-        from oracle import AugmentedReconstructor, OracleSystem
+        t0 = time.perf_counter()
+        info = host_cpu_info()
         nf = max(1, min(args.cpu_frames, F))
-        with threadpool_limits(limits=1):
-            sysm = OracleSystem(spec)
-            ref = AugmentedReconstructor(sysm)
-            t0 = time.perf_counter()
-            refs = [ref.solve(seq32[t].astype(np.float64))[0] for t in range(nf)]
-            cpu_wall = time.perf_counter() - t0
-        # the GPU on the same frames from a fresh context, against the FP64 oracle
-        vctx = fw.FewhaContext(spec, device=dev)
-        errs = []
-        for t in range(nf):
-            g = vctx.fewha_solve_aug(slopes[t]).double().cpu().numpy()
-            errs.append(float(np.linalg.norm(g - refs[t]) / np.linalg.norm(refs[t])))
-        out["cpu_baseline"] = {"value": round(it * nf / cpu_wall, 3), "unit": "applies/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"first {nf} frames of the same sequence (FP64 NumPy oracle, "
-                                         f"{1000 * cpu_wall / nf:.1f} ms/frame incl. the first frame's extra apply)"}
-        # free-running: both sides carry their own residual from frame 0 (FP32 rounding
-        # differences accumulate slowly; the per-frame bound applies from an identical state)
-        out["rel_err_vs_oracle_free_running"] = {"frames": nf, "max": max(errs), "last": errs[-1]}
+        s1, sa, sols, sols_p = cpu_baselines(spec, seq, nf, max(1, args.cpu_frames_all), workers)
+        cpu = {"elt": (s1, sa, sols, sols_p)}
+        if args.small:
+            nsm = min(len(small[1]), 2 * nf)
+            cpu["small"] = cpu_baselines(small[0], small[1], nsm, max(1, nsm // 4), workers)
+        loop_ref = None
+        if args.loop and args.loop_check_frames:
+            loop_ref = _oracle_loop_run((full[0], full[1][:args.loop_check_frames], args.loop_pts,
+                                         args.loop_fit_iter, args.loop_gain))
+        log(f"CPU baselines: {time.perf_counter() - t0:.1f} s on {info['model']} ({workers} processes)")
+
+    import torch
+    dev = "cuda:0"
+    out, ctx = run_single(args, dev, spec, seq)
+    slopes = torch.from_numpy(seq[:args.cpu_frames]).to(dev)
+    log("single instance: kernel profile and per-kernel timer done")
+    if cpu is not None:
+        s1, sa, sols, sols_p = cpu["elt"]
+        info = host_cpu_info()
+        out["cpu_baseline"] = {
+            "value": sa["applies_per_s"], "unit": "applies/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {sa['frames'] // workers} frames of the same ELT sequence solved by each of {workers} "
+                      f"single-threaded processes of the FP64 NumPy oracle from a common start",
+            "cpu_model": info["model"], "nproc": info["nproc"], "cpus_available": info["affinity"],
+            "all_core": sa, "single_thread": {**s1, "sample": f"first {s1['frames']} frames, one process, one thread"}}
+        out["rel_err_vs_oracle_free_running"] = free_running_errors(spec, slopes, sols, sols_p, dev)
+    del ctx
+    torch.cuda.empty_cache()
     out["input_generation_s"] = round(t_gen, 2)
-    if args.batch > 0:
-        del ctx, pctx
+    if args.small:
+        out["small"] = run_small(args, dev, *small)
+        if cpu is not None:
+            s1, sa, sols, sols_p = cpu["small"]
+            out["small"]["cpu_baseline"] = {"single_thread": s1, "all_core": {**sa, "cores": workers}}
+            sl = torch.from_numpy(small[1][:len(sols)]).to(dev)
+            out["small"]["rel_err_vs_oracle_free_running"] = free_running_errors(small[0], sl, sols, sols_p, dev)
+        log(f"small FP64: frame p50 {out['small']['frame_ms_p50']} ms")
         torch.cuda.empty_cache()
-        out["batched"] = run_batch(args, dev)
+    if args.loop:
+        res, early = run_full_loop(args, dev, *full)
+        if cpu is not None and loop_ref is not None:
+            refs, ts = loop_ref
+            res["rel_err_vs_oracle_commands"] = [float(f"{np.linalg.norm(a - r) / np.linalg.norm(r):.3e}")
+                                                 for a, r in zip(early, refs)]
+            res["oracle_loop_step_ms"] = round(1000 * float(np.median(ts)), 1)
+        out["full_loop"] = res
+        log(f"full ELT loop: step p50 {res['loop_step_ms_p50']} ms, p99 {res['loop_step_ms_p99']} ms")
+        torch.cuda.empty_cache()
+    if args.batch > 0:
+        out["batched"] = run_batch(args, dev, atmos, gen_s["batched"])
         torch.cuda.empty_cache()
     if args.ragged > 0:
-        out["ragged"] = run_ragged(args, dev)
+        out["ragged"] = run_ragged(args, dev, ragged, gen_s["ragged"])
         torch.cuda.empty_cache()
     if args.unet:
         out["unet"] = run_unet(args, dev)
         torch.cuda.empty_cache()
     if args.warmstart:
-        out["warmstart"] = run_warmstart(args, dev)
+        out["warmstart"] = run_warmstart(args, dev, ws, gen_s["warmstart"])
     print(json.dumps(out), flush=True)
     return 0
 

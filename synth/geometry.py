@@ -190,6 +190,19 @@ def config_elt_full(seed: int = 2, precision: str = "fp32") -> SystemSpec:
     return fit_layer_grids(spec)
 
 
+def elt_mcao_dms():
+    """The three deformable mirrors of the paper's MCAO system (Sec. 6, system table), as
+    (altitude [m], actuators per side, spacing [m]): 85 x 85 at 0 m with 0.5 m spacing,
+    47 x 47 at 4 km and 53 x 53 at 12.7 km with 1 m spacing."""
+    return [(0.0, 85, 0.5), (4000.0, 47, 1.0), (12700.0, 53, 1.0)]
+
+
+def mcao_fit_directions():
+    """The 5 x 5 grid of science directions of the MCAO asterism figure (Sec. 6): +-60 arcsec
+    in steps of 30 arcsec, as (theta_x, theta_y) [rad], row by row."""
+    return [(x * 30 * ARCSEC, y * 30 * ARCSEC) for y in range(-2, 3) for x in range(-2, 3)]
+
+
 def config_tiny(seed: int = 3, n: int = 16, levels: int = 3, n_sub: int = 8) -> SystemSpec:
     """Two layers (0 and 6 km) on n x n grids and two 8x8 WFS (one NGS, one LGS at 90 km);
     small enough to assemble every operator densely."""

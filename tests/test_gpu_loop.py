@@ -121,8 +121,7 @@ def test_elt_mcao_closed_loop_fp32():
     spec = synth.config_elt_full(precision="fp32")
     seq = synth.make_sequence(spec, 4, seed=9).astype(np.float32).astype(np.float64)
     sysm = OracleSystem(spec)
-    dms = [(0.0, 85, 0.5), (4000.0, 47, 1.0), (12700.0, 53, 1.0)]
-    dirs = [(x * 30 * ARC, y * 30 * ARC) for y in range(-2, 3) for x in range(-2, 3)]
+    dms, dirs = synth.elt_mcao_dms(), synth.mcao_fit_directions()
     ctx = fw.FewhaContext(spec, device=DEV)
     loop = fw.LoopContext(ctx, dms, gain=0.4, closed=True, fit_iter=4, dirs=dirs, n_pts=40, pupil_d=spec.D,
                           obstruction=spec.obstruction)
