@@ -34,9 +34,9 @@ VALU_PEAK_INST_S = 256 * 4 * 2.4e9 / 4
 SEED = 20201112
 
 
-COARSE_BLOCK = 64      # largest wavelet block a single workgroup transforms in LDS
+COARSE_BLOCK = 32      # analysis levels whose block fits this side run in one workgroup's LDS
 # operator kernels in the library's profiler numbering (see include/fewha.h)
-OP_KERNELS = ["idwt_coarse", "idwt_step", "data_term", "adj_gather", "dwt_step", "dwt_coarse"]
+OP_KERNELS = ["idwt", "data_term", "adj_gather", "dwt_tiles", "dwt_coarse"]
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2011_06842_amd", "csrc")
 
@@ -46,35 +46,53 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def coarse_sizes(spec):
-    """Per layer: side of the top-left block the coarse kernels transform in LDS (0 if none)."""
+def ana_segments(n, levels, kmax):
+    """Tiled analysis levels of a layer: (group, first level, count), as the library plans them
+    (groups of kmax block sizes above the coarse block, one launch each, finest first)."""
     out = []
-    for l in spec.layers:
-        lc = 1
-        while (l.n >> (lc - 1)) > COARSE_BLOCK:
-            lc += 1
-        out.append(l.n >> (lc - 1) if l.levels >= lc else 0)
-    return out
+    lc = 1
+    while (n >> (lc - 1)) > COARSE_BLOCK:
+        lc += 1
+    for lev in range(1, min(levels, lc - 1) + 1):
+        g = ((n >> (lev - 1)).bit_length() - 1 - (COARSE_BLOCK.bit_length() - 1) - 1) // kmax
+        if out and out[-1][0] == g:
+            out[-1][2] += 1
+        else:
+            out.append([g, lev, 1])
+    return out, lc
 
 
 def op_kernel_bytes(name, step, spec, steps, N, S, V, e):
     """Algorithmic HBM bytes of one launch of an operator kernel inside M x: every operand it
     must read or write once (x, the prior and the slope weights included), intermediates
     between kernels counted once at each side, nothing counted twice within a kernel."""
-    if name == "idwt_coarse":     # coarse coefficients in, coarse image (or LL band) out
-        return sum(2 * b * b for b in coarse_sizes(spec)) * e
-    if name == "dwt_coarse":      # LL band in; coefficients out; prior and x in
-        return sum(4 * b * b for b in coarse_sizes(spec)) * e
-    nb, nl = steps[step] if step is not None else (0, 0)
-    if name == "idwt_step":       # LL band + 3 detail bands in, next LL band (or image) out
-        return 2 * nb * nb * nl * e
-    if name == "dwt_step":        # image/LL in; 3 detail bands + LL out; prior and x of the details in
-        return 3.5 * nb * nb * nl * e
+    kmax = 2 if spec.precision == "fp64" else 3
+    if name == "idwt":            # coefficients in, images out
+        return 2 * N * e
     if name == "data_term":       # layer images in, slope weights in, sensor nodes out
         return (N + S + V) * e
     if name == "adj_gather":      # sensor nodes in, layer images out
         return (V + N) * e
-    raise ValueError(name)
+    groups = sorted({sg[0] for l in spec.layers for sg in ana_segments(l.n, l.levels, kmax)[0]}, reverse=True)
+    total = 0
+    for l in spec.layers:
+        segs, lc = ana_segments(l.n, l.levels, kmax)
+        if name == "dwt_coarse":  # LL block (or image) in; coefficients, prior and x of the block
+            if l.levels >= lc:
+                b = l.n >> (lc - 1)
+                total += 4 * b * b
+            continue
+        for g, l1, k in segs:     # input window of the launch; 3 bands per level (+ prior, x)
+            if g != groups[step]:
+                continue
+            nb_in = l.n >> (l1 - 1)
+            total += nb_in * nb_in
+            for j in range(k):
+                m = nb_in >> (j + 1)
+                total += 3 * m * m * 3
+            m = nb_in >> k
+            total += m * m * (3 if l1 + k - 1 == l.levels else 1)
+    return total * e
 
 
 def frame_kernel_bytes(name, N, S, V, e, m, it, mp):
@@ -257,8 +275,8 @@ def run_batch(args, dev, atmos, t_gen):
         if not nl:
             continue
         if name in OP_KERNELS:
-            if name.endswith("_step"):
-                b = sum(op_kernel_bytes(name, k, spec, steps, N, S, V, e) for k in range(len(steps)))
+            if name == "dwt_tiles":
+                b = B * sum(op_kernel_bytes(name, k, spec, steps, N, S, V, e) for k in range(len(steps)))
                 b *= (nl / P) / len(steps)
             else:
                 b = op_kernel_bytes(name, None, spec, steps, N, S, V, e) * (B if "coarse" in name else 1)
@@ -887,7 +905,7 @@ def run_single(args, dev, spec, seq):
     m, mp = spec.recycle_k, 1
     opk = {}
     for kid, name in enumerate(OP_KERNELS):
-        for st in (range(len(steps)) if name.endswith("_step") else [None]):
+        for st in (range(len(steps)) if name == "dwt_tiles" else [None]):
             us = 1000 * ctx.fewha_time_kernel(kid, st or 0, args.kernel_reps)
             b = op_kernel_bytes(name, st, spec, steps, N, S, V, e)
             key = name if st is None else f"{name}[{steps[st][0]}x{steps[st][0]} x{steps[st][1]}]"
@@ -898,7 +916,7 @@ def run_single(args, dev, spec, seq):
     per_kernel = {}
     for v in opk.values():
         k = v["kernel"]
-        nst = len(steps) if k.endswith("_step") else 1
+        nst = len(steps) if k == "dwt_tiles" else 1
         nl = kernels.get(k, {}).get("launches_per_frame", 0) / nst
         pk = per_kernel.setdefault(k, {"us_per_frame": 0.0, "bytes_per_frame": 0.0, "launches_per_frame": 0.0})
         pk["us_per_frame"] += v["avg_us"] * nl

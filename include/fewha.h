@@ -252,16 +252,17 @@ fewha_status fewha_profile(fewha_ctx* ctx, int32_t enable);
 fewha_status fewha_profile_read(const fewha_ctx* ctx, double* ms, int64_t* launches, int32_t n, int32_t* n_out);
 const char* fewha_kernel_name(int32_t i);
 
-/* Diagnostic timer of one operator kernel (profiler index 0-5: coarse synthesis, tiled synthesis
- * step, fused data term, propagation adjoint, tiled analysis step, coarse analysis; `step`
- * selects the tiled level, see fewha_wavelet_steps).  The kernel is launched `reps` times with
+/* Diagnostic timer of one operator kernel (profiler index 0-4: synthesis, fused data term,
+ * propagation adjoint, tiled analysis, coarse analysis; `step` selects the tiled analysis
+ * launch, see fewha_wavelet_steps).  The kernel is launched `reps` times with
  * the arguments it has inside M x (input: the carried coefficients), captured into one graph and
  * replayed between two events recorded on `stream`; *avg_ms receives the mean duration.
  * Overwrites the context's scratch vectors (not the carried state).  Synchronises `stream`. */
 fewha_status fewha_time_kernel(fewha_ctx* ctx, int32_t kernel, int32_t step, int32_t reps, void* stream,
                                float* avg_ms);
 
-/* Tiled wavelet levels of the context (ascending block size) and the number of layers in each. */
+/* Tiled analysis launches of the context (finest levels first): the largest block each
+ * transforms and the number of layers in it. */
 fewha_status fewha_wavelet_steps(const fewha_ctx* ctx, int32_t* block_sizes, int32_t* layer_counts, int32_t n,
                                  int32_t* n_out);
 

@@ -408,7 +408,7 @@ class FewhaContext:
         return ms.value
 
     def fewha_wavelet_steps(self):
-        """[(block size, layer count)] of the tiled wavelet levels."""
+        """[(largest block, layer count)] of the tiled analysis launches (finest first)."""
         bs = (C.c_int32 * 16)()
         lc = (C.c_int32 * 16)()
         n = C.c_int32()

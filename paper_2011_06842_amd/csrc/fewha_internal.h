@@ -20,14 +20,17 @@ constexpr int kGramElems = 1536;    // elements per Gram workgroup (one instance
 constexpr int kKMax = FEWHA_MAX_RECYCLE;
 constexpr int kSlotsMax = kKMax + 256;
 constexpr int kTile = 14;           // wavefront-node tile side of the fused data-term kernel (16 with the halo)
-constexpr int kCoarseThreads = 1024;  // threads of the one-workgroup-per-layer coarse wavelet kernels
-// Wavelet blocks up to CB x CB are transformed inside one workgroup's LDS; larger levels are
-// tiled over many workgroups (one CU's LDS bandwidth is the limit of the in-LDS passes).
-template <typename T> struct CoarseBlock { static constexpr int value = 64; };
-inline int coarse_block(int /*precision*/) { return 64; }
-constexpr int kST = 32;             // output tile side of a tiled synthesis step
-constexpr int kSmallTileBelow = 256; // synthesis tiles of kST / 2 when a step has fewer kST tiles
-constexpr int kAT = 16;             // coefficient tile side (per band) of a tiled analysis step
+constexpr int kCoarseThreads = 256;  // threads of the one-workgroup-per-layer coarse analysis kernel
+// Analysis levels whose block fits CB x CB run inside one workgroup's LDS; larger levels are
+// tiled over many workgroups, up to kAnaLevels<T> of them per launch.
+template <typename T> struct CoarseBlock { static constexpr int value = 32; };
+inline int coarse_block(int /*precision*/) { return 32; }
+inline int ana_levels_per_launch(int precision) { return precision == FEWHA_FP64 ? 2 : 3; }
+// output tile side (per band) of the last level of a tiled analysis launch of k levels: the
+// first level's outputs are then 16 x 16 per band
+inline int ana_tile(int k) { return 16 >> (k - 1); }
+constexpr int kSynTile = 32;        // image tile side of the synthesis
+constexpr int kSmallTileBelow = 256; // synthesis tiles of kSynTile / 2 when there are fewer kSynTile tiles
 constexpr int kGT = 32;             // layer-node tile columns of the adjoint gather
 constexpr int kGRowStep = kThreads / kGT;        // tile rows per gather thread row (8)
 constexpr int64_t kGatherWide = int64_t(1) << 21;  // from this many coefficients on, 4 rows per gather thread
@@ -138,7 +141,7 @@ struct Scalars {
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
     size_t layers, wfs, pairs, cellidx, frac, ranges, weight, prior_a, jinv;
-    size_t insts, vecblk, gramblk, step_layers, data_tiles, gather_tiles, grecs, recbase, gwin;
+    size_t insts, vecblk, gramblk, syn_items, ana_items, data_tiles, gather_tiles, grecs, recbase, gwin;
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
     size_t c, r, z, b, b_prev;
     size_t ring_u, ring_q;
@@ -150,8 +153,7 @@ struct Layout {
 
 // Kernels, for the optional event profiler and the per-kernel timer.
 enum KernelId : int {
-    KID_IDWT_COARSE = 0, KID_IDWT_STEP, KID_DATA_TERM, KID_ADJ_GATHER, KID_DWT_STEP, KID_DWT_COARSE,
-    KID_SLOPES_ADJ, KID_RESIDUAL, KID_GRAM, KID_GRAM_SOLVE, KID_GALERKIN, KID_INIT_DIR, KID_UPDATE1,
+    KID_IDWT = 0, KID_DATA_TERM, KID_ADJ_GATHER, KID_DWT_TILES, KID_DWT_COARSE, KID_SLOPES_ADJ, KID_RESIDUAL, KID_GRAM, KID_GRAM_SOLVE, KID_GALERKIN, KID_INIT_DIR, KID_UPDATE1,
     KID_UPDATE2, KID_FINISH, KID_FWD_SLOPES, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
@@ -164,10 +166,10 @@ struct Profiler {
     int64_t launches[KID_COUNT] = {};
 };
 
-// One tiled wavelet level of block size nb: its layers (global ids) at step_off of the
-// device list of step layers.
+// One tiled analysis launch: ni workgroup items at loff of the device item list, from nl
+// layers; nb is the largest block it transforms.
 struct StepInfo {
-    int nb = 0, nl = 0, loff = 0;
+    int nb = 0, nl = 0, loff = 0, ni = 0;
 };
 
 struct Ctx {
@@ -193,7 +195,8 @@ struct Ctx {
     int slots = 0;             // ring capacity k + max_iter
     int max_rng = 0;           // largest gather contribution count of a layer row/column
     int max_gwin_side = 0;     // largest side of the sensor-node rectangle of a gather tile
-    std::vector<StepInfo> steps;  // tiled wavelet levels (ascending block size)
+    std::vector<StepInfo> steps;  // tiled analysis launches (finest levels first)
+    int syn_small = 0, syn_large = 0;   // synthesis tiles of kSynTile / 2 and of kSynTile
     int npq = 0;               // (p, q) partial entries written by one analysis
     int64_t n_cells = 0, n_ranges = 0;
     std::vector<fewha_layer> layers;

@@ -1,10 +1,9 @@
 // HIP kernels (gfx950 / CDNA4) of the system operator M = W^-T A^T C^-1 A W^-1 + alpha D
 // (Sec. 3) and of the right-hand side b = W^-T A^T C^-1 s.
 //
-//   W^-1 (synthesis, Sec. 3):  k_idwt_coarse  one workgroup per layer; every level whose block
-//                                             fits the coarse block, separable passes in LDS
-//                              k_idwt_step    one launch per larger block size; 32x32 output tiles,
-//                                             separable passes in LDS from a 36x36 coefficient halo
+//   W^-1 (synthesis, Sec. 3):  k_idwt         one launch: per 32x32 (or 16x16) image tile, the
+//                                             windows of every level the tile depends on, loaded
+//                                             at once and synthesised coarsest first in LDS
 //   A^T C^-1 A (Sec. 2):       k_data_term    per (sensor, 14x14 node tile), one node of the
 //                                             16x16 halo tile per thread: bilinear propagation from
 //                                             every layer (NGS shift, LGS cone), Shack-Hartmann
@@ -14,9 +13,11 @@
 //                                             systems, sensor rectangles staged in LDS): exact
 //                                             transpose of the bilinear propagation as a gather
 //                                             (no atomics, deterministic)
-//   W^-T + alpha D:            k_dwt_step / k_dwt_coarse, the mirror images of the synthesis,
-//                                             with the prior and an optional (x, Mx) partial fused
-//                                             into the final coefficients
+//   W^-T + alpha D:            k_dwt_tiles    up to three levels per launch and tile from one input
+//                                             window, then k_dwt_coarse (the levels whose block
+//                                             fits 32x32, one workgroup per layer); the prior and
+//                                             an optional (x, Mx) partial fused into the final
+//                                             coefficients
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -97,292 +98,344 @@ struct Taps {
 
 // ------------------------------------------------------------------ wavelet synthesis
 
-// Levels levels..coarse_lev of one layer in LDS.  Every coefficient of those levels lies in
-// the top-left (n >> (coarse_lev-1))^2 block of the Mallat pyramid, so the block is loaded
-// once; each level then synthesises its top-left block in place (its details are never
-// overwritten by coarser levels).  1-D periodic synthesis of a 2m block:
-// x_i = sum_{t = i mod 2} h_t a_{((i-t)/2) mod m} + g_t d_{((i-t)/2) mod m}, columns then rows.
-template <typename T>
-__global__ void __launch_bounds__(kCoarseThreads) k_idwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
-                                                                 const T* __restrict__ coef, T* __restrict__ ll_out,
-                                                                 T* __restrict__ phi, const int32_t* __restrict__ skip) {
-    constexpr int CB = CoarseBlock<T>::value;
-    __shared__ T A[CB * CB];
-    __shared__ T B[CB * CB];
-    const LayerDev d = lays[blockIdx.x];
-    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
-    const int n = d.n, lc = d.coarse_lev, levels = d.levels;
-    if (levels < lc) return;
-    const T* C = coef + d.off;
-    const Taps<T> tp(f);
-    const int nb0 = n >> (lc - 1), lg0 = ilog2i(nb0);
-    // 16-byte chunks of consecutive positions of a row (nb0 >= 8 is a multiple of the chunk)
-    using VC = Vec16<T>;
-    using V = typename VC::type;
-    constexpr int PERC = CB * CB / (VC::n * kCoarseThreads);
-    const int nch = nb0 * nb0 / VC::n;
-    {
-        V v[PERC];
+// One workgroup computes one ST x ST tile (n x n when the layer is smaller) of a layer's image
+// phi = W^-1 c / delta in a single launch.  Output rows [a, a + w) of a synthesis level read the
+// coefficient rows [floor(a/2) - 2, floor((a + w - 1)/2)] of each band (periodic), so the
+// tile depends on a window of every level that shrinks to about six coefficients at the coarse
+// end; the workgroup loads those windows of every level at once and synthesises them from the
+// coarsest level down, each level's LL window staying in LDS.  Neighbouring tiles recompute
+// the overlapping coarse windows, which costs a few hundred values per tile; no intermediate
+// goes through global memory and every output takes exactly the row and column passes of the
+// level-by-level transform: x_i = sum_{t = i mod 2} h_t a_{(i-t)/2} + g_t d_{(i-t)/2}, rows
+// (the vertical pass) then columns.  Every loop runs over the compile-time bound of its
+// window (valid entries masked), so no index needs a run-time division.
+constexpr int kMaxLevels = 10;   // layers are at most 1024 x 1024
+
+// Bound of the window side at level l of an st-wide output tile: (st - 1)/2 + 3 at the first
+// level (tiles start at even positions), then half of the previous side plus 3.
+constexpr int syn_window(int st, int l) {
+    int w = st;
+    for (int j = 1; j <= l; ++j) w = (j == 1 ? (w - 1) / 2 : w / 2) + 3;
+    return w;
+}
+// LDS offset of level l's buffer (2 W rows of 2 W + 1; quadrant rows and columns at W)
+constexpr int syn_boff(int st, int l) {
+    int s = 0;
+    for (int j = 1; j < l; ++j) s += 2 * syn_window(st, j) * (2 * syn_window(st, j) + 1);
+    return s;
+}
+constexpr int cdiv_c(int a, int b) { return (a + b - 1) / b; }
+// loads per thread of all levels' windows (four quadrants per level at the bound)
+constexpr int syn_loads(int st) {
+    int s = 0;
+    for (int l = 1; l <= kMaxLevels; ++l) s += cdiv_c(4 * syn_window(st, l) * syn_window(st, l), kThreads);
+    return s;
+}
+
+template <typename T, int ST>
+struct SynTile {
+    // the windows of levels 0..kMaxLevels of one tile: start and side per direction
+    int ay[kMaxLevels + 1], wy[kMaxLevels + 1], ax[kMaxLevels + 1], wx[kMaxLevels + 1];
+
+    // quadrant loads of level l (Q = 4 W^2 slots, q = slot / W^2: 0 LL, 1 top right, 2 bottom
+    // left, 3 bottom right of the Mallat block), into v starting at index k0
+    template <int l>
+    __device__ __forceinline__ void load(const T* __restrict__ C, int n, int L, T* v, int* dst, int k0) const {
+        constexpr int W = syn_window(ST, l), Q = 4 * W * W, P = cdiv_c(Q, kThreads), SB = 2 * W + 1;
+        const int m = n >> l;
 #pragma unroll
-        for (int k = 0; k < PERC; ++k) {   // unconditional (clamped) loads
-            const int ch0 = threadIdx.x + k * kCoarseThreads, ch = ch0 < nch ? ch0 : 0;
-            const int e = ch * VC::n;
-            v[k] = *reinterpret_cast<const V*>(C + (e >> lg0) * n + (e & (nb0 - 1)));
-        }
-#pragma unroll
-        for (int k = 0; k < PERC; ++k) {
-            const int ch = threadIdx.x + k * kCoarseThreads;
-            if (ch < nch) {
-                const int e = ch * VC::n;
-                VC::put(&A[(e >> lg0) * CB + (e & (nb0 - 1))], v[k]);
-            }
+        for (int k = 0; k < P; ++k) {
+            const int e = threadIdx.x + k * kThreads;
+            const int q = e / (W * W), rem = e - q * (W * W), rr = rem / W, cc = rem - rr * W;
+            const int hr = q >> 1, hc = q & 1;
+            const bool ok = l <= L && e < Q && rr < wy[l] && cc < wx[l] && (q > 0 || l == L);
+            const int kr = (ay[l] + rr) & (m - 1), kc = (ax[l] + cc) & (m - 1);
+            v[k0 + k] = C[ok ? (kr + m * hr) * n + kc + m * hc : 0];
+            dst[k0 + k] = ok ? syn_boff(ST, l) + (hr * W + rr) * SB + hc * W + cc : -1;
         }
     }
-    __syncthreads();
-    // outputs 2i and 2i + 1 of a line read the same three coefficients of each band, so
-    // every pass computes the pair from one read
-    for (int lev = levels; lev >= lc; --lev) {
-        const int nb = n >> (lev - 1), m = nb >> 1, lg = ilog2i(nb), lgm = lg - 1;
-        for (int e = threadIdx.x; e < m * nb; e += kCoarseThreads) {   // rows 2i, 2i + 1
-            const int i = e >> lg, x = e & (nb - 1);
-            T ev = 0, od = 0;
+
+    // synthesis of level l: level l - 1's LL window (the image tile at l = 1)
+    template <int l>
+    __device__ __forceinline__ void level(T* __restrict__ buf, T* __restrict__ I, const Taps<T>& tp, T* __restrict__ phi,
+                                          size_t off, int n, T inv_delta) const {
+        constexpr int W = syn_window(ST, l), SB = 2 * W + 1, W2 = syn_window(ST, l - 1);
+        const T* B = buf + syn_boff(ST, l);
+        const int a2 = ay[l - 1], h2 = wy[l - 1], b2 = ax[l - 1], v2 = wx[l - 1], wxl = wx[l];
+        // vertical pass: the rows of level l - 1's window, both column halves (I: rows of SB)
+        for (int e = threadIdx.x; e < W2 * 2 * W; e += kThreads) {
+            const int i = e / (2 * W), col = e - i * (2 * W);
+            const int cc = col >= W ? col - W : col;
+            if (i < h2 && cc < wxl) {
+                const int ai = a2 + i, odd = ai & 1, base = (ai >> 1) - (a2 >> 1) + 2;
+                T v = 0;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int ky = (i - k) & (m - 1);
-                const T a = A[ky * CB + x], b = A[(m + ky) * CB + x];
-                ev += tp.he[k] * a + tp.ge[k] * b;
-                od += tp.ho[k] * a + tp.go[k] * b;
+                for (int k = 0; k < 3; ++k) {
+                    const T a = B[(base - k) * SB + col], b = B[(W + base - k) * SB + col];
+                    v += (odd ? tp.ho[k] : tp.he[k]) * a + (odd ? tp.go[k] : tp.ge[k]) * b;
+                }
+                I[i * SB + col] = v;
             }
-            B[(2 * i) * CB + x] = ev;
-            B[(2 * i + 1) * CB + x] = od;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < nb * m; e += kCoarseThreads) {   // columns 2i, 2i + 1
-            const int y = e >> lgm, i = e & (m - 1);
-            T ev = 0, od = 0;
+        // horizontal pass: into level l - 1's LL quadrant, or the image
+        for (int e = threadIdx.x; e < W2 * W2; e += kThreads) {
+            const int i = e / W2, j = e - i * W2;
+            if (i < h2 && j < v2) {
+                const int aj = b2 + j, odd = aj & 1, base = (aj >> 1) - (b2 >> 1) + 2;
+                T v = 0;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int kx = (i - k) & (m - 1);
-                const T a = B[y * CB + kx], b = B[y * CB + m + kx];
-                ev += tp.he[k] * a + tp.ge[k] * b;
-                od += tp.ho[k] * a + tp.go[k] * b;
+                for (int k = 0; k < 3; ++k) {
+                    const T a = I[i * SB + base - k], b = I[i * SB + W + base - k];
+                    v += (odd ? tp.ho[k] : tp.he[k]) * a + (odd ? tp.go[k] : tp.ge[k]) * b;
+                }
+                if constexpr (l > 1)
+                    buf[syn_boff(ST, l - 1) + i * (2 * W2 + 1) + j] = v;
+                else
+                    phi[off + size_t(ay[0] + i) * n + ax[0] + j] = v * inv_delta;
             }
-            A[y * CB + 2 * i] = ev;
-            A[y * CB + 2 * i + 1] = od;
         }
         __syncthreads();
     }
-    T* out = (lc == 1 ? phi : ll_out) + d.off;
-    const T s = lc == 1 ? T(d.inv_delta) : T(1);
-    for (int ch = threadIdx.x; ch < nch; ch += kCoarseThreads) {
-        const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
-        T val[VC::n];
-#pragma unroll
-        for (int j = 0; j < VC::n; ++j) val[j] = A[r * CB + c + j] * s;
-        VC::store(out + r * n + c, val);
+};
+
+template <typename T, int ST, int l>
+__device__ __forceinline__ void syn_load_all(const SynTile<T, ST>& tl, const T* C, int n, int L, T* v, int* dst, int k0) {
+    if constexpr (l <= kMaxLevels) {
+        tl.template load<l>(C, n, L, v, dst, k0);
+        syn_load_all<T, ST, l + 1>(tl, C, n, L, v, dst, k0 + cdiv_c(4 * syn_window(ST, l) * syn_window(ST, l), kThreads));
     }
 }
 
-// One synthesis level of block size nbs (> the coarse block) on the listed layers; ST x ST
-// output tile per workgroup (the tile size changes no output bit: each output takes the same
-// row and column passes).  The LL band comes from the previous step (or from the
-// coefficients when this is the layer's coarsest level); the final level writes phi / delta.
+template <typename T, int ST, int l>
+__device__ __forceinline__ void syn_levels(const SynTile<T, ST>& tl, T* buf, T* I, const Taps<T>& tp, T* phi, size_t off,
+                                           int n, int L, T inv_delta) {
+    if constexpr (l >= 1) {
+        if (l <= L) tl.template level<l>(buf, I, tp, phi, off, n, inv_delta);
+        syn_levels<T, ST, l - 1>(tl, buf, I, tp, phi, off, n, L, inv_delta);
+    }
+}
+
 template <typename T, int ST>
-__global__ void __launch_bounds__(kThreads) k_idwt_step(const LayerDev* __restrict__ lays,
-                                                         const int32_t* __restrict__ sl, int nbs,
-                                                         Filt<T> f, const T* __restrict__ coef,
-                                                         const T* __restrict__ ll_in, T* __restrict__ ll_out,
-                                                         T* __restrict__ phi, const int32_t* __restrict__ skip) {
-    constexpr int H = ST / 2 + 2;   // coefficient rows (per band) feeding one tile
-    __shared__ T R[2 * H][2 * H + 1];
-    __shared__ T I[ST][2 * H + 1];
-    const int tx = nbs / ST, tiles = tx * tx;
-    const int bid = die_ordered_block();
-    const int li = bid / tiles, tile = bid - li * tiles;
-    const LayerDev d = lays[sl[li]];
+__global__ void __launch_bounds__(kThreads) k_idwt(const LayerDev* __restrict__ lays, const int2* __restrict__ items,
+                                                    Filt<T> f, const T* __restrict__ coef, T* __restrict__ phi,
+                                                    const int32_t* __restrict__ skip) {
+    constexpr int W1 = syn_window(ST, 1);
+    constexpr int PER = syn_loads(ST);
+    __shared__ T buf[syn_boff(ST, kMaxLevels + 1)];
+    __shared__ T I[ST * (2 * W1 + 1)];
+    const int2 it = items[die_ordered_block()];
+    if (it.x < 0) return;               // padding of the die-ordered grid
+    const LayerDev d = lays[it.x];
     if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
-    const int n = d.n;
-    const int lev = ilog2i(n / nbs) + 1;
-    const int M = nbs >> 1;
-    const int y0 = (tile / tx) * ST, x0 = (tile % tx) * ST;
-    const T* C = coef + d.off;
-    const T* LL = (lev == d.levels ? coef : ll_in) + d.off;
-    const int ky0 = (y0 >> 1) - 2, kx0 = (x0 >> 1) - 2;
-    const Taps<T> tp(f);
-    // staged in pairs: kx0 is even and M a multiple of 2, so the two coefficients of a pair
-    // are adjacent (also across the periodic wrap) and the pair is 2-element aligned
+    const int n = d.n, L = d.levels;
+    const int ts = n < ST ? n : ST, tx = n / ts;
+    const int ty = it.y / tx;
+    SynTile<T, ST> tl;
+    tl.ay[0] = ty * ts;
+    tl.wy[0] = ts;
+    tl.ax[0] = (it.y - ty * tx) * ts;
+    tl.wx[0] = ts;
+#pragma unroll
+    for (int l = 1; l <= kMaxLevels; ++l) {   // >> of a negative start: floor
+        tl.wy[l] = ((tl.ay[l - 1] + tl.wy[l - 1] - 1) >> 1) - (tl.ay[l - 1] >> 1) + 3;
+        tl.wx[l] = ((tl.ax[l - 1] + tl.wx[l - 1] - 1) >> 1) - (tl.ax[l - 1] >> 1) + 3;
+        tl.ay[l] = (tl.ay[l - 1] >> 1) - 2;
+        tl.ax[l] = (tl.ax[l - 1] >> 1) - 2;
+    }
     {
-        using V2 = typename Vec2<T>::type;
-        constexpr int NP = 2 * H * H, PER = (NP + kThreads - 1) / kThreads;   // pairs (H per row)
-        V2 v[PER];
+        T v[PER];
+        int dst[PER];
+        syn_load_all<T, ST, 1>(tl, coef + d.off, n, L, v, dst, 0);
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped index)
-            const int e0 = threadIdx.x + k * kThreads, e = e0 < NP ? e0 : NP - 1;
-            const int rr = e / H, cc = 2 * (e - rr * H);
-            const int hr = rr >= H, hc = cc >= H;
-            const int kr = (ky0 + rr - H * hr) & (M - 1), kc = (kx0 + cc - H * hc) & (M - 1);
-            const T* src = (!hr && !hc) ? LL + kr * n + kc : C + (kr + M * hr) * n + kc + M * hc;
-            v[k] = *reinterpret_cast<const V2*>(src);
-        }
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = threadIdx.x + k * kThreads;
-            if (e < NP) {
-                const int rr = e / H, cc = 2 * (e - rr * H);
-                R[rr][cc] = v[k].x;
-                R[rr][cc + 1] = v[k].y;
-            }
-        }
+        for (int k = 0; k < PER; ++k)
+            if (dst[k] >= 0) buf[dst[k]] = v[k];
     }
     __syncthreads();
-    // row pass: output rows 2m and 2m + 1 read the same three coefficient rows of each band
-    for (int e = threadIdx.x; e < (ST / 2) * 2 * H; e += kThreads) {
-        const int m = e / (2 * H), cc = e - m * (2 * H);
-        T ev = 0, od = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T a = R[m - k + 2][cc], b = R[H + m - k + 2][cc];
-            ev += tp.he[k] * a + tp.ge[k] * b;
-            od += tp.ho[k] * a + tp.go[k] * b;
-        }
-        I[2 * m][cc] = ev;
-        I[2 * m + 1][cc] = od;
-    }
-    __syncthreads();
-    // column pass: the pair of outputs (2m, 2m + 1) of a row, stored together
-    const T s = T(d.inv_delta);
-    for (int e = threadIdx.x; e < ST * (ST / 2); e += kThreads) {
-        const int yy = e / (ST / 2), m = e - yy * (ST / 2);
-        T ev = 0, od = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T a = I[yy][m - k + 2], b = I[yy][H + m - k + 2];
-            ev += tp.he[k] * a + tp.ge[k] * b;
-            od += tp.ho[k] * a + tp.go[k] * b;
-        }
-        const size_t o = size_t(d.off) + size_t(y0 + yy) * n + x0 + 2 * m;   // even: 2-element aligned
-        using V2 = typename Vec2<T>::type;
-        if (lev == 1)
-            *reinterpret_cast<V2*>(phi + o) = V2{ev * s, od * s};
-        else
-            *reinterpret_cast<V2*>(ll_out + o) = V2{ev, od};
-    }
+    const Taps<T> tp(f);
+    syn_levels<T, ST, kMaxLevels>(tl, buf, I, tp, phi, size_t(d.off), n, L, T(d.inv_delta));
 }
 
 // ------------------------------------------------------------------ wavelet analysis
 
-// One analysis level of block size nbs on the listed layers: 16x16 coefficients of every band
-// per tile, rows then columns from a 36x36 halo, a_k = sum_t h_t x_{(2k+t) mod nbs}.  Final
-// coefficients are scaled by 1/delta.  MODE 1 (inside M x): they get + (alpha D)_i x_i, and the
-// partial of (x, out) over them goes to the tile's slot among the layer's partials (tiles of
-// finer levels first).  MODE 2 (the right-hand side of a frame): the partial of (out, out)
-// goes there instead (its sum tells the frame whether b is finite).  The prior and x operands
-// are requested before the halo so that their latency overlaps it.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) k_dwt_step(const LayerDev* __restrict__ lays,
-                                                        const int32_t* __restrict__ sl, int nbs,
-                                                        Filt<T> f, const T* __restrict__ img,
-                                                        const T* __restrict__ ll_in, T* __restrict__ ll_out,
-                                                        T* __restrict__ out, const T* __restrict__ prior_a,
-                                                        const T* __restrict__ xprior, double* __restrict__ dotpart,
-                                                        const int32_t* __restrict__ skip) {
+// K consecutive analysis levels l1 .. l1 + K - 1 of one layer for one tile (item: layer, tile,
+// l1 | K << 8 | T << 16, partial slot), T = 16 >> (K - 1): from an input window of
+// v0 = (T << K) + 4 ((1 << K) - 1) values per side (a_k = sum_t h_t x_{2k+t} reads 2 v + 4
+// inputs for v outputs) down to a T x T tile of the K-th level.  The workgroup loads its
+// input window once (the image, or the LL band of a previous launch), then per level a row
+// pass (low and high pass of every input row) and a column pass; the LL window of each level
+// stays in LDS for the next.  Its outputs at level j are the T 2^(K-1-j) square block of
+// positions its tile covers (every position of a level belongs to exactly one tile; 16 x 16
+// at the first level); the rest of each LL window is the halo the next level reads.  Final
+// coefficients are scaled by 1/delta; MODE 1 (inside M x) adds (alpha D)_i x_i and sums
+// (x, out) over the tile's outputs into its partial slot, MODE 2 (the right-hand side) sums
+// (out, out) there.  The last level's LL band goes to ll_out for the next launch or the coarse
+// kernel, or is a coefficient when it is the layer's coarsest.  Every thread owns at most one
+// output position per level, so the prior and x operands of its outputs are requested before
+// the window.  FP32 runs up to three levels per launch, FP64 up to two (LDS).
+constexpr int ana_v0(int K) { return ((16 >> (K - 1)) << K) + 4 * ((1 << K) - 1); }
+template <typename T> struct AnaMaxLevels;
+template <> struct AnaMaxLevels<float> { static constexpr int value = 3; };
+template <> struct AnaMaxLevels<double> { static constexpr int value = 2; };
+
+template <typename T, int MODE, int K>
+__device__ __forceinline__ void dwt_tiles_body(const LayerDev& d, int4 it, const Taps<T>& tp, const T* __restrict__ img,
+                                               const T* __restrict__ ll_in, T* __restrict__ ll_out, T* __restrict__ out,
+                                               const T* __restrict__ prior_a, const T* __restrict__ xprior, T* A, T* Bf,
+                                               double& dot) {
     constexpr bool PRIOR = MODE == 1;
-    constexpr int W = 2 * kAT + 4;
-    __shared__ T R[W][W + 1];
-    __shared__ T I[W][2 * kAT + 1];
-    const int M = nbs >> 1, tx = M / kAT, tiles = tx * tx;
-    const int bid = die_ordered_block();
-    const int li = bid / tiles, tile = bid - li * tiles;
-    const LayerDev d = lays[sl[li]];
-    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
-    const int n = d.n;
-    const int lev = ilog2i(n / nbs) + 1;
-    const int ky0 = (tile / tx) * kAT, kx0 = (tile % tx) * kAT;
-    const int ky = threadIdx.x / kAT, kx = threadIdx.x % kAT;   // 256 threads = 16 x 16
-    const int gy = ky0 + ky, gx = kx0 + kx;
-    const bool fin_ll = lev == d.levels;
+    constexpr int TT = 16 >> (K - 1), V0 = ana_v0(K), SA = V0 + 1;
+    const int n = d.n, l1 = it.z & 0xff;
+    const int nb_in = n >> (l1 - 1);
+    const int mt = (nb_in >> K) / TT;
+    const int ty = it.y / mt, tx = it.y - ty * mt;
+    const bool fin = l1 + K - 1 == d.levels;
     const size_t base = size_t(d.off);
-    const size_t o[4] = {base + size_t(gy) * n + M + gx, base + size_t(M + gy) * n + gx,
-                         base + size_t(M + gy) * n + M + gx, base + size_t(gy) * n + gx};
-    const int nout = fin_ll ? 4 : 3;
-    T pa[4] = {0, 0, 0, 0}, xp[4] = {0, 0, 0, 0};
-    if (PRIOR) {   // o[3] (the LL position) is a valid address even when it is not an output
+    const int t = threadIdx.x;
+    T pa[K][4], xp[K][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            pa[k] = prior_a[o[k]];
-            xp[k] = xprior[o[k]];
+    for (int j = 0; j < K; ++j) {
+        const int own = TT << (K - 1 - j);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pa[j][b] = xp[j][b] = T(0);
+        if (PRIOR && t < own * own) {   // o[3] (the LL position) is a valid address even when it is not an output
+            const int m = n >> (l1 + j), r = t / own, c = t - r * own;
+            const int gy = ty * own + r, gx = tx * own + c;
+            const size_t o[4] = {base + size_t(gy) * n + m + gx, base + size_t(m + gy) * n + gx,
+                                 base + size_t(m + gy) * n + m + gx, base + size_t(gy) * n + gx};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                pa[j][b] = prior_a[o[b]];
+                xp[j][b] = xprior[o[b]];
+            }
         }
     }
-    const T* src = (lev == 1 ? img : ll_in) + d.off;
-    const Taps<T> tp(f);
-    // staged in 16-byte chunks: 2 kx0 and nbs are multiples of the chunk, so a chunk is
-    // contiguous (also across the periodic wrap) and aligned
+    // input window in 16-byte chunks: its start (a multiple of T 2^K >= 16) and the block
+    // side are multiples of the chunk, so a chunk is contiguous across the periodic wrap
     {
         using VC = Vec16<T>;
-        constexpr int CPR = W / VC::n, NCH = W * CPR, PER = (NCH + kThreads - 1) / kThreads;
+        constexpr int CPR = V0 / VC::n, NCH = V0 * CPR, PER = cdiv_c(NCH, kThreads);
+        const T* src = (l1 == 1 ? img : ll_in) + d.off;
+        const int sy = (ty * TT) << K, sx = (tx * TT) << K;
         typename VC::type v[PER];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped index)
-            const int e0 = threadIdx.x + k * kThreads, e = e0 < NCH ? e0 : NCH - 1;
+            const int e0 = t + k * kThreads, e = e0 < NCH ? e0 : NCH - 1;
             const int r = e / CPR, q = e - r * CPR;
-            v[k] = *reinterpret_cast<const typename VC::type*>(
-                src + ((2 * ky0 + r) & (nbs - 1)) * n + ((2 * kx0 + q * VC::n) & (nbs - 1)));
+            v[k] = *reinterpret_cast<const typename VC::type*>(src + ((sy + r) & (nb_in - 1)) * n +
+                                                               ((sx + q * VC::n) & (nb_in - 1)));
         }
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int e = threadIdx.x + k * kThreads;
+            const int e = t + k * kThreads;
             if (e < NCH) {
                 const int r = e / CPR, q = e - r * CPR;
-                VC::put(&R[r][q * VC::n], v[k]);
+                VC::put(&A[r * SA + q * VC::n], v[k]);
             }
         }
     }
     __syncthreads();
-    // row pass: the low- and high-pass outputs of one (row, k) from the same six inputs
-    for (int e = threadIdx.x; e < W * kAT; e += kThreads) {
-        const int rr = e / kAT, k = e & (kAT - 1);
-        T lo = 0, hi = 0;
-#pragma unroll
-        for (int t = 0; t < 6; ++t) {
-            const T x = R[rr][2 * k + t];
-            lo += tp.h[t] * x;
-            hi += tp.g[t] * x;
-        }
-        I[rr][k] = lo;
-        I[rr][kAT + k] = hi;
-    }
-    __syncthreads();
-    T ll = 0, yh = 0, xh = 0, hh = 0;
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-        const T lo = I[2 * ky + t][kx], hi = I[2 * ky + t][kAT + kx];
-        ll += tp.h[t] * lo;
-        yh += tp.g[t] * lo;
-        xh += tp.h[t] * hi;
-        hh += tp.g[t] * hi;
-    }
     const T s = T(d.inv_delta);
-    const T v[4] = {xh, yh, hh, ll};
-    double dot = 0;
-    for (int k = 0; k < nout; ++k) {
-        T val = v[k] * s;
-        if (PRIOR) val += pa[k] * xp[k];
-        out[o[k]] = val;
-        dot += double(val) * (MODE == 2 ? double(val) : double(xp[k]));   // (x, M x) or (b, b)
-    }
-    if (!fin_ll) ll_out[o[3]] = ll;
-    if (MODE != 0 && dotpart) {
-        int slot = d.pq0 + tile;
-        for (int j = 1; j < lev; ++j) {
-            const int mt = (n >> j) / kAT;
-            slot += mt * mt;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int vin = (TT << (K - j)) + 4 * ((1 << (K - j)) - 1);   // compile-time after unrolling
+        const int vo = (vin - 4) >> 1, sb = 2 * vo + 1;
+        // row pass: low- and high-pass outputs of one (row, k) from the same six inputs
+        for (int e = t; e < vin * vo; e += kThreads) {
+            const int rr = e / vo, k = e - rr * vo;
+            T lo = 0, hi = 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const T x = A[rr * SA + 2 * k + q];
+                lo += tp.h[q] * x;
+                hi += tp.g[q] * x;
+            }
+            Bf[rr * sb + k] = lo;
+            Bf[rr * sb + vo + k] = hi;
         }
-        const double vv[1] = {dot};
-        block_partials<1>(vv, dotpart, 0, 0, slot);
+        __syncthreads();
+        // column pass: the tile's own positions (item t is thread t's), then the halo rows and
+        // columns the next level reads
+        const int own = TT << (K - 1 - j);
+        const int m = n >> (l1 + j);
+        const bool last = j == K - 1;
+        for (int e = t; e < vo * vo; e += kThreads) {
+            int r, c;
+            if (e < own * own) {
+                r = e / own;
+                c = e - r * own;
+            } else {
+                const int e2 = e - own * own;   // halo: rows [0, own) x columns [own, vo), then rows [own, vo)
+                if (e2 < own * (vo - own)) {
+                    r = e2 / (vo - own);
+                    c = own + e2 - r * (vo - own);
+                } else {
+                    const int e3 = e2 - own * (vo - own);
+                    r = own + e3 / vo;
+                    c = e3 - (e3 / vo) * vo;
+                }
+            }
+            T ll = 0, yh = 0, xh = 0, hh = 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const T lo = Bf[(2 * r + q) * sb + c], hi = Bf[(2 * r + q) * sb + vo + c];
+                ll += tp.h[q] * lo;
+                yh += tp.g[q] * lo;
+                xh += tp.h[q] * hi;
+                hh += tp.g[q] * hi;
+            }
+            A[r * SA + c] = ll;
+            if (e < own * own) {
+                const int gy = ty * own + r, gx = tx * own + c;
+                const size_t o[4] = {base + size_t(gy) * n + m + gx, base + size_t(m + gy) * n + gx,
+                                     base + size_t(m + gy) * n + m + gx, base + size_t(gy) * n + gx};
+                const T v4[4] = {xh, yh, hh, ll};
+                const int nout = last && fin ? 4 : 3;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (b < nout) {
+                        T val = v4[b] * s;
+                        if (PRIOR) val += pa[j][b] * xp[j][b];
+                        out[o[b]] = val;
+                        dot += double(val) * (MODE == 2 ? double(val) : double(xp[j][b]));   // (x, M x) or (b, b)
+                    }
+                }
+                if (last && !fin) ll_out[o[3]] = ll;
+            }
+        }
+        __syncthreads();
     }
 }
 
-// Levels coarse_lev..levels of one layer in LDS (mirror of k_idwt_coarse).  After the last
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_dwt_tiles(const LayerDev* __restrict__ lays, const int4* __restrict__ items,
+                                                         Filt<T> f, const T* __restrict__ img, const T* __restrict__ ll_in,
+                                                         T* __restrict__ ll_out, T* __restrict__ out,
+                                                         const T* __restrict__ prior_a, const T* __restrict__ xprior,
+                                                         double* __restrict__ dotpart, const int32_t* __restrict__ skip) {
+    constexpr int KM = AnaMaxLevels<T>::value, V0 = ana_v0(KM), V1 = (V0 - 4) / 2;
+    __shared__ T A[V0 * (V0 + 1)];
+    __shared__ T Bf[V0 * (2 * V1 + 1)];
+    const int4 it = items[die_ordered_block()];
+    if (it.x < 0) return;               // padding of the die-ordered grid
+    const LayerDev d = lays[it.x];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
+    const Taps<T> tp(f);
+    const int K = (it.z >> 8) & 0xff;
+    double dot = 0;
+    if (KM >= 3 && K == 3)
+        dwt_tiles_body<T, MODE, KM >= 3 ? 3 : 1>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
+    else if (K == 2)
+        dwt_tiles_body<T, MODE, 2>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
+    else
+        dwt_tiles_body<T, MODE, 1>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
+    if (MODE != 0 && dotpart) {
+        const double vv[1] = {dot};
+        block_partials<1>(vv, dotpart, 0, 0, d.pq0 + it.w);
+    }
+}
+
+// Levels coarse_lev..levels of one layer in LDS (the coarse block).  After the last
 // level the block holds the whole coarse Mallat pyramid; it is written once, each thread
 // owning fixed positions whose prior and x operands it requested at kernel start.
 template <typename T, int MODE>
@@ -986,8 +1039,8 @@ inline unsigned cdiv(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
 // ------------------------------------------------------------------ profiler
 
 const char* const kKernelNames[KID_COUNT] = {
-    "idwt_coarse", "idwt_step", "data_term", "adj_gather", "dwt_step", "dwt_coarse", "slopes_adj", "residual",
-    "gram", "gram_solve", "galerkin_apply", "init_dir", "update1", "update2", "finish", "fwd_slopes"};
+    "idwt", "data_term", "adj_gather", "dwt_tiles", "dwt_coarse", "slopes_adj", "residual", "gram", "gram_solve",
+    "galerkin_apply", "init_dir", "update1", "update2", "finish", "fwd_slopes"};
 
 ProfScope::ProfScope(const Ctx& ctx, int kid, hipStream_t stream) : c(ctx), s(stream) {
     Profiler& p = c.prof;
@@ -1024,37 +1077,24 @@ hipError_t profiler_collect(const Ctx& c, hipStream_t s) {
 
 // ------------------------------------------------------------------ operator launchers
 
-// A synthesis step with kST x kST tiles, or with tiles of half that side when the large tiles
-// would give fewer workgroups than the GPU has compute units (a single small instance): the
-// step is then bound by the latency of each workgroup, and four times as many smaller tiles
-// finish sooner.
+// The synthesis in one launch: kSynTile x kSynTile output tiles, or tiles of half that side
+// when the large ones would give fewer workgroups than kSmallTileBelow (a single small
+// instance): the launch is then bound by the latency of each workgroup, and four times as many
+// smaller tiles finish sooner.  The tile side changes no output bit.
 template <typename T>
-void launch_idwt_step(const StepInfo& w, const LayerDev* lays, const int32_t* sl, const Filt<T>& f, const T* x,
-                      const T* ll_in, T* ll_out, T* phi, hipStream_t s, const int32_t* skip) {
-    const int tiles = (w.nb / kST) * (w.nb / kST) * w.nl;
-    if (tiles < kSmallTileBelow)
-        k_idwt_step<T, kST / 2><<<4 * tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi, skip);
-    else
-        k_idwt_step<T, kST><<<tiles, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, x, ll_in, ll_out, phi, skip);
-}
-
-template <typename T>
-void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* ob, const int32_t* skip) {
+void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* /*ob*/, const int32_t* skip) {
     const Filt<T> f = make_filt<T>();
-    const OpBufs bb = ob ? *ob : ctx_bufs(c);
-    T* buf[2] = {reinterpret_cast<T*>(bb.tmp0), reinterpret_cast<T*>(bb.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
-    const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
-    {
-        ProfScope ps_(c, KID_IDWT_COARSE, s);
-        k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], phi, skip);
-    }
-    for (size_t j = 0; j < c.steps.size(); ++j) {
-        ProfScope ps_(c, KID_IDWT_STEP, s);
-        launch_idwt_step<T>(c.steps[j], lays, sl, f, x, buf[j & 1], buf[(j + 1) & 1], phi, s, skip);
-    }
+    const int2* items = c.at<int2>(c.lay.syn_items);
+    ProfScope ps_(c, KID_IDWT, s);
+    if (c.syn_large < kSmallTileBelow)
+        k_idwt<T, kSynTile / 2><<<c.syn_small, kThreads, 0, s>>>(lays, items, f, x, phi, skip);
+    else
+        k_idwt<T, kSynTile><<<c.syn_large, kThreads, 0, s>>>(lays, items + c.syn_small, f, x, phi, skip);
 }
 
+// The analysis: the tiled launches (finest levels first), each LL band handed to the next
+// launch through the two scratch vectors, then the coarse kernel.
 template <typename T>
 void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part, hipStream_t s,
                   const OpBufs* ob, const int32_t* skip) {
@@ -1062,26 +1102,25 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
     const OpBufs bb = ob ? *ob : ctx_bufs(c);
     T* buf[2] = {reinterpret_cast<T*>(bb.tmp0), reinterpret_cast<T*>(bb.tmp1)};
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
-    const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
+    const int4* items = c.at<int4>(c.lay.ana_items);
     const T* pa = c.at<T>(c.lay.prior_a);
     const int J = int(c.steps.size());
     // with xprior: + alpha D x and the (x, y) partials; without it but with pq_part: (y, y)
     const int mode = xprior ? 1 : (pq_part ? 2 : 0);
-    for (int j = 0; j < J; ++j) {                 // largest block first
-        const StepInfo& w = c.steps[J - 1 - j];
-        const int tiles = (w.nb / 2 / kAT) * (w.nb / 2 / kAT);
-        ProfScope ps_(c, KID_DWT_STEP, s);
+    for (int j = 0; j < J; ++j) {
+        const StepInfo& w = c.steps[j];
+        ProfScope ps_(c, KID_DWT_TILES, s);
         auto go = [&](auto kern) {
-            kern<<<tiles * w.nl, kThreads, 0, s>>>(lays, sl + w.loff, w.nb, f, img, buf[(j + 1) & 1], buf[j & 1], y, pa,
-                                                   xprior, pq_part, skip);
+            kern<<<w.ni, kThreads, 0, s>>>(lays, items + w.loff, f, img, buf[(j + 1) & 1], buf[j & 1], y, pa, xprior,
+                                           pq_part, skip);
         };
-        if (mode == 1) go(k_dwt_step<T, 1>);
-        else if (mode == 2) go(k_dwt_step<T, 2>);
-        else go(k_dwt_step<T, 0>);
+        if (mode == 1) go(k_dwt_tiles<T, 1>);
+        else if (mode == 2) go(k_dwt_tiles<T, 2>);
+        else go(k_dwt_tiles<T, 0>);
     }
     ProfScope ps_(c, KID_DWT_COARSE, s);
     auto go = [&](auto kern) {
-        kern<<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J - 1) & 1], y, pa, xprior, pq_part, skip);
+        kern<<<c.L, kCoarseThreads, 0, s>>>(lays, f, img, buf[(J + 1) & 1], y, pa, xprior, pq_part, skip);
     };
     if (mode == 1) go(k_dwt_coarse<T, 1>);
     else if (mode == 2) go(k_dwt_coarse<T, 2>);
@@ -1181,38 +1220,31 @@ template <typename T>
 static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
     const Filt<T> f = make_filt<T>();
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
-    const int32_t* sl = c.at<int32_t>(c.lay.step_layers);
     T* buf[2] = {c.at<T>(c.lay.tmp0), c.at<T>(c.lay.tmp1)};
     const T* x = c.at<T>(c.lay.c);
     T* y = c.at<T>(c.lay.vy);
     const int J = int(c.steps.size());
     switch (kid) {
-        case KID_IDWT_COARSE:
-            k_idwt_coarse<T><<<c.L, kCoarseThreads, 0, s>>>(lays, f, x, buf[0], c.at<T>(c.lay.nodal), nullptr);
+        case KID_IDWT:
+            launch_winv<T>(c, x, c.at<T>(c.lay.nodal), s, nullptr, nullptr);
             break;
-        case KID_IDWT_STEP: {
-            if (step < 0 || step >= J) return hipErrorInvalidValue;
-            launch_idwt_step<T>(c.steps[step], lays, sl, f, x, buf[step & 1], buf[(step + 1) & 1],
-                                c.at<T>(c.lay.nodal), s, nullptr);
-            break;
-        }
         case KID_DATA_TERM:
             launch_data_term<T>(c, c.at<T>(c.lay.nodal), c.at<T>(c.lay.psi_nodes), s);
             break;
         case KID_ADJ_GATHER:
             launch_adj_gather<T>(c, c.at<T>(c.lay.psi_nodes), c.at<T>(c.lay.psi_layers), s);
             break;
-        case KID_DWT_STEP: {
+        case KID_DWT_TILES: {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
             const StepInfo& w = c.steps[step];
-            const int j = J - 1 - step;
-            k_dwt_step<T, 1><<<(w.nb / 2 / kAT) * (w.nb / 2 / kAT) * w.nl, kThreads, 0, s>>>(
-                lays, sl + w.loff, w.nb, f, c.at<T>(c.lay.psi_layers), buf[(j + 1) & 1], buf[j & 1], y,
-                c.at<T>(c.lay.prior_a), x, c.at<double>(c.lay.pq_part), nullptr);
+            k_dwt_tiles<T, 1><<<w.ni, kThreads, 0, s>>>(lays, c.at<int4>(c.lay.ana_items) + w.loff, f,
+                                                         c.at<T>(c.lay.psi_layers), buf[(step + 1) & 1], buf[step & 1],
+                                                         y, c.at<T>(c.lay.prior_a), x, c.at<double>(c.lay.pq_part),
+                                                         nullptr);
             break;
         }
         case KID_DWT_COARSE:
-            k_dwt_coarse<T, 1><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J - 1) & 1],
+            k_dwt_coarse<T, 1><<<c.L, kCoarseThreads, 0, s>>>(lays, f, c.at<T>(c.lay.psi_layers), buf[(J + 1) & 1],
                                                                  y, c.at<T>(c.lay.prior_a), x,
                                                                  c.at<double>(c.lay.pq_part), nullptr);
             break;

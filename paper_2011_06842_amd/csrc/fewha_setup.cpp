@@ -23,9 +23,12 @@ int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 // Workgroup table that gives die x (workgroups x, x + kXcds, ...) the x-th contiguous share of
 // `items`, so that neighbouring tiles share one die's L2; padding entries are (-1, 0).
-std::vector<int2> die_order(const std::vector<int2>& items) {
+template <typename Item>
+std::vector<Item> die_order(const std::vector<Item>& items) {
     const int T = int(items.size()), grid = round_up(std::max(T, 1), kXcds), per = grid / kXcds;
-    std::vector<int2> out(grid, make_int2(-1, 0));
+    Item pad{};
+    pad.x = -1;   // padding: the kernels return at once
+    std::vector<Item> out(grid, pad);
     for (int b = 0; b < grid; ++b) {
         const int e = (b % kXcds) * per + b / kXcds;
         if (e < T) out[b] = items[e];
@@ -153,7 +156,8 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
 struct Sizes {
     int B = 0, L = 0, G = 0, slots = 0, esz = 8, KE = 1;
     int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;   // pairs: also the record bases
-    int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, step_list = 0, gather_rows = 1;
+    int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, gather_rows = 1;
+    int syn_small = 0, syn_large = 0, ana_items = 0, ana_groups = 0;
     int64_t gwin = 0;   // gather windows: (layer tile, sensor of its instance) pairs
     std::vector<StepInfo> steps;
 };
@@ -171,15 +175,41 @@ int vec_blocks(int64_t n, int be) { return int(std::min<int64_t>(kVecBlocksMax, 
 // sums its Gram partials exactly as the same instance alone does.
 int gram_blocks(int64_t n) { return int(std::min<int64_t>(kGramBlocks, std::max<int64_t>(1, (n + kGramElems - 1) / kGramElems))); }
 
-// (p, q) partials of one layer: one per tile of every tiled analysis level, then the coarse one
-int layer_pq(int n, int levels, int cb) {
-    const int lc = coarse_first_level(n, cb);
-    int t = 0;
-    for (int lev = 1; lev <= levels && lev < lc; ++lev) {
-        const int m = (n >> (lev - 1)) / 2 / kAT;
-        t += m * m;
+// Tiled analysis levels of one layer: for every group of block sizes above the coarse block
+// (groups of kmax consecutive sizes counted from the coarse end, one launch each) the layer has
+// levels in, its first level there and their count; finest first.
+struct AnaSeg {
+    int g, l1, k;
+};
+std::vector<AnaSeg> ana_segments(int n, int levels, int cb, int kmax) {
+    std::vector<AnaSeg> out;
+    const int last = std::min(levels, coarse_first_level(n, cb) - 1);
+    for (int lev = 1; lev <= last; ++lev) {
+        const int g = (ilog2(n >> (lev - 1)) - ilog2(cb) - 1) / kmax;
+        if (out.empty() || out.back().g != g) out.push_back(AnaSeg{g, lev, 1});
+        else ++out.back().k;
     }
+    return out;
+}
+
+// workgroups (tiles of the segment's last level) of one segment
+int seg_tiles(int n, const AnaSeg& s) {
+    const int m = (n >> (s.l1 - 1)) >> s.k, t = ana_tile(s.k);
+    return (m / t) * (m / t);
+}
+
+// (p, q) partials of one layer: one per tiled analysis workgroup (launches in order), then the
+// coarse one
+int layer_pq(int n, int levels, int cb, int kmax) {
+    int t = 0;
+    for (const AnaSeg& sg : ana_segments(n, levels, cb, kmax)) t += seg_tiles(n, sg);
     return t + 1;
+}
+
+// Synthesis tiles of one layer with tile side st (n when the layer is smaller).
+int syn_tiles(int n, int st) {
+    const int ts = std::min(st, n);
+    return (n / ts) * (n / ts);
 }
 
 Sizes batch_sizes(const fewha_config* cfgs, int nb) {
@@ -188,14 +218,18 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
     z.esz = cfgs[0].precision == FEWHA_FP64 ? 8 : 4;
     z.slots = cfgs[0].recycle_k + cfgs[0].max_iter;
     z.KE = std::max(1, 2 * cfgs[0].recycle_k * (cfgs[0].recycle_k + 1));   // X and Y of the Gram pass
-    const int cb = coarse_block(cfgs[0].precision);
+    const int cb = coarse_block(cfgs[0].precision), kmax = ana_levels_per_launch(cfgs[0].precision);
     for (int i = 0; i < nb; ++i) {
         const fewha_config* c = &cfgs[i];
         int64_t Ni = 0;
         for (int l = 0; l < c->n_layers; ++l) {
             const int n = c->layers[l].n;
             Ni += int64_t(n) * n;
-            z.NPQ += layer_pq(n, c->layers[l].levels, cb);
+            z.NPQ += layer_pq(n, c->layers[l].levels, cb, kmax);
+            z.syn_small += syn_tiles(n, kSynTile / 2);
+            z.syn_large += syn_tiles(n, kSynTile);
+            for (const AnaSeg& sg : ana_segments(n, c->layers[l].levels, cb, kmax))
+                z.ana_groups = std::max(z.ana_groups, sg.g + 1);
         }
         for (int g = 0; g < c->n_wfs; ++g) {
             const int ns = c->wfs[g].n_sub;
@@ -223,19 +257,27 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
             z.gather_tiles += gt;
             z.gwin += int64_t(gt) * cfgs[i].n_wfs;
         }
-    // tiled wavelet levels: block sizes above the coarse block, with every layer that has them
-    for (int nbs = 2 * cb; nbs <= 1024; nbs *= 2) {
+    z.syn_small = round_up(z.syn_small, kXcds);
+    z.syn_large = round_up(z.syn_large, kXcds);
+    // tiled analysis launches: one per group of block sizes that has workgroups, finest first
+    for (int g = z.ana_groups - 1; g >= 0; --g) {
         StepInfo st;
-        st.nb = nbs;
-        st.loff = z.step_list;
+        st.loff = z.ana_items;
+        int items = 0;
         for (int i = 0; i < nb; ++i)
             for (int l = 0; l < cfgs[i].n_layers; ++l) {
                 const fewha_layer& Ly = cfgs[i].layers[l];
-                if (Ly.n >= nbs && ilog2(Ly.n / nbs) + 1 <= Ly.levels) ++st.nl;
+                for (const AnaSeg& sg : ana_segments(Ly.n, Ly.levels, cb, kmax))
+                    if (sg.g == g) {
+                        items += seg_tiles(Ly.n, sg);
+                        ++st.nl;
+                        st.nb = std::max(st.nb, Ly.n >> (sg.l1 - 1));
+                    }
             }
-        if (st.nl) {
+        if (items) {
+            st.ni = round_up(items, kXcds);
+            z.ana_items += st.ni;
             z.steps.push_back(st);
-            z.step_list += st.nl;
         }
     }
     return z;
@@ -281,7 +323,8 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.insts = take(sizeof(InstDev) * z.B);
     lo.vecblk = take(sizeof(VecBlk) * z.VB);
     lo.gramblk = take(sizeof(GramBlk) * z.GB);
-    lo.step_layers = take(sizeof(int32_t) * std::max(1, z.step_list));
+    lo.syn_items = take(sizeof(int2) * (z.syn_small + z.syn_large));
+    lo.ana_items = take(sizeof(int4) * std::max(1, z.ana_items));
     lo.data_tiles = take(sizeof(int2) * round_up(z.data_tiles, kXcds));
     lo.gather_tiles = take(sizeof(int2) * round_up(z.gather_tiles, kXcds));
     lo.grecs = take((z.esz == 8 ? sizeof(GatherRec<double>) : sizeof(GatherRec<float>)) * z.ranges);
@@ -444,7 +487,7 @@ fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, 
         d.g0 = g0;
         d.ng = G;
         d.pq0 = pqoff;
-        d.pq_coarse = layer_pq(d.n, d.levels, cb) - 1;
+        d.pq_coarse = layer_pq(d.n, d.levels, cb, ana_levels_per_launch(cfg->precision)) - 1;
         d.rb0 = 0;                                   // set once every pair exists (build_tables)
         pqoff += d.pq_coarse + 1;
         off += int64_t(d.n) * d.n;
@@ -651,11 +694,45 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     ctx.max_rng = 0;
     for (size_t i = 1; i < t.rng.size(); i += 2) ctx.max_rng = std::max(ctx.max_rng, int(t.rng[i]));
     // layers of every tiled wavelet level, and the block -> sensor / layer tables
-    std::vector<int32_t> sl;
-    for (const StepInfo& st : z.steps)
+    // synthesis tiles (half-size tiles, then full-size), die-ordered per launch
+    std::vector<int2> s16, s32;
+    for (int l = 0; l < z.L; ++l) {
+        for (int k = 0; k < syn_tiles(t.ld[l].n, kSynTile / 2); ++k) s16.push_back(make_int2(l, k));
+        for (int k = 0; k < syn_tiles(t.ld[l].n, kSynTile); ++k) s32.push_back(make_int2(l, k));
+    }
+    std::vector<int2> syn = die_order(s16);
+    ctx.syn_small = int(syn.size());
+    {
+        const std::vector<int2> o32 = die_order(s32);
+        ctx.syn_large = int(o32.size());
+        syn.insert(syn.end(), o32.begin(), o32.end());
+    }
+    // tiled analysis items (layer, tile, l1 | k << 8 | tile side << 16, partial slot) of every
+    // launch, the partial slots of a layer numbered in launch and tile order
+    std::vector<int4> ana;
+    {
+        const int kmax = ana_levels_per_launch(cfgs[0].precision);
+        std::vector<int> slot(z.L, 0);
+        for (int g = z.ana_groups - 1; g >= 0; --g) {
+            std::vector<int4> items;
+            for (int l = 0; l < z.L; ++l)
+                for (const AnaSeg& sg : ana_segments(t.ld[l].n, t.ld[l].levels, cb, kmax))
+                    if (sg.g == g)
+                        for (int k = 0; k < seg_tiles(t.ld[l].n, sg); ++k)
+                            items.push_back(make_int4(l, k, sg.l1 | (sg.k << 8) | (ana_tile(sg.k) << 16), slot[l]++));
+            if (!items.empty()) {
+                const std::vector<int4> o = die_order(items);
+                ana.insert(ana.end(), o.begin(), o.end());
+            }
+        }
         for (int l = 0; l < z.L; ++l)
-            if (t.ld[l].n >= st.nb && ilog2(t.ld[l].n / st.nb) + 1 <= t.ld[l].levels) sl.push_back(l);
-    if (sl.empty()) sl.push_back(0);
+            if (slot[l] != t.ld[l].pq_coarse) { ctx.err = "internal: analysis partial count mismatch"; return FEWHA_E_INVAL; }
+        if (int(ana.size()) != z.ana_items || int(syn.size()) != z.syn_small + z.syn_large) {
+            ctx.err = "internal: wavelet item count mismatch";
+            return FEWHA_E_INVAL;
+        }
+        if (ana.empty()) ana.push_back(make_int4(-1, 0, 0, 0));
+    }
     std::vector<int2> dt_items, gt_items;
     for (int g = 0; g < z.G; ++g)
         for (int k = 0; k < t.wd[g].tiles_x * t.wd[g].tiles_x; ++k) dt_items.push_back(make_int2(g, k));
@@ -774,7 +851,8 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
               up(lo.insts, ctx.insts.data(), sizeof(InstDev) * ctx.insts.size()) &&
               up(lo.vecblk, vb.data(), sizeof(VecBlk) * vb.size()) &&
               up(lo.gramblk, gb.data(), sizeof(GramBlk) * gb.size()) &&
-              up(lo.step_layers, sl.data(), sizeof(int32_t) * sl.size()) &&
+              up(lo.syn_items, syn.data(), sizeof(int2) * syn.size()) &&
+              up(lo.ana_items, ana.data(), sizeof(int4) * ana.size()) &&
               up(lo.data_tiles, dtiles.data(), sizeof(int2) * dtiles.size()) &&
               up(lo.gather_tiles, gtiles.data(), sizeof(int2) * gtiles.size()) &&
               up(lo.grecs, recs.data(), recs.size()) &&
