@@ -78,9 +78,7 @@ def op_kernel_bytes(name, step, spec, steps, N, S, V, e):
     for l in spec.layers:
         segs, lc = ana_segments(l.n, l.levels, kmax)
         if name == "dwt_coarse":  # LL block (or image) in; coefficients, prior and x of the block
-            if l.levels >= lc:
-                b = l.n >> (lc - 1)
-                total += 4 * b * b
+            total += 4 * (l.n >> (lc - 1)) ** 2 if l.levels >= lc else 0
             continue
         for g, l1, k in segs:     # input window of the launch; 3 bands per level (+ prior, x)
             if g != groups[step]:
@@ -256,6 +254,8 @@ def run_batch(args, dev, atmos, t_gen):
     sp = spec.copy()
     sp.block_elems = best
     ctx = fw.FewhaContext([sp] * B, device=dev, precond_inv=jinv)
+    tuned, tune_ms = ctx.fewha_autotune(reps=5)
+    log(f"batched leg: autotuner chose {tuned}")
     wall, fm = timed(ctx, args.batch_warmup, args.batch_steps)
     log(f"batched leg: timed {args.batch_steps} frames, p50 {np.median(fm):.3f} ms")
     N, S = ctx.N, ctx.S
@@ -315,6 +315,7 @@ def run_batch(args, dev, atmos, t_gen):
         "instance_frames_per_s": round(B * args.batch_steps / wall, 1),
         "steps": args.batch_steps, "warmup": args.batch_warmup,
         "block_elems": best, "tuner_frame_ms": {str(k): round(v, 4) for k, v in tune.items()},
+        "autotuner": {"chosen": tuned, "apply_ms_per_candidate": {k: round(v, 4) for k, v in tune_ms.items()}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(dom, "batched"),
                      "share_of_frame": round(kern[dom]["ms_per_frame"] / float(np.median(fm)), 3)},
@@ -855,6 +856,8 @@ def run_single(args, dev, spec, seq):
     V = sum((w.n_sub + 1) ** 2 for w in spec.wfs)
     c = torch.empty(N, dtype=torch.float32, device=dev)
     info = ctx.new_info()
+    tuned, tune_ms = ctx.fewha_autotune(reps=args.kernel_reps)   # tile shapes (no result bit changes)
+    log(f"single instance: autotuner chose {tuned} ({ {k: round(v * 1000, 2) for k, v in tune_ms.items()} } us per apply)")
     time_frames(ctx, slopes, 0, args.warmup, c, info)
     wall, frame_ms = time_frames(ctx, slopes, args.warmup, args.steps, c, info)
     last_info = fw.decode_info(info)
@@ -885,6 +888,7 @@ def run_single(args, dev, spec, seq):
     # per-kernel durations from HIP events around every launch of a fresh run of the same
     # frames (profiling synchronises per call, so it runs outside the timed region)
     pctx = fw.FewhaContext(spec, device=dev)
+    pctx.fewha_set_tuning(tuned["syn_tile"], tuned["gather_rows"])
     pc = torch.empty_like(c)
     for t in range(args.warmup):
         pctx.fewha_solve_aug(slopes[t], pc)
@@ -974,6 +978,7 @@ def run_single(args, dev, spec, seq):
         "timed_frames_ms_p50": round(float(np.percentile(frame_ms, 50)), 4),
         "frames_per_s": round(args.steps / wall, 1),
         "operator_apply_ms": round(op_ms, 4),
+        "autotuner": {"chosen": tuned, "apply_us_per_candidate": {k: round(v * 1000, 2) for k, v in tune_ms.items()}},
         "operator_applies_per_s_alone": round(1000.0 / op_ms, 1),
         "last_frame_rel_res": last_info["rel_res"],
         "roofline": roofline,

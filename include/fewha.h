@@ -254,12 +254,37 @@ const char* fewha_kernel_name(int32_t i);
 
 /* Diagnostic timer of one operator kernel (profiler index 0-4: synthesis, fused data term,
  * propagation adjoint, tiled analysis, coarse analysis; `step` selects the tiled analysis
- * launch, see fewha_wavelet_steps).  The kernel is launched `reps` times with
+ * launch, see fewha_wavelet_steps; -1 times a whole application of M).  The kernel is launched `reps` times with
  * the arguments it has inside M x (input: the carried coefficients), captured into one graph and
  * replayed between two events recorded on `stream`; *avg_ms receives the mean duration.
  * Overwrites the context's scratch vectors (not the carried state).  Synchronises `stream`. */
 fewha_status fewha_time_kernel(fewha_ctx* ctx, int32_t kernel, int32_t step, int32_t reps, void* stream,
                                float* avg_ms);
+
+/* Tile shapes of the operator kernels that change no result bit: the synthesis image tile
+ * (16 or 32; 0 = 16 when 32 would give fewer than 256 workgroups, the default) and the layer
+ * rows per thread of the propagation adjoint's gather (1: tiles of 8 x 32 nodes, 4: 32 x 32
+ * with the sensor nodes staged in LDS; default 4 from 2^21 coefficients on). */
+typedef struct {
+    int32_t syn_tile;
+    int32_t gather_rows;
+    int32_t reserved[6];   /* zero */
+} fewha_tuning;
+
+fewha_status fewha_get_tuning(const fewha_ctx* ctx, fewha_tuning* t);   /* the shapes in use (syn_tile resolved) */
+/* Selects tile shapes (FEWHA_E_INVAL for other values); drops the captured frame graphs. */
+fewha_status fewha_set_tuning(fewha_ctx* ctx, const fewha_tuning* t);
+
+/* Autotuner: times every combination of the tile shapes (synthesis 16 / 32 x gather rows 1 /
+ * 4) on `reps` applications of M to the carried coefficients, captured into a graph and
+ * replayed between two events on `stream`; keeps the fastest in the context and returns it in
+ * *best (may be NULL), the mean application time of each candidate in ms[0..n) (order: syn
+ * 16 rows 1, syn 16 rows 4, syn 32 rows 1, syn 32 rows 4) and their count in *n_out.  The
+ * caller stores *best and restores it with fewha_set_tuning on a later context of the same
+ * configuration.  Overwrites the scratch vectors (not the carried state); synchronises
+ * `stream`. */
+fewha_status fewha_autotune(fewha_ctx* ctx, int32_t reps, void* stream, fewha_tuning* best, float* ms, int32_t n,
+                            int32_t* n_out);
 
 /* Tiled analysis launches of the context (finest levels first): the largest block each
  * transforms and the number of layers in it. */

@@ -27,7 +27,8 @@ EXPORTS = ["fewha_workspace_size", "fewha_setup", "fewha_workspace_size_batch", 
            "fewha_instances", "fewha_frame_iterations", "fewha_sizes", "fewha_apply_A", "fewha_rhs",
            "fewha_solve_aug", "fewha_apply_A_noalloc", "fewha_reset", "fewha_apply_piece", "fewha_get_vector", "fewha_state_size",
            "fewha_get_state", "fewha_set_state", "fewha_use_graphs", "fewha_profile", "fewha_profile_read",
-           "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_destroy", "fewha_last_error",
+           "fewha_kernel_name", "fewha_time_kernel", "fewha_wavelet_steps", "fewha_get_tuning", "fewha_set_tuning",
+           "fewha_autotune", "fewha_destroy", "fewha_last_error",
            "fewha_unet_workspace_size", "fewha_unet_setup", "fewha_unet_num_params", "fewha_unet_num_nodes",
            "fewha_unet_set_params", "fewha_unet_get_params", "fewha_unet_forward", "fewha_unet_backward",
            "fewha_unet_adam_step", "fewha_unet_get_grads", "fewha_unet_destroy", "fewha_unet_last_error",
@@ -71,6 +72,10 @@ class fewha_unet_config(C.Structure):
 
 class fewha_warmstart(C.Structure):
     _fields_ = [("scale_c", C.c_float), ("scale_r", C.c_float), ("scale_out", C.c_float)]
+
+
+class fewha_tuning(C.Structure):
+    _fields_ = [("syn_tile", C.c_int32), ("gather_rows", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class fewha_dm(C.Structure):
@@ -124,6 +129,10 @@ def load_library(path: str = LIB_PATH):
         "fewha_kernel_name": ([C.c_int32], C.c_char_p),
         "fewha_time_kernel": ([vp, C.c_int32, C.c_int32, C.c_int32, vp, C.POINTER(C.c_float)], st),
         "fewha_wavelet_steps": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)], st),
+        "fewha_get_tuning": ([vp, C.POINTER(fewha_tuning)], st),
+        "fewha_set_tuning": ([vp, C.POINTER(fewha_tuning)], st),
+        "fewha_autotune": ([vp, C.c_int32, vp, C.POINTER(fewha_tuning), C.POINTER(C.c_float), C.c_int32,
+                            C.POINTER(C.c_int32)], st),
         "fewha_destroy": ([vp], st),
         "fewha_last_error": ([vp], C.c_char_p),
         "fewha_unet_workspace_size": ([C.POINTER(fewha_unet_config), C.POINTER(C.c_size_t)], st),
@@ -406,6 +415,28 @@ class FewhaContext:
         ms = C.c_float()
         _check(self.lib.fewha_time_kernel(self.ctx, kernel, step, reps, _stream(stream), C.byref(ms)), self.ctx)
         return ms.value
+
+    def fewha_get_tuning(self) -> dict:
+        """Tile shapes in use: {"syn_tile": 16 | 32, "gather_rows": 1 | 4}."""
+        t = fewha_tuning()
+        _check(self.lib.fewha_get_tuning(self.ctx, C.byref(t)), self.ctx)
+        return {"syn_tile": t.syn_tile, "gather_rows": t.gather_rows}
+
+    def fewha_set_tuning(self, syn_tile=0, gather_rows=None):
+        t = fewha_tuning()
+        t.syn_tile = int(syn_tile)
+        t.gather_rows = int(self.fewha_get_tuning()["gather_rows"] if gather_rows is None else gather_rows)
+        _check(self.lib.fewha_set_tuning(self.ctx, C.byref(t)), self.ctx)
+
+    def fewha_autotune(self, reps=20, stream=None):
+        """Times the tile-shape candidates on M x, keeps the fastest; returns (best, {candidate: ms})."""
+        t = fewha_tuning()
+        ms = (C.c_float * 4)()
+        n = C.c_int32()
+        _check(self.lib.fewha_autotune(self.ctx, int(reps), _stream(stream), C.byref(t), ms, 4, C.byref(n)), self.ctx)
+        cands = [(16, 1), (16, 4), (32, 1), (32, 4)]
+        return ({"syn_tile": t.syn_tile, "gather_rows": t.gather_rows},
+                {f"syn{a}_rows{b}": float(ms[i]) for i, (a, b) in enumerate(cands[:n.value])})
 
     def fewha_wavelet_steps(self):
         """[(largest block, layer count)] of the tiled analysis launches (finest first)."""

@@ -431,6 +431,59 @@ fewha_status fewha_time_kernel(fewha_ctx* ctx, int32_t kernel, int32_t step, int
     return FEWHA_OK;
 }
 
+fewha_status fewha_get_tuning(const fewha_ctx* ctx, fewha_tuning* t) {
+    if (!ctx || !t) return FEWHA_E_INVAL;
+    std::memset(t, 0, sizeof(*t));
+    const fewha::Ctx& c = ctx->c;
+    t->syn_tile = c.syn_tile ? c.syn_tile : (c.syn_large < fewha::kSmallTileBelow ? fewha::kSynTile / 2 : fewha::kSynTile);
+    t->gather_rows = c.gather_rows;
+    return FEWHA_OK;
+}
+
+fewha_status fewha_set_tuning(fewha_ctx* ctx, const fewha_tuning* t) {
+    if (!ctx || !t) return FEWHA_E_INVAL;
+    if (t->syn_tile != 0 && t->syn_tile != fewha::kSynTile / 2 && t->syn_tile != fewha::kSynTile)
+        return fail(ctx, FEWHA_E_INVAL, "syn_tile must be 0, 16 or 32");
+    if (t->gather_rows != 1 && t->gather_rows != 4) return fail(ctx, FEWHA_E_INVAL, "gather_rows must be 1 or 4");
+    fewha::Ctx& c = ctx->c;
+    if (c.syn_tile != t->syn_tile || c.gather_rows != t->gather_rows) {
+        c.syn_tile = t->syn_tile;
+        c.gather_rows = t->gather_rows;
+        fewha::release_graphs(c);   // the captured frames hold the old launches
+    }
+    return FEWHA_OK;
+}
+
+fewha_status fewha_autotune(fewha_ctx* ctx, int32_t reps, void* stream, fewha_tuning* best, float* ms, int32_t n,
+                            int32_t* n_out) {
+    if (!ctx || reps < 1) return FEWHA_E_INVAL;
+    fewha::Ctx& c = ctx->c;
+    const int syn[2] = {fewha::kSynTile / 2, fewha::kSynTile}, rows[2] = {1, 4};
+    fewha_tuning cand[4] = {}, keep = {};
+    (void)fewha_get_tuning(ctx, &keep);
+    float tm[4] = {};
+    int k = 0, b = -1;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j, ++k) {
+            cand[k].syn_tile = syn[i];
+            cand[k].gather_rows = rows[j];
+            (void)fewha_set_tuning(ctx, &cand[k]);
+            hipError_t e = c.prec == FEWHA_FP64
+                               ? fewha::time_operator_kernel<double>(c, fewha::KID_APPLY, 0, reps, as_stream(stream), &tm[k])
+                               : fewha::time_operator_kernel<float>(c, fewha::KID_APPLY, 0, reps, as_stream(stream), &tm[k]);
+            if (e != hipSuccess) {
+                (void)fewha_set_tuning(ctx, &keep);
+                return fail(ctx, FEWHA_E_HIP, std::string("autotune timing failed: ") + hipGetErrorString(e));
+            }
+            if (b < 0 || tm[k] < tm[b]) b = k;
+        }
+    (void)fewha_set_tuning(ctx, &cand[b]);
+    if (best) *best = cand[b];
+    for (int i = 0; i < n && i < 4; ++i) ms[i] = tm[i];
+    if (n_out) *n_out = 4;
+    return FEWHA_OK;
+}
+
 fewha_status fewha_wavelet_steps(const fewha_ctx* ctx, int32_t* block_sizes, int32_t* layer_counts, int32_t n,
                                  int32_t* n_out) {
     if (!ctx) return FEWHA_E_INVAL;

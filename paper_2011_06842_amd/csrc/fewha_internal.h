@@ -16,7 +16,7 @@ namespace fewha {
 constexpr int kThreads = 256;       // threads of every 1-D kernel (4 wavefronts of 64)
 constexpr int kVecBlocksMax = 1024; // vector-kernel workgroups of one instance (grid-stride beyond)
 constexpr int kDefaultBlockElems = 384;  // default elements per vector workgroup
-constexpr int kGramElems = 1536;    // elements per Gram workgroup (one instance: <= kGramBlocks)
+constexpr int kGramElems = 768;     // elements per Gram workgroup (one instance: <= kGramBlocks)
 constexpr int kKMax = FEWHA_MAX_RECYCLE;
 constexpr int kSlotsMax = kKMax + 256;
 constexpr int kTile = 14;           // wavefront-node tile side of the fused data-term kernel (16 with the halo)
@@ -36,7 +36,7 @@ constexpr int kGRowStep = kThreads / kGT;        // tile rows per gather thread 
 constexpr int64_t kGatherWide = int64_t(1) << 21;  // from this many coefficients on, 4 rows per gather thread
 constexpr int kRMax = 6;            // contributions per layer row/column held by a gather record
 constexpr int kXcds = 8;            // accelerator complex dies; workgroup i runs on die i mod kXcds
-constexpr int kGramBlocks = 128;    // Gram workgroups of one instance at most (partials per entry)
+constexpr int kGramBlocks = 256;    // Gram workgroups of one instance at most (partials per entry)
 constexpr int kGramThreads = 1024;  // threads of a Gram workgroup (16 wavefronts)
 constexpr int kDataThreads = 256;   // threads of the fused data-term kernel (one halo-tile node each)
 constexpr int kSolveThreads = 1024; // threads of the single-block Gram reduction and solve
@@ -157,6 +157,7 @@ enum KernelId : int {
     KID_UPDATE2, KID_FINISH, KID_FWD_SLOPES, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
+constexpr int KID_APPLY = -1;   // the per-kernel timer's id of a whole application of M
 
 struct Profiler {
     bool on = false;
@@ -180,8 +181,9 @@ struct Ctx {
     int VB = 0, GB = 0;        // vector and Gram workgroups of all instances
     int block_elems = kDefaultBlockElems;
     int data_grid = 0;         // workgroups of the fused data term (tiles, padded to kXcds)
-    int gather_grid = 0;       // workgroups of the gather (layer tiles, padded to kXcds)
-    int gather_rows = 1;       // layer rows per gather thread (tile of 8 gather_rows x kGT nodes)
+    int gather_grid1 = 0, gather_grid4 = 0;   // gather workgroups (layer tiles, padded to kXcds) of 1 and 4 rows
+    int gather_rows = 1;       // layer rows per gather thread (tile of 8 gather_rows x kGT nodes), 1 or 4
+    int syn_tile = 0;          // synthesis image tile: 16, 32, or 0 (by the number of tiles)
     std::vector<InstDev> insts;
     std::vector<int> layers_n;     // grid size of every layer (host)
     std::vector<int64_t> s_offs;   // slope offsets of the instances (B + 1)

@@ -407,6 +407,121 @@ __device__ __forceinline__ void dwt_tiles_body(const LayerDev& d, int4 it, const
     }
 }
 
+// Levels coarse_lev..levels of one layer in LDS (the coarse block, in A and B).  After the
+// last level the block holds the whole coarse Mallat pyramid; it is written once, each thread
+// owning fixed positions whose prior and x operands it requested first.  Returns the thread's
+// share of the partial ((x, out) for MODE 1, (out, out) for MODE 2).
+template <typename T, int MODE>
+__device__ __forceinline__ double dwt_coarse_body(const LayerDev& d, const Filt<T>& f, const T* __restrict__ img,
+                                                  const T* __restrict__ ll_in, T* __restrict__ out,
+                                                  const T* __restrict__ prior_a, const T* __restrict__ xprior,
+                                                  T* __restrict__ A, T* __restrict__ B) {
+    constexpr bool PRIOR = MODE == 1;
+    constexpr int CB = CoarseBlock<T>::value;
+    const int n = d.n, lc = d.coarse_lev, levels = d.levels;
+    double dot = 0;
+    if (levels >= lc) {
+        // 16-byte chunks of consecutive positions of a row (nb0 >= 8 is a multiple of the
+        // chunk; layer offsets and rows keep chunks aligned)
+        using VC = Vec16<T>;
+        using V = typename VC::type;
+        constexpr int PERC = CB * CB / (VC::n * kThreads);
+        const int nb0 = n >> (lc - 1), lg0 = ilog2i(nb0), nch = nb0 * nb0 / VC::n;
+        const T* src = (lc == 1 ? img : ll_in) + d.off;
+        const Taps<T> tp(f);
+        V pa[PERC], xp[PERC], v[PERC];
+#pragma unroll
+        for (int k = 0; k < PERC; ++k) {   // unconditional (clamped) loads
+            const int ch0 = threadIdx.x + k * kThreads, ch = ch0 < nch ? ch0 : 0;
+            const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
+            v[k] = *reinterpret_cast<const V*>(src + r * n + c);
+            pa[k] = xp[k] = V{};
+            if (PRIOR) {
+                pa[k] = *reinterpret_cast<const V*>(prior_a + size_t(d.off) + r * n + c);
+                xp[k] = *reinterpret_cast<const V*>(xprior + size_t(d.off) + r * n + c);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PERC; ++k) {
+            const int ch = threadIdx.x + k * kThreads;
+            if (ch < nch) {
+                const int e = ch * VC::n;
+                VC::put(&A[(e >> lg0) * CB + (e & (nb0 - 1))], v[k]);
+            }
+        }
+        __syncthreads();
+        for (int lev = lc; lev <= levels; ++lev) {
+            const int nb = n >> (lev - 1), m = nb >> 1, lgm = ilog2i(m), lg = lgm + 1;
+            for (int e = threadIdx.x; e < nb * m; e += kThreads) {   // rows: [a | d]
+                const int y = e >> lgm, k = e & (m - 1);
+                T lo = 0, hi = 0;
+#pragma unroll
+                for (int t = 0; t < 6; ++t) {
+                    const T v = A[y * CB + ((2 * k + t) & (nb - 1))];
+                    lo += tp.h[t] * v;
+                    hi += tp.g[t] * v;
+                }
+                B[y * CB + k] = lo;
+                B[y * CB + m + k] = hi;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < m * nb; e += kThreads) {   // columns
+                const int k = e >> lg, x = e & (nb - 1);
+                T lo = 0, hi = 0;
+#pragma unroll
+                for (int t = 0; t < 6; ++t) {
+                    const T v = B[((2 * k + t) & (nb - 1)) * CB + x];
+                    lo += tp.h[t] * v;
+                    hi += tp.g[t] * v;
+                }
+                A[k * CB + x] = lo;
+                A[(m + k) * CB + x] = hi;
+            }
+            __syncthreads();
+        }
+        const T s = T(d.inv_delta);
+#pragma unroll
+        for (int k = 0; k < PERC; ++k) {
+            const int ch = threadIdx.x + k * kThreads;
+            if (ch < nch) {
+                const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
+                T val[VC::n], a[VC::n], x[VC::n];
+                VC::put(a, pa[k]);
+                VC::put(x, xp[k]);
+#pragma unroll
+                for (int j = 0; j < VC::n; ++j) {
+                    val[j] = A[r * CB + c + j] * s;
+                    if (PRIOR) val[j] += a[j] * x[j];
+                    dot += double(val[j]) * (MODE == 2 ? double(val[j]) : double(x[j]));
+                }
+                VC::store(out + size_t(d.off) + size_t(r) * n + c, val);
+            }
+        }
+    }
+    return dot;
+}
+
+// The coarse levels of every layer, one workgroup per layer.  (A fused variant, in which the
+// workgroup that finishes a layer's last tile runs them, needs device-scope fences around a
+// counter; on gfx950 those cost more than this launch.)
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kThreads) k_dwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
+                                                          const T* __restrict__ img, const T* __restrict__ ll_in,
+                                                          T* __restrict__ out, const T* __restrict__ prior_a,
+                                                          const T* __restrict__ xprior, double* __restrict__ dotpart,
+                                                          const int32_t* __restrict__ skip) {
+    constexpr int CB = CoarseBlock<T>::value;
+    __shared__ T A[CB * CB];
+    __shared__ T B[CB * CB];
+    const LayerDev d = lays[blockIdx.x];
+    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
+    const double dot = dwt_coarse_body<T, MODE>(d, f, img, ll_in, out, prior_a, xprior, A, B);
+    if (MODE != 0 && dotpart) {
+        const double vv[1] = {dot};
+        block_partials<1>(vv, dotpart, 0, 0, d.pq0 + d.pq_coarse);
+    }
+}
+
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) k_dwt_tiles(const LayerDev* __restrict__ lays, const int4* __restrict__ items,
                                                          Filt<T> f, const T* __restrict__ img, const T* __restrict__ ll_in,
@@ -432,114 +547,6 @@ __global__ void __launch_bounds__(kThreads) k_dwt_tiles(const LayerDev* __restri
     if (MODE != 0 && dotpart) {
         const double vv[1] = {dot};
         block_partials<1>(vv, dotpart, 0, 0, d.pq0 + it.w);
-    }
-}
-
-// Levels coarse_lev..levels of one layer in LDS (the coarse block).  After the last
-// level the block holds the whole coarse Mallat pyramid; it is written once, each thread
-// owning fixed positions whose prior and x operands it requested at kernel start.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kCoarseThreads) k_dwt_coarse(const LayerDev* __restrict__ lays, Filt<T> f,
-                                                                const T* __restrict__ img, const T* __restrict__ ll_in,
-                                                                T* __restrict__ out, const T* __restrict__ prior_a,
-                                                                const T* __restrict__ xprior,
-                                                                double* __restrict__ dotpart, const int32_t* __restrict__ skip) {
-    constexpr bool PRIOR = MODE == 1;
-    constexpr int CB = CoarseBlock<T>::value;
-    __shared__ T A[CB * CB];
-    __shared__ T B[CB * CB];
-    const LayerDev d = lays[blockIdx.x];
-    if (skip && skip[d.inst]) return;   // tolerance mode: the instance has converged
-    const int n = d.n, lc = d.coarse_lev, levels = d.levels;
-    double dot = 0;
-    if (levels >= lc) {
-        // 16-byte chunks of consecutive positions of a row (nb0 >= 8 is a multiple of the
-        // chunk; layer offsets and rows keep chunks aligned)
-        using VC = Vec16<T>;
-        using V = typename VC::type;
-        constexpr int PERC = CB * CB / (VC::n * kCoarseThreads);
-        const int nb0 = n >> (lc - 1), lg0 = ilog2i(nb0), nch = nb0 * nb0 / VC::n;
-        const T* src = (lc == 1 ? img : ll_in) + d.off;
-        const Taps<T> tp(f);
-        V pa[PERC], xp[PERC], v[PERC];
-#pragma unroll
-        for (int k = 0; k < PERC; ++k) {   // unconditional (clamped) loads
-            const int ch0 = threadIdx.x + k * kCoarseThreads, ch = ch0 < nch ? ch0 : 0;
-            const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
-            v[k] = *reinterpret_cast<const V*>(src + r * n + c);
-            pa[k] = xp[k] = V{};
-            if (PRIOR) {
-                pa[k] = *reinterpret_cast<const V*>(prior_a + size_t(d.off) + r * n + c);
-                xp[k] = *reinterpret_cast<const V*>(xprior + size_t(d.off) + r * n + c);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < PERC; ++k) {
-            const int ch = threadIdx.x + k * kCoarseThreads;
-            if (ch < nch) {
-                const int e = ch * VC::n;
-                VC::put(&A[(e >> lg0) * CB + (e & (nb0 - 1))], v[k]);
-            }
-        }
-        __syncthreads();
-        for (int lev = lc; lev <= levels; ++lev) {
-            const int nb = n >> (lev - 1), m = nb >> 1, lgm = ilog2i(m), lg = lgm + 1;
-            for (int e = threadIdx.x; e < nb * m; e += kCoarseThreads) {   // rows: [a | d]
-                const int y = e >> lgm, k = e & (m - 1);
-                T lo = 0, hi = 0;
-#pragma unroll
-                for (int t = 0; t < 6; ++t) {
-                    const T v = A[y * CB + ((2 * k + t) & (nb - 1))];
-                    lo += tp.h[t] * v;
-                    hi += tp.g[t] * v;
-                }
-                B[y * CB + k] = lo;
-                B[y * CB + m + k] = hi;
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < m * nb; e += kCoarseThreads) {   // columns
-                const int k = e >> lg, x = e & (nb - 1);
-                T lo = 0, hi = 0;
-#pragma unroll
-                for (int t = 0; t < 6; ++t) {
-                    const T v = B[((2 * k + t) & (nb - 1)) * CB + x];
-                    lo += tp.h[t] * v;
-                    hi += tp.g[t] * v;
-                }
-                A[k * CB + x] = lo;
-                A[(m + k) * CB + x] = hi;
-            }
-            __syncthreads();
-        }
-        const T s = T(d.inv_delta);
-#pragma unroll
-        for (int k = 0; k < PERC; ++k) {
-            const int ch = threadIdx.x + k * kCoarseThreads;
-            if (ch < nch) {
-                const int e = ch * VC::n, r = e >> lg0, c = e & (nb0 - 1);
-                T val[VC::n], a[VC::n], x[VC::n];
-                VC::put(a, pa[k]);
-                VC::put(x, xp[k]);
-#pragma unroll
-                for (int j = 0; j < VC::n; ++j) {
-                    val[j] = A[r * CB + c + j] * s;
-                    if (PRIOR) val[j] += a[j] * x[j];
-                    dot += double(val[j]) * (MODE == 2 ? double(val[j]) : double(x[j]));
-                }
-                VC::store(out + size_t(d.off) + size_t(r) * n + c, val);
-            }
-        }
-    }
-    if (MODE != 0 && dotpart) {
-        __shared__ double sh[kCoarseThreads / 64];
-        const double w = wave_sum(dot);
-        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0;
-            for (int k = 0; k < kCoarseThreads / 64; ++k) t += sh[k];
-            dotpart[d.pq0 + d.pq_coarse] = t;
-        }
     }
 }
 
@@ -1087,7 +1094,7 @@ void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* 
     const LayerDev* lays = c.at<LayerDev>(c.lay.layers);
     const int2* items = c.at<int2>(c.lay.syn_items);
     ProfScope ps_(c, KID_IDWT, s);
-    if (c.syn_large < kSmallTileBelow)
+    if (c.syn_tile == kSynTile / 2 || (c.syn_tile == 0 && c.syn_large < kSmallTileBelow))
         k_idwt<T, kSynTile / 2><<<c.syn_small, kThreads, 0, s>>>(lays, items, f, x, phi, skip);
     else
         k_idwt<T, kSynTile><<<c.syn_large, kThreads, 0, s>>>(lays, items + c.syn_small, f, x, phi, skip);
@@ -1147,15 +1154,17 @@ template <typename T>
 void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s, const int32_t* skip) {
     ProfScope ps_(c, KID_ADJ_GATHER, s);
     if (c.max_rng <= kRMax) {
+        const bool wide = c.gather_rows > 1;
+        const int grid = wide ? c.gather_grid4 : c.gather_grid1;
+        const int2* tiles = c.at<int2>(c.lay.gather_tiles) + (wide ? c.gather_grid1 : 0);
         auto go = [&](auto kern) {
-            kern<<<c.gather_grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
-                                                   c.at<int2>(c.lay.gather_tiles), c.at<int64_t>(c.lay.recbase),
+            kern<<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
+                                                   tiles, c.at<int64_t>(c.lay.recbase),
                                                    c.at<GatherRec<T>>(c.lay.grecs), psi_nodes, psi_layers, skip);
         };
-        const bool wide = c.gather_rows > 1;
         auto gow = [&](auto kern) {
-            kern<<<c.gather_grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
-                                                   c.at<int2>(c.lay.gather_tiles), c.at<int64_t>(c.lay.recbase),
+            kern<<<grid, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<LayerDev>(c.lay.layers),
+                                                   tiles, c.at<int64_t>(c.lay.recbase),
                                                    c.at<GatherRec<T>>(c.lay.grecs), c.at<int4>(c.lay.gwin),
                                                    psi_nodes, psi_layers, skip);
         };
@@ -1225,6 +1234,9 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
     T* y = c.at<T>(c.lay.vy);
     const int J = int(c.steps.size());
     switch (kid) {
+        case KID_APPLY:   // all of M x
+            launch_apply_M<T>(c, x, y, nullptr, s, nullptr, nullptr);
+            break;
         case KID_IDWT:
             launch_winv<T>(c, x, c.at<T>(c.lay.nodal), s, nullptr, nullptr);
             break;

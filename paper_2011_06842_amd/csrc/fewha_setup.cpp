@@ -156,7 +156,7 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
 struct Sizes {
     int B = 0, L = 0, G = 0, slots = 0, esz = 8, KE = 1;
     int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;   // pairs: also the record bases
-    int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles = 0, gather_rows = 1;
+    int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles1 = 0, gather_tiles4 = 0, gather_rows = 1;
     int syn_small = 0, syn_large = 0, ana_items = 0, ana_groups = 0;
     int64_t gwin = 0;   // gather windows: (layer tile, sensor of its instance) pairs
     std::vector<StepInfo> steps;
@@ -250,11 +250,13 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
         z.GB += gram_blocks(Ni);
     }
     // adjoint-gather tiles: 8 x kGT nodes for small systems (more workgroups), 32 x kGT beyond
+    // (both tile shapes are built; the context starts with this one, see fewha_set_tuning)
     z.gather_rows = z.N >= kGatherWide ? 4 : 1;
     for (int i = 0; i < nb; ++i)
         for (int l = 0; l < cfgs[i].n_layers; ++l) {
-            const int gt = gather_tiles_of(cfgs[i].layers[l].n, z.gather_rows);
-            z.gather_tiles += gt;
+            z.gather_tiles1 += gather_tiles_of(cfgs[i].layers[l].n, 1);
+            const int gt = gather_tiles_of(cfgs[i].layers[l].n, 4);
+            z.gather_tiles4 += gt;
             z.gwin += int64_t(gt) * cfgs[i].n_wfs;
         }
     z.syn_small = round_up(z.syn_small, kXcds);
@@ -326,7 +328,7 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.syn_items = take(sizeof(int2) * (z.syn_small + z.syn_large));
     lo.ana_items = take(sizeof(int4) * std::max(1, z.ana_items));
     lo.data_tiles = take(sizeof(int2) * round_up(z.data_tiles, kXcds));
-    lo.gather_tiles = take(sizeof(int2) * round_up(z.gather_tiles, kXcds));
+    lo.gather_tiles = take(sizeof(int2) * (round_up(z.gather_tiles1, kXcds) + round_up(z.gather_tiles4, kXcds)));
     lo.grecs = take((z.esz == 8 ? sizeof(GatherRec<double>) : sizeof(GatherRec<float>)) * z.ranges);
     lo.recbase = take(sizeof(int64_t) * std::max<int64_t>(1, z.pairs));
     lo.gwin = take(sizeof(int4) * std::max<int64_t>(1, z.gwin));
@@ -607,7 +609,8 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     ctx.npq = z.NPQ;
     ctx.slots = z.slots;
     ctx.data_grid = round_up(std::max(z.data_tiles, 1), kXcds);
-    ctx.gather_grid = round_up(std::max(z.gather_tiles, 1), kXcds);
+    ctx.gather_grid1 = round_up(std::max(z.gather_tiles1, 1), kXcds);
+    ctx.gather_grid4 = round_up(std::max(z.gather_tiles4, 1), kXcds);
     ctx.gather_rows = z.gather_rows;
     ctx.steps = z.steps;
     ctx.block_elems = block_elems(&cfgs[0]);
@@ -736,9 +739,17 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     std::vector<int2> dt_items, gt_items;
     for (int g = 0; g < z.G; ++g)
         for (int k = 0; k < t.wd[g].tiles_x * t.wd[g].tiles_x; ++k) dt_items.push_back(make_int2(g, k));
-    for (int l = 0; l < z.L; ++l)
-        for (int k = 0; k < gather_tiles_of(t.ld[l].n, z.gather_rows); ++k) gt_items.push_back(make_int2(l, k));
-    const std::vector<int2> dtiles = die_order(dt_items), gtiles = die_order(gt_items);
+    std::vector<int2> gt_items4;
+    for (int l = 0; l < z.L; ++l) {
+        for (int k = 0; k < gather_tiles_of(t.ld[l].n, 1); ++k) gt_items.push_back(make_int2(l, k));
+        for (int k = 0; k < gather_tiles_of(t.ld[l].n, 4); ++k) gt_items4.push_back(make_int2(l, k));
+    }
+    const std::vector<int2> dtiles = die_order(dt_items);
+    std::vector<int2> gtiles = die_order(gt_items);   // 8 x kGT node tiles, then 32 x kGT
+    {
+        const std::vector<int2> g4 = die_order(gt_items4);
+        gtiles.insert(gtiles.end(), g4.begin(), g4.end());
+    }
     // record bases of every (layer, sensor of its instance) pair
     std::vector<int64_t> recbase;
     for (int l = 0; l < z.L; ++l) {
@@ -746,17 +757,18 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
         d.rb0 = int32_t(recbase.size());
         for (int j = 0; j < d.ng; ++j) recbase.push_back(t.pd[t.wd[d.g0 + j].pair0 + (l - d.l0)].rng_off);
     }
-    // gather windows: per (layer tile, sensor of the layer's instance) the rectangle of sensor
-    // nodes that the tile's records reach, {first row, rows, first column, columns}; a tile
-    // the sensor does not see gets the 1 x 1 window {0, 1, 0, 1} (all its weights are zero)
+    // gather windows of the 32 x kGT tiles: per (layer tile, sensor of the layer's instance)
+    // the rectangle of sensor nodes that the tile's records reach, {first row, rows, first
+    // column, columns}; a tile the sensor does not see gets the 1 x 1 window {0, 1, 0, 1} (all
+    // its weights are zero)
     std::vector<int4> gwin;
     ctx.max_gwin_side = 1;
     {
-        const int tr = kGRowStep * z.gather_rows;
+        const int tr = kGRowStep * 4;
         for (int l = 0; l < z.L; ++l) {
             LayerDev& d = t.ld[l];
             d.wb0 = int32_t(gwin.size());
-            const int n = d.n, tx = (n + kGT - 1) / kGT, nt = gather_tiles_of(n, z.gather_rows);
+            const int n = d.n, tx = (n + kGT - 1) / kGT, nt = gather_tiles_of(n, 4);
             for (int k = 0; k < nt; ++k) {
                 const int a0 = (k / tx) * tr, b0 = (k % tx) * kGT;
                 for (int j = 0; j < d.ng; ++j) {

@@ -309,18 +309,29 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
     const T* pj = jinv + g.off;
     const double ma = ar < m ? 1.0 : 0.0, mb = bc <= m ? 1.0 : 0.0;
     f64x4 c = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
-    // one 16-element chunk per step: its three (four) loads issued together, then converted
-    // and fed to the matrix cores (more chunks in flight cost the occupancy that hides them)
+    // one 16-element chunk per step: its three (four) loads issued together; the next chunk's
+    // loads are in flight while this one is converted and fed to the matrix cores
     const int64_t step = int64_t(g.nb) * NW * 16;
     const int64_t n = g.n;
-    for (int64_t base = (int64_t(g.local) * NW + wv) * 16; base < n; base += step) {   // n % 16 == 0
+    int64_t base = (int64_t(g.local) * NW + wv) * 16;   // n % 16 == 0
+    Raw4<T> ra, rb, rj, rq;
+    if (base < n) {
         const int64_t e0 = base + 4 * kq;
-        Raw4<T> ra, rb, rj, rq;
         ra.load(pa + e0);
         rb.load(pb + e0);
         rj.load(pj + e0);
         if (!ONE_TILE) rq.load(pq + e0);
-        __builtin_amdgcn_sched_barrier(0);
+    }
+    while (base < n) {
+        const int64_t nx = base + step;
+        Raw4<T> na, nb, nj, nq;
+        if (nx < n) {
+            const int64_t e0 = nx + 4 * kq;
+            na.load(pa + e0);
+            nb.load(pb + e0);
+            nj.load(pj + e0);
+            if (!ONE_TILE) nq.load(pq + e0);
+        }
         double av[4], bv[4], jq[4];                // jq: J^-1 Q_a, the row operand of Y
         ra.to(av, ma);
         rb.to(bv, mb);
@@ -339,6 +350,11 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
             c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], c, 0, 0, 0);
             c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(jq[j], bv[j], c2, 0, 0, 0);
         }
+        ra = na;
+        rb = nb;
+        rj = nj;
+        if (!ONE_TILE) rq = nq;
+        base = nx;
     }
     // lane l, register v holds tile entry (row 4 v + l / 16, column l mod 16); the NW tiles are
     // summed by the first 256 threads, one entry each, in a fixed pairwise order

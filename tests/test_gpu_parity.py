@@ -389,3 +389,26 @@ def test_free_running_elt_fp32_within_the_methods_own_sensitivity():
         assert abs(gi["rel_res"] - i_ref["rel_res"]) <= 0.05 * i_ref["rel_res"], (t, gi, i_ref)
     print("\nframe, GPU vs oracle, oracle drift under 2^-24 perturbations:",
           [(t, f"{e:.2e}", f"{s_:.2e}") for t, e, s_ in rows[::5]])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name, precision", [("elt", "fp32"), ("small", "fp64")])
+def test_autotuner_choices_change_no_bit(name, precision):
+    """The autotuner times the four tile-shape candidates and keeps the fastest; frames solved
+    with each candidate (set on a second context) are bit-identical to the default's."""
+    spec, seq, _ = system(name, precision)
+    dt = np.float64 if precision == "fp64" else np.float32
+    a = fw.FewhaContext(spec, device=DEV)
+    ref = [host(a.fewha_solve_aug(dev(seq[t], dt))) for t in range(3)]
+    best, ms = a.fewha_autotune(reps=5)
+    assert len(ms) == 4 and all(v > 0 for v in ms.values())
+    assert ms[f"syn{best['syn_tile']}_rows{best['gather_rows']}"] == min(ms.values())
+    assert a.fewha_get_tuning() == best
+    for syn_tile, rows in [(16, 1), (16, 4), (32, 1), (32, 4)]:
+        b = fw.FewhaContext(spec, device=DEV)
+        b.fewha_set_tuning(syn_tile, rows)
+        assert b.fewha_get_tuning() == {"syn_tile": syn_tile, "gather_rows": rows}
+        for t in range(3):
+            assert np.array_equal(host(b.fewha_solve_aug(dev(seq[t], dt))), ref[t]), (syn_tile, rows, t)
+    with pytest.raises(fw.FewhaError):
+        a.fewha_set_tuning(24, 1)
