@@ -443,6 +443,9 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     __shared__ double gm[kKMax];
     const InstDev I = insts[blockIdx.x];               // one workgroup per instance
     Scalars* __restrict__ sc = scs + blockIdx.x;
+    // the (p, q) of the recycled directions, requested first: their latency overlaps the
+    // partial sums
+    const double gam = threadIdx.x < m ? sc->gam[sl.s[threadIdx.x]] : 0.0;
     const double* __restrict__ gp = gpart + size_t(I.gb0) * ke;
     const int ngb = I.ngb;
     const int ne = 2 * m * (m + 1);
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
         else if (ngb <= 64) reduce_partials<8, 4>(gp, ngb, ne, wv, lane, X);
         else reduce_partials<4, 8>(gp, ngb, ne, wv, lane, X);
     }
-    if (threadIdx.x < m) gm[threadIdx.x] = sc->gam[sl.s[threadIdx.x]];
+    if (threadIdx.x < m) gm[threadIdx.x] = gam;
     __syncthreads();
     if (threadIdx.x >= 64) return;
     const int k = threadIdx.x, W = m + 1;
@@ -599,6 +602,38 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
     const Seg sg = seg_of(vb, N, npq);
     if (skip && skip[sg.inst]) return;   // tolerance mode: the instance has stopped
     Scalars* __restrict__ sc = scs + sg.inst;
+    constexpr int MP1 = MP > 0 ? MP : 1;
+    // UN elements per step with every operand requested first (clamped indices, so that no
+    // load waits behind a condition); the first step's are requested before the sums of the
+    // (p, q) and (r, z) partials below, so that their latencies overlap.  Elements are visited,
+    // and summed, in increasing j as one at a time.
+    constexpr int UN = 2;
+    const int64_t stride = int64_t(sg.nb) * kThreads;
+    const int64_t j0 = int64_t(sg.local) * kThreads + threadIdx.x;
+    T cv[UN], pv[UN], rv[UN], qv[UN], jv[UN], Qv[UN][MP1], Uv[UN][MP1];
+    auto fetch = [&](int64_t jb) {
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int64_t jj = jb + u * stride;
+            const int64_t i = sg.off + (jj < sg.n ? jj : int64_t(sg.n) - 1);
+            cv[u] = c[i];
+            pv[u] = p[i];
+            rv[u] = r[i];
+            qv[u] = q[i];
+            jv[u] = T(0);
+#pragma unroll
+            for (int a = 0; a < MP1; ++a) Qv[u][a] = Uv[u][a] = T(0);
+            if (!last) {
+                jv[u] = jinv[i];
+#pragma unroll
+                for (int a = 0; a < MP; ++a) {
+                    Qv[u][a] = Q[size_t(pl.s[a]) * N + i];
+                    Uv[u][a] = U[size_t(pl.s[a]) * N + i];
+                }
+            }
+        }
+    };
+    fetch(j0);
     const double pq = block_sum_array(pq_part + sg.pq0, sg.npq);
     double rz;
     if (it == 0) {
@@ -623,7 +658,6 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0;
-    constexpr int MP1 = MP > 0 ? MP : 1;
     // one element: the update and its partial-sum terms, from loaded operands
     auto element = [&](int64_t i, T cv, T pv, T rv, T qv, T jv, const T* Qv, const T* Uv) {
         if (broken) {   // keep c and r; the slot and z become zero vectors
@@ -651,48 +685,25 @@ __global__ void __launch_bounds__(kThreads) k_update1(int64_t N, const VecBlk* _
             }
         }
     };
-    // UN elements per step with every load issued first (the elements are visited, and
-    // summed, in the same order as one at a time), then the rest one at a time
-    constexpr int UN = 2;
-    const int64_t stride = int64_t(sg.nb) * kThreads;
-    int64_t j = int64_t(sg.local) * kThreads + threadIdx.x;
-    for (; j + (UN - 1) * stride < sg.n; j += UN * stride) {
-        T cv[UN], pv[UN], rv[UN], qv[UN], jv[UN] = {}, Qv[UN][MP1] = {}, Uv[UN][MP1] = {};
+    for (int64_t jb = j0; jb < sg.n; jb += UN * stride) {
+        T c0[UN], p0[UN], r0[UN], q0[UN], jz[UN], Q0[UN][MP1], U0[UN][MP1];
 #pragma unroll
         for (int u = 0; u < UN; ++u) {
-            const int64_t i = sg.off + j + u * stride;
-            cv[u] = c[i];
-            pv[u] = p[i];
-            rv[u] = r[i];
-            qv[u] = q[i];
-        }
-        if (!last) {
+            c0[u] = cv[u];
+            p0[u] = pv[u];
+            r0[u] = rv[u];
+            q0[u] = qv[u];
+            jz[u] = jv[u];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                const int64_t i = sg.off + j + u * stride;
-                jv[u] = jinv[i];
-#pragma unroll
-                for (int a = 0; a < MP; ++a) {
-                    Qv[u][a] = Q[size_t(pl.s[a]) * N + i];
-                    Uv[u][a] = U[size_t(pl.s[a]) * N + i];
-                }
+            for (int a = 0; a < MP1; ++a) {
+                Q0[u][a] = Qv[u][a];
+                U0[u][a] = Uv[u][a];
             }
         }
+        if (jb + UN * stride < sg.n) fetch(jb + UN * stride);   // the next step's operands in flight
 #pragma unroll
-        for (int u = 0; u < UN; ++u) element(sg.off + j + u * stride, cv[u], pv[u], rv[u], qv[u], jv[u], Qv[u], Uv[u]);
-    }
-    for (; j < sg.n; j += stride) {
-        const int64_t i = sg.off + j;
-        T jv = 0, Qv[MP1] = {}, Uv[MP1] = {};
-        if (!last) {
-            jv = jinv[i];
-#pragma unroll
-            for (int a = 0; a < MP; ++a) {
-                Qv[a] = Q[size_t(pl.s[a]) * N + i];
-                Uv[a] = U[size_t(pl.s[a]) * N + i];
-            }
-        }
-        element(i, c[i], p[i], r[i], q[i], jv, Qv, Uv);
+        for (int u = 0; u < UN; ++u)
+            if (jb + u * stride < sg.n) element(sg.off + jb + u * stride, c0[u], p0[u], r0[u], q0[u], jz[u], Q0[u], U0[u]);
     }
     __shared__ double sh[NV][kThreads / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -724,6 +735,23 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
     constexpr int MP1 = MP > 0 ? MP : 1;
     const Seg sg = seg_of(vb, N, 0);
     if (done && done[sg.inst]) return;   // tolerance mode: the instance has stopped
+    // four elements per step with every operand requested first (clamped indices); the first
+    // step's are requested before the partial sums below, so that their latencies overlap
+    const int64_t stride = int64_t(sg.nb) * kThreads;
+    const int64_t j0 = int64_t(sg.local) * kThreads + threadIdx.x;
+    T zv[4], pv[4], uv[4][MP1];
+    auto fetch = [&](int64_t jb) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t jj = jb + u * stride;
+            const int64_t i = sg.off + (jj < sg.n ? jj : int64_t(sg.n) - 1);
+            zv[u] = z[i];
+            pv[u] = p[i];
+#pragma unroll
+            for (int a = 0; a < MP1; ++a) uv[u][a] = a < MP ? U[size_t(pl.s[a]) * N + i] : T(0);
+        }
+    };
+    fetch(j0);
     Scalars* __restrict__ sc = scs + sg.inst;
     if (tol > 0) {
         // tolerance mode: ||r|| <= tol ||b|| after this iteration's update (FP64, from the
@@ -805,33 +833,25 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
     double yr[MP1];
 #pragma unroll
     for (int a = 0; a < MP; ++a) yr[a] = a < mp ? sy[a] : 0.0;
-    // four elements per step with every load issued first, then the rest one at a time
-    const int64_t stride = int64_t(sg.nb) * kThreads;
-    int64_t j = int64_t(sg.local) * kThreads + threadIdx.x;
-    for (; j + 3 * stride < sg.n; j += 4 * stride) {
-        T zv[4], pv[4], uv[4][MP1] = {};
+    for (int64_t jb = j0; jb < sg.n; jb += 4 * stride) {
+        T z0[4], p0[4], u0[4][MP1];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int64_t i = sg.off + j + u * stride;
-            zv[u] = z[i];
-            pv[u] = p[i];
+            z0[u] = zv[u];
+            p0[u] = pv[u];
 #pragma unroll
-            for (int a = 0; a < MP; ++a) uv[u][a] = U[size_t(pl.s[a]) * N + i];
+            for (int a = 0; a < MP1; ++a) u0[u][a] = uv[u][a];
         }
+        if (jb + 4 * stride < sg.n) fetch(jb + 4 * stride);   // the next step's operands in flight
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            double vv = double(zv[u]) + beta * double(pv[u]);
+            if (jb + u * stride < sg.n) {
+                double vv = double(z0[u]) + beta * double(p0[u]);
 #pragma unroll
-            for (int a = 0; a < MP; ++a) vv -= yr[a] * double(uv[u][a]);   // yr = 0 beyond mp
-            pn[sg.off + j + u * stride] = T(vv);
+                for (int a = 0; a < MP; ++a) vv -= yr[a] * double(u0[u][a]);   // yr = 0 beyond mp
+                pn[sg.off + jb + u * stride] = T(vv);
+            }
         }
-    }
-    for (; j < sg.n; j += stride) {
-        const int64_t i = sg.off + j;
-        double vv = double(z[i]) + beta * double(p[i]);
-#pragma unroll
-        for (int a = 0; a < MP; ++a) vv -= yr[a] * double(U[size_t(pl.s[a]) * N + i]);   // yr = 0 beyond mp
-        pn[i] = T(vv);
     }
 }
 
