@@ -54,8 +54,9 @@
 extern "C" {
 #endif
 
-#define FEWHA_ABI_VERSION 1
+#define FEWHA_ABI_VERSION 2
 #define FEWHA_MAX_LAYERS 32
+#define FEWHA_MAX_LEVELS 10   /* wavelet levels of a layer (n <= 1024) */
 #define FEWHA_MAX_WFS 32
 #define FEWHA_MAX_RECYCLE 32
 #define FEWHA_MAX_INSTANCES 4096
@@ -128,6 +129,13 @@ typedef struct {
     int32_t precision;           /* fewha_precision */
     int32_t block_elems;         /* elements per workgroup of the vector kernels (0 = 384); fixes the
                                     reduction order, so results are reproducible for a given value */
+    int32_t pad2_;
+    const double* level_weight;  /* host, FEWHA_MAX_LEVELS + 1 entries, or NULL: the frequency-weighted
+                                    ("modified") Jacobi preconditioner J = diag(w) diag(M) of Sec. 4, with
+                                    w = level_weight[l - 1] on the detail coefficients of level l (1 =
+                                    finest) and w = level_weight[levels] on the scaling coefficients of a
+                                    layer with `levels` levels; entries used must be finite and > 0.
+                                    Ignored when precond_inv is given. */
 } fewha_config;
 
 /* Written by the device at the end of every fewha_solve_aug. */

@@ -311,6 +311,22 @@ class OracleSystem:
             out.append(diag.ravel() / lay.spacing ** 2)
         return np.concatenate(out) + self.alpha * D
 
+    # --- frequency-weighted ("modified") Jacobi preconditioner (Sec. 4) ---
+    def modified_jacobi(self, level_weight, D=None):
+        """J^-1 of J = diag(w) diag(M): the paper weights the low- and high-frequency parts of
+        the Jacobi diagonal differently and gives no weights; here w is level_weight[l - 1] on
+        the details of level l (1 = finest) and level_weight[levels] on the scaling
+        (approximation) coefficients.  Parity unpinned: only the level bookkeeping and the
+        product are checked."""
+        d = self.diag_M(D)
+        w = []
+        for lay in self.layers:
+            lev = self.coefficient_levels(lay) - 1
+            nc = lay.n >> lay.levels
+            lev[:nc, :nc] = lay.levels
+            w.append(np.asarray(level_weight, dtype=np.float64)[lev].ravel())
+        return 1.0 / (np.concatenate(w) * d)
+
     # --- dense assembly (tiny configurations only) ---
     def dense_M(self):
         D = self.prior()
@@ -565,7 +581,13 @@ class AugmentedReconstructor:
         spec = system.spec
         self.sys = system
         self.D = system.prior()
-        self.Jinv = 1.0 / system.diag_M(self.D) if Jinv is None else np.asarray(Jinv, np.float64)
+        lw = getattr(spec, "level_weight", None)
+        if Jinv is not None:
+            self.Jinv = np.asarray(Jinv, np.float64)
+        elif lw is not None:
+            self.Jinv = system.modified_jacobi(list(lw) + [1.0] * (16 - len(lw)), self.D)
+        else:
+            self.Jinv = 1.0 / system.diag_M(self.D)
         self.max_iter = spec.max_iter if max_iter is None else max_iter
         self.k = spec.recycle_k if k is None else k
         self.mode = spec.recycle_mode if mode is None else mode

@@ -14,7 +14,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfewha.so")
 
-FEWHA_ABI_VERSION = 1
+FEWHA_ABI_VERSION = 2
+FEWHA_MAX_LEVELS = 10
 FEWHA_E_BREAKDOWN = 5
 FLAG_BREAKDOWN, FLAG_TOL_UNMET, FLAG_WS_REJECTED, FLAG_BAD_RHS = 1, 2, 4, 8
 FEWHA_FP64, FEWHA_FP32_OP_FP64_RED = 0, 1
@@ -56,7 +57,7 @@ class fewha_config(C.Structure):
                 ("prior_diag", C.POINTER(C.c_double)), ("precond_inv", C.POINTER(C.c_double)),
                 ("max_iter", C.c_int32), ("recycle_k", C.c_int32), ("recycle_mode", C.c_int32),
                 ("project_all", C.c_int32), ("rel_tol", C.c_double), ("precision", C.c_int32),
-                ("block_elems", C.c_int32)]
+                ("block_elems", C.c_int32), ("pad2_", C.c_int32), ("level_weight", C.POINTER(C.c_double))]
 
 
 class fewha_solve_info(C.Structure):
@@ -189,7 +190,7 @@ def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
     """fewha_config from any object with the attributes of a system description (layers with
     height/weight/spacing/origin_x/origin_y/n/levels; wfs with n_sub/subap/theta_x/theta_y/
     lgs_height/weight; alpha, r0, L0, max_iter, recycle_k, recycle_mode, project_all,
-    precision, optionally block_elems).  `keep` collects the host arrays that must outlive the
+    precision, optionally block_elems and level_weight).  `keep` collects the host arrays that must outlive the
     setup call."""
     keep = [] if keep is None else keep
     L, G = len(spec.layers), len(spec.wfs)
@@ -227,6 +228,11 @@ def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
     cfg.rel_tol = float(getattr(spec, "rel_tol", 0.0) or 0.0)
     cfg.precision = FEWHA_FP64 if spec.precision == "fp64" else FEWHA_FP32_OP_FP64_RED
     cfg.block_elems = int(getattr(spec, "block_elems", 0) or 0)
+    lw = getattr(spec, "level_weight", None)
+    if lw is not None:
+        w = np.ones(FEWHA_MAX_LEVELS + 1)
+        w[:len(lw)] = lw
+        cfg.level_weight = dptr(w)
     return cfg
 
 

@@ -124,6 +124,15 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
                 err = "prior_diag must be finite and > 0 (entry " + std::to_string(i) + ")";
                 return FEWHA_E_INVAL;
             }
+        if (cfg->level_weight && !cfg->precond_inv) {
+            int lmax = 0;
+            for (int l = 0; l < cfg->n_layers; ++l) lmax = std::max(lmax, cfg->layers[l].levels);
+            for (int j = 0; j <= lmax; ++j)
+                if (!(cfg->level_weight[j] > 0) || !std::isfinite(cfg->level_weight[j])) {
+                    err = "level_weight must be finite and > 0 (entry " + std::to_string(j) + ")";
+                    return FEWHA_E_INVAL;
+                }
+        }
         for (int64_t i = 0; cfg->precond_inv && i < n_coef; ++i)
             if (!(cfg->precond_inv[i] > 0) || !std::isfinite(cfg->precond_inv[i])) {
                 err = "precond_inv must be finite and > 0 (entry " + std::to_string(i) + ")";
@@ -588,6 +597,18 @@ fewha_status jacobi_of(Tables& t, const fewha_config* cfg, size_t base, int l0, 
             return FEWHA_E_NOT_SPD;
         }
         t.Jinv[base + i] = 1.0 / d;
+    }
+    if (cfg->level_weight) {   // modified Jacobi: a weight per wavelet level (scaling block: index levels)
+        int64_t off = 0;
+        for (int l = 0; l < cfg->n_layers; ++l) {
+            const int n = cfg->layers[l].n, lv = cfg->layers[l].levels, nc = n >> lv;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) {
+                    const int j = (a < nc && b < nc) ? lv : coef_level(a, b, n, lv) - 1;
+                    t.Jinv[base + off + int64_t(a) * n + b] /= cfg->level_weight[j];
+                }
+            off += int64_t(n) * n;
+        }
     }
     return FEWHA_OK;
 }

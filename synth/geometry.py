@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import dataclasses
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -73,6 +73,9 @@ class SystemSpec:
     precision: str = "fp64"          # "fp64" or "fp32"
     snr: float = 10.0
     dt: float = 2e-3                  # frame period [s]
+    # frequency-weighted Jacobi: weight of the details of level l at [l - 1], of the scaling
+    # coefficients at [levels]; None for the exact Jacobi preconditioner
+    level_weight: Optional[Tuple[float, ...]] = None
 
     def copy(self, **changes) -> "SystemSpec":
         new = dataclasses.replace(self, **changes)

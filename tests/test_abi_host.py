@@ -130,7 +130,7 @@ int main(void) { printf("%zu %zu\\n", sizeof(fewha_unet_config), offsetof(fewha_
     assert [int(v) for v in out] == [ctypes.sizeof(_lib.fewha_unet_config), _lib.fewha_unet_config.lr.offset]
     lib = fw.load_library()
     cfg = _lib.fewha_unet_config()
-    cfg.abi_version, cfg.n_groups = 1, 1
+    cfg.abi_version, cfg.n_groups = _lib.FEWHA_ABI_VERSION, 1
     cfg.images[0], cfg.size[0] = 2, 24           # not a power of two
     cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = 1e-3, 0.9, 0.999, 1e-8
     n = ctypes.c_size_t()

@@ -724,3 +724,30 @@ def test_identical_consecutive_frames_converge_monotonically(tiny, tiny_dense):
         errs.append(errM(c))
     assert all(errs[i + 1] <= errs[i] * (1 + 1e-9) + 1e-14 for i in range(len(errs) - 1))
     assert errs[-1] <= 1e-8 * np.sqrt(cstar @ Md @ cstar)
+
+
+def test_modified_jacobi_level_map_from_basis_support():
+    """The frequency-weighted Jacobi weights land on the coefficients of the right wavelet
+    level, identified independently of the level bookkeeping: the synthesised basis function
+    of a level-l coefficient of periodic db3 spans 5 (2^l - 1) + 1 samples per direction, and
+    the scaling (approximation) functions are the only ones of the coarsest level with a
+    nonzero sum.  With distinct weights 2^j the returned J^-1 times diag(M) is 2^-j."""
+    spec = synth.config_tiny(n=64, levels=3, n_sub=8)
+    spec.layers = spec.layers[:1]
+    sysm = OracleSystem(spec)
+    weights = [2.0 ** j for j in range(11)]
+    ratio = sysm.modified_jacobi(weights) * sysm.diag_M()
+    n, L = 64, 3
+    for i in range(0, n * n, 7):
+        e = np.zeros(sysm.N)
+        e[i] = 1.0
+        f = sysm.W_inv(e)[0]
+        sy, sx = int(np.any(f != 0, axis=1).sum()), int(np.any(f != 0, axis=0).sum())
+        lev = {6: 1, 16: 2, 36: 3}[max(sy, sx)]
+        j = L if (lev == L and abs(f.sum()) > 1e-9) else lev - 1
+        assert abs(ratio[i] - 2.0 ** -j) < 1e-12, (i, lev, ratio[i])
+
+
+def test_modified_jacobi_unit_weights_is_jacobi():
+    sysm = OracleSystem(synth.config_tiny())
+    np.testing.assert_allclose(sysm.modified_jacobi([1.0] * 11), 1.0 / sysm.diag_M(), rtol=1e-15)
