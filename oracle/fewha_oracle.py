@@ -146,6 +146,13 @@ class OracleSystem:
             if w.weight is None:
                 raise ValueError("slope weights (inverse noise variances) are not set")
         self.weights = np.concatenate([np.asarray(w.weight, dtype=np.float64) for w in spec.wfs])
+        # inverse noise covariance C_eta^-1 per sensor (readings of the LGS noise model, which the
+        # paper leaves unstated): a symmetric 2x2 block per subaperture [[wx, wc], [wc, wy]]
+        # (diagonal weights and an optional cross term), and for a tip/tilt-filtered sensor
+        # B - B T (T^T B T)^-1 T^T B with T the sensor's global tip and tilt slope patterns
+        self.cross = [None if getattr(w, "cross_weight", None) is None else np.asarray(w.cross_weight, np.float64)
+                      for w in spec.wfs]
+        self.tt = [bool(getattr(w, "tt_filter", False)) for w in spec.wfs]
         # 1-D bilinear interpolation data of every (guide star, layer) pair, Sec. 2
         self.interp = {}
         for g, w in enumerate(spec.wfs):
@@ -265,21 +272,44 @@ class OracleSystem:
         return np.concatenate(out)
 
     # --- M (Eq. for M) and b (definition of the right-hand side) ---
+    def apply_Cinv(self, s):
+        """C_eta^-1 s.  Inactive subapertures (zero weights) contribute nothing, whatever their
+        slope values."""
+        out = []
+        for g, (w, sg) in enumerate(zip(self.wfs, self.split_slopes(s))):
+            n2 = w.n_sub * w.n_sub
+            wt = np.asarray(w.weight, np.float64)
+            wx, wy = wt[:n2], wt[n2:]
+            wc = self.cross[g] if self.cross[g] is not None else np.zeros(n2)
+            act = (wx != 0) | (wy != 0)
+            sx = np.where(act, sg[:n2], 0.0)
+            sy = np.where(act, sg[n2:], 0.0)
+            bx = wx * sx + wc * sy
+            by = wc * sx + wy * sy
+            if self.tt[g]:
+                G = np.array([[wx.sum(), wc.sum()], [wc.sum(), wy.sum()]])     # T^T B T
+                m = np.linalg.solve(G, np.array([bx.sum(), by.sum()]))        # (T^T B T)^-1 T^T B s
+                bx = bx - (wx * m[0] + wc * m[1])                              # - B T m
+                by = by - (wc * m[0] + wy * m[1])
+            out.append(np.concatenate([bx, by]))
+        return np.concatenate(out)
+
     def apply_M(self, x, D=None):
         D = self.prior() if D is None else D
         s = self.A(self.W_inv(x))
-        return self.W_invT(self.A_T(self.weights * s)) + self.alpha * D * x
+        return self.W_invT(self.A_T(self.apply_Cinv(s))) + self.alpha * D * x
 
     def rhs(self, s):
-        return self.W_invT(self.A_T(self.weights * s))
+        return self.W_invT(self.A_T(self.apply_Cinv(s)))
 
     # --- exact diag(M) (Jacobi preconditioner, Sec. 4) ---
     def diag_M(self, D=None):
-        """diag(M)_i = alpha D_i + || C^-1/2 A W^-1 e_i ||^2.  Each 2-D basis function of the
-        Mallat pyramid is an outer product of two 1-D level-l functions, bilinear
-        interpolation of a separable function is separable, and so are both slope
-        components; the squared norm is then a small matrix product per (layer, level,
-        guide star)."""
+        """diag(M)_i = alpha D_i + || B^1/2 A W^-1 e_i ||^2 with B the block-diagonal part of
+        C_eta^-1 (a tip/tilt filter's rank-2 correction is left out of the preconditioner).
+        Each 2-D basis function of the Mallat pyramid is an outer product of two 1-D level-l
+        functions, bilinear interpolation of a separable function is separable, and so are
+        both slope components and their product; the squared norm is then a small matrix
+        product per (layer, level, guide star)."""
         D = self.prior() if D is None else D
         out = []
         for l, lay in enumerate(self.layers):
@@ -306,6 +336,9 @@ class OracleSystem:
                     wy = w.weight[ns * ns:].reshape(ns, ns)
                     # s^x_ij = (Yh_i + Yh_i+1)/2 (Xh_j+1 - Xh_j); s^y_ij = (Yh_i+1 - Yh_i)(Xh_j + Xh_j+1)/2
                     blk += (Sy ** 2).T @ wx @ (Dx ** 2) + (Dy ** 2).T @ wy @ (Sx ** 2)
+                    if self.cross[g] is not None:   # + 2 wc s^x s^y
+                        wc = self.cross[g].reshape(ns, ns)
+                        blk += 2.0 * (Sy * Dy).T @ wc @ (Dx * Sx)
                 sel = levs[:m2, :m2] == lev
                 diag[:m2, :m2][sel] = blk[sel]
             out.append(diag.ravel() / lay.spacing ** 2)

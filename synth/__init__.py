@@ -12,13 +12,14 @@ of the method.
 """
 from .geometry import (ARCSEC, LayerSpec, WfsSpec, SystemSpec, subaperture_mask,
                        wfs_node_coords, fit_layer_grids, n_coeffs, n_slopes,
-                       config_small, config_elt_mcao, config_elt_full, config_tiny, config_mixed, config_random_instance,
+                       config_small, config_elt_mcao, config_elt_full, config_elt_lgs_noise, config_tiny, config_mixed, config_random_instance,
                        elt_mcao_dms, mcao_fit_directions)
 from .atmosphere import FrozenFlowAtmosphere, SlopeSimulator, make_sequence
 
 __all__ = [
     "ARCSEC", "LayerSpec", "WfsSpec", "SystemSpec", "subaperture_mask", "wfs_node_coords",
     "fit_layer_grids", "n_coeffs", "n_slopes", "config_small", "config_elt_mcao", "config_elt_full",
+    "config_elt_lgs_noise",
     "config_tiny", "config_mixed", "config_random_instance", "elt_mcao_dms", "mcao_fit_directions",
     "FrozenFlowAtmosphere", "SlopeSimulator",
     "make_sequence",

@@ -107,20 +107,56 @@ class SlopeSimulator:
             out.append(np.concatenate([sx.ravel(), sy.ravel()]))
         return out
 
+    @staticmethod
+    def elongation_geometry(w: WfsSpec):
+        """Per subaperture: the radial unit vector (ex, ey) from the pupil centre and the
+        variance factor k = 1 + (elongation r / R)^2 along it."""
+        ns = w.n_sub
+        c = (np.arange(ns) + 0.5 - ns / 2.0) * w.subap
+        X, Y = np.meshgrid(c, c, indexing="xy")
+        r = np.hypot(X, Y)
+        ex = np.where(r > 0, X / np.where(r > 0, r, 1.0), 1.0)
+        ey = np.where(r > 0, Y / np.where(r > 0, r, 1.0), 0.0)
+        k = 1.0 + (w.elongation * r / (ns * w.subap / 2.0)) ** 2
+        return ex.ravel(), ey.ravel(), k.ravel()
+
     def calibrate_noise(self, snr: float) -> None:
-        """Set per-WFS sigma (from noise-free frame-0 slopes) and the slope weights."""
+        """Set per-WFS sigma (from noise-free frame-0 slopes) and the inverse noise covariance:
+        diagonal slope weights, and for an elongated LGS spot the 2x2 block per subaperture
+        B = Sigma^-1, Sigma = sigma^2 (I + (k - 1) e e^T)."""
         for w, s in zip(self.spec.wfs, self.clean_slopes(0)):
             m = np.concatenate([w.mask.ravel(), w.mask.ravel()])
             rms = float(np.sqrt(np.mean(s[m] ** 2)))
             w.sigma = rms / snr
-            w.weight = np.where(m, 1.0 / w.sigma ** 2, 0.0)
+            if w.elongation > 0:
+                ex, ey, k = self.elongation_geometry(w)
+                a = (1.0 - 1.0 / k) / w.sigma ** 2
+                mk = w.mask.ravel()
+                bxx = np.where(mk, 1.0 / w.sigma ** 2 - a * ex * ex, 0.0)
+                byy = np.where(mk, 1.0 / w.sigma ** 2 - a * ey * ey, 0.0)
+                w.weight = np.concatenate([bxx, byy])
+                w.cross_weight = np.where(mk, -a * ex * ey, 0.0)
+            else:
+                w.weight = np.where(m, 1.0 / w.sigma ** 2, 0.0)
+                w.cross_weight = None
 
     def noisy_slopes(self, t: int, seed: int) -> np.ndarray:
         rng = np.random.default_rng([seed, t])
         parts = []
         for w, s in zip(self.spec.wfs, self.clean_slopes(t)):
             m = np.concatenate([w.mask.ravel(), w.mask.ravel()])
-            parts.append(np.where(m, s + w.sigma * rng.standard_normal(s.size), 0.0))
+            z = rng.standard_normal(s.size)
+            if w.elongation > 0:   # eta = sigma (z + (sqrt(k) - 1) (e . z) e)
+                n2 = w.n_sub * w.n_sub
+                ex, ey, k = self.elongation_geometry(w)
+                ez = (np.sqrt(k) - 1.0) * (ex * z[:n2] + ey * z[n2:])
+                z = np.concatenate([z[:n2] + ez * ex, z[n2:] + ez * ey])
+            noisy = s + w.sigma * z
+            if w.tt_jitter > 0:    # a global tip/tilt of this frame (LGS uplink jitter)
+                a = w.sigma * w.tt_jitter * rng.standard_normal(2)
+                n2 = w.n_sub * w.n_sub
+                noisy = noisy + np.concatenate([np.full(n2, a[0]), np.full(n2, a[1])])
+            parts.append(np.where(m, noisy, 0.0))
         return np.concatenate(parts)
 
 

@@ -53,6 +53,14 @@ class WfsSpec:
     mask: np.ndarray = None  # (n_sub, n_sub) bool, active subapertures
     weight: Optional[np.ndarray] = None  # 2 n_sub^2 slope weights (inverse noise variance incl. mask)
     sigma: float = 0.0       # slope noise standard deviation used by the simulator
+    # laser-guide-star noise model (simulator and C_eta^-1): spot elongation, radial from the
+    # launch axis at the pupil centre, raises the noise standard deviation along the radius
+    # to sigma sqrt(1 + (elongation r / R)^2) at distance r (R = pupil radius); the inverse
+    # covariance is then a 2x2 block per subaperture, whose off-diagonal is cross_weight
+    elongation: float = 0.0
+    cross_weight: Optional[np.ndarray] = None   # n_sub^2 (x, y) entries of the blocks, or None
+    tt_filter: bool = False  # C_eta^-1 blind to this sensor's global tip/tilt
+    tt_jitter: float = 0.0   # simulator: per-frame global tip/tilt of the slopes, in units of sigma
 
 
 @dataclass
@@ -204,6 +212,20 @@ def mcao_fit_directions():
     """The 5 x 5 grid of science directions of the MCAO asterism figure (Sec. 6): +-60 arcsec
     in steps of 30 arcsec, as (theta_x, theta_y) [rad], row by row."""
     return [(x * 30 * ARCSEC, y * 30 * ARCSEC) for y in range(-2, 3) for x in range(-2, 3)]
+
+
+def config_elt_lgs_noise(seed: int = 2, precision: str = "fp32", elongation: float = 3.0,
+                         tt_jitter: float = 5.0) -> SystemSpec:
+    """The full ELT system (config_elt_full: 6 LGS + 3 NGS) with the laser-guide-star noise
+    model: radially elongated spots (noise along the radius sqrt(1 + elongation^2) times larger
+    at the pupil edge) and a per-frame tip/tilt jitter of the LGS slopes, which the
+    reconstructor filters out of the LGS data (the NGS measure tip/tilt)."""
+    spec = config_elt_full(seed=seed, precision=precision)
+    for w in spec.wfs:
+        if w.lgs_height > 0:
+            w.elongation, w.tt_filter, w.tt_jitter = elongation, True, tt_jitter
+    spec.name = "elt_lgs_noise_" + precision
+    return spec
 
 
 def config_tiny(seed: int = 3, n: int = 16, levels: int = 3, n_sub: int = 8) -> SystemSpec:
