@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FEWHA_ABI_VERSION 2
+#define FEWHA_ABI_VERSION 3
 #define FEWHA_MAX_LAYERS 32
 #define FEWHA_MAX_LEVELS 10   /* wavelet levels of a layer (n <= 1024) */
 #define FEWHA_MAX_WFS 32
@@ -100,6 +100,16 @@ typedef struct {
     double theta_x, theta_y;     /* guide-star direction [rad] */
     double lgs_height;           /* H [m] of a laser guide star; 0 for a natural guide star */
     const double* slope_weight;  /* host, 2 n_sub^2: diagonal of C_eta^-1 (0 = inactive subaperture) */
+    /* Laser-guide-star noise model (the paper counts its cost but does not state it; this is the
+     * library's reading).  C_eta^-1 of the sensor is B, a symmetric 2x2 block per subaperture
+     * [[w_x, w_c], [w_c, w_y]] (w_x, w_y from slope_weight), each positive semi-definite and
+     * zero on inactive subapertures; with tt_filter it is B - B T (T^T B T)^-1 T^T B, T the
+     * sensor's global tip and tilt slope patterns (all x slopes 1, all y slopes 1 on active
+     * subapertures), so that the reconstruction ignores the sensor's tip/tilt.  The Jacobi
+     * preconditioner uses the diagonal of the operator with B. */
+    const double* cross_weight;  /* host, n_sub^2 (row-major subapertures) w_c entries, or NULL (all 0) */
+    int32_t tt_filter;           /* 1: filter the sensor's tip/tilt (T^T B T must be positive definite) */
+    int32_t pad2_;
 } fewha_wfs;
 
 typedef struct {
@@ -189,8 +199,9 @@ fewha_status fewha_apply_A(fewha_ctx* ctx, const void* d_x, void* d_y, void* str
 
 /* y = M x, as fewha_apply_A, for callers that cannot allocate device memory (code under HIP
  * graph capture, serving loops, harnesses that forbid allocation): the operator's
- * intermediates (nodal image, two wavelet buffers, sensor nodes, layer adjoint field:
- * 4 N + V elements, each block 256-byte aligned) live in a 16 MiB device array of the library,
+ * intermediates (nodal image, two wavelet buffers, sensor nodes, layer adjoint field, weighted
+ * slopes: 4 N + V + S elements, each block 256-byte aligned) live in a 16 MiB device array of
+ * the library,
  * one per GPU, held until the process ends; its address is taken by fewha_setup on each
  * device.  Calls nothing that allocates (also no message strings).  FEWHA_E_NOMEM (nothing
  * launched) when the intermediates exceed 16 MiB; FEWHA_E_STATE when no context was set up on

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfewha.so")
 
-FEWHA_ABI_VERSION = 2
+FEWHA_ABI_VERSION = 3
 FEWHA_MAX_LEVELS = 10
 FEWHA_E_BREAKDOWN = 5
 FLAG_BREAKDOWN, FLAG_TOL_UNMET, FLAG_WS_REJECTED, FLAG_BAD_RHS = 1, 2, 4, 8
@@ -47,7 +47,8 @@ class fewha_layer(C.Structure):
 
 class fewha_wfs(C.Structure):
     _fields_ = [("n_sub", C.c_int32), ("pad_", C.c_int32), ("subap", C.c_double), ("theta_x", C.c_double),
-                ("theta_y", C.c_double), ("lgs_height", C.c_double), ("slope_weight", C.POINTER(C.c_double))]
+                ("theta_y", C.c_double), ("lgs_height", C.c_double), ("slope_weight", C.POINTER(C.c_double)),
+                ("cross_weight", C.POINTER(C.c_double)), ("tt_filter", C.c_int32), ("pad2_", C.c_int32)]
 
 
 class fewha_config(C.Structure):
@@ -189,7 +190,7 @@ def _stream(stream) -> Optional[int]:
 def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
     """fewha_config from any object with the attributes of a system description (layers with
     height/weight/spacing/origin_x/origin_y/n/levels; wfs with n_sub/subap/theta_x/theta_y/
-    lgs_height/weight; alpha, r0, L0, max_iter, recycle_k, recycle_mode, project_all,
+    lgs_height/weight, optionally cross_weight/tt_filter; alpha, r0, L0, max_iter, recycle_k, recycle_mode, project_all,
     precision, optionally block_elems and level_weight).  `keep` collects the host arrays that must outlive the
     setup call."""
     keep = [] if keep is None else keep
@@ -203,8 +204,14 @@ def make_config(spec, prior_diag=None, precond_inv=None, keep=None):
             raise FewhaError(f"sensor {i}: slope weights are not set")
         wt = np.ascontiguousarray(w.weight, dtype=np.float64)
         keep.append(wt)
+        cw = getattr(w, "cross_weight", None)
+        cwp = None
+        if cw is not None:
+            cw = np.ascontiguousarray(cw, dtype=np.float64)
+            keep.append(cw)
+            cwp = cw.ctypes.data_as(C.POINTER(C.c_double))
         wfs[i] = fewha_wfs(w.n_sub, 0, w.subap, w.theta_x, w.theta_y, w.lgs_height,
-                           wt.ctypes.data_as(C.POINTER(C.c_double)))
+                           wt.ctypes.data_as(C.POINTER(C.c_double)), cwp, int(bool(getattr(w, "tt_filter", False))), 0)
     keep += [layers, wfs]
 
     def dptr(a):

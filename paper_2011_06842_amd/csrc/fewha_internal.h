@@ -76,6 +76,9 @@ struct WfsDev {
     int32_t pair0;        // pair (this sensor, layer l0 + j) is pair0 + j
     int32_t pad_;
     int64_t fwd0;         // bilinear cells of pair (this sensor, layer l0 + j) at fwd0 + j * 2 (ns + 1)
+    int32_t tt;           // tip/tilt filter of C_eta^-1
+    int32_t pad2_;
+    double tg[3];         // (T^T B T)^-1: [0] [1]; [1] [2]
 };
 
 // Transpose of the bilinear propagation along one axis, for one layer row (column) a of one
@@ -140,7 +143,7 @@ struct Scalars {
 
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
-    size_t layers, wfs, pairs, cellidx, frac, ranges, weight, prior_a, jinv;
+    size_t layers, wfs, pairs, cellidx, frac, ranges, weight, xweight, ttv, wslopes, prior_a, jinv;
     size_t insts, vecblk, gramblk, syn_items, ana_items, data_tiles, gather_tiles, grecs, recbase, gwin;
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
     size_t c, r, z, b, b_prev;
@@ -154,7 +157,7 @@ struct Layout {
 // Kernels, for the optional event profiler and the per-kernel timer.
 enum KernelId : int {
     KID_IDWT = 0, KID_DATA_TERM, KID_ADJ_GATHER, KID_DWT_TILES, KID_DWT_COARSE, KID_SLOPES_ADJ, KID_RESIDUAL, KID_GRAM, KID_GRAM_SOLVE, KID_GALERKIN, KID_INIT_DIR, KID_UPDATE1,
-    KID_UPDATE2, KID_FINISH, KID_FWD_SLOPES, KID_COUNT
+    KID_UPDATE2, KID_FINISH, KID_FWD_SLOPES, KID_TT_CORRECT, KID_COUNT
 };
 extern const char* const kKernelNames[KID_COUNT];
 constexpr int KID_APPLY = -1;   // the per-kernel timer's id of a whole application of M
@@ -199,6 +202,7 @@ struct Ctx {
     int max_gwin_side = 0;     // largest side of the sensor-node rectangle of a gather tile
     std::vector<StepInfo> steps;  // tiled analysis launches (finest levels first)
     int syn_small = 0, syn_large = 0;   // synthesis tiles of kSynTile / 2 and of kSynTile
+    bool any_cross = false, any_tt = false;   // LGS noise model: 2x2 noise blocks / tip/tilt filters
     int npq = 0;               // (p, q) partial entries written by one analysis
     int64_t n_cells = 0, n_ranges = 0;
     std::vector<fewha_layer> layers;
@@ -229,11 +233,11 @@ struct Ctx {
 // buffers (N elements each), the sensor-node field (V) and the layer adjoint field (N).  The
 // context's own live in its workspace; fewha_apply_A_noalloc brings its own.
 struct OpBufs {
-    char *nodal, *tmp0, *tmp1, *psi_nodes, *psi_layers;
+    char *nodal, *tmp0, *tmp1, *psi_nodes, *psi_layers, *wslopes;
 };
 inline OpBufs ctx_bufs(const Ctx& c) {
     return OpBufs{c.ws + c.lay.nodal, c.ws + c.lay.tmp0, c.ws + c.lay.tmp1, c.ws + c.lay.psi_nodes,
-                  c.ws + c.lay.psi_layers};
+                  c.ws + c.lay.psi_layers, c.ws + c.lay.wslopes};
 }
 
 // Records HIP events around one kernel launch on `s` when profiling is enabled.
@@ -258,7 +262,7 @@ template <typename T> void launch_winv(const Ctx& c, const T* x, T* phi, hipStre
 template <typename T> void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_part,
                                         hipStream_t s, const OpBufs* ob = nullptr, const int32_t* skip = nullptr);
 template <typename T> void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s,
-                                            const int32_t* skip = nullptr);
+                                            const int32_t* skip = nullptr, T* wsl = nullptr);
 template <typename T> void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted, hipStream_t s);
 template <typename T> void launch_adj_gather(const Ctx& c, const T* psi_nodes, T* psi_layers, hipStream_t s,
                                              const int32_t* skip = nullptr);

@@ -73,13 +73,15 @@ fewha_status fewha_apply_A_noalloc(fewha_ctx* ctx, const void* d_x, void* d_y, v
     if (!base)
         return fail_static(ctx, FEWHA_E_STATE,
                            "the static scratch array of the current device has no address: set up a context on it");
-    // nodal image, two wavelet ping-pong buffers and the layer adjoint (N each), sensor nodes (V)
+    // nodal image, two wavelet ping-pong buffers and the layer adjoint (N each), sensor nodes
+    // (V), weighted slopes of tip/tilt-filtered sensors (S)
     const size_t vN = align256(c.esz * size_t(c.N)), vV = align256(c.esz * size_t(c.V));
-    if (4 * vN + vV > kScratchBytes)
+    const size_t vS = align256(c.esz * size_t(c.S));
+    if (4 * vN + vV + vS > kScratchBytes)
         return fail_static(ctx, FEWHA_E_NOMEM,
                            "the operator's intermediates exceed the 16 MiB static scratch array of "
                            "fewha_apply_A_noalloc (use fewha_apply_A)");
-    const OpBufs ob{base, base + vN, base + 2 * vN, base + 3 * vN, base + 3 * vN + vV};
+    const OpBufs ob{base, base + vN, base + 2 * vN, base + 3 * vN, base + 3 * vN + vV, base + 4 * vN + vV};
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (c.prec == FEWHA_FP64)
         launch_apply_M<double>(c, static_cast<const double*>(d_x), static_cast<double*>(d_y), nullptr, s, &ob);

@@ -576,7 +576,8 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
                                                             const int32_t* __restrict__ cidx,
                                                             const T* __restrict__ frac, const T* __restrict__ phi,
                                                             const T* __restrict__ w, T* __restrict__ psi,
-                                                            const int32_t* __restrict__ skip) {
+                                                            const int32_t* __restrict__ skip, const T* __restrict__ xw,
+                                                            T* __restrict__ wsl) {
     constexpr int E = kTile + 2, S1 = kTile + 1;
     static_assert(E * E == kDataThreads, "one halo-tile node per thread");
     static_assert(S1 * S1 <= kDataThreads, "one subaperture per thread");
@@ -602,10 +603,11 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
     const int ls = threadIdx.x / S1, lt = threadIdx.x - ls * S1;
     const int si = i0 - 1 + ls, sj = j0 - 1 + lt;
     const bool sub = threadIdx.x < S1 * S1 && si >= 0 && si < ns && sj >= 0 && sj < ns;
-    T wx = 0, wy = 0;
+    T wx = 0, wy = 0, wc = 0;
     if (sub) {
         wx = w[W.soff + si * ns + sj];
         wy = w[W.soff + ns * ns + si * ns + sj];
+        if (xw) wc = xw[W.soff / 2 + si * ns + sj];   // off-diagonal of the subaperture's 2x2 block
     }
     // the bilinear cells of the tile's rows and columns on each layer: every load is issued
     // before the first LDS store
@@ -694,8 +696,19 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
             const T p10 = sphi[(ls + 1) * E + lt], p11 = sphi[(ls + 1) * E + lt + 1];
             const T sx = T(0.5) * ((p01 - p00) + (p11 - p10));
             const T sy = T(0.5) * ((p10 - p00) + (p11 - p01));
-            tx = wx * sx;
-            ty = wy * sy;
+            if (xw) {   // C_eta^-1 block [[wx, wc], [wc, wy]]
+                tx = wx * sx + wc * sy;
+                ty = wc * sx + wy * sy;
+            } else {
+                tx = wx * sx;
+                ty = wy * sy;
+            }
+            // a tip/tilt-filtered sensor keeps its weighted slopes for the rank-2 correction
+            // (each subaperture written by the tile that owns its first node)
+            if (wsl && W.tt && si >= i0 && si < i0 + kTile && sj >= j0 && sj < j0 + kTile) {
+                wsl[W.soff + si * ns + sj] = tx;
+                wsl[W.soff + ns * ns + si * ns + sj] = ty;
+            }
         }
         stx[threadIdx.x] = tx;
         sty[threadIdx.x] = ty;
@@ -713,10 +726,14 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
 }
 
 // Gamma^T (w s) per node (weighted = 1) or Gamma^T (mask s) (weighted = 0, mask = w != 0).
+// With the 2x2 noise blocks (xw) the weighted slope pair of a subaperture is
+// [[wx, wc], [wc, wy]] (sx, sy), zero on an inactive subaperture (wx = wy = 0).  The weighted
+// slopes of a tip/tilt-filtered sensor also go to wsl (node (i, j) writes subaperture (i, j)).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restrict__ wfs, int G, int64_t V,
                                                           const T* __restrict__ w, const T* __restrict__ s,
-                                                          T* __restrict__ psi, int weighted) {
+                                                          T* __restrict__ psi, int weighted, const T* __restrict__ xw,
+                                                          T* __restrict__ wsl) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= V) return;
     const WfsDev W = wfs[find_sensor(wfs, G, e, [](const WfsDev& w) { return w.noff; })];
@@ -732,8 +749,58 @@ __global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restric
         const T ww = w[o], sv = s[o];
         return ok && ww != T(0) ? (weighted ? ww * sv : sv) : T(0);
     };
-    psi[e] = T(0.5) * ((t(0, i, j - 1) - t(0, i, j)) + (t(0, i - 1, j - 1) - t(0, i - 1, j))) +
-             T(0.5) * ((t(1, i - 1, j) - t(1, i, j)) + (t(1, i - 1, j - 1) - t(1, i, j - 1)));
+    auto tb = [&](int comp, int si, int sj) -> T {   // the block form
+        const bool ok = si >= 0 && si < ns && sj >= 0 && sj < ns;
+        const int64_t q = ok ? si * ns + sj : 0;
+        const int64_t ox = W.soff + q, oy = W.soff + int64_t(ns) * ns + q;
+        const T wx = w[ox], wy = w[oy], wc = xw[W.soff / 2 + q], sx = s[ox], sy = s[oy];
+        const bool act = ok && (wx != T(0) || wy != T(0));
+        const T v = comp == 0 ? wx * sx + wc * sy : wc * sx + wy * sy;
+        return act ? v : T(0);
+    };
+    if (weighted && xw)
+        psi[e] = T(0.5) * ((tb(0, i, j - 1) - tb(0, i, j)) + (tb(0, i - 1, j - 1) - tb(0, i - 1, j))) +
+                 T(0.5) * ((tb(1, i - 1, j) - tb(1, i, j)) + (tb(1, i - 1, j - 1) - tb(1, i, j - 1)));
+    else
+        psi[e] = T(0.5) * ((t(0, i, j - 1) - t(0, i, j)) + (t(0, i - 1, j - 1) - t(0, i - 1, j))) +
+                 T(0.5) * ((t(1, i - 1, j) - t(1, i, j)) + (t(1, i - 1, j - 1) - t(1, i, j - 1)));
+    if (weighted && wsl && W.tt && i < ns && j < ns) {
+        wsl[W.soff + i * ns + j] = xw ? tb(0, i, j) : t(0, i, j);
+        wsl[W.soff + int64_t(ns) * ns + i * ns + j] = xw ? tb(1, i, j) : t(1, i, j);
+    }
+}
+
+// Tip/tilt filter of a sensor's C_eta^-1 (B - B T (T^T B T)^-1 T^T B): the sensor-node vector
+// Gamma^T B y already holds the B part; this subtracts m_x v_x + m_y v_y, v_k = Gamma^T B T e_k
+// (precomputed) and m = (T^T B T)^-1 T^T B y, whose two sums over the weighted slopes B y (wsl)
+// are taken in FP64 in a fixed order.  One workgroup per sensor.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_tt_correct(const WfsDev* __restrict__ wfs, const T* __restrict__ wsl,
+                                                          const T* __restrict__ ttv, int64_t V, T* __restrict__ psi,
+                                                          const int32_t* __restrict__ skip) {
+    const WfsDev W = wfs[blockIdx.x];
+    if (!W.tt) return;
+    if (skip && skip[W.inst]) return;   // tolerance mode: the instance has converged
+    const int n2 = W.ns * W.ns, nv = (W.ns + 1) * (W.ns + 1);
+    double v[2] = {0.0, 0.0};
+    for (int k = threadIdx.x; k < n2; k += kThreads) {
+        v[0] += double(wsl[W.soff + k]);
+        v[1] += double(wsl[W.soff + n2 + k]);
+    }
+    __shared__ double sh[2][kThreads / 64];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double w = wave_sum(v[c]);
+        if ((threadIdx.x & 63) == 0) sh[c][threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    const double tx = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    const double ty = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    const double mx = W.tg[0] * tx + W.tg[1] * ty, my = W.tg[1] * tx + W.tg[2] * ty;
+    for (int k = threadIdx.x; k < nv; k += kThreads) {
+        const int64_t o = W.noff + k;
+        psi[o] = T(double(psi[o]) - mx * double(ttv[o]) - my * double(ttv[V + o]));
+    }
 }
 
 // Gamma P phi per subaperture (operator piece A), zero on inactive subapertures.
@@ -1047,7 +1114,7 @@ inline unsigned cdiv(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
 
 const char* const kKernelNames[KID_COUNT] = {
     "idwt", "data_term", "adj_gather", "dwt_tiles", "dwt_coarse", "slopes_adj", "residual", "gram", "gram_solve",
-    "galerkin_apply", "init_dir", "update1", "update2", "finish", "fwd_slopes"};
+    "galerkin_apply", "init_dir", "update1", "update2", "finish", "fwd_slopes", "tt_correct"};
 
 ProfScope::ProfScope(const Ctx& ctx, int kid, hipStream_t stream) : c(ctx), s(stream) {
     Profiler& p = c.prof;
@@ -1134,20 +1201,36 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
     else go(k_dwt_coarse<T, 0>);
 }
 
+// The rank-2 tip/tilt correction of the filtered sensors (after the data term or the slope
+// adjoint wrote the weighted slopes to wsl).
 template <typename T>
-void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s, const int32_t* skip) {
-    ProfScope ps_(c, KID_DATA_TERM, s);
-    k_data_term<T><<<c.data_grid, kDataThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles),
-                                                        c.at<LayerDev>(c.lay.layers), c.at<int32_t>(c.lay.cellidx),
-                                                        c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), psi_nodes,
-                                                        skip);
+void launch_tt_correct(const Ctx& c, T* psi_nodes, const T* wsl, hipStream_t s, const int32_t* skip) {
+    if (!c.any_tt) return;
+    ProfScope ps_(c, KID_TT_CORRECT, s);
+    k_tt_correct<T><<<c.G, kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), wsl, c.at<T>(c.lay.ttv), c.V, psi_nodes, skip);
 }
 
 template <typename T>
+void launch_data_term(const Ctx& c, const T* phi, T* psi_nodes, hipStream_t s, const int32_t* skip, T* wsl) {
+    if (!wsl) wsl = c.at<T>(c.lay.wslopes);
+    {
+        ProfScope ps_(c, KID_DATA_TERM, s);
+        k_data_term<T><<<c.data_grid, kDataThreads, 0, s>>>(
+            c.at<WfsDev>(c.lay.wfs), c.at<int2>(c.lay.data_tiles), c.at<LayerDev>(c.lay.layers),
+            c.at<int32_t>(c.lay.cellidx), c.at<T>(c.lay.frac), phi, c.at<T>(c.lay.weight), psi_nodes, skip,
+            c.any_cross ? c.at<T>(c.lay.xweight) : nullptr, c.any_tt ? wsl : nullptr);
+    }
+    launch_tt_correct<T>(c, psi_nodes, wsl, s, skip);
+}
+
+// weighted = 1: Gamma^T C_eta^-1 s without the tip/tilt correction (launch_tt_correct follows
+// where the frame needs it); weighted = 0: Gamma^T (mask s).
+template <typename T>
 void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted, hipStream_t s) {
     ProfScope ps_(c, KID_SLOPES_ADJ, s);
-    k_slopes_adj<T><<<cdiv(c.V, kThreads), kThreads, 0, s>>>(c.at<WfsDev>(c.lay.wfs), c.G, c.V, c.at<T>(c.lay.weight),
-                                                             slopes, psi_nodes, weighted);
+    k_slopes_adj<T><<<cdiv(c.V, kThreads), kThreads, 0, s>>>(
+        c.at<WfsDev>(c.lay.wfs), c.G, c.V, c.at<T>(c.lay.weight), slopes, psi_nodes, weighted,
+        weighted && c.any_cross ? c.at<T>(c.lay.xweight) : nullptr, weighted && c.any_tt ? c.at<T>(c.lay.wslopes) : nullptr);
 }
 
 template <typename T>
@@ -1206,7 +1289,7 @@ void launch_apply_M(const Ctx& c, const T* x, T* y, double* pq_part, hipStream_t
     T* psi_n = reinterpret_cast<T*>(bb.psi_nodes);
     T* psi_l = reinterpret_cast<T*>(bb.psi_layers);
     launch_winv<T>(c, x, phi, s, &bb, skip);
-    launch_data_term<T>(c, phi, psi_n, s, skip);
+    launch_data_term<T>(c, phi, psi_n, s, skip, reinterpret_cast<T*>(bb.wslopes));
     launch_adj_gather<T>(c, psi_n, psi_l, s, skip);
     launch_winvt<T>(c, psi_l, y, x, pq_part, s, &bb, skip);
 }
@@ -1219,6 +1302,7 @@ void launch_rhs(const Ctx& c, const T* slopes, T* b, hipStream_t s, double* bb_p
     T* psi_n = c.at<T>(c.lay.psi_nodes);
     T* psi_l = c.at<T>(c.lay.psi_layers);
     if (slopes) launch_slopes_adj<T>(c, slopes, psi_n, 1, s);
+    launch_tt_correct<T>(c, psi_n, c.at<T>(c.lay.wslopes), s, nullptr);
     launch_adj_gather<T>(c, psi_n, psi_l, s);
     launch_winvt<T>(c, psi_l, b, static_cast<const T*>(nullptr), bb_part, s);
 }
@@ -1241,7 +1325,7 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
             launch_winv<T>(c, x, c.at<T>(c.lay.nodal), s, nullptr, nullptr);
             break;
         case KID_DATA_TERM:
-            launch_data_term<T>(c, c.at<T>(c.lay.nodal), c.at<T>(c.lay.psi_nodes), s);
+            launch_data_term<T>(c, c.at<T>(c.lay.nodal), c.at<T>(c.lay.psi_nodes), s, nullptr, nullptr);
             break;
         case KID_ADJ_GATHER:
             launch_adj_gather<T>(c, c.at<T>(c.lay.psi_nodes), c.at<T>(c.lay.psi_layers), s);
@@ -1309,7 +1393,7 @@ hipError_t time_operator_kernel(Ctx& c, int kid, int step, int reps, hipStream_t
     template void launch_winv<T>(const Ctx&, const T*, T*, hipStream_t, const OpBufs*, const int32_t*);   \
     template void launch_winvt<T>(const Ctx&, const T*, T*, const T*, double*, hipStream_t, const OpBufs*, \
                                   const int32_t*);                                                        \
-    template void launch_data_term<T>(const Ctx&, const T*, T*, hipStream_t, const int32_t*);             \
+    template void launch_data_term<T>(const Ctx&, const T*, T*, hipStream_t, const int32_t*, T*);         \
     template void launch_slopes_adj<T>(const Ctx&, const T*, T*, int, hipStream_t);                       \
     template void launch_adj_gather<T>(const Ctx&, const T*, T*, hipStream_t, const int32_t*);            \
     template void launch_fwd_slopes<T>(const Ctx&, const T*, T*, hipStream_t);                            \

@@ -103,6 +103,27 @@ fewha_status validate_config(const fewha_config* cfg, std::string& err) {
         if (!W.slope_weight) { err = "slope_weight is NULL"; return FEWHA_E_INVAL; }
         for (int i = 0; i < 2 * W.n_sub * W.n_sub; ++i)
             if (!(W.slope_weight[i] >= 0) || !std::isfinite(W.slope_weight[i])) { err = "slope weights must be finite and >= 0"; return FEWHA_E_INVAL; }
+        {
+            const int n2 = W.n_sub * W.n_sub;
+            double gx = 0, gy = 0, gc = 0;
+            for (int i = 0; i < n2; ++i) {
+                const double wx = W.slope_weight[i], wy = W.slope_weight[n2 + i], wc = W.cross_weight ? W.cross_weight[i] : 0.0;
+                if (!std::isfinite(wc)) { err = "cross weights must be finite"; return FEWHA_E_INVAL; }
+                if (wx == 0 && wy == 0 && wc != 0) { err = "cross weight on an inactive subaperture"; return FEWHA_E_INVAL; }
+                if (wx * wy - wc * wc < -1e-12 * wx * wy) {
+                    err = "the 2x2 noise block of subaperture " + std::to_string(i) + " is not positive semi-definite";
+                    return FEWHA_E_INVAL;
+                }
+                gx += wx;
+                gy += wy;
+                gc += wc;
+            }
+            if (W.tt_filter != 0 && W.tt_filter != 1) { err = "tt_filter must be 0 or 1"; return FEWHA_E_INVAL; }
+            if (W.tt_filter && !(gx > 0 && gy > 0 && gx * gy - gc * gc > 1e-12 * gx * gy)) {
+                err = "tip/tilt filter: T^T B T is singular";
+                return FEWHA_E_INVAL;
+            }
+        }
         for (int l = 0; l < cfg->n_layers; ++l)
             if (W.lgs_height > 0 && cfg->layers[l].height >= W.lgs_height) { err = "a layer lies at or above a laser guide star"; return FEWHA_E_INVAL; }
     }
@@ -342,6 +363,8 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.recbase = take(sizeof(int64_t) * std::max<int64_t>(1, z.pairs));
     lo.gwin = take(sizeof(int4) * std::max<int64_t>(1, z.gwin));
     lo.weight = take(e * S);
+    lo.xweight = take(e * (S / 2));
+    lo.ttv = take(e * 2 * V);
     lo.prior_a = take(e * N);
     lo.jinv = take(e * N);
     lo.nodal = take(e * N);
@@ -349,6 +372,7 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.tmp1 = take(e * N);
     lo.psi_nodes = take(e * V);
     lo.psi_layers = take(e * N);
+    lo.wslopes = take(e * S);
     lo.vx = take(e * N);
     lo.vy = take(e * N);
     lo.c = take(e * N);
@@ -381,6 +405,9 @@ struct Tables {
     std::vector<PairDev> pd;
     std::vector<int32_t> cidx, rng;
     std::vector<double> cfrac, D, Jinv, wts;
+    std::vector<double> xw;         // cross weights, n_sub^2 per sensor (slope offset / 2)
+    std::vector<double> ttv;        // tip/tilt filter node vectors Gamma^T B T e_x, then e_y (V each)
+    std::vector<double> ttvy;
 };
 
 // Prior D (Sec. 3): inverse von Karman spectrum at the band frequency of every coefficient.
@@ -451,16 +478,29 @@ void data_diag_of(const fewha_config* cfg, const LayerDev* ld, PairOf pair, cons
                     }
                 const double* wx = W.slope_weight;
                 const double* wy = W.slope_weight + size_t(ns) * ns;
-                std::vector<double> T1(size_t(ns) * m2), T2(size_t(ns) * m2);
+                const double* wc = W.cross_weight;
+                // cross term 2 w_c s^x s^y: avg_y diff_y (i) times diff_x avg_x (j)
+                std::vector<double> SDy(wc ? size_t(ns) * m2 : 0), DSx(wc ? size_t(ns) * m2 : 0);
+                if (wc)
+                    for (int i = 0; i < ns; ++i)
+                        for (int q = 0; q < m2; ++q) {
+                            const double y0 = Yh[size_t(i) * m2 + q], y1 = Yh[size_t(i + 1) * m2 + q];
+                            const double x0 = Xh[size_t(i) * m2 + q], x1 = Xh[size_t(i + 1) * m2 + q];
+                            SDy[size_t(i) * m2 + q] = 0.5 * (y0 + y1) * (y1 - y0);
+                            DSx[size_t(i) * m2 + q] = (x1 - x0) * 0.5 * (x0 + x1);
+                        }
+                std::vector<double> T1(size_t(ns) * m2), T2(size_t(ns) * m2), T3(wc ? size_t(ns) * m2 : 0);
                 for (int i = 0; i < ns; ++i)
                     for (int q = 0; q < m2; ++q) {
-                        double s1 = 0, s2 = 0;
+                        double s1 = 0, s2 = 0, s3 = 0;
                         for (int j = 0; j < ns; ++j) {
                             s1 += wx[size_t(i) * ns + j] * Dx2[size_t(j) * m2 + q];
                             s2 += wy[size_t(i) * ns + j] * Sx2[size_t(j) * m2 + q];
+                            if (wc) s3 += wc[size_t(i) * ns + j] * DSx[size_t(j) * m2 + q];
                         }
                         T1[size_t(i) * m2 + q] = s1;
                         T2[size_t(i) * m2 + q] = s2;
+                        if (wc) T3[size_t(i) * m2 + q] = s3;
                     }
                 for (int a = 0; a < m2; ++a)
                     for (int b = 0; b < m2; ++b) {
@@ -468,6 +508,8 @@ void data_diag_of(const fewha_config* cfg, const LayerDev* ld, PairOf pair, cons
                         double s = 0;
                         for (int i = 0; i < ns; ++i)
                             s += Sy2[size_t(i) * m2 + a] * T1[size_t(i) * m2 + b] + Dy2[size_t(i) * m2 + a] * T2[size_t(i) * m2 + b];
+                        if (wc)
+                            for (int i = 0; i < ns; ++i) s += 2.0 * SDy[size_t(i) * m2 + a] * T3[size_t(i) * m2 + b];
                         blk[size_t(a) * m2 + b] += s;
                     }
             }
@@ -523,6 +565,40 @@ fewha_status add_instance(Tables& t, const fewha_config* cfg, int inst, int cb, 
         toff += w.tiles_x * w.tiles_x;
         soff += 2 * int64_t(ns) * ns;
         noff += int64_t(ns + 1) * (ns + 1);
+        // noise blocks: cross weights, and for a tip/tilt-filtered sensor (T^T B T)^-1 and the
+        // node vectors v_k = Gamma^T B T e_k (the slope adjoint of the device, on the host)
+        {
+            const int n2 = ns * ns, np = ns + 1;
+            const double* wx = W.slope_weight;
+            const double* wy = W.slope_weight + n2;
+            std::vector<double> wc(n2, 0.0);
+            if (W.cross_weight) std::copy(W.cross_weight, W.cross_weight + n2, wc.begin());
+            t.xw.insert(t.xw.end(), wc.begin(), wc.end());
+            w.tt = W.tt_filter;
+            double gx = 0, gy = 0, gc = 0;
+            for (int i = 0; i < n2; ++i) {
+                gx += wx[i];
+                gy += wy[i];
+                gc += wc[i];
+            }
+            const double det = gx * gy - gc * gc;
+            w.tg[0] = w.tt ? gy / det : 0.0;
+            w.tg[1] = w.tt ? -gc / det : 0.0;
+            w.tg[2] = w.tt ? gx / det : 0.0;
+            for (int k = 0; k < 2; ++k) {
+                // slope field B T e_k: (w_x, w_c) for tip, (w_c, w_y) for tilt
+                auto tf = [&](int comp, int si, int sj) -> double {
+                    if (!w.tt || si < 0 || si >= ns || sj < 0 || sj >= ns) return 0.0;
+                    const int o = si * ns + sj;
+                    return comp == 0 ? (k == 0 ? wx[o] : wc[o]) : (k == 0 ? wc[o] : wy[o]);
+                };
+                std::vector<double>& dst = k == 0 ? t.ttv : t.ttvy;
+                for (int i = 0; i < np; ++i)
+                    for (int j = 0; j < np; ++j)
+                        dst.push_back(0.5 * ((tf(0, i, j - 1) - tf(0, i, j)) + (tf(0, i - 1, j - 1) - tf(0, i - 1, j))) +
+                                      0.5 * ((tf(1, i - 1, j) - tf(1, i, j)) + (tf(1, i - 1, j - 1) - tf(1, i, j - 1))));
+            }
+        }
         t.wd.push_back(w);
         t.wts.insert(t.wts.end(), W.slope_weight, W.slope_weight + 2 * ns * ns);
         for (int l = 0; l < L; ++l) {
@@ -873,6 +949,14 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     };
     const auto frac_t = typed(t.cfrac);
     const auto w_t = typed(t.wts);
+    const auto xw_t = typed(t.xw);
+    std::vector<double> ttv_all(t.ttv);
+    ttv_all.insert(ttv_all.end(), t.ttvy.begin(), t.ttvy.end());
+    const auto ttv_t = typed(ttv_all);
+    ctx.any_cross = false;
+    ctx.any_tt = false;
+    for (double v : t.xw) ctx.any_cross = ctx.any_cross || v != 0.0;
+    for (const WfsDev& w : t.wd) ctx.any_tt = ctx.any_tt || w.tt;
     const auto pa_t = typed(t.D);
     const auto j_t = typed(t.Jinv);
     bool ok = up(lo.layers, t.ld.data(), sizeof(LayerDev) * t.ld.size()) &&
@@ -892,7 +976,8 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
               up(lo.recbase, recbase.data(), sizeof(int64_t) * recbase.size()) &&
               up(lo.gwin, gwin.data(), sizeof(int4) * gwin.size()) &&
               up(lo.lconst, lconst.data(), sizeof(float) * lconst.size()) &&
-              up(lo.weight, w_t.data(), w_t.size()) && up(lo.prior_a, pa_t.data(), pa_t.size()) &&
+              up(lo.weight, w_t.data(), w_t.size()) && up(lo.xweight, xw_t.data(), xw_t.size()) &&
+              up(lo.ttv, ttv_t.data(), ttv_t.size()) && up(lo.prior_a, pa_t.data(), pa_t.size()) &&
               up(lo.jinv, j_t.data(), j_t.size());
     if (ok) ok = hipStreamSynchronize(stream) == hipSuccess;   // host vectors die at return
     if (!ok) { ctx.err = "hipMemcpyAsync of the setup tables failed"; return FEWHA_E_HIP; }

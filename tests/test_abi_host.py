@@ -45,6 +45,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(fewha_layer), sizeof(fewha_wfs), sizeof(fewha_config), sizeof(fewha_solve_info));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(fewha_wfs, slope_weight), offsetof(fewha_config, alpha),
          offsetof(fewha_config, max_iter), offsetof(fewha_config, rel_tol), offsetof(fewha_config, precision));
+  printf("%zu %zu %zu\\n", offsetof(fewha_wfs, cross_weight), offsetof(fewha_wfs, tt_filter),
+         offsetof(fewha_config, level_weight));
   return 0;
 }
 """)
@@ -54,7 +56,8 @@ int main(void) {
     C = ctypes
     want = [C.sizeof(_lib.fewha_layer), C.sizeof(_lib.fewha_wfs), C.sizeof(_lib.fewha_config),
             C.sizeof(_lib.fewha_solve_info), _lib.fewha_wfs.slope_weight.offset, _lib.fewha_config.alpha.offset,
-            _lib.fewha_config.max_iter.offset, _lib.fewha_config.rel_tol.offset, _lib.fewha_config.precision.offset]
+            _lib.fewha_config.max_iter.offset, _lib.fewha_config.rel_tol.offset, _lib.fewha_config.precision.offset,
+            _lib.fewha_wfs.cross_weight.offset, _lib.fewha_wfs.tt_filter.offset, _lib.fewha_config.level_weight.offset]
     assert [int(v) for v in out] == want
 
 
@@ -74,6 +77,17 @@ def test_workspace_size_is_host_only_and_grows_with_recycling():
     assert fw.fewha_workspace_size(spec) < n2
 
 
+def _set_cross(spec, active):
+    """A cross weight on an inactive subaperture, or one that makes an active block indefinite."""
+    w = spec.wfs[0]
+    n2 = w.n_sub ** 2
+    act = (w.weight[:n2] != 0) | (w.weight[n2:] != 0)
+    i = int(np.flatnonzero(act)[0] if active else np.flatnonzero(~act)[0])
+    cw = np.zeros(n2)
+    cw[i] = 2.0 * max(w.weight[i], w.weight[n2 + i], 1.0)
+    w.cross_weight = cw
+
+
 @pytest.mark.parametrize("mutate, needle", [
     (lambda s: setattr(s.layers[0], "n", 24), "power of two"),
     (lambda s: setattr(s.layers[0], "levels", 9), "levels"),
@@ -83,6 +97,9 @@ def test_workspace_size_is_host_only_and_grows_with_recycling():
     (lambda s: setattr(s.wfs[1], "lgs_height", 5000.0), "laser guide star"),
     (lambda s: s.wfs[0].weight.__setitem__(3, -1.0), "weights"),
     (lambda s: setattr(s, "project_all", True) or setattr(s, "recycle_mode", "paper"), "project_all"),
+    (lambda s: _set_cross(s, active=False), "inactive subaperture"),
+    (lambda s: _set_cross(s, active=True), "positive semi-definite"),
+    (lambda s: setattr(s.wfs[0], "cross_weight", np.full(s.wfs[0].n_sub ** 2, np.nan)), "finite"),
 ])
 def test_invalid_configurations_are_rejected(mutate, needle):
     spec = _spec()
