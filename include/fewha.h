@@ -281,7 +281,8 @@ fewha_status fewha_time_kernel(fewha_ctx* ctx, int32_t kernel, int32_t step, int
                                float* avg_ms);
 
 /* Tile shapes of the operator kernels that change no result bit: the synthesis image tile
- * (16 or 32; 0 = 16 when 32 would give fewer than 256 workgroups, the default) and the layer
+ * (16, 32 or, FP32 only, 64; 0 = 16 when 32 would give fewer than 256 workgroups, else 32, the
+ * default) and the layer
  * rows per thread of the propagation adjoint's gather (1: tiles of 8 x 32 nodes, 4: 32 x 32
  * with the sensor nodes staged in LDS; default 4 from 2^21 coefficients on). */
 typedef struct {
@@ -294,11 +295,12 @@ fewha_status fewha_get_tuning(const fewha_ctx* ctx, fewha_tuning* t);   /* the s
 /* Selects tile shapes (FEWHA_E_INVAL for other values); drops the captured frame graphs. */
 fewha_status fewha_set_tuning(fewha_ctx* ctx, const fewha_tuning* t);
 
-/* Autotuner: times every combination of the tile shapes (synthesis 16 / 32 x gather rows 1 /
- * 4) on `reps` applications of M to the carried coefficients, captured into a graph and
- * replayed between two events on `stream`; keeps the fastest in the context and returns it in
- * *best (may be NULL), the mean application time of each candidate in ms[0..n) (order: syn
- * 16 rows 1, syn 16 rows 4, syn 32 rows 1, syn 32 rows 4) and their count in *n_out.  The
+/* Autotuner: times every combination of the tile shapes (synthesis 16 / 32 / 64 (FP32) x
+ * gather rows 1 / 4) on `reps` applications of M to the carried coefficients, captured into a
+ * graph and replayed between two events on `stream`; keeps the fastest in the context and
+ * returns it in *best (may be NULL), the mean application time of each candidate in ms[0..n)
+ * (order: syn 16 rows 1, syn 16 rows 4, syn 32 rows 1, syn 32 rows 4, syn 64 rows 1, syn 64
+ * rows 4) and their count (4 in FP64, 6 in FP32) in *n_out.  The
  * caller stores *best and restores it with fewha_set_tuning on a later context of the same
  * configuration.  Overwrites the scratch vectors (not the carried state); synchronises
  * `stream`. */

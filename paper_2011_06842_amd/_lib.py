@@ -444,10 +444,10 @@ class FewhaContext:
     def fewha_autotune(self, reps=20, stream=None):
         """Times the tile-shape candidates on M x, keeps the fastest; returns (best, {candidate: ms})."""
         t = fewha_tuning()
-        ms = (C.c_float * 4)()
+        ms = (C.c_float * 6)()
         n = C.c_int32()
-        _check(self.lib.fewha_autotune(self.ctx, int(reps), _stream(stream), C.byref(t), ms, 4, C.byref(n)), self.ctx)
-        cands = [(16, 1), (16, 4), (32, 1), (32, 4)]
+        _check(self.lib.fewha_autotune(self.ctx, int(reps), _stream(stream), C.byref(t), ms, 6, C.byref(n)), self.ctx)
+        cands = [(16, 1), (16, 4), (32, 1), (32, 4), (64, 1), (64, 4)]
         return ({"syn_tile": t.syn_tile, "gather_rows": t.gather_rows},
                 {f"syn{a}_rows{b}": float(ms[i]) for i, (a, b) in enumerate(cands[:n.value])})
 

@@ -442,8 +442,10 @@ fewha_status fewha_get_tuning(const fewha_ctx* ctx, fewha_tuning* t) {
 
 fewha_status fewha_set_tuning(fewha_ctx* ctx, const fewha_tuning* t) {
     if (!ctx || !t) return FEWHA_E_INVAL;
-    if (t->syn_tile != 0 && t->syn_tile != fewha::kSynTile / 2 && t->syn_tile != fewha::kSynTile)
-        return fail(ctx, FEWHA_E_INVAL, "syn_tile must be 0, 16 or 32");
+    const bool big_ok = ctx->c.prec != FEWHA_FP64;   // 64 x 64 tiles need FP32 (LDS)
+    if (t->syn_tile != 0 && t->syn_tile != fewha::kSynTile / 2 && t->syn_tile != fewha::kSynTile &&
+        !(big_ok && t->syn_tile == 2 * fewha::kSynTile))
+        return fail(ctx, FEWHA_E_INVAL, "syn_tile must be 0, 16, 32 or (FP32) 64");
     if (t->gather_rows != 1 && t->gather_rows != 4) return fail(ctx, FEWHA_E_INVAL, "gather_rows must be 1 or 4");
     fewha::Ctx& c = ctx->c;
     if (c.syn_tile != t->syn_tile || c.gather_rows != t->gather_rows) {
@@ -458,12 +460,13 @@ fewha_status fewha_autotune(fewha_ctx* ctx, int32_t reps, void* stream, fewha_tu
                             int32_t* n_out) {
     if (!ctx || reps < 1) return FEWHA_E_INVAL;
     fewha::Ctx& c = ctx->c;
-    const int syn[2] = {fewha::kSynTile / 2, fewha::kSynTile}, rows[2] = {1, 4};
-    fewha_tuning cand[4] = {}, keep = {};
+    const int nsyn = c.prec == FEWHA_FP64 ? 2 : 3;
+    const int syn[3] = {fewha::kSynTile / 2, fewha::kSynTile, 2 * fewha::kSynTile}, rows[2] = {1, 4};
+    fewha_tuning cand[6] = {}, keep = {};
     (void)fewha_get_tuning(ctx, &keep);
-    float tm[4] = {};
+    float tm[6] = {};
     int k = 0, b = -1;
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < nsyn; ++i)
         for (int j = 0; j < 2; ++j, ++k) {
             cand[k].syn_tile = syn[i];
             cand[k].gather_rows = rows[j];
@@ -479,8 +482,8 @@ fewha_status fewha_autotune(fewha_ctx* ctx, int32_t reps, void* stream, fewha_tu
         }
     (void)fewha_set_tuning(ctx, &cand[b]);
     if (best) *best = cand[b];
-    for (int i = 0; i < n && i < 4; ++i) ms[i] = tm[i];
-    if (n_out) *n_out = 4;
+    for (int i = 0; i < n && i < k; ++i) ms[i] = tm[i];
+    if (n_out) *n_out = k;
     return FEWHA_OK;
 }
 

@@ -186,7 +186,7 @@ struct Ctx {
     int data_grid = 0;         // workgroups of the fused data term (tiles, padded to kXcds)
     int gather_grid1 = 0, gather_grid4 = 0;   // gather workgroups (layer tiles, padded to kXcds) of 1 and 4 rows
     int gather_rows = 1;       // layer rows per gather thread (tile of 8 gather_rows x kGT nodes), 1 or 4
-    int syn_tile = 0;          // synthesis image tile: 16, 32, or 0 (by the number of tiles)
+    int syn_tile = 0;          // synthesis image tile: 16, 32, 64 (FP32), or 0 (by the number of tiles)
     std::vector<InstDev> insts;
     std::vector<int> layers_n;     // grid size of every layer (host)
     std::vector<int64_t> s_offs;   // slope offsets of the instances (B + 1)
@@ -201,7 +201,7 @@ struct Ctx {
     int max_rng = 0;           // largest gather contribution count of a layer row/column
     int max_gwin_side = 0;     // largest side of the sensor-node rectangle of a gather tile
     std::vector<StepInfo> steps;  // tiled analysis launches (finest levels first)
-    int syn_small = 0, syn_large = 0;   // synthesis tiles of kSynTile / 2 and of kSynTile
+    int syn_small = 0, syn_large = 0, syn_huge = 0;   // synthesis tiles of kSynTile / 2, kSynTile, 2 kSynTile
     bool any_cross = false, any_tt = false;   // LGS noise model: 2x2 noise blocks / tip/tilt filters
     int npq = 0;               // (p, q) partial entries written by one analysis
     int64_t n_cells = 0, n_ranges = 0;

@@ -143,6 +143,11 @@ struct SynTile {
     __device__ __forceinline__ void load(const T* __restrict__ C, int n, int L, T* v, int* dst, int k0) const {
         constexpr int W = syn_window(ST, l), Q = 4 * W * W, P = cdiv_c(Q, kThreads), SB = 2 * W + 1;
         const int m = n >> l;
+        if (l > L) {   // uniform: levels the layer does not have
+#pragma unroll
+            for (int k = 0; k < P; ++k) dst[k0 + k] = -1;
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int e = threadIdx.x + k * kThreads;
@@ -162,6 +167,44 @@ struct SynTile {
         constexpr int W = syn_window(ST, l), SB = 2 * W + 1, W2 = syn_window(ST, l - 1);
         const T* B = buf + syn_boff(ST, l);
         const int a2 = ay[l - 1], h2 = wy[l - 1], b2 = ax[l - 1], v2 = wx[l - 1], wxl = wx[l];
+        if constexpr (l == 1) {
+            // the finest level: the tile starts at even rows and columns, so outputs 2i and 2i + 1
+            // read the same three coefficients of each band (base = i + 2) and are formed as a
+            // pair, with the same arithmetic as one at a time
+            using V2 = typename Vec2<T>::type;
+            for (int e = threadIdx.x; e < (ST / 2) * 2 * W; e += kThreads) {   // vertical pass
+                const int i = e / (2 * W), col = e - i * (2 * W);
+                const int cc = col >= W ? col - W : col;
+                if (2 * i < h2 && cc < wxl) {
+                    T ev = 0, od = 0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const T a = B[(i + 2 - k) * SB + col], b = B[(W + i + 2 - k) * SB + col];
+                        ev += tp.he[k] * a + tp.ge[k] * b;
+                        od += tp.ho[k] * a + tp.go[k] * b;
+                    }
+                    I[(2 * i) * SB + col] = ev;
+                    I[(2 * i + 1) * SB + col] = od;
+                }
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < ST * (ST / 2); e += kThreads) {   // horizontal pass
+                const int i = e / (ST / 2), j = e - i * (ST / 2);
+                if (i < h2 && 2 * j < v2) {
+                    T ev = 0, od = 0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const T a = I[i * SB + j + 2 - k], b = I[i * SB + W + j + 2 - k];
+                        ev += tp.he[k] * a + tp.ge[k] * b;
+                        od += tp.ho[k] * a + tp.go[k] * b;
+                    }
+                    *reinterpret_cast<V2*>(phi + off + size_t(ay[0] + i) * n + ax[0] + 2 * j) =
+                        V2{ev * inv_delta, od * inv_delta};
+                }
+            }
+            __syncthreads();
+            return;
+        }
         // vertical pass: the rows of level l - 1's window, both column halves (I: rows of SB)
         for (int e = threadIdx.x; e < W2 * 2 * W; e += kThreads) {
             const int i = e / (2 * W), col = e - i * (2 * W);
@@ -1151,6 +1194,16 @@ hipError_t profiler_collect(const Ctx& c, hipStream_t s) {
 
 // ------------------------------------------------------------------ operator launchers
 
+template <typename T>
+inline Filt<float> f32_filt(const Filt<T>& f) {
+    Filt<float> g;
+    for (int t = 0; t < 6; ++t) {
+        g.h[t] = float(f.h[t]);
+        g.g[t] = float(f.g[t]);
+    }
+    return g;
+}
+
 // The synthesis in one launch: kSynTile x kSynTile output tiles, or tiles of half that side
 // when the large ones would give fewer workgroups than kSmallTileBelow (a single small
 // instance): the launch is then bound by the latency of each workgroup, and four times as many
@@ -1163,6 +1216,10 @@ void launch_winv(const Ctx& c, const T* x, T* phi, hipStream_t s, const OpBufs* 
     ProfScope ps_(c, KID_IDWT, s);
     if (c.syn_tile == kSynTile / 2 || (c.syn_tile == 0 && c.syn_large < kSmallTileBelow))
         k_idwt<T, kSynTile / 2><<<c.syn_small, kThreads, 0, s>>>(lays, items, f, x, phi, skip);
+    else if (c.syn_tile == 2 * kSynTile && sizeof(T) == 4)   // 64 x 64 tiles: FP32 only (LDS)
+        k_idwt<float, 2 * kSynTile><<<c.syn_huge, kThreads, 0, s>>>(lays, items + c.syn_small + c.syn_large, f32_filt(f),
+                                                                     reinterpret_cast<const float*>(x),
+                                                                     reinterpret_cast<float*>(phi), skip);
     else
         k_idwt<T, kSynTile><<<c.syn_large, kThreads, 0, s>>>(lays, items + c.syn_small, f, x, phi, skip);
 }

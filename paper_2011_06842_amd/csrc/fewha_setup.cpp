@@ -187,7 +187,7 @@ struct Sizes {
     int B = 0, L = 0, G = 0, slots = 0, esz = 8, KE = 1;
     int64_t N = 0, S = 0, V = 0, cells = 0, ranges = 0, pairs = 0;   // pairs: also the record bases
     int VB = 0, GB = 0, NPQ = 0, data_tiles = 0, gather_tiles1 = 0, gather_tiles4 = 0, gather_rows = 1;
-    int syn_small = 0, syn_large = 0, ana_items = 0, ana_groups = 0;
+    int syn_small = 0, syn_large = 0, syn_huge = 0, ana_items = 0, ana_groups = 0;
     int64_t gwin = 0;   // gather windows: (layer tile, sensor of its instance) pairs
     std::vector<StepInfo> steps;
 };
@@ -258,6 +258,7 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
             z.NPQ += layer_pq(n, c->layers[l].levels, cb, kmax);
             z.syn_small += syn_tiles(n, kSynTile / 2);
             z.syn_large += syn_tiles(n, kSynTile);
+            z.syn_huge += syn_tiles(n, 2 * kSynTile);
             for (const AnaSeg& sg : ana_segments(n, c->layers[l].levels, cb, kmax))
                 z.ana_groups = std::max(z.ana_groups, sg.g + 1);
         }
@@ -291,6 +292,7 @@ Sizes batch_sizes(const fewha_config* cfgs, int nb) {
         }
     z.syn_small = round_up(z.syn_small, kXcds);
     z.syn_large = round_up(z.syn_large, kXcds);
+    z.syn_huge = round_up(z.syn_huge, kXcds);
     // tiled analysis launches: one per group of block sizes that has workgroups, finest first
     for (int g = z.ana_groups - 1; g >= 0; --g) {
         StepInfo st;
@@ -355,7 +357,7 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.insts = take(sizeof(InstDev) * z.B);
     lo.vecblk = take(sizeof(VecBlk) * z.VB);
     lo.gramblk = take(sizeof(GramBlk) * z.GB);
-    lo.syn_items = take(sizeof(int2) * (z.syn_small + z.syn_large));
+    lo.syn_items = take(sizeof(int2) * (z.syn_small + z.syn_large + z.syn_huge));
     lo.ana_items = take(sizeof(int4) * std::max(1, z.ana_items));
     lo.data_tiles = take(sizeof(int2) * round_up(z.data_tiles, kXcds));
     lo.gather_tiles = take(sizeof(int2) * (round_up(z.gather_tiles1, kXcds) + round_up(z.gather_tiles4, kXcds)));
@@ -795,17 +797,20 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     for (size_t i = 1; i < t.rng.size(); i += 2) ctx.max_rng = std::max(ctx.max_rng, int(t.rng[i]));
     // layers of every tiled wavelet level, and the block -> sensor / layer tables
     // synthesis tiles (half-size tiles, then full-size), die-ordered per launch
-    std::vector<int2> s16, s32;
+    std::vector<int2> s16, s32, s64;
     for (int l = 0; l < z.L; ++l) {
         for (int k = 0; k < syn_tiles(t.ld[l].n, kSynTile / 2); ++k) s16.push_back(make_int2(l, k));
         for (int k = 0; k < syn_tiles(t.ld[l].n, kSynTile); ++k) s32.push_back(make_int2(l, k));
+        for (int k = 0; k < syn_tiles(t.ld[l].n, 2 * kSynTile); ++k) s64.push_back(make_int2(l, k));
     }
     std::vector<int2> syn = die_order(s16);
     ctx.syn_small = int(syn.size());
     {
-        const std::vector<int2> o32 = die_order(s32);
+        const std::vector<int2> o32 = die_order(s32), o64 = die_order(s64);
         ctx.syn_large = int(o32.size());
+        ctx.syn_huge = int(o64.size());
         syn.insert(syn.end(), o32.begin(), o32.end());
+        syn.insert(syn.end(), o64.begin(), o64.end());
     }
     // tiled analysis items (layer, tile, l1 | k << 8 | tile side << 16, partial slot) of every
     // launch, the partial slots of a layer numbered in launch and tile order
@@ -827,7 +832,7 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
         }
         for (int l = 0; l < z.L; ++l)
             if (slot[l] != t.ld[l].pq_coarse) { ctx.err = "internal: analysis partial count mismatch"; return FEWHA_E_INVAL; }
-        if (int(ana.size()) != z.ana_items || int(syn.size()) != z.syn_small + z.syn_large) {
+        if (int(ana.size()) != z.ana_items || int(syn.size()) != z.syn_small + z.syn_large + z.syn_huge) {
             ctx.err = "internal: wavelet item count mismatch";
             return FEWHA_E_INVAL;
         }

@@ -401,10 +401,10 @@ def test_autotuner_choices_change_no_bit(name, precision):
     a = fw.FewhaContext(spec, device=DEV)
     ref = [host(a.fewha_solve_aug(dev(seq[t], dt))) for t in range(3)]
     best, ms = a.fewha_autotune(reps=5)
-    assert len(ms) == 4 and all(v > 0 for v in ms.values())
+    assert len(ms) == (4 if precision == "fp64" else 6) and all(v > 0 for v in ms.values())
     assert ms[f"syn{best['syn_tile']}_rows{best['gather_rows']}"] == min(ms.values())
     assert a.fewha_get_tuning() == best
-    for syn_tile, rows in [(16, 1), (16, 4), (32, 1), (32, 4)]:
+    for syn_tile, rows in [(16, 1), (16, 4), (32, 1), (32, 4)] + ([(64, 1), (64, 4)] if precision == "fp32" else []):
         b = fw.FewhaContext(spec, device=DEV)
         b.fewha_set_tuning(syn_tile, rows)
         assert b.fewha_get_tuning() == {"syn_tile": syn_tile, "gather_rows": rows}
@@ -412,3 +412,6 @@ def test_autotuner_choices_change_no_bit(name, precision):
             assert np.array_equal(host(b.fewha_solve_aug(dev(seq[t], dt))), ref[t]), (syn_tile, rows, t)
     with pytest.raises(fw.FewhaError):
         a.fewha_set_tuning(24, 1)
+    if precision == "fp64":
+        with pytest.raises(fw.FewhaError):
+            a.fewha_set_tuning(64, 1)
