@@ -16,7 +16,7 @@ namespace fewha {
 constexpr int kThreads = 256;       // threads of every 1-D kernel (4 wavefronts of 64)
 constexpr int kVecBlocksMax = 1024; // vector-kernel workgroups of one instance (grid-stride beyond)
 constexpr int kDefaultBlockElems = 384;  // default elements per vector workgroup
-constexpr int kGramElems = 768;     // elements per Gram workgroup (one instance: <= kGramBlocks)
+constexpr int kGramElems = 1536;    // elements per Gram workgroup (one instance: <= kGramBlocks)
 constexpr int kKMax = FEWHA_MAX_RECYCLE;
 constexpr int kSlotsMax = kKMax + 256;
 constexpr int kTile = 14;           // wavefront-node tile side of the fused data-term kernel (16 with the halo)
@@ -36,7 +36,7 @@ constexpr int kGRowStep = kThreads / kGT;        // tile rows per gather thread 
 constexpr int64_t kGatherWide = int64_t(1) << 21;  // from this many coefficients on, 4 rows per gather thread
 constexpr int kRMax = 6;            // contributions per layer row/column held by a gather record
 constexpr int kXcds = 8;            // accelerator complex dies; workgroup i runs on die i mod kXcds
-constexpr int kGramBlocks = 256;    // Gram workgroups of one instance at most (partials per entry)
+constexpr int kGramBlocks = 128;    // Gram workgroups of one instance at most (partials per entry)
 constexpr int kGramThreads = 1024;  // threads of a Gram workgroup (16 wavefronts)
 constexpr int kDataThreads = 256;   // threads of the fused data-term kernel (one halo-tile node each)
 constexpr int kSolveThreads = 1024; // threads of the single-block Gram reduction and solve
