@@ -86,6 +86,8 @@ __device__ __forceinline__ void block_row_sums(const double* __restrict__ part, 
 // G = R^T R (R upper) of the symmetric matrix whose upper triangle is X[a * ld + b] (a <= b),
 // columns in order, column j dropped (row j of R zero, keep[j] = 0) when its pivot is
 // <= 1e-14 max diag G.  R is written to Rout[i * m + k] (LDS or global); returns the drop count.
+// The entries of R agree with the textbook recurrences to a few units in the last place (the
+// reciprocal square root is not correctly rounded).
 template <int MB>
 __device__ int wave_cholesky(const double* X, int ld, int m, double* Rout, int32_t* keep) {
     const int k = threadIdx.x & 63;
@@ -109,8 +111,10 @@ __device__ int wave_cholesky(const double* X, int ld, int m, double* Rout, int32
                 if (i < j) s += lane_value(c[i], j) * c[i];
             const double d = lane_value(g[j] - s, j);
             const bool kj = d > thr;
-            const double rjj = kj ? sqrt(d) : 0.0;
-            c[j] = !kj ? 0.0 : (k == j ? rjj : (k > j ? (g[j] - s) / rjj : 0.0));
+            // R_jj = d / sqrt(d) and R_jk = (G_jk - s_k) / R_jj through one reciprocal square root,
+            // so that the column costs a multiply per lane and no division on the chain
+            const double ir = kj ? rsqrt(d) : 0.0;
+            c[j] = !kj ? 0.0 : (k == j ? d * ir : (k > j ? (g[j] - s) * ir : 0.0));
             dropped += kj ? 0 : 1;
             if (k == 0) keep[j] = kj ? 1 : 0;
         }
@@ -387,12 +391,19 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
 // entry e0 + 4 b + row.  Lane c of a row adds the partials j = c + 16 q in increasing j, QB of
 // them per round; the row's 16 sums are then added by DPP row shifts (lane 15 of the row ends
 // with the entry's sum).  Loads outside the partials are clamped and their values dropped.
+// emap (LDS, may be NULL): the t-th entry reduced is emap[t] (ne entries in the map).
 template <int EB, int QB>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ gp, int ngb, int ne, int wv, int lane,
-                                                double* __restrict__ X) {
+                                                double* __restrict__ X, const int16_t* __restrict__ emap) {
     constexpr int NWS = kSolveThreads / 64;
     const int row = lane >> 4, c = lane & 15;
     for (int e0 = wv * 4 * EB; e0 < ne; e0 += NWS * 4 * EB) {
+        int ent[EB];
+#pragma unroll
+        for (int b = 0; b < EB; ++b) {
+            const int t = e0 + 4 * b + row;
+            ent[b] = emap ? emap[t < ne ? t : 0] : t;
+        }
         double s[EB];
 #pragma unroll
         for (int b = 0; b < EB; ++b) s[b] = 0.0;
@@ -402,9 +413,9 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ gp, i
             for (int b = 0; b < EB; ++b)
 #pragma unroll
                 for (int q = 0; q < QB; ++q) {
-                    const int e = e0 + 4 * b + row, j = j0 + 16 * q + c;
-                    const bool ok = e < ne && j < ngb;
-                    v[b][q] = gp[ok ? size_t(e) * ngb + j : 0];
+                    const int j = j0 + 16 * q + c;
+                    const bool ok = e0 + 4 * b + row < ne && j < ngb;
+                    v[b][q] = gp[ok ? size_t(ent[b]) * ngb + j : 0];
                 }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -424,7 +435,7 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ gp, i
         if (c == 15) {
 #pragma unroll
             for (int b = 0; b < EB; ++b)
-                if (e0 + 4 * b + row < ne) X[e0 + 4 * b + row] = s[b];
+                if (e0 + 4 * b + row < ne) X[ent[b]] = s[b];
         }
     }
 }
@@ -448,17 +459,45 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     const double gam = threadIdx.x < m ? sc->gam[sl.s[threadIdx.x]] : 0.0;
     const double* __restrict__ gp = gpart + size_t(I.gb0) * ke;
     const int ngb = I.ngb;
-    const int ne = 2 * m * (m + 1);
+    const int W = m + 1;
+    // GALERKIN uses the upper triangles of X and Y with their r column (both matrices are
+    // symmetric in their first m columns): only those m (m + 3) entries are reduced, Y's lower
+    // triangle is mirrored after.  PAPER reads both triangles of X.
+    __shared__ int16_t emap[kKMax * (kKMax + 3)];
+    const bool upper = mode != FEWHA_RECYCLE_PAPER;
+    const int nh = m * (m + 3) / 2;
+    const int ne = upper ? 2 * nh : 2 * m * W;
+    if (upper) {
+        for (int t = threadIdx.x; t < 2 * nh; t += kSolveThreads) {
+            const int half = t >= nh ? 1 : 0;
+            int rem = t - half * nh, a = 0;
+            while (rem >= W - a) {   // row a holds columns a .. m
+                rem -= W - a;
+                ++a;
+            }
+            emap[t] = int16_t(half * m * W + a * W + a + rem);
+        }
+        __syncthreads();
+    }
     {   // 32 loads per lane requested at once (16 where there are at most 16 partials)
         const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        if (ngb <= 16) reduce_partials<16, 1>(gp, ngb, ne, wv, lane, X);
-        else if (ngb <= 64) reduce_partials<8, 4>(gp, ngb, ne, wv, lane, X);
-        else reduce_partials<4, 8>(gp, ngb, ne, wv, lane, X);
+        const int16_t* em = upper ? emap : nullptr;
+        if (ngb <= 16) reduce_partials<16, 1>(gp, ngb, ne, wv, lane, X, em);
+        else if (ngb <= 64) reduce_partials<8, 4>(gp, ngb, ne, wv, lane, X, em);
+        else reduce_partials<4, 8>(gp, ngb, ne, wv, lane, X, em);
     }
     if (threadIdx.x < m) gm[threadIdx.x] = gam;
     __syncthreads();
+    if (upper) {
+        double* Yl = X + m * W;
+        for (int e = threadIdx.x; e < m * m; e += kSolveThreads) {
+            const int a = e / m, b = e - a * m;
+            if (a > b) Yl[a * W + b] = Yl[b * W + a];
+        }
+        __syncthreads();
+    }
     if (threadIdx.x >= 64) return;
-    const int k = threadIdx.x, W = m + 1;
+    const int k = threadIdx.x;
     // tolerance mode: only the last `avail` slots of the window hold this instance's real
     // directions (an instance that stopped early has fewer); the others are made zero rows and
     // columns, which both variants skip (zero pivot / zero (p, q)), and are not reported
