@@ -254,7 +254,7 @@ def run_batch(args, dev, atmos, t_gen):
     sp = spec.copy()
     sp.block_elems = best
     ctx = fw.FewhaContext([sp] * B, device=dev, precond_inv=jinv)
-    tuned, tune_ms = ctx.fewha_autotune(reps=5)
+    tuned, tune_ms = choose_tiles(ctx, args.batch_tuning, 5)
     log(f"batched leg: autotuner chose {tuned}")
     wall, fm = timed(ctx, args.batch_warmup, args.batch_steps)
     log(f"batched leg: timed {args.batch_steps} frames, p50 {np.median(fm):.3f} ms")
@@ -756,6 +756,16 @@ def cpu_baselines(spec, seq, n_single, n_all, workers):
 
 # ---------------------------------------------------------------- GPU legs
 
+def choose_tiles(ctx, spec_tuning, reps):
+    """The autotuner's tile shapes, or the fixed ones `spec_tuning` names ("synS_rowsR"; for
+    profiled runs, whose tracing overhead distorts the tuner's timings)."""
+    if spec_tuning == "auto":
+        return ctx.fewha_autotune(reps=reps)
+    syn, rows = spec_tuning.replace("syn", "").split("_rows")
+    ctx.fewha_set_tuning(int(syn), int(rows))
+    return {"syn_tile": int(syn), "gather_rows": int(rows)}, {}
+
+
 def time_frames(ctx, slopes, t0, n, c, info):
     """Frames t0..t0+n-1 (each a graph replay), one HIP event after each on the context's stream:
     (wall s, per-frame ms)."""
@@ -860,7 +870,7 @@ def run_single(args, dev, spec, seq):
     V = sum((w.n_sub + 1) ** 2 for w in spec.wfs)
     c = torch.empty(N, dtype=torch.float32, device=dev)
     info = ctx.new_info()
-    tuned, tune_ms = ctx.fewha_autotune(reps=args.kernel_reps)   # tile shapes (no result bit changes)
+    tuned, tune_ms = choose_tiles(ctx, args.tuning, args.kernel_reps)   # tile shapes (no result bit changes)
     log(f"single instance: autotuner chose {tuned} ({ {k: round(v * 1000, 2) for k, v in tune_ms.items()} } us per apply)")
     time_frames(ctx, slopes, 0, args.warmup, c, info)
     wall, frame_ms = time_frames(ctx, slopes, args.warmup, args.steps, c, info)
@@ -1052,6 +1062,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--tuning", default="auto",
+                    help="single-instance tile shapes: auto (the autotuner) or synS_rowsR, e.g. syn16_rows1")
+    ap.add_argument("--batch-tuning", default="auto", help="batched-leg tile shapes (as --tuning)")
     ap.add_argument("--latency-frames", type=int, default=2000,
                     help="frames of the single-instance sequence (timed frames first, the rest a latency pass)")
     ap.add_argument("--cpu-frames", type=int, default=20, help="frames of the single-thread oracle baseline")
