@@ -144,7 +144,7 @@ struct Scalars {
 // Byte layout of the workspace (offsets from its base).
 struct Layout {
     size_t layers, wfs, pairs, cellidx, frac, ranges, weight, xweight, ttv, wslopes, prior_a, jinv;
-    size_t insts, vecblk, gramblk, syn_items, ana_items, data_tiles, gather_tiles, grecs, recbase, gwin;
+    size_t insts, vecblk, gramblk, syn_items, ana_items, data_tiles, gather_tiles, grecs, recbase, gwin, node_sensor;
     size_t nodal, tmp0, tmp1, psi_nodes, psi_layers, vx, vy;
     size_t c, r, z, b, b_prev;
     size_t ring_u, ring_q;

@@ -772,14 +772,18 @@ __global__ void __launch_bounds__(kDataThreads) k_data_term(const WfsDev* __rest
 // With the 2x2 noise blocks (xw) the weighted slope pair of a subaperture is
 // [[wx, wc], [wc, wy]] (sx, sy), zero on an inactive subaperture (wx = wy = 0).  The weighted
 // slopes of a tip/tilt-filtered sensor also go to wsl (node (i, j) writes subaperture (i, j)).
+// The node's sensor is found from the sensor of the block's first node (a setup table), so
+// that it costs one or two dependent loads instead of a binary search over all sensors.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_slopes_adj(const WfsDev* __restrict__ wfs, int G, int64_t V,
                                                           const T* __restrict__ w, const T* __restrict__ s,
                                                           T* __restrict__ psi, int weighted, const T* __restrict__ xw,
-                                                          T* __restrict__ wsl) {
+                                                          T* __restrict__ wsl, const int32_t* __restrict__ node_sensor) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= V) return;
-    const WfsDev W = wfs[find_sensor(wfs, G, e, [](const WfsDev& w) { return w.noff; })];
+    int g = node_sensor[blockIdx.x];
+    while (g + 1 < G && wfs[g + 1].noff <= e) ++g;
+    const WfsDev W = wfs[g];
     const int ns = W.ns, np = ns + 1;
     const int loc = int(e - W.noff);
     const int i = loc / np, j = loc % np;
@@ -1287,7 +1291,8 @@ void launch_slopes_adj(const Ctx& c, const T* slopes, T* psi_nodes, int weighted
     ProfScope ps_(c, KID_SLOPES_ADJ, s);
     k_slopes_adj<T><<<cdiv(c.V, kThreads), kThreads, 0, s>>>(
         c.at<WfsDev>(c.lay.wfs), c.G, c.V, c.at<T>(c.lay.weight), slopes, psi_nodes, weighted,
-        weighted && c.any_cross ? c.at<T>(c.lay.xweight) : nullptr, weighted && c.any_tt ? c.at<T>(c.lay.wslopes) : nullptr);
+        weighted && c.any_cross ? c.at<T>(c.lay.xweight) : nullptr, weighted && c.any_tt ? c.at<T>(c.lay.wslopes) : nullptr,
+        c.at<int32_t>(c.lay.node_sensor));
 }
 
 template <typename T>

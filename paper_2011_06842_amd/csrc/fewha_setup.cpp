@@ -364,6 +364,7 @@ Layout compute_layout(const fewha_config* cfgs, int nb) {
     lo.grecs = take((z.esz == 8 ? sizeof(GatherRec<double>) : sizeof(GatherRec<float>)) * z.ranges);
     lo.recbase = take(sizeof(int64_t) * std::max<int64_t>(1, z.pairs));
     lo.gwin = take(sizeof(int4) * std::max<int64_t>(1, z.gwin));
+    lo.node_sensor = take(sizeof(int32_t) * std::max<int64_t>(1, (V + kThreads - 1) / kThreads));
     lo.weight = take(e * S);
     lo.xweight = take(e * (S / 2));
     lo.ttv = take(e * 2 * V);
@@ -964,7 +965,16 @@ fewha_status build_tables(Ctx& ctx, const fewha_config* cfgs, int nb, hipStream_
     for (const WfsDev& w : t.wd) ctx.any_tt = ctx.any_tt || w.tt;
     const auto pa_t = typed(t.D);
     const auto j_t = typed(t.Jinv);
+    // sensor of the first node of every kThreads-node block of the sensor-node vector (the slope
+    // adjoint starts its search there)
+    std::vector<int32_t> node_sensor(size_t(std::max<int64_t>(1, (ctx.V + kThreads - 1) / kThreads)), 0);
+    for (size_t b = 0, g = 0; b < node_sensor.size(); ++b) {
+        const int64_t e0 = int64_t(b) * kThreads;
+        while (g + 1 < t.wd.size() && t.wd[g + 1].noff <= e0) ++g;
+        node_sensor[b] = int32_t(g);
+    }
     bool ok = up(lo.layers, t.ld.data(), sizeof(LayerDev) * t.ld.size()) &&
+              up(lo.node_sensor, node_sensor.data(), sizeof(int32_t) * node_sensor.size()) &&
               up(lo.wfs, t.wd.data(), sizeof(WfsDev) * t.wd.size()) &&
               up(lo.pairs, t.pd.data(), sizeof(PairDev) * t.pd.size()) &&
               up(lo.cellidx, t.cidx.data(), sizeof(int32_t) * t.cidx.size()) &&
