@@ -130,7 +130,7 @@ struct Scalars {
     double y[kKMax];      // Galerkin coefficients
     double y2[kKMax];     // initial-direction coefficients
     double gam[kSlotsMax];// (p_j, q_j) of every ring slot
-    double R[kKMax * kKMax];
+    double R[kKMax * kKMax];   // GALERKIN: G+ of the recycled Gram matrix (m x m, row-major); PAPER: rows of X
     int32_t keep[kKMax];
     int32_t flags, dropped, used, iters;
     int32_t conv_iter;    // tolerance mode: first iteration whose residual met the tolerance (0: not yet)

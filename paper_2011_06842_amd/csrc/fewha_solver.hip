@@ -78,107 +78,88 @@ __device__ __forceinline__ void block_row_sums(const double* __restrict__ part, 
     __syncthreads();
 }
 
-// Small dense algebra of the recycle space on one wavefront (m <= MB <= 64, all 64 lanes
-// active): lane k owns column k (and row k) of the factor in registers; pivots and solution
-// entries are broadcast by reading one lane's register into scalar registers, so no step
-// waits on a chain of memory or LDS round trips.
+// Small dense algebra of the recycle space on one wavefront (m <= 64, all 64 lanes active).
+// This runs once per frame on a single wavefront, where every step of a dependency chain costs
+// its full latency (a broadcast, a multiply-add: tens of cycles each), so the forms below are
+// chosen for short chains rather than few operations.
 
-// G = R^T R (R upper) of the symmetric matrix whose upper triangle is X[a * ld + b] (a <= b),
-// columns in order, column j dropped (row j of R zero, keep[j] = 0) when its pivot is
-// <= 1e-14 max diag G.  R is written to Rout[i * m + k] (LDS or global); returns the drop count.
-// The entries of R agree with the textbook recurrences to a few units in the last place (the
-// reciprocal square root is not correctly rounded).
-template <int MB>
-__device__ int wave_cholesky(const double* X, int ld, int m, double* Rout, int32_t* keep) {
-    const int k = threadIdx.x & 63;
-    double g[MB], c[MB];
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-        g[i] = (i < m && k < m && i <= k) ? X[i * ld + k] : 0.0;
-        c[i] = 0.0;
-    }
-    double dmax = k < m ? X[k * ld + k] : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
-    const double thr = 1e-14 * dmax;
-    int dropped = 0;
-#pragma unroll
-    for (int j = 0; j < MB; ++j) {
-        if (j < m) {
-            double s = 0;
-#pragma unroll
-            for (int i = 0; i < MB; ++i)
-                if (i < j) s += lane_value(c[i], j) * c[i];
-            const double d = lane_value(g[j] - s, j);
-            const bool kj = d > thr;
-            // R_jj = d / sqrt(d) and R_jk = (G_jk - s_k) / R_jj through one reciprocal square root,
-            // so that the column costs a multiply per lane and no division on the chain
-            const double ir = kj ? rsqrt(d) : 0.0;
-            c[j] = !kj ? 0.0 : (k == j ? d * ir : (k > j ? (g[j] - s) * ir : 0.0));
-            dropped += kj ? 0 : 1;
-            if (k == 0) keep[j] = kj ? 1 : 0;
-        }
-    }
-    if (k < m)
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-            if (i < m) Rout[i * m + k] = c[i];
-    return dropped;
+// The Galerkin system G y = v by Gauss-Jordan elimination in place (G symmetric positive
+// semi-definite: pivots in order, no exchanges).  Lane c < m holds column c of G in a[0..m-1],
+// lane m the right-hand side v; rows m..MB-1 and the other lanes are zero.  Step j broadcasts
+// column j (its row j is the pivot p: G_jj after the earlier steps, the Schur complement, which
+// is the square of the Cholesky pivot); row j is divided by p and eliminated from every other
+// row, and column j becomes column j of the inverse.  Index j is dropped when p <= thr: its
+// step then runs with 1/p replaced by 0, which leaves the other columns as they are and zeroes
+// row j and column j.  Lanes c < m end with the columns of G+ (the inverse of G restricted to
+// the kept indices, zero rows and columns for the dropped ones) and lane m with y = G+ v.
+// Returns the mask of kept indices.  Every step is the same straight-line code (no branch on
+// the pivot): one broadcast of a column and two multiply-adds per entry, so the compiler can
+// overlap a step's entry updates with the next pivot's reciprocal.
+// 1 / p for a positive normal p: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - p r), within an ulp or two (a correctly rounded division takes about twice as
+// many dependent steps, and each pivot's reciprocal is on the elimination's critical path).
+__device__ __forceinline__ double recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    r = fma(r, fma(-p, r, 1.0), r);
+    r = fma(r, fma(-p, r, 1.0), r);
+    return r;
 }
 
-// y = G^-1 v with the factor above (dropped columns give y_j = 0); lane k passes v_k and gets y_k.
-// Lane k holds 1 / R[k][k] (0 for a dropped column), so that a step of either sweep is a
-// multiply and a broadcast (no division on the dependency chain).
 template <int MB>
-__device__ double wave_chol_solve(const double* R, const int32_t* keep, int m, double v) {
-    const int k = threadIdx.x & 63;
-    double col[MB], row[MB];
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-        col[i] = (i < m && k < m) ? R[i * m + k] : 0.0;   // R[i][k]
-        row[i] = (i < m && k < m) ? R[k * m + i] : 0.0;   // R[k][i]
-    }
-    const double inv = (k < m && keep[k]) ? 1.0 / R[k * m + k] : 0.0;
-    // R^T t = v, column by column
+__device__ __forceinline__ unsigned wave_gauss_jordan(double (&a)[MB], int m, double thr) {
+    const int c = threadIdx.x & 63;
+    bool mine = false;   // lane c < m: pivot c was kept
 #pragma unroll
     for (int j = 0; j < MB; ++j) {
         if (j < m) {
-            const double tj = lane_value(inv != 0.0 ? v * inv : 0.0, j);
-            if (k == j) v = tj;
-            else if (k > j) v -= col[j] * tj;
-        }
-    }
-    // R y = t, from the last column back
+            // column j, read before lane j rewrites it (all at once where the scalar registers
+            // hold it, so that the reads overlap the reciprocal)
+            constexpr bool HOIST = MB <= 24;
+            double f[HOIST ? MB : 1];
+            if constexpr (HOIST)
 #pragma unroll
-    for (int j = MB - 1; j >= 0; --j) {
-        if (j < m) {
-            const double yj = lane_value(inv != 0.0 ? v * inv : 0.0, j);
-            if (k == j) v = yj;
-            else if (k < j) v -= row[j] * yj;
+                for (int i = 0; i < MB; ++i) f[i] = lane_value(a[i], j);
+            const double p = HOIST ? f[j < (HOIST ? MB : 1) ? j : 0] : lane_value(a[j], j);
+            const bool kj = p > thr;
+            if (c == j) mine = kj;
+            const double ip = kj ? recip(p) : 0.0;
+            const double nj = c == j ? 0.0 : 1.0;
+            const double rj = (c == j ? 1.0 : a[j]) * ip;
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (i != j) {
+                    const double fi = HOIST ? f[i < (HOIST ? MB : 1) ? i : 0] : lane_value(a[i], j);
+                    a[i] = a[i] * nj - fi * rj;
+                }
+            a[j] = rj;
         }
     }
-    return k < m ? v : 0.0;
+    const unsigned kept = unsigned(__ballot(mine && c < m));
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+        if ((c < m && !mine) || !((kept >> i) & 1u)) a[i] = 0.0;
+    return kept;
 }
 
 // Sequential single-vector projections as a triangular solve: x_j = (v_j - sum_{i<j} x_i L(j, i)) / d_j,
-// with L(j, i) = M[j * ldr + i * ldc] read by lane j... column-oriented: after x_j, lanes k > j
-// subtract x_j L(k, j).  Lane k passes v_k, gets x_k.
-template <int MB>
+// L(j, i) = Mx[j * ldr + i * ldc] (LDS), column-oriented: after x_j, lanes k > j subtract
+// x_j L(k, j).  Lane k passes v_k, gets x_k.
 __device__ double wave_forward_sub(const double* Mx, int ldr, int ldc, const double* diag, int m, double v) {
     const int k = threadIdx.x & 63;
+    const bool on = k < m;
     // a recycled direction with (p, q) = 0 is the zero vector (stored by a frame whose residual
     // was exactly zero): its coefficient is zero.  Lane k holds 1 / d_k (0 for such a direction).
-    const double inv = (k < m && diag[k] > 0) ? 1.0 / diag[k] : 0.0;
-#pragma unroll
-    for (int j = 0; j < MB; ++j) {
-        if (j < m) {
-            const double xj = lane_value(inv != 0.0 ? v * inv : 0.0, j);
-            const double lkj = (k > j && k < m) ? Mx[k * ldr + j * ldc] : 0.0;
-            if (k == j) v = xj;
-            else if (k > j) v -= xj * lkj;
-        }
+    const double inv = (on && diag[k] > 0) ? 1.0 / diag[k] : 0.0;
+    double nx = (on && k > 0) ? Mx[k * ldr] : 0.0;
+#pragma unroll 1
+    for (int j = 0; j < m; ++j) {
+        const double lkj = nx;
+        nx = (on && k > j + 1) ? Mx[k * ldr + (j + 1) * ldc] : 0.0;
+        const double xj = lane_value(inv != 0.0 ? v * inv : 0.0, j);
+        if (k == j) v = xj;
+        else if (k > j) v -= xj * lkj;
     }
-    return k < m ? v : 0.0;
+    return on ? v : 0.0;
 }
 
 // ------------------------------------------------------------------ frame start
@@ -441,8 +422,8 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ gp, i
 }
 
 // Reduce the Gram partials and solve for the Galerkin coefficients y (Sec. 4.1).
-// GALERKIN: G_ab = X_ab (a <= b, mirrored), Cholesky processing columns in order and dropping
-// column j when its pivot is <= 1e-14 max diag G; y = G^-1 U^T r.
+// GALERKIN: G_ab = X_ab (a <= b, mirrored), eliminated in order, index j dropped when its pivot
+// is <= 1e-14 max diag G; y = G^-1 U^T r.  MB: m rounded up to the register blocking.
 // PAPER: sequential sigma_j with the running residual, (r, p_j) = sigma_j g_j +
 // sum_{i<j} sigma_i (q_i, p_j); X is kept for the initial-direction step.
 template <int MB>
@@ -461,8 +442,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     const int ngb = I.ngb;
     const int W = m + 1;
     // GALERKIN uses the upper triangles of X and Y with their r column (both matrices are
-    // symmetric in their first m columns): only those m (m + 3) entries are reduced, Y's lower
-    // triangle is mirrored after.  PAPER reads both triangles of X.
+    // symmetric in their first m columns): only those m (m + 3) entries are reduced, and the
+    // lower triangles are read through the upper ones.  PAPER reads both triangles of X.
     __shared__ int16_t emap[kKMax * (kKMax + 3)];
     const bool upper = mode != FEWHA_RECYCLE_PAPER;
     const int nh = m * (m + 3) / 2;
@@ -488,14 +469,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
     }
     if (threadIdx.x < m) gm[threadIdx.x] = gam;
     __syncthreads();
-    if (upper) {
-        double* Yl = X + m * W;
-        for (int e = threadIdx.x; e < m * m; e += kSolveThreads) {
-            const int a = e / m, b = e - a * m;
-            if (a > b) Yl[a * W + b] = Yl[b * W + a];
-        }
-        __syncthreads();
-    }
     if (threadIdx.x >= 64) return;
     const int k = threadIdx.x;
     // tolerance mode: only the last `avail` slots of the window hold this instance's real
@@ -511,41 +484,64 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     }
     const double v = k < m ? X[k * W + m] : 0.0;   // (U_k, r)
-    // the Cholesky factor lives in LDS for both solves below (read back at LDS latency, in
-    // order within the wavefront), then goes to the scalars for the kernels after this one
-    __shared__ double sR[kKMax * kKMax];
-    __shared__ int32_t skeep[kKMax];
-    double y;
+    // entry (a, b) of the upper-triangle store (GALERKIN), for lanes k < m
+    auto sym = [&](const double* M, int a, int b) { return M[min(a, b) * W + max(a, b)]; };
+    // Initial direction (condition 1 of Alg. 2): its coefficients solve the same system with
+    // the right-hand side (Q_k, z), z = J^-1 r_new, r_new = r - Q y, that is
+    // w_k = (J^-1 Q_k, r) - sum_b (J^-1 Q_k, Q_b) y_b, accumulated from its first term
+    const double* Y = X + m * W;
+    double w = k < m ? Y[k * W + m] : 0.0;
+    double y, y2, a[MB];
     if (mode == FEWHA_RECYCLE_PAPER) {
         // (r, p_j) = sigma_j g_j + sum_{i<j} sigma_i (q_i, p_j),  (q_i, p_j) = X[j][i]
-        y = wave_forward_sub<MB>(X, W, 1, gm, m, v);
+        y = wave_forward_sub(X, W, 1, gm, m, v);
         if (k < m)
             for (int b = 0; b < m; ++b) sc->R[k * m + b] = X[k * W + b];
         if (k == 0) sc->dropped = 0;
     } else {
-        const int dropped = wave_cholesky<MB>(X, W, m, sR, skeep);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        y = wave_chol_solve<MB>(sR, skeep, m, v);
-        for (int e = k; e < m * m; e += 64) sc->R[e] = sR[e];
-        if (k < m) sc->keep[k] = skeep[k];
-        if (k == 0) sc->dropped = dropped - hide;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            a[i] = i >= m ? 0.0 : k < m ? sym(X, i, k) : k == m ? X[i * W + m] : 0.0;
+        double dmax = k < m ? X[k * W + k] : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+        // row k of Y, read before the elimination so that its LDS latency is hidden there
+        // (at most 16 entries: more would not stay in registers beside the columns)
+        constexpr int YB = MB <= 16 ? MB : 1;
+        double yrow[YB];
+#pragma unroll
+        for (int i = 0; i < YB; ++i) yrow[i] = (MB <= 16 && i < m && k < m) ? sym(Y, k, i) : 0.0;
+        const unsigned kept = wave_gauss_jordan<MB>(a, m, 1e-14 * dmax);
+        // y from lane m to every lane (and into w); G+ (symmetric: lane k's column is its row k)
+        // to the scalars for the in-loop projections
+        y = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const double yi = lane_value(a[i], m);
+            if (i == k) y = yi;
+            const double yki = MB <= 16 ? yrow[i < YB ? i : 0] : ((i < m && k < m) ? sym(Y, k, i) : 0.0);
+            if (i < m) w -= yki * yi;
+        }
+        if (k < m)
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (i < m) sc->R[i * m + k] = a[i];
+        if (k < m) sc->keep[k] = (kept >> k) & 1u;
+        if (k == 0) sc->dropped = (m - __builtin_popcount(kept)) - hide;
     }
     if (k < m) sc->y[k] = y;
     if (k == 0) sc->used = m - hide;
-    // Initial direction (condition 1 of Alg. 2): its coefficients solve the same system with
-    // the right-hand side (Q_k, z), z = J^-1 r_new, r_new = r - Q y, that is
-    // w_k = (J^-1 Q_k, r) - sum_b (J^-1 Q_k, Q_b) y_b
-    const double* Y = X + m * W;
-    double w = k < m ? Y[k * W + m] : 0.0;
-#pragma unroll
-    for (int b = 0; b < MB; ++b)
-        if (b < m) w -= (k < m ? Y[k * W + b] : 0.0) * lane_value(y, b);
-    double y2;
     if (mode == FEWHA_RECYCLE_PAPER) {
+#pragma unroll 1
+        for (int b = 0; b < m; ++b) w -= (k < m ? Y[k * W + b] : 0.0) * lane_value(y, b);
         // (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j),  (p_i, q_j) = X[i][j]
-        y2 = wave_forward_sub<MB>(X, 1, W, gm, m, w);
+        y2 = wave_forward_sub(X, 1, W, gm, m, w);
     } else {
-        y2 = wave_chol_solve<MB>(sR, skeep, m, w);
+        // y2 = G+ w, row k of G+ being lane k's column
+        y2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (i < m) y2 += a[i] * lane_value(w, i);
     }
     if (k < m) sc->y2[k] = y2;
     // a non-finite projection coefficient is a breakdown: the Galerkin pass then leaves the frame
@@ -811,27 +807,22 @@ __global__ void __launch_bounds__(kThreads) k_update2(int64_t N, const VecBlk* _
     __shared__ bool sbroken;
     double v[NV];
     block_row_sums<NV>(part, pstride, sg, P_RZ1, NV, v);   // (r,z), (Q_a,z) a < MP, (U_a,r) a < MP (entries a >= mp unused)
-    __shared__ double y3[MP1], R[MP1 * MP1];
-    __shared__ int32_t keep[MP1];
-    if (MP > 1 && project_all) {
-        for (int e = threadIdx.x; e < mp * mp; e += kThreads) R[e] = sc->R[e];
-        if (threadIdx.x < mp) keep[threadIdx.x] = sc->keep[threadIdx.x];
-        __syncthreads();
-    }
+    __shared__ double y3[MP1];
     if (threadIdx.x < 64) {
         const int k = threadIdx.x;
         if constexpr (MP > 0) {
             if (project_all) {
-                if (MP == 1 && k == 0) {
-                    R[0] = sc->R[0];
-                    keep[0] = sc->keep[0];
-                }
-                double vk = 0;
+                // y3 = G+ (U^T r) with G+ from the Gram solve (zero rows and columns for the
+                // dropped directions); lane k takes row k
+                if (k < mp) {
+                    double yk = 0;
 #pragma unroll
-                for (int a = 0; a < MP; ++a)
-                    if (a == k) vk = v[1 + a];
-                const double yk = wave_chol_solve<MP1>(R, keep, mp, vk);
-                if (k < mp) y3[k] = yk;
+                    for (int a = 0; a < MP; ++a) {
+                        const double g = sc->R[k * mp + (a < mp ? a : 0)];   // loads not behind a condition
+                        if (a < mp) yk += g * v[1 + a];
+                    }
+                    y3[k] = yk;
+                }
             } else if (k == 0) {
                 const double g = sc->gam[pl.s[0]];
                 y3[0] = g > 0 ? v[1] / g : 0.0;
@@ -1250,15 +1241,15 @@ void enqueue_galerkin_init(const Ctx& c, const Frame<T>& f, hipStream_t s) {
         }
         {
             ProfScope ps_(c, KID_GRAM_SOLVE, s);
-            if (m <= 8)
-                k_gram_solve<8><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart,
-                                                                 f.done ? 1 : 0);
-            else if (m <= 16)
-                k_gram_solve<16><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart,
-                                                                 f.done ? 1 : 0);
-            else
-                k_gram_solve<32><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart,
-                                                                 f.done ? 1 : 0);
+#define GS(mb) k_gram_solve<mb><<<c.B, kSolveThreads, 0, s>>>(m, c.mode, f.act, f.sc, f.insts, f.ke, f.gpart, \
+                                                             f.done ? 1 : 0)
+            if (m <= 4) GS(4);
+            else if (m <= 8) GS(8);
+            else if (m <= 12) GS(12);
+            else if (m <= 16) GS(16);
+            else if (m <= 24) GS(24);
+            else GS(32);
+#undef GS
         }
         ProfScope ps_(c, KID_GALERKIN, s);
         switch (f.mb) {
