@@ -50,10 +50,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Block (kThreads) reduction of NV register values; thread k < NV writes
 // part[(slot0 + k) * stride + col].  Fixed shuffle/LDS tree: deterministic.
-template <int NV>
+// Sum of NW (a power of two) wavefront sums in a fixed pairwise order.
+template <int NW>
+__device__ __forceinline__ double pairwise_sum(const double* s) {
+    if constexpr (NW == 1) return s[0];
+    else return pairwise_sum<NW / 2>(s) + pairwise_sum<NW / 2>(s + NW / 2);
+}
+
+template <int NV, int NT = kThreads>
 __device__ __forceinline__ void block_partials(const double (&v)[NV], double* __restrict__ part, int slot0,
                                                int stride, int col) {
-    __shared__ double sh[NV > 0 ? NV : 1][kThreads / 64];
+    __shared__ double sh[NV > 0 ? NV : 1][NT / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -63,7 +70,7 @@ __device__ __forceinline__ void block_partials(const double (&v)[NV], double* __
     __syncthreads();
     if (threadIdx.x < NV) {
         const int k = threadIdx.x;
-        part[size_t(slot0 + k) * stride + col] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+        part[size_t(slot0 + k) * stride + col] = pairwise_sum<NT / 64>(sh[k]);
     }
     __syncthreads();
 }

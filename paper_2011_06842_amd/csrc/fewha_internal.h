@@ -14,6 +14,8 @@
 namespace fewha {
 
 constexpr int kThreads = 256;       // threads of every 1-D kernel (4 wavefronts of 64)
+constexpr int kAnaWide = 512;       // tiled analysis of a small context: eight wavefronts per workgroup
+constexpr int kAnaWideItems = 512;  // ... up to this many tiles per launch
 constexpr int kVecBlocksMax = 1024; // vector-kernel workgroups of one instance (grid-stride beyond)
 constexpr int kDefaultBlockElems = 384;  // default elements per vector workgroup
 constexpr int kGramElems = 1536;    // elements per Gram workgroup (one instance: <= kGramBlocks)

@@ -75,6 +75,11 @@ __device__ __forceinline__ int die_ordered_block() {
     return (g % kXcds) ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
 }
 
+// Tiled analysis launches of at most kAnaWideItems tiles (a single instance: the GPU is far
+// from full, and the longest tiles set the launch's duration) run kAnaWide-thread workgroups;
+// larger ones keep kThreads, which fit more tiles per compute unit.
+inline bool ana_wide(int items) { return items <= kAnaWideItems; }
+
 // Filter taps split by parity, so that every index is a compile-time constant (a tap index
 // that varies across lanes would otherwise be fetched from memory inside the loops).
 template <typename T>
@@ -321,7 +326,7 @@ template <typename T> struct AnaMaxLevels;
 template <> struct AnaMaxLevels<float> { static constexpr int value = 3; };
 template <> struct AnaMaxLevels<double> { static constexpr int value = 2; };
 
-template <typename T, int MODE, int K>
+template <typename T, int MODE, int K, int NT>
 __device__ __forceinline__ void dwt_tiles_body(const LayerDev& d, int4 it, const Taps<T>& tp, const T* __restrict__ img,
                                                const T* __restrict__ ll_in, T* __restrict__ ll_out, T* __restrict__ out,
                                                const T* __restrict__ prior_a, const T* __restrict__ xprior, T* A, T* Bf,
@@ -334,7 +339,9 @@ __device__ __forceinline__ void dwt_tiles_body(const LayerDev& d, int4 it, const
     const int ty = it.y / mt, tx = it.y - ty * mt;
     const bool fin = l1 + K - 1 == d.levels;
     const size_t base = size_t(d.off);
-    const int t = threadIdx.x;
+    // the first NT threads of the workgroup do the work; the others (NT below the launch
+    // width) take no item but join the barriers
+    const int t = int(threadIdx.x) < NT ? int(threadIdx.x) : (1 << 20);
     T pa[K][4], xp[K][4];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -357,20 +364,20 @@ __device__ __forceinline__ void dwt_tiles_body(const LayerDev& d, int4 it, const
     // side are multiples of the chunk, so a chunk is contiguous across the periodic wrap
     {
         using VC = Vec16<T>;
-        constexpr int CPR = V0 / VC::n, NCH = V0 * CPR, PER = cdiv_c(NCH, kThreads);
+        constexpr int CPR = V0 / VC::n, NCH = V0 * CPR, PER = cdiv_c(NCH, NT);
         const T* src = (l1 == 1 ? img : ll_in) + d.off;
         const int sy = (ty * TT) << K, sx = (tx * TT) << K;
         typename VC::type v[PER];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {   // unconditional loads (clamped index)
-            const int e0 = t + k * kThreads, e = e0 < NCH ? e0 : NCH - 1;
+            const int e0 = t + k * NT, e = e0 < NCH ? e0 : NCH - 1;
             const int r = e / CPR, q = e - r * CPR;
             v[k] = *reinterpret_cast<const typename VC::type*>(src + ((sy + r) & (nb_in - 1)) * n +
                                                                ((sx + q * VC::n) & (nb_in - 1)));
         }
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int e = t + k * kThreads;
+            const int e = t + k * NT;
             if (e < NCH) {
                 const int r = e / CPR, q = e - r * CPR;
                 VC::put(&A[r * SA + q * VC::n], v[k]);
@@ -384,7 +391,7 @@ __device__ __forceinline__ void dwt_tiles_body(const LayerDev& d, int4 it, const
         const int vin = (TT << (K - j)) + 4 * ((1 << (K - j)) - 1);   // compile-time after unrolling
         const int vo = (vin - 4) >> 1, sb = 2 * vo + 1;
         // row pass: low- and high-pass outputs of one (row, k) from the same six inputs
-        for (int e = t; e < vin * vo; e += kThreads) {
+        for (int e = t; e < vin * vo; e += NT) {
             const int rr = e / vo, k = e - rr * vo;
             T lo = 0, hi = 0;
 #pragma unroll
@@ -402,7 +409,7 @@ __device__ __forceinline__ void dwt_tiles_body(const LayerDev& d, int4 it, const
         const int own = TT << (K - 1 - j);
         const int m = n >> (l1 + j);
         const bool last = j == K - 1;
-        for (int e = t; e < vo * vo; e += kThreads) {
+        for (int e = t; e < vo * vo; e += NT) {
             int r, c;
             if (e < own * own) {
                 r = e / own;
@@ -565,8 +572,11 @@ __global__ void __launch_bounds__(kThreads) k_dwt_coarse(const LayerDev* __restr
     }
 }
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) k_dwt_tiles(const LayerDev* __restrict__ lays, const int4* __restrict__ items,
+// LW: workgroup width, kThreads or kAnaWide (the wide one only where the launch has few tiles:
+// it gives the three-level tiles, the longest, twice the threads; every tile computes the same
+// values and partial either way).
+template <typename T, int MODE, int LW>
+__global__ void __launch_bounds__(LW) k_dwt_tiles(const LayerDev* __restrict__ lays, const int4* __restrict__ items,
                                                          Filt<T> f, const T* __restrict__ img, const T* __restrict__ ll_in,
                                                          T* __restrict__ ll_out, T* __restrict__ out,
                                                          const T* __restrict__ prior_a, const T* __restrict__ xprior,
@@ -581,15 +591,17 @@ __global__ void __launch_bounds__(kThreads) k_dwt_tiles(const LayerDev* __restri
     const Taps<T> tp(f);
     const int K = (it.z >> 8) & 0xff;
     double dot = 0;
+    // three-level tiles (the largest windows) over the whole workgroup, the others over four
+    // wavefronts
     if (KM >= 3 && K == 3)
-        dwt_tiles_body<T, MODE, KM >= 3 ? 3 : 1>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
+        dwt_tiles_body<T, MODE, KM >= 3 ? 3 : 1, LW>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
     else if (K == 2)
-        dwt_tiles_body<T, MODE, 2>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
+        dwt_tiles_body<T, MODE, 2, kThreads>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
     else
-        dwt_tiles_body<T, MODE, 1>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
+        dwt_tiles_body<T, MODE, 1, kThreads>(d, it, tp, img, ll_in, ll_out, out, prior_a, xprior, A, Bf, dot);
     if (MODE != 0 && dotpart) {
         const double vv[1] = {dot};
-        block_partials<1>(vv, dotpart, 0, 0, d.pq0 + it.w);
+        block_partials<1, LW>(vv, dotpart, 0, 0, d.pq0 + it.w);
     }
 }
 
@@ -1245,13 +1257,14 @@ void launch_winvt(const Ctx& c, const T* img, T* y, const T* xprior, double* pq_
     for (int j = 0; j < J; ++j) {
         const StepInfo& w = c.steps[j];
         ProfScope ps_(c, KID_DWT_TILES, s);
-        auto go = [&](auto kern) {
-            kern<<<w.ni, kThreads, 0, s>>>(lays, items + w.loff, f, img, buf[(j + 1) & 1], buf[j & 1], y, pa, xprior,
-                                           pq_part, skip);
+        auto go = [&](auto kern, int lw) {
+            kern<<<w.ni, lw, 0, s>>>(lays, items + w.loff, f, img, buf[(j + 1) & 1], buf[j & 1], y, pa, xprior,
+                                     pq_part, skip);
         };
-        if (mode == 1) go(k_dwt_tiles<T, 1>);
-        else if (mode == 2) go(k_dwt_tiles<T, 2>);
-        else go(k_dwt_tiles<T, 0>);
+        const bool wide = ana_wide(w.ni);
+        if (mode == 1) wide ? go(k_dwt_tiles<T, 1, kAnaWide>, kAnaWide) : go(k_dwt_tiles<T, 1, kThreads>, kThreads);
+        else if (mode == 2) wide ? go(k_dwt_tiles<T, 2, kAnaWide>, kAnaWide) : go(k_dwt_tiles<T, 2, kThreads>, kThreads);
+        else wide ? go(k_dwt_tiles<T, 0, kAnaWide>, kAnaWide) : go(k_dwt_tiles<T, 0, kThreads>, kThreads);
     }
     ProfScope ps_(c, KID_DWT_COARSE, s);
     auto go = [&](auto kern) {
@@ -1395,10 +1408,13 @@ static hipError_t launch_one(const Ctx& c, int kid, int step, hipStream_t s) {
         case KID_DWT_TILES: {
             if (step < 0 || step >= J) return hipErrorInvalidValue;
             const StepInfo& w = c.steps[step];
-            k_dwt_tiles<T, 1><<<w.ni, kThreads, 0, s>>>(lays, c.at<int4>(c.lay.ana_items) + w.loff, f,
-                                                         c.at<T>(c.lay.psi_layers), buf[(step + 1) & 1], buf[step & 1],
-                                                         y, c.at<T>(c.lay.prior_a), x, c.at<double>(c.lay.pq_part),
-                                                         nullptr);
+            auto go = [&](auto kern, int lw) {
+                kern<<<w.ni, lw, 0, s>>>(lays, c.at<int4>(c.lay.ana_items) + w.loff, f, c.at<T>(c.lay.psi_layers),
+                                         buf[(step + 1) & 1], buf[step & 1], y, c.at<T>(c.lay.prior_a), x,
+                                         c.at<double>(c.lay.pq_part), nullptr);
+            };
+            if (ana_wide(w.ni)) go(k_dwt_tiles<T, 1, kAnaWide>, kAnaWide);
+            else go(k_dwt_tiles<T, 1, kThreads>, kThreads);
             break;
         }
         case KID_DWT_COARSE:
