@@ -26,6 +26,17 @@ __device__ __forceinline__ double dpp_row_shr(double v) {
     return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
+// v of the lane that DPP control CTRL names, with every row of 16 lanes enabled (for the row
+// rotations: every lane reads a lane of its own row).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(
+        __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), CTRL, 0xf, 0xf, false));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 // v of the lane CTRL names (DPP row broadcast) in the rows ROWS selects (bit r: row r of 16
 // lanes), 0 in the other rows.
 template <int CTRL, int ROWS>

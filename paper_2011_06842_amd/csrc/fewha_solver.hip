@@ -265,11 +265,20 @@ __device__ __forceinline__ void load4(const double* p, double (&v)[4], double f)
 // row/column l mod 16, elements 4 (l / 16) .. +3; on a diagonal tile the row vector Q_a of Y
 // is the lane's own column operand), the four wavefronts' tiles are summed in LDS in a fixed
 // order and written as one partial each.
-template <typename T, bool ONE_TILE>
+//
+// BLK4 (GALERKIN, m <= 11, one tile): only the upper triangles are needed, so the products run
+// on v_mfma_f64_4x4x4 instead, which takes its four 4x4 blocks' A and B operands from the same
+// lanes as the 16x16 form (lane 16 k + 4 b + i: row or column 4 b + i at depth k) and gives
+// block b's entry (i, j) to lane 16 i + 4 b + j.  With B rotated by 4 d lanes within each row of
+// 16, block b pairs rows 4 b.. with columns 4 (b + d).., so d = 0 .. ND - 1 (ND = ceil((m + 1) / 4)
+// <= 3) covers every block on or above the diagonal: ND instructions of 16 cycles per matrix
+// and depth step instead of one of 64.  Only entries on or above the diagonal are written.
+template <typename T, bool ONE_TILE, bool BLK4 = false>
 __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk* __restrict__ gt, int m, SlotList sl,
                                                         const T* __restrict__ U, const T* __restrict__ Q,
                                                         const T* __restrict__ r, const T* __restrict__ jinv,
                                                         double* __restrict__ gpart) {
+    static_assert(!BLK4 || ONE_TILE, "the small-block form covers one tile");
     constexpr int NW = kGramThreads / 64;          // wavefronts per workgroup
     __shared__ double sh[NW][256];
     GramBlk g;
@@ -294,6 +303,8 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
     const T* pj = jinv + g.off;
     const double ma = ar < m ? 1.0 : 0.0, mb = bc <= m ? 1.0 : 0.0;
     f64x4 c = {0.0, 0.0, 0.0, 0.0}, c2 = {0.0, 0.0, 0.0, 0.0};
+    double x4[3] = {0.0, 0.0, 0.0}, y4[3] = {0.0, 0.0, 0.0};   // BLK4: block diagonal d of X and Y
+    const int nd = (m + 1 + 3) / 4;
     // one 16-element chunk per step: its three (four) loads issued together; the next chunk's
     // loads are in flight while this one is converted and fed to the matrix cores
     const int64_t step = int64_t(g.nb) * NW * 16;
@@ -330,10 +341,29 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
 #pragma unroll
             for (int j = 0; j < 4; ++j) jq[j] *= qa[j];
         }
+        if constexpr (BLK4) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], c, 0, 0, 0);
-            c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(jq[j], bv[j], c2, 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+                // B of columns 4 (b + d) + j in the lanes of block b: a left rotation by 4 d
+                // within each row of 16 (data-parallel row rotate right by 16 - 4 d)
+                const double b1 = dpp_f64<0x12C>(bv[j]), b2 = dpp_f64<0x128>(bv[j]);
+                x4[0] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[j], bv[j], x4[0], 0, 0, 0);
+                y4[0] = __builtin_amdgcn_mfma_f64_4x4x4f64(jq[j], bv[j], y4[0], 0, 0, 0);
+                if (nd > 1) {
+                    x4[1] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[j], b1, x4[1], 0, 0, 0);
+                    y4[1] = __builtin_amdgcn_mfma_f64_4x4x4f64(jq[j], b1, y4[1], 0, 0, 0);
+                }
+                if (nd > 2) {
+                    x4[2] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[j], b2, x4[2], 0, 0, 0);
+                    y4[2] = __builtin_amdgcn_mfma_f64_4x4x4f64(jq[j], b2, y4[2], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[j], bv[j], c, 0, 0, 0);
+                c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(jq[j], bv[j], c2, 0, 0, 0);
+            }
         }
         ra = na;
         rb = nb;
@@ -355,6 +385,28 @@ __global__ void __launch_bounds__(kGramThreads) k_gram(int64_t N, const GramBlk*
             for (int w = 0; w < h; ++w) v[w] = v[w] + v[w + h];
         return v[0];
     };
+    if constexpr (BLK4) {
+        // lane 16 i + 4 b + j holds entry (4 b + i, 4 ((b + d) & 3) + j) of diagonal d; entries no
+        // diagonal covers stay zero (and only those on or above the diagonal are written)
+        const int bi = (lane & 15) >> 2, ei = 4 * bi + (lane >> 4);
+        const bool wu = wr && row <= col;
+        auto put = [&](const double (&acc)[3]) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sh[wv][v * 64 + lane] = 0.0;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                if (d < nd) sh[wv][ei * 16 + 4 * ((bi + d) & 3) + (lane & 3)] = acc[d];
+        };
+        put(x4);
+        __syncthreads();
+        if (wu) gpart[size_t(g.gbase) + size_t(row * (m + 1) + col) * g.nb + g.local] = tile_sum();
+        __syncthreads();
+        put(y4);
+        __syncthreads();
+        if (wu) gpart[size_t(g.gbase) + size_t(m * (m + 1) + row * (m + 1) + col) * g.nb + g.local] = tile_sum();
+        return;
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) sh[wv][(4 * v + (lane >> 4)) * 16 + (lane & 15)] = c[v];
     __syncthreads();
@@ -1234,7 +1286,9 @@ void enqueue_galerkin_init(const Ctx& c, const Frame<T>& f, hipStream_t s) {
         {
             ProfScope ps_(c, KID_GRAM, s);
             const dim3 grid(c.GB, ((m + 15) / 16) * ((m + 1 + 15) / 16));
-            if (m < 16)
+            if (m <= 11 && c.mode != FEWHA_RECYCLE_PAPER)
+                k_gram<T, true, true><<<grid, kGramThreads, 0, s>>>(f.N, f.gt, m, f.act, f.U, f.Q, f.r, f.jinv, f.gpart);
+            else if (m < 16)
                 k_gram<T, true><<<grid, kGramThreads, 0, s>>>(f.N, f.gt, m, f.act, f.U, f.Q, f.r, f.jinv, f.gpart);
             else
                 k_gram<T, false><<<grid, kGramThreads, 0, s>>>(f.N, f.gt, m, f.act, f.U, f.Q, f.r, f.jinv, f.gpart);
