@@ -180,6 +180,29 @@ def test_large_recycle_space_fp64(mode):
         assert gi["recycle_used"] == ri["recycle_used"] and gi["dropped"] == ri["dropped"]
 
 
+@pytest.mark.parametrize("k", [1, 3, 4, 5, 7, 8, 11, 12, 15])
+def test_recycle_dimensions_galerkin_fp64(k):
+    """GALERKIN frames with k recycled directions across the Gram's forms: one 4x4 block
+    diagonal (k <= 3), two (4 <= k <= 7) and three (8 <= k <= 11) of the small-block
+    matrix-core form, and the 16x16 tile (12 <= k <= 15).  As many iterations per frame as k,
+    so the ring holds k directions from the second frame on; the same bar as the k = 20 test
+    (10 times the oracle's own deviation under 1e-15 slope perturbations, at least 1e-10)."""
+    spec, seq, _ = system("small")
+    spec = spec.copy(recycle_k=k, max_iter=max(k, 4), recycle_mode="galerkin")
+    sysm = OracleSystem(spec)
+    frames = 4
+    errs, infos = _run_sequence(spec, seq, sysm, frames)
+    a, b = AugmentedReconstructor(sysm), AugmentedReconstructor(sysm)
+    rng = np.random.default_rng(1)
+    for t in range(frames):
+        ca, _ = a.solve(seq[t])
+        cb, _ = b.solve(seq[t] * (1 + 1e-15 * rng.standard_normal(seq[t].shape)))
+        assert errs[t] <= max(1e-10, 10 * rel(cb, ca)), (t, errs[t], rel(cb, ca))
+    assert max(gi["recycle_used"] for gi, _ in infos) == k
+    for gi, ri in infos:
+        assert gi["recycle_used"] == ri["recycle_used"] and gi["dropped"] == ri["dropped"] and gi["flags"] == 0
+
+
 def test_plain_pcg_k0_fp64():
     spec, seq, sysm = system("small")
     spec = spec.copy(recycle_k=0)
