@@ -180,11 +180,12 @@ def test_large_recycle_space_fp64(mode):
         assert gi["recycle_used"] == ri["recycle_used"] and gi["dropped"] == ri["dropped"]
 
 
-@pytest.mark.parametrize("k", [1, 3, 4, 5, 7, 8, 11, 12, 15])
+@pytest.mark.parametrize("k", [1, 3, 4, 5, 7, 8, 11, 12, 15, 24, 32])
 def test_recycle_dimensions_galerkin_fp64(k):
     """GALERKIN frames with k recycled directions across the Gram's forms: one 4x4 block
     diagonal (k <= 3), two (4 <= k <= 7) and three (8 <= k <= 11) of the small-block
-    matrix-core form, and the 16x16 tile (12 <= k <= 15).  As many iterations per frame as k,
+    matrix-core form, the 16x16 tile (12 <= k <= 15) and 2 x 2 tiles (24, 32; the elimination's
+    widest register blocking at 32).  As many iterations per frame as k,
     so the ring holds k directions from the second frame on; the same bar as the k = 20 test
     (10 times the oracle's own deviation under 1e-15 slope perturbations, at least 1e-10)."""
     spec, seq, _ = system("small")
