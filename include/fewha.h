@@ -77,8 +77,10 @@ typedef enum { FEWHA_FP64 = 0, FEWHA_FP32_OP_FP64_RED = 1 } fewha_precision;
 
 /* Recycling variants of Alg. 2 (Sec. 4.1).  PAPER: sequential single-vector Galerkin and
  * initial-direction projections against the previous frame's directions, as printed.
- * GALERKIN: the same projections solved jointly with the k x k Gram matrix U^T Q (FP64
- * Cholesky, near-dependent columns dropped) over a ring of the k most recent directions. */
+ * GALERKIN: the same projections solved jointly with the k x k Gram matrix U^T Q (FP64,
+ * eliminated in order with the pivots of its Cholesky factorisation; a direction whose pivot is
+ * at most 1e-14 of the largest diagonal entry is dropped) over a ring of the k most recent
+ * directions. */
 typedef enum { FEWHA_RECYCLE_PAPER = 0, FEWHA_RECYCLE_GALERKIN = 1 } fewha_recycle_mode;
 
 /* One turbulence layer (Sec. 2 layered atmosphere; Sec. 3 layer grid of 2^(2 J_l) nodes). */
