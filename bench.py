@@ -726,19 +726,20 @@ def frame_stats(ts_s, it):
 def cpu_baselines(spec, seq, n_single, n_all, workers):
     """Single-thread and all-core figures of the FP64 oracle on the first frames of `seq`:
     one process (one BLAS/NumPy thread) for the single-thread figure and its solutions, one
-    more with every operator output perturbed at FP32 rounding size (2^-24), then `workers`
-    processes each
+    more with every operator output perturbed at FP32 rounding size (2^-24) and, for an FP64
+    configuration, one at FP64 rounding size (2^-52), then `workers` processes each
     solving the same frames concurrently after a common start (aggregate applies/s over the
     span from the common start to the last finish)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     ctx = mp.get_context("fork")
     it = spec.max_iter
-    with ProcessPoolExecutor(max_workers=2, mp_context=ctx) as ex:
+    sizes = [24] + ([52] if spec.precision == "fp64" else [])
+    with ProcessPoolExecutor(max_workers=1 + len(sizes), mp_context=ctx) as ex:
         f1 = ex.submit(_oracle_run, (spec, seq[:n_single], True, 0.0, False))
-        f2 = ex.submit(_oracle_run, (spec, seq[:n_single], True, 2.0 ** -24, False))
+        fp = {e: ex.submit(_oracle_run, (spec, seq[:n_single], True, 2.0 ** -e, False)) for e in sizes}
         setup1, ts1, sols = f1.result()
-        _, _, sols_p = f2.result()
+        sols_p = {e: f.result()[2] for e, f in fp.items()}
     barrier = ctx.Barrier(workers)
     with ProcessPoolExecutor(max_workers=workers, mp_context=ctx, initializer=_set_barrier,
                              initargs=(barrier,)) as ex:
@@ -1044,17 +1045,23 @@ def run_precond(args, dev, spec, seq):
 def free_running_errors(spec, slopes_dev, sols, sols_p, dev):
     """A fresh GPU context over the frames the oracle solved: relative error of every frame's
     coefficients against the FP64 oracle, next to the oracle's own drift when every operator
-    output is perturbed at FP32 rounding size (the method's sensitivity over the same frames)."""
+    output is perturbed at FP32 rounding size and, for FP64, at FP64 rounding size (the method's
+    sensitivity over the same frames).  `sols_p`: perturbed solutions by the exponent e of 2^-e."""
     import numpy as np
     import paper_2011_06842_amd as fw
     vctx = fw.FewhaContext(spec, device=dev)
-    errs, sens = [], []
+    errs = []
+    sens = {e: [] for e in sols_p}
     for t, ref in enumerate(sols):
         g = vctx.fewha_solve_aug(slopes_dev[t]).double().cpu().numpy()
         errs.append(float(np.linalg.norm(g - ref) / np.linalg.norm(ref)))
-        sens.append(float(np.linalg.norm(sols_p[t] - ref) / np.linalg.norm(ref)))
-    return {"frames": len(sols), "max": max(errs), "last": errs[-1], "per_frame": [float(f"{x:.3e}") for x in errs],
-            "oracle_vs_oracle_with_M_outputs_perturbed_2^-24": [float(f"{x:.3e}") for x in sens]}
+        for e, sp in sols_p.items():
+            sens[e].append(float(np.linalg.norm(sp[t] - ref) / np.linalg.norm(ref)))
+    out = {"frames": len(sols), "max": max(errs), "last": errs[-1], "per_frame": [float(f"{x:.3e}") for x in errs]}
+    for e, v in sens.items():
+        out[f"oracle_vs_oracle_with_M_outputs_perturbed_2^-{e}"] = [float(f"{x:.3e}") for x in v]
+        out[f"oracle_vs_oracle_2^-{e}_max"] = max(v)
+    return out
 
 
 def main(argv=None):

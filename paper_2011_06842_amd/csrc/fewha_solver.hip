@@ -557,23 +557,54 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
         double dmax = k < m ? X[k * W + k] : 0.0;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
-        // row k of Y, read before the elimination so that its LDS latency is hidden there
-        // (at most 16 entries: more would not stay in registers beside the columns)
-        constexpr int YB = MB <= 16 ? MB : 1;
-        double yrow[YB];
+        // rows k of G and Y, read before the elimination so that their LDS latency is hidden
+        // there (at most 16 entries each: more would not stay in registers beside the columns)
+        constexpr bool PRE = MB <= 16;
+        constexpr int YB = PRE ? MB : 1;
+        double grow[YB], yrow[YB];
 #pragma unroll
-        for (int i = 0; i < YB; ++i) yrow[i] = (MB <= 16 && i < m && k < m) ? sym(Y, k, i) : 0.0;
+        for (int i = 0; i < YB; ++i) {
+            grow[i] = (PRE && i < m && k < m) ? sym(X, k, i) : 0.0;
+            yrow[i] = (PRE && i < m && k < m) ? sym(Y, k, i) : 0.0;
+        }
+        auto g_ki = [&](int i) { return PRE ? grow[i < YB ? i : 0] : ((i < m && k < m) ? sym(X, k, i) : 0.0); };
+        auto y_ki = [&](int i) { return PRE ? yrow[i < YB ? i : 0] : ((i < m && k < m) ? sym(Y, k, i) : 0.0); };
         const unsigned kept = wave_gauss_jordan<MB>(a, m, 1e-14 * dmax);
-        // y from lane m to every lane (and into w); G+ (symmetric: lane k's column is its row k)
-        // to the scalars for the in-loop projections
+        const bool kk = k < m && ((kept >> k) & 1u);
+        // One step of iterative refinement (residual in FP64, correction through G+) for each of
+        // the two solves: a product with the explicit inverse alone carries the inverse's
+        // rounding error times the condition number, where the solve it replaces does not.
+        // x <- x + G+ (rhs - G x), on the kept indices (G+ is zero on the others).
+        auto refine = [&](double x, double rhs) {
+            double res = rhs;
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (i < m) res -= g_ki(i) * lane_value(x, i);
+            res = kk ? res : 0.0;
+            double dx = 0.0;
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+                if (i < m) dx += a[i] * lane_value(res, i);
+            return kk ? x + dx : x;
+        };
+        // y from lane m to every lane; G+ (symmetric: lane k's column is its row k) to the
+        // scalars for the in-loop projections
         y = 0.0;
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
             const double yi = lane_value(a[i], m);
             if (i == k) y = yi;
-            const double yki = MB <= 16 ? yrow[i < YB ? i : 0] : ((i < m && k < m) ? sym(Y, k, i) : 0.0);
-            if (i < m) w -= yki * yi;
         }
+        y = refine(y, v);
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (i < m) w -= y_ki(i) * lane_value(y, i);
+        // y2 = G+ w, row k of G+ being lane k's column, then refined as y was
+        y2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+            if (i < m) y2 += a[i] * lane_value(w, i);
+        y2 = refine(y2, w);
         if (k < m)
 #pragma unroll
             for (int i = 0; i < MB; ++i)
@@ -588,12 +619,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_gram_solve(int m, int mode, S
         for (int b = 0; b < m; ++b) w -= (k < m ? Y[k * W + b] : 0.0) * lane_value(y, b);
         // (z, q_j) = tau_j g_j + sum_{i<j} tau_i (p_i, q_j),  (p_i, q_j) = X[i][j]
         y2 = wave_forward_sub(X, 1, W, gm, m, w);
-    } else {
-        // y2 = G+ w, row k of G+ being lane k's column
-        y2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-            if (i < m) y2 += a[i] * lane_value(w, i);
     }
     if (k < m) sc->y2[k] = y2;
     // a non-finite projection coefficient is a breakdown: the Galerkin pass then leaves the frame
