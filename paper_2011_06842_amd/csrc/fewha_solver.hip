@@ -78,10 +78,20 @@ __device__ __forceinline__ void block_row_sums(const double* __restrict__ part, 
     __syncthreads();
 }
 
-// Small dense algebra of the recycle space on one wavefront (m <= 64, all 64 lanes active).
+// Small dense algebra of the recycle space on one wavefront (m <= kKMax = 32, all 64 lanes active).
 // This runs once per frame on a single wavefront, where every step of a dependency chain costs
 // its full latency (a broadcast, a multiply-add: tens of cycles each), so the forms below are
 // chosen for short chains rather than few operations.
+
+// 1 / p for a positive normal p: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - p r), within an ulp or two (a correctly rounded division takes about twice as
+// many dependent steps, and each pivot's reciprocal is on the elimination's critical path).
+__device__ __forceinline__ double recip(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    r = fma(r, fma(-p, r, 1.0), r);
+    r = fma(r, fma(-p, r, 1.0), r);
+    return r;
+}
 
 // The Galerkin system G y = v by Gauss-Jordan elimination in place (G symmetric positive
 // semi-definite: pivots in order, no exchanges).  Lane c < m holds column c of G in a[0..m-1],
@@ -95,16 +105,6 @@ __device__ __forceinline__ void block_row_sums(const double* __restrict__ part, 
 // Returns the mask of kept indices.  Every step is the same straight-line code (no branch on
 // the pivot): one broadcast of a column and two multiply-adds per entry, so the compiler can
 // overlap a step's entry updates with the next pivot's reciprocal.
-// 1 / p for a positive normal p: the hardware estimate refined by two Newton-Raphson steps
-// r <- r + r (1 - p r), within an ulp or two (a correctly rounded division takes about twice as
-// many dependent steps, and each pivot's reciprocal is on the elimination's critical path).
-__device__ __forceinline__ double recip(double p) {
-    double r = __builtin_amdgcn_rcp(p);
-    r = fma(r, fma(-p, r, 1.0), r);
-    r = fma(r, fma(-p, r, 1.0), r);
-    return r;
-}
-
 template <int MB>
 __device__ __forceinline__ unsigned wave_gauss_jordan(double (&a)[MB], int m, double thr) {
     const int c = threadIdx.x & 63;
